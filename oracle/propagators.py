@@ -1,0 +1,56 @@
+"""Fine and coarse propagators (Section 2: F advances one slice of length
+dT = T/N with J steps of dt = dT/J; G advances it with coarse steps).
+
+Pairings of Section 2.1: PA-III is F = (2.5), G = (2.4); NPA-I is F = (2.3),
+G = (2.4); PA-II is F = G = (2.5).  ``m_coarse`` coarse sub-steps of dT/m are
+allowed (the paper uses one).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import schemes
+
+
+def fine(prob, u: np.ndarray, steps: int | None = None) -> np.ndarray:
+    """F(T_{n+1}, T_n, u): J steps of the fine scheme with tau = dT/J."""
+    J = prob.j_fine if steps is None else steps
+    tau = prob.dt
+    v = np.array(u, dtype=np.float64, copy=True)
+    for _ in range(J):
+        if prob.fine_kind == "linear":
+            v = schemes.step_stab(v, tau, prob.eps, prob.s_fine, prob.f_zero)
+        elif prob.fine_kind == "nonlinear":
+            v = schemes.step_newton(v, tau, prob.eps, prob.nl_variant,
+                                    prob.newton_tol, prob.newton_max, prob.f_zero)
+        else:
+            raise ValueError(prob.fine_kind)
+    return v
+
+
+def coarse(prob, u: np.ndarray, kind: str | None = None, nn_params=None) -> np.ndarray:
+    """G(T_{n+1}, T_n, u): m_coarse steps of tau = dT/m_coarse of scheme (2.4)
+    ("approx2"), of the stabilised step ("stab"), or the learned surrogate."""
+    kind = prob.coarse_kind if kind is None else kind
+    v = np.array(u, dtype=np.float64, copy=True)
+    if kind == "neural":
+        from . import nn
+        return nn.surrogate_step(nn_params, v)
+    m = prob.m_coarse
+    tau = prob.dT / m
+    for _ in range(m):
+        if kind == "approx2":
+            v = schemes.step_approx2(v, tau, prob.eps, prob.f_zero)
+        elif kind == "stab":
+            v = schemes.step_stab(v, tau, prob.eps, prob.s_fine, prob.f_zero)
+        else:
+            raise ValueError(kind)
+    return v
+
+
+def fine_sequential(prob, u0: np.ndarray) -> list:
+    """The serial fine solution at every T_n: [u0, F(u0), F(F(u0)), ...]."""
+    out = [np.array(u0, dtype=np.float64, copy=True)]
+    for _ in range(prob.n_slices):
+        out.append(fine(prob, out[-1]))
+    return out

@@ -1,0 +1,127 @@
+"""Pins of the oracle's Parareal iteration (2.2).
+
+* a closed form: for linear propagators acting on one eigenmode the
+  iteration is a scalar recurrence whose solution is the truncated binomial
+  expansion of the fine power, sum_{j<=k} binom(n,j) (phi-gam)^j gam^{n-j};
+* finite termination (proof of Theorem 3.7): U_n^k equals the sequential fine
+  value bit for bit for n <= k, and k = N reproduces the whole fine solve;
+* G = F converges in one iteration;
+* the error bound of Theorems 3.7/3.9/3.11 on the linearised model.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import linear_model as lm, operators as ops, parareal, propagators
+import workloads
+
+
+def _norm1(v):
+    return ops.norm_h(v, v.ndim)
+
+
+def test_linear_mode_closed_form():
+    n, N, dT, J, eps = 15, 7, 0.05, 12, 0.08
+    PJ = lm.propagator_matrix(n, 1, dT / J, eps, 2.0, J)   # fine (2.5) form
+    P = lm.propagator_matrix(n, 1, dT, eps, 1.0, 1)        # coarse (2.4) form
+    S = ops.sine_matrix(n)
+    p = 2
+    u0 = S[:, p].copy()
+    phi = float(u0 @ PJ @ u0)
+    gam = float(u0 @ P @ u0)
+    out = parareal.parareal(u0, N, lambda u: PJ @ u, lambda u: P @ u, _norm1, tol=0.0)
+    for k, Uk in enumerate(out["U"]):
+        for nn in range(N + 1):
+            c = sum(math.comb(nn, j) * (phi - gam) ** j * gam ** (nn - j) for j in range(0, min(k, nn) + 1))
+            assert np.max(np.abs(Uk[nn] - c * u0)) < 1e-13, (k, nn)
+
+
+def _small_problem(kind="linear"):
+    p = workloads.Problem(dim=1, n=32, eps=0.05, T=0.12, n_slices=6, j_fine=20,
+                          m_coarse=1, fine_kind=kind)
+    u0 = workloads.u0_uniform(32, 1, 0.3, 0)
+    return p, u0
+
+
+@pytest.mark.parametrize("kind", ["linear", "nonlinear"])
+def test_finite_termination_bitwise(kind):
+    prob, u0 = _small_problem(kind)
+    seq = propagators.fine_sequential(prob, u0)
+    out = parareal.parareal(u0, prob.n_slices, lambda u: propagators.fine(prob, u),
+                            lambda u: propagators.coarse(prob, u), _norm1, tol=0.0)
+    assert out["k"] == prob.n_slices
+    for k, Uk in enumerate(out["U"]):
+        for nn in range(0, min(k, prob.n_slices) + 1):
+            assert np.array_equal(Uk[nn], seq[nn]), (k, nn)
+    for nn in range(prob.n_slices + 1):
+        assert np.array_equal(out["final"][nn], seq[nn])
+
+
+def test_skip_converged_changes_nothing():
+    prob, u0 = _small_problem()
+    kw = dict(norm=_norm1, tol=0.0)
+    Ff = lambda u: propagators.fine(prob, u)
+    Gf = lambda u: propagators.coarse(prob, u)
+    a = parareal.parareal(u0, prob.n_slices, Ff, Gf, **kw)
+    b = parareal.parareal(u0, prob.n_slices, Ff, Gf, skip_converged=True, **kw)
+    for Ua, Ub in zip(a["U"], b["U"]):
+        for x, y in zip(Ua, Ub):
+            assert np.array_equal(x, y)
+    assert a["delta"] == b["delta"]
+
+
+def test_g_equal_f_converges_in_one_iteration():
+    prob, u0 = _small_problem()
+    Ff = lambda u: propagators.fine(prob, u)
+    out = parareal.parareal(u0, prob.n_slices, Ff, Ff, _norm1, tol=1e-300)
+    assert out["delta"][0] == 0.0 and out["k"] == 1
+    seq = propagators.fine_sequential(prob, u0)
+    for nn in range(prob.n_slices + 1):
+        assert np.array_equal(out["final"][nn], seq[nn])
+
+
+def test_fallback_from_bad_coarse_still_reaches_fine_solution():
+    prob, u0 = _small_problem()
+    Ff = lambda u: propagators.fine(prob, u)
+    Gp = lambda u: propagators.coarse(prob, u)
+    bad = lambda u: 2.0 * propagators.coarse(prob, u)   # a corrupted surrogate
+    out = parareal.parareal(u0, prob.n_slices, Ff, bad, _norm1, tol=1e-12, fallback_G=Gp)
+    assert out["fallback_at"] == 2          # delta^2 >= delta^1 triggers it
+    assert out["delta"][2] < out["delta"][1]  # and the plain G contracts again
+    seq = propagators.fine_sequential(prob, u0)
+    err = max(_norm1(out["final"][i] - seq[i]) for i in range(prob.n_slices + 1))
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("i_fine,i_coarse", [(1, 1), (2, 2), (2, 1)])
+def test_linearised_error_bound(i_fine, i_coarse):
+    # PA-I, PA-II, PA-III on the linearised model (Theorems 3.7, 3.9, 3.11)
+    n, N, dT, J, eps = 15, 10, 0.02, 20, 0.1
+    PJ = lm.propagator_matrix(n, 1, dT / J, eps, i_fine, J)
+    P = lm.propagator_matrix(n, 1, dT, eps, i_coarse, 1)
+    alpha = float(np.linalg.norm(PJ - P, 2))
+    beta = float(np.linalg.norm(P, 2))
+    assert 0 < beta < 1  # Lemma 3.1
+    u0 = np.random.default_rng(4).uniform(-1, 1, n)
+    exact = [u0]
+    for _ in range(N):
+        exact.append(PJ @ exact[-1])
+    out = parareal.parareal(u0, N, lambda u: PJ @ u, lambda u: P @ u,
+                            lambda v: float(np.linalg.norm(v)), tol=0.0)
+    e0 = max(np.linalg.norm(out["U"][0][j] - exact[j]) for j in range(1, N + 1))
+    for k in range(1, N + 1):
+        ek = max(np.linalg.norm(out["U"][k][j] - exact[j]) for j in range(1, N + 1))
+        assert ek <= lm.bound_factor(alpha, beta, N, k) * e0 * (1 + 1e-9) + 1e-14
+
+
+def test_toeplitz_power_first_column_lemma_3_4():
+    beta, N = 0.7, 9
+    T = lm.toeplitz_T(beta, N)
+    for k in range(1, N):
+        Tk = np.linalg.matrix_power(T, k)
+        for i in range(1, N + 1):   # 1-based row index of Lemma 3.4
+            ref = 0.0 if i <= k else math.comb(i - 2, k - 1) * beta ** (i - 1 - k)
+            assert abs(Tk[i - 1, 0] - ref) < 1e-13
+        # Lemma 3.5
+        assert np.max(np.sum(np.abs(Tk), axis=1)) <= min(((1 - beta ** (N - 1)) / (1 - beta)) ** k, math.comb(N - 1, k)) + 1e-12
