@@ -1,0 +1,136 @@
+/*
+ * ch.h -- C ABI of the MI355X (gfx950) Parareal library for the Cahn-Hilliard
+ * equation  u_t + eps^2 Lap^2 u = Lap f(u),  f(u) = u^3 - u,  u = Lap u = 0 on
+ * the boundary of (0,1)^d  (paper: Section 1, equation (1.1)).
+ *
+ * The library advances many independent instances ("problems") of the
+ * equation, each split into N time slices of length dT = T/N (Section 2).
+ * All device memory is owned by the caller: the library never allocates
+ * device memory; it asks for a workspace size and works inside the buffer it
+ * is given.  Every call is asynchronous on the given HIP stream.
+ *
+ * Data layout (all float64, row-major, interior points only, y slowest):
+ *   one state           : n^d values, index iy*n + ix;
+ *   "slice layout"      : for instance i, N_i states (the inputs of its N_i
+ *                         slices), instances packed in creation order;
+ *                         ch_layout() reports the offsets;
+ *   "iterate layout"    : for instance i, N_i + 1 states U_0..U_N.
+ *
+ * Errors: every entry returns a ch_status; argument problems are detected
+ * on the host before any launch; a HIP error reports CH_ERR_HIP; the text of
+ * the last error is available from ch_last_error().  No entry point throws.
+ * A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CH_H
+#define CH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ch_status {
+  CH_OK = 0,
+  CH_ERR_ARG = 1,          /* invalid argument or layout                      */
+  CH_ERR_HIP = 2,          /* a HIP runtime call or kernel launch failed       */
+  CH_ERR_UNSUPPORTED = 3,  /* valid problem the kernels do not cover (n, dim) */
+  CH_ERR_NOCONV = 4,       /* Newton or Krylov iteration cap, or non-finite   */
+  CH_ERR_STATE = 5         /* call order violated (e.g. workspace not bound)  */
+} ch_status;
+
+/* fine propagator: linear stabilised step (scheme (2.5) for s = 2), or the
+ * implicit step solved by Newton's method (scheme (2.3), or backward Euler) */
+enum { CH_FINE_LINEAR = 0, CH_FINE_NONLINEAR = 1 };
+enum { CH_NL_EYRE = 0, CH_NL_FULL_BE = 1 };
+/* coarse propagator: scheme (2.4) (default), the stabilised step, or the
+ * learned surrogate (weights bound with ch_nn_bind) */
+enum { CH_COARSE_APPROX2 = 0, CH_COARSE_STAB = 1, CH_COARSE_NEURAL = 2 };
+/* arithmetic of the sine transforms of the linear fine step */
+enum { CH_PREC_FP64 = 0, CH_PREC_SPLIT_BF16 = 1 };
+
+typedef struct ch_problem {
+  int32_t dim;          /* 1 or 2                                              */
+  int32_t n;            /* interior points per dimension, h = 1/(n+1)          */
+  double eps;           /* interface width                                     */
+  double T;             /* final time                                          */
+  int32_t n_slices;     /* Parareal slices N (dT = T/N)                        */
+  int32_t j_fine;       /* fine steps per slice J (dt = dT/J), Section 2       */
+  int32_t m_coarse;     /* coarse sub-steps per slice (paper: 1)               */
+  double s_fine;        /* stabilisation constant s of the linear step (2.0)   */
+  int32_t fine_kind;    /* CH_FINE_*                                           */
+  int32_t nl_variant;   /* CH_NL_*                                             */
+  int32_t coarse_kind;  /* CH_COARSE_*                                         */
+  int32_t precision;    /* CH_PREC_*                                           */
+  double newton_tol;    /* Newton stop: ||Y_{m+1}-Y_m||_h <= tol (1e-10)       */
+  int32_t newton_max;   /* Newton iteration cap (20)                           */
+  double krylov_rtol;   /* relative residual target of the inner CG solves    */
+  int32_t krylov_max;   /* CG iteration cap                                    */
+  int32_t f_zero;       /* test hook: f(u) == 0                                */
+} ch_problem;
+
+typedef struct ch_ctx ch_ctx;
+typedef void* ch_stream; /* a hipStream_t (NULL = default stream) */
+
+/* Iterate state of ch_parareal_iterate; every pointer is device memory owned
+ * by the caller, sized from ch_layout().  U_0 of each instance holds u0. */
+typedef struct ch_pr_state {
+  double* U;          /* iterate layout: U_n^k, n = 0..N_i                      */
+  double* F;          /* slice layout: F(U_n^k) of the latest fine sweep        */
+  double* G_old;      /* slice layout: G(U_n^k) kept for the correction         */
+  double* delta;      /* [n_inst]: update norm max_n ||U_n^{k+1}-U_n^k||_h      */
+  int32_t* status;    /* [n_inst]: 0 ok; 1 = solver cap hit; 2 = non-finite     */
+  int32_t k;          /* host: corrections done so far                          */
+  int32_t predicted;  /* host: 1 once the coarse prediction U^0 has been formed */
+} ch_pr_state;
+
+/* Validate the problems and plan the device work.  Host-only. */
+ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out);
+ch_status ch_destroy(ch_ctx* ctx);
+
+/* Bytes of device workspace the context needs (tables and solver scratch). */
+ch_status ch_workspace_size(const ch_ctx* ctx, size_t* bytes);
+/* Hand the context its workspace (256-byte aligned device pointer) and upload
+ * its tables on `stream`.  Must precede every compute call. */
+ch_status ch_bind_workspace(ch_ctx* ctx, void* dptr, size_t bytes, ch_stream stream);
+
+/* Element counts of the slice layout and the iterate layout, and the offsets
+ * of instance `inst` in both (in float64 elements). */
+ch_status ch_layout(const ch_ctx* ctx, int32_t inst, int64_t* slice_total, int64_t* iter_total,
+                    int64_t* slice_off, int64_t* iter_off);
+
+/* F(T_{n+1}, T_n, U_n) for every slice whose mask byte is non-zero (all if
+ * mask is NULL): J fine steps of dt = dT/J (Section 2).  U_in and F_out use
+ * the slice layout and must not overlap; mask is device memory, one byte per
+ * slice in slice-layout order. */
+ch_status ch_fine_propagate(ch_ctx* ctx, const double* U_in, double* F_out,
+                            const uint8_t* slice_mask, ch_stream stream);
+
+/* G(T_{n+1}, T_n, U_n), independently for every masked slice (same layout
+ * and rules as ch_fine_propagate). */
+ch_status ch_coarse_propagate(ch_ctx* ctx, const double* U_in, double* G_out,
+                              const uint8_t* slice_mask, ch_stream stream);
+
+/* One step of the Parareal iteration (2.2) for every instance.
+ * First call (st->predicted == 0): the coarse prediction U_{n+1}^0 = G(U_n^0),
+ * G_old_n = U_{n+1}^0.  Later calls: the fine sweep F_n = F(U_n^k) over the
+ * slices n >= k (earlier ones are final, finite termination), then the
+ * sequential correction U_{n+1}^{k+1} = F_n + (G(U_n^{k+1}) - G_old_n) and
+ * the update norm into st->delta.  Instances whose previous delta was below
+ * tol are left unchanged.  No host synchronisation inside. */
+ch_status ch_parareal_iterate(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream);
+
+/* Discrete energy (Section 1, (1.2)) of `count` states of instance `inst`:
+ * E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u).  E_out is
+ * device memory of `count` doubles. */
+ch_status ch_energy(ch_ctx* ctx, int32_t inst, const double* u, int32_t count, double* E_out,
+                    ch_stream stream);
+
+const char* ch_status_str(ch_status s);
+const char* ch_last_error(const ch_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CH_H */

@@ -1,0 +1,172 @@
+"""ctypes binding of libch.so (C ABI declared in include/ch.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch provides the device memory (workspace, states) and the
+stream.  Names mirror the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libch.so")
+
+CH_OK, CH_ERR_ARG, CH_ERR_HIP, CH_ERR_UNSUPPORTED, CH_ERR_NOCONV, CH_ERR_STATE = range(6)
+FINE = {"linear": 0, "nonlinear": 1}
+NL = {"eyre": 0, "be": 1}
+COARSE = {"approx2": 0, "stab": 1, "neural": 2}
+PREC = {"fp64": 0, "split_bf16": 1}
+
+# every symbol include/ch.h declares
+EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
+           "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate", "ch_energy",
+           "ch_status_str", "ch_last_error")
+
+
+class ChProblem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("T", ctypes.c_double), ("n_slices", ctypes.c_int32), ("j_fine", ctypes.c_int32),
+                ("m_coarse", ctypes.c_int32), ("s_fine", ctypes.c_double),
+                ("fine_kind", ctypes.c_int32), ("nl_variant", ctypes.c_int32),
+                ("coarse_kind", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("newton_tol", ctypes.c_double), ("newton_max", ctypes.c_int32),
+                ("krylov_rtol", ctypes.c_double), ("krylov_max", ctypes.c_int32),
+                ("f_zero", ctypes.c_int32)]
+
+
+class ChPrState(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_void_p), ("F", ctypes.c_void_p), ("G_old", ctypes.c_void_p),
+                ("delta", ctypes.c_void_p), ("status", ctypes.c_void_p), ("k", ctypes.c_int32),
+                ("predicted", ctypes.c_int32)]
+
+
+class CHError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libch.so; raise if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CHError(f"{LIB_PATH} is missing: build it with paper_2304_14074_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    lib.ch_create.argtypes = [ctypes.POINTER(ChProblem), i32, ctypes.POINTER(vp)]
+    lib.ch_destroy.argtypes = [vp]
+    lib.ch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ch_bind_workspace.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.ch_layout.argtypes = [vp, i32, i64p, i64p, i64p, i64p]
+    lib.ch_fine_propagate.argtypes = [vp, vp, vp, vp, vp]
+    lib.ch_coarse_propagate.argtypes = [vp, vp, vp, vp, vp]
+    lib.ch_parareal_iterate.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, vp]
+    lib.ch_energy.argtypes = [vp, i32, vp, i32, vp, vp]
+    lib.ch_status_str.argtypes = [i32]
+    lib.ch_status_str.restype = ctypes.c_char_p
+    lib.ch_last_error.argtypes = [vp]
+    lib.ch_last_error.restype = ctypes.c_char_p
+    for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
+                 "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate", "ch_energy"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def to_problem(p) -> ChProblem:
+    """Marshal any object with the problem attributes (dim, n, eps, ...)."""
+    g = lambda name, default: getattr(p, name, default)
+    return ChProblem(dim=int(g("dim", 2)), n=int(g("n", 128)), eps=float(g("eps", 0.02)),
+                     T=float(g("T", 1.0)), n_slices=int(g("n_slices", 1)),
+                     j_fine=int(g("j_fine", 1)), m_coarse=int(g("m_coarse", 1)),
+                     s_fine=float(g("s_fine", 2.0)), fine_kind=FINE[g("fine_kind", "linear")],
+                     nl_variant=NL[g("nl_variant", "eyre")],
+                     coarse_kind=COARSE[g("coarse_kind", "approx2")],
+                     precision=PREC[g("precision", "fp64")],
+                     newton_tol=float(g("newton_tol", 1e-10)), newton_max=int(g("newton_max", 20)),
+                     krylov_rtol=float(g("krylov_rtol", 1e-13)),
+                     krylov_max=int(g("krylov_max", 200)), f_zero=int(bool(g("f_zero", False))))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One ch_ctx with its workspace (a torch uint8 tensor on the device)."""
+
+    def __init__(self, problems, device="cuda"):
+        self.lib = load()
+        self.problems = list(problems)
+        arr = (ChProblem * len(self.problems))(*[to_problem(p) for p in self.problems])
+        handle = ctypes.c_void_p()
+        st = self.lib.ch_create(arr, len(self.problems), ctypes.byref(handle))
+        if st != CH_OK:
+            raise CHError(f"ch_create: {self.lib.ch_status_str(st).decode()}")
+        self.h = handle
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.ch_workspace_size(self.h, ctypes.byref(nbytes)))
+        self.device = torch.device(device)
+        # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.ch_bind_workspace(self.h, _ptr(self.workspace), nbytes.value, _stream()))
+        self.slice_total, self.iter_total = self.layout(0)[:2]
+
+    def _check(self, st):
+        if st != CH_OK:
+            msg = self.lib.ch_last_error(self.h).decode() if getattr(self, "h", None) else ""
+            raise CHError(f"{self.lib.ch_status_str(st).decode()}: {msg}")
+
+    def layout(self, inst):
+        a, b, c, d = (ctypes.c_int64() for _ in range(4))
+        self._check(self.lib.ch_layout(self.h, inst, ctypes.byref(a), ctypes.byref(b),
+                                       ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def ch_fine_propagate(self, U_in, F_out, mask=None, stream=None):
+        self._check(self.lib.ch_fine_propagate(self.h, _ptr(U_in), _ptr(F_out), _ptr(mask), _stream(stream)))
+
+    def ch_coarse_propagate(self, U_in, G_out, mask=None, stream=None):
+        self._check(self.lib.ch_coarse_propagate(self.h, _ptr(U_in), _ptr(G_out), _ptr(mask), _stream(stream)))
+
+    def new_state(self):
+        """Device buffers of one Parareal run (U_0 of each instance still to be set)."""
+        dev = self.device
+        n = len(self.problems)
+        return {"U": torch.zeros(self.iter_total, dtype=torch.float64, device=dev),
+                "F": torch.zeros(self.slice_total, dtype=torch.float64, device=dev),
+                "G_old": torch.zeros(self.slice_total, dtype=torch.float64, device=dev),
+                "delta": torch.full((n,), float("inf"), dtype=torch.float64, device=dev),
+                "status": torch.zeros(n, dtype=torch.int32, device=dev),
+                "c": ChPrState(0, 0, 0, 0, 0, 0, 0)}
+
+    def ch_parareal_iterate(self, state, tol, stream=None):
+        c = state["c"]
+        c.U, c.F, c.G_old = state["U"].data_ptr(), state["F"].data_ptr(), state["G_old"].data_ptr()
+        c.delta, c.status = state["delta"].data_ptr(), state["status"].data_ptr()
+        self._check(self.lib.ch_parareal_iterate(self.h, ctypes.byref(c), float(tol), _stream(stream)))
+
+    def ch_energy(self, inst, u, count, E_out, stream=None):
+        self._check(self.lib.ch_energy(self.h, inst, _ptr(u), count, _ptr(E_out), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,438 @@
+// Host runtime behind the C ABI of include/ch.h: validation, workspace
+// planning, table generation, kernel dispatch.  The library allocates no
+// device memory: all tables and scratch live in the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ch.h"
+#include "ch_internal.h"
+
+using chk::InstDev;
+using chk::WorkItem;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Sub-allocation plan of the workspace (byte offsets).
+struct Block {
+  size_t off = 0, bytes = 0;
+};
+
+struct ClassPlan {      // all instances sharing (dim, n)
+  int dim = 2, n = 0;
+  std::vector<WorkItem> items;   // every slice of every instance in the class
+  std::vector<int32_t> insts;    // instance indices
+  Block items_blk, insts_blk;
+  Block sine_blk;                // 2D: Se | So | lam ; 1D: S | lam
+};
+
+}  // namespace
+
+struct ch_ctx {
+  std::vector<ch_problem> probs;
+  std::vector<InstDev> inst;        // host copy (device pointers filled at bind)
+  std::vector<int64_t> slice_off, iter_off;
+  int64_t slice_total = 0, iter_total = 0;
+  std::vector<ClassPlan> classes;
+  Block inst_blk, active_blk;
+  std::vector<Block> rsig_fine_blk, rsig_stab_blk, cg_blk;
+  size_t ws_bytes = 0;
+  char* ws = nullptr;               // bound workspace
+  std::string err;
+};
+
+namespace {
+
+ch_status fail(ch_ctx* c, ch_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+ch_status hip_check(ch_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return CH_OK;
+  return fail(c, CH_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// sin(j k pi / (n+1)) with the integer product reduced modulo 2(n+1) first,
+// so the argument stays in [0, 2 pi) and carries no large-argument error.
+double sine_entry(long j, long k, long n) {
+  const long period = 2 * (n + 1);
+  const long m = (j * k) % period;
+  const long double ang = (long double)m * 3.14159265358979323846264338327950288L / (long double)(n + 1);
+  return (double)(std::sqrt(2.0L / (long double)(n + 1)) * sinl(ang));
+}
+// Eigenvalues of the Dirichlet difference Laplacian (1-based p):
+// lam_p = (2/h^2)(cos(p pi/(n+1)) - 1) = -(4/h^2) sin^2(p pi / (2(n+1))).
+double lap_eig(long p, long n) {
+  const long double h = 1.0L / (long double)(n + 1);
+  const long double sn = sinl((long double)p * 3.14159265358979323846264338327950288L /
+                              (2.0L * (long double)(n + 1)));
+  return (double)(-4.0L / (h * h) * sn * sn);
+}
+
+bool supported_2d(int n) { return n == 32 || n == 64 || n == 128; }
+
+}  // namespace
+
+extern "C" {
+
+const char* ch_status_str(ch_status s) {
+  switch (s) {
+    case CH_OK: return "CH_OK";
+    case CH_ERR_ARG: return "CH_ERR_ARG";
+    case CH_ERR_HIP: return "CH_ERR_HIP";
+    case CH_ERR_UNSUPPORTED: return "CH_ERR_UNSUPPORTED";
+    case CH_ERR_NOCONV: return "CH_ERR_NOCONV";
+    case CH_ERR_STATE: return "CH_ERR_STATE";
+  }
+  return "CH_ERR_UNKNOWN";
+}
+
+const char* ch_last_error(const ch_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
+  if (!out) return CH_ERR_ARG;
+  *out = nullptr;
+  if (!probs || n_inst <= 0) return CH_ERR_ARG;
+  ch_ctx* c = new ch_ctx();
+  c->probs.assign(probs, probs + n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const ch_problem& p = probs[i];
+    ch_status bad = CH_OK;
+    if (p.dim != 1 && p.dim != 2) bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: dim %d", i, p.dim);
+    else if (p.n < 2) bad = fail(c, CH_ERR_ARG, "instance %d: n = %d", i, p.n);
+    else if (!(p.eps > 0) || !(p.T > 0) || !(p.s_fine >= 0))
+      bad = fail(c, CH_ERR_ARG, "instance %d: eps, T must be > 0 and s >= 0", i);
+    else if (p.n_slices < 1 || p.j_fine < 1 || p.m_coarse < 1)
+      bad = fail(c, CH_ERR_ARG, "instance %d: n_slices, j_fine, m_coarse must be >= 1", i);
+    else if (p.krylov_max < 1 || !(p.krylov_rtol > 0))
+      bad = fail(c, CH_ERR_ARG, "instance %d: krylov_max >= 1 and krylov_rtol > 0 needed", i);
+    else if (p.fine_kind != CH_FINE_LINEAR && p.fine_kind != CH_FINE_NONLINEAR)
+      bad = fail(c, CH_ERR_ARG, "instance %d: fine_kind %d", i, p.fine_kind);
+    else if (p.coarse_kind < CH_COARSE_APPROX2 || p.coarse_kind > CH_COARSE_NEURAL)
+      bad = fail(c, CH_ERR_ARG, "instance %d: coarse_kind %d", i, p.coarse_kind);
+    else if (p.precision != CH_PREC_FP64 && p.precision != CH_PREC_SPLIT_BF16)
+      bad = fail(c, CH_ERR_ARG, "instance %d: precision %d", i, p.precision);
+    else if (p.fine_kind == CH_FINE_NONLINEAR)
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: nonlinear fine step not built", i);
+    else if (p.coarse_kind == CH_COARSE_NEURAL)
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: neural coarse propagator not built", i);
+    else if (p.precision == CH_PREC_SPLIT_BF16)
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: split-bf16 not built", i);
+    else if (p.dim == 2 && !supported_2d(p.n))
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 2D n = %d (kernels cover 32, 64, 128)", i, p.n);
+    else if (p.dim == 1 && (p.n > 128 || p.n % 2))
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 1D n = %d (even n <= 128)", i, p.n);
+    if (bad != CH_OK) {
+      ch_status s = bad;
+      // keep the message for the caller: the context is not returned, so
+      // print it to stderr as well.
+      fprintf(stderr, "ch_create: %s\n", c->err.c_str());
+      delete c;
+      return s;
+    }
+  }
+  // layouts
+  c->slice_off.resize(n_inst);
+  c->iter_off.resize(n_inst);
+  int64_t so = 0, io = 0, slice_base = 0;
+  c->inst.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const ch_problem& p = probs[i];
+    const int64_t P = p.dim == 2 ? (int64_t)p.n * p.n : p.n;
+    c->slice_off[i] = so;
+    c->iter_off[i] = io;
+    InstDev& d = c->inst[i];
+    memset(&d, 0, sizeof d);
+    d.dim = p.dim; d.n = p.n; d.n_slices = p.n_slices; d.j_fine = p.j_fine;
+    d.m_coarse = p.m_coarse; d.coarse_kind = p.coarse_kind; d.fine_kind = p.fine_kind;
+    d.nl_variant = p.nl_variant; d.f_zero = p.f_zero; d.krylov_max = p.krylov_max;
+    d.newton_max = p.newton_max; d.precision = p.precision;
+    d.eps = p.eps; d.dT = p.T / p.n_slices; d.dt = d.dT / p.j_fine; d.s_fine = p.s_fine;
+    d.h = 1.0 / (p.n + 1); d.newton_tol = p.newton_tol; d.krylov_rtol = p.krylov_rtol;
+    d.off_slices = so; d.off_iter = io; d.slice_base = slice_base;
+    so += (int64_t)p.n_slices * P;
+    io += (int64_t)(p.n_slices + 1) * P;
+    slice_base += p.n_slices;
+  }
+  c->slice_total = so;
+  c->iter_total = io;
+  // classes
+  std::map<std::pair<int, int>, int> cls;
+  for (int i = 0; i < n_inst; ++i) {
+    auto key = std::make_pair(probs[i].dim, probs[i].n);
+    if (!cls.count(key)) {
+      cls[key] = (int)c->classes.size();
+      ClassPlan cp;
+      cp.dim = probs[i].dim;
+      cp.n = probs[i].n;
+      c->classes.push_back(cp);
+    }
+    ClassPlan& cp = c->classes[cls[key]];
+    cp.insts.push_back(i);
+    for (int s = 0; s < probs[i].n_slices; ++s) cp.items.push_back(WorkItem{i, s});
+  }
+  // workspace plan
+  size_t off = 0;
+  auto take = [&](size_t bytes) { Block b; b.off = off; b.bytes = bytes; off = align_up(off + bytes); return b; };
+  c->inst_blk = take(sizeof(InstDev) * n_inst);
+  c->active_blk = take(sizeof(int32_t) * n_inst);
+  for (auto& cp : c->classes) {
+    cp.items_blk = take(sizeof(WorkItem) * cp.items.size());
+    cp.insts_blk = take(sizeof(int32_t) * cp.insts.size());
+    const size_t n = cp.n;
+    cp.sine_blk = cp.dim == 2 ? take(sizeof(double) * (2 * (n / 2) * (n / 2) + n))
+                              : take(sizeof(double) * (n * n + n));
+  }
+  c->rsig_fine_blk.resize(n_inst);
+  c->rsig_stab_blk.resize(n_inst);
+  c->cg_blk.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const size_t P = probs[i].dim == 2 ? (size_t)probs[i].n * probs[i].n : probs[i].n;
+    c->rsig_fine_blk[i] = take(sizeof(double) * P);
+    c->rsig_stab_blk[i] = take(sizeof(double) * P);
+    if (probs[i].dim == 2) c->cg_blk[i] = take(sizeof(double) * P * chk::CG_VECS);
+  }
+  c->ws_bytes = off;
+  *out = c;
+  return CH_OK;
+}
+
+ch_status ch_destroy(ch_ctx* ctx) {
+  delete ctx;
+  return CH_OK;
+}
+
+ch_status ch_workspace_size(const ch_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return CH_ERR_ARG;
+  *bytes = ctx->ws_bytes;
+  return CH_OK;
+}
+
+ch_status ch_layout(const ch_ctx* ctx, int32_t inst, int64_t* slice_total, int64_t* iter_total,
+                    int64_t* slice_off, int64_t* iter_off) {
+  if (!ctx) return CH_ERR_ARG;
+  if (inst < 0 || inst >= (int32_t)ctx->probs.size()) return CH_ERR_ARG;
+  if (slice_total) *slice_total = ctx->slice_total;
+  if (iter_total) *iter_total = ctx->iter_total;
+  if (slice_off) *slice_off = ctx->slice_off[inst];
+  if (iter_off) *iter_off = ctx->iter_off[inst];
+  return CH_OK;
+}
+
+ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream stream) {
+  if (!c) return CH_ERR_ARG;
+  if (!dptr || (reinterpret_cast<uintptr_t>(dptr) % kAlign) != 0)
+    return fail(c, CH_ERR_ARG, "workspace must be a non-null 256-byte aligned device pointer");
+  if (bytes < c->ws_bytes)
+    return fail(c, CH_ERR_ARG, "workspace too small: %zu < %zu bytes", bytes, c->ws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)dptr;
+  c->ws = ws;
+  const int n_inst = (int)c->probs.size();
+  // host images of everything, copied in one pass
+  std::vector<char> img(c->ws_bytes, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    InstDev& d = c->inst[i];
+    const ch_problem& p = c->probs[i];
+    d.rsig_fine = (const double*)(ws + c->rsig_fine_blk[i].off);
+    d.rsig_stab = (const double*)(ws + c->rsig_stab_blk[i].off);
+    d.cg = p.dim == 2 ? (double*)(ws + c->cg_blk[i].off) : nullptr;
+    // inverse symbols 1/(1 + tau eps^2 Lam^2 - s tau Lam) of the linear step
+    const int n = p.n;
+    std::vector<double> lam(n);
+    for (int k = 0; k < n; ++k) lam[k] = lap_eig(k + 1, n);
+    auto fill = [&](Block b, double tau) {
+      double* t = (double*)(img.data() + b.off);
+      if (p.dim == 2) {
+        for (int r = 0; r < n; ++r)
+          for (int q = 0; q < n; ++q) {
+            const double L = lam[r] + lam[q];
+            t[r * n + q] = 1.0 / (1.0 + tau * p.eps * p.eps * L * L - p.s_fine * tau * L);
+          }
+      } else {
+        for (int r = 0; r < n; ++r) {
+          const double L = lam[r];
+          t[r] = 1.0 / (1.0 + tau * p.eps * p.eps * L * L - p.s_fine * tau * L);
+        }
+      }
+    };
+    fill(c->rsig_fine_blk[i], d.dt);
+    fill(c->rsig_stab_blk[i], d.dT / p.m_coarse);
+  }
+  memcpy(img.data() + c->inst_blk.off, c->inst.data(), sizeof(InstDev) * n_inst);
+  for (auto& cp : c->classes) {
+    memcpy(img.data() + cp.items_blk.off, cp.items.data(), sizeof(WorkItem) * cp.items.size());
+    memcpy(img.data() + cp.insts_blk.off, cp.insts.data(), sizeof(int32_t) * cp.insts.size());
+    const int n = cp.n;
+    double* t = (double*)(img.data() + cp.sine_blk.off);
+    if (cp.dim == 2) {
+      const int H = n / 2;
+      // Se[a][m] = S[a][2m], So[a][m] = S[a][2m+1]  (0-based), then lam
+      for (int a = 0; a < H; ++a)
+        for (int m = 0; m < H; ++m) {
+          t[a * H + m] = sine_entry(a + 1, 2 * m + 1, n);
+          t[H * H + a * H + m] = sine_entry(a + 1, 2 * m + 2, n);
+        }
+      for (int k = 0; k < n; ++k) t[2 * H * H + k] = lap_eig(k + 1, n);
+    } else {
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) t[a * n + b] = sine_entry(a + 1, b + 1, n);
+      for (int k = 0; k < n; ++k) t[n * n + k] = lap_eig(k + 1, n);
+    }
+  }
+  ch_status st = hip_check(c, hipMemcpyAsync(ws, img.data(), c->ws_bytes, hipMemcpyHostToDevice, s),
+                           "workspace upload");
+  if (st != CH_OK) return st;
+  for (auto& cp : c->classes) {
+    if (cp.dim != 2) continue;
+    const double* lam = (const double*)(ws + cp.sine_blk.off) + 2 * (cp.n / 2) * (cp.n / 2);
+    st = hip_check(c, chk::launch_cg_tables(cp.n, 2, (const int32_t*)(ws + cp.insts_blk.off),
+                                            (int)cp.insts.size(),
+                                            (const InstDev*)(ws + c->inst_blk.off), lam, s),
+                   "cg tables");
+    if (st != CH_OK) return st;
+  }
+  // the host image must outlive the copy
+  return hip_check(c, hipStreamSynchronize(s), "bind synchronize");
+}
+
+static ch_status require_bound(ch_ctx* c) {
+  if (!c) return CH_ERR_ARG;
+  if (!c->ws) return fail(c, CH_ERR_STATE, "workspace not bound");
+  return CH_OK;
+}
+
+static const double* class_sine(const ch_ctx* c, const ClassPlan& cp) {
+  return (const double*)(c->ws + cp.sine_blk.off);
+}
+
+static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const uint8_t* mask,
+                          const int32_t* active, int k_min, int in_iter, hipStream_t s) {
+  const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
+  for (auto& cp : c->classes) {
+    const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
+    const double* tab = class_sine(c, cp);
+    hipError_t e;
+    if (cp.dim == 2) {
+      const int H = cp.n / 2;
+      e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, tab + H * H, U_in, F_out,
+                              mask, active, k_min, in_iter, s);
+    } else {
+      e = chk::launch_fine_1d(cp.n, items, (int)cp.items.size(), inst, tab, nullptr, U_in, F_out,
+                              mask, active, k_min, in_iter, s);
+    }
+    ch_status st = hip_check(c, e, "fine sweep launch");
+    if (st != CH_OK) return st;
+  }
+  return CH_OK;
+}
+
+ch_status ch_fine_propagate(ch_ctx* c, const double* U_in, double* F_out, const uint8_t* mask,
+                            ch_stream stream) {
+  ch_status st = require_bound(c);
+  if (st != CH_OK) return st;
+  if (!U_in || !F_out) return fail(c, CH_ERR_ARG, "null state pointer");
+  const size_t bytes = sizeof(double) * c->slice_total;
+  const char *a = (const char*)U_in, *b = (const char*)F_out;
+  if (a < b + bytes && b < a + bytes) return fail(c, CH_ERR_ARG, "U_in and F_out overlap");
+  return fine_all(c, U_in, F_out, mask, nullptr, 0, 0, (hipStream_t)stream);
+}
+
+static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_out,
+                            const uint8_t* mask, ch_pr_state* st, int k, hipStream_t s) {
+  const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
+  const int32_t* active = mode == 0 ? nullptr : (const int32_t*)(c->ws + c->active_blk.off);
+  for (auto& cp : c->classes) {
+    const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
+    const int32_t* insts = (const int32_t*)(c->ws + cp.insts_blk.off);
+    const double* tab = class_sine(c, cp);
+    double* U = st ? st->U : nullptr;
+    const double* F = st ? st->F : nullptr;
+    double* Gold = st ? st->G_old : nullptr;
+    double* delta = st ? st->delta : nullptr;
+    int32_t* status = st ? st->status : nullptr;
+    hipError_t e;
+    if (cp.dim == 2) {
+      const int H = cp.n / 2;
+      e = chk::launch_coarse_2d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
+                                inst, tab, tab + H * H, U_in, G_out, mask, U, F, Gold, delta, status,
+                                active, k, s);
+    } else {
+      e = chk::launch_coarse_1d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
+                                inst, tab, U_in, G_out, mask, U, F, Gold, delta, status, active, k, s);
+    }
+    ch_status r = hip_check(c, e, "coarse launch");
+    if (r != CH_OK) return r;
+  }
+  return CH_OK;
+}
+
+ch_status ch_coarse_propagate(ch_ctx* c, const double* U_in, double* G_out, const uint8_t* mask,
+                              ch_stream stream) {
+  ch_status st = require_bound(c);
+  if (st != CH_OK) return st;
+  if (!U_in || !G_out) return fail(c, CH_ERR_ARG, "null state pointer");
+  const size_t bytes = sizeof(double) * c->slice_total;
+  const char *a = (const char*)U_in, *b = (const char*)G_out;
+  if (a < b + bytes && b < a + bytes) return fail(c, CH_ERR_ARG, "U_in and G_out overlap");
+  return coarse_all(c, 0, U_in, G_out, mask, nullptr, 0, (hipStream_t)stream);
+}
+
+ch_status ch_parareal_iterate(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (!st || !st->U || !st->F || !st->G_old || !st->delta || !st->status)
+    return fail(c, CH_ERR_ARG, "incomplete ch_pr_state");
+  if (st->k < 0) return fail(c, CH_ERR_ARG, "negative iteration counter");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* active = (int32_t*)(c->ws + c->active_blk.off);
+  const int n_inst = (int)c->probs.size();
+  if (!st->predicted) {
+    r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 1, s), "flags");
+    if (r != CH_OK) return r;
+    r = coarse_all(c, 1, nullptr, nullptr, nullptr, st, 0, s);
+    if (r != CH_OK) return r;
+    st->predicted = 1;
+    return CH_OK;
+  }
+  if (st->k > 0) {
+    r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 0, s), "flags");
+    if (r != CH_OK) return r;
+  }
+  r = fine_all(c, st->U, st->F, nullptr, active, st->k, 1, s);
+  if (r != CH_OK) return r;
+  r = coarse_all(c, 2, nullptr, nullptr, nullptr, st, st->k, s);
+  if (r != CH_OK) return r;
+  st->k += 1;
+  return CH_OK;
+}
+
+ch_status ch_energy(ch_ctx* c, int32_t inst, const double* u, int32_t count, double* E_out,
+                    ch_stream stream) {
+  ch_status st = require_bound(c);
+  if (st != CH_OK) return st;
+  if (inst < 0 || inst >= (int32_t)c->probs.size()) return fail(c, CH_ERR_ARG, "instance index");
+  if (count < 0 || (count > 0 && (!u || !E_out))) return fail(c, CH_ERR_ARG, "energy arguments");
+  const ch_problem& p = c->probs[inst];
+  return hip_check(c, chk::launch_energy(p.n, p.dim, u, count, p.eps, E_out, (hipStream_t)stream),
+                   "energy launch");
+}
+
+}  // extern "C"

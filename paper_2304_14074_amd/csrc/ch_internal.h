@@ -1,0 +1,61 @@
+// Internal declarations shared by the host runtime (ch_api.cpp) and the
+// device code (ch_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace chk {
+
+// Per-instance parameters, one record per instance in device memory.
+struct InstDev {
+  int32_t dim, n, n_slices, j_fine;
+  int32_t m_coarse, coarse_kind, fine_kind, nl_variant;
+  int32_t f_zero, krylov_max, newton_max, precision;
+  double eps, dt, dT, s_fine, h;
+  double newton_tol, krylov_rtol;
+  int64_t off_slices;        // element offset of slice 0 in the slice layout
+  int64_t off_iter;          // element offset of U_0 in the iterate layout
+  int64_t slice_base;        // index of slice 0 among all slices (mask index)
+  const double* rsig_fine;   // [n^d] 1/sigma, sigma = 1 + dt eps^2 Lam^2 - s dt Lam
+  const double* rsig_stab;   // [n^d] same with tau = dT/m_coarse
+  double* cg;                // per-instance CG scratch, CG_VECS * n^d doubles
+};
+constexpr int CG_VECS = 7;   // x, r, p, q, d, b-scale, minv (owned layout)
+
+struct WorkItem { int32_t inst, slice; };
+
+// Launch helpers implemented in ch_kernels.hip; return hipSuccess or an error.
+// Fine sweep.  Work items with slice < k_min or an inactive instance are
+// skipped; in_iter selects the iterate layout for the input states.
+hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                          const double* Se, const double* So, const double* U_in,
+                          double* F_out, const uint8_t* mask, const int32_t* active,
+                          int k_min, int in_iter, hipStream_t s);
+hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                          const double* S, const double* rsig1, const double* U_in,
+                          double* F_out, const uint8_t* mask, const int32_t* active,
+                          int k_min, int in_iter, hipStream_t s);
+// mode 0: independent G per masked slice (parallel); 1: prediction chain;
+// 2: correction chain starting at slice k+1 with U_{k+1} = F_k.
+hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
+                            const WorkItem* items, int n_items, const InstDev* inst,
+                            const double* Se, const double* So, const double* U_in,
+                            double* G_out, const uint8_t* mask, double* U, const double* F,
+                            double* G_old, double* delta, int32_t* status,
+                            const int32_t* active, int k, hipStream_t s);
+hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
+                            const WorkItem* items, int n_items, const InstDev* inst,
+                            const double* S, const double* U_in, double* G_out,
+                            const uint8_t* mask, double* U, const double* F, double* G_old,
+                            double* delta, int32_t* status, const int32_t* active, int k,
+                            hipStream_t s);
+// Fill the per-instance CG tables (d and b-scale in the owned layout).
+hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts,
+                            const InstDev* inst, const double* lam, hipStream_t s);
+hipError_t launch_energy(int n, int dim, const double* u, int count, double eps, double* E,
+                         hipStream_t s);
+hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
+                              int first, hipStream_t s);
+
+}  // namespace chk

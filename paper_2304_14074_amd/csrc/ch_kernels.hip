@@ -1,0 +1,999 @@
+// Device code for the Cahn-Hilliard Parareal library, gfx950 (CDNA4).
+//
+// Central building block: the 2D sine transform X -> S X S^T of an n x n
+// state, where S[j][k] = sqrt(2/(n+1)) sin((j+1)(k+1) pi/(n+1)) holds the
+// eigenvectors of the Dirichlet difference Laplacian (paper, Section 3: D_h
+// and its eigenvalues).  Each half of the transform ("stage") is one dense
+// product Y = S X, done on the FP64 matrix cores (v_mfma_f64_16x16x4f64) and
+// written back transposed, so two stages give S X S and four stages the
+// inverse-after-forward pair of a spectral solve.  The product uses the
+// even/odd symmetry S[n-1-a][b] = (-1)^b S[a][b]: with Se = S[0:n/2, even
+// cols] and So = S[0:n/2, odd cols], E = Se X[even rows], O = So X[odd rows],
+// Y[a] = E[a] + O[a] and Y[n-1-a] = E[a] - O[a] -- half the multiply-adds.
+//
+// A workgroup owns one n x n state for a whole sequence of steps: the state
+// lives in LDS (n = 64, 128), the folded sine rows of its waves stay in
+// registers, and the state never leaves the CU between the J fine steps of a
+// slice.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "ch_internal.h"
+
+namespace chk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ geometry
+template <int N, int NW>
+struct Geo {
+  static constexpr int H = N / 2;        // folded rows
+  static constexpr int TR = H / 16;      // 16-row tiles of E (and O)
+  static constexpr int TC = N / 16;      // 16-col tiles
+  static constexpr int WPR = NW / TR;    // waves per tile row
+  static constexpr int CPW = TC / WPR;   // tile columns per wave
+  static constexpr int KS = H / 4;       // k-steps of 4
+  static constexpr int LDX = N + 1;      // LDS row stride (odd: transposed writes spread banks)
+  static constexpr int NT = NW * 64;     // threads
+  static constexpr int OWN = 8 * CPW;    // points owned per thread
+  static_assert(NW % TR == 0, "waves must tile the folded rows");
+  static_assert(TC % WPR == 0, "waves must tile the columns");
+  static_assert(OWN * NT == N * N, "ownership must cover the grid");
+};
+
+// Lane coordinates.  MFMA f64 16x16x4 operand layout (lane l): A[i][k] with
+// i = l%16, k = l/16; B[k][j] with k = l/16, j = l%16; D[i][j] in element r
+// with i = l/16 + 4r, j = l%16.
+template <int N, int NW>
+struct Lane {
+  int g, j, tr, c0;
+  __device__ Lane() {
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    g = l >> 4;
+    j = l & 15;
+    tr = w / Geo<N, NW>::WPR;
+    c0 = (w % Geo<N, NW>::WPR) * Geo<N, NW>::CPW;
+  }
+  // Output element (q, r) of this lane's E/O tiles is row a, column c; it
+  // produces Y[a][c] (slot half 0) and Y[N-1-a][c] (half 1), which are
+  // written transposed, i.e. to state positions (row c, col a) and
+  // (row c, col N-1-a).  These are the points the thread "owns".
+  __device__ __forceinline__ int row_a(int r) const { return 16 * tr + g + 4 * r; }
+  __device__ __forceinline__ int col_c(int q) const { return 16 * (c0 + q) + j; }
+};
+
+template <int N, int NW>
+__device__ __forceinline__ void load_sine_regs(const double* __restrict__ Se,
+                                               const double* __restrict__ So,
+                                               const Lane<N, NW>& L,
+                                               double (&sE)[Geo<N, NW>::KS],
+                                               double (&sO)[Geo<N, NW>::KS]) {
+  constexpr int H = Geo<N, NW>::H;
+#pragma unroll
+  for (int ks = 0; ks < Geo<N, NW>::KS; ++ks) {
+    const int row = 16 * L.tr + L.j, col = 4 * ks + L.g;
+    sE[ks] = Se[row * H + col];
+    sO[ks] = So[row * H + col];
+  }
+}
+
+// One stage: accumulators E = Se X[even rows], O = So X[odd rows] for this
+// wave's tiles.  X is the LDS state (row stride LDX).
+template <int N, int NW>
+__device__ __forceinline__ void mma_stage(const double* X, const double (&sE)[Geo<N, NW>::KS],
+                                          const double (&sO)[Geo<N, NW>::KS],
+                                          d4 (&aE)[Geo<N, NW>::CPW], d4 (&aO)[Geo<N, NW>::CPW],
+                                          const Lane<N, NW>& L) {
+  using G = Geo<N, NW>;
+#pragma unroll
+  for (int q = 0; q < G::CPW; ++q) {
+    aE[q] = d4{0.0, 0.0, 0.0, 0.0};
+    aO[q] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  // Software-pipelined: the B operands of k-step ks+1 are read from LDS
+  // while the MFMAs of k-step ks run; the scheduling barrier keeps the
+  // compiler from hoisting every read of the unrolled loop (register blow-up).
+  const double* base = X + (2 * L.g) * G::LDX + 16 * L.c0 + L.j;
+  double be[G::CPW], bo[G::CPW];
+#pragma unroll
+  for (int q = 0; q < G::CPW; ++q) {
+    be[q] = base[16 * q];
+    bo[q] = base[G::LDX + 16 * q];
+  }
+#pragma unroll
+  for (int ks = 0; ks < G::KS; ++ks) {
+    double ne[G::CPW], no[G::CPW];
+    if (ks + 1 < G::KS) {
+      const double* pe = base + (8 * (ks + 1)) * G::LDX;
+#pragma unroll
+      for (int q = 0; q < G::CPW; ++q) {
+        ne[q] = pe[16 * q];
+        no[q] = pe[G::LDX + 16 * q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < G::CPW; ++q) {
+      aE[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sE[ks], be[q], aE[q], 0, 0, 0);
+      aO[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sO[ks], bo[q], aO[q], 0, 0, 0);
+    }
+    if (ks + 1 < G::KS) {
+#pragma unroll
+      for (int q = 0; q < G::CPW; ++q) {
+        be[q] = ne[q];
+        bo[q] = no[q];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Unfold accumulators into the owned values y[slot]: slot (q*4+r)*2 + 0 is
+// Y[a][c], slot +1 is Y[N-1-a][c].
+template <int N, int NW>
+__device__ __forceinline__ void unfold(const d4 (&aE)[Geo<N, NW>::CPW],
+                                       const d4 (&aO)[Geo<N, NW>::CPW],
+                                       double (&y)[Geo<N, NW>::OWN]) {
+#pragma unroll
+  for (int q = 0; q < Geo<N, NW>::CPW; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      y[(q * 4 + r) * 2 + 0] = aE[q][r] + aO[q][r];
+      y[(q * 4 + r) * 2 + 1] = aE[q][r] - aO[q][r];
+    }
+}
+
+// Offsets (in X) of the owned points.
+template <int N, int NW>
+__device__ __forceinline__ int own_off(const Lane<N, NW>& L, int slot) {
+  const int qr = slot >> 1, half = slot & 1;
+  const int q = qr >> 2, r = qr & 3;
+  const int a = L.row_a(r), c = L.col_c(q);
+  return c * Geo<N, NW>::LDX + (half ? (N - 1 - a) : a);
+}
+template <int N, int NW>
+__device__ __forceinline__ void own_rc(const Lane<N, NW>& L, int slot, int& row, int& col) {
+  const int qr = slot >> 1, half = slot & 1;
+  const int q = qr >> 2, r = qr & 3;
+  const int a = L.row_a(r);
+  row = L.col_c(q);
+  col = half ? (N - 1 - a) : a;
+}
+
+template <int N, int NW>
+__device__ __forceinline__ void store_owned(double* X, const Lane<N, NW>& L,
+                                            const double (&y)[Geo<N, NW>::OWN]) {
+#pragma unroll
+  for (int s = 0; s < Geo<N, NW>::OWN; ++s) X[own_off<N, NW>(L, s)] = y[s];
+}
+template <int N, int NW>
+__device__ __forceinline__ void load_owned(const double* X, const Lane<N, NW>& L,
+                                           double (&y)[Geo<N, NW>::OWN]) {
+#pragma unroll
+  for (int s = 0; s < Geo<N, NW>::OWN; ++s) y[s] = X[own_off<N, NW>(L, s)];
+}
+
+// Full stage: X <- (S X)^T, optionally scaled pointwise by w at the owned
+// (row, col) positions of the result (w in row-major n x n, may be null).
+template <int N, int NW>
+__device__ __forceinline__ void stage(double* X, const double (&sE)[Geo<N, NW>::KS],
+                                      const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
+                                      const double* __restrict__ w) {
+  using G = Geo<N, NW>;
+  d4 aE[G::CPW], aO[G::CPW];
+  mma_stage<N, NW>(X, sE, sO, aE, aO, L);
+  double y[G::OWN];
+  unfold<N, NW>(aE, aO, y);
+  if (w) {
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      int row, col;
+      own_rc<N, NW>(L, s, row, col);
+      y[s] *= w[row * N + col];
+    }
+  }
+  __syncthreads();  // every wave has finished reading X
+  store_owned<N, NW>(X, L, y);
+  __syncthreads();
+}
+
+// Last stage of a pass: the result stays in registers (owned values).
+template <int N, int NW>
+__device__ __forceinline__ void stage_regs(const double* X, const double (&sE)[Geo<N, NW>::KS],
+                                           const double (&sO)[Geo<N, NW>::KS],
+                                           const Lane<N, NW>& L, double (&y)[Geo<N, NW>::OWN]) {
+  using G = Geo<N, NW>;
+  d4 aE[G::CPW], aO[G::CPW];
+  mma_stage<N, NW>(X, sE, sO, aE, aO, L);
+  unfold<N, NW>(aE, aO, y);
+}
+
+// ------------------------------------------------------------ reductions
+template <int NW>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <int NW>
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// Deterministic block sums of K values at once (fixed tree, fixed wave order).
+template <int NW, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = wave_sum<NW>(v[i]);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0)
+#pragma unroll
+    for (int i = 0; i < K; ++i) red[i * NW + w] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) s += red[i * NW + ww];
+    v[i] = s;
+  }
+}
+template <int NW>
+__device__ __forceinline__ void block_minmax(double& mn, double& mx, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    red[w] = mn;
+    red[NW + w] = mx;
+  }
+  __syncthreads();
+  mn = red[0];
+  mx = red[NW];
+#pragma unroll
+  for (int ww = 1; ww < NW; ++ww) {
+    mn = fmin(mn, red[ww]);
+    mx = fmax(mx, red[NW + ww]);
+  }
+}
+
+// ------------------------------------------------- linear stabilised step
+// Right-hand side of the linear step at the owned points, from the owned
+// state values v (in registers, state orientation):
+//   r = u + c_lap * Lap5(f(u) - s u),  c_lap = tau / h^2  (zero boundary ghosts).
+// Leaves r in X (state orientation).
+template <int N, int NW>
+__device__ __forceinline__ void rhs_owned(double* X, const Lane<N, NW>& L,
+                                          double (&v)[Geo<N, NW>::OWN], double c_lap, double s,
+                                          int f_zero) {
+  using G = Geo<N, NW>;
+#pragma unroll
+  for (int k = 0; k < G::OWN; ++k) {
+    const double u = v[k];
+    X[own_off<N, NW>(L, k)] = f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < G::OWN; ++k) {
+    int row, col;
+    own_rc<N, NW>(L, k, row, col);
+    const double* p = X + row * G::LDX + col;
+    const double wc = p[0];
+    const double wn = (row > 0) ? p[-G::LDX] : 0.0;
+    const double ws = (row < N - 1) ? p[G::LDX] : 0.0;
+    const double ww = (col > 0) ? p[-1] : 0.0;
+    const double we = (col < N - 1) ? p[1] : 0.0;
+    v[k] = v[k] + c_lap * ((wn + ws) + (ww + we) - 4.0 * wc);
+  }
+  __syncthreads();
+  store_owned<N, NW>(X, L, v);
+  __syncthreads();
+}
+
+// nsteps linear steps starting from the state in X (state orientation);
+// the result is left in X and in v.
+template <int N, int NW>
+__device__ void linear_steps(double* X, const double (&sE)[Geo<N, NW>::KS],
+                             const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
+                             double (&v)[Geo<N, NW>::OWN], int nsteps, double c_lap, double s,
+                             int f_zero, const double* __restrict__ rsig) {
+  load_owned<N, NW>(X, L, v);
+  for (int m = 0; m < nsteps; ++m) {
+    rhs_owned<N, NW>(X, L, v, c_lap, s, f_zero);
+    stage<N, NW>(X, sE, sO, L, nullptr);  // X = (S r)^T
+    stage<N, NW>(X, sE, sO, L, rsig);     // X = (S r S) / sigma   (spectral)
+    stage<N, NW>(X, sE, sO, L, nullptr);
+    stage_regs<N, NW>(X, sE, sO, L, v);   // v = S (.) S   (state, owned)
+    __syncthreads();
+    store_owned<N, NW>(X, L, v);
+    __syncthreads();
+  }
+}
+
+template <int N, int NW>
+__device__ __forceinline__ void load_state(double* X, const double* __restrict__ src) {
+  using G = Geo<N, NW>;
+  for (int idx = threadIdx.x; idx < N * N; idx += G::NT) X[(idx / N) * G::LDX + (idx % N)] = src[idx];
+}
+template <int N, int NW>
+__device__ __forceinline__ void store_state(const double* X, double* __restrict__ dst) {
+  using G = Geo<N, NW>;
+  for (int idx = threadIdx.x; idx < N * N; idx += G::NT) dst[idx] = X[(idx / N) * G::LDX + (idx % N)];
+}
+
+// Fine sweep: one workgroup per (instance, slice) work item; J linear steps
+// of dt, the state resident in LDS throughout.
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                 const double* __restrict__ Se, const double* __restrict__ So,
+                 const double* __restrict__ U_in, double* __restrict__ F_out,
+                 const uint8_t* __restrict__ mask, const int32_t* __restrict__ active,
+                 int k_min, int in_iter) {
+  extern __shared__ double smem[];
+  double* X = smem;
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if (it.slice < k_min || (active && !active[it.inst])) return;
+  const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
+  Lane<N, NW> L;
+  double sE[Geo<N, NW>::KS], sO[Geo<N, NW>::KS];
+  load_sine_regs<N, NW>(Se, So, L, sE, sO);
+  load_state<N, NW>(X, U_in + off_in);
+  __syncthreads();
+  double v[Geo<N, NW>::OWN];
+  linear_steps<N, NW>(X, sE, sO, L, v, P.j_fine, P.dt / (P.h * P.h), P.s_fine, P.f_zero,
+                      P.rsig_fine);
+  store_state<N, NW>(X, F_out + off);
+}
+
+// --------------------------------------------- scheme (2.4) by spectral CG
+// (I - tau Lap diag(u^2) + eps^2 tau Lap^2) v = (I - tau Lap) u is, with
+// A = -Lap (SPD), equivalent to the SPD system
+//   K v = (A^{-1} + tau eps^2 A + tau diag(q)) v = A^{-1} u + tau u,  q = u^2.
+// In sine coordinates vh = S v S: K_hat = diag(d) + tau S diag(q) S with
+// d = 1/mu + tau eps^2 mu, mu = -(lam_p + lam_q); rhs b_hat = (1/mu + tau) u_hat.
+// Preconditioner: diag(d + tau c), c = (min q + max q)/2.  Each CG iteration
+// applies K_hat with one inverse and one forward 2D sine transform.
+// CG vectors live in the per-instance scratch in "owned" order
+// (index slot * NT + thread), which is coalesced for every thread.
+template <int N, int NW>
+__device__ void approx2_solve(double* X, double* red, const double (&sE)[Geo<N, NW>::KS],
+                              const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
+                              const InstDev& P, int& status) {
+  using G = Geo<N, NW>;
+  const int t = threadIdx.x;
+  const int64_t NN = (int64_t)N * N;
+  double* cx = P.cg;            // solution (spectral)
+  double* cr = P.cg + NN;       // residual
+  double* cp = P.cg + 2 * NN;   // direction
+  double* cq = P.cg + 3 * NN;   // q = u^2 (state, owned)
+  const double* cd = P.cg + 4 * NN;   // d
+  const double* cb = P.cg + 5 * NN;   // 1/mu + tau
+  double* cm = P.cg + 6 * NN;   // 1 / (d + tau c)
+  const double tau = P.dT / P.m_coarse;
+  double y[G::OWN];
+  for (int sub = 0; sub < P.m_coarse; ++sub) {
+    // q = u^2 at owned points, shift c
+    double mn = 1e300, mx = -1e300;
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      const double u = X[own_off<N, NW>(L, s)];
+      const double q = P.f_zero ? 0.0 : u * u;
+      cq[s * G::NT + t] = q;
+      mn = fmin(mn, q);
+      mx = fmax(mx, q);
+    }
+    block_minmax<NW>(mn, mx, red);
+    const double cshift = 0.5 * (mn + mx);
+    // u_hat (2 stages), b_hat, initial CG state x = 0, r = b, p = z = M^{-1} r
+    stage<N, NW>(X, sE, sO, L, nullptr);
+    stage_regs<N, NW>(X, sE, sO, L, y);
+    double acc[3] = {0.0, 0.0, 0.0};  // r.z, b.b
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      const int64_t o = (int64_t)s * G::NT + t;
+      const double d = cd[o];
+      // f == 0 (test hook) removes the tau u term of the right-hand side
+      const double b = (P.f_zero ? (cb[o] - tau) : cb[o]) * y[s];
+      const double mi = 1.0 / (d + tau * cshift);
+      cm[o] = mi;
+      cx[o] = 0.0;
+      cr[o] = b;
+      const double z = b * mi;
+      cp[o] = z;
+      y[s] = z;  // p, written to X below
+      acc[0] += b * z;
+      acc[1] += b * b;
+    }
+    block_sum<NW, 3>(acc, red);
+    double rz = acc[0];
+    const double bb = acc[1];
+    const double stop2 = P.krylov_rtol * P.krylov_rtol * bb;
+    int it = 0;
+    bool done = !(bb > 0.0);
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);  // X = p (spectral, owned orientation)
+    __syncthreads();
+    while (!done) {
+      // Kp = d p + tau S (q . S p S) S
+      stage<N, NW>(X, sE, sO, L, nullptr);
+      {
+        // second stage with the pointwise q at owned (state) points
+        d4 aE[G::CPW], aO[G::CPW];
+        mma_stage<N, NW>(X, sE, sO, aE, aO, L);
+        unfold<N, NW>(aE, aO, y);
+#pragma unroll
+        for (int s = 0; s < G::OWN; ++s) y[s] *= cq[(int64_t)s * G::NT + t];
+        __syncthreads();
+        store_owned<N, NW>(X, L, y);
+        __syncthreads();
+      }
+      stage<N, NW>(X, sE, sO, L, nullptr);
+      stage_regs<N, NW>(X, sE, sO, L, y);
+      double a1[1] = {0.0};
+#pragma unroll
+      for (int s = 0; s < G::OWN; ++s) {
+        const int64_t o = (int64_t)s * G::NT + t;
+        const double p = cp[o];
+        const double kp = cd[o] * p + tau * y[s];
+        y[s] = kp;
+        a1[0] += p * kp;
+      }
+      block_sum<NW, 1>(a1, red);
+      const double alpha = rz / a1[0];
+      double a2[2] = {0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < G::OWN; ++s) {
+        const int64_t o = (int64_t)s * G::NT + t;
+        cx[o] += alpha * cp[o];
+        const double r = cr[o] - alpha * y[s];
+        cr[o] = r;
+        a2[0] += r * r;
+        a2[1] += r * (r * cm[o]);
+      }
+      block_sum<NW, 2>(a2, red);
+      ++it;
+      if (a2[0] <= stop2) {
+        done = true;
+        break;
+      }
+      if (it >= P.krylov_max || !(a2[0] == a2[0])) {
+        status |= 1;
+        break;
+      }
+      const double beta = a2[1] / rz;
+      rz = a2[1];
+#pragma unroll
+      for (int s = 0; s < G::OWN; ++s) {
+        const int64_t o = (int64_t)s * G::NT + t;
+        const double p = cr[o] * cm[o] + beta * cp[o];
+        cp[o] = p;
+        y[s] = p;
+      }
+      __syncthreads();
+      store_owned<N, NW>(X, L, y);
+      __syncthreads();
+    }
+    // v = S x S  (back to the state) -> X
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) y[s] = cx[(int64_t)s * G::NT + t];
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);
+    __syncthreads();
+    stage<N, NW>(X, sE, sO, L, nullptr);
+    stage<N, NW>(X, sE, sO, L, nullptr);
+  }
+}
+
+// One coarse propagation of the state in X (state orientation), result in X.
+template <int N, int NW>
+__device__ void coarse_apply(double* X, double* red, const double (&sE)[Geo<N, NW>::KS],
+                             const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
+                             const InstDev& P, int& status) {
+  if (P.coarse_kind == 1) {  // stabilised step with tau = dT/m
+    double v[Geo<N, NW>::OWN];
+    const double tau = P.dT / P.m_coarse;
+    linear_steps<N, NW>(X, sE, sO, L, v, P.m_coarse, tau / (P.h * P.h), P.s_fine, P.f_zero,
+                        P.rsig_stab);
+  } else {
+    approx2_solve<N, NW>(X, red, sE, sO, L, P, status);
+  }
+}
+
+// mode 0: G on each masked work item independently.
+// mode 1: prediction chain per instance: U_{n+1} = G(U_n), G_old_n = U_{n+1}.
+// mode 2: correction chain per instance from slice k+1 (U_{k+1} = F_k).
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restrict__ items,
+            const InstDev* __restrict__ inst, const double* __restrict__ Se,
+            const double* __restrict__ So, const double* __restrict__ U_in,
+            double* __restrict__ G_out, const uint8_t* __restrict__ mask, double* U,
+            const double* __restrict__ F, double* G_old, double* delta, int32_t* status_out,
+            const int32_t* __restrict__ active, int k) {
+  using G = Geo<N, NW>;
+  extern __shared__ double smem[];
+  double* X = smem;
+  double* red = smem + N * G::LDX;
+  Lane<N, NW> L;
+  double sE[G::KS], sO[G::KS];
+  int status = 0;
+  const int64_t NN = (int64_t)N * N;
+  if (mode == 0) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev P = inst[it.inst];
+    if (mask && !mask[P.slice_base + it.slice]) return;
+    load_sine_regs<N, NW>(Se, So, L, sE, sO);
+    const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+    load_state<N, NW>(X, U_in + off);
+    __syncthreads();
+    coarse_apply<N, NW>(X, red, sE, sO, L, P, status);
+    store_state<N, NW>(X, G_out + off);
+    return;
+  }
+  const int ii = insts[blockIdx.x];
+  if (active && !active[ii]) return;
+  const InstDev P = inst[ii];
+  load_sine_regs<N, NW>(Se, So, L, sE, sO);
+  double* Ui = U + P.off_iter;
+  const double* Fi = F + P.off_slices;
+  double* Gi = G_old + P.off_slices;
+  const int Ns = P.n_slices;
+  if (mode == 1) {
+    load_state<N, NW>(X, Ui);
+    __syncthreads();
+    for (int n = 0; n < Ns; ++n) {
+      coarse_apply<N, NW>(X, red, sE, sO, L, P, status);
+      for (int idx = threadIdx.x; idx < NN; idx += G::NT) {
+        const double gv = X[(idx / N) * G::LDX + idx % N];
+        Ui[(n + 1) * NN + idx] = gv;
+        Gi[n * NN + idx] = gv;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) status_out[ii] = status;
+    return;
+  }
+  // mode 2
+  if (k >= Ns) {  // every slice already final (finite termination)
+    if (threadIdx.x == 0) delta[ii] = 0.0;
+    return;
+  }
+  double dmax = 0.0;
+  {
+    // U_{k+1} = F_k + (G(U_k) - G_old_k) with G(U_k) == G_old_k exactly.
+    double acc[1] = {0.0};
+    for (int idx = threadIdx.x; idx < NN; idx += G::NT) {
+      const double unew = Fi[k * NN + idx];
+      const double dd = unew - Ui[(k + 1) * NN + idx];
+      acc[0] += dd * dd;
+      Ui[(k + 1) * NN + idx] = unew;
+      X[(idx / N) * G::LDX + idx % N] = unew;
+    }
+    block_sum<NW, 1>(acc, red);
+    dmax = acc[0];
+    __syncthreads();
+  }
+  for (int n = k + 1; n < Ns; ++n) {
+    coarse_apply<N, NW>(X, red, sE, sO, L, P, status);
+    double acc[1] = {0.0};
+    for (int idx = threadIdx.x; idx < NN; idx += G::NT) {
+      const int xo = (idx / N) * G::LDX + idx % N;
+      const double gv = X[xo];
+      const double unew = Fi[n * NN + idx] + (gv - Gi[n * NN + idx]);
+      const double dd = unew - Ui[(n + 1) * NN + idx];
+      acc[0] += dd * dd;
+      Ui[(n + 1) * NN + idx] = unew;
+      Gi[n * NN + idx] = gv;
+      X[xo] = unew;
+    }
+    block_sum<NW, 1>(acc, red);
+    dmax = fmax(dmax, acc[0]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double dlt = sqrt(P.h * P.h * dmax);
+    delta[ii] = dlt;
+    if (!(dlt == dlt) || dlt > 1e300) status |= 2;
+    status_out[ii] = status;
+  }
+}
+
+// CG tables in owned order: d = 1/mu + tau eps^2 mu and b-scale = 1/mu + tau,
+// mu = -(lam_row + lam_col), tau = dT/m (2D).
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_cg_tables_2d(const int32_t* __restrict__ insts, const InstDev* __restrict__ inst,
+               const double* __restrict__ lam) {
+  using G = Geo<N, NW>;
+  const InstDev P = inst[insts[blockIdx.x]];
+  Lane<N, NW> L;
+  const int t = threadIdx.x;
+  const double tau = P.dT / P.m_coarse;
+  for (int s = 0; s < G::OWN; ++s) {
+    int row, col;
+    own_rc<N, NW>(L, s, row, col);
+    const double mu = -(lam[row] + lam[col]);
+    P.cg[4 * (int64_t)N * N + (int64_t)s * G::NT + t] = 1.0 / mu + tau * P.eps * P.eps * mu;
+    P.cg[5 * (int64_t)N * N + (int64_t)s * G::NT + t] = 1.0 / mu + tau;
+  }
+}
+
+// ------------------------------------------------------------------- 1D
+// One workgroup of n threads per state; S (n x n) staged in LDS.  Thread i
+// owns grid point i (state) and sine index i (spectral).
+__device__ __forceinline__ double sine_apply_1d(const double* Sl, const double* vin, int n, int i) {
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) acc += Sl[k * n + i] * vin[k];
+  return acc;
+}
+
+__global__ void k_fine_linear_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                                 const double* __restrict__ S, const double* __restrict__ rsig1,
+                                 const double* __restrict__ U_in, double* __restrict__ F_out,
+                                 const uint8_t* __restrict__ mask,
+                                 const int32_t* __restrict__ active, int k_min, int in_iter) {
+  extern __shared__ double smem[];
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if (it.slice < k_min || (active && !active[it.inst])) return;
+  const int n = P.n, i = threadIdx.x;
+  double* Sl = smem;
+  double* w = smem + n * n;
+  double* r = w + n;
+  for (int idx = i; idx < n * n; idx += n) Sl[idx] = S[idx];
+  const int64_t off = P.off_slices + (int64_t)it.slice * n;
+  double u = U_in[(in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * n + i];
+  const double c = P.dt / (P.h * P.h), s = P.s_fine;
+  const double rs = P.rsig_fine[i];
+  __syncthreads();
+  for (int m = 0; m < P.j_fine; ++m) {
+    w[i] = P.f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
+    __syncthreads();
+    const double wl = i > 0 ? w[i - 1] : 0.0, wr = i < n - 1 ? w[i + 1] : 0.0;
+    r[i] = u + c * ((wl + wr) - 2.0 * w[i]);
+    __syncthreads();
+    const double rh = sine_apply_1d(Sl, r, n, i) * rs;
+    __syncthreads();
+    w[i] = rh;
+    __syncthreads();
+    u = sine_apply_1d(Sl, w, n, i);
+    __syncthreads();
+  }
+  F_out[off + i] = u;
+}
+
+template <int NMAX>
+__device__ double block_sum_1d(double v, double* red) {
+  // n threads (<= NMAX, multiple of 64 not required): fixed tree over waves
+  v = wave_sum<1>(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int ww = 0; ww < nw; ++ww) s += red[ww];
+  return s;
+}
+
+// Scheme (2.4) (or the stabilised step) on the state u held by thread i.
+__device__ double coarse_apply_1d(double u, const InstDev& P, const double* Sl, double* buf,
+                                  double* red, const double* lam, const double* rsig_stab,
+                                  int& status) {
+  const int n = P.n, i = threadIdx.x;
+  const double tau = P.dT / P.m_coarse;
+  for (int sub = 0; sub < P.m_coarse; ++sub) {
+    if (P.coarse_kind == 1) {
+      const double c = tau / (P.h * P.h), s = P.s_fine;
+      buf[i] = P.f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
+      __syncthreads();
+      const double wl = i > 0 ? buf[i - 1] : 0.0, wr = i < n - 1 ? buf[i + 1] : 0.0;
+      const double r = u + c * ((wl + wr) - 2.0 * buf[i]);
+      __syncthreads();
+      buf[i] = r;
+      __syncthreads();
+      const double rh = sine_apply_1d(Sl, buf, n, i) * rsig_stab[i];
+      __syncthreads();
+      buf[i] = rh;
+      __syncthreads();
+      u = sine_apply_1d(Sl, buf, n, i);
+      __syncthreads();
+      continue;
+    }
+    const double mu = -lam[i];
+    const double d = 1.0 / mu + tau * P.eps * P.eps * mu;
+    const double q = P.f_zero ? 0.0 : u * u;
+    double mn = q, mx = q;
+    for (int o = 32; o > 0; o >>= 1) {
+      mn = fmin(mn, __shfl_xor(mn, o, 64));
+      mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    __syncthreads();
+    if ((i & 63) == 0) { red[i >> 6] = mn; red[32 + (i >> 6)] = mx; }
+    __syncthreads();
+    const int nw = (n + 63) >> 6;
+    mn = red[0]; mx = red[32];
+    for (int ww = 1; ww < nw; ++ww) { mn = fmin(mn, red[ww]); mx = fmax(mx, red[32 + ww]); }
+    const double mi = 1.0 / (d + tau * 0.5 * (mn + mx));
+    buf[i] = u;
+    __syncthreads();
+    const double uh = sine_apply_1d(Sl, buf, n, i);
+    const double b = (P.f_zero ? 1.0 / mu : 1.0 / mu + tau) * uh;
+    double x = 0.0, r = b, z = b * mi, p = z;
+    double rz = block_sum_1d<1024>(r * z, red);
+    const double bb = block_sum_1d<1024>(b * b, red);
+    const double stop2 = P.krylov_rtol * P.krylov_rtol * bb;
+    int it = 0;
+    bool go = bb > 0.0;
+    while (go) {
+      __syncthreads();
+      buf[i] = p;
+      __syncthreads();
+      const double ps = sine_apply_1d(Sl, buf, n, i) * q;
+      __syncthreads();
+      buf[i] = ps;
+      __syncthreads();
+      const double kp = d * p + tau * sine_apply_1d(Sl, buf, n, i);
+      const double pkp = block_sum_1d<1024>(p * kp, red);
+      const double alpha = rz / pkp;
+      x += alpha * p;
+      r -= alpha * kp;
+      const double rr = block_sum_1d<1024>(r * r, red);
+      const double rzn = block_sum_1d<1024>(r * (r * mi), red);
+      ++it;
+      if (rr <= stop2) break;
+      if (it >= P.krylov_max || !(rr == rr)) { status |= 1; break; }
+      const double beta = rzn / rz;
+      rz = rzn;
+      p = r * mi + beta * p;
+    }
+    __syncthreads();
+    buf[i] = x;
+    __syncthreads();
+    u = sine_apply_1d(Sl, buf, n, i);
+    __syncthreads();
+  }
+  return u;
+}
+
+__global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
+                            const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                            const double* __restrict__ S, const double* __restrict__ lam,
+                            const double* __restrict__ U_in, double* __restrict__ G_out,
+                            const uint8_t* __restrict__ mask, double* U,
+                            const double* __restrict__ F, double* G_old, double* delta,
+                            int32_t* status_out, const int32_t* __restrict__ active, int k) {
+  extern __shared__ double smem[];
+  const int i = threadIdx.x;
+  int status = 0;
+  if (mode == 0) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev P = inst[it.inst];
+    if (mask && !mask[P.slice_base + it.slice]) return;
+    const int n = P.n;
+    double* Sl = smem; double* buf = smem + n * n; double* red = buf + n;
+    for (int idx = i; idx < n * n; idx += n) Sl[idx] = S[idx];
+    __syncthreads();
+    const int64_t off = P.off_slices + (int64_t)it.slice * n;
+    G_out[off + i] = coarse_apply_1d(U_in[off + i], P, Sl, buf, red, lam, P.rsig_stab, status);
+    return;
+  }
+  const int ii = insts[blockIdx.x];
+  if (active && !active[ii]) return;
+  const InstDev P = inst[ii];
+  const int n = P.n;
+  double* Sl = smem; double* buf = smem + n * n; double* red = buf + n;
+  for (int idx = i; idx < n * n; idx += n) Sl[idx] = S[idx];
+  __syncthreads();
+  double* Ui = U + P.off_iter;
+  const double* Fi = F + P.off_slices;
+  double* Gi = G_old + P.off_slices;
+  if (mode == 1) {
+    double u = Ui[i];
+    for (int s = 0; s < P.n_slices; ++s) {
+      u = coarse_apply_1d(u, P, Sl, buf, red, lam, P.rsig_stab, status);
+      Ui[(s + 1) * n + i] = u;
+      Gi[s * n + i] = u;
+    }
+    if (i == 0) status_out[ii] = status;
+    return;
+  }
+  if (k >= P.n_slices) {
+    if (i == 0) delta[ii] = 0.0;
+    return;
+  }
+  double u = Fi[k * n + i];
+  double dd = u - Ui[(k + 1) * n + i];
+  double dmax = block_sum_1d<1024>(dd * dd, red);
+  Ui[(k + 1) * n + i] = u;
+  for (int s = k + 1; s < P.n_slices; ++s) {
+    const double g = coarse_apply_1d(u, P, Sl, buf, red, lam, P.rsig_stab, status);
+    const double un = Fi[s * n + i] + (g - Gi[s * n + i]);
+    dd = un - Ui[(s + 1) * n + i];
+    dmax = fmax(dmax, block_sum_1d<1024>(dd * dd, red));
+    Ui[(s + 1) * n + i] = un;
+    Gi[s * n + i] = g;
+    u = un;
+  }
+  if (i == 0) {
+    const double dlt = sqrt(P.h * dmax);
+    delta[ii] = dlt;
+    if (!(dlt == dlt) || dlt > 1e300) status |= 2;
+    status_out[ii] = status;
+  }
+}
+
+// --------------------------------------------------------------- energy
+// E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u); one block per state.
+__global__ void __launch_bounds__(256)
+k_energy(int n, int dim, const double* __restrict__ u, double eps, double* __restrict__ E) {
+  __shared__ double red[8];
+  const double* s = u + (int64_t)blockIdx.x * (dim == 2 ? (int64_t)n * n : n);
+  const double h = 1.0 / (n + 1), ih2 = 1.0 / (h * h);
+  double bulk = 0.0, grad = 0.0;
+  const int64_t tot = dim == 2 ? (int64_t)n * n : n;
+  for (int64_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const double c = s[idx];
+    double lap;
+    if (dim == 2) {
+      const int iy = (int)(idx / n), ix = (int)(idx % n);
+      const double a = iy > 0 ? s[idx - n] : 0.0, b = iy < n - 1 ? s[idx + n] : 0.0;
+      const double l = ix > 0 ? s[idx - 1] : 0.0, r = ix < n - 1 ? s[idx + 1] : 0.0;
+      lap = ((a + b) + (l + r) - 4.0 * c) * ih2;
+    } else {
+      const double l = idx > 0 ? s[idx - 1] : 0.0, r = idx < n - 1 ? s[idx + 1] : 0.0;
+      lap = ((l + r) - 2.0 * c) * ih2;
+    }
+    const double t = c * c - 1.0;
+    bulk += 0.25 * t * t;
+    grad += -c * lap;
+  }
+  double v[2] = {bulk, grad};
+  v[0] = wave_sum<4>(v[0]);
+  v[1] = wave_sum<4>(v[1]);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[w] = v[0]; red[4 + w] = v[1]; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hd = dim == 2 ? h * h : h;
+    const double b = (red[0] + red[1]) + (red[2] + red[3]);
+    const double g = (red[4] + red[5]) + (red[6] + red[7]);
+    E[blockIdx.x] = hd * b + 0.5 * eps * eps * hd * g;
+  }
+}
+
+__global__ void k_flag_active(const double* __restrict__ delta, int32_t* __restrict__ active,
+                              int n_inst, double tol, int first) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  if (first) active[i] = 1;
+  else if (active[i] && delta[i] < tol) active[i] = 0;
+}
+
+// ------------------------------------------------------------ launchers
+template <int N, int NW>
+static hipError_t fine2d(const WorkItem* items, int n_items, const InstDev* inst,
+                         const double* Se, const double* So, const double* U_in, double* F_out,
+                         const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                         hipStream_t s) {
+  const size_t lds = (size_t)N * Geo<N, NW>::LDX * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_2d<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fine_linear_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
+                     Se, So, U_in, F_out, mask, active, k_min, in_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                          const double* Se, const double* So, const double* U_in, double* F_out,
+                          const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                          hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (n) {
+    case 32: return fine2d<32, 2>(items, n_items, inst, Se, So, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 64: return fine2d<64, 4>(items, n_items, inst, Se, So, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 128: return fine2d<128, 4>(items, n_items, inst, Se, So, U_in, F_out, mask, active, k_min, in_iter, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                          const double* S, const double* rsig1, const double* U_in, double* F_out,
+                          const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                          hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const size_t lds = ((size_t)n * n + 2 * n) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_1d,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fine_linear_1d, dim3(n_items), dim3(n), lds, s, items, inst, S, rsig1, U_in,
+                     F_out, mask, active, k_min, in_iter);
+  return hipGetLastError();
+}
+
+template <int N, int NW>
+static hipError_t coarse2d(int mode, const int32_t* insts, int n_insts, const WorkItem* items,
+                           int n_items, const InstDev* inst, const double* Se, const double* So,
+                           const double* U_in, double* G_out, const uint8_t* mask, double* U,
+                           const double* F, double* G_old, double* delta, int32_t* status,
+                           const int32_t* active, int k, hipStream_t s) {
+  const size_t lds = ((size_t)N * Geo<N, NW>::LDX + 4 * NW) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_coarse_2d<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = mode == 0 ? n_items : n_insts;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_coarse_2d<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts, items,
+                     inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
+                            const WorkItem* items, int n_items, const InstDev* inst,
+                            const double* Se, const double* So, const double* U_in,
+                            double* G_out, const uint8_t* mask, double* U, const double* F,
+                            double* G_old, double* delta, int32_t* status,
+                            const int32_t* active, int k, hipStream_t s) {
+  switch (n) {
+    case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
+    case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
+    case 128: return coarse2d<128, 4>(mode, insts, n_insts, items, n_items, inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
+                            const WorkItem* items, int n_items, const InstDev* inst,
+                            const double* S, const double* U_in, double* G_out,
+                            const uint8_t* mask, double* U, const double* F, double* G_old,
+                            double* delta, int32_t* status, const int32_t* active, int k,
+                            hipStream_t s) {
+  // lam for 1D is stored right after S (n x n) in the table block
+  const double* lam = S + (size_t)n * n;
+  const size_t lds = ((size_t)n * n + n + 64) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_coarse_1d,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = mode == 0 ? n_items : n_insts;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coarse_1d, dim3(grid), dim3(n), lds, s, mode, insts, items, inst, S, lam,
+                     U_in, G_out, mask, U, F, G_old, delta, status, active, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts, const InstDev* inst,
+                            const double* lam, hipStream_t s) {
+  if (dim != 2 || n_insts <= 0) return hipSuccess;
+  switch (n) {
+    case 32: hipLaunchKernelGGL((k_cg_tables_2d<32, 2>), dim3(n_insts), dim3(128), 0, s, insts, inst, lam); break;
+    case 64: hipLaunchKernelGGL((k_cg_tables_2d<64, 4>), dim3(n_insts), dim3(256), 0, s, insts, inst, lam); break;
+    case 128: hipLaunchKernelGGL((k_cg_tables_2d<128, 4>), dim3(n_insts), dim3(256), 0, s, insts, inst, lam); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(int n, int dim, const double* u, int count, double eps, double* E,
+                         hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_energy, dim3(count), dim3(256), 0, s, n, dim, u, eps, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
+                              int first, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_active, dim3((n_inst + 255) / 256), dim3(256), 0, s, delta, active,
+                     n_inst, tol, first);
+  return hipGetLastError();
+}
+
+}  // namespace chk

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates problems on the host (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ch.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ch_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("ch_create", "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate", "ch_energy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2304_14074_amd import chlib
+    lib = chlib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(chlib.EXPORTS) == set(_declared())
+
+
+def _create(probs):
+    from paper_2304_14074_amd import chlib
+    lib = chlib.load()
+    arr = (chlib.ChProblem * len(probs))(*[chlib.to_problem(p) for p in probs])
+    h = ctypes.c_void_p()
+    st = lib.ch_create(arr, len(probs), ctypes.byref(h))
+    return lib, st, h
+
+
+def test_create_and_layout_host_only():
+    import workloads
+    from paper_2304_14074_amd import chlib
+    probs = [workloads.Problem(dim=2, n=64, n_slices=3, j_fine=5),
+             workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5),
+             workloads.Problem(dim=1, n=128, n_slices=4, j_fine=5)]
+    lib, st, h = _create(probs)
+    assert st == chlib.CH_OK
+    sz = ctypes.c_size_t()
+    assert lib.ch_workspace_size(h, ctypes.byref(sz)) == chlib.CH_OK and sz.value > 0
+    vals = [ctypes.c_int64() for _ in range(4)]
+    assert lib.ch_layout(h, 1, *[ctypes.byref(v) for v in vals]) == chlib.CH_OK
+    st_tot, it_tot, so, io = [v.value for v in vals]
+    assert st_tot == 3 * 64 * 64 + 2 * 128 * 128 + 4 * 128
+    assert it_tot == 4 * 64 * 64 + 3 * 128 * 128 + 5 * 128
+    assert so == 3 * 64 * 64 and io == 4 * 64 * 64
+    assert lib.ch_layout(h, 3, *[ctypes.byref(v) for v in vals]) == chlib.CH_ERR_ARG
+    # compute calls before binding a workspace are refused
+    assert lib.ch_fine_propagate(h, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), None, None) == chlib.CH_ERR_STATE
+    lib.ch_destroy(h)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=3), 3), (dict(n=96), 3), (dict(eps=0.0), 1), (dict(n_slices=0), 1),
+    (dict(j_fine=0), 1), (dict(dim=1, n=129), 3), (dict(m_coarse=0), 1)])
+def test_create_rejects_bad_problems(kw, code):
+    import workloads
+    p = workloads.Problem(dim=2, n=64, n_slices=2, j_fine=2)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    lib, st, h = _create([p])
+    assert st == code
+    assert not h.value
+
+
+def test_status_strings():
+    from paper_2304_14074_amd import chlib
+    lib = chlib.load()
+    assert lib.ch_status_str(0) == b"CH_OK"
+    assert lib.ch_status_str(4) == b"CH_ERR_NOCONV"

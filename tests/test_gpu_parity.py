@@ -1,0 +1,177 @@
+"""GPU vs oracle parity of every hot-path call, through the C ABI.
+
+FP64 path bound: relative L2 <= 1e-11 per state (the two sides use different
+solvers -- sine-transform GEMMs vs sparse LU -- so agreement is to rounding).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import energy as o_energy, operators, parareal, propagators
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _states(n, dim, count, seed, amps=(0.05, 0.5, 0.9)):
+    rng = np.random.default_rng(seed)
+    return np.stack([amps[i % len(amps)] * rng.uniform(-1, 1, (n,) * dim) for i in range(count)])
+
+
+@pytest.mark.parametrize("n", [32, 64, 128])
+def test_fine_2d_matches_oracle(n):
+    from paper_2304_14074_amd import chlib
+    J = 40
+    p = workloads.Problem(dim=2, n=n, eps=0.02, T=3 * J * 2e-5, n_slices=3, j_fine=J)
+    ctx = chlib.Context([p])
+    X = _states(n, 2, 3, seed=n)
+    print(f"fine 2D n={n} J={J}", flush=True)
+    out = gu.fine(ctx, [X])[0]
+    for s in range(3):
+        ref = propagators.fine(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+def test_fine_1d_full_small_config():
+    from paper_2304_14074_amd import chlib
+    p = workloads.small_1d()
+    ctx = chlib.Context([p])
+    X = _states(128, 1, p.n_slices, seed=1, amps=(0.1, 0.6, 0.95))
+    print("fine 1D n=128 J=313 N=16", flush=True)
+    out = gu.fine(ctx, [X])[0]
+    for s in range(p.n_slices):
+        ref = propagators.fine(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+@pytest.mark.parametrize("dim,n,kind,m", [(2, 32, "approx2", 1), (2, 64, "approx2", 1),
+                                          (2, 128, "approx2", 1), (2, 64, "approx2", 2),
+                                          (2, 64, "stab", 4), (1, 128, "approx2", 1),
+                                          (1, 128, "stab", 2)])
+def test_coarse_matches_oracle(dim, n, kind, m):
+    from paper_2304_14074_amd import chlib
+    p = workloads.Problem(dim=dim, n=n, eps=0.02, T=3 / 32, n_slices=3, j_fine=10, m_coarse=m,
+                          coarse_kind=kind)
+    ctx = chlib.Context([p])
+    X = _states(n, dim, 3, seed=7 + n)
+    print(f"coarse {kind} dim={dim} n={n} m={m}", flush=True)
+    out = gu.coarse(ctx, [X])[0]
+    for s in range(3):
+        ref = propagators.coarse(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+def test_mask_leaves_unmasked_slices_untouched():
+    from paper_2304_14074_amd import chlib
+    p = workloads.Problem(dim=2, n=64, eps=0.03, T=4e-4, n_slices=4, j_fine=5)
+    ctx = chlib.Context([p])
+    X = _states(64, 2, 4, seed=3)
+    U = gu.pack_slices(ctx, [X])
+    F = torch.full_like(U, 7.0)
+    mask = torch.tensor([1, 0, 1, 0], dtype=torch.uint8, device="cuda")
+    ctx.ch_fine_propagate(U, F, mask)
+    torch.cuda.synchronize()
+    out = gu.unpack_slices(ctx, F)[0]
+    assert np.all(out[1] == 7.0) and np.all(out[3] == 7.0)
+    assert gu.rel(out[0], propagators.fine(p, X[0])) < TOL
+
+
+def test_ragged_batch_of_instances():
+    from paper_2304_14074_amd import chlib
+    probs = [workloads.Problem(dim=2, n=64, eps=0.03, T=2 * 10 * 2e-5, n_slices=2, j_fine=10),
+             workloads.Problem(dim=2, n=128, eps=0.015, T=1 * 10 * 2e-5, n_slices=1, j_fine=10),
+             workloads.Problem(dim=1, n=128, eps=0.03, T=3 * 20 * 1e-4, n_slices=3, j_fine=20),
+             workloads.Problem(dim=2, n=32, eps=0.04, T=2 * 7 * 3e-5, n_slices=2, j_fine=7)]
+    ctx = chlib.Context(probs)
+    states = [_states(p.n, p.dim, p.n_slices, seed=20 + i) for i, p in enumerate(probs)]
+    outs = gu.fine(ctx, states)
+    for p, X, out in zip(probs, states, outs):
+        for s in range(p.n_slices):
+            assert gu.rel(out[s], propagators.fine(p, X[s])) < TOL
+
+
+def test_f_zero_closed_form_mode_decay():
+    # f == 0: a sine mode decays by rho^J exactly (up to rounding)
+    from paper_2304_14074_amd import chlib
+    n, J, dt, eps, s = 64, 50, 2e-5, 0.02, 2.0
+    p = workloads.Problem(dim=2, n=n, eps=eps, T=J * dt, n_slices=1, j_fine=J, f_zero=True)
+    ctx = chlib.Context([p])
+    x = np.arange(1, n + 1) / (n + 1)
+    u = np.outer(np.sin(3 * np.pi * x), np.sin(5 * np.pi * x))
+    lam = lambda k: 2 * (n + 1) ** 2 * (np.cos(k * np.pi / (n + 1)) - 1)
+    L = lam(3) + lam(5)
+    rho = (1 - s * dt * L) / (1 + dt * eps ** 2 * L ** 2 - s * dt * L)
+    out = gu.fine(ctx, [u[None]])[0][0]
+    assert gu.rel(out, rho ** J * u) < 1e-12
+
+
+def test_energy_matches_oracle():
+    from paper_2304_14074_amd import chlib
+    for dim, n in [(2, 64), (2, 128), (1, 128)]:
+        p = workloads.Problem(dim=dim, n=n, eps=0.02, T=1.0, n_slices=3, j_fine=1)
+        ctx = chlib.Context([p])
+        X = _states(n, dim, 3, seed=5)
+        u = torch.from_numpy(X.reshape(-1)).cuda()
+        E = torch.zeros(3, dtype=torch.float64, device="cuda")
+        ctx.ch_energy(0, u, 3, E)
+        torch.cuda.synchronize()
+        for s in range(3):
+            ref = o_energy.energy(X[s], 0.02)
+            assert abs(E[s].item() - ref) <= 1e-13 * abs(ref)
+
+
+def _oracle_run(p, u0, K):
+    return parareal.parareal(u0, p.n_slices, lambda u: propagators.fine(p, u),
+                             lambda u: propagators.coarse(p, u),
+                             lambda v: operators.norm_h(v, p.dim), tol=0.0, kmax=K)
+
+
+@pytest.mark.parametrize("dim,n,kind", [(2, 64, "approx2"), (1, 128, "approx2"), (2, 32, "stab")])
+def test_parareal_iterates_match_oracle(dim, n, kind):
+    from paper_2304_14074_amd import chlib
+    N, J = 5, 25
+    p = workloads.Problem(dim=dim, n=n, eps=0.03, T=N * J * 4e-5, n_slices=N, j_fine=J,
+                          coarse_kind=kind, m_coarse=2 if kind == "stab" else 1)
+    u0 = workloads.u0_uniform(n, dim, 0.3, 11)
+    ctx = chlib.Context([p])
+    st = ctx.new_state()
+    st["U"][: n ** dim] = torch.from_numpy(u0.reshape(-1)).cuda()
+    ref = _oracle_run(p, u0, N)
+    print(f"parareal dim={dim} n={n} {kind}", flush=True)
+    ctx.ch_parareal_iterate(st, 0.0)   # coarse prediction
+    torch.cuda.synchronize()
+    U = gu.unpack_iter(ctx, st["U"])[0]
+    for j in range(N + 1):
+        assert gu.rel(U[j], ref["U"][0][j]) < TOL, ("k=0", j)
+    for k in range(1, N + 1):
+        ctx.ch_parareal_iterate(st, 0.0)
+        torch.cuda.synchronize()
+        U = gu.unpack_iter(ctx, st["U"])[0]
+        for j in range(N + 1):
+            assert gu.rel(U[j], ref["U"][k][j]) < TOL, (k, j, gu.rel(U[j], ref["U"][k][j]))
+        d = st["delta"][0].item()
+        assert abs(d - ref["delta"][k - 1]) <= 1e-9 * max(ref["delta"][k - 1], 1e-300) + 1e-15
+
+
+def test_finite_termination_bitwise_on_gpu():
+    # U_n^k equals the GPU's own sequential fine chain bit for bit for n <= k
+    from paper_2304_14074_amd import chlib
+    N, J, n = 4, 15, 64
+    p = workloads.Problem(dim=2, n=n, eps=0.03, T=N * J * 4e-5, n_slices=N, j_fine=J)
+    u0 = workloads.u0_uniform(n, 2, 0.3, 12)
+    ctx = chlib.Context([p])
+    one = chlib.Context([workloads.Problem(dim=2, n=n, eps=0.03, T=J * 4e-5, n_slices=1, j_fine=J)])
+    seq = [u0]
+    for _ in range(N):
+        seq.append(gu.fine(one, [seq[-1][None]])[0][0])
+    st = ctx.new_state()
+    st["U"][: n * n] = torch.from_numpy(u0.reshape(-1)).cuda()
+    ctx.ch_parareal_iterate(st, 0.0)
+    for k in range(1, N + 1):
+        ctx.ch_parareal_iterate(st, 0.0)
+        torch.cuda.synchronize()
+        U = gu.unpack_iter(ctx, st["U"])[0]
+        for j in range(0, k + 1):
+            assert np.array_equal(U[j], seq[j]), (k, j)
