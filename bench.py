@@ -1,0 +1,170 @@
+"""Benchmark of the Parareal hot path on one MI355X.
+
+Workload: 2D Cahn-Hilliard on a 128 x 128 interior grid, eps = 0.02, T = 2,
+N = 64 slices, J = 1563 fine steps per slice (dt = 2e-5 nominal), linear
+stabilised fine step (s = 2) in FP64, coarse propagator = scheme (2.4) solved
+by spectral CG, u0 = 0.05 * Uniform(-1, 1) (seed 0).
+
+One step = one Parareal iteration over all 64 slices: the fine sweep
+(ch_fine_propagate) followed by the sequential coarse sweep, correction and
+update norm (ch_parareal_correct).  value = fine grid-point-steps per second
+of whole steps (N * J * n^2 per step).  The fine-sweep kernel is also timed
+alone with HIP events on the stream it runs on, for the roofline figure.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fine grid-point-steps/s; Parareal time-to-1e-8 (neural G vs plain G), 1 GPU"
+FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
+HBM_PEAK_GBS = 8000.0
+
+
+def fine_flops_per_point_step(n: int) -> float:
+    """Executed FP64 flops of one linear fine step per grid point: four
+    folded sine-transform stages, each 2 * (n/2)^2 * n multiply-adds per
+    n^2 points -> 4 * n flops per point (the even/odd fold halves 8n)."""
+    return 4.0 * n
+
+
+def cpu_baseline(prob, u0, budget_s: float = 12.0) -> dict:
+    """The oracle's fine propagator (sparse-LU linear step), timed as it is
+    on a bounded sample of the same workload: one slice, S fine steps."""
+    import numpy as np
+    from oracle import propagators
+    t0 = time.perf_counter()
+    propagators.fine(prob, u0, steps=10)
+    per = (time.perf_counter() - t0) / 10
+    steps = max(20, int(budget_s / max(per, 1e-6)))
+    t0 = time.perf_counter()
+    propagators.fine(prob, u0, steps=steps)
+    dt = time.perf_counter() - t0
+    pts = prob.n ** prob.dim
+    return {"value": steps * pts / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 slice x {steps} fine steps of the {prob.n}x{prob.n} linear step "
+                      f"(scipy sparse LU, single thread); host os.cpu_count()={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the slice-parallel multi-GPU design is described but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2304_14074_amd import chlib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prob = workloads.linear_2d_128()
+    u0 = workloads.linear_2d_128_u0(0)
+    n, N, J = prob.n, prob.n_slices, prob.j_fine
+    P = n * n
+    ctx = chlib.Context([prob])
+    st = ctx.new_state()
+    st["U"][:P] = torch.from_numpy(u0.reshape(-1)).cuda()
+    stream = torch.cuda.current_stream()
+    ctx.ch_parareal_iterate(st, 0.0)           # coarse prediction U^0 (untimed)
+    torch.cuda.synchronize()
+    U_in = st["U"][: N * P]                     # slice inputs U_0..U_{N-1}
+
+    def one_step(ev=None):
+        st["c"].k = 0                           # every step sweeps all N slices
+        if ev:
+            ev[0].record(stream)
+        ctx.ch_fine_propagate(U_in, st["F"])
+        if ev:
+            ev[1].record(stream)
+        ctx.ch_parareal_correct(st, 0.0)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fine_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    corr_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    ms_per_step = wall * 1e3 / args.steps
+    point_steps = N * J * P
+    value = point_steps / (ms_per_step / 1e3)
+    fine_avg = sum(fine_ms) / len(fine_ms)
+    flops = point_steps * fine_flops_per_point_step(n)
+    achieved = flops / (fine_avg / 1e3) / 1e12
+
+    extra = {"fine_sweep_ms": fine_avg, "correction_ms": sum(corr_ms) / len(corr_ms),
+             "fine_only_point_steps_per_s": point_steps / (fine_avg / 1e3),
+             "fine_kernel_flops": flops}
+    if not args.no_ttt:
+        # Parareal from scratch to an update norm below 1e-8, plain coarse G
+        st2 = ctx.new_state()
+        st2["U"][:P] = torch.from_numpy(u0.reshape(-1)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.ch_parareal_iterate(st2, 1e-8)
+        deltas = []
+        while st2["c"].k < N:
+            ctx.ch_parareal_iterate(st2, 1e-8)
+            d = st2["delta"][0].item()       # one device->host read per iteration
+            deltas.append(d)
+            if d < 1e-8:
+                break
+        ttt = time.perf_counter() - t0
+        # serial fine solve on the GPU for comparison: N dependent one-slice sweeps
+        one = chlib.Context([workloads.Problem(dim=2, n=n, eps=prob.eps, T=prob.dT, n_slices=1,
+                                               j_fine=J)])
+        a = torch.from_numpy(u0.reshape(-1)).cuda()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(N):
+            one.ch_fine_propagate(a, b)
+            a, b = b, a
+        torch.cuda.synchronize()
+        serial = time.perf_counter() - t0
+        extra.update({"plain_G_time_to_1e-8_s": ttt, "plain_G_iterations": len(deltas),
+                      "plain_G_deltas_first_last": [deltas[0], deltas[-1]],
+                      "serial_fine_gpu_s": serial, "neural_G_time_to_1e-8_s": None})
+
+    out = {"metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "2D CH 128x128 interior grid, eps=0.02, T=2, N=64 slices, "
+                                  "J=1563 (dt=1.9994e-5), linear stabilised fine step s=2, FP64, "
+                                  "coarse scheme (2.4) by spectral CG; one Parareal iteration "
+                                  "over all slices per step",
+                      "n": n, "slices": N, "fine_steps": J, "precision": "fp64"},
+           "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                        "kernel": "k_fine_linear_2d<128,4> (fine sweep, all slices)"},
+           "extra": extra}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, u0)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

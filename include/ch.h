@@ -121,6 +121,14 @@ ch_status ch_coarse_propagate(ch_ctx* ctx, const double* U_in, double* G_out,
  * tol are left unchanged.  No host synchronisation inside. */
 ch_status ch_parareal_iterate(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream);
 
+/* The second half of ch_parareal_iterate alone (after the prediction): with
+ * st->F already holding F(U_n^k) for n >= k, run the sequential coarse sweep
+ * and correction of (2.2) and the update norm, and advance st->k.  For a
+ * single instance the slice inputs U_0..U_{N-1} are the first N states of
+ * the iterate layout, so ch_fine_propagate(st->U, st->F) followed by this
+ * call equals one ch_parareal_iterate. */
+ch_status ch_parareal_correct(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream);
+
 /* Discrete energy (Section 1, (1.2)) of `count` states of instance `inst`:
  * E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u).  E_out is
  * device memory of `count` doubles. */

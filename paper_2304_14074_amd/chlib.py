@@ -22,8 +22,8 @@ PREC = {"fp64": 0, "split_bf16": 1}
 
 # every symbol include/ch.h declares
 EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
-           "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate", "ch_energy",
-           "ch_status_str", "ch_last_error")
+           "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
+           "ch_parareal_correct", "ch_energy", "ch_status_str", "ch_last_error")
 
 
 class ChProblem(ctypes.Structure):
@@ -67,13 +67,15 @@ def load() -> ctypes.CDLL:
     lib.ch_fine_propagate.argtypes = [vp, vp, vp, vp, vp]
     lib.ch_coarse_propagate.argtypes = [vp, vp, vp, vp, vp]
     lib.ch_parareal_iterate.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, vp]
+    lib.ch_parareal_correct.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, vp]
     lib.ch_energy.argtypes = [vp, i32, vp, i32, vp, vp]
     lib.ch_status_str.argtypes = [i32]
     lib.ch_status_str.restype = ctypes.c_char_p
     lib.ch_last_error.argtypes = [vp]
     lib.ch_last_error.restype = ctypes.c_char_p
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
-                 "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate", "ch_energy"):
+                 "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
+                 "ch_parareal_correct", "ch_energy"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -151,11 +153,20 @@ class Context:
                 "status": torch.zeros(n, dtype=torch.int32, device=dev),
                 "c": ChPrState(0, 0, 0, 0, 0, 0, 0)}
 
-    def ch_parareal_iterate(self, state, tol, stream=None):
+    @staticmethod
+    def _state_struct(state):
         c = state["c"]
         c.U, c.F, c.G_old = state["U"].data_ptr(), state["F"].data_ptr(), state["G_old"].data_ptr()
         c.delta, c.status = state["delta"].data_ptr(), state["status"].data_ptr()
+        return c
+
+    def ch_parareal_iterate(self, state, tol, stream=None):
+        c = self._state_struct(state)
         self._check(self.lib.ch_parareal_iterate(self.h, ctypes.byref(c), float(tol), _stream(stream)))
+
+    def ch_parareal_correct(self, state, tol, stream=None):
+        c = self._state_struct(state)
+        self._check(self.lib.ch_parareal_correct(self.h, ctypes.byref(c), float(tol), _stream(stream)))
 
     def ch_energy(self, inst, u, count, E_out, stream=None):
         self._check(self.lib.ch_energy(self.h, inst, _ptr(u), count, _ptr(E_out), _stream(stream)))

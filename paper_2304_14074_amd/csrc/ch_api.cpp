@@ -395,15 +395,20 @@ ch_status ch_coarse_propagate(ch_ctx* c, const double* U_in, double* G_out, cons
   return coarse_all(c, 0, U_in, G_out, mask, nullptr, 0, (hipStream_t)stream);
 }
 
-ch_status ch_parareal_iterate(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream) {
+static ch_status pr_check(ch_ctx* c, ch_pr_state* st) {
   ch_status r = require_bound(c);
   if (r != CH_OK) return r;
   if (!st || !st->U || !st->F || !st->G_old || !st->delta || !st->status)
     return fail(c, CH_ERR_ARG, "incomplete ch_pr_state");
   if (st->k < 0) return fail(c, CH_ERR_ARG, "negative iteration counter");
-  hipStream_t s = (hipStream_t)stream;
+  return CH_OK;
+}
+
+// phase 0: prediction; 1: fine sweep + correction; 2: correction only.
+static ch_status pr_step(ch_ctx* c, ch_pr_state* st, double tol, hipStream_t s, int with_fine) {
   int32_t* active = (int32_t*)(c->ws + c->active_blk.off);
   const int n_inst = (int)c->probs.size();
+  ch_status r;
   if (!st->predicted) {
     r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 1, s), "flags");
     if (r != CH_OK) return r;
@@ -416,12 +421,27 @@ ch_status ch_parareal_iterate(ch_ctx* c, ch_pr_state* st, double tol, ch_stream 
     r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 0, s), "flags");
     if (r != CH_OK) return r;
   }
-  r = fine_all(c, st->U, st->F, nullptr, active, st->k, 1, s);
-  if (r != CH_OK) return r;
+  if (with_fine) {
+    r = fine_all(c, st->U, st->F, nullptr, active, st->k, 1, s);
+    if (r != CH_OK) return r;
+  }
   r = coarse_all(c, 2, nullptr, nullptr, nullptr, st, st->k, s);
   if (r != CH_OK) return r;
   st->k += 1;
   return CH_OK;
+}
+
+ch_status ch_parareal_iterate(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream) {
+  ch_status r = pr_check(c, st);
+  if (r != CH_OK) return r;
+  return pr_step(c, st, tol, (hipStream_t)stream, 1);
+}
+
+ch_status ch_parareal_correct(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream) {
+  ch_status r = pr_check(c, st);
+  if (r != CH_OK) return r;
+  if (!st->predicted) return fail(c, CH_ERR_STATE, "the coarse prediction has not been formed");
+  return pr_step(c, st, tol, (hipStream_t)stream, 0);
 }
 
 ch_status ch_energy(ch_ctx* c, int32_t inst, const double* u, int32_t count, double* E_out,
