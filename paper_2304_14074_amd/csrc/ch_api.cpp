@@ -197,7 +197,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     cp.items_blk = take(sizeof(WorkItem) * cp.items.size());
     cp.insts_blk = take(sizeof(int32_t) * cp.insts.size());
     const size_t n = cp.n;
-    cp.sine_blk = cp.dim == 2 ? take(sizeof(double) * (2 * (n / 2) * (n / 2) + n))
+    cp.sine_blk = cp.dim == 2 ? take(sizeof(double) * (2 * (n + 1) + n))
                               : take(sizeof(double) * (n * n + n));
   }
   c->rsig_fine_blk.resize(n_inst);
@@ -283,14 +283,9 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
     const int n = cp.n;
     double* t = (double*)(img.data() + cp.sine_blk.off);
     if (cp.dim == 2) {
-      const int H = n / 2;
-      // Se[a][m] = S[a][2m], So[a][m] = S[a][2m+1]  (0-based), then lam
-      for (int a = 0; a < H; ++a)
-        for (int m = 0; m < H; ++m) {
-          t[a * H + m] = sine_entry(a + 1, 2 * m + 1, n);
-          t[H * H + a * H + m] = sine_entry(a + 1, 2 * m + 2, n);
-        }
-      for (int k = 0; k < n; ++k) t[2 * H * H + k] = lap_eig(k + 1, n);
+      // T[m] = sqrt(2/(n+1)) sin(m pi/(n+1)), m < 2(n+1), then lam
+      for (int m = 0; m < 2 * (n + 1); ++m) t[m] = sine_entry(m, 1, n);
+      for (int k = 0; k < n; ++k) t[2 * (n + 1) + k] = lap_eig(k + 1, n);
     } else {
       for (int a = 0; a < n; ++a)
         for (int b = 0; b < n; ++b) t[a * n + b] = sine_entry(a + 1, b + 1, n);
@@ -302,7 +297,7 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
   if (st != CH_OK) return st;
   for (auto& cp : c->classes) {
     if (cp.dim != 2) continue;
-    const double* lam = (const double*)(ws + cp.sine_blk.off) + 2 * (cp.n / 2) * (cp.n / 2);
+    const double* lam = (const double*)(ws + cp.sine_blk.off) + 2 * (cp.n + 1);
     st = hip_check(c, chk::launch_cg_tables(cp.n, 2, (const int32_t*)(ws + cp.insts_blk.off),
                                             (int)cp.insts.size(),
                                             (const InstDev*)(ws + c->inst_blk.off), lam, s),
@@ -331,8 +326,7 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
     const double* tab = class_sine(c, cp);
     hipError_t e;
     if (cp.dim == 2) {
-      const int H = cp.n / 2;
-      e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, tab + H * H, U_in, F_out,
+      e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                               mask, active, k_min, in_iter, s);
     } else {
       e = chk::launch_fine_1d(cp.n, items, (int)cp.items.size(), inst, tab, nullptr, U_in, F_out,
@@ -370,9 +364,8 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     int32_t* status = st ? st->status : nullptr;
     hipError_t e;
     if (cp.dim == 2) {
-      const int H = cp.n / 2;
       e = chk::launch_coarse_2d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
-                                inst, tab, tab + H * H, U_in, G_out, mask, U, F, Gold, delta, status,
+                                inst, tab, U_in, G_out, mask, U, F, Gold, delta, status,
                                 active, k, s);
     } else {
       e = chk::launch_coarse_1d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),

@@ -29,7 +29,7 @@ struct WorkItem { int32_t inst, slice; };
 // Fine sweep.  Work items with slice < k_min or an inactive instance are
 // skipped; in_iter selects the iterate layout for the input states.
 hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
-                          const double* Se, const double* So, const double* U_in,
+                          const double* Tsin, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,
                           int k_min, int in_iter, hipStream_t s);
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
@@ -40,7 +40,7 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
 // 2: correction chain starting at slice k+1 with U_{k+1} = F_k.
 hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const WorkItem* items, int n_items, const InstDev* inst,
-                            const double* Se, const double* So, const double* U_in,
+                            const double* Tsin, const double* U_in,
                             double* G_out, const uint8_t* mask, double* U, const double* F,
                             double* G_old, double* delta, int32_t* status,
                             const int32_t* active, int k, hipStream_t s);

@@ -12,9 +12,10 @@
 // Y[a] = E[a] + O[a] and Y[n-1-a] = E[a] - O[a] -- half the multiply-adds.
 //
 // A workgroup owns one n x n state for a whole sequence of steps: the state
-// lives in LDS (n = 64, 128), the folded sine rows of its waves stay in
-// registers, and the state never leaves the CU between the J fine steps of a
-// slice.
+// lives in LDS (n = 32, 64, 128) and never leaves the CU between the J fine
+// steps of a slice.  The sine operands come from a 2(n+1)-entry table in LDS:
+// S[a][b] depends only on (a+1)(b+1) mod 2(n+1), so each lane walks the table
+// with an incremental index instead of holding rows of S in registers.
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include "ch_internal.h"
@@ -32,9 +33,13 @@ struct Geo {
   static constexpr int WPR = NW / TR;    // waves per tile row
   static constexpr int CPW = TC / WPR;   // tile columns per wave
   static constexpr int KS = H / 4;       // k-steps of 4
-  static constexpr int LDX = N + 1;      // LDS row stride (odd: transposed writes spread banks)
+  static constexpr int LDX = N + 3;      // LDS row stride: zero halo column each side, odd
+                                         // stride (transposed writes spread over banks)
   static constexpr int NT = NW * 64;     // threads
   static constexpr int OWN = 8 * CPW;    // points owned per thread
+  static constexpr int P2 = 2 * (N + 1);  // period of the sine table
+  static constexpr int XSZ = (N + 2) * LDX;  // doubles of the LDS state incl. zero halo ring
+  static constexpr int XOFF = LDX + 1;       // interior origin within the LDS state
   static_assert(NW % TR == 0, "waves must tile the folded rows");
   static_assert(TC % WPR == 0, "waves must tile the columns");
   static_assert(OWN * NT == N * N, "ownership must cover the grid");
@@ -61,26 +66,36 @@ struct Lane {
   __device__ __forceinline__ int col_c(int q) const { return 16 * (c0 + q) + j; }
 };
 
+// Sine-table walk of one lane: the A operand of k-step ks is
+// Se[16 tr + j][4 ks + g] = S[a][2(4ks+g)]   (E)  and
+// So[16 tr + j][4 ks + g] = S[a][2(4ks+g)+1] (O), a = 16 tr + j, i.e. table
+// entries (a+1)(8ks+2g+1) and (a+1)(8ks+2g+2) mod 2(n+1).
+struct SineWalk {
+  int e0, o0, step;
+};
 template <int N, int NW>
-__device__ __forceinline__ void load_sine_regs(const double* __restrict__ Se,
-                                               const double* __restrict__ So,
-                                               const Lane<N, NW>& L,
-                                               double (&sE)[Geo<N, NW>::KS],
-                                               double (&sO)[Geo<N, NW>::KS]) {
-  constexpr int H = Geo<N, NW>::H;
-#pragma unroll
-  for (int ks = 0; ks < Geo<N, NW>::KS; ++ks) {
-    const int row = 16 * L.tr + L.j, col = 4 * ks + L.g;
-    sE[ks] = Se[row * H + col];
-    sO[ks] = So[row * H + col];
-  }
+__device__ __forceinline__ SineWalk sine_walk(const Lane<N, NW>& L) {
+  constexpr int P2 = Geo<N, NW>::P2;
+  const int a1 = 16 * L.tr + L.j + 1;
+  SineWalk w;
+  w.e0 = (a1 * (2 * L.g + 1)) % P2;
+  w.o0 = (a1 * (2 * L.g + 2)) % P2;
+  w.step = (8 * a1) % P2;
+  return w;
+}
+// Table T[m] = sqrt(2/(n+1)) sin(m pi/(n+1)), m < 2(n+1), copied to LDS.
+template <int N, int NW>
+__device__ __forceinline__ void load_sine_table(double* T, const double* __restrict__ Tg) {
+  for (int m = threadIdx.x; m < Geo<N, NW>::P2; m += Geo<N, NW>::NT) T[m] = Tg[m];
 }
 
 // One stage: accumulators E = Se X[even rows], O = So X[odd rows] for this
-// wave's tiles.  X is the LDS state (row stride LDX).
+// wave's tiles.  X is the LDS state (row stride LDX), T the LDS sine table.
+// Software-pipelined: the operands of k-step ks+1 are read from LDS while the
+// MFMAs of k-step ks run; the scheduling barrier keeps the compiler from
+// hoisting every read of the unrolled loop.
 template <int N, int NW>
-__device__ __forceinline__ void mma_stage(const double* X, const double (&sE)[Geo<N, NW>::KS],
-                                          const double (&sO)[Geo<N, NW>::KS],
+__device__ __forceinline__ void mma_stage(const double* X, const double* T, const SineWalk& sw,
                                           d4 (&aE)[Geo<N, NW>::CPW], d4 (&aO)[Geo<N, NW>::CPW],
                                           const Lane<N, NW>& L) {
   using G = Geo<N, NW>;
@@ -89,10 +104,9 @@ __device__ __forceinline__ void mma_stage(const double* X, const double (&sE)[Ge
     aE[q] = d4{0.0, 0.0, 0.0, 0.0};
     aO[q] = d4{0.0, 0.0, 0.0, 0.0};
   }
-  // Software-pipelined: the B operands of k-step ks+1 are read from LDS
-  // while the MFMAs of k-step ks run; the scheduling barrier keeps the
-  // compiler from hoisting every read of the unrolled loop (register blow-up).
   const double* base = X + (2 * L.g) * G::LDX + 16 * L.c0 + L.j;
+  int ie = sw.e0, io = sw.o0;
+  double se = T[ie], so = T[io];
   double be[G::CPW], bo[G::CPW];
 #pragma unroll
   for (int q = 0; q < G::CPW; ++q) {
@@ -101,8 +115,14 @@ __device__ __forceinline__ void mma_stage(const double* X, const double (&sE)[Ge
   }
 #pragma unroll
   for (int ks = 0; ks < G::KS; ++ks) {
-    double ne[G::CPW], no[G::CPW];
+    double ne[G::CPW], no[G::CPW], nse = 0.0, nso = 0.0;
     if (ks + 1 < G::KS) {
+      ie += sw.step;
+      ie -= (ie >= G::P2) ? G::P2 : 0;
+      io += sw.step;
+      io -= (io >= G::P2) ? G::P2 : 0;
+      nse = T[ie];
+      nso = T[io];
       const double* pe = base + (8 * (ks + 1)) * G::LDX;
 #pragma unroll
       for (int q = 0; q < G::CPW; ++q) {
@@ -112,10 +132,12 @@ __device__ __forceinline__ void mma_stage(const double* X, const double (&sE)[Ge
     }
 #pragma unroll
     for (int q = 0; q < G::CPW; ++q) {
-      aE[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sE[ks], be[q], aE[q], 0, 0, 0);
-      aO[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sO[ks], bo[q], aO[q], 0, 0, 0);
+      aE[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(se, be[q], aE[q], 0, 0, 0);
+      aO[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(so, bo[q], aO[q], 0, 0, 0);
     }
     if (ks + 1 < G::KS) {
+      se = nse;
+      so = nso;
 #pragma unroll
       for (int q = 0; q < G::CPW; ++q) {
         be[q] = ne[q];
@@ -174,20 +196,21 @@ __device__ __forceinline__ void load_owned(const double* X, const Lane<N, NW>& L
 // Full stage: X <- (S X)^T, optionally scaled pointwise by w at the owned
 // (row, col) positions of the result (w in row-major n x n, may be null).
 template <int N, int NW>
-__device__ __forceinline__ void stage(double* X, const double (&sE)[Geo<N, NW>::KS],
-                                      const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
-                                      const double* __restrict__ w) {
+__device__ __forceinline__ void stage(double* X, const double* T, const SineWalk& sw,
+                                      const Lane<N, NW>& L, const double* __restrict__ w) {
   using G = Geo<N, NW>;
   d4 aE[G::CPW], aO[G::CPW];
-  mma_stage<N, NW>(X, sE, sO, aE, aO, L);
+  mma_stage<N, NW>(X, T, sw, aE, aO, L);
   double y[G::OWN];
   unfold<N, NW>(aE, aO, y);
   if (w) {
+    // w is symmetric: read w[col][row] so that lanes with consecutive
+    // rows (consecutive j) read consecutive addresses.
 #pragma unroll
     for (int s = 0; s < G::OWN; ++s) {
       int row, col;
       own_rc<N, NW>(L, s, row, col);
-      y[s] *= w[row * N + col];
+      y[s] *= w[col * N + row];
     }
   }
   __syncthreads();  // every wave has finished reading X
@@ -197,12 +220,11 @@ __device__ __forceinline__ void stage(double* X, const double (&sE)[Geo<N, NW>::
 
 // Last stage of a pass: the result stays in registers (owned values).
 template <int N, int NW>
-__device__ __forceinline__ void stage_regs(const double* X, const double (&sE)[Geo<N, NW>::KS],
-                                           const double (&sO)[Geo<N, NW>::KS],
+__device__ __forceinline__ void stage_regs(const double* X, const double* T, const SineWalk& sw,
                                            const Lane<N, NW>& L, double (&y)[Geo<N, NW>::OWN]) {
   using G = Geo<N, NW>;
   d4 aE[G::CPW], aO[G::CPW];
-  mma_stage<N, NW>(X, sE, sO, aE, aO, L);
+  mma_stage<N, NW>(X, T, sw, aE, aO, L);
   unfold<N, NW>(aE, aO, y);
 }
 
@@ -273,7 +295,7 @@ __device__ __forceinline__ void rhs_owned(double* X, const Lane<N, NW>& L,
   using G = Geo<N, NW>;
 #pragma unroll
   for (int k = 0; k < G::OWN; ++k) {
-    const double u = v[k];
+    const double u = v[k];  // w = f(u) - s u (zero on the boundary)
     X[own_off<N, NW>(L, k)] = f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
   }
   __syncthreads();
@@ -281,12 +303,13 @@ __device__ __forceinline__ void rhs_owned(double* X, const Lane<N, NW>& L,
   for (int k = 0; k < G::OWN; ++k) {
     int row, col;
     own_rc<N, NW>(L, k, row, col);
+    // the zero halo ring of X supplies the Dirichlet ghost values
     const double* p = X + row * G::LDX + col;
     const double wc = p[0];
-    const double wn = (row > 0) ? p[-G::LDX] : 0.0;
-    const double ws = (row < N - 1) ? p[G::LDX] : 0.0;
-    const double ww = (col > 0) ? p[-1] : 0.0;
-    const double we = (col < N - 1) ? p[1] : 0.0;
+    const double wn = p[-G::LDX];
+    const double ws = p[G::LDX];
+    const double ww = p[-1];
+    const double we = p[1];
     v[k] = v[k] + c_lap * ((wn + ws) + (ww + we) - 4.0 * wc);
   }
   __syncthreads();
@@ -297,23 +320,28 @@ __device__ __forceinline__ void rhs_owned(double* X, const Lane<N, NW>& L,
 // nsteps linear steps starting from the state in X (state orientation);
 // the result is left in X and in v.
 template <int N, int NW>
-__device__ void linear_steps(double* X, const double (&sE)[Geo<N, NW>::KS],
-                             const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
+__device__ void linear_steps(double* X, const double* T, const SineWalk& sw, const Lane<N, NW>& L,
                              double (&v)[Geo<N, NW>::OWN], int nsteps, double c_lap, double s,
                              int f_zero, const double* __restrict__ rsig) {
   load_owned<N, NW>(X, L, v);
   for (int m = 0; m < nsteps; ++m) {
     rhs_owned<N, NW>(X, L, v, c_lap, s, f_zero);
-    stage<N, NW>(X, sE, sO, L, nullptr);  // X = (S r)^T
-    stage<N, NW>(X, sE, sO, L, rsig);     // X = (S r S) / sigma   (spectral)
-    stage<N, NW>(X, sE, sO, L, nullptr);
-    stage_regs<N, NW>(X, sE, sO, L, v);   // v = S (.) S   (state, owned)
+    stage<N, NW>(X, T, sw, L, nullptr);  // X = (S r)^T
+    stage<N, NW>(X, T, sw, L, rsig);     // X = (S r S) / sigma   (spectral)
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, v);   // v = S (.) S   (state, owned)
     __syncthreads();
     store_owned<N, NW>(X, L, v);
     __syncthreads();
   }
 }
 
+// Zero the whole LDS state buffer (the halo ring stays zero afterwards: the
+// transform stages only ever write interior points).  Xbuf = buffer start.
+template <int N, int NW>
+__device__ __forceinline__ void zero_state(double* Xbuf) {
+  for (int i = threadIdx.x; i < Geo<N, NW>::XSZ; i += Geo<N, NW>::NT) Xbuf[i] = 0.0;
+}
 template <int N, int NW>
 __device__ __forceinline__ void load_state(double* X, const double* __restrict__ src) {
   using G = Geo<N, NW>;
@@ -330,12 +358,12 @@ __device__ __forceinline__ void store_state(const double* X, double* __restrict_
 template <int N, int NW>
 __global__ void __launch_bounds__(NW * 64)
 k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
-                 const double* __restrict__ Se, const double* __restrict__ So,
-                 const double* __restrict__ U_in, double* __restrict__ F_out,
-                 const uint8_t* __restrict__ mask, const int32_t* __restrict__ active,
-                 int k_min, int in_iter) {
+                 const double* __restrict__ Tg, const double* __restrict__ U_in,
+                 double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                 const int32_t* __restrict__ active, int k_min, int in_iter) {
   extern __shared__ double smem[];
-  double* X = smem;
+  double* X = smem + Geo<N, NW>::XOFF;   // interior origin
+  double* T = smem + Geo<N, NW>::XSZ;
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
@@ -343,12 +371,14 @@ k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__
   const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
   const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
   Lane<N, NW> L;
-  double sE[Geo<N, NW>::KS], sO[Geo<N, NW>::KS];
-  load_sine_regs<N, NW>(Se, So, L, sE, sO);
+  const SineWalk sw = sine_walk<N, NW>(L);
+  load_sine_table<N, NW>(T, Tg);
+  zero_state<N, NW>(smem);
+  __syncthreads();
   load_state<N, NW>(X, U_in + off_in);
   __syncthreads();
   double v[Geo<N, NW>::OWN];
-  linear_steps<N, NW>(X, sE, sO, L, v, P.j_fine, P.dt / (P.h * P.h), P.s_fine, P.f_zero,
+  linear_steps<N, NW>(X, T, sw, L, v, P.j_fine, P.dt / (P.h * P.h), P.s_fine, P.f_zero,
                       P.rsig_fine);
   store_state<N, NW>(X, F_out + off);
 }
@@ -364,9 +394,8 @@ k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__
 // CG vectors live in the per-instance scratch in "owned" order
 // (index slot * NT + thread), which is coalesced for every thread.
 template <int N, int NW>
-__device__ void approx2_solve(double* X, double* red, const double (&sE)[Geo<N, NW>::KS],
-                              const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
-                              const InstDev& P, int& status) {
+__device__ void approx2_solve(double* X, double* red, const double* T, const SineWalk& sw,
+                              const Lane<N, NW>& L, const InstDev& P, int& status) {
   using G = Geo<N, NW>;
   const int t = threadIdx.x;
   const int64_t NN = (int64_t)N * N;
@@ -393,8 +422,8 @@ __device__ void approx2_solve(double* X, double* red, const double (&sE)[Geo<N, 
     block_minmax<NW>(mn, mx, red);
     const double cshift = 0.5 * (mn + mx);
     // u_hat (2 stages), b_hat, initial CG state x = 0, r = b, p = z = M^{-1} r
-    stage<N, NW>(X, sE, sO, L, nullptr);
-    stage_regs<N, NW>(X, sE, sO, L, y);
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);
     double acc[3] = {0.0, 0.0, 0.0};  // r.z, b.b
 #pragma unroll
     for (int s = 0; s < G::OWN; ++s) {
@@ -423,11 +452,11 @@ __device__ void approx2_solve(double* X, double* red, const double (&sE)[Geo<N, 
     __syncthreads();
     while (!done) {
       // Kp = d p + tau S (q . S p S) S
-      stage<N, NW>(X, sE, sO, L, nullptr);
+      stage<N, NW>(X, T, sw, L, nullptr);
       {
         // second stage with the pointwise q at owned (state) points
         d4 aE[G::CPW], aO[G::CPW];
-        mma_stage<N, NW>(X, sE, sO, aE, aO, L);
+        mma_stage<N, NW>(X, T, sw, aE, aO, L);
         unfold<N, NW>(aE, aO, y);
 #pragma unroll
         for (int s = 0; s < G::OWN; ++s) y[s] *= cq[(int64_t)s * G::NT + t];
@@ -435,8 +464,8 @@ __device__ void approx2_solve(double* X, double* red, const double (&sE)[Geo<N, 
         store_owned<N, NW>(X, L, y);
         __syncthreads();
       }
-      stage<N, NW>(X, sE, sO, L, nullptr);
-      stage_regs<N, NW>(X, sE, sO, L, y);
+      stage<N, NW>(X, T, sw, L, nullptr);
+      stage_regs<N, NW>(X, T, sw, L, y);
       double a1[1] = {0.0};
 #pragma unroll
       for (int s = 0; s < G::OWN; ++s) {
@@ -487,23 +516,22 @@ __device__ void approx2_solve(double* X, double* red, const double (&sE)[Geo<N, 
     __syncthreads();
     store_owned<N, NW>(X, L, y);
     __syncthreads();
-    stage<N, NW>(X, sE, sO, L, nullptr);
-    stage<N, NW>(X, sE, sO, L, nullptr);
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage<N, NW>(X, T, sw, L, nullptr);
   }
 }
 
 // One coarse propagation of the state in X (state orientation), result in X.
 template <int N, int NW>
-__device__ void coarse_apply(double* X, double* red, const double (&sE)[Geo<N, NW>::KS],
-                             const double (&sO)[Geo<N, NW>::KS], const Lane<N, NW>& L,
-                             const InstDev& P, int& status) {
+__device__ void coarse_apply(double* X, double* red, const double* T, const SineWalk& sw,
+                             const Lane<N, NW>& L, const InstDev& P, int& status) {
   if (P.coarse_kind == 1) {  // stabilised step with tau = dT/m
     double v[Geo<N, NW>::OWN];
     const double tau = P.dT / P.m_coarse;
-    linear_steps<N, NW>(X, sE, sO, L, v, P.m_coarse, tau / (P.h * P.h), P.s_fine, P.f_zero,
+    linear_steps<N, NW>(X, T, sw, L, v, P.m_coarse, tau / (P.h * P.h), P.s_fine, P.f_zero,
                         P.rsig_stab);
   } else {
-    approx2_solve<N, NW>(X, red, sE, sO, L, P, status);
+    approx2_solve<N, NW>(X, red, T, sw, L, P, status);
   }
 }
 
@@ -513,35 +541,40 @@ __device__ void coarse_apply(double* X, double* red, const double (&sE)[Geo<N, N
 template <int N, int NW>
 __global__ void __launch_bounds__(NW * 64)
 k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restrict__ items,
-            const InstDev* __restrict__ inst, const double* __restrict__ Se,
-            const double* __restrict__ So, const double* __restrict__ U_in,
+            const InstDev* __restrict__ inst, const double* __restrict__ Tg,
+            const double* __restrict__ U_in,
             double* __restrict__ G_out, const uint8_t* __restrict__ mask, double* U,
             const double* __restrict__ F, double* G_old, double* delta, int32_t* status_out,
             const int32_t* __restrict__ active, int k) {
   using G = Geo<N, NW>;
   extern __shared__ double smem[];
-  double* X = smem;
-  double* red = smem + N * G::LDX;
+  double* X = smem + G::XOFF;   // interior origin
+  double* T = smem + G::XSZ;
+  double* red = T + G::P2;
   Lane<N, NW> L;
-  double sE[G::KS], sO[G::KS];
+  const SineWalk sw = sine_walk<N, NW>(L);
   int status = 0;
   const int64_t NN = (int64_t)N * N;
   if (mode == 0) {
     const WorkItem it = items[blockIdx.x];
     const InstDev P = inst[it.inst];
     if (mask && !mask[P.slice_base + it.slice]) return;
-    load_sine_regs<N, NW>(Se, So, L, sE, sO);
+    load_sine_table<N, NW>(T, Tg);
+    zero_state<N, NW>(smem);
+    __syncthreads();
     const int64_t off = P.off_slices + (int64_t)it.slice * NN;
     load_state<N, NW>(X, U_in + off);
     __syncthreads();
-    coarse_apply<N, NW>(X, red, sE, sO, L, P, status);
+    coarse_apply<N, NW>(X, red, T, sw, L, P, status);
     store_state<N, NW>(X, G_out + off);
     return;
   }
   const int ii = insts[blockIdx.x];
   if (active && !active[ii]) return;
   const InstDev P = inst[ii];
-  load_sine_regs<N, NW>(Se, So, L, sE, sO);
+  load_sine_table<N, NW>(T, Tg);
+  zero_state<N, NW>(smem);
+  __syncthreads();
   double* Ui = U + P.off_iter;
   const double* Fi = F + P.off_slices;
   double* Gi = G_old + P.off_slices;
@@ -550,7 +583,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     load_state<N, NW>(X, Ui);
     __syncthreads();
     for (int n = 0; n < Ns; ++n) {
-      coarse_apply<N, NW>(X, red, sE, sO, L, P, status);
+      coarse_apply<N, NW>(X, red, T, sw, L, P, status);
       for (int idx = threadIdx.x; idx < NN; idx += G::NT) {
         const double gv = X[(idx / N) * G::LDX + idx % N];
         Ui[(n + 1) * NN + idx] = gv;
@@ -582,7 +615,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     __syncthreads();
   }
   for (int n = k + 1; n < Ns; ++n) {
-    coarse_apply<N, NW>(X, red, sE, sO, L, P, status);
+    coarse_apply<N, NW>(X, red, T, sw, L, P, status);
     double acc[1] = {0.0};
     for (int idx = threadIdx.x; idx < NN; idx += G::NT) {
       const int xo = (idx / N) * G::LDX + idx % N;
@@ -881,27 +914,27 @@ __global__ void k_flag_active(const double* __restrict__ delta, int32_t* __restr
 // ------------------------------------------------------------ launchers
 template <int N, int NW>
 static hipError_t fine2d(const WorkItem* items, int n_items, const InstDev* inst,
-                         const double* Se, const double* So, const double* U_in, double* F_out,
+                         const double* Tg, const double* U_in, double* F_out,
                          const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
                          hipStream_t s) {
-  const size_t lds = (size_t)N * Geo<N, NW>::LDX * sizeof(double);
+  const size_t lds = (size_t)(Geo<N, NW>::XSZ + Geo<N, NW>::P2) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fine_linear_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
-                     Se, So, U_in, F_out, mask, active, k_min, in_iter);
+                     Tg, U_in, F_out, mask, active, k_min, in_iter);
   return hipGetLastError();
 }
 
 hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
-                          const double* Se, const double* So, const double* U_in, double* F_out,
+                          const double* Tg, const double* U_in, double* F_out,
                           const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
                           hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (n) {
-    case 32: return fine2d<32, 2>(items, n_items, inst, Se, So, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 64: return fine2d<64, 4>(items, n_items, inst, Se, So, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 128: return fine2d<128, 4>(items, n_items, inst, Se, So, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 32: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 64: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 128: return fine2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -922,31 +955,31 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
 
 template <int N, int NW>
 static hipError_t coarse2d(int mode, const int32_t* insts, int n_insts, const WorkItem* items,
-                           int n_items, const InstDev* inst, const double* Se, const double* So,
+                           int n_items, const InstDev* inst, const double* Tg,
                            const double* U_in, double* G_out, const uint8_t* mask, double* U,
                            const double* F, double* G_old, double* delta, int32_t* status,
                            const int32_t* active, int k, hipStream_t s) {
-  const size_t lds = ((size_t)N * Geo<N, NW>::LDX + 4 * NW) * sizeof(double);
+  const size_t lds = ((size_t)Geo<N, NW>::XSZ + Geo<N, NW>::P2 + 4 * NW) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = mode == 0 ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_coarse_2d<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts, items,
-                     inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k);
+                     inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const WorkItem* items, int n_items, const InstDev* inst,
-                            const double* Se, const double* So, const double* U_in,
+                            const double* Tg, const double* U_in,
                             double* G_out, const uint8_t* mask, double* U, const double* F,
                             double* G_old, double* delta, int32_t* status,
                             const int32_t* active, int k, hipStream_t s) {
   switch (n) {
-    case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
-    case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
-    case 128: return coarse2d<128, 4>(mode, insts, n_insts, items, n_items, inst, Se, So, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
+    case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
+    case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
+    case 128: return coarse2d<128, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -976,7 +1009,7 @@ hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts, c
   switch (n) {
     case 32: hipLaunchKernelGGL((k_cg_tables_2d<32, 2>), dim3(n_insts), dim3(128), 0, s, insts, inst, lam); break;
     case 64: hipLaunchKernelGGL((k_cg_tables_2d<64, 4>), dim3(n_insts), dim3(256), 0, s, insts, inst, lam); break;
-    case 128: hipLaunchKernelGGL((k_cg_tables_2d<128, 4>), dim3(n_insts), dim3(256), 0, s, insts, inst, lam); break;
+    case 128: hipLaunchKernelGGL((k_cg_tables_2d<128, 8>), dim3(n_insts), dim3(512), 0, s, insts, inst, lam); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
