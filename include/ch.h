@@ -65,9 +65,10 @@ typedef struct ch_problem {
   int32_t precision;    /* CH_PREC_*                                           */
   double newton_tol;    /* Newton stop: ||Y_{m+1}-Y_m||_h <= tol (1e-10)       */
   int32_t newton_max;   /* Newton iteration cap (20)                           */
-  double krylov_rtol;   /* relative residual target of the inner CG solves    */
+  double krylov_rtol;   /* relative residual target of the coarse CG solves   */
   int32_t krylov_max;   /* CG iteration cap                                    */
   int32_t f_zero;       /* test hook: f(u) == 0                                */
+  double nl_krylov_rtol;/* relative residual target of the CG inside Newton    */
 } ch_problem;
 
 typedef struct ch_ctx ch_ctx;

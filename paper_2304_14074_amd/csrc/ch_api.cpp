@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -27,8 +28,8 @@ struct Block {
   size_t off = 0, bytes = 0;
 };
 
-struct ClassPlan {      // all instances sharing (dim, n)
-  int dim = 2, n = 0;
+struct ClassPlan {      // all instances sharing (dim, n, fine kind)
+  int dim = 2, n = 0, fine_kind = 0;
   std::vector<WorkItem> items;   // every slice of every instance in the class
   std::vector<int32_t> insts;    // instance indices
   Block items_blk, insts_blk;
@@ -43,8 +44,8 @@ struct ch_ctx {
   std::vector<int64_t> slice_off, iter_off;
   int64_t slice_total = 0, iter_total = 0;
   std::vector<ClassPlan> classes;
-  Block inst_blk, active_blk;
-  std::vector<Block> rsig_fine_blk, rsig_stab_blk, cg_blk;
+  Block inst_blk, active_blk, status_blk;
+  std::vector<Block> rsig_fine_blk, rsig_stab_blk, tab_blk, work_blk;
   size_t ws_bytes = 0;
   char* ws = nullptr;               // bound workspace
   std::string err;
@@ -129,8 +130,12 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       bad = fail(c, CH_ERR_ARG, "instance %d: coarse_kind %d", i, p.coarse_kind);
     else if (p.precision != CH_PREC_FP64 && p.precision != CH_PREC_SPLIT_BF16)
       bad = fail(c, CH_ERR_ARG, "instance %d: precision %d", i, p.precision);
-    else if (p.fine_kind == CH_FINE_NONLINEAR)
-      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: nonlinear fine step not built", i);
+    else if (p.fine_kind == CH_FINE_NONLINEAR && p.dim != 2)
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: nonlinear fine step is built for 2D", i);
+    else if (p.fine_kind == CH_FINE_NONLINEAR &&
+             (p.nl_variant < CH_NL_EYRE || p.nl_variant > CH_NL_FULL_BE || p.newton_max < 1 ||
+              !(p.newton_tol > 0) || !(p.nl_krylov_rtol > 0)))
+      bad = fail(c, CH_ERR_ARG, "instance %d: Newton parameters", i);
     else if (p.coarse_kind == CH_COARSE_NEURAL)
       bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: neural coarse propagator not built", i);
     else if (p.precision == CH_PREC_SPLIT_BF16)
@@ -166,6 +171,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     d.newton_max = p.newton_max; d.precision = p.precision;
     d.eps = p.eps; d.dT = p.T / p.n_slices; d.dt = d.dT / p.j_fine; d.s_fine = p.s_fine;
     d.h = 1.0 / (p.n + 1); d.newton_tol = p.newton_tol; d.krylov_rtol = p.krylov_rtol;
+    d.nl_krylov_rtol = p.nl_krylov_rtol;
     d.off_slices = so; d.off_iter = io; d.slice_base = slice_base;
     so += (int64_t)p.n_slices * P;
     io += (int64_t)(p.n_slices + 1) * P;
@@ -174,14 +180,15 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   c->slice_total = so;
   c->iter_total = io;
   // classes
-  std::map<std::pair<int, int>, int> cls;
+  std::map<std::tuple<int, int, int>, int> cls;
   for (int i = 0; i < n_inst; ++i) {
-    auto key = std::make_pair(probs[i].dim, probs[i].n);
+    auto key = std::make_tuple(probs[i].dim, probs[i].n, probs[i].fine_kind);
     if (!cls.count(key)) {
       cls[key] = (int)c->classes.size();
       ClassPlan cp;
       cp.dim = probs[i].dim;
       cp.n = probs[i].n;
+      cp.fine_kind = probs[i].fine_kind;
       c->classes.push_back(cp);
     }
     ClassPlan& cp = c->classes[cls[key]];
@@ -193,6 +200,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   auto take = [&](size_t bytes) { Block b; b.off = off; b.bytes = bytes; off = align_up(off + bytes); return b; };
   c->inst_blk = take(sizeof(InstDev) * n_inst);
   c->active_blk = take(sizeof(int32_t) * n_inst);
+  c->status_blk = take(sizeof(int32_t) * n_inst);
   for (auto& cp : c->classes) {
     cp.items_blk = take(sizeof(WorkItem) * cp.items.size());
     cp.insts_blk = take(sizeof(int32_t) * cp.insts.size());
@@ -202,12 +210,16 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   }
   c->rsig_fine_blk.resize(n_inst);
   c->rsig_stab_blk.resize(n_inst);
-  c->cg_blk.resize(n_inst);
+  c->tab_blk.resize(n_inst);
+  c->work_blk.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) {
     const size_t P = probs[i].dim == 2 ? (size_t)probs[i].n * probs[i].n : probs[i].n;
     c->rsig_fine_blk[i] = take(sizeof(double) * P);
     c->rsig_stab_blk[i] = take(sizeof(double) * P);
-    if (probs[i].dim == 2) c->cg_blk[i] = take(sizeof(double) * P * chk::CG_VECS);
+    if (probs[i].dim == 2) {
+      c->tab_blk[i] = take(sizeof(double) * P * chk::TAB_VECS);
+      c->work_blk[i] = take(sizeof(double) * P * chk::WORK_VECS * (size_t)probs[i].n_slices);
+    }
   }
   c->ws_bytes = off;
   *out = c;
@@ -253,7 +265,9 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
     const ch_problem& p = c->probs[i];
     d.rsig_fine = (const double*)(ws + c->rsig_fine_blk[i].off);
     d.rsig_stab = (const double*)(ws + c->rsig_stab_blk[i].off);
-    d.cg = p.dim == 2 ? (double*)(ws + c->cg_blk[i].off) : nullptr;
+    d.tab = p.dim == 2 ? (double*)(ws + c->tab_blk[i].off) : nullptr;
+    d.work = p.dim == 2 ? (double*)(ws + c->work_blk[i].off) : nullptr;
+    d.status = (int32_t*)(ws + c->status_blk.off) + i;
     // inverse symbols 1/(1 + tau eps^2 Lam^2 - s tau Lam) of the linear step
     const int n = p.n;
     std::vector<double> lam(n);
@@ -325,7 +339,10 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
     const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
     const double* tab = class_sine(c, cp);
     hipError_t e;
-    if (cp.dim == 2) {
+    if (cp.dim == 2 && cp.fine_kind == CH_FINE_NONLINEAR) {
+      e = chk::launch_fine_newton_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
+                                     mask, active, k_min, in_iter, s);
+    } else if (cp.dim == 2) {
       e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                               mask, active, k_min, in_iter, s);
     } else {

@@ -19,9 +19,13 @@ struct InstDev {
   int64_t slice_base;        // index of slice 0 among all slices (mask index)
   const double* rsig_fine;   // [n^d] 1/sigma, sigma = 1 + dt eps^2 Lam^2 - s dt Lam
   const double* rsig_stab;   // [n^d] same with tau = dT/m_coarse
-  double* cg;                // per-instance CG scratch, CG_VECS * n^d doubles
+  double* tab;               // 2D: TAB_VECS * n^2 spectral tables (owned order)
+  double* work;              // 2D: per slice WORK_VECS * n^2 solver vectors
+  int32_t* status;           // solver flags raised by fine/parallel-coarse kernels
+  double nl_krylov_rtol;     // CG target inside Newton
 };
-constexpr int CG_VECS = 7;   // x, r, p, q, d, b-scale, minv (owned layout)
+constexpr int TAB_VECS = 4;   // d(coarse), 1/mu + tau(coarse), d(fine), 1/mu
+constexpr int WORK_VECS = 7;  // x, r, p, q, minv, u_hat, y_hat
 
 struct WorkItem { int32_t inst, slice; };
 
@@ -32,6 +36,10 @@ hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstD
                           const double* Tsin, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,
                           int k_min, int in_iter, hipStream_t s);
+hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                                 const double* Tsin, const double* U_in, double* F_out,
+                                 const uint8_t* mask, const int32_t* active, int k_min,
+                                 int in_iter, hipStream_t s);
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* S, const double* rsig1, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,

@@ -23,6 +23,26 @@
 namespace chk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+// A vector in "owned" order (element slot * NT + thread) accessed through a
+// buffer descriptor: the per-slot offset goes in a scalar register, so an
+// unrolled loop over slots needs one address register per thread instead of
+// one per slot.  Accesses past n_elems read 0 / are dropped by the hardware.
+struct OVec {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ OVec() {}
+  __device__ __forceinline__ OVec(const double* p, int64_t n_elems)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n_elems * 8),
+                                            0x00020000)) {}
+  __device__ __forceinline__ double ld(int elem_off, int voff_bytes) const {
+    return __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(r, voff_bytes, elem_off * 8, 0));
+  }
+  __device__ __forceinline__ void st(int elem_off, int voff_bytes, double v) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff_bytes, elem_off * 8, 0);
+  }
+};
 
 // ------------------------------------------------------------------ geometry
 template <int N, int NW>
@@ -383,136 +403,200 @@ k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__
   store_state<N, NW>(X, F_out + off);
 }
 
-// --------------------------------------------- scheme (2.4) by spectral CG
-// (I - tau Lap diag(u^2) + eps^2 tau Lap^2) v = (I - tau Lap) u is, with
-// A = -Lap (SPD), equivalent to the SPD system
-//   K v = (A^{-1} + tau eps^2 A + tau diag(q)) v = A^{-1} u + tau u,  q = u^2.
-// In sine coordinates vh = S v S: K_hat = diag(d) + tau S diag(q) S with
-// d = 1/mu + tau eps^2 mu, mu = -(lam_p + lam_q); rhs b_hat = (1/mu + tau) u_hat.
-// Preconditioner: diag(d + tau c), c = (min q + max q)/2.  Each CG iteration
-// applies K_hat with one inverse and one forward 2D sine transform.
-// CG vectors live in the per-instance scratch in "owned" order
-// (index slot * NT + thread), which is coalesced for every thread.
+// ------------------------------------------------------- spectral CG
+constexpr int CG_CHUNK = 8;
+// Both the coarse scheme (2.4) and the Newton steps of the implicit fine
+// schemes need solves with operators of the form
+//   I + tau eps^2 Lap^2 - tau Lap diag(q)      (q >= 0, or q = 3Y^2 - 1),
+// which, multiplied by A^{-1} with A = -Lap (SPD), become the SPD operator
+//   K = A^{-1} + tau eps^2 A + tau diag(q).
+// In sine coordinates xh = S x S:  K_hat = diag(d) + tau S diag(q) S with
+// d = 1/mu + tau eps^2 mu, mu = -(lam_p + lam_q).  CG from x = 0 with the
+// diagonal preconditioner diag(d + tau c), c = (min q + max q)/2; one
+// operator application = one inverse and one forward 2D sine transform.
+// Vectors live in the work item's scratch in owned order (slot * NT +
+// thread: coalesced for every thread).  b: owned spectral right-hand side.
+// Returns the iteration count, or -1 when the cap is hit or the residual
+// is not finite.  The result is left in cx.
 template <int N, int NW>
-__device__ void approx2_solve(double* X, double* red, const double* T, const SineWalk& sw,
-                              const Lane<N, NW>& L, const InstDev& P, int& status) {
+__device__ int spectral_cg(double* X, double* red, const double* T, const SineWalk& sw,
+                           const Lane<N, NW>& L, const OVec& cx, const OVec& cr, const OVec& cp,
+                           const OVec& cq, const OVec& cm, const OVec& cd, double tau,
+                           double cshift, double rtol, int maxit,
+                           const double (&b)[Geo<N, NW>::OWN]) {
   using G = Geo<N, NW>;
-  const int t = threadIdx.x;
-  const int64_t NN = (int64_t)N * N;
-  double* cx = P.cg;            // solution (spectral)
-  double* cr = P.cg + NN;       // residual
-  double* cp = P.cg + 2 * NN;   // direction
-  double* cq = P.cg + 3 * NN;   // q = u^2 (state, owned)
-  const double* cd = P.cg + 4 * NN;   // d
-  const double* cb = P.cg + 5 * NN;   // 1/mu + tau
-  double* cm = P.cg + 6 * NN;   // 1 / (d + tau c)
-  const double tau = P.dT / P.m_coarse;
+  const int vo = threadIdx.x * 8;
   double y[G::OWN];
-  for (int sub = 0; sub < P.m_coarse; ++sub) {
-    // q = u^2 at owned points, shift c
-    double mn = 1e300, mx = -1e300;
+  double acc[2] = {0.0, 0.0};
+  double dv[G::OWN];
 #pragma unroll
-    for (int s = 0; s < G::OWN; ++s) {
-      const double u = X[own_off<N, NW>(L, s)];
-      const double q = P.f_zero ? 0.0 : u * u;
-      cq[s * G::NT + t] = q;
-      mn = fmin(mn, q);
-      mx = fmax(mx, q);
-    }
-    block_minmax<NW>(mn, mx, red);
-    const double cshift = 0.5 * (mn + mx);
-    // u_hat (2 stages), b_hat, initial CG state x = 0, r = b, p = z = M^{-1} r
+  for (int s = 0; s < G::OWN; ++s) dv[s] = cd.ld(s * G::NT, vo);
+#pragma unroll
+  for (int s = 0; s < G::OWN; ++s) {
+    const int o = s * G::NT;
+    const double mi = 1.0 / (dv[s] + tau * cshift);
+    cm.st(o, vo, mi);
+    cx.st(o, vo, 0.0);
+    cr.st(o, vo, b[s]);
+    const double z = b[s] * mi;
+    cp.st(o, vo, z);
+    y[s] = z;
+    acc[0] += b[s] * z;
+    acc[1] += b[s] * b[s];
+  }
+  block_sum<NW, 2>(acc, red);
+  double rz = acc[0];
+  const double bb = acc[1];
+  if (!(bb > 0.0)) return 0;
+  const double stop2 = rtol * rtol * bb;
+  __syncthreads();
+  store_owned<N, NW>(X, L, y);  // X = p (spectral, owned orientation)
+  __syncthreads();
+  for (int it = 1; it <= maxit; ++it) {
+    // K p = d p + tau S (q . S p S) S: two stages to the state, the pointwise
+    // q at the owned state points, two stages back.
     stage<N, NW>(X, T, sw, L, nullptr);
     stage_regs<N, NW>(X, T, sw, L, y);
-    double acc[3] = {0.0, 0.0, 0.0};  // r.z, b.b
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) y[s] *= cq.ld(s * G::NT, vo);
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);
+    __syncthreads();
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);
+    double a1[1] = {0.0};
 #pragma unroll
     for (int s = 0; s < G::OWN; ++s) {
-      const int64_t o = (int64_t)s * G::NT + t;
-      const double d = cd[o];
-      // f == 0 (test hook) removes the tau u term of the right-hand side
-      const double b = (P.f_zero ? (cb[o] - tau) : cb[o]) * y[s];
-      const double mi = 1.0 / (d + tau * cshift);
-      cm[o] = mi;
-      cx[o] = 0.0;
-      cr[o] = b;
-      const double z = b * mi;
-      cp[o] = z;
-      y[s] = z;  // p, written to X below
-      acc[0] += b * z;
-      acc[1] += b * b;
+      const int o = s * G::NT;
+      const double p = cp.ld(o, vo);
+      const double kp = cd.ld(o, vo) * p + tau * y[s];
+      y[s] = kp;
+      a1[0] += p * kp;
     }
-    block_sum<NW, 3>(acc, red);
-    double rz = acc[0];
-    const double bb = acc[1];
-    const double stop2 = P.krylov_rtol * P.krylov_rtol * bb;
-    int it = 0;
-    bool done = !(bb > 0.0);
-    __syncthreads();
-    store_owned<N, NW>(X, L, y);  // X = p (spectral, owned orientation)
-    __syncthreads();
-    while (!done) {
-      // Kp = d p + tau S (q . S p S) S
-      stage<N, NW>(X, T, sw, L, nullptr);
-      {
-        // second stage with the pointwise q at owned (state) points
-        d4 aE[G::CPW], aO[G::CPW];
-        mma_stage<N, NW>(X, T, sw, aE, aO, L);
-        unfold<N, NW>(aE, aO, y);
+    block_sum<NW, 1>(a1, red);
+    const double alpha = rz / a1[0];
+    double a2[2] = {0.0, 0.0};
+    // Chunked: the buffer accesses carry no alias information, so every
+    // load of a chunk is issued before its stores (one memory round trip
+    // per chunk instead of one per slot).
 #pragma unroll
-        for (int s = 0; s < G::OWN; ++s) y[s] *= cq[(int64_t)s * G::NT + t];
-        __syncthreads();
-        store_owned<N, NW>(X, L, y);
-        __syncthreads();
-      }
-      stage<N, NW>(X, T, sw, L, nullptr);
-      stage_regs<N, NW>(X, T, sw, L, y);
-      double a1[1] = {0.0};
+    for (int s0 = 0; s0 < G::OWN; s0 += CG_CHUNK) {
+      double xv[CG_CHUNK], pv[CG_CHUNK], rv[CG_CHUNK], mv[CG_CHUNK];
 #pragma unroll
-      for (int s = 0; s < G::OWN; ++s) {
-        const int64_t o = (int64_t)s * G::NT + t;
-        const double p = cp[o];
-        const double kp = cd[o] * p + tau * y[s];
-        y[s] = kp;
-        a1[0] += p * kp;
+      for (int c = 0; c < CG_CHUNK; ++c) {
+        const int o = (s0 + c) * G::NT;
+        xv[c] = cx.ld(o, vo);
+        pv[c] = cp.ld(o, vo);
+        rv[c] = cr.ld(o, vo);
+        mv[c] = cm.ld(o, vo);
       }
-      block_sum<NW, 1>(a1, red);
-      const double alpha = rz / a1[0];
-      double a2[2] = {0.0, 0.0};
 #pragma unroll
-      for (int s = 0; s < G::OWN; ++s) {
-        const int64_t o = (int64_t)s * G::NT + t;
-        cx[o] += alpha * cp[o];
-        const double r = cr[o] - alpha * y[s];
-        cr[o] = r;
-        a2[0] += r * r;
-        a2[1] += r * (r * cm[o]);
+      for (int c = 0; c < CG_CHUNK; ++c) {
+        xv[c] += alpha * pv[c];
+        rv[c] -= alpha * y[s0 + c];
+        a2[0] += rv[c] * rv[c];
+        a2[1] += rv[c] * (rv[c] * mv[c]);
+        y[s0 + c] = rv[c] * mv[c];   // z = M^{-1} r, kept for the direction update
       }
-      block_sum<NW, 2>(a2, red);
-      ++it;
-      if (a2[0] <= stop2) {
-        done = true;
-        break;
-      }
-      if (it >= P.krylov_max || !(a2[0] == a2[0])) {
-        status |= 1;
-        break;
-      }
-      const double beta = a2[1] / rz;
-      rz = a2[1];
 #pragma unroll
-      for (int s = 0; s < G::OWN; ++s) {
-        const int64_t o = (int64_t)s * G::NT + t;
-        const double p = cr[o] * cm[o] + beta * cp[o];
-        cp[o] = p;
-        y[s] = p;
+      for (int c = 0; c < CG_CHUNK; ++c) {
+        const int o = (s0 + c) * G::NT;
+        cx.st(o, vo, xv[c]);
+        cr.st(o, vo, rv[c]);
       }
-      __syncthreads();
-      store_owned<N, NW>(X, L, y);
-      __syncthreads();
     }
-    // v = S x S  (back to the state) -> X
+    block_sum<NW, 2>(a2, red);
+    if (a2[0] <= stop2) return it;
+    if (!(a2[0] == a2[0])) return -1;
+    const double beta = a2[1] / rz;
+    rz = a2[1];
 #pragma unroll
-    for (int s = 0; s < G::OWN; ++s) y[s] = cx[(int64_t)s * G::NT + t];
+    for (int s0 = 0; s0 < G::OWN; s0 += CG_CHUNK) {
+      double pv[CG_CHUNK];
+#pragma unroll
+      for (int c = 0; c < CG_CHUNK; ++c) pv[c] = cp.ld((s0 + c) * G::NT, vo);
+#pragma unroll
+      for (int c = 0; c < CG_CHUNK; ++c) {
+        y[s0 + c] = y[s0 + c] + beta * pv[c];
+        cp.st((s0 + c) * G::NT, vo, y[s0 + c]);
+      }
+    }
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);
+    __syncthreads();
+  }
+  return -1;
+}
+
+// Work vectors of one work item (owned order, n^2 each) and the instance's
+// spectral tables.
+struct Work {
+  OVec x, r, p, q, m, uh, yh;
+  OVec d_coarse, b_coarse, d_fine, imu;
+};
+__device__ __forceinline__ Work work_vectors(const InstDev& P, int slice) {
+  const int64_t NN = (int64_t)P.n * P.n;
+  double* w = P.work + (int64_t)slice * WORK_VECS * NN;
+  Work W;
+  W.x = OVec(w, NN);
+  W.r = OVec(w + NN, NN);
+  W.p = OVec(w + 2 * NN, NN);
+  W.q = OVec(w + 3 * NN, NN);
+  W.m = OVec(w + 4 * NN, NN);
+  W.uh = OVec(w + 5 * NN, NN);
+  W.yh = OVec(w + 6 * NN, NN);
+  W.d_coarse = OVec(P.tab, NN);
+  W.b_coarse = OVec(P.tab + NN, NN);
+  W.d_fine = OVec(P.tab + 2 * NN, NN);
+  W.imu = OVec(P.tab + 3 * NN, NN);
+  return W;
+}
+
+// q at the owned state points (state values in y), stored to cq; returns the
+// preconditioner shift (min q + max q)/2.
+template <int N, int NW>
+__device__ __forceinline__ double set_q(const OVec& cq, double* red,
+                                        const double (&y)[Geo<N, NW>::OWN], double a3, double a0) {
+  using G = Geo<N, NW>;
+  const int vo = threadIdx.x * 8;
+  double mn = 1e300, mx = -1e300;
+#pragma unroll
+  for (int s = 0; s < G::OWN; ++s) {
+    const double q = a3 * y[s] * y[s] + a0;
+    cq.st(s * G::NT, vo, q);
+    mn = fmin(mn, q);
+    mx = fmax(mx, q);
+  }
+  block_minmax<NW>(mn, mx, red);
+  return 0.5 * (mn + mx);
+}
+
+// Scheme (2.4): (I - tau Lap diag(u^2) + eps^2 tau Lap^2) v = (I - tau Lap) u,
+// i.e. K v = A^{-1} u + tau u with q = u^2 (f == 0: q = 0 and K v = A^{-1} u).
+// The state u is in X (state orientation) on entry; v is left there.
+template <int N, int NW>
+__device__ void approx2_solve(double* X, double* red, const double* T, const SineWalk& sw,
+                              const Lane<N, NW>& L, const InstDev& P, const Work& W,
+                              int& status) {
+  using G = Geo<N, NW>;
+  const int vo = threadIdx.x * 8;
+  const double tau = P.dT / P.m_coarse;
+  double y[G::OWN], b[G::OWN];
+  for (int sub = 0; sub < P.m_coarse; ++sub) {
+    load_owned<N, NW>(X, L, y);
+    const double cshift = set_q<N, NW>(W.q, red, y, P.f_zero ? 0.0 : 1.0, 0.0);
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);   // u_hat
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      const double cb = W.b_coarse.ld(s * G::NT, vo);
+      b[s] = (P.f_zero ? (cb - tau) : cb) * y[s];
+    }
+    const int its = spectral_cg<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, W.d_coarse, tau,
+                                       cshift, P.krylov_rtol, P.krylov_max, b);
+    if (its < 0) status |= 1;
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) y[s] = W.x.ld(s * G::NT, vo);
     __syncthreads();
     store_owned<N, NW>(X, L, y);
     __syncthreads();
@@ -521,17 +605,139 @@ __device__ void approx2_solve(double* X, double* red, const double* T, const Sin
   }
 }
 
+// ------------------------------------------------ implicit fine step
+// One step of scheme (2.3) (nl_variant 0) or of backward Euler (1) from the
+// state u to the root Y of H, by Newton's method from Y_0 = u, stopped when
+// ||Y_{m+1} - Y_m||_h <= newton_tol (returning Y_{m+1}).  With A = -Lap,
+//   (2.3): A^{-1} H(Y) = A^{-1}(Y - u) + tau eps^2 A Y + tau (Y^3 - u),
+//   BE   : A^{-1} H(Y) = A^{-1}(Y - u) + tau eps^2 A Y + tau (Y^3 - Y),
+// and the Newton matrix A^{-1} H'(Y) = A^{-1} + tau eps^2 A + tau diag(q),
+// q = 3Y^2 (2.3) or 3Y^2 - 1 (BE), is SPD (BE: for tau < 4 eps^2).  In sine
+// coordinates A^{-1} H = d Yh + tau S(Y^3)S - (1/mu + tau) uh (2.3), or
+// d Yh + tau S(Y^3)S - tau Yh - uh/mu (BE), with d = 1/mu + tau eps^2 mu.
+// The state is carried in sine coordinates (Yh, uh in the work vectors).
+// Returns false if Newton or CG hit a cap.
+template <int N, int NW>
+__device__ bool newton_step(double* X, double* red, const double* T, const SineWalk& sw,
+                            const Lane<N, NW>& L, const InstDev& P, const Work& W) {
+  using G = Geo<N, NW>;
+  const int vo = threadIdx.x * 8;
+  const double tau = P.dt;
+  const bool be = P.nl_variant == 1;
+  double y[G::OWN], b[G::OWN];
+  bool ok = true;
+  for (int it = 0; it < P.newton_max; ++it) {
+    // Y at the owned state points: two stages from Yh
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) y[s] = W.yh.ld(s * G::NT, vo);
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);
+    __syncthreads();
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);
+    const double cshift = set_q<N, NW>(W.q, red, y, P.f_zero ? 0.0 : 3.0,
+                                       (be && !P.f_zero) ? -1.0 : 0.0);
+    // S (Y^3) S
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) y[s] = P.f_zero ? 0.0 : y[s] * y[s] * y[s];
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);
+    __syncthreads();
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      const int o = s * G::NT;
+      const double yh = W.yh.ld(o, vo), uh = W.uh.ld(o, vo);
+      const double d = W.d_fine.ld(o, vo), im = W.imu.ld(o, vo);
+      double g;
+      if (P.f_zero) g = d * yh - im * uh;
+      else if (be) g = d * yh + tau * y[s] - tau * yh - im * uh;
+      else g = d * yh + tau * y[s] - (im + tau) * uh;
+      b[s] = -g;
+    }
+    const int its = spectral_cg<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, W.d_fine, tau,
+                                       cshift, P.nl_krylov_rtol, P.krylov_max, b);
+    if (its < 0) ok = false;
+    double a[1] = {0.0};
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      const int o = s * G::NT;
+      const double dx = W.x.ld(o, vo);
+      W.yh.st(o, vo, W.yh.ld(o, vo) + dx);
+      a[0] += dx * dx;
+    }
+    block_sum<NW, 1>(a, red);
+    const double step = sqrt(P.h * P.h * a[0]);  // ||S dYh S||_h = h ||dYh||_F
+    if (step <= P.newton_tol) return ok;
+    if (!(step == step)) return false;
+  }
+  return false;
+}
+
+// Implicit fine sweep: one workgroup per work item, J Newton-solved steps.
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_newton_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                 const double* __restrict__ Tg, const double* __restrict__ U_in,
+                 double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                 const int32_t* __restrict__ active, int k_min, int in_iter) {
+  using G = Geo<N, NW>;
+  extern __shared__ double smem[];
+  double* X = smem + G::XOFF;
+  double* T = smem + G::XSZ;
+  double* red = T + G::P2;
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if (it.slice < k_min || (active && !active[it.inst])) return;
+  const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
+  Lane<N, NW> L;
+  const SineWalk sw = sine_walk<N, NW>(L);
+  const Work W = work_vectors(P, it.slice);
+  const int vo = threadIdx.x * 8;
+  load_sine_table<N, NW>(T, Tg);
+  zero_state<N, NW>(smem);
+  __syncthreads();
+  load_state<N, NW>(X, U_in + off_in);
+  __syncthreads();
+  double y[G::OWN];
+  stage<N, NW>(X, T, sw, L, nullptr);
+  stage_regs<N, NW>(X, T, sw, L, y);   // u_hat
+#pragma unroll
+  for (int s = 0; s < G::OWN; ++s) {
+    W.uh.st(s * G::NT, vo, y[s]);
+    W.yh.st(s * G::NT, vo, y[s]);
+  }
+  bool ok = true;
+  for (int m = 0; m < P.j_fine; ++m) {
+    ok = newton_step<N, NW>(X, red, T, sw, L, P, W) && ok;
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) W.uh.st(s * G::NT, vo, W.yh.ld(s * G::NT, vo));
+  }
+#pragma unroll
+  for (int s = 0; s < G::OWN; ++s) y[s] = W.uh.ld(s * G::NT, vo);
+  __syncthreads();
+  store_owned<N, NW>(X, L, y);
+  __syncthreads();
+  stage<N, NW>(X, T, sw, L, nullptr);
+  stage<N, NW>(X, T, sw, L, nullptr);
+  store_state<N, NW>(X, F_out + off);
+  if (!ok && threadIdx.x == 0) atomicOr(P.status, 1);
+}
+
 // One coarse propagation of the state in X (state orientation), result in X.
 template <int N, int NW>
 __device__ void coarse_apply(double* X, double* red, const double* T, const SineWalk& sw,
-                             const Lane<N, NW>& L, const InstDev& P, int& status) {
+                             const Lane<N, NW>& L, const InstDev& P, const Work& W, int& status) {
   if (P.coarse_kind == 1) {  // stabilised step with tau = dT/m
     double v[Geo<N, NW>::OWN];
     const double tau = P.dT / P.m_coarse;
     linear_steps<N, NW>(X, T, sw, L, v, P.m_coarse, tau / (P.h * P.h), P.s_fine, P.f_zero,
                         P.rsig_stab);
   } else {
-    approx2_solve<N, NW>(X, red, T, sw, L, P, status);
+    approx2_solve<N, NW>(X, red, T, sw, L, P, W, status);
   }
 }
 
@@ -565,13 +771,15 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     const int64_t off = P.off_slices + (int64_t)it.slice * NN;
     load_state<N, NW>(X, U_in + off);
     __syncthreads();
-    coarse_apply<N, NW>(X, red, T, sw, L, P, status);
+    coarse_apply<N, NW>(X, red, T, sw, L, P, work_vectors(P, it.slice), status);
     store_state<N, NW>(X, G_out + off);
+    if (status && threadIdx.x == 0) atomicOr(P.status, status);
     return;
   }
   const int ii = insts[blockIdx.x];
   if (active && !active[ii]) return;
   const InstDev P = inst[ii];
+  const Work W = work_vectors(P, 0);
   load_sine_table<N, NW>(T, Tg);
   zero_state<N, NW>(smem);
   __syncthreads();
@@ -583,7 +791,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     load_state<N, NW>(X, Ui);
     __syncthreads();
     for (int n = 0; n < Ns; ++n) {
-      coarse_apply<N, NW>(X, red, T, sw, L, P, status);
+      coarse_apply<N, NW>(X, red, T, sw, L, P, W, status);
       for (int idx = threadIdx.x; idx < NN; idx += G::NT) {
         const double gv = X[(idx / N) * G::LDX + idx % N];
         Ui[(n + 1) * NN + idx] = gv;
@@ -591,7 +799,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) status_out[ii] = status;
+    if (threadIdx.x == 0) status_out[ii] = status | *P.status;
     return;
   }
   // mode 2
@@ -615,7 +823,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     __syncthreads();
   }
   for (int n = k + 1; n < Ns; ++n) {
-    coarse_apply<N, NW>(X, red, T, sw, L, P, status);
+    coarse_apply<N, NW>(X, red, T, sw, L, P, W, status);
     double acc[1] = {0.0};
     for (int idx = threadIdx.x; idx < NN; idx += G::NT) {
       const int xo = (idx / N) * G::LDX + idx % N;
@@ -635,12 +843,13 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     const double dlt = sqrt(P.h * P.h * dmax);
     delta[ii] = dlt;
     if (!(dlt == dlt) || dlt > 1e300) status |= 2;
-    status_out[ii] = status;
+    status_out[ii] = status | *P.status;
   }
 }
 
-// CG tables in owned order: d = 1/mu + tau eps^2 mu and b-scale = 1/mu + tau,
-// mu = -(lam_row + lam_col), tau = dT/m (2D).
+// Per-instance spectral tables in owned order (2D): d = 1/mu + tau eps^2 mu and
+// 1/mu + tau for the coarse tau = dT/m; d for the fine tau = dt; 1/mu.
+// mu = -(lam_row + lam_col).
 template <int N, int NW>
 __global__ void __launch_bounds__(NW * 64)
 k_cg_tables_2d(const int32_t* __restrict__ insts, const InstDev* __restrict__ inst,
@@ -649,13 +858,17 @@ k_cg_tables_2d(const int32_t* __restrict__ insts, const InstDev* __restrict__ in
   const InstDev P = inst[insts[blockIdx.x]];
   Lane<N, NW> L;
   const int t = threadIdx.x;
-  const double tau = P.dT / P.m_coarse;
+  const double tc = P.dT / P.m_coarse, tf = P.dt;
+  const int64_t NN = (int64_t)N * N;
   for (int s = 0; s < G::OWN; ++s) {
     int row, col;
     own_rc<N, NW>(L, s, row, col);
     const double mu = -(lam[row] + lam[col]);
-    P.cg[4 * (int64_t)N * N + (int64_t)s * G::NT + t] = 1.0 / mu + tau * P.eps * P.eps * mu;
-    P.cg[5 * (int64_t)N * N + (int64_t)s * G::NT + t] = 1.0 / mu + tau;
+    const int64_t o = (int64_t)s * G::NT + t;
+    P.tab[o] = 1.0 / mu + tc * P.eps * P.eps * mu;           // d, coarse tau
+    P.tab[NN + o] = 1.0 / mu + tc;                           // b-scale, coarse tau
+    P.tab[2 * NN + o] = 1.0 / mu + tf * P.eps * P.eps * mu;  // d, fine tau
+    P.tab[3 * NN + o] = 1.0 / mu;                            // 1/mu
   }
 }
 
@@ -935,6 +1148,33 @@ hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstD
     case 32: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
     case 64: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
     case 128: return fine2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int NW>
+static hipError_t newton2d(const WorkItem* items, int n_items, const InstDev* inst,
+                           const double* Tg, const double* U_in, double* F_out,
+                           const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                           hipStream_t s) {
+  const size_t lds = ((size_t)Geo<N, NW>::XSZ + Geo<N, NW>::P2 + 4 * NW) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_newton_2d<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fine_newton_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
+                     Tg, U_in, F_out, mask, active, k_min, in_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                                 const double* Tg, const double* U_in, double* F_out,
+                                 const uint8_t* mask, const int32_t* active, int k_min,
+                                 int in_iter, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (n) {
+    case 32: return newton2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 64: return newton2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 128: return newton2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
     default: return hipErrorInvalidValue;
   }
 }

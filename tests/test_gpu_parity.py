@@ -222,3 +222,55 @@ def test_full_small_1d_parareal_to_tolerance():
         err = gu.rel(U[j], ref["final"][j])
         print(f"T_{j}: gpu-vs-oracle {err:.2e}  oracle two-route floor {floor:.2e}", flush=True)
         assert err <= max(TOL, 2.0 * floor), (j, err, floor)
+
+
+@pytest.mark.parametrize("n,variant", [(32, "eyre"), (64, "eyre"), (128, "eyre"), (64, "be")])
+def test_nonlinear_fine_matches_oracle(n, variant):
+    # implicit fine step (scheme (2.3) or backward Euler) by Newton + spectral CG
+    from paper_2304_14074_amd import chlib
+    J = 4 if n == 128 else 6
+    p = workloads.Problem(dim=2, n=n, eps=0.015, T=2 * J * 1e-5, n_slices=2, j_fine=J,
+                          fine_kind="nonlinear", nl_variant=variant)
+    ctx = chlib.Context([p])
+    rng = np.random.default_rng(n)
+    X = np.stack([0.25 + 0.05 * rng.standard_normal((n, n)), 0.9 * rng.uniform(-1, 1, (n, n))])
+    print(f"nonlinear fine n={n} {variant}", flush=True)
+    out = gu.fine(ctx, [X])[0]
+    for s in range(2):
+        ref = propagators.fine(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+def test_nonlinear_f_zero_is_linear_biharmonic_solve():
+    from paper_2304_14074_amd import chlib
+    n, J, tau, eps = 64, 3, 1e-4, 0.03
+    p = workloads.Problem(dim=2, n=n, eps=eps, T=J * tau, n_slices=1, j_fine=J,
+                          fine_kind="nonlinear", f_zero=True)
+    ctx = chlib.Context([p])
+    x = np.arange(1, n + 1) / (n + 1)
+    u = np.outer(np.sin(2 * np.pi * x), np.sin(3 * np.pi * x))
+    lam = lambda k: 2 * (n + 1) ** 2 * (np.cos(k * np.pi / (n + 1)) - 1)
+    L = lam(2) + lam(3)
+    out = gu.fine(ctx, [u[None]])[0][0]
+    assert gu.rel(out, (1.0 / (1 + tau * eps ** 2 * L ** 2)) ** J * u) < 1e-12
+
+
+def test_nonlinear_parareal_iterates_match_oracle():
+    # NPA-I: implicit fine step, coarse scheme (2.4)
+    from paper_2304_14074_amd import chlib
+    N, J, n = 3, 4, 32
+    p = workloads.Problem(dim=2, n=n, eps=0.03, T=N * J * 5e-5, n_slices=N, j_fine=J,
+                          fine_kind="nonlinear")
+    u0 = workloads.u0_gauss(n, 2, 0.25, 0.05, 3)
+    ctx = chlib.Context([p])
+    st = ctx.new_state()
+    st["U"][: n * n] = torch.from_numpy(u0.reshape(-1)).cuda()
+    ref = _oracle_run(p, u0, N)
+    ctx.ch_parareal_iterate(st, 0.0)
+    for k in range(1, N + 1):
+        ctx.ch_parareal_iterate(st, 0.0)
+        torch.cuda.synchronize()
+        U = gu.unpack_iter(ctx, st["U"])[0]
+        for j in range(N + 1):
+            assert gu.rel(U[j], ref["U"][k][j]) < TOL, (k, j)
+    assert int(st["status"][0].item()) == 0
