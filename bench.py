@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance run")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 fine sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -117,6 +118,34 @@ def main():
     extra = {"fine_sweep_ms": fine_avg, "correction_ms": sum(corr_ms) / len(corr_ms),
              "fine_only_point_steps_per_s": point_steps / (fine_avg / 1e3),
              "fine_kernel_flops": flops}
+    if not args.no_split:
+        # the same fine sweep with split-BF16 transforms inside FP64 defect
+        # correction; error against the FP64 sweep of the same inputs
+        import copy
+        ps = copy.copy(prob)
+        ps.precision = "split_bf16"
+        cs = chlib.Context([ps])
+        Fs = torch.empty_like(st["F"])
+        cs.ch_fine_propagate(U_in, Fs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            cs.ch_fine_propagate(U_in, Fs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sms = e0.elapsed_time(e1) / args.steps
+        ctx.ch_fine_propagate(U_in, st["F"])
+        torch.cuda.synchronize()
+        a = Fs.view(N, P)
+        b = st["F"].view(N, P)
+        rel = (torch.linalg.norm(a - b, dim=1) / torch.linalg.norm(b, dim=1)).max().item()
+        # executed BF16 flops: 2 solves x 4 stages x 3 products x 2 (n/2)^2 n x 2 per point
+        bflops = point_steps * 2 * 4 * 3 * 2 * (n // 2) ** 2 * n * 2 / (n * n)
+        extra.update({"split_bf16_fine_sweep_ms": sms,
+                      "split_bf16_point_steps_per_s": point_steps / (sms / 1e3),
+                      "split_bf16_max_slice_rel_err_vs_fp64": rel,
+                      "split_bf16_mfma_tflops": bflops / (sms / 1e3) / 1e12})
     if not args.no_ttt:
         # Parareal from scratch to an update norm below 1e-8, plain coarse G
         st2 = ctx.new_state()

@@ -28,8 +28,8 @@ struct Block {
   size_t off = 0, bytes = 0;
 };
 
-struct ClassPlan {      // all instances sharing (dim, n, fine kind)
-  int dim = 2, n = 0, fine_kind = 0;
+struct ClassPlan {      // all instances sharing (dim, n, fine kind, precision)
+  int dim = 2, n = 0, fine_kind = 0, precision = 0;
   std::vector<WorkItem> items;   // every slice of every instance in the class
   std::vector<int32_t> insts;    // instance indices
   Block items_blk, insts_blk;
@@ -138,8 +138,10 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       bad = fail(c, CH_ERR_ARG, "instance %d: Newton parameters", i);
     else if (p.coarse_kind == CH_COARSE_NEURAL)
       bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: neural coarse propagator not built", i);
-    else if (p.precision == CH_PREC_SPLIT_BF16)
-      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: split-bf16 not built", i);
+    else if (p.precision == CH_PREC_SPLIT_BF16 &&
+             (p.dim != 2 || p.fine_kind != CH_FINE_LINEAR || (p.n != 64 && p.n != 128)))
+      bad = fail(c, CH_ERR_UNSUPPORTED,
+                 "instance %d: split-bf16 covers the 2D linear step with n = 64, 128", i);
     else if (p.dim == 2 && !supported_2d(p.n))
       bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 2D n = %d (kernels cover 32, 64, 128)", i, p.n);
     else if (p.dim == 1 && (p.n > 128 || p.n % 2))
@@ -180,15 +182,16 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   c->slice_total = so;
   c->iter_total = io;
   // classes
-  std::map<std::tuple<int, int, int>, int> cls;
+  std::map<std::tuple<int, int, int, int>, int> cls;
   for (int i = 0; i < n_inst; ++i) {
-    auto key = std::make_tuple(probs[i].dim, probs[i].n, probs[i].fine_kind);
+    auto key = std::make_tuple(probs[i].dim, probs[i].n, probs[i].fine_kind, probs[i].precision);
     if (!cls.count(key)) {
       cls[key] = (int)c->classes.size();
       ClassPlan cp;
       cp.dim = probs[i].dim;
       cp.n = probs[i].n;
       cp.fine_kind = probs[i].fine_kind;
+      cp.precision = probs[i].precision;
       c->classes.push_back(cp);
     }
     ClassPlan& cp = c->classes[cls[key]];
@@ -342,6 +345,9 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
     if (cp.dim == 2 && cp.fine_kind == CH_FINE_NONLINEAR) {
       e = chk::launch_fine_newton_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                                      mask, active, k_min, in_iter, s);
+    } else if (cp.dim == 2 && cp.precision == CH_PREC_SPLIT_BF16) {
+      e = chk::launch_fine_split_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
+                                    mask, active, k_min, in_iter, s);
     } else if (cp.dim == 2) {
       e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                               mask, active, k_min, in_iter, s);

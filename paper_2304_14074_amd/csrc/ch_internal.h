@@ -40,6 +40,10 @@ hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, cons
                                  const double* Tsin, const double* U_in, double* F_out,
                                  const uint8_t* mask, const int32_t* active, int k_min,
                                  int in_iter, hipStream_t s);
+hipError_t launch_fine_split_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                                const double* Tsin, const double* U_in, double* F_out,
+                                const uint8_t* mask, const int32_t* active, int k_min,
+                                int in_iter, hipStream_t s);
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* S, const double* rsig1, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,

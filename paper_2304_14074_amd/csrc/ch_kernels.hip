@@ -872,6 +872,315 @@ k_cg_tables_2d(const int32_t* __restrict__ insts, const InstDev* __restrict__ in
   }
 }
 
+// ------------------------------------------- split-BF16 linear fine step
+// Reduced-precision variant of the linear step: the sine transforms run on
+// the BF16 matrix cores as three products S_hi X_hi + S_hi X_lo + S_lo X_hi
+// (hi = bf16(x), lo = bf16(x - hi), both round-to-nearest-even; lo*lo
+// dropped) accumulated in FP32, inside an FP64 defect correction:
+//   u1 = u + P^{-1}_lp d,        d = tau Lap (f(u) - eps^2 Lap u)       (= rhs - P u)
+//   u2 = u1 + P^{-1}_lp r,       r = (u - u1) + tau Lap (f(u) - s u - eps^2 Lap u1 + s u1)
+// with P = I + tau eps^2 Lap^2 - s tau Lap.  The FP64 state lives in
+// registers; the defect and residual stencils use an FP64 LDS buffer that
+// aliases the BF16 transform buffer.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int N, int NW>
+struct GeoB {
+  static constexpr int H = N / 2, TR = H / 16, TC = N / 16, WPR = NW / TR, CPW = TC / WPR;
+  static constexpr int KS = H / 32;           // k-steps of 32
+  static constexpr int RS = 2 * N + 8;        // split-buffer row stride (bf16): Eh|El|Oh|Ol|pad
+  static constexpr int NT = NW * 64, OWN = 8 * CPW;
+  static constexpr int LDX = N + 3, XSZ = (N + 2) * LDX, XOFF = LDX + 1;  // FP64 stencil buffer
+  static_assert(KS >= 1, "bf16 k-steps need n >= 64");
+  static_assert(NW % TR == 0 && TC % WPR == 0, "wave tiling");
+  static_assert(OWN * NT == N * N, "ownership");
+  static_assert((size_t)N * RS * 2 <= (size_t)XSZ * 8, "split buffer fits in the FP64 buffer");
+};
+
+// BF16 MFMA 16x16x32 lane layout: A[i][k] i = l%16, k = 8(l/16)+e; B[k][j]
+// k = 8(l/16)+e, j = l%16; D[i][j] in element r: i = 4(l/16) + r, j = l%16.
+template <int N, int NW>
+struct LaneB {
+  int g, j, tr, c0;
+  __device__ LaneB() {
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    g = l >> 4;
+    j = l & 15;
+    tr = w / GeoB<N, NW>::WPR;
+    c0 = (w % GeoB<N, NW>::WPR) * GeoB<N, NW>::CPW;
+  }
+  __device__ __forceinline__ int row_a(int r) const { return 16 * tr + 4 * g + r; }
+  __device__ __forceinline__ int col_c(int q) const { return 16 * (c0 + q) + j; }
+};
+// slot (q*4 + r)*2 + half: Y[a][c] (half 0) / Y[N-1-a][c] (half 1); state point (row c, col a|N-1-a)
+template <int N, int NW>
+__device__ __forceinline__ void ownb_rc(const LaneB<N, NW>& L, int slot, int& row, int& col) {
+  const int qr = slot >> 1, half = slot & 1, q = qr >> 2, r = qr & 3;
+  const int a = L.row_a(r);
+  row = L.col_c(q);
+  col = half ? (N - 1 - a) : a;
+}
+
+__device__ __forceinline__ __bf16 bf16_rne(float x) { return (__bf16)x; }
+
+// Write value v of logical position Y[yr][yc] into the split buffer (row yr,
+// even/odd column halves, hi and lo parts).
+template <int N, int NW>
+__device__ __forceinline__ void split_put(__bf16* SB, int yr, int yc, float v) {
+  using G = GeoB<N, NW>;
+  const __bf16 hi = bf16_rne(v);
+  const __bf16 lo = bf16_rne(v - (float)hi);
+  const int base = yr * G::RS + ((yc & 1) ? 2 * G::H : 0) + (yc >> 1);
+  SB[base] = hi;
+  SB[base + G::H] = lo;
+}
+
+// Owned values (state orientation, see ownb_rc) as the input of a transform:
+// the value at state (row c, col a) is the logical Y_0[a][c].
+template <int N, int NW>
+__device__ __forceinline__ void split_store_owned(__bf16* SB, const LaneB<N, NW>& L,
+                                                  const double (&v)[GeoB<N, NW>::OWN]) {
+#pragma unroll
+  for (int s = 0; s < GeoB<N, NW>::OWN; ++s) {
+    int row, col;
+    ownb_rc<N, NW>(L, s, row, col);
+    split_put<N, NW>(SB, col, row, (float)v[s]);
+  }
+}
+
+struct SineB {       // A operands (hi/lo of the folded sine rows), k-steps of 32
+  bf8 eh[2], el[2], oh[2], ol[2];
+};
+template <int N, int NW>
+__device__ __forceinline__ void sine_operands(const double* __restrict__ Tg, const LaneB<N, NW>& L,
+                                              SineB& A) {
+  using G = GeoB<N, NW>;
+  constexpr int P2 = 2 * (N + 1);
+  const int a1 = 16 * L.tr + L.j + 1;
+#pragma unroll
+  for (int ks = 0; ks < G::KS; ++ks)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 32 * ks + 8 * L.g + e;
+      const double se = Tg[(a1 * (2 * k + 1)) % P2];
+      const double so = Tg[(a1 * (2 * k + 2)) % P2];
+      const __bf16 seh = bf16_rne((float)se), soh = bf16_rne((float)so);
+      A.eh[ks][e] = seh;
+      A.el[ks][e] = bf16_rne((float)(se - (double)(float)seh));
+      A.oh[ks][e] = soh;
+      A.ol[ks][e] = bf16_rne((float)(so - (double)(float)soh));
+    }
+}
+
+// One split-BF16 stage: Y = S X (three BF16 products, FP32 accumulation),
+// unfolded into owned FP32 values y[slot] (see ownb_rc for the positions).
+template <int N, int NW>
+__device__ __forceinline__ void split_stage(const __bf16* SB, const SineB& A, const LaneB<N, NW>& L,
+                                            float (&y)[GeoB<N, NW>::OWN]) {
+  using G = GeoB<N, NW>;
+  f4 aE[G::CPW], aO[G::CPW];
+#pragma unroll
+  for (int q = 0; q < G::CPW; ++q) {
+    aE[q] = f4{0.f, 0.f, 0.f, 0.f};
+    aO[q] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int ks = 0; ks < G::KS; ++ks) {
+#pragma unroll
+    for (int q = 0; q < G::CPW; ++q) {
+      const __bf16* row = SB + (16 * (L.c0 + q) + L.j) * G::RS + 32 * ks + 8 * L.g;
+      const bf8 beh = *(const bf8*)(row);
+      const bf8 bel = *(const bf8*)(row + G::H);
+      const bf8 boh = *(const bf8*)(row + 2 * G::H);
+      const bf8 bol = *(const bf8*)(row + 3 * G::H);
+      aE[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.eh[ks], beh, aE[q], 0, 0, 0);
+      aE[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.eh[ks], bel, aE[q], 0, 0, 0);
+      aE[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.el[ks], beh, aE[q], 0, 0, 0);
+      aO[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.oh[ks], boh, aO[q], 0, 0, 0);
+      aO[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.oh[ks], bol, aO[q], 0, 0, 0);
+      aO[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.ol[ks], boh, aO[q], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < G::CPW; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      y[(q * 4 + r) * 2 + 0] = aE[q][r] + aO[q][r];
+      y[(q * 4 + r) * 2 + 1] = aE[q][r] - aO[q][r];
+    }
+}
+
+// Low-precision solve P^{-1} v of the owned FP64 values v (state orientation),
+// result (FP64 of the FP32 result) back in v.  Four stages; the symbol
+// 1/sigma is applied after the second.
+template <int N, int NW>
+__device__ void split_solve(__bf16* SB, const SineB& A, const LaneB<N, NW>& L,
+                            double (&v)[GeoB<N, NW>::OWN], const double* __restrict__ rsig) {
+  using G = GeoB<N, NW>;
+  float y[G::OWN];
+  __syncthreads();
+  split_store_owned<N, NW>(SB, L, v);
+  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    split_stage<N, NW>(SB, A, L, y);
+    if (st == 1) {
+#pragma unroll
+      for (int s = 0; s < G::OWN; ++s) {
+        const int qr = s >> 1, half = s & 1, q = qr >> 2, r = qr & 3;
+        const int a = L.row_a(r), yr = half ? (N - 1 - a) : a, yc = L.col_c(q);
+        y[s] *= (float)rsig[yr * N + yc];
+      }
+    }
+    if (st < 3) {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < G::OWN; ++s) {
+        const int qr = s >> 1, half = s & 1, q = qr >> 2, r = qr & 3;
+        const int a = L.row_a(r);
+        split_put<N, NW>(SB, half ? (N - 1 - a) : a, L.col_c(q), y[s]);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < G::OWN; ++s) v[s] = (double)y[s];
+}
+
+// FP64 5-point Laplacian (times c) of owned values v, via the LDS stencil
+// buffer X (interior origin, zero halo ring).
+template <int N, int NW>
+__device__ __forceinline__ void lap_owned(double* X, const LaneB<N, NW>& L,
+                                          const double (&v)[GeoB<N, NW>::OWN],
+                                          double (&out)[GeoB<N, NW>::OWN], double c) {
+  using G = GeoB<N, NW>;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < G::OWN; ++s) {
+    int row, col;
+    ownb_rc<N, NW>(L, s, row, col);
+    X[row * G::LDX + col] = v[s];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < G::OWN; ++s) {
+    int row, col;
+    ownb_rc<N, NW>(L, s, row, col);
+    const double* p = X + row * G::LDX + col;
+    out[s] = c * ((p[-G::LDX] + p[G::LDX]) + (p[-1] + p[1]) - 4.0 * p[0]);
+  }
+}
+
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                const double* __restrict__ Tg, const double* __restrict__ U_in,
+                double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                const int32_t* __restrict__ active, int k_min, int in_iter) {
+  using G = GeoB<N, NW>;
+  extern __shared__ double smem[];
+  double* X = smem + G::XOFF;            // FP64 stencil buffer (interior origin)
+  __bf16* SB = (__bf16*)smem;            // BF16 transform buffer (aliases X)
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if (it.slice < k_min || (active && !active[it.inst])) return;
+  const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
+  LaneB<N, NW> L;
+  SineB A;
+  sine_operands<N, NW>(Tg, L, A);
+  const double tau = P.dt, ih2 = 1.0 / (P.h * P.h), e2 = P.eps * P.eps, s = P.s_fine;
+  double u[G::OWN], t1[G::OWN], t2[G::OWN];
+  for (int i = threadIdx.x; i < G::XSZ; i += G::NT) smem[i] = 0.0;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < N * N; idx += G::NT)
+    X[(idx / N) * G::LDX + idx % N] = U_in[off_in + idx];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < G::OWN; ++k) {
+    int row, col;
+    ownb_rc<N, NW>(L, k, row, col);
+    u[k] = X[row * G::LDX + col];
+  }
+  // u and u1 are parked in the work item's scratch during the two solves so
+  // that only one FP64 vector is held in registers next to the MFMA state.
+  const Work W = work_vectors(P, it.slice);
+  const int vo = threadIdx.x * 8;
+  for (int m = 0; m < P.j_fine; ++m) {
+    // defect d = tau Lap(f(u) - eps^2 Lap u)
+    lap_owned<N, NW>(X, L, u, t1, ih2);
+#pragma unroll
+    for (int k = 0; k < G::OWN; ++k) {
+      t1[k] = (P.f_zero ? 0.0 : u[k] * u[k] * u[k] - u[k]) - e2 * t1[k];
+      W.x.st(k * G::NT, vo, u[k]);
+    }
+    lap_owned<N, NW>(X, L, t1, t2, tau * ih2);
+    // delta1 = P^{-1}_lp d
+    split_solve<N, NW>(SB, A, L, t2, P.rsig_fine);
+    // u1 = u + delta1 (t2); w = f(u) - s u + s u1 (t1)
+#pragma unroll
+    for (int k = 0; k < G::OWN; ++k) u[k] = W.x.ld(k * G::NT, vo);
+#pragma unroll
+    for (int k = 0; k < G::OWN; ++k) {
+      t2[k] = u[k] + t2[k];
+      W.r.st(k * G::NT, vo, t2[k]);
+      t1[k] = (P.f_zero ? 0.0 : u[k] * u[k] * u[k] - u[k]) - s * u[k] + s * t2[k];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < G::XSZ; i += G::NT) smem[i] = 0.0;  // halo after BF16 use
+    // residual r = (u - u1) + tau Lap(w - eps^2 Lap u1)
+    lap_owned<N, NW>(X, L, t2, u, ih2);
+#pragma unroll
+    for (int k = 0; k < G::OWN; ++k) t1[k] -= e2 * u[k];
+    lap_owned<N, NW>(X, L, t1, t2, tau * ih2);
+#pragma unroll
+    for (int k = 0; k < G::OWN; ++k)
+      t2[k] += W.x.ld(k * G::NT, vo) - W.r.ld(k * G::NT, vo);
+    split_solve<N, NW>(SB, A, L, t2, P.rsig_fine);
+#pragma unroll
+    for (int k = 0; k < G::OWN; ++k) u[k] = W.r.ld(k * G::NT, vo) + t2[k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < G::XSZ; i += G::NT) smem[i] = 0.0;  // halo after BF16 use
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < G::OWN; ++k) {
+    int row, col;
+    ownb_rc<N, NW>(L, k, row, col);
+    X[row * G::LDX + col] = u[k];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < N * N; idx += G::NT)
+    F_out[off + idx] = X[(idx / N) * G::LDX + idx % N];
+}
+
+template <int N, int NW>
+static hipError_t split2d(const WorkItem* items, int n_items, const InstDev* inst, const double* Tg,
+                          const double* U_in, double* F_out, const uint8_t* mask,
+                          const int32_t* active, int k_min, int in_iter, hipStream_t s) {
+  const size_t lds = (size_t)GeoB<N, NW>::XSZ * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_split_2d<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fine_split_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
+                     Tg, U_in, F_out, mask, active, k_min, in_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_split_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                                const double* Tg, const double* U_in, double* F_out,
+                                const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                                hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (n) {
+    case 64: return split2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 128: return split2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ------------------------------------------------------------------- 1D
 // One workgroup of n threads per state; S (n x n) staged in LDS.  Thread i
 // owns grid point i (state) and sine index i (spectral).

@@ -274,3 +274,39 @@ def test_nonlinear_parareal_iterates_match_oracle():
         for j in range(N + 1):
             assert gu.rel(U[j], ref["U"][k][j]) < TOL, (k, j)
     assert int(st["status"][0].item()) == 0
+
+
+SPLIT_TOL = 1e-4   # reduced-precision bound on a whole fine propagation
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_split_bf16_fine_within_reduced_precision_bound(n):
+    # BF16x3 transforms inside FP64 defect correction vs the FP64 oracle
+    from paper_2304_14074_amd import chlib
+    J = 200
+    p = workloads.Problem(dim=2, n=n, eps=0.02, T=2 * J * 2e-5, n_slices=2, j_fine=J,
+                          precision="split_bf16")
+    ctx = chlib.Context([p])
+    rng = np.random.default_rng(40 + n)
+    X = np.stack([0.05 * rng.uniform(-1, 1, (n, n)), 0.8 * rng.uniform(-1, 1, (n, n))])
+    out = gu.fine(ctx, [X])[0]
+    for s in range(2):
+        ref = propagators.fine(p, X[s])
+        err = gu.rel(out[s], ref)
+        print(f"split-bf16 n={n} slice {s}: rel L2 vs FP64 oracle {err:.2e}", flush=True)
+        assert err < SPLIT_TOL, err
+
+
+def test_split_bf16_full_slice_128():
+    # one full slice of the 128x128, eps=0.02, J=1563 workload in split precision
+    from paper_2304_14074_amd import chlib
+    p = workloads.linear_2d_128()
+    p.precision = "split_bf16"
+    p.n_slices, p.T = 1, p.dT
+    ctx = chlib.Context([p])
+    u0 = workloads.linear_2d_128_u0(0)
+    out = gu.fine(ctx, [u0[None]])[0][0]
+    ref = propagators.fine(p, u0)
+    err = gu.rel(out, ref)
+    print(f"split-bf16 full slice: rel L2 vs FP64 oracle {err:.2e}", flush=True)
+    assert err < SPLIT_TOL, err
