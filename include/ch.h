@@ -136,6 +136,40 @@ ch_status ch_parareal_correct(ch_ctx* ctx, ch_pr_state* st, double tol, ch_strea
 ch_status ch_energy(ch_ctx* ctx, int32_t inst, const double* u, int32_t count, double* E_out,
                     ch_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Learned coarse propagator (G_nn(u) = u + net(u)): a 4-level convolutional
+ * encoder-decoder with BF16 weights and FP32 accumulation on n x n grids
+ * (n divisible by 8).  Parameter vector: for each layer, W[c_out][c_in][k][k]
+ * then b[c_out]; ch_nn_layer describes the layers.  Activation workspaces
+ * are caller device memory of ch_nn_workspace_bytes(batch, n) bytes.  These
+ * calls need no context.  States u/out/target are float64 (batch, n, n).
+ * ---------------------------------------------------------------------- */
+int64_t ch_nn_param_count(void);
+ch_status ch_nn_layer(int32_t layer, int32_t* c_in, int32_t* c_out, int32_t* k, int32_t* stride,
+                      int32_t* act, int32_t* cat);
+size_t ch_nn_workspace_bytes(int32_t batch, int32_t n);
+/* out = u + net(u) */
+ch_status ch_nn_forward(const uint16_t* w_bf16, const double* u, int32_t batch, int32_t n,
+                        void* ws, double* out, ch_stream stream);
+/* forward, loss = mean((u + net(u) - target)^2) (device float), gradient of
+ * the loss w.r.t. every parameter into grad (float32, overwritten);
+ * batch * n * n <= 2^20 */
+ch_status ch_nn_train_step(const uint16_t* w_bf16, const double* u, const double* target,
+                           int32_t batch, int32_t n, void* ws, float* grad, float* loss,
+                           ch_stream stream);
+/* Adam on the FP32 master weights (bias-corrected, step >= 1), then the BF16
+ * copy rounded to nearest even */
+ch_status ch_nn_adam(float* w_master, uint16_t* w_bf16, float* m, float* v, const float* grad,
+                     int64_t count, float lr, float beta1, float beta2, float eps, int32_t step,
+                     ch_stream stream);
+ch_status ch_nn_to_bf16(const float* w_master, uint16_t* w_bf16, int64_t count, ch_stream stream);
+/* weights used by instances whose coarse kind is CH_COARSE_NEURAL */
+ch_status ch_nn_bind(ch_ctx* ctx, const uint16_t* w_bf16);
+/* switch the coarse propagator of one instance (e.g. the fallback from the
+ * learned to the plain propagator); the context must have been created with
+ * a learned-propagator instance to switch one to it */
+ch_status ch_set_coarse_kind(ch_ctx* ctx, int32_t inst, int32_t kind, ch_stream stream);
+
 const char* ch_status_str(ch_status s);
 const char* ch_last_error(const ch_ctx* ctx);
 

@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libch.so")
-SOURCES = ["ch_kernels.hip", "ch_api.cpp"]
+SOURCES = ["ch_kernels.hip", "ch_nn.hip", "ch_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -23,7 +23,9 @@ PREC = {"fp64": 0, "split_bf16": 1}
 # every symbol include/ch.h declares
 EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
            "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
-           "ch_parareal_correct", "ch_energy", "ch_status_str", "ch_last_error")
+           "ch_parareal_correct", "ch_energy", "ch_status_str", "ch_last_error",
+           "ch_nn_param_count", "ch_nn_layer", "ch_nn_workspace_bytes", "ch_nn_forward",
+           "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind")
 
 
 class ChProblem(ctypes.Structure):
@@ -73,6 +75,21 @@ def load() -> ctypes.CDLL:
     lib.ch_status_str.restype = ctypes.c_char_p
     lib.ch_last_error.argtypes = [vp]
     lib.ch_last_error.restype = ctypes.c_char_p
+    f32, i64 = ctypes.c_float, ctypes.c_int64
+    lib.ch_nn_param_count.argtypes = []
+    lib.ch_nn_param_count.restype = i64
+    lib.ch_nn_layer.argtypes = [i32] + [ctypes.POINTER(i32)] * 6
+    lib.ch_nn_workspace_bytes.argtypes = [i32, i32]
+    lib.ch_nn_workspace_bytes.restype = ctypes.c_size_t
+    lib.ch_nn_forward.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    lib.ch_nn_train_step.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
+    lib.ch_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
+    lib.ch_nn_to_bf16.argtypes = [vp, vp, i64, vp]
+    lib.ch_nn_bind.argtypes = [vp, vp]
+    lib.ch_set_coarse_kind.argtypes = [vp, i32, i32, vp]
+    for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
+                 "ch_nn_bind", "ch_set_coarse_kind"):
+        getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
                  "ch_parareal_correct", "ch_energy"):
@@ -172,6 +189,13 @@ class Context:
     def ch_energy(self, inst, u, count, E_out, stream=None):
         self._check(self.lib.ch_energy(self.h, inst, _ptr(u), count, _ptr(E_out), _stream(stream)))
 
+    def ch_nn_bind(self, w_bf16):
+        self._nn_w = w_bf16          # keep the weights alive while bound
+        self._check(self.lib.ch_nn_bind(self.h, _ptr(w_bf16)))
+
+    def ch_set_coarse_kind(self, inst, kind, stream=None):
+        self._check(self.lib.ch_set_coarse_kind(self.h, inst, COARSE[kind], _stream(stream)))
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.ch_destroy(self.h)
@@ -182,3 +206,59 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------ learned coarse propagator
+def _nn_check(st, what):
+    if st != CH_OK:
+        raise CHError(f"{what}: {load().ch_status_str(st).decode()}")
+
+
+def ch_nn_param_count() -> int:
+    return int(load().ch_nn_param_count())
+
+
+def ch_nn_layers():
+    lib = load()
+    out, l = [], 0
+    while True:
+        v = [ctypes.c_int32() for _ in range(6)]
+        if lib.ch_nn_layer(l, *[ctypes.byref(x) for x in v]) != CH_OK:
+            return out
+        out.append(tuple(x.value for x in v))
+        l += 1
+
+
+class NNWorkspace:
+    """Activation workspace of the surrogate for a given batch and grid."""
+
+    def __init__(self, batch, n, device="cuda"):
+        nbytes = int(load().ch_nn_workspace_bytes(batch, n))
+        if nbytes == 0:
+            raise CHError("bad surrogate workspace shape")
+        self.batch, self.n = batch, n
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.grad = None
+
+
+def ch_nn_forward(w_bf16, u, out, ws: NNWorkspace, stream=None):
+    b, n = u.shape[0], u.shape[-1]
+    _nn_check(load().ch_nn_forward(_ptr(w_bf16), _ptr(u), b, n, _ptr(ws.buf), _ptr(out),
+                                   _stream(stream)), "ch_nn_forward")
+
+
+def ch_nn_train_step(w_bf16, u, target, grad, loss, ws: NNWorkspace, stream=None):
+    b, n = u.shape[0], u.shape[-1]
+    _nn_check(load().ch_nn_train_step(_ptr(w_bf16), _ptr(u), _ptr(target), b, n, _ptr(ws.buf),
+                                      _ptr(grad), _ptr(loss), _stream(stream)), "ch_nn_train_step")
+
+
+def ch_nn_adam(w_master, w_bf16, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _nn_check(load().ch_nn_adam(_ptr(w_master), _ptr(w_bf16), _ptr(m), _ptr(v), _ptr(grad),
+                                w_master.numel(), lr, beta1, beta2, eps, step, _stream(stream)),
+              "ch_nn_adam")
+
+
+def ch_nn_to_bf16(w_master, w_bf16, stream=None):
+    _nn_check(load().ch_nn_to_bf16(_ptr(w_master), _ptr(w_bf16), w_master.numel(), _stream(stream)),
+              "ch_nn_to_bf16")

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <tuple>
 #include <string>
@@ -46,6 +47,11 @@ struct ch_ctx {
   std::vector<ClassPlan> classes;
   Block inst_blk, active_blk, status_blk;
   std::vector<Block> rsig_fine_blk, rsig_stab_blk, tab_blk, work_blk;
+  // learned coarse propagator
+  Block nn_blk, nn_out_blk, nn_part_blk;
+  size_t nn_floats = 0;
+  const uint16_t* nn_w = nullptr;
+  bool nn_planned = false;
   size_t ws_bytes = 0;
   char* ws = nullptr;               // bound workspace
   std::string err;
@@ -136,8 +142,9 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
              (p.nl_variant < CH_NL_EYRE || p.nl_variant > CH_NL_FULL_BE || p.newton_max < 1 ||
               !(p.newton_tol > 0) || !(p.nl_krylov_rtol > 0)))
       bad = fail(c, CH_ERR_ARG, "instance %d: Newton parameters", i);
-    else if (p.coarse_kind == CH_COARSE_NEURAL)
-      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: neural coarse propagator not built", i);
+    else if (p.coarse_kind == CH_COARSE_NEURAL && (p.dim != 2 || p.n % 8 != 0))
+      bad = fail(c, CH_ERR_UNSUPPORTED,
+                 "instance %d: the learned coarse propagator needs 2D with n divisible by 8", i);
     else if (p.precision == CH_PREC_SPLIT_BF16 &&
              (p.dim != 2 || p.fine_kind != CH_FINE_LINEAR || (p.n != 64 && p.n != 128)))
       bad = fail(c, CH_ERR_UNSUPPORTED,
@@ -222,6 +229,25 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     if (probs[i].dim == 2) {
       c->tab_blk[i] = take(sizeof(double) * P * chk::TAB_VECS);
       c->work_blk[i] = take(sizeof(double) * P * chk::WORK_VECS * (size_t)probs[i].n_slices);
+    }
+  }
+  // learned coarse propagator workspace: activations for a batch of all
+  // slices of the largest neural instance, FP64 outputs, norm partials
+  {
+    size_t fl = 0, outd = 0, partd = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      if (probs[i].coarse_kind != CH_COARSE_NEURAL) continue;
+      c->nn_planned = true;
+      const size_t P = (size_t)probs[i].n * probs[i].n;
+      fl = std::max(fl, chk::nn_plan(probs[i].n_slices, probs[i].n).floats);
+      outd = std::max(outd, (size_t)probs[i].n_slices * P);
+      partd = std::max(partd, (size_t)probs[i].n_slices * ((P + 255) / 256));
+    }
+    if (c->nn_planned) {
+      c->nn_floats = fl;
+      c->nn_blk = take(fl * sizeof(float));
+      c->nn_out_blk = take(outd * sizeof(double));
+      c->nn_part_blk = take(partd * sizeof(double));
     }
   }
   c->ws_bytes = off;
@@ -397,6 +423,51 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     ch_status r = hip_check(c, e, "coarse launch");
     if (r != CH_OK) return r;
   }
+  // learned coarse propagator: host-driven sequence of network passes
+  for (int i = 0; i < (int)c->probs.size(); ++i) {
+    const InstDev& d = c->inst[i];
+    if (d.coarse_kind != CH_COARSE_NEURAL) continue;
+    if (!c->nn_w) return fail(c, CH_ERR_STATE, "instance %d: no surrogate weights bound", i);
+    const int n = d.n, N = d.n_slices;
+    const int64_t P = (int64_t)n * n;
+    float* nws = (float*)(c->ws + c->nn_blk.off);
+    double* g = (double*)(c->ws + c->nn_out_blk.off);
+    double* part = (double*)(c->ws + c->nn_part_blk.off);
+    const int nb = (int)((P + 255) / 256);
+    hipError_t e = hipSuccess;
+    if (mode == 0) {
+      const chk::NNPlan pl = chk::nn_plan(N, n);
+      e = chk::nn_forward(c->nn_w, U_in + d.off_slices, N, n, nws, pl, g, s);
+      if (e == hipSuccess) e = chk::masked_copy(G_out + d.off_slices, g, mask, P, N, d.slice_base, s);
+    } else {
+      const chk::NNPlan pl = chk::nn_plan(1, n);
+      const int32_t* act = active + i;
+      double* Ui = st->U + d.off_iter;
+      const double* Fi = st->F + d.off_slices;
+      double* Gi = st->G_old + d.off_slices;
+      if (mode == 1) {
+        for (int sl = 0; sl < N && e == hipSuccess; ++sl) {
+          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s);
+          if (e == hipSuccess) e = chk::pr_correct(Ui + (sl + 1) * P, nullptr, Gi + sl * P, g, P, part, 1, act, s);
+        }
+      } else if (k >= N) {
+        e = chk::pr_delta(part, nb, 0, d.h * d.h, st->delta + i, st->status + i, act, s);
+      } else {
+        // U_{k+1} = F_k + (G(U_k) - G_old_k), G(U_k) == G_old_k
+        e = chk::pr_correct(Ui + (k + 1) * P, Fi + k * P, Gi + k * P, Gi + k * P, P, part, 0, act, s);
+        for (int sl = k + 1; sl < N && e == hipSuccess; ++sl) {
+          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s);
+          if (e == hipSuccess)
+            e = chk::pr_correct(Ui + (sl + 1) * P, Fi + sl * P, Gi + sl * P, g, P,
+                                part + (int64_t)(sl - k) * nb, 0, act, s);
+        }
+        if (e == hipSuccess)
+          e = chk::pr_delta(part, nb, N - k, d.h * d.h, st->delta + i, st->status + i, act, s);
+      }
+    }
+    ch_status r = hip_check(c, e, "learned coarse propagator");
+    if (r != CH_OK) return r;
+  }
   return CH_OK;
 }
 
@@ -458,6 +529,79 @@ ch_status ch_parareal_correct(ch_ctx* c, ch_pr_state* st, double tol, ch_stream 
   if (r != CH_OK) return r;
   if (!st->predicted) return fail(c, CH_ERR_STATE, "the coarse prediction has not been formed");
   return pr_step(c, st, tol, (hipStream_t)stream, 0);
+}
+
+int64_t ch_nn_param_count(void) { return chk::nn_param_count(); }
+
+ch_status ch_nn_layer(int32_t layer, int32_t* c_in, int32_t* c_out, int32_t* k, int32_t* stride,
+                      int32_t* act, int32_t* cat) {
+  if (layer < 0 || layer >= chk::NN_LAYERS) return CH_ERR_ARG;
+  const chk::NNLayer& L = chk::kNNLayers[layer];
+  if (c_in) *c_in = L.c_in;
+  if (c_out) *c_out = L.c_out;
+  if (k) *k = L.k;
+  if (stride) *stride = L.stride;
+  if (act) *act = L.act;
+  if (cat) *cat = L.cat;
+  return CH_OK;
+}
+
+size_t ch_nn_workspace_bytes(int32_t batch, int32_t n) {
+  if (batch < 1 || n < 8 || n % 8) return 0;
+  return chk::nn_plan(batch, n).floats * sizeof(float);
+}
+
+ch_status ch_nn_forward(const uint16_t* w, const double* u, int32_t batch, int32_t n, void* ws,
+                        double* out, ch_stream stream) {
+  if (!w || !u || !ws || !out || batch < 1 || n < 8 || n % 8) return CH_ERR_ARG;
+  const chk::NNPlan pl = chk::nn_plan(batch, n);
+  return chk::nn_forward(w, u, batch, n, (float*)ws, pl, out, (hipStream_t)stream) == hipSuccess
+             ? CH_OK : CH_ERR_HIP;
+}
+
+ch_status ch_nn_train_step(const uint16_t* w, const double* u, const double* target, int32_t batch,
+                           int32_t n, void* ws, float* grad, float* loss, ch_stream stream) {
+  if (!w || !u || !target || !ws || !grad || !loss || batch < 1 || n < 8 || n % 8) return CH_ERR_ARG;
+  if ((int64_t)batch * n * n > 4096 * 256) return CH_ERR_ARG;
+  const chk::NNPlan pl = chk::nn_plan(batch, n);
+  return chk::nn_train_step(w, u, target, batch, n, (float*)ws, pl, grad, loss,
+                            (hipStream_t)stream) == hipSuccess ? CH_OK : CH_ERR_HIP;
+}
+
+ch_status ch_nn_adam(float* w_master, uint16_t* w_bf16, float* m, float* v, const float* grad,
+                     int64_t count, float lr, float beta1, float beta2, float eps, int32_t step,
+                     ch_stream stream) {
+  if (!w_master || !w_bf16 || !m || !v || !grad || count < 1 || step < 1) return CH_ERR_ARG;
+  return chk::nn_adam(w_master, w_bf16, m, v, grad, count, lr, beta1, beta2, eps, step,
+                      (hipStream_t)stream) == hipSuccess ? CH_OK : CH_ERR_HIP;
+}
+
+ch_status ch_nn_to_bf16(const float* w_master, uint16_t* w_bf16, int64_t count, ch_stream stream) {
+  if (!w_master || !w_bf16 || count < 1) return CH_ERR_ARG;
+  return chk::nn_to_bf16(w_master, w_bf16, count, (hipStream_t)stream) == hipSuccess ? CH_OK
+                                                                                      : CH_ERR_HIP;
+}
+
+ch_status ch_nn_bind(ch_ctx* c, const uint16_t* w_bf16) {
+  if (!c) return CH_ERR_ARG;
+  c->nn_w = w_bf16;
+  return CH_OK;
+}
+
+ch_status ch_set_coarse_kind(ch_ctx* c, int32_t inst, int32_t kind, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (inst < 0 || inst >= (int32_t)c->probs.size()) return fail(c, CH_ERR_ARG, "instance index");
+  if (kind < CH_COARSE_APPROX2 || kind > CH_COARSE_NEURAL) return fail(c, CH_ERR_ARG, "kind");
+  if (c->probs[inst].dim != 2 && kind == CH_COARSE_NEURAL)
+    return fail(c, CH_ERR_UNSUPPORTED, "learned coarse propagator needs 2D");
+  if (kind == CH_COARSE_NEURAL && !c->nn_planned)
+    return fail(c, CH_ERR_STATE, "context was created without a learned-propagator workspace");
+  c->inst[inst].coarse_kind = kind;
+  InstDev* dev = (InstDev*)(c->ws + c->inst_blk.off) + inst;
+  return hip_check(c, hipMemcpyAsync(&dev->coarse_kind, &c->inst[inst].coarse_kind, sizeof(int32_t),
+                                     hipMemcpyHostToDevice, (hipStream_t)stream),
+                   "coarse kind update");
 }
 
 ch_status ch_energy(ch_ctx* c, int32_t inst, const double* u, int32_t count, double* E_out,

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <algorithm>
 #include <cstdint>
 
 namespace chk {
@@ -69,5 +70,29 @@ hipError_t launch_energy(int n, int dim, const double* u, int count, double eps,
                          hipStream_t s);
 hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
                               int first, hipStream_t s);
+
+// ---- learned coarse propagator (ch_nn.hip)
+struct NNLayer { int c_in, c_out, k, stride, act, cat; };
+constexpr int NN_LAYERS = 12;
+extern const NNLayer kNNLayers[NN_LAYERS];
+struct NNPlan {   // float offsets inside an NN workspace
+  size_t x0, act[NN_LAYERS], grad[NN_LAYERS], tmp, part, floats;
+};
+NNPlan nn_plan(int batch, int n);
+int64_t nn_param_count();
+int64_t nn_param_offset(int layer);
+hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
+                      const NNPlan& p, double* out, hipStream_t s);
+hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, int batch, int n,
+                         float* ws, const NNPlan& p, float* grad, float* loss, hipStream_t s);
+hipError_t nn_adam(float* wm, uint16_t* wb, float* m, float* v, const float* g, int64_t count,
+                   float lr, float b1, float b2, float eps, int t, hipStream_t s);
+hipError_t nn_to_bf16(const float* wm, uint16_t* wb, int64_t count, hipStream_t s);
+hipError_t pr_correct(double* Un1, const double* Fn, double* Gn, const double* g, int64_t count,
+                      double* part, int predict, const int32_t* active, hipStream_t s);
+hipError_t pr_delta(const double* part, int nb, int nslices, double h2, double* delta,
+                    int32_t* status, const int32_t* active, hipStream_t s);
+hipError_t masked_copy(double* dst, const double* src, const uint8_t* mask, int64_t P, int nslices,
+                       int64_t slice_base, hipStream_t s);
 
 }  // namespace chk

@@ -765,6 +765,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     const WorkItem it = items[blockIdx.x];
     const InstDev P = inst[it.inst];
     if (mask && !mask[P.slice_base + it.slice]) return;
+    if (P.coarse_kind == 2) return;  // learned propagator: separate path
     load_sine_table<N, NW>(T, Tg);
     zero_state<N, NW>(smem);
     __syncthreads();
@@ -779,6 +780,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
   const int ii = insts[blockIdx.x];
   if (active && !active[ii]) return;
   const InstDev P = inst[ii];
+  if (P.coarse_kind == 2) return;  // learned propagator: separate path
   const Work W = work_vectors(P, 0);
   load_sine_table<N, NW>(T, Tg);
   zero_state<N, NW>(smem);

@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "ch.h")
 
 def _declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(ch_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(ch_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
