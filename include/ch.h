@@ -148,7 +148,9 @@ int64_t ch_nn_param_count(void);
 ch_status ch_nn_layer(int32_t layer, int32_t* c_in, int32_t* c_out, int32_t* k, int32_t* stride,
                       int32_t* act, int32_t* cat);
 size_t ch_nn_workspace_bytes(int32_t batch, int32_t n);
-/* out = u + net(u) */
+/* out = clip(u + net(u), -1.5, 1.5) (the clip bounds repeated application on
+ * states far from the training data; ch_nn_train_step uses the unclipped
+ * output) */
 ch_status ch_nn_forward(const uint16_t* w_bf16, const double* u, int32_t batch, int32_t n,
                         void* ws, double* out, ch_stream stream);
 /* forward, loss = mean((u + net(u) - target)^2) (device float), gradient of

@@ -76,8 +76,15 @@ def loss_and_grad(theta: np.ndarray, u: np.ndarray, target: np.ndarray, layers=L
     return float(loss.detach()), th.grad.numpy().copy()
 
 
+OUT_BOUND = 1.5
+
+
 def surrogate_step(theta, u: np.ndarray) -> np.ndarray:
-    """G_nn(u) for one state (n x n), FP64."""
+    """G_nn(u) for one state (n x n), FP64: the network output clipped to
+    [-1.5, 1.5] (the propagator is applied repeatedly in the coarse sweep,
+    possibly far from its training states; training uses the unclipped
+    output)."""
     with torch.no_grad():
         th = torch.as_tensor(np.asarray(theta, dtype=np.float64))
-        return forward(th, torch.tensor(u[None], dtype=torch.float64))[0].numpy()
+        out = forward(th, torch.tensor(u[None], dtype=torch.float64))[0].numpy()
+        return np.clip(out, -OUT_BOUND, OUT_BOUND)

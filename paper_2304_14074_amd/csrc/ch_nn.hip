@@ -247,11 +247,15 @@ __global__ void k_to_f32(const double* __restrict__ u, float* __restrict__ x, in
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < count) x[i] = (float)u[i];
 }
-// out = u + head (FP64)
+// out = clip(u + head, -OUT_BOUND, OUT_BOUND) (FP64).  The clip keeps the
+// propagator bounded on states far from the training data (repeated
+// application inside the coarse sweep); solutions of the equation stay well
+// inside it.  Training uses the unclipped output.
+constexpr double OUT_BOUND = 1.5;
 __global__ void k_residual_out(const double* __restrict__ u, const float* __restrict__ h,
                                double* __restrict__ out, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < count) out[i] = u[i] + (double)h[i];
+  if (i < count) out[i] = fmin(fmax(u[i] + (double)h[i], -OUT_BOUND), OUT_BOUND);
 }
 // MSE: dh = 2 (u + h - target)/count; per-block partial sums of squares
 __global__ void k_mse(const double* __restrict__ u, const float* __restrict__ h,
