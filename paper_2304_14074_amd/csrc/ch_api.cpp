@@ -93,7 +93,7 @@ double lap_eig(long p, long n) {
   return (double)(-4.0L / (h * h) * sn * sn);
 }
 
-bool supported_2d(int n) { return n == 32 || n == 64 || n == 128; }
+bool supported_2d(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
 
 }  // namespace
 
@@ -150,7 +150,9 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       bad = fail(c, CH_ERR_UNSUPPORTED,
                  "instance %d: split-bf16 covers the 2D linear step with n = 64, 128", i);
     else if (p.dim == 2 && !supported_2d(p.n))
-      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 2D n = %d (kernels cover 32, 64, 128)", i, p.n);
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 2D n = %d (kernels cover 32, 64, 128, 256)", i, p.n);
+    else if (p.dim == 2 && p.n == 256 && p.fine_kind == CH_FINE_NONLINEAR)
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: the implicit fine step covers n <= 128", i);
     else if (p.dim == 1 && (p.n > 128 || p.n % 2))
       bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 1D n = %d (even n <= 128)", i, p.n);
     if (bad != CH_OK) {

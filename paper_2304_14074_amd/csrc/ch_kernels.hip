@@ -874,6 +874,359 @@ k_cg_tables_2d(const int32_t* __restrict__ insts, const InstDev* __restrict__ in
   }
 }
 
+// ------------------------------------------------- streamed large grids
+// n = 256: the 512 KB FP64 state does not fit on a CU, so each transform
+// stage streams it between two global buffers of the work item (L2 / MALL
+// resident) and stages its B operand through a double-buffered LDS chunk.
+// A stage computes Y = S X for the folded rows in two column halves (the
+// accumulators of one half fill the register budget) and writes Y^T.
+template <int N, int NW>
+struct GeoS {
+  static constexpr int H = N / 2, TR = H / 16, HALF = N / 2, TCH = HALF / 16;
+  static constexpr int MC = 16;                 // folded k (m) per LDS chunk
+  static constexpr int CR = 2 * MC;             // X rows per chunk
+  static constexpr int LDC = HALF + 8;          // chunk row stride (doubles)
+  static constexpr int CHUNK = CR * LDC;        // doubles per chunk buffer
+  static constexpr int NT = NW * 64, P2 = 2 * (N + 1);
+  static_assert(TR == NW, "one wave per 16 folded rows");
+  static_assert((CR * HALF) % NT == 0, "chunk load tiling");
+};
+
+template <int N, int NW>
+__device__ __attribute__((noinline)) void stream_stage(const double* __restrict__ Xg, double* __restrict__ Out,
+                             const double* __restrict__ w, double* Lc, const double* T) {
+  using G = GeoS<N, NW>;
+  const int t = threadIdx.x, l = t & 63, wv = t >> 6, g = l >> 4, j = l & 15;
+  const int tr = wv;
+  const int a1 = 16 * tr + j + 1;
+  constexpr int PER = G::CR * G::HALF / G::NT;   // doubles per thread per chunk load
+  for (int hc = 0; hc < 2; ++hc) {
+    d4 aE[G::TCH], aO[G::TCH];
+#pragma unroll
+    for (int q = 0; q < G::TCH; ++q) {
+      aE[q] = d4{0.0, 0.0, 0.0, 0.0};
+      aO[q] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    double pf[PER];
+    // chunk c covers X rows [2 MC c, 2 MC c + 2 MC), columns [HALF hc, HALF hc + HALF)
+    auto fetch = [&](int c) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = i * G::NT + t, r = e / G::HALF, col = e % G::HALF;
+        pf[i] = Xg[(int64_t)(2 * G::MC * c + r) * N + G::HALF * hc + col];
+      }
+    };
+    auto put = [&](double* buf) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = i * G::NT + t, r = e / G::HALF, col = e % G::HALF;
+        buf[r * G::LDC + col] = pf[i];
+      }
+    };
+    constexpr int NCH = G::H / G::MC;
+    fetch(0);
+    __syncthreads();   // previous users of the chunk buffers are done
+    put(Lc);
+    __syncthreads();
+    int ie = (a1 * (2 * g + 1)) % G::P2, io = (a1 * (2 * g + 2)) % G::P2;
+    const int step = (8 * a1) % G::P2;
+    for (int c = 0; c < NCH; ++c) {
+      double* cur = Lc + (c & 1) * G::CHUNK;
+      if (c + 1 < NCH) fetch(c + 1);
+#pragma unroll
+      for (int kl = 0; kl < G::MC / 4; ++kl) {
+        const double se = T[ie], so = T[io];
+        ie += step; ie -= (ie >= G::P2) ? G::P2 : 0;
+        io += step; io -= (io >= G::P2) ? G::P2 : 0;
+        const double* pe = cur + (2 * (4 * kl + g)) * G::LDC + j;
+#pragma unroll
+        for (int q = 0; q < G::TCH; ++q) {
+          aE[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(se, pe[16 * q], aE[q], 0, 0, 0);
+          aO[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(so, pe[G::LDC + 16 * q], aO[q], 0, 0, 0);
+        }
+      }
+      if (c + 1 < NCH) put(Lc + ((c + 1) & 1) * G::CHUNK);
+      __syncthreads();
+    }
+    // epilogue: Out[c][a] = Y[a][c] times w[c][a] (w indexed like Out)
+#pragma unroll
+    for (int q = 0; q < G::TCH; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * tr + g + 4 * r, cc = G::HALF * hc + 16 * q + j;
+        double top = aE[q][r] + aO[q][r], bot = aE[q][r] - aO[q][r];
+        if (w) {
+          top *= w[(int64_t)cc * N + a];
+          bot *= w[(int64_t)cc * N + (N - 1 - a)];
+        }
+        Out[(int64_t)cc * N + a] = top;
+        Out[(int64_t)cc * N + (N - 1 - a)] = bot;
+      }
+  }
+  __syncthreads();   // Out complete before anyone reads it
+}
+
+// r = u + c_lap Lap5(f(u) - s u) on global arrays (zero boundary ghosts).
+template <int N, int NW>
+__device__ void stream_rhs(const double* __restrict__ u, double* __restrict__ r, double c_lap,
+                           double s, int f_zero) {
+  for (int idx = threadIdx.x; idx < N * N; idx += NW * 64) {
+    const int iy = idx / N, ix = idx % N;
+    auto wof = [&](double v) { return f_zero ? -s * v : v * v * v - (1.0 + s) * v; };
+    const double c = u[idx];
+    const double wn = iy > 0 ? wof(u[idx - N]) : 0.0, ws = iy < N - 1 ? wof(u[idx + N]) : 0.0;
+    const double ww = ix > 0 ? wof(u[idx - 1]) : 0.0, we = ix < N - 1 ? wof(u[idx + 1]) : 0.0;
+    r[idx] = c + c_lap * ((wn + ws) + (ww + we) - 4.0 * wof(c));
+  }
+  __syncthreads();
+}
+
+// nsteps linear steps of the state in b0 (global); the result ends in b0.
+template <int N, int NW>
+__device__ void stream_linear_steps(double* b0, double* b1, double* Lc, const double* T,
+                                    int nsteps, double c_lap, double s, int f_zero,
+                                    const double* __restrict__ rsig) {
+  for (int m = 0; m < nsteps; ++m) {
+    stream_rhs<N, NW>(b0, b1, c_lap, s, f_zero);
+    stream_stage<N, NW>(b1, b0, nullptr, Lc, T);
+    stream_stage<N, NW>(b0, b1, rsig, Lc, T);
+    stream_stage<N, NW>(b1, b0, nullptr, Lc, T);
+    stream_stage<N, NW>(b0, b1, nullptr, Lc, T);
+    for (int idx = threadIdx.x; idx < N * N; idx += NW * 64) b0[idx] = b1[idx];
+    __syncthreads();
+  }
+}
+
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_linear_stream(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                     const double* __restrict__ Tg, const double* __restrict__ U_in,
+                     double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                     const int32_t* __restrict__ active, int k_min, int in_iter) {
+  using G = GeoS<N, NW>;
+  extern __shared__ double smem[];
+  double* Lc = smem;
+  double* T = smem + 2 * G::CHUNK;
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if (it.slice < k_min || (active && !active[it.inst])) return;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
+  double* b0 = P.work + (int64_t)it.slice * WORK_VECS * NN;
+  double* b1 = b0 + NN;
+  for (int m = threadIdx.x; m < G::P2; m += G::NT) T[m] = Tg[m];
+  for (int idx = threadIdx.x; idx < NN; idx += G::NT) b0[idx] = U_in[off_in + idx];
+  __syncthreads();
+  stream_linear_steps<N, NW>(b0, b1, Lc, T, P.j_fine, P.dt / (P.h * P.h), P.s_fine, P.f_zero,
+                             P.rsig_fine);
+  for (int idx = threadIdx.x; idx < NN; idx += G::NT) F_out[off + idx] = b0[idx];
+}
+
+// Whole-workgroup reductions of values produced in strided passes.
+template <int NW, int K>
+__device__ __forceinline__ void wg_sum(double (&v)[K], double* red) { block_sum<NW, K>(v, red); }
+
+// Scheme (2.4) on the streamed state in b0 (global), result in b0.  Same
+// spectral CG as the on-chip variant; vectors in natural [row][col] order,
+// tables d (coarse tau) and 1/mu + tau in P.tab (natural order for n = 256).
+template <int N, int NW>
+__device__ void stream_approx2(double* b0, double* b1, double* cx, double* cr, double* cp,
+                               double* cq, double* cm, double* Lc, const double* T, double* red,
+                               const InstDev& P, int& status) {
+  const int NN = N * N, NT = NW * 64, t = threadIdx.x;
+  const double* cd = P.tab;
+  const double* cb = P.tab + NN;
+  const double tau = P.dT / P.m_coarse;
+  for (int sub = 0; sub < P.m_coarse; ++sub) {
+    double mn = 1e300, mx = -1e300;
+    for (int i = t; i < NN; i += NT) {
+      const double q = P.f_zero ? 0.0 : b0[i] * b0[i];
+      cq[i] = q;
+      mn = fmin(mn, q);
+      mx = fmax(mx, q);
+    }
+    block_minmax<NW>(mn, mx, red);
+    const double cshift = 0.5 * (mn + mx);
+    stream_stage<N, NW>(b0, b1, nullptr, Lc, T);
+    stream_stage<N, NW>(b1, b0, nullptr, Lc, T);   // b0 = u_hat
+    double acc[2] = {0.0, 0.0};
+    for (int i = t; i < NN; i += NT) {
+      const double b = (P.f_zero ? cb[i] - tau : cb[i]) * b0[i];
+      const double mi = 1.0 / (cd[i] + tau * cshift);
+      cm[i] = mi;
+      cx[i] = 0.0;
+      cr[i] = b;
+      cp[i] = b * mi;
+      acc[0] += b * b * mi;
+      acc[1] += b * b;
+    }
+    wg_sum<NW, 2>(acc, red);
+    double rz = acc[0];
+    const double stop2 = P.krylov_rtol * P.krylov_rtol * acc[1];
+    bool ok = !(acc[1] > 0.0);
+    for (int it = 1; !ok && it <= P.krylov_max; ++it) {
+      stream_stage<N, NW>(cp, b0, nullptr, Lc, T);
+      stream_stage<N, NW>(b0, b1, cq, Lc, T);       // q . (S p S)
+      stream_stage<N, NW>(b1, b0, nullptr, Lc, T);
+      stream_stage<N, NW>(b0, b1, nullptr, Lc, T);  // b1 = S (q . S p S) S
+      double a1[1] = {0.0};
+      for (int i = t; i < NN; i += NT) {
+        const double kp = cd[i] * cp[i] + tau * b1[i];
+        b1[i] = kp;
+        a1[0] += cp[i] * kp;
+      }
+      wg_sum<NW, 1>(a1, red);
+      const double alpha = rz / a1[0];
+      double a2[2] = {0.0, 0.0};
+      for (int i = t; i < NN; i += NT) {
+        cx[i] += alpha * cp[i];
+        const double r = cr[i] - alpha * b1[i];
+        cr[i] = r;
+        a2[0] += r * r;
+        a2[1] += r * (r * cm[i]);
+      }
+      wg_sum<NW, 2>(a2, red);
+      if (a2[0] <= stop2) { ok = true; break; }
+      if (!(a2[0] == a2[0])) break;
+      const double beta = a2[1] / rz;
+      rz = a2[1];
+      for (int i = t; i < NN; i += NT) cp[i] = cr[i] * cm[i] + beta * cp[i];
+      __syncthreads();
+    }
+    if (!ok) status |= 1;
+    stream_stage<N, NW>(cx, b1, nullptr, Lc, T);
+    stream_stage<N, NW>(b1, b0, nullptr, Lc, T);   // b0 = v
+  }
+}
+
+template <int N, int NW>
+__device__ void stream_coarse_apply(double* b0, const InstDev& P, double* w, double* Lc,
+                                    const double* T, double* red, int& status) {
+  const int64_t NN = (int64_t)N * N;
+  if (P.coarse_kind == 1) {
+    const double tau = P.dT / P.m_coarse;
+    stream_linear_steps<N, NW>(b0, w + NN, Lc, T, P.m_coarse, tau / (P.h * P.h), P.s_fine,
+                               P.f_zero, P.rsig_stab);
+  } else {
+    stream_approx2<N, NW>(b0, w + NN, w + 2 * NN, w + 3 * NN, w + 4 * NN, w + 5 * NN, w + 6 * NN,
+                          Lc, T, red, P, status);
+  }
+}
+
+// Streamed counterpart of k_coarse_2d (same modes).  Work vectors: b0 =
+// work[0] holds the state, the rest are solver scratch.
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_coarse_stream(int mode, const int32_t* __restrict__ insts, const WorkItem* __restrict__ items,
+                const InstDev* __restrict__ inst, const double* __restrict__ Tg,
+                const double* __restrict__ U_in, double* __restrict__ G_out,
+                const uint8_t* __restrict__ mask, double* U, const double* __restrict__ F,
+                double* G_old, double* delta, int32_t* status_out,
+                const int32_t* __restrict__ active, int k) {
+  using G = GeoS<N, NW>;
+  extern __shared__ double smem[];
+  double* Lc = smem;
+  double* T = smem + 2 * G::CHUNK;
+  double* red = T + G::P2;
+  const int64_t NN = (int64_t)N * N;
+  const int t = threadIdx.x;
+  int status = 0;
+  for (int m = t; m < G::P2; m += G::NT) T[m] = Tg[m];
+  if (mode == 0) {
+    const WorkItem it = items[blockIdx.x];
+    const InstDev P = inst[it.inst];
+    if (mask && !mask[P.slice_base + it.slice]) return;
+    if (P.coarse_kind == 2) return;
+    double* w = P.work + (int64_t)it.slice * WORK_VECS * NN;
+    const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+    for (int64_t i = t; i < NN; i += G::NT) w[i] = U_in[off + i];
+    __syncthreads();
+    stream_coarse_apply<N, NW>(w, P, w, Lc, T, red, status);
+    for (int64_t i = t; i < NN; i += G::NT) G_out[off + i] = w[i];
+    if (status && t == 0) atomicOr(P.status, status);
+    return;
+  }
+  const int ii = insts[blockIdx.x];
+  if (active && !active[ii]) return;
+  const InstDev P = inst[ii];
+  if (P.coarse_kind == 2) return;
+  double* w = P.work;
+  double* Ui = U + P.off_iter;
+  const double* Fi = F + P.off_slices;
+  double* Gi = G_old + P.off_slices;
+  const int Ns = P.n_slices;
+  if (mode == 1) {
+    for (int64_t i = t; i < NN; i += G::NT) w[i] = Ui[i];
+    __syncthreads();
+    for (int n = 0; n < Ns; ++n) {
+      stream_coarse_apply<N, NW>(w, P, w, Lc, T, red, status);
+      for (int64_t i = t; i < NN; i += G::NT) {
+        Ui[(n + 1) * NN + i] = w[i];
+        Gi[n * NN + i] = w[i];
+      }
+      __syncthreads();
+    }
+    if (t == 0) status_out[ii] = status | *P.status;
+    return;
+  }
+  if (k >= Ns) {
+    if (t == 0) delta[ii] = 0.0;
+    return;
+  }
+  double dmax;
+  {
+    double acc[1] = {0.0};
+    for (int64_t i = t; i < NN; i += G::NT) {
+      const double un = Fi[k * NN + i];
+      const double d = un - Ui[(k + 1) * NN + i];
+      acc[0] += d * d;
+      Ui[(k + 1) * NN + i] = un;
+      w[i] = un;
+    }
+    block_sum<NW, 1>(acc, red);
+    dmax = acc[0];
+  }
+  for (int n = k + 1; n < Ns; ++n) {
+    stream_coarse_apply<N, NW>(w, P, w, Lc, T, red, status);
+    double acc[1] = {0.0};
+    for (int64_t i = t; i < NN; i += G::NT) {
+      const double gv = w[i];
+      const double un = Fi[n * NN + i] + (gv - Gi[n * NN + i]);
+      const double d = un - Ui[(n + 1) * NN + i];
+      acc[0] += d * d;
+      Ui[(n + 1) * NN + i] = un;
+      Gi[n * NN + i] = gv;
+      w[i] = un;
+    }
+    block_sum<NW, 1>(acc, red);
+    dmax = fmax(dmax, acc[0]);
+  }
+  if (t == 0) {
+    const double dlt = sqrt(P.h * P.h * dmax);
+    delta[ii] = dlt;
+    if (!(dlt == dlt) || dlt > 1e300) status |= 2;
+    status_out[ii] = status | *P.status;
+  }
+}
+
+// Natural-order spectral tables for streamed instances (see k_cg_tables_2d).
+__global__ void k_cg_tables_natural(const int32_t* __restrict__ insts,
+                                    const InstDev* __restrict__ inst, const double* __restrict__ lam) {
+  const InstDev P = inst[insts[blockIdx.y]];
+  const int n = P.n;
+  const int64_t NN = (int64_t)n * n;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= NN) return;
+  const double mu = -(lam[i / n] + lam[i % n]);
+  const double tc = P.dT / P.m_coarse, tf = P.dt;
+  P.tab[i] = 1.0 / mu + tc * P.eps * P.eps * mu;
+  P.tab[NN + i] = 1.0 / mu + tc;
+  P.tab[2 * NN + i] = 1.0 / mu + tf * P.eps * P.eps * mu;
+  P.tab[3 * NN + i] = 1.0 / mu;
+}
+
 // ------------------------------------------- split-BF16 linear fine step
 // Reduced-precision variant of the linear step: the sine transforms run on
 // the BF16 matrix cores as three products S_hi X_hi + S_hi X_lo + S_lo X_hi
@@ -1450,12 +1803,27 @@ static hipError_t fine2d(const WorkItem* items, int n_items, const InstDev* inst
   return hipGetLastError();
 }
 
+template <int N, int NW>
+static hipError_t fine_stream(const WorkItem* items, int n_items, const InstDev* inst,
+                              const double* Tg, const double* U_in, double* F_out,
+                              const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                              hipStream_t s) {
+  const size_t lds = (size_t)(2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_stream<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fine_linear_stream<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items,
+                     inst, Tg, U_in, F_out, mask, active, k_min, in_iter);
+  return hipGetLastError();
+}
+
 hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* Tg, const double* U_in, double* F_out,
                           const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
                           hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (n) {
+    case 256: return fine_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
     case 32: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
     case 64: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
     case 128: return fine2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
@@ -1521,6 +1889,24 @@ static hipError_t coarse2d(int mode, const int32_t* insts, int n_insts, const Wo
   return hipGetLastError();
 }
 
+template <int N, int NW>
+static hipError_t coarse_stream(int mode, const int32_t* insts, int n_insts, const WorkItem* items,
+                                int n_items, const InstDev* inst, const double* Tg,
+                                const double* U_in, double* G_out, const uint8_t* mask, double* U,
+                                const double* F, double* G_old, double* delta, int32_t* status,
+                                const int32_t* active, int k, hipStream_t s) {
+  const size_t lds =
+      ((size_t)2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2 + 4 * NW) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_coarse_stream<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = mode == 0 ? n_items : n_insts;
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_coarse_stream<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
+                     items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k);
+  return hipGetLastError();
+}
+
 hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const WorkItem* items, int n_items, const InstDev* inst,
                             const double* Tg, const double* U_in,
@@ -1528,6 +1914,7 @@ hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             double* G_old, double* delta, int32_t* status,
                             const int32_t* active, int k, hipStream_t s) {
   switch (n) {
+    case 256: return coarse_stream<256, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
     case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
     case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
     case 128: return coarse2d<128, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
@@ -1558,6 +1945,10 @@ hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts, c
                             const double* lam, hipStream_t s) {
   if (dim != 2 || n_insts <= 0) return hipSuccess;
   switch (n) {
+    case 256:
+      hipLaunchKernelGGL(k_cg_tables_natural, dim3((256 * 256 + 255) / 256, n_insts), dim3(256), 0, s,
+                         insts, inst, lam);
+      break;
     case 32: hipLaunchKernelGGL((k_cg_tables_2d<32, 2>), dim3(n_insts), dim3(128), 0, s, insts, inst, lam); break;
     case 64: hipLaunchKernelGGL((k_cg_tables_2d<64, 4>), dim3(n_insts), dim3(256), 0, s, insts, inst, lam); break;
     case 128: hipLaunchKernelGGL((k_cg_tables_2d<128, 8>), dim3(n_insts), dim3(512), 0, s, insts, inst, lam); break;

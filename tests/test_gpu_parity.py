@@ -310,3 +310,49 @@ def test_split_bf16_full_slice_128():
     err = gu.rel(out, ref)
     print(f"split-bf16 full slice: rel L2 vs FP64 oracle {err:.2e}", flush=True)
     assert err < SPLIT_TOL, err
+
+
+def test_streamed_256_fine_matches_oracle():
+    # n = 256 streams the state through global memory (does not fit on a CU)
+    from paper_2304_14074_amd import chlib
+    J = 8
+    p = workloads.Problem(dim=2, n=256, eps=0.015, T=2 * J * 1e-5, n_slices=2, j_fine=J)
+    ctx = chlib.Context([p])
+    rng = np.random.default_rng(256)
+    X = np.stack([0.25 + 0.05 * rng.standard_normal((256, 256)), 0.9 * rng.uniform(-1, 1, (256, 256))])
+    out = gu.fine(ctx, [X])[0]
+    for s in range(2):
+        ref = propagators.fine(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+@pytest.mark.parametrize("kind,m", [("approx2", 1), ("stab", 2)])
+def test_streamed_256_coarse_matches_oracle(kind, m):
+    from paper_2304_14074_amd import chlib
+    p = workloads.Problem(dim=2, n=256, eps=0.015, T=2 / 32, n_slices=2, j_fine=10,
+                          coarse_kind=kind, m_coarse=m)
+    ctx = chlib.Context([p])
+    rng = np.random.default_rng(257)
+    X = np.stack([0.25 + 0.05 * rng.standard_normal((256, 256)), 0.9 * rng.uniform(-1, 1, (256, 256))])
+    out = gu.coarse(ctx, [X])[0]
+    for s in range(2):
+        ref = propagators.coarse(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+def test_streamed_256_parareal_iterates_match_oracle():
+    from paper_2304_14074_amd import chlib
+    N, J, n = 3, 6, 256
+    p = workloads.Problem(dim=2, n=n, eps=0.02, T=N * J * 2e-5, n_slices=N, j_fine=J)
+    u0 = workloads.u0_uniform(n, 2, 0.3, 9)
+    ctx = chlib.Context([p])
+    st = ctx.new_state()
+    st["U"][: n * n] = torch.from_numpy(u0.reshape(-1)).cuda()
+    ref = _oracle_run(p, u0, N)
+    ctx.ch_parareal_iterate(st, 0.0)
+    for k in range(1, N + 1):
+        ctx.ch_parareal_iterate(st, 0.0)
+        torch.cuda.synchronize()
+        U = gu.unpack_iter(ctx, st["U"])[0]
+        for j in range(N + 1):
+            assert gu.rel(U[j], ref["U"][k][j]) < TOL, (k, j)
