@@ -130,6 +130,19 @@ ch_status ch_parareal_iterate(ch_ctx* ctx, ch_pr_state* st, double tol, ch_strea
  * call equals one ch_parareal_iterate. */
 ch_status ch_parareal_correct(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream);
 
+/* hipGraph of one Parareal iteration (after the prediction): captured on
+ * the non-default `stream`, replayable with ch_graph_launch; each replay
+ * performs the next iteration (the iteration index lives in device memory).
+ * After replays, ch_iteration_count refreshes st->k from the device.  Not
+ * available while an instance uses the learned coarse propagator (its coarse
+ * sweep is driven from the host).  The caller owns the handle. */
+ch_status ch_parareal_graph_create(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream,
+                                   void** graph_exec);
+ch_status ch_graph_launch(void* graph_exec, ch_stream stream);
+ch_status ch_graph_destroy(void* graph_exec);
+/* Synchronous: copy the device iteration counter into st->k. */
+ch_status ch_iteration_count(ch_ctx* ctx, ch_pr_state* st, ch_stream stream);
+
 /* Discrete energy (Section 1, (1.2)) of `count` states of instance `inst`:
  * E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u).  E_out is
  * device memory of `count` doubles. */

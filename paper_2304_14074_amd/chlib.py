@@ -25,7 +25,8 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
            "ch_parareal_correct", "ch_energy", "ch_status_str", "ch_last_error",
            "ch_nn_param_count", "ch_nn_layer", "ch_nn_workspace_bytes", "ch_nn_forward",
-           "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind")
+           "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind",
+           "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count")
 
 
 class ChProblem(ctypes.Structure):
@@ -87,8 +88,14 @@ def load() -> ctypes.CDLL:
     lib.ch_nn_to_bf16.argtypes = [vp, vp, i64, vp]
     lib.ch_nn_bind.argtypes = [vp, vp]
     lib.ch_set_coarse_kind.argtypes = [vp, i32, i32, vp]
+    lib.ch_parareal_graph_create.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, vp,
+                                             ctypes.POINTER(vp)]
+    lib.ch_graph_launch.argtypes = [vp, vp]
+    lib.ch_graph_destroy.argtypes = [vp]
+    lib.ch_iteration_count.argtypes = [vp, ctypes.POINTER(ChPrState), vp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
-                 "ch_nn_bind", "ch_set_coarse_kind"):
+                 "ch_nn_bind", "ch_set_coarse_kind", "ch_parareal_graph_create", "ch_graph_launch",
+                 "ch_graph_destroy", "ch_iteration_count"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -188,6 +195,25 @@ class Context:
 
     def ch_energy(self, inst, u, count, E_out, stream=None):
         self._check(self.lib.ch_energy(self.h, inst, _ptr(u), count, _ptr(E_out), _stream(stream)))
+
+    def ch_parareal_graph_create(self, state, tol, stream):
+        """Capture one iteration on a non-default torch stream; returns a handle."""
+        c = self._state_struct(state)
+        h = ctypes.c_void_p()
+        self._check(self.lib.ch_parareal_graph_create(self.h, ctypes.byref(c), float(tol),
+                                                      _stream(stream), ctypes.byref(h)))
+        return h
+
+    def ch_graph_launch(self, handle, stream):
+        self._check(self.lib.ch_graph_launch(handle, _stream(stream)))
+
+    def ch_graph_destroy(self, handle):
+        self._check(self.lib.ch_graph_destroy(handle))
+
+    def ch_iteration_count(self, state, stream=None):
+        c = self._state_struct(state)
+        self._check(self.lib.ch_iteration_count(self.h, ctypes.byref(c), _stream(stream)))
+        return c.k
 
     def ch_nn_bind(self, w_bf16):
         self._nn_w = w_bf16          # keep the weights alive while bound

@@ -45,7 +45,7 @@ struct ch_ctx {
   std::vector<int64_t> slice_off, iter_off;
   int64_t slice_total = 0, iter_total = 0;
   std::vector<ClassPlan> classes;
-  Block inst_blk, active_blk, status_blk;
+  Block inst_blk, active_blk, status_blk, k_blk;
   std::vector<Block> rsig_fine_blk, rsig_stab_blk, tab_blk, work_blk;
   // learned coarse propagator
   Block nn_blk, nn_out_blk, nn_part_blk;
@@ -213,6 +213,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   c->inst_blk = take(sizeof(InstDev) * n_inst);
   c->active_blk = take(sizeof(int32_t) * n_inst);
   c->status_blk = take(sizeof(int32_t) * n_inst);
+  c->k_blk = take(sizeof(int32_t));
   for (auto& cp : c->classes) {
     cp.items_blk = take(sizeof(WorkItem) * cp.items.size());
     cp.insts_blk = take(sizeof(int32_t) * cp.insts.size());
@@ -364,7 +365,7 @@ static const double* class_sine(const ch_ctx* c, const ClassPlan& cp) {
 }
 
 static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const uint8_t* mask,
-                          const int32_t* active, int k_min, int in_iter, hipStream_t s) {
+                          const int32_t* active, const int32_t* k_min, int in_iter, hipStream_t s) {
   const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
   for (auto& cp : c->classes) {
     const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
@@ -397,13 +398,14 @@ ch_status ch_fine_propagate(ch_ctx* c, const double* U_in, double* F_out, const 
   const size_t bytes = sizeof(double) * c->slice_total;
   const char *a = (const char*)U_in, *b = (const char*)F_out;
   if (a < b + bytes && b < a + bytes) return fail(c, CH_ERR_ARG, "U_in and F_out overlap");
-  return fine_all(c, U_in, F_out, mask, nullptr, 0, 0, (hipStream_t)stream);
+  return fine_all(c, U_in, F_out, mask, nullptr, nullptr, 0, (hipStream_t)stream);
 }
 
 static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_out,
                             const uint8_t* mask, ch_pr_state* st, int k, hipStream_t s) {
   const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
   const int32_t* active = mode == 0 ? nullptr : (const int32_t*)(c->ws + c->active_blk.off);
+  const int32_t* kdev = mode == 2 ? (const int32_t*)(c->ws + c->k_blk.off) : nullptr;
   for (auto& cp : c->classes) {
     const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
     const int32_t* insts = (const int32_t*)(c->ws + cp.insts_blk.off);
@@ -417,10 +419,11 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     if (cp.dim == 2) {
       e = chk::launch_coarse_2d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
                                 inst, tab, U_in, G_out, mask, U, F, Gold, delta, status,
-                                active, k, s);
+                                active, k, kdev, s);
     } else {
       e = chk::launch_coarse_1d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
-                                inst, tab, U_in, G_out, mask, U, F, Gold, delta, status, active, k, s);
+                                inst, tab, U_in, G_out, mask, U, F, Gold, delta, status, active, k,
+                                kdev, s);
     }
     ch_status r = hip_check(c, e, "coarse launch");
     if (r != CH_OK) return r;
@@ -493,30 +496,38 @@ static ch_status pr_check(ch_ctx* c, ch_pr_state* st) {
   return CH_OK;
 }
 
-// phase 0: prediction; 1: fine sweep + correction; 2: correction only.
-static ch_status pr_step(ch_ctx* c, ch_pr_state* st, double tol, hipStream_t s, int with_fine) {
+// One step of the iteration.  The iteration index the kernels use lives in
+// device memory (k_blk) and is advanced by a kernel, so a captured step can
+// be replayed for successive iterations; st->k mirrors it on the host
+// (host_k = false while capturing: the replays advance only the device copy).
+static ch_status pr_step(ch_ctx* c, ch_pr_state* st, double tol, hipStream_t s, int with_fine,
+                         bool host_k = true) {
   int32_t* active = (int32_t*)(c->ws + c->active_blk.off);
+  int32_t* kdev = (int32_t*)(c->ws + c->k_blk.off);
   const int n_inst = (int)c->probs.size();
   ch_status r;
   if (!st->predicted) {
-    r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 1, s), "flags");
+    r = hip_check(c, chk::launch_counter(kdev, 0, 0, s), "iteration counter");
+    if (r != CH_OK) return r;
+    r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 1, kdev, s), "flags");
     if (r != CH_OK) return r;
     r = coarse_all(c, 1, nullptr, nullptr, nullptr, st, 0, s);
     if (r != CH_OK) return r;
     st->predicted = 1;
+    st->k = 0;
     return CH_OK;
   }
-  if (st->k > 0) {
-    r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 0, s), "flags");
-    if (r != CH_OK) return r;
-  }
+  r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 0, kdev, s), "flags");
+  if (r != CH_OK) return r;
   if (with_fine) {
-    r = fine_all(c, st->U, st->F, nullptr, active, st->k, 1, s);
+    r = fine_all(c, st->U, st->F, nullptr, active, kdev, 1, s);
     if (r != CH_OK) return r;
   }
   r = coarse_all(c, 2, nullptr, nullptr, nullptr, st, st->k, s);
   if (r != CH_OK) return r;
-  st->k += 1;
+  r = hip_check(c, chk::launch_counter(kdev, 1, 1, s), "iteration counter");
+  if (r != CH_OK) return r;
+  if (host_k) st->k += 1;
   return CH_OK;
 }
 
@@ -531,6 +542,58 @@ ch_status ch_parareal_correct(ch_ctx* c, ch_pr_state* st, double tol, ch_stream 
   if (r != CH_OK) return r;
   if (!st->predicted) return fail(c, CH_ERR_STATE, "the coarse prediction has not been formed");
   return pr_step(c, st, tol, (hipStream_t)stream, 0);
+}
+
+ch_status ch_parareal_graph_create(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream,
+                                   void** graph_exec) {
+  ch_status r = pr_check(c, st);
+  if (r != CH_OK) return r;
+  if (!graph_exec) return fail(c, CH_ERR_ARG, "null graph handle");
+  if (!st->predicted) return fail(c, CH_ERR_STATE, "form the coarse prediction first");
+  if (!stream) return fail(c, CH_ERR_ARG, "capture needs a non-default stream");
+  for (const auto& d : c->inst)
+    if (d.coarse_kind == CH_COARSE_NEURAL)
+      return fail(c, CH_ERR_UNSUPPORTED, "the learned coarse sweep is host-driven: no capture");
+  hipStream_t s = (hipStream_t)stream;
+  hipGraph_t g = nullptr;
+  r = hip_check(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (r != CH_OK) return r;
+  ch_status inner = pr_step(c, st, tol, s, 1, false);
+  r = hip_check(c, hipStreamEndCapture(s, &g), "end capture");
+  if (inner != CH_OK) return inner;
+  if (r != CH_OK) return r;
+  hipGraphExec_t ex = nullptr;
+  r = hip_check(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
+  hipGraphDestroy(g);
+  if (r != CH_OK) return r;
+  *graph_exec = (void*)ex;
+  return CH_OK;
+}
+
+ch_status ch_graph_launch(void* graph_exec, ch_stream stream) {
+  if (!graph_exec) return CH_ERR_ARG;
+  return hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream) == hipSuccess ? CH_OK
+                                                                                      : CH_ERR_HIP;
+}
+
+ch_status ch_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return CH_ERR_ARG;
+  return hipGraphExecDestroy((hipGraphExec_t)graph_exec) == hipSuccess ? CH_OK : CH_ERR_HIP;
+}
+
+ch_status ch_iteration_count(ch_ctx* c, ch_pr_state* st, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (!st) return fail(c, CH_ERR_ARG, "null state");
+  int32_t k = 0;
+  hipStream_t s = (hipStream_t)stream;
+  r = hip_check(c, hipMemcpyAsync(&k, c->ws + c->k_blk.off, sizeof k, hipMemcpyDeviceToHost, s),
+                "counter read");
+  if (r != CH_OK) return r;
+  r = hip_check(c, hipStreamSynchronize(s), "counter sync");
+  if (r != CH_OK) return r;
+  st->k = k;
+  return CH_OK;
 }
 
 int64_t ch_nn_param_count(void) { return chk::nn_param_count(); }

@@ -31,24 +31,25 @@ constexpr int WORK_VECS = 7;  // x, r, p, q, minv, u_hat, y_hat
 struct WorkItem { int32_t inst, slice; };
 
 // Launch helpers implemented in ch_kernels.hip; return hipSuccess or an error.
-// Fine sweep.  Work items with slice < k_min or an inactive instance are
-// skipped; in_iter selects the iterate layout for the input states.
+// Fine sweep.  Work items with slice < *kmin (kmin may be null) or of an
+// inactive instance are skipped; in_iter selects the iterate layout for the
+// input states.
 hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* Tsin, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,
-                          int k_min, int in_iter, hipStream_t s);
+                          const int32_t* kmin, int in_iter, hipStream_t s);
 hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                  const double* Tsin, const double* U_in, double* F_out,
-                                 const uint8_t* mask, const int32_t* active, int k_min,
+                                 const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                                  int in_iter, hipStream_t s);
 hipError_t launch_fine_split_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                 const double* Tsin, const double* U_in, double* F_out,
-                                const uint8_t* mask, const int32_t* active, int k_min,
+                                const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                                 int in_iter, hipStream_t s);
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* S, const double* rsig1, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,
-                          int k_min, int in_iter, hipStream_t s);
+                          const int32_t* kmin, int in_iter, hipStream_t s);
 // mode 0: independent G per masked slice (parallel); 1: prediction chain;
 // 2: correction chain starting at slice k+1 with U_{k+1} = F_k.
 hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
@@ -56,20 +57,21 @@ hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const double* Tsin, const double* U_in,
                             double* G_out, const uint8_t* mask, double* U, const double* F,
                             double* G_old, double* delta, int32_t* status,
-                            const int32_t* active, int k, hipStream_t s);
+                            const int32_t* active, int k, const int32_t* kdev, hipStream_t s);
 hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
                             const WorkItem* items, int n_items, const InstDev* inst,
                             const double* S, const double* U_in, double* G_out,
                             const uint8_t* mask, double* U, const double* F, double* G_old,
                             double* delta, int32_t* status, const int32_t* active, int k,
-                            hipStream_t s);
+                            const int32_t* kdev, hipStream_t s);
 // Fill the per-instance CG tables (d and b-scale in the owned layout).
 hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts,
                             const InstDev* inst, const double* lam, hipStream_t s);
 hipError_t launch_energy(int n, int dim, const double* u, int count, double eps, double* E,
                          hipStream_t s);
 hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
-                              int first, hipStream_t s);
+                              int first, const int32_t* kdev, hipStream_t s);
+hipError_t launch_counter(int32_t* kdev, int value, int add, hipStream_t s);
 
 // ---- learned coarse propagator (ch_nn.hip)
 struct NNLayer { int c_in, c_out, k, stride, act, cat; };

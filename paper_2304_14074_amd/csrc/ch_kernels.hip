@@ -380,14 +380,14 @@ __global__ void __launch_bounds__(NW * 64)
 k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
                  const double* __restrict__ Tg, const double* __restrict__ U_in,
                  double* __restrict__ F_out, const uint8_t* __restrict__ mask,
-                 const int32_t* __restrict__ active, int k_min, int in_iter) {
+                 const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
   extern __shared__ double smem[];
   double* X = smem + Geo<N, NW>::XOFF;   // interior origin
   double* T = smem + Geo<N, NW>::XSZ;
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
-  if (it.slice < k_min || (active && !active[it.inst])) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
   const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
   const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
   Lane<N, NW> L;
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(NW * 64)
 k_fine_newton_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
                  const double* __restrict__ Tg, const double* __restrict__ U_in,
                  double* __restrict__ F_out, const uint8_t* __restrict__ mask,
-                 const int32_t* __restrict__ active, int k_min, int in_iter) {
+                 const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
   using G = Geo<N, NW>;
   extern __shared__ double smem[];
   double* X = smem + G::XOFF;
@@ -690,7 +690,7 @@ k_fine_newton_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
-  if (it.slice < k_min || (active && !active[it.inst])) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
   const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
   const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
   Lane<N, NW> L;
@@ -751,8 +751,9 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
             const double* __restrict__ U_in,
             double* __restrict__ G_out, const uint8_t* __restrict__ mask, double* U,
             const double* __restrict__ F, double* G_old, double* delta, int32_t* status_out,
-            const int32_t* __restrict__ active, int k) {
+            const int32_t* __restrict__ active, int k, const int32_t* __restrict__ kdev) {
   using G = Geo<N, NW>;
+  if (kdev) k = *kdev;
   extern __shared__ double smem[];
   double* X = smem + G::XOFF;   // interior origin
   double* T = smem + G::XSZ;
@@ -1002,7 +1003,7 @@ __global__ void __launch_bounds__(NW * 64)
 k_fine_linear_stream(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
                      const double* __restrict__ Tg, const double* __restrict__ U_in,
                      double* __restrict__ F_out, const uint8_t* __restrict__ mask,
-                     const int32_t* __restrict__ active, int k_min, int in_iter) {
+                     const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
   using G = GeoS<N, NW>;
   extern __shared__ double smem[];
   double* Lc = smem;
@@ -1010,7 +1011,7 @@ k_fine_linear_stream(const WorkItem* __restrict__ items, const InstDev* __restri
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
-  if (it.slice < k_min || (active && !active[it.inst])) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
   const int64_t NN = (int64_t)N * N;
   const int64_t off = P.off_slices + (int64_t)it.slice * NN;
   const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
@@ -1124,8 +1125,9 @@ k_coarse_stream(int mode, const int32_t* __restrict__ insts, const WorkItem* __r
                 const double* __restrict__ U_in, double* __restrict__ G_out,
                 const uint8_t* __restrict__ mask, double* U, const double* __restrict__ F,
                 double* G_old, double* delta, int32_t* status_out,
-                const int32_t* __restrict__ active, int k) {
+                const int32_t* __restrict__ active, int k, const int32_t* __restrict__ kdev) {
   using G = GeoS<N, NW>;
+  if (kdev) k = *kdev;
   extern __shared__ double smem[];
   double* Lc = smem;
   double* T = smem + 2 * G::CHUNK;
@@ -1432,7 +1434,7 @@ __global__ void __launch_bounds__(NW * 64)
 k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
                 const double* __restrict__ Tg, const double* __restrict__ U_in,
                 double* __restrict__ F_out, const uint8_t* __restrict__ mask,
-                const int32_t* __restrict__ active, int k_min, int in_iter) {
+                const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
   using G = GeoB<N, NW>;
   extern __shared__ double smem[];
   double* X = smem + G::XOFF;            // FP64 stencil buffer (interior origin)
@@ -1440,7 +1442,7 @@ k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ 
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
-  if (it.slice < k_min || (active && !active[it.inst])) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
   const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
   const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
   LaneB<N, NW> L;
@@ -1514,24 +1516,24 @@ k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ 
 template <int N, int NW>
 static hipError_t split2d(const WorkItem* items, int n_items, const InstDev* inst, const double* Tg,
                           const double* U_in, double* F_out, const uint8_t* mask,
-                          const int32_t* active, int k_min, int in_iter, hipStream_t s) {
+                          const int32_t* active, const int32_t* kmin, int in_iter, hipStream_t s) {
   const size_t lds = (size_t)GeoB<N, NW>::XSZ * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_split_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fine_split_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
-                     Tg, U_in, F_out, mask, active, k_min, in_iter);
+                     Tg, U_in, F_out, mask, active, kmin, in_iter);
   return hipGetLastError();
 }
 
 hipError_t launch_fine_split_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                 const double* Tg, const double* U_in, double* F_out,
-                                const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                                const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
                                 hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (n) {
-    case 64: return split2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 128: return split2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 64: return split2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 128: return split2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1549,12 +1551,12 @@ __global__ void k_fine_linear_1d(const WorkItem* __restrict__ items, const InstD
                                  const double* __restrict__ S, const double* __restrict__ rsig1,
                                  const double* __restrict__ U_in, double* __restrict__ F_out,
                                  const uint8_t* __restrict__ mask,
-                                 const int32_t* __restrict__ active, int k_min, int in_iter) {
+                                 const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
   extern __shared__ double smem[];
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
-  if (it.slice < k_min || (active && !active[it.inst])) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
   const int n = P.n, i = threadIdx.x;
   double* Sl = smem;
   double* w = smem + n * n;
@@ -1680,8 +1682,10 @@ __global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
                             const double* __restrict__ U_in, double* __restrict__ G_out,
                             const uint8_t* __restrict__ mask, double* U,
                             const double* __restrict__ F, double* G_old, double* delta,
-                            int32_t* status_out, const int32_t* __restrict__ active, int k) {
+                            int32_t* status_out, const int32_t* __restrict__ active, int k,
+                            const int32_t* __restrict__ kdev) {
   extern __shared__ double smem[];
+  if (kdev) k = *kdev;
   const int i = threadIdx.x;
   int status = 0;
   if (mode == 0) {
@@ -1780,53 +1784,64 @@ k_energy(int n, int dim, const double* __restrict__ u, double eps, double* __res
   }
 }
 
+// first != 0: every instance active.  Otherwise instances whose last update
+// norm fell below tol stop, once at least one correction has been made
+// (device iteration counter *kdev > 0).
 __global__ void k_flag_active(const double* __restrict__ delta, int32_t* __restrict__ active,
-                              int n_inst, double tol, int first) {
+                              int n_inst, double tol, int first, const int32_t* __restrict__ kdev) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_inst) return;
   if (first) active[i] = 1;
-  else if (active[i] && delta[i] < tol) active[i] = 0;
+  else if (*kdev > 0 && active[i] && delta[i] < tol) active[i] = 0;
+}
+// *kdev = value (add == 0) or *kdev += value
+__global__ void k_counter(int32_t* kdev, int value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *kdev = add ? *kdev + value : value;
+}
+hipError_t launch_counter(int32_t* kdev, int value, int add, hipStream_t s) {
+  hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, kdev, value, add);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ launchers
 template <int N, int NW>
 static hipError_t fine2d(const WorkItem* items, int n_items, const InstDev* inst,
                          const double* Tg, const double* U_in, double* F_out,
-                         const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                         const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
                          hipStream_t s) {
   const size_t lds = (size_t)(Geo<N, NW>::XSZ + Geo<N, NW>::P2) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fine_linear_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
-                     Tg, U_in, F_out, mask, active, k_min, in_iter);
+                     Tg, U_in, F_out, mask, active, kmin, in_iter);
   return hipGetLastError();
 }
 
 template <int N, int NW>
 static hipError_t fine_stream(const WorkItem* items, int n_items, const InstDev* inst,
                               const double* Tg, const double* U_in, double* F_out,
-                              const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                              const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
                               hipStream_t s) {
   const size_t lds = (size_t)(2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_stream<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fine_linear_stream<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items,
-                     inst, Tg, U_in, F_out, mask, active, k_min, in_iter);
+                     inst, Tg, U_in, F_out, mask, active, kmin, in_iter);
   return hipGetLastError();
 }
 
 hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* Tg, const double* U_in, double* F_out,
-                          const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                          const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
                           hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (n) {
-    case 256: return fine_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 32: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 64: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 128: return fine2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 256: return fine_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 32: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 64: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 128: return fine2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1834,33 +1849,33 @@ hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstD
 template <int N, int NW>
 static hipError_t newton2d(const WorkItem* items, int n_items, const InstDev* inst,
                            const double* Tg, const double* U_in, double* F_out,
-                           const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                           const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
                            hipStream_t s) {
   const size_t lds = ((size_t)Geo<N, NW>::XSZ + Geo<N, NW>::P2 + 4 * NW) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_newton_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fine_newton_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
-                     Tg, U_in, F_out, mask, active, k_min, in_iter);
+                     Tg, U_in, F_out, mask, active, kmin, in_iter);
   return hipGetLastError();
 }
 
 hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                  const double* Tg, const double* U_in, double* F_out,
-                                 const uint8_t* mask, const int32_t* active, int k_min,
+                                 const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                                  int in_iter, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (n) {
-    case 32: return newton2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 64: return newton2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
-    case 128: return newton2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, k_min, in_iter, s);
+    case 32: return newton2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 64: return newton2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 128: return newton2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* S, const double* rsig1, const double* U_in, double* F_out,
-                          const uint8_t* mask, const int32_t* active, int k_min, int in_iter,
+                          const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
                           hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   const size_t lds = ((size_t)n * n + 2 * n) * sizeof(double);
@@ -1868,7 +1883,7 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fine_linear_1d, dim3(n_items), dim3(n), lds, s, items, inst, S, rsig1, U_in,
-                     F_out, mask, active, k_min, in_iter);
+                     F_out, mask, active, kmin, in_iter);
   return hipGetLastError();
 }
 
@@ -1877,7 +1892,7 @@ static hipError_t coarse2d(int mode, const int32_t* insts, int n_insts, const Wo
                            int n_items, const InstDev* inst, const double* Tg,
                            const double* U_in, double* G_out, const uint8_t* mask, double* U,
                            const double* F, double* G_old, double* delta, int32_t* status,
-                           const int32_t* active, int k, hipStream_t s) {
+                           const int32_t* active, int k, const int32_t* kdev, hipStream_t s) {
   const size_t lds = ((size_t)Geo<N, NW>::XSZ + Geo<N, NW>::P2 + 4 * NW) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1885,7 +1900,7 @@ static hipError_t coarse2d(int mode, const int32_t* insts, int n_insts, const Wo
   const int grid = mode == 0 ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_coarse_2d<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts, items,
-                     inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k);
+                     inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
   return hipGetLastError();
 }
 
@@ -1894,7 +1909,7 @@ static hipError_t coarse_stream(int mode, const int32_t* insts, int n_insts, con
                                 int n_items, const InstDev* inst, const double* Tg,
                                 const double* U_in, double* G_out, const uint8_t* mask, double* U,
                                 const double* F, double* G_old, double* delta, int32_t* status,
-                                const int32_t* active, int k, hipStream_t s) {
+                                const int32_t* active, int k, const int32_t* kdev, hipStream_t s) {
   const size_t lds =
       ((size_t)2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2 + 4 * NW) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_stream<N, NW>,
@@ -1903,7 +1918,7 @@ static hipError_t coarse_stream(int mode, const int32_t* insts, int n_insts, con
   const int grid = mode == 0 ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_coarse_stream<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
-                     items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k);
+                     items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
   return hipGetLastError();
 }
 
@@ -1912,12 +1927,12 @@ hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const double* Tg, const double* U_in,
                             double* G_out, const uint8_t* mask, double* U, const double* F,
                             double* G_old, double* delta, int32_t* status,
-                            const int32_t* active, int k, hipStream_t s) {
+                            const int32_t* active, int k, const int32_t* kdev, hipStream_t s) {
   switch (n) {
-    case 256: return coarse_stream<256, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
-    case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
-    case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
-    case 128: return coarse2d<128, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, s);
+    case 256: return coarse_stream<256, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
+    case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
+    case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
+    case 128: return coarse2d<128, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1927,7 +1942,7 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
                             const double* S, const double* U_in, double* G_out,
                             const uint8_t* mask, double* U, const double* F, double* G_old,
                             double* delta, int32_t* status, const int32_t* active, int k,
-                            hipStream_t s) {
+                            const int32_t* kdev, hipStream_t s) {
   // lam for 1D is stored right after S (n x n) in the table block
   const double* lam = S + (size_t)n * n;
   const size_t lds = ((size_t)n * n + n + 64) * sizeof(double);
@@ -1937,7 +1952,7 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
   const int grid = mode == 0 ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_coarse_1d, dim3(grid), dim3(n), lds, s, mode, insts, items, inst, S, lam,
-                     U_in, G_out, mask, U, F, G_old, delta, status, active, k);
+                     U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
   return hipGetLastError();
 }
 
@@ -1965,9 +1980,9 @@ hipError_t launch_energy(int n, int dim, const double* u, int count, double eps,
 }
 
 hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
-                              int first, hipStream_t s) {
+                              int first, const int32_t* kdev, hipStream_t s) {
   hipLaunchKernelGGL(k_flag_active, dim3((n_inst + 255) / 256), dim3(256), 0, s, delta, active,
-                     n_inst, tol, first);
+                     n_inst, tol, first, kdev);
   return hipGetLastError();
 }
 
