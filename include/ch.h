@@ -130,6 +130,16 @@ ch_status ch_parareal_iterate(ch_ctx* ctx, ch_pr_state* st, double tol, ch_strea
  * call equals one ch_parareal_iterate. */
 ch_status ch_parareal_correct(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream);
 
+/* Autotuner of the on-chip FP64 linear fine kernels (2D, n <= 128): times
+ * every workgroup-size variant over `steps` fine steps of all slices of each
+ * grid-size class on the given inputs (slice layout; F_out is overwritten)
+ * and keeps the fastest.  Synchronous. */
+ch_status ch_autotune(ch_ctx* ctx, const double* U_in, double* F_out, int32_t steps,
+                      ch_stream stream);
+/* Query (set = 0) or set (set = 1) the waves per workgroup of the fine
+ * kernel for grid size n (e.g. from a cached tuning result). */
+ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
+
 /* hipGraph of one Parareal iteration (after the prediction): captured on
  * the non-default `stream`, replayable with ch_graph_launch; each replay
  * performs the next iteration (the iteration index lives in device memory).
@@ -142,6 +152,8 @@ ch_status ch_graph_launch(void* graph_exec, ch_stream stream);
 ch_status ch_graph_destroy(void* graph_exec);
 /* Synchronous: copy the device iteration counter into st->k. */
 ch_status ch_iteration_count(ch_ctx* ctx, ch_pr_state* st, ch_stream stream);
+/* Set the iteration counter (device and st->k), e.g. to repeat an iteration. */
+ch_status ch_set_iteration(ch_ctx* ctx, ch_pr_state* st, int32_t k, ch_stream stream);
 
 /* Discrete energy (Section 1, (1.2)) of `count` states of instance `inst`:
  * E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u).  E_out is

@@ -26,7 +26,8 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_parareal_correct", "ch_energy", "ch_status_str", "ch_last_error",
            "ch_nn_param_count", "ch_nn_layer", "ch_nn_workspace_bytes", "ch_nn_forward",
            "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind",
-           "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count")
+           "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
+           "ch_autotune", "ch_fine_variant", "ch_set_iteration")
 
 
 class ChProblem(ctypes.Structure):
@@ -91,11 +92,15 @@ def load() -> ctypes.CDLL:
     lib.ch_parareal_graph_create.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, vp,
                                              ctypes.POINTER(vp)]
     lib.ch_graph_launch.argtypes = [vp, vp]
+    lib.ch_autotune.argtypes = [vp, vp, vp, i32, vp]
+    lib.ch_set_iteration.argtypes = [vp, ctypes.POINTER(ChPrState), i32, vp]
+    lib.ch_fine_variant.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     lib.ch_graph_destroy.argtypes = [vp]
     lib.ch_iteration_count.argtypes = [vp, ctypes.POINTER(ChPrState), vp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
                  "ch_nn_bind", "ch_set_coarse_kind", "ch_parareal_graph_create", "ch_graph_launch",
-                 "ch_graph_destroy", "ch_iteration_count"):
+                 "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
+                 "ch_set_iteration"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -214,6 +219,44 @@ class Context:
         c = self._state_struct(state)
         self._check(self.lib.ch_iteration_count(self.h, ctypes.byref(c), _stream(stream)))
         return c.k
+
+    def ch_set_iteration(self, state, k, stream=None):
+        c = self._state_struct(state)
+        self._check(self.lib.ch_set_iteration(self.h, ctypes.byref(c), k, _stream(stream)))
+
+    def ch_autotune(self, U_in, F_out, steps=20, stream=None):
+        self._check(self.lib.ch_autotune(self.h, _ptr(U_in), _ptr(F_out), steps, _stream(stream)))
+
+    def ch_fine_variant(self, n, waves=None):
+        w = ctypes.c_int32(0 if waves is None else waves)
+        self._check(self.lib.ch_fine_variant(self.h, n, ctypes.byref(w), 0 if waves is None else 1))
+        return w.value
+
+    def autotune(self, U_in, F_out, cache_path=None, steps=20):
+        """Tuned fine-kernel variants, from a JSON cache keyed by GPU
+        architecture and grid size when present, else measured and cached."""
+        import json
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        sizes = sorted({p.n for p in self.problems if p.dim == 2 and p.n <= 128
+                        and getattr(p, "fine_kind", "linear") == "linear"
+                        and getattr(p, "precision", "fp64") == "fp64"})
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        entry = cache.get(arch, {})
+        if all(f"linear-fp64-n{n}" in entry for n in sizes):
+            for n in sizes:
+                self.ch_fine_variant(n, entry[f"linear-fp64-n{n}"])
+            return {n: entry[f"linear-fp64-n{n}"] for n in sizes}, True
+        self.ch_autotune(U_in, F_out, steps)
+        chosen = {n: self.ch_fine_variant(n) for n in sizes}
+        if cache_path:
+            entry.update({f"linear-fp64-n{n}": w for n, w in chosen.items()})
+            cache[arch] = entry
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1)
+        return chosen, False
 
     def ch_nn_bind(self, w_bf16):
         self._nn_w = w_bf16          # keep the weights alive while bound

@@ -31,6 +31,7 @@ struct Block {
 
 struct ClassPlan {      // all instances sharing (dim, n, fine kind, precision)
   int dim = 2, n = 0, fine_kind = 0, precision = 0;
+  int waves = 0;        // fine-kernel variant (0 = default), set by the autotuner
   std::vector<WorkItem> items;   // every slice of every instance in the class
   std::vector<int32_t> insts;    // instance indices
   Block items_blk, insts_blk;
@@ -53,6 +54,7 @@ struct ch_ctx {
   const uint16_t* nn_w = nullptr;
   bool nn_planned = false;
   size_t ws_bytes = 0;
+  size_t host_init_bytes = 0;       // leading part of the workspace uploaded at bind
   char* ws = nullptr;               // bound workspace
   std::string err;
 };
@@ -221,6 +223,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     cp.sine_blk = cp.dim == 2 ? take(sizeof(double) * (2 * (n + 1) + n))
                               : take(sizeof(double) * (n * n + n));
   }
+  // blocks initialised from the host image first, device-only blocks after
   c->rsig_fine_blk.resize(n_inst);
   c->rsig_stab_blk.resize(n_inst);
   c->tab_blk.resize(n_inst);
@@ -229,6 +232,10 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     const size_t P = probs[i].dim == 2 ? (size_t)probs[i].n * probs[i].n : probs[i].n;
     c->rsig_fine_blk[i] = take(sizeof(double) * P);
     c->rsig_stab_blk[i] = take(sizeof(double) * P);
+  }
+  c->host_init_bytes = off;
+  for (int i = 0; i < n_inst; ++i) {
+    const size_t P = probs[i].dim == 2 ? (size_t)probs[i].n * probs[i].n : probs[i].n;
     if (probs[i].dim == 2) {
       c->tab_blk[i] = take(sizeof(double) * P * chk::TAB_VECS);
       c->work_blk[i] = take(sizeof(double) * P * chk::WORK_VECS * (size_t)probs[i].n_slices);
@@ -291,7 +298,7 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
   c->ws = ws;
   const int n_inst = (int)c->probs.size();
   // host images of everything, copied in one pass
-  std::vector<char> img(c->ws_bytes, 0);
+  std::vector<char> img(c->host_init_bytes, 0);
   for (int i = 0; i < n_inst; ++i) {
     InstDev& d = c->inst[i];
     const ch_problem& p = c->probs[i];
@@ -338,7 +345,8 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
       for (int k = 0; k < n; ++k) t[n * n + k] = lap_eig(k + 1, n);
     }
   }
-  ch_status st = hip_check(c, hipMemcpyAsync(ws, img.data(), c->ws_bytes, hipMemcpyHostToDevice, s),
+  ch_status st = hip_check(c, hipMemcpyAsync(ws, img.data(), c->host_init_bytes,
+                                             hipMemcpyHostToDevice, s),
                            "workspace upload");
   if (st != CH_OK) return st;
   for (auto& cp : c->classes) {
@@ -379,7 +387,7 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
                                     mask, active, k_min, in_iter, s);
     } else if (cp.dim == 2) {
       e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
-                              mask, active, k_min, in_iter, s);
+                              mask, active, k_min, in_iter, s, cp.waves);
     } else {
       e = chk::launch_fine_1d(cp.n, items, (int)cp.items.size(), inst, tab, nullptr, U_in, F_out,
                               mask, active, k_min, in_iter, s);
@@ -544,6 +552,75 @@ ch_status ch_parareal_correct(ch_ctx* c, ch_pr_state* st, double tol, ch_stream 
   return pr_step(c, st, tol, (hipStream_t)stream, 0);
 }
 
+static bool tunable(const ClassPlan& cp) {
+  return cp.dim == 2 && cp.fine_kind == CH_FINE_LINEAR && cp.precision == CH_PREC_FP64 &&
+         cp.n <= 128;
+}
+
+ch_status ch_autotune(ch_ctx* c, const double* U_in, double* F_out, int32_t steps, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (!U_in || !F_out || steps < 1) return fail(c, CH_ERR_ARG, "autotune arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(c, CH_ERR_HIP, "event create");
+  for (auto& cp : c->classes) {
+    if (!tunable(cp)) continue;
+    int opts[8];
+    const int no = chk::fine_wave_options(cp.n, opts);
+    float best = 1e30f;
+    int best_w = opts[0];
+    const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
+    for (int o = 0; o < no; ++o) {
+      // warm-up then timed launch of `steps` fine steps over the class
+      hipError_t e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, class_sine(c, cp),
+                                         U_in, F_out, nullptr, nullptr, nullptr, 0, s, opts[o], 1);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, class_sine(c, cp), U_in,
+                                F_out, nullptr, nullptr, nullptr, 0, s, opts[o], steps);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return hip_check(c, e, "autotune run");
+      }
+      if (ms < best) { best = ms; best_w = opts[o]; }
+    }
+    cp.waves = best_w;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return CH_OK;
+}
+
+ch_status ch_fine_variant(ch_ctx* c, int32_t n, int32_t* waves, int32_t set) {
+  if (!c || !waves) return CH_ERR_ARG;
+  bool found = false;
+  for (auto& cp : c->classes) {
+    if (!tunable(cp) || cp.n != n) continue;
+    found = true;
+    if (set) {
+      int opts[8];
+      const int no = chk::fine_wave_options(n, opts);
+      bool ok = false;
+      for (int o = 0; o < no; ++o) ok = ok || opts[o] == *waves;
+      if (!ok) return fail(c, CH_ERR_ARG, "n = %d has no %d-wave variant", n, *waves);
+      cp.waves = *waves;
+    } else {
+      int opts[8];
+      chk::fine_wave_options(n, opts);
+      *waves = cp.waves ? cp.waves : opts[0];
+    }
+  }
+  return found ? CH_OK : fail(c, CH_ERR_ARG, "no tunable class with n = %d", n);
+}
+
 ch_status ch_parareal_graph_create(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream,
                                    void** graph_exec) {
   ch_status r = pr_check(c, st);
@@ -594,6 +671,16 @@ ch_status ch_iteration_count(ch_ctx* c, ch_pr_state* st, ch_stream stream) {
   if (r != CH_OK) return r;
   st->k = k;
   return CH_OK;
+}
+
+ch_status ch_set_iteration(ch_ctx* c, ch_pr_state* st, int32_t k, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (!st || k < 0) return fail(c, CH_ERR_ARG, "set iteration arguments");
+  r = hip_check(c, chk::launch_counter((int32_t*)(c->ws + c->k_blk.off), k, 0, (hipStream_t)stream),
+                "iteration counter");
+  if (r == CH_OK) st->k = k;
+  return r;
 }
 
 int64_t ch_nn_param_count(void) { return chk::nn_param_count(); }

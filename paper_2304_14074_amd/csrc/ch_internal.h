@@ -34,10 +34,13 @@ struct WorkItem { int32_t inst, slice; };
 // Fine sweep.  Work items with slice < *kmin (kmin may be null) or of an
 // inactive instance are skipped; in_iter selects the iterate layout for the
 // input states.
+// waves: workgroup size variant (0 = default); j_steps > 0 overrides J (tuning).
 hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* Tsin, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,
-                          const int32_t* kmin, int in_iter, hipStream_t s);
+                          const int32_t* kmin, int in_iter, hipStream_t s, int waves = 0,
+                          int j_steps = 0);
+int fine_wave_options(int n, int* out);
 hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                  const double* Tsin, const double* U_in, double* F_out,
                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,

@@ -380,7 +380,8 @@ __global__ void __launch_bounds__(NW * 64)
 k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
                  const double* __restrict__ Tg, const double* __restrict__ U_in,
                  double* __restrict__ F_out, const uint8_t* __restrict__ mask,
-                 const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
+                 const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter,
+                 int j_steps) {
   extern __shared__ double smem[];
   double* X = smem + Geo<N, NW>::XOFF;   // interior origin
   double* T = smem + Geo<N, NW>::XSZ;
@@ -398,8 +399,8 @@ k_fine_linear_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__
   load_state<N, NW>(X, U_in + off_in);
   __syncthreads();
   double v[Geo<N, NW>::OWN];
-  linear_steps<N, NW>(X, T, sw, L, v, P.j_fine, P.dt / (P.h * P.h), P.s_fine, P.f_zero,
-                      P.rsig_fine);
+  linear_steps<N, NW>(X, T, sw, L, v, j_steps > 0 ? j_steps : P.j_fine, P.dt / (P.h * P.h),
+                      P.s_fine, P.f_zero, P.rsig_fine);
   store_state<N, NW>(X, F_out + off);
 }
 
@@ -1808,13 +1809,13 @@ template <int N, int NW>
 static hipError_t fine2d(const WorkItem* items, int n_items, const InstDev* inst,
                          const double* Tg, const double* U_in, double* F_out,
                          const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
-                         hipStream_t s) {
+                         hipStream_t s, int j_steps = 0) {
   const size_t lds = (size_t)(Geo<N, NW>::XSZ + Geo<N, NW>::P2) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fine_linear_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items, inst,
-                     Tg, U_in, F_out, mask, active, kmin, in_iter);
+                     Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps);
   return hipGetLastError();
 }
 
@@ -1832,16 +1833,31 @@ static hipError_t fine_stream(const WorkItem* items, int n_items, const InstDev*
   return hipGetLastError();
 }
 
+// Tunable variants of the on-chip linear fine kernel: waves per workgroup.
+int fine_wave_options(int n, int* out) {
+  switch (n) {
+    case 32: out[0] = 2; out[1] = 1; return 2;
+    case 64: out[0] = 4; out[1] = 2; out[2] = 8; return 3;
+    case 128: out[0] = 8; out[1] = 16; return 2;
+    default: out[0] = 8; return 1;
+  }
+}
+
 hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* Tg, const double* U_in, double* F_out,
                           const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
-                          hipStream_t s) {
+                          hipStream_t s, int waves, int j_steps) {
   if (n_items <= 0) return hipSuccess;
-  switch (n) {
-    case 256: return fine_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
-    case 32: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
-    case 64: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
-    case 128: return fine2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+  const int key = n * 100 + waves;
+  switch (key) {
+    case 25608: case 25600: return fine_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 3202: case 3200: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
+    case 3201: return fine2d<32, 1>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
+    case 6404: case 6400: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
+    case 6402: return fine2d<64, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
+    case 6408: return fine2d<64, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
+    case 12808: case 12800: return fine2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
+    case 12816: return fine2d<128, 16>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
     default: return hipErrorInvalidValue;
   }
 }

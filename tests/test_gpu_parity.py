@@ -356,3 +356,23 @@ def test_streamed_256_parareal_iterates_match_oracle():
         U = gu.unpack_iter(ctx, st["U"])[0]
         for j in range(N + 1):
             assert gu.rel(U[j], ref["U"][k][j]) < TOL, (k, j)
+
+
+def test_batched_256_instances_sampled_against_oracle():
+    # the full 256-instance batch in one fine-sweep call (the benchmark's
+    # launch shape); sampled slices of two instances against the oracle
+    from paper_2304_14074_amd import chlib
+    probs = workloads.batched_instances(256, 4)
+    ctx = chlib.Context(probs)
+    rng = np.random.default_rng(77)
+    states = [0.05 * rng.uniform(-1, 1, (p.n_slices, p.n, p.n)) for p in probs]
+    print("batched fine sweep of 256 instances", flush=True)
+    outs = gu.fine(ctx, states)
+    checked = 0
+    for i, p in enumerate(probs):
+        if p.n in (64, 128) and checked < 2 and p.n == (64 if checked == 0 else 128):
+            ref = propagators.fine(p, states[i][1])
+            assert gu.rel(outs[i][1], ref) < TOL, (i, gu.rel(outs[i][1], ref))
+            checked += 1
+    assert checked == 2
+    assert all(np.all(np.isfinite(o)) for o in outs)
