@@ -19,12 +19,18 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fine grid-point-steps/s; Parareal time-to-1e-8 (neural G vs plain G), 1 GPU"
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
+# HBM bytes of one fine-sweep launch of the 128x128 workload, from FETCH_SIZE and
+# WRITE_SIZE counter runs calibrated by a 1 GiB copy, for the kernel as it is now;
+# set to None whenever the fine kernel changes until the counters are taken again.
+FINE_LAUNCH_TRAFFIC_BYTES = 19167.5 * 1024
 
 
 def fine_flops_per_point_step(n: int) -> float:
@@ -135,6 +141,8 @@ def main():
     ap.add_argument("--nn-traj", type=int, default=256)
     ap.add_argument("--nn-steps", type=int, default=3000)
     ap.add_argument("--workload", default="linear_2d_128", choices=["linear_2d_128", "batched"])
+    ap.add_argument("--profile-fine", action="store_true",
+                    help="one fine-sweep launch and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -143,8 +151,26 @@ def main():
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)))
         return
+    if args.profile_fine:
+        # one fine-sweep launch of the workload plus a plain 1 GiB device copy
+        # (the copy calibrates byte counters: it moves 1 GiB in and 1 GiB out)
+        import torch
+        import workloads
+        from paper_2304_14074_amd import chlib
+        prob = workloads.linear_2d_128()
+        ctx = chlib.Context([prob])
+        u0 = torch.from_numpy(np.stack([workloads.u0_uniform(prob.n, 2, 0.05, i)
+                                        for i in range(prob.n_slices)]).reshape(-1)).cuda()
+        F = torch.empty_like(u0)
+        ctx.ch_fine_propagate(u0, F)
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"fine_launch_in_bytes": u0.numel() * 8, "fine_launch_out_bytes": F.numel() * 8,
+                          "copy_bytes_each_way": a.numel() * 8}))
+        return
 
-    import numpy as np
     import torch
 
     import workloads
@@ -295,8 +321,9 @@ def main():
                                   "over all slices per step",
                       "n": n, "slices": N, "fine_steps": J, "precision": "fp64"},
            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                        "kernel": "k_fine_linear_2d<128,4> (fine sweep, all slices)"},
+                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                        "traffic": FINE_LAUNCH_TRAFFIC_BYTES,
+                        "kernel": "k_fine_linear_2d<128,8> (fine sweep, all 64 slices)"},
            "extra": extra}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, u0)

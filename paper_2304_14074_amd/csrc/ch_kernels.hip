@@ -421,6 +421,96 @@ constexpr int CG_CHUNK = 8;
 // is not finite.  The result is left in cx.
 template <int N, int NW>
 __device__ int spectral_cg(double* X, double* red, const double* T, const SineWalk& sw,
+                           const Lane<N, NW>& L, const OVec& cx, const OVec& cr_unused,
+                           const OVec& cp_unused, const OVec& cq, const OVec& cm,
+                           const OVec& cd, double tau, double cshift, double rtol, int maxit,
+                           const double (&b)[Geo<N, NW>::OWN]) {
+  // The direction p and the residual r stay in registers (owned values);
+  // x, M^{-1}, d and q are read through buffer descriptors.
+  using G = Geo<N, NW>;
+  const int vo = threadIdx.x * 8;
+  double y[G::OWN], pv[G::OWN], rv[G::OWN];
+  double acc[2] = {0.0, 0.0};
+  {
+    double dv[G::OWN];
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) dv[s] = cd.ld(s * G::NT, vo);
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      const int o = s * G::NT;
+      const double mi = 1.0 / (dv[s] + tau * cshift);
+      cm.st(o, vo, mi);
+      cx.st(o, vo, 0.0);
+      rv[s] = b[s];
+      pv[s] = b[s] * mi;
+      acc[0] += b[s] * pv[s];
+      acc[1] += b[s] * b[s];
+    }
+  }
+  block_sum<NW, 2>(acc, red);
+  double rz = acc[0];
+  const double bb = acc[1];
+  if (!(bb > 0.0)) return 0;
+  const double stop2 = rtol * rtol * bb;
+  for (int it = 1; it <= maxit; ++it) {
+    __syncthreads();
+    store_owned<N, NW>(X, L, pv);  // X = p (spectral, owned orientation)
+    __syncthreads();
+    // K p = d p + tau S (q . S p S) S
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) y[s] *= cq.ld(s * G::NT, vo);
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);
+    __syncthreads();
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);
+    double a1[1] = {0.0};
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      const double kp = cd.ld(s * G::NT, vo) * pv[s] + tau * y[s];
+      y[s] = kp;
+      a1[0] += pv[s] * kp;
+    }
+    block_sum<NW, 1>(a1, red);
+    const double alpha = rz / a1[0];
+    double a2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s0 = 0; s0 < G::OWN; s0 += CG_CHUNK) {
+      double xv[CG_CHUNK], mv[CG_CHUNK];
+#pragma unroll
+      for (int c = 0; c < CG_CHUNK; ++c) {
+        xv[c] = cx.ld((s0 + c) * G::NT, vo);
+        mv[c] = cm.ld((s0 + c) * G::NT, vo);
+      }
+#pragma unroll
+      for (int c = 0; c < CG_CHUNK; ++c) {
+        const int s = s0 + c;
+        xv[c] += alpha * pv[s];
+        rv[s] -= alpha * y[s];
+        const double z = rv[s] * mv[c];
+        a2[0] += rv[s] * rv[s];
+        a2[1] += rv[s] * z;
+        y[s] = z;
+      }
+#pragma unroll
+      for (int c = 0; c < CG_CHUNK; ++c) cx.st((s0 + c) * G::NT, vo, xv[c]);
+    }
+    block_sum<NW, 2>(a2, red);
+    if (a2[0] <= stop2) return it;
+    if (!(a2[0] == a2[0])) return -1;
+    const double beta = a2[1] / rz;
+    rz = a2[1];
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) pv[s] = y[s] + beta * pv[s];
+  }
+  return -1;
+}
+
+// Variant with every CG vector in memory (lower register use).
+template <int N, int NW>
+__device__ int spectral_cg_mem(double* X, double* red, const double* T, const SineWalk& sw,
                            const Lane<N, NW>& L, const OVec& cx, const OVec& cr, const OVec& cp,
                            const OVec& cq, const OVec& cm, const OVec& cd, double tau,
                            double cshift, double rtol, int maxit,
@@ -657,8 +747,8 @@ __device__ bool newton_step(double* X, double* red, const double* T, const SineW
       else g = d * yh + tau * y[s] - (im + tau) * uh;
       b[s] = -g;
     }
-    const int its = spectral_cg<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, W.d_fine, tau,
-                                       cshift, P.nl_krylov_rtol, P.krylov_max, b);
+    const int its = spectral_cg_mem<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, W.d_fine,
+                                           tau, cshift, P.nl_krylov_rtol, P.krylov_max, b);
     if (its < 0) ok = false;
     double a[1] = {0.0};
 #pragma unroll
