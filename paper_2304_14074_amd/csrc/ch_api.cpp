@@ -153,8 +153,6 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
                  "instance %d: split-bf16 covers the 2D linear step with n = 64, 128", i);
     else if (p.dim == 2 && !supported_2d(p.n))
       bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 2D n = %d (kernels cover 32, 64, 128, 256)", i, p.n);
-    else if (p.dim == 2 && p.n == 256 && p.fine_kind == CH_FINE_NONLINEAR)
-      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: the implicit fine step covers n <= 128", i);
     else if (p.dim == 1 && (p.n > 128 || p.n % 2))
       bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 1D n = %d (even n <= 128)", i, p.n);
     if (bad != CH_OK) {
@@ -185,6 +183,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     d.eps = p.eps; d.dT = p.T / p.n_slices; d.dt = d.dT / p.j_fine; d.s_fine = p.s_fine;
     d.h = 1.0 / (p.n + 1); d.newton_tol = p.newton_tol; d.krylov_rtol = p.krylov_rtol;
     d.nl_krylov_rtol = p.nl_krylov_rtol;
+    d.work_vecs = (p.dim == 2 && p.n == 256 && p.fine_kind == CH_FINE_NONLINEAR) ? 9 : chk::WORK_VECS;
     d.off_slices = so; d.off_iter = io; d.slice_base = slice_base;
     so += (int64_t)p.n_slices * P;
     io += (int64_t)(p.n_slices + 1) * P;
@@ -238,7 +237,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     const size_t P = probs[i].dim == 2 ? (size_t)probs[i].n * probs[i].n : probs[i].n;
     if (probs[i].dim == 2) {
       c->tab_blk[i] = take(sizeof(double) * P * chk::TAB_VECS);
-      c->work_blk[i] = take(sizeof(double) * P * chk::WORK_VECS * (size_t)probs[i].n_slices);
+      c->work_blk[i] = take(sizeof(double) * P * (size_t)c->inst[i].work_vecs * (size_t)probs[i].n_slices);
     }
   }
   // learned coarse propagator workspace: activations for a batch of all

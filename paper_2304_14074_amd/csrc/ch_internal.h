@@ -24,9 +24,11 @@ struct InstDev {
   double* work;              // 2D: per slice WORK_VECS * n^2 solver vectors
   int32_t* status;           // solver flags raised by fine/parallel-coarse kernels
   double nl_krylov_rtol;     // CG target inside Newton
+  int32_t work_vecs;         // solver vectors per slice in `work`
+  int32_t pad2;
 };
 constexpr int TAB_VECS = 4;   // d(coarse), 1/mu + tau(coarse), d(fine), 1/mu
-constexpr int WORK_VECS = 7;  // x, r, p, q, minv, u_hat, y_hat
+constexpr int WORK_VECS = 7;  // x, r, p, q, minv, u_hat, y_hat (streamed Newton: 9)
 
 struct WorkItem { int32_t inst, slice; };
 

@@ -627,7 +627,7 @@ struct Work {
 };
 __device__ __forceinline__ Work work_vectors(const InstDev& P, int slice) {
   const int64_t NN = (int64_t)P.n * P.n;
-  double* w = P.work + (int64_t)slice * WORK_VECS * NN;
+  double* w = P.work + (int64_t)slice * P.work_vecs * NN;
   Work W;
   W.x = OVec(w, NN);
   W.r = OVec(w + NN, NN);
@@ -1106,7 +1106,7 @@ k_fine_linear_stream(const WorkItem* __restrict__ items, const InstDev* __restri
   const int64_t NN = (int64_t)N * N;
   const int64_t off = P.off_slices + (int64_t)it.slice * NN;
   const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
-  double* b0 = P.work + (int64_t)it.slice * WORK_VECS * NN;
+  double* b0 = P.work + (int64_t)it.slice * P.work_vecs * NN;
   double* b1 = b0 + NN;
   for (int m = threadIdx.x; m < G::P2; m += G::NT) T[m] = Tg[m];
   for (int idx = threadIdx.x; idx < NN; idx += G::NT) b0[idx] = U_in[off_in + idx];
@@ -1120,9 +1120,63 @@ k_fine_linear_stream(const WorkItem* __restrict__ items, const InstDev* __restri
 template <int NW, int K>
 __device__ __forceinline__ void wg_sum(double (&v)[K], double* red) { block_sum<NW, K>(v, red); }
 
-// Scheme (2.4) on the streamed state in b0 (global), result in b0.  Same
-// spectral CG as the on-chip variant; vectors in natural [row][col] order,
-// tables d (coarse tau) and 1/mu + tau in P.tab (natural order for n = 256).
+// Streamed spectral CG for diag(d) + tau S diag(q) S (see spectral_cg): the
+// right-hand side is in cr on entry (natural order), the solution is left in
+// cx.  b0, b1 are transform scratch.  Returns iterations or -1.
+template <int N, int NW>
+__device__ int stream_spectral_cg(double* b0, double* b1, double* cx, double* cr, double* cp,
+                                  const double* cq, double* cm, const double* cd, double tau,
+                                  double cshift, double rtol, int maxit, double* Lc,
+                                  const double* T, double* red) {
+  const int NN = N * N, NT = NW * 64, t = threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  for (int i = t; i < NN; i += NT) {
+    const double b = cr[i];
+    const double mi = 1.0 / (cd[i] + tau * cshift);
+    cm[i] = mi;
+    cx[i] = 0.0;
+    cp[i] = b * mi;
+    acc[0] += b * b * mi;
+    acc[1] += b * b;
+  }
+  wg_sum<NW, 2>(acc, red);
+  double rz = acc[0];
+  const double stop2 = rtol * rtol * acc[1];
+  if (!(acc[1] > 0.0)) return 0;
+  for (int it = 1; it <= maxit; ++it) {
+    stream_stage<N, NW>(cp, b0, nullptr, Lc, T);
+    stream_stage<N, NW>(b0, b1, cq, Lc, T);       // q . (S p S)
+    stream_stage<N, NW>(b1, b0, nullptr, Lc, T);
+    stream_stage<N, NW>(b0, b1, nullptr, Lc, T);  // b1 = S (q . S p S) S
+    double a1[1] = {0.0};
+    for (int i = t; i < NN; i += NT) {
+      const double kp = cd[i] * cp[i] + tau * b1[i];
+      b1[i] = kp;
+      a1[0] += cp[i] * kp;
+    }
+    wg_sum<NW, 1>(a1, red);
+    const double alpha = rz / a1[0];
+    double a2[2] = {0.0, 0.0};
+    for (int i = t; i < NN; i += NT) {
+      cx[i] += alpha * cp[i];
+      const double r = cr[i] - alpha * b1[i];
+      cr[i] = r;
+      a2[0] += r * r;
+      a2[1] += r * (r * cm[i]);
+    }
+    wg_sum<NW, 2>(a2, red);
+    if (a2[0] <= stop2) return it;
+    if (!(a2[0] == a2[0])) return -1;
+    const double beta = a2[1] / rz;
+    rz = a2[1];
+    for (int i = t; i < NN; i += NT) cp[i] = cr[i] * cm[i] + beta * cp[i];
+    __syncthreads();
+  }
+  return -1;
+}
+
+// Scheme (2.4) on the streamed state in b0 (global), result in b0.  Tables
+// d (coarse tau) and 1/mu + tau in P.tab (natural order for n = 256).
 template <int N, int NW>
 __device__ void stream_approx2(double* b0, double* b1, double* cx, double* cr, double* cp,
                                double* cq, double* cm, double* Lc, const double* T, double* red,
@@ -1143,54 +1197,108 @@ __device__ void stream_approx2(double* b0, double* b1, double* cx, double* cr, d
     const double cshift = 0.5 * (mn + mx);
     stream_stage<N, NW>(b0, b1, nullptr, Lc, T);
     stream_stage<N, NW>(b1, b0, nullptr, Lc, T);   // b0 = u_hat
-    double acc[2] = {0.0, 0.0};
-    for (int i = t; i < NN; i += NT) {
-      const double b = (P.f_zero ? cb[i] - tau : cb[i]) * b0[i];
-      const double mi = 1.0 / (cd[i] + tau * cshift);
-      cm[i] = mi;
-      cx[i] = 0.0;
-      cr[i] = b;
-      cp[i] = b * mi;
-      acc[0] += b * b * mi;
-      acc[1] += b * b;
-    }
-    wg_sum<NW, 2>(acc, red);
-    double rz = acc[0];
-    const double stop2 = P.krylov_rtol * P.krylov_rtol * acc[1];
-    bool ok = !(acc[1] > 0.0);
-    for (int it = 1; !ok && it <= P.krylov_max; ++it) {
-      stream_stage<N, NW>(cp, b0, nullptr, Lc, T);
-      stream_stage<N, NW>(b0, b1, cq, Lc, T);       // q . (S p S)
-      stream_stage<N, NW>(b1, b0, nullptr, Lc, T);
-      stream_stage<N, NW>(b0, b1, nullptr, Lc, T);  // b1 = S (q . S p S) S
-      double a1[1] = {0.0};
-      for (int i = t; i < NN; i += NT) {
-        const double kp = cd[i] * cp[i] + tau * b1[i];
-        b1[i] = kp;
-        a1[0] += cp[i] * kp;
-      }
-      wg_sum<NW, 1>(a1, red);
-      const double alpha = rz / a1[0];
-      double a2[2] = {0.0, 0.0};
-      for (int i = t; i < NN; i += NT) {
-        cx[i] += alpha * cp[i];
-        const double r = cr[i] - alpha * b1[i];
-        cr[i] = r;
-        a2[0] += r * r;
-        a2[1] += r * (r * cm[i]);
-      }
-      wg_sum<NW, 2>(a2, red);
-      if (a2[0] <= stop2) { ok = true; break; }
-      if (!(a2[0] == a2[0])) break;
-      const double beta = a2[1] / rz;
-      rz = a2[1];
-      for (int i = t; i < NN; i += NT) cp[i] = cr[i] * cm[i] + beta * cp[i];
-      __syncthreads();
-    }
-    if (!ok) status |= 1;
+    for (int i = t; i < NN; i += NT) cr[i] = (P.f_zero ? cb[i] - tau : cb[i]) * b0[i];
+    __syncthreads();
+    const int its = stream_spectral_cg<N, NW>(b0, b1, cx, cr, cp, cq, cm, cd, tau, cshift,
+                                              P.krylov_rtol, P.krylov_max, Lc, T, red);
+    if (its < 0) status |= 1;
     stream_stage<N, NW>(cx, b1, nullptr, Lc, T);
     stream_stage<N, NW>(b1, b0, nullptr, Lc, T);   // b0 = v
   }
+}
+
+// Implicit fine step (see newton_step) on streamed vectors: the state is
+// carried in sine coordinates (uh, yh, natural order).
+template <int N, int NW>
+__device__ bool stream_newton_step(double* b0, double* b1, double* cx, double* cr, double* cp,
+                                   double* cq, double* cm, double* uh, double* yh, double* Lc,
+                                   const double* T, double* red, const InstDev& P) {
+  const int NN = N * N, NT = NW * 64, t = threadIdx.x;
+  const double* cd = P.tab + 2 * NN;
+  const double* imu = P.tab + 3 * NN;
+  const double tau = P.dt;
+  const bool be = P.nl_variant == 1;
+  bool ok = true;
+  for (int it = 0; it < P.newton_max; ++it) {
+    stream_stage<N, NW>(yh, b1, nullptr, Lc, T);
+    stream_stage<N, NW>(b1, b0, nullptr, Lc, T);   // b0 = Y (state)
+    double mn = 1e300, mx = -1e300;
+    for (int i = t; i < NN; i += NT) {
+      const double y = b0[i];
+      const double q = P.f_zero ? 0.0 : 3.0 * y * y + (be ? -1.0 : 0.0);
+      cq[i] = q;
+      b1[i] = P.f_zero ? 0.0 : y * y * y;
+      mn = fmin(mn, q);
+      mx = fmax(mx, q);
+    }
+    block_minmax<NW>(mn, mx, red);
+    const double cshift = 0.5 * (mn + mx);
+    stream_stage<N, NW>(b1, b0, nullptr, Lc, T);
+    stream_stage<N, NW>(b0, b1, nullptr, Lc, T);   // b1 = S Y^3 S
+    for (int i = t; i < NN; i += NT) {
+      double g;
+      if (P.f_zero) g = cd[i] * yh[i] - imu[i] * uh[i];
+      else if (be) g = cd[i] * yh[i] + tau * b1[i] - tau * yh[i] - imu[i] * uh[i];
+      else g = cd[i] * yh[i] + tau * b1[i] - (imu[i] + tau) * uh[i];
+      cr[i] = -g;
+    }
+    __syncthreads();
+    const int its = stream_spectral_cg<N, NW>(b0, b1, cx, cr, cp, cq, cm, cd, tau, cshift,
+                                              P.nl_krylov_rtol, P.krylov_max, Lc, T, red);
+    if (its < 0) ok = false;
+    double a[1] = {0.0};
+    for (int i = t; i < NN; i += NT) {
+      yh[i] += cx[i];
+      a[0] += cx[i] * cx[i];
+    }
+    wg_sum<NW, 1>(a, red);
+    const double step = sqrt(P.h * P.h * a[0]);
+    if (step <= P.newton_tol) return ok;
+    if (!(step == step)) return false;
+  }
+  return false;
+}
+
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_newton_stream(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                     const double* __restrict__ Tg, const double* __restrict__ U_in,
+                     double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                     const int32_t* __restrict__ active, const int32_t* __restrict__ kmin,
+                     int in_iter) {
+  using G = GeoS<N, NW>;
+  extern __shared__ double smem[];
+  double* Lc = smem;
+  double* T = smem + 2 * G::CHUNK;
+  double* red = T + G::P2;
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
+  double* w = P.work + (int64_t)it.slice * P.work_vecs * NN;
+  double *b0 = w, *b1 = w + NN, *cx = w + 2 * NN, *cr = w + 3 * NN, *cp = w + 4 * NN;
+  double *cq = w + 5 * NN, *cm = w + 6 * NN, *uh = w + 7 * NN, *yh = w + 8 * NN;
+  const int t = threadIdx.x;
+  for (int m = t; m < G::P2; m += G::NT) T[m] = Tg[m];
+  for (int64_t i = t; i < NN; i += G::NT) b0[i] = U_in[off_in + i];
+  __syncthreads();
+  stream_stage<N, NW>(b0, b1, nullptr, Lc, T);
+  stream_stage<N, NW>(b1, uh, nullptr, Lc, T);   // u_hat
+  for (int64_t i = t; i < NN; i += G::NT) yh[i] = uh[i];
+  __syncthreads();
+  bool ok = true;
+  for (int m = 0; m < P.j_fine; ++m) {
+    ok = stream_newton_step<N, NW>(b0, b1, cx, cr, cp, cq, cm, uh, yh, Lc, T, red, P) && ok;
+    for (int64_t i = t; i < NN; i += G::NT) uh[i] = yh[i];
+    __syncthreads();
+  }
+  stream_stage<N, NW>(uh, b1, nullptr, Lc, T);
+  stream_stage<N, NW>(b1, b0, nullptr, Lc, T);
+  for (int64_t i = t; i < NN; i += G::NT) F_out[off + i] = b0[i];
+  if (!ok && t == 0) atomicOr(P.status, 1);
 }
 
 template <int N, int NW>
@@ -1232,7 +1340,7 @@ k_coarse_stream(int mode, const int32_t* __restrict__ insts, const WorkItem* __r
     const InstDev P = inst[it.inst];
     if (mask && !mask[P.slice_base + it.slice]) return;
     if (P.coarse_kind == 2) return;
-    double* w = P.work + (int64_t)it.slice * WORK_VECS * NN;
+    double* w = P.work + (int64_t)it.slice * P.work_vecs * NN;
     const int64_t off = P.off_slices + (int64_t)it.slice * NN;
     for (int64_t i = t; i < NN; i += G::NT) w[i] = U_in[off + i];
     __syncthreads();
@@ -1966,12 +2074,28 @@ static hipError_t newton2d(const WorkItem* items, int n_items, const InstDev* in
   return hipGetLastError();
 }
 
+template <int N, int NW>
+static hipError_t newton_stream(const WorkItem* items, int n_items, const InstDev* inst,
+                                const double* Tg, const double* U_in, double* F_out,
+                                const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                                int in_iter, hipStream_t s) {
+  const size_t lds =
+      ((size_t)2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2 + 4 * NW) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_newton_stream<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fine_newton_stream<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items,
+                     inst, Tg, U_in, F_out, mask, active, kmin, in_iter);
+  return hipGetLastError();
+}
+
 hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                  const double* Tg, const double* U_in, double* F_out,
                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                                  int in_iter, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (n) {
+    case 256: return newton_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
     case 32: return newton2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
     case 64: return newton2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
     case 128: return newton2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);

@@ -376,3 +376,33 @@ def test_batched_256_instances_sampled_against_oracle():
             checked += 1
     assert checked == 2
     assert all(np.all(np.isfinite(o)) for o in outs)
+
+
+def test_streamed_256_nonlinear_step_full_size_parameters():
+    # the 256x256, eps=0.015, dt=1e-5 implicit step: one step against the oracle
+    from paper_2304_14074_amd import chlib
+    base = workloads.nonlinear_2d_256()
+    p = workloads.Problem(dim=2, n=256, eps=base.eps, T=2 * base.dt, n_slices=2, j_fine=1,
+                          fine_kind="nonlinear")
+    ctx = chlib.Context([p])
+    X = np.stack([workloads.nonlinear_2d_256_u0(0), workloads.u0_uniform(256, 2, 0.9, 5)])
+    print("nonlinear 256 single step", flush=True)
+    out = gu.fine(ctx, [X])[0]
+    for s in range(2):
+        ref = propagators.fine(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+def test_streamed_256_nonlinear_energy_decays():
+    # scheme (2.3) is unconditionally gradient stable: the discrete energy of
+    # the 256x256 run cannot increase (property at the full size)
+    from paper_2304_14074_amd import chlib
+    base = workloads.nonlinear_2d_256()
+    J = 200
+    p = workloads.Problem(dim=2, n=256, eps=base.eps, T=J * base.dt, n_slices=1, j_fine=J,
+                          fine_kind="nonlinear")
+    ctx = chlib.Context([p])
+    u0 = workloads.u0_uniform(256, 2, 0.5, 6)
+    out = gu.fine(ctx, [u0[None]])[0][0]
+    e0, e1 = o_energy.energy(u0, p.eps), o_energy.energy(out, p.eps)
+    assert np.all(np.isfinite(out)) and e1 < e0
