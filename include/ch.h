@@ -140,6 +140,15 @@ ch_status ch_autotune(ch_ctx* ctx, const double* U_in, double* F_out, int32_t st
  * kernel for grid size n (e.g. from a cached tuning result). */
 ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
 
+/* Query (set = 0) or set (set = 1) how many workgroups run each instance's
+ * sequential coarse sweep of (2.2) for the 2D grid-size class n: 1 (one
+ * workgroup per instance) or 4 (the 2D sine transforms of every solve of
+ * (2.4) split over four workgroups that meet at device-memory barriers;
+ * n = 128, at most 64 instances in the class, the default where available).
+ * Both give the same iterates to rounding.  Instances with the stabilised
+ * coarse step always use one workgroup. */
+ch_status ch_chain_variant(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set);
+
 /* hipGraph of one Parareal iteration (after the prediction): captured on
  * the non-default `stream`, replayable with ch_graph_launch; each replay
  * performs the next iteration (the iteration index lives in device memory).

@@ -36,6 +36,8 @@ struct ClassPlan {      // all instances sharing (dim, n, fine kind, precision)
   std::vector<int32_t> insts;    // instance indices
   Block items_blk, insts_blk;
   Block sine_blk;                // 2D: Se | So | lam ; 1D: S | lam
+  int chain_groups = 1;          // workgroups per instance in the coarse chain
+  Block sync_blk;                // barrier words of the multi-workgroup chain
 };
 
 }  // namespace
@@ -233,6 +235,12 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     c->rsig_stab_blk[i] = take(sizeof(double) * P);
   }
   c->host_init_bytes = off;
+  for (auto& cp : c->classes) {
+    if (cp.dim != 2) continue;
+    const int cap = chk::chain_coop_capacity(cp.n);
+    if (cap > 0 && (int)cp.insts.size() <= cap) cp.chain_groups = 4;
+    cp.sync_blk = take(sizeof(int32_t) * 64 * 8 * ((cp.insts.size() + 7) / 8));
+  }
   for (int i = 0; i < n_inst; ++i) {
     const size_t P = probs[i].dim == 2 ? (size_t)probs[i].n * probs[i].n : probs[i].n;
     if (probs[i].dim == 2) {
@@ -423,7 +431,13 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     double* delta = st ? st->delta : nullptr;
     int32_t* status = st ? st->status : nullptr;
     hipError_t e;
-    if (cp.dim == 2) {
+    bool coop = cp.dim == 2 && mode != 0 && cp.chain_groups > 1;
+    for (int32_t i : cp.insts) coop = coop && c->inst[i].coarse_kind != CH_COARSE_STAB;
+    if (coop) {
+      e = chk::launch_chain_coop(cp.n, mode, insts, (int)cp.insts.size(), inst, tab, U, F, Gold,
+                                 delta, status, active, k, kdev,
+                                 (int32_t*)(c->ws + cp.sync_blk.off), s);
+    } else if (cp.dim == 2) {
       e = chk::launch_coarse_2d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
                                 inst, tab, U_in, G_out, mask, U, F, Gold, delta, status,
                                 active, k, kdev, s);
@@ -618,6 +632,27 @@ ch_status ch_fine_variant(ch_ctx* c, int32_t n, int32_t* waves, int32_t set) {
     }
   }
   return found ? CH_OK : fail(c, CH_ERR_ARG, "no tunable class with n = %d", n);
+}
+
+ch_status ch_chain_variant(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {
+  if (!c || !groups) return CH_ERR_ARG;
+  bool found = false;
+  for (auto& cp : c->classes) {
+    if (cp.dim != 2 || cp.n != n) continue;
+    found = true;
+    if (set) {
+      if (*groups != 1 && *groups != 4)
+        return fail(c, CH_ERR_ARG, "chain groups must be 1 or 4, got %d", *groups);
+      const int cap = chk::chain_coop_capacity(n);
+      if (*groups == 4 && (cap == 0 || (int)cp.insts.size() > cap))
+        return fail(c, CH_ERR_UNSUPPORTED, "no multi-workgroup chain for n = %d with %zu instances",
+                    n, cp.insts.size());
+      cp.chain_groups = *groups;
+    } else {
+      *groups = cp.chain_groups;
+    }
+  }
+  return found ? CH_OK : fail(c, CH_ERR_ARG, "no 2D class with n = %d", n);
 }
 
 ch_status ch_parareal_graph_create(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream,

@@ -69,6 +69,13 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
                             const uint8_t* mask, double* U, const double* F, double* G_old,
                             double* delta, int32_t* status, const int32_t* active, int k,
                             const int32_t* kdev, hipStream_t s);
+// Coarse chain (modes 1, 2) on a group of workgroups per instance (2D n = 128,
+// scheme (2.4)); sync: 512 ints per 8 instances (cleared by the launch).
+int chain_coop_capacity(int n);
+hipError_t launch_chain_coop(int n, int mode, const int32_t* insts, int n_insts,
+                             const InstDev* inst, const double* Tsin, double* U, const double* F,
+                             double* G_old, double* delta, int32_t* status, const int32_t* active,
+                             int k, const int32_t* kdev, int32_t* sync, hipStream_t s);
 // Fill the per-instance CG tables (d and b-scale in the owned layout).
 hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts,
                             const InstDev* inst, const double* lam, hipStream_t s);

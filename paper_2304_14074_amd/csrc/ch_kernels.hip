@@ -966,6 +966,420 @@ k_cg_tables_2d(const int32_t* __restrict__ insts, const InstDev* __restrict__ in
   }
 }
 
+// ------------------------------------------- cooperative coarse chain
+// The coarse sweep is sequential over slices, so one instance's chain runs
+// on a group of G workgroups (same XCD: member m of group x is workgroup
+// x + 8 m under round-robin dispatch) that split every 2D transform.  A
+// "slab stage" multiplies S by an N x B block held in LDS (B = N/G).  A 2D
+// transform alternates a left product (column-local: block of columns of X)
+// and a right product (row-local: the transposed block of rows), so one
+// operator application S diag(q) S ... S needs two transposing exchanges
+// through global memory per CG iteration; every CG vector of a group member
+// is a block of N x B values held in registers.
+template <int N, int G, int NW>
+struct GeoC {
+  static constexpr int B = N / G, H = N / 2, TR = H / 16, TCB = B / 16;
+  static constexpr int WPR = NW / TR, CPW = TCB / WPR, KS = H / 4;
+  static constexpr int LDB = B + 1;            // slab row stride (odd)
+  static constexpr int NT = NW * 64, OWN = 8 * CPW, P2 = 2 * (N + 1);
+  static_assert(NW % TR == 0 && TCB % WPR == 0 && CPW >= 1, "wave tiling");
+  static_assert(OWN * NT == N * B, "ownership");
+};
+
+// Owned slot s of a slab-stage output: row a' (0..N-1), slab column c (0..B-1).
+template <int N, int G, int NW>
+__device__ __forceinline__ void slab_rc(int s, int& row, int& col) {
+  using C = GeoC<N, G, NW>;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int g = l >> 4, j = l & 15, tr = w / C::WPR, c0 = (w % C::WPR) * C::CPW;
+  const int qr = s >> 1, half = s & 1, q = qr >> 2, r = qr & 3;
+  const int a = 16 * tr + g + 4 * r;
+  row = half ? (N - 1 - a) : a;
+  col = 16 * (c0 + q) + j;
+}
+
+// y = S * slab (N x B in LDS), folded; owned results in y.
+template <int N, int G, int NW>
+__device__ __forceinline__ void slab_stage(const double* Xs, const double* T,
+                                           double (&y)[GeoC<N, G, NW>::OWN]) {
+  using C = GeoC<N, G, NW>;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int g = l >> 4, j = l & 15, tr = w / C::WPR, c0 = (w % C::WPR) * C::CPW;
+  d4 aE[C::CPW], aO[C::CPW];
+#pragma unroll
+  for (int q = 0; q < C::CPW; ++q) {
+    aE[q] = d4{0.0, 0.0, 0.0, 0.0};
+    aO[q] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int a1 = 16 * tr + j + 1;
+  int ie = (a1 * (2 * g + 1)) % C::P2, io = (a1 * (2 * g + 2)) % C::P2;
+  const int step = (8 * a1) % C::P2;
+  const double* base = Xs + (2 * g) * C::LDB + 16 * c0 + j;
+#pragma unroll 4
+  for (int ks = 0; ks < C::KS; ++ks) {
+    const double se = T[ie], so = T[io];
+    ie += step; ie -= (ie >= C::P2) ? C::P2 : 0;
+    io += step; io -= (io >= C::P2) ? C::P2 : 0;
+    const double* pe = base + (8 * ks) * C::LDB;
+#pragma unroll
+    for (int q = 0; q < C::CPW; ++q) {
+      aE[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(se, pe[16 * q], aE[q], 0, 0, 0);
+      aO[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(so, pe[C::LDB + 16 * q], aO[q], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < C::CPW; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      y[(q * 4 + r) * 2 + 0] = aE[q][r] + aO[q][r];
+      y[(q * 4 + r) * 2 + 1] = aE[q][r] - aO[q][r];
+    }
+}
+
+template <int N, int G, int NW>
+__device__ __forceinline__ void slab_put(double* Xs, const double (&v)[GeoC<N, G, NW>::OWN]) {
+  using C = GeoC<N, G, NW>;
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    Xs[row * C::LDB + col] = v[s];
+  }
+}
+
+// State of one group member: barrier words, exchange buffers, partial sums.
+// Consecutive exchanges (and consecutive reductions) alternate between two
+// buffers, so a buffer is rewritten only after a later barrier has shown
+// that every member finished reading it; one barrier per exchange suffices.
+struct CoopCtx {
+  int32_t *cnt, *gen;
+  double* xg;       // two exchange matrices N x N (natural order)
+  double* part;     // two slots of 8 x 8 partial sums
+  int G, mem, ok, xsel, psel;
+};
+
+// Barrier of the G members of one group.  The spin is bounded by the wall
+// clock (about 0.2 s): on time-out the member clears cc.ok and every later
+// barrier of the launch returns at once, so a lost member can never hang the
+// kernel; the host sees the failure in the status word.
+__device__ __forceinline__ void group_barrier(CoopCtx& cc) {
+  __threadfence();   // every wave: its stores visible device-wide
+  __syncthreads();
+  __shared__ int ok_s;
+  if (threadIdx.x == 0) {
+    int ok = cc.ok;
+    if (ok) {
+      const int g0 = __hip_atomic_load(cc.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const int arrived =
+          __hip_atomic_fetch_add(cc.cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived == cc.G - 1) {
+        __hip_atomic_store(cc.cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(cc.gen, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(cc.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+          if (wall_clock64() - t0 > 20000000ull) { ok = 0; break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __threadfence();
+    }
+    ok_s = ok;
+  }
+  __syncthreads();
+  cc.ok = ok_s;
+}
+
+// Group-wide sum of K values in a fixed order (partials exchanged in memory,
+// summed by every member in member order, so all members agree bitwise).
+template <int NW, int K>
+__device__ __forceinline__ void group_sum(double (&v)[K], double* red, CoopCtx& cc) {
+  block_sum<NW, K>(v, red);
+  double* part = cc.part + 64 * cc.psel;
+  cc.psel ^= 1;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < K; ++i) part[i * 8 + cc.mem] = v[i];
+  group_barrier(cc);
+  for (int i = 0; i < K; ++i) {
+    double s = 0.0;
+    for (int m = 0; m < cc.G; ++m) s += __builtin_nontemporal_load(&part[i * 8 + m]);
+    v[i] = s;
+  }
+}
+template <int NW>
+__device__ __forceinline__ void group_minmax(double& mn, double& mx, double* red, CoopCtx& cc) {
+  block_minmax<NW>(mn, mx, red);
+  double* part = cc.part + 64 * cc.psel;
+  cc.psel ^= 1;
+  if (threadIdx.x == 0) {
+    part[cc.mem] = mn;
+    part[8 + cc.mem] = mx;
+  }
+  group_barrier(cc);
+  double a = 1e300, b = -1e300;
+  for (int m = 0; m < cc.G; ++m) {
+    a = fmin(a, __builtin_nontemporal_load(&part[m]));
+    b = fmax(b, __builtin_nontemporal_load(&part[8 + m]));
+  }
+  mn = a;
+  mx = b;
+}
+
+// Exchange A: from a column block (left-product output v: rows 0..N-1, block
+// columns C_m) to the transposed row block slab[k][r'] = M[R_m[r']][k].
+template <int N, int G, int NW>
+__device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
+                                   CoopCtx& cc) {
+  using C = GeoC<N, G, NW>;
+  double* xg = cc.xg + (int64_t)N * N * cc.xsel;
+  cc.xsel ^= 1;
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    xg[(int64_t)row * N + cc.mem * C::B + col] = v[s];
+  }
+  group_barrier(cc);
+  for (int i = threadIdx.x; i < C::B * N; i += C::NT) {
+    const int rr = i / N, k = i % N;   // coalesced rows of the exchange matrix
+    Xs[k * C::LDB + rr] = __builtin_nontemporal_load(&xg[(int64_t)(cc.mem * C::B + rr) * N + k]);
+  }
+  __syncthreads();
+}
+
+// Exchange B: from a right-product output v (slab form: element (a, c) is
+// M[R_m[c]][a]) to the column block slab[k][c] = M[k][C_m[c]].
+template <int N, int G, int NW>
+__device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
+                                   CoopCtx& cc) {
+  using C = GeoC<N, G, NW>;
+  double* xg = cc.xg + (int64_t)N * N * cc.xsel;
+  cc.xsel ^= 1;
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    xg[(int64_t)(cc.mem * C::B + col) * N + row] = v[s];
+  }
+  group_barrier(cc);
+  for (int i = threadIdx.x; i < N * C::B; i += C::NT) {
+    const int k = i / C::B, c = i % C::B;
+    Xs[k * C::LDB + c] = __builtin_nontemporal_load(&xg[(int64_t)k * N + cc.mem * C::B + c]);
+  }
+  __syncthreads();
+}
+
+// One solve of scheme (2.4) by the group.  On entry u holds the member's row
+// block of the state in slab form (element (a, c) = u[R_m[c]][a]); on exit it
+// holds the result in the same form.
+template <int N, int G, int NW>
+__device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const double* T,
+                             double* red, CoopCtx& cc, const InstDev& P,
+                             const double (&dv)[GeoC<N, G, NW>::OWN],
+                             const double (&bv)[GeoC<N, G, NW>::OWN], int& status) {
+  using C = GeoC<N, G, NW>;
+  const double tau = P.dT / P.m_coarse;
+  double y[C::OWN], q[C::OWN], pv[C::OWN], rv[C::OWN], xv[C::OWN], mv[C::OWN];
+  for (int sub = 0; sub < P.m_coarse; ++sub) {
+    double mn = 1e300, mx = -1e300;
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      q[s] = P.f_zero ? 0.0 : u[s] * u[s];
+      mn = fmin(mn, q[s]);
+      mx = fmax(mx, q[s]);
+    }
+    group_minmax<NW>(mn, mx, red, cc);
+    const double cshift = 0.5 * (mn + mx);
+    // u_hat = S u S: right product on the row block, exchange, left product
+    __syncthreads();
+    slab_put<N, G, NW>(Xs, u);
+    __syncthreads();
+    slab_stage<N, G, NW>(Xs, T, y);
+    xchg_rowsT_to_cols<N, G, NW>(y, Xs, cc);
+    slab_stage<N, G, NW>(Xs, T, y);   // column block of u_hat
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      const double b = (P.f_zero ? bv[s] - tau : bv[s]) * y[s];
+      mv[s] = 1.0 / (dv[s] + tau * cshift);
+      xv[s] = 0.0;
+      rv[s] = b;
+      pv[s] = b * mv[s];
+      acc[0] += b * pv[s];
+      acc[1] += b * b;
+    }
+    group_sum<NW, 2>(acc, red, cc);
+    double rz = acc[0];
+    const double stop2 = P.krylov_rtol * P.krylov_rtol * acc[1];
+    bool done = !(acc[1] > 0.0);
+    for (int it = 1; !done && it <= P.krylov_max; ++it) {
+      // K p = d p + tau S (q . S p S) S
+      __syncthreads();
+      slab_put<N, G, NW>(Xs, pv);
+      __syncthreads();
+      slab_stage<N, G, NW>(Xs, T, y);          // left: S p (column block)
+      xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
+      slab_stage<N, G, NW>(Xs, T, y);          // right: (S p S) row block
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) y[s] *= q[s];
+      __syncthreads();
+      slab_put<N, G, NW>(Xs, y);
+      __syncthreads();
+      slab_stage<N, G, NW>(Xs, T, y);          // right: (q . S p S) S
+      xchg_rowsT_to_cols<N, G, NW>(y, Xs, cc);
+      slab_stage<N, G, NW>(Xs, T, y);          // left: column block
+      double a1[1] = {0.0};
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) {
+        y[s] = dv[s] * pv[s] + tau * y[s];
+        a1[0] += pv[s] * y[s];
+      }
+      group_sum<NW, 1>(a1, red, cc);
+      const double alpha = rz / a1[0];
+      double a2[2] = {0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) {
+        xv[s] += alpha * pv[s];
+        rv[s] -= alpha * y[s];
+        y[s] = rv[s] * mv[s];
+        a2[0] += rv[s] * rv[s];
+        a2[1] += rv[s] * y[s];
+      }
+      group_sum<NW, 2>(a2, red, cc);
+      if (a2[0] <= stop2) { done = true; break; }
+      // a2 is the same in every member; cc.ok drops only on a barrier time-out
+      if (!(a2[0] == a2[0]) || !cc.ok) break;
+      const double beta = a2[1] / rz;
+      rz = a2[1];
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) pv[s] = y[s] + beta * pv[s];
+    }
+    if (!done) status |= 1;
+    // v = S x S: left product, exchange, right product -> row block
+    __syncthreads();
+    slab_put<N, G, NW>(Xs, xv);
+    __syncthreads();
+    slab_stage<N, G, NW>(Xs, T, y);
+    xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
+    slab_stage<N, G, NW>(Xs, T, u);
+  }
+}
+
+// Cooperative chain (modes 1 and 2 of k_coarse_2d) for scheme (2.4), n = N.
+template <int N, int G, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
+             const InstDev* __restrict__ inst, const double* __restrict__ Tg,
+             const double* __restrict__ lam, double* U, const double* __restrict__ F,
+             double* G_old, double* delta, int32_t* status_out, const int32_t* __restrict__ active,
+             int k, const int32_t* __restrict__ kdev, int32_t* sync) {
+  using C = GeoC<N, G, NW>;
+  extern __shared__ double smem[];
+  double* Xs = smem;
+  double* T = smem + N * C::LDB;
+  double* red = T + C::P2;
+  if (kdev) k = *kdev;
+  const int xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
+  const int mem = rest % G, grp = rest / G;
+  const int idx = grp * 8 + xcd;
+  if (idx >= n_insts) return;
+  const int ii = insts[idx];
+  if (active && !active[ii]) return;
+  const InstDev P = inst[ii];
+  if (P.coarse_kind != 0) return;
+  CoopCtx cc;
+  cc.cnt = sync + idx * 64;
+  cc.gen = cc.cnt + 32;
+  cc.xg = P.work;                      // slice-0 work vectors of the instance
+  cc.part = P.work + 2 * (int64_t)N * N;
+  cc.G = G;
+  cc.mem = mem;
+  cc.ok = 1;
+  cc.xsel = 0;
+  cc.psel = 0;
+  for (int m = threadIdx.x; m < C::P2; m += C::NT) T[m] = Tg[m];
+  // spectral tables of the member's column block (owned slots)
+  const double tau = P.dT / P.m_coarse;
+  double dv[C::OWN], bv[C::OWN], u[C::OWN];
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    const double mu = -(lam[row] + lam[mem * C::B + col]);
+    dv[s] = 1.0 / mu + tau * P.eps * P.eps * mu;
+    bv[s] = 1.0 / mu + tau;
+  }
+  __syncthreads();
+  const int64_t NN = (int64_t)N * N;
+  double* Ui = U + P.off_iter;
+  const double* Fi = F + P.off_slices;
+  double* Gi = G_old + P.off_slices;
+  const int Ns = P.n_slices;
+  int status = 0;
+  // state element (a, c) of the slab form is u[R_m[c]][a] = row mem*B + c, column a
+  auto gidx = [&](int s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    return (int64_t)(mem * C::B + col) * N + row;
+  };
+  if (mode == 1) {
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) u[s] = Ui[gidx(s)];
+    for (int n = 0; n < Ns; ++n) {
+      coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, dv, bv, status);
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) {
+        Ui[(n + 1) * NN + gidx(s)] = u[s];
+        Gi[n * NN + gidx(s)] = u[s];
+      }
+    }
+    if (threadIdx.x == 0 && mem == 0) status_out[ii] = status | *P.status | (cc.ok ? 0 : 4);
+    return;
+  }
+  if (k >= Ns) {
+    if (threadIdx.x == 0 && mem == 0) delta[ii] = 0.0;
+    return;
+  }
+  double dmax;
+  {
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      const int64_t o = gidx(s);
+      const double un = Fi[k * NN + o];
+      const double d = un - Ui[(k + 1) * NN + o];
+      acc[0] += d * d;
+      Ui[(k + 1) * NN + o] = un;
+      u[s] = un;
+    }
+    group_sum<NW, 1>(acc, red, cc);
+    dmax = acc[0];
+  }
+  for (int n = k + 1; n < Ns; ++n) {
+    coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, dv, bv, status);
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      const int64_t o = gidx(s);
+      const double gv = u[s];
+      const double un = Fi[n * NN + o] + (gv - Gi[n * NN + o]);
+      const double d = un - Ui[(n + 1) * NN + o];
+      acc[0] += d * d;
+      Ui[(n + 1) * NN + o] = un;
+      Gi[n * NN + o] = gv;
+      u[s] = un;
+    }
+    group_sum<NW, 1>(acc, red, cc);
+    dmax = fmax(dmax, acc[0]);
+  }
+  if (threadIdx.x == 0 && mem == 0) {
+    const double dlt = sqrt(P.h * P.h * dmax);
+    delta[ii] = dlt;
+    if (!(dlt == dlt) || dlt > 1e300) status |= 2;
+    status_out[ii] = status | *P.status | (cc.ok ? 0 : 4);
+  }
+}
+
 // ------------------------------------------------- streamed large grids
 // n = 256: the 512 KB FP64 state does not fit on a CU, so each transform
 // stage streams it between two global buffers of the work item (L2 / MALL
@@ -2184,6 +2598,61 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
   hipLaunchKernelGGL(k_coarse_1d, dim3(grid), dim3(n), lds, s, mode, insts, items, inst, S, lam,
                      U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
   return hipGetLastError();
+}
+
+__global__ void k_zero_i32(int32_t* p, int count) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+template <int N, int G, int NW>
+static hipError_t chain_coop(int mode, const int32_t* insts, int n_insts, const InstDev* inst,
+                             const double* Tg, const double* lam, double* U, const double* F,
+                             double* G_old, double* delta, int32_t* status, const int32_t* active,
+                             int k, const int32_t* kdev, int32_t* sync, hipStream_t s) {
+  using C = GeoC<N, G, NW>;
+  const size_t lds = ((size_t)N * C::LDB + C::P2 + 4 * NW) * sizeof(double);
+  const void* fn = (const void*)k_chain_coop<N, G, NW>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  // every workgroup of the grid must be resident at once
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NW * 64, lds)) != hipSuccess)
+    return e;
+  const int groups = (n_insts + 7) / 8;
+  const int grid = 8 * G * groups;
+  if (grid > cus * per_cu) return hipErrorCooperativeLaunchTooLarge;
+  const int words = 64 * 8 * groups;
+  hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
+  hipLaunchKernelGGL((k_chain_coop<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
+                     n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync);
+  return hipGetLastError();
+}
+
+// Largest instance count the cooperative chain takes for class size n (0: none).
+int chain_coop_capacity(int n) {
+  switch (n) {
+    case 128: return 64;
+    default: return 0;
+  }
+}
+
+// Coarse chain on a group of workgroups per instance (2D, n = 128, scheme
+// (2.4) only); hipErrorNotSupported for other sizes.
+hipError_t launch_chain_coop(int n, int mode, const int32_t* insts, int n_insts,
+                             const InstDev* inst, const double* Tg, double* U, const double* F,
+                             double* G_old, double* delta, int32_t* status, const int32_t* active,
+                             int k, const int32_t* kdev, int32_t* sync, hipStream_t s) {
+  if (n_insts <= 0) return hipSuccess;
+  if (n_insts > chain_coop_capacity(n)) return hipErrorNotSupported;
+  const double* lam = Tg + 2 * (n + 1);
+  switch (n) {
+    case 128: return chain_coop<128, 4, 4>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts, const InstDev* inst,

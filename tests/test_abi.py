@@ -78,3 +78,29 @@ def test_status_strings():
     lib = chlib.load()
     assert lib.ch_status_str(0) == b"CH_OK"
     assert lib.ch_status_str(4) == b"CH_ERR_NOCONV"
+
+
+def test_chain_variant_selection_host_only():
+    import workloads
+    from paper_2304_14074_amd import chlib
+    probs = [workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5),
+             workloads.Problem(dim=2, n=64, n_slices=2, j_fine=5)]
+    lib, st, h = _create(probs)
+    assert st == chlib.CH_OK
+    g = ctypes.c_int32(0)
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 4
+    assert lib.ch_chain_variant(h, 64, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    g.value = 4
+    assert lib.ch_chain_variant(h, 64, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    g.value = 3
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 1) == chlib.CH_ERR_ARG
+    g.value = 1
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    assert lib.ch_chain_variant(h, 32, ctypes.byref(g), 0) == chlib.CH_ERR_ARG
+    lib.ch_destroy(h)
+    # more instances than the multi-workgroup chain takes: one workgroup each
+    lib, st, h = _create([workloads.Problem(dim=2, n=128, n_slices=1, j_fine=1)] * 65)
+    assert st == chlib.CH_OK
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    lib.ch_destroy(h)

@@ -1,5 +1,6 @@
 """A captured Parareal iteration replayed as a hipGraph gives the eager
-iterates bit for bit, replay after replay (ragged batch of instances)."""
+iterates bit for bit, replay after replay (ragged batch of instances, one of
+them on the multi-workgroup coarse sweep)."""
 import numpy as np
 import pytest
 import torch
@@ -13,7 +14,9 @@ pytestmark = pytest.mark.gpu
 def _problems():
     return [workloads.Problem(dim=2, n=64, eps=0.03, T=4 * 12 * 4e-5, n_slices=4, j_fine=12),
             workloads.Problem(dim=2, n=32, eps=0.02, T=3 * 9 * 4e-5, n_slices=3, j_fine=9),
-            workloads.Problem(dim=1, n=128, eps=0.03, T=3 * 20 * 1e-4, n_slices=3, j_fine=20)]
+            workloads.Problem(dim=1, n=128, eps=0.03, T=3 * 20 * 1e-4, n_slices=3, j_fine=20),
+            # n = 128: the coarse sweep runs on a group of four workgroups
+            workloads.Problem(dim=2, n=128, eps=0.02, T=3 * 6 * 2e-5, n_slices=3, j_fine=6)]
 
 
 def _init(ctx, st):

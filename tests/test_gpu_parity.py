@@ -406,3 +406,86 @@ def test_streamed_256_nonlinear_energy_decays():
     out = gu.fine(ctx, [u0[None]])[0][0]
     e0, e1 = o_energy.energy(u0, p.eps), o_energy.energy(out, p.eps)
     assert np.all(np.isfinite(out)) and e1 < e0
+
+
+@pytest.mark.parametrize("groups", [1, 4])
+def test_chain_variants_parareal_128_match_oracle(groups):
+    # the coarse sweep of (2.2) on one workgroup per instance and split over a
+    # group of four workgroups: both against the oracle's iterates
+    from paper_2304_14074_amd import chlib
+    N, J, n = 4, 8, 128
+    p = workloads.Problem(dim=2, n=n, eps=0.02, T=N * J * 2e-5, n_slices=N, j_fine=J)
+    u0 = workloads.u0_uniform(n, 2, 0.3, 13)
+    ctx = chlib.Context([p])
+    assert ctx.ch_chain_variant(n, groups) == groups
+    st = ctx.new_state()
+    st["U"][: n * n] = torch.from_numpy(u0.reshape(-1)).cuda()
+    ref = _oracle_run(p, u0, N)
+    print(f"chain variant groups={groups}", flush=True)
+    ctx.ch_parareal_iterate(st, 0.0)
+    torch.cuda.synchronize()
+    U = gu.unpack_iter(ctx, st["U"])[0]
+    for j in range(N + 1):
+        assert gu.rel(U[j], ref["U"][0][j]) < TOL, ("k=0", j)
+    for k in range(1, N + 1):
+        ctx.ch_parareal_iterate(st, 0.0)
+        torch.cuda.synchronize()
+        U = gu.unpack_iter(ctx, st["U"])[0]
+        for j in range(N + 1):
+            assert gu.rel(U[j], ref["U"][k][j]) < TOL, (k, j, gu.rel(U[j], ref["U"][k][j]))
+        d = st["delta"][0].item()
+        assert abs(d - ref["delta"][k - 1]) <= 1e-9 * max(ref["delta"][k - 1], 1e-300) + 1e-15
+    assert int(st["status"][0].item()) == 0
+
+
+def test_chain_group_ragged_batch_matches_single_workgroup_chain():
+    # nine instances (two groups of eight slots, seven idle) with different
+    # eps, slice counts and amplitudes; a tenth with the stabilised coarse
+    # step makes its class fall back to one workgroup per instance
+    from paper_2304_14074_amd import chlib
+    n = 128
+    probs = [workloads.Problem(dim=2, n=n, eps=0.02 + 0.002 * i, T=(2 + i % 3) * 4 * 2e-5,
+                               n_slices=2 + i % 3, j_fine=4) for i in range(9)]
+    u0s = [workloads.u0_uniform(n, 2, (0.05, 0.5, 0.9)[i % 3], 40 + i) for i in range(9)]
+
+    def run(groups, probs, u0s):
+        ctx = chlib.Context(probs)
+        assert ctx.ch_chain_variant(n, groups) == groups
+        st = ctx.new_state()
+        for i, u0 in enumerate(u0s):
+            _, _, _, io = ctx.layout(i)
+            st["U"][io: io + n * n] = torch.from_numpy(u0.reshape(-1)).cuda()
+        out = []
+        for _ in range(4):
+            ctx.ch_parareal_iterate(st, 0.0)
+            torch.cuda.synchronize()
+            out.append((gu.unpack_iter(ctx, st["U"]), st["delta"].cpu().numpy().copy(),
+                        st["status"].cpu().numpy().copy()))
+        return out
+
+    a = run(4, probs, u0s)
+    b = run(1, probs, u0s)
+    for (Ua, da, sa), (Ub, db, sb) in zip(a, b):
+        assert np.all(sa == 0) and np.all(sb == 0)
+        for i in range(9):
+            for j in range(len(Ua[i])):
+                assert gu.rel(Ua[i][j], Ub[i][j]) < 1e-12, (i, j)
+            if np.isfinite(db[i]):
+                assert abs(da[i] - db[i]) <= 1e-9 * max(db[i], 1e-300) + 1e-15
+            else:   # no update norm yet after the prediction
+                assert da[i] == db[i]
+    ref = _oracle_run(probs[4], u0s[4], 3)
+    for k in range(1, 4):
+        for j in range(len(ref["U"][k])):
+            assert gu.rel(a[k][0][4][j], ref["U"][k][j]) < TOL, (k, j)
+    # a stabilised-coarse instance in the class: the whole class uses one
+    # workgroup per instance and still matches
+    mixed = probs[:2] + [workloads.Problem(dim=2, n=n, eps=0.02, T=2 * 4 * 2e-5, n_slices=2,
+                                           j_fine=4, coarse_kind="stab", m_coarse=2)]
+    c = run(4, mixed, u0s[:3])
+    d = run(1, mixed, u0s[:3])
+    for (Ua, _, sa), (Ub, _, _) in zip(c, d):
+        assert np.all(sa == 0)
+        for i in range(3):
+            for j in range(len(Ua[i])):
+                assert np.array_equal(Ua[i][j], Ub[i][j]), (i, j)
