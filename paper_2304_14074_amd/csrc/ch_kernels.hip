@@ -980,10 +980,13 @@ template <int N, int G, int NW>
 struct GeoC {
   static constexpr int B = N / G, H = N / 2, TR = H / 16, TCB = B / 16;
   static constexpr int WPR = NW / TR, CPW = TCB / WPR, KS = H / 4;
-  static constexpr int LDB = B + 1;            // slab row stride (odd)
+  // slab row stride: B + 8 with B a multiple of 16 puts the four k-rows of an
+  // MFMA B operand (rows 2g) on alternating bank halves (conflict-free)
+  static constexpr int LDB = B + 8;
   static constexpr int NT = NW * 64, OWN = 8 * CPW, P2 = 2 * (N + 1);
   static_assert(NW % TR == 0 && TCB % WPR == 0 && CPW >= 1, "wave tiling");
   static_assert(OWN * NT == N * B, "ownership");
+  static_assert(B % 16 == 0 && N % 8 == 0, "bank-split slab stride, 8 x 8 exchange tiles");
 };
 
 // Owned slot s of a slab-stage output: row a' (0..N-1), slab column c (0..B-1).
@@ -998,7 +1001,9 @@ __device__ __forceinline__ void slab_rc(int s, int& row, int& col) {
   col = 16 * (c0 + q) + j;
 }
 
-// y = S * slab (N x B in LDS), folded; owned results in y.
+// y = S * slab (N x B in LDS), folded; owned results in y.  Software-
+// pipelined like the full-width stage: the sine and data operands of k-step
+// ks+1 are read from LDS while the MFMAs of k-step ks run.
 template <int N, int G, int NW>
 __device__ __forceinline__ void slab_stage(const double* Xs, const double* T,
                                            double (&y)[GeoC<N, G, NW>::OWN]) {
@@ -1015,17 +1020,45 @@ __device__ __forceinline__ void slab_stage(const double* Xs, const double* T,
   int ie = (a1 * (2 * g + 1)) % C::P2, io = (a1 * (2 * g + 2)) % C::P2;
   const int step = (8 * a1) % C::P2;
   const double* base = Xs + (2 * g) * C::LDB + 16 * c0 + j;
-#pragma unroll 4
+  double se = T[ie], so = T[io];
+  double be[C::CPW], bo[C::CPW];
+#pragma unroll
+  for (int q = 0; q < C::CPW; ++q) {
+    be[q] = base[16 * q];
+    bo[q] = base[C::LDB + 16 * q];
+  }
+#pragma unroll
   for (int ks = 0; ks < C::KS; ++ks) {
-    const double se = T[ie], so = T[io];
-    ie += step; ie -= (ie >= C::P2) ? C::P2 : 0;
-    io += step; io -= (io >= C::P2) ? C::P2 : 0;
-    const double* pe = base + (8 * ks) * C::LDB;
+    double ne[C::CPW], no[C::CPW], nse = 0.0, nso = 0.0;
+    if (ks + 1 < C::KS) {
+      ie += step;
+      ie -= (ie >= C::P2) ? C::P2 : 0;
+      io += step;
+      io -= (io >= C::P2) ? C::P2 : 0;
+      nse = T[ie];
+      nso = T[io];
+      const double* pe = base + (8 * (ks + 1)) * C::LDB;
+#pragma unroll
+      for (int q = 0; q < C::CPW; ++q) {
+        ne[q] = pe[16 * q];
+        no[q] = pe[C::LDB + 16 * q];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < C::CPW; ++q) {
-      aE[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(se, pe[16 * q], aE[q], 0, 0, 0);
-      aO[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(so, pe[C::LDB + 16 * q], aO[q], 0, 0, 0);
+      aE[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(se, be[q], aE[q], 0, 0, 0);
+      aO[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(so, bo[q], aO[q], 0, 0, 0);
     }
+    if (ks + 1 < C::KS) {
+      se = nse;
+      so = nso;
+#pragma unroll
+      for (int q = 0; q < C::CPW; ++q) {
+        be[q] = ne[q];
+        bo[q] = no[q];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int q = 0; q < C::CPW; ++q)
@@ -1047,21 +1080,23 @@ __device__ __forceinline__ void slab_put(double* Xs, const double (&v)[GeoC<N, G
   }
 }
 
-// State of one group member: barrier words, exchange buffers, partial sums.
-// Consecutive exchanges (and consecutive reductions) alternate between two
-// buffers, so a buffer is rewritten only after a later barrier has shown
+// State of one group member: barrier counter, exchange buffers, partial
+// sums.  Consecutive exchanges (and consecutive reductions) alternate between
+// two buffers, so a buffer is rewritten only after a later barrier has shown
 // that every member finished reading it; one barrier per exchange suffices.
 struct CoopCtx {
-  int32_t *cnt, *gen;
+  int32_t* cnt;     // arrivals, monotonic over the launch (zeroed before it)
   double* xg;       // two exchange matrices N x N (natural order)
   double* part;     // two slots of 8 x 8 partial sums
-  int G, mem, ok, xsel, psel;
+  int mem, ok, xsel, psel, nb;
 };
 
-// Barrier of the G members of one group.  The spin is bounded by the wall
-// clock (about 0.2 s): on time-out the member clears cc.ok and every later
-// barrier of the launch returns at once, so a lost member can never hang the
-// kernel; the host sees the failure in the status word.
+// Barrier of the G members of one group: barrier b is passed once the
+// counter reaches G (b + 1).  The spin is bounded by the wall clock (about
+// 0.2 s): on time-out the member clears cc.ok and every later barrier of the
+// launch returns at once, so a lost member can never hang the kernel; the
+// host sees the failure in the status word.
+template <int G>
 __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
   __threadfence();   // every wave: its stores visible device-wide
   __syncthreads();
@@ -1069,62 +1104,49 @@ __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
   if (threadIdx.x == 0) {
     int ok = cc.ok;
     if (ok) {
-      const int g0 = __hip_atomic_load(cc.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const int target = G * (cc.nb + 1);
       const int arrived =
-          __hip_atomic_fetch_add(cc.cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (arrived == cc.G - 1) {
-        __hip_atomic_store(cc.cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(cc.gen, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
+          __hip_atomic_fetch_add(cc.cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived != target - 1) {
         const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(cc.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        while (__hip_atomic_load(cc.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
           if (wall_clock64() - t0 > 20000000ull) { ok = 0; break; }
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      __threadfence();
+      __threadfence();   // acquire: later reads see every member's stores
     }
     ok_s = ok;
   }
   __syncthreads();
   cc.ok = ok_s;
+  cc.nb += 1;
 }
 
 // Group-wide sum of K values in a fixed order (partials exchanged in memory,
 // summed by every member in member order, so all members agree bitwise).
-template <int NW, int K>
+template <int NW, int G, int K>
 __device__ __forceinline__ void group_sum(double (&v)[K], double* red, CoopCtx& cc) {
   block_sum<NW, K>(v, red);
   double* part = cc.part + 64 * cc.psel;
   cc.psel ^= 1;
   if (threadIdx.x == 0)
+#pragma unroll
     for (int i = 0; i < K; ++i) part[i * 8 + cc.mem] = v[i];
-  group_barrier(cc);
+  group_barrier<G>(cc);
+  double pv[K][G];
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+#pragma unroll
+    for (int m = 0; m < G; ++m) pv[i][m] = __builtin_nontemporal_load(&part[i * 8 + m]);
+#pragma unroll
   for (int i = 0; i < K; ++i) {
     double s = 0.0;
-    for (int m = 0; m < cc.G; ++m) s += __builtin_nontemporal_load(&part[i * 8 + m]);
+#pragma unroll
+    for (int m = 0; m < G; ++m) s += pv[i][m];
     v[i] = s;
   }
 }
-template <int NW>
-__device__ __forceinline__ void group_minmax(double& mn, double& mx, double* red, CoopCtx& cc) {
-  block_minmax<NW>(mn, mx, red);
-  double* part = cc.part + 64 * cc.psel;
-  cc.psel ^= 1;
-  if (threadIdx.x == 0) {
-    part[cc.mem] = mn;
-    part[8 + cc.mem] = mx;
-  }
-  group_barrier(cc);
-  double a = 1e300, b = -1e300;
-  for (int m = 0; m < cc.G; ++m) {
-    a = fmin(a, __builtin_nontemporal_load(&part[m]));
-    b = fmax(b, __builtin_nontemporal_load(&part[8 + m]));
-  }
-  mn = a;
-  mx = b;
-}
-
 // Exchange A: from a column block (left-product output v: rows 0..N-1, block
 // columns C_m) to the transposed row block slab[k][r'] = M[R_m[r']][k].
 template <int N, int G, int NW>
@@ -1139,120 +1161,234 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
     slab_rc<N, G, NW>(s, row, col);
     xg[(int64_t)row * N + cc.mem * C::B + col] = v[s];
   }
-  group_barrier(cc);
-  for (int i = threadIdx.x; i < C::B * N; i += C::NT) {
-    const int rr = i / N, k = i % N;   // coalesced rows of the exchange matrix
-    Xs[k * C::LDB + rr] = __builtin_nontemporal_load(&xg[(int64_t)(cc.mem * C::B + rr) * N + k]);
+  group_barrier<G>(cc);
+  // 8 x 8 tiles (8 consecutive k per row, 8 rows per wave instruction): 64-byte
+  // global segments and bank-conflict-free transposed LDS writes
+  constexpr int R = C::B * N / C::NT;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double t[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int tile = w + NW * j, rr = 8 * (tile % (C::B / 8)) + (l >> 3);
+    const int k = 8 * (tile / (C::B / 8)) + (l & 7);
+    t[j] = __builtin_nontemporal_load(&xg[(int64_t)(cc.mem * C::B + rr) * N + k]);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int tile = w + NW * j, rr = 8 * (tile % (C::B / 8)) + (l >> 3);
+    const int k = 8 * (tile / (C::B / 8)) + (l & 7);
+    Xs[k * C::LDB + rr] = t[j];
   }
   __syncthreads();
 }
 
 // Exchange B: from a right-product output v (slab form: element (a, c) is
-// M[R_m[c]][a]) to the column block slab[k][c] = M[k][C_m[c]].
-template <int N, int G, int NW>
+// M[R_m[c]][a]) to the column block slab[k][c] = M[k][C_m[c]].  With K > 0 a
+// group reduction of acc[0..K) rides on the same barrier (per-member values
+// posted before it, combined in member order after it): sums, or with MINMAX
+// (K = 2) the minimum of acc[0] and the maximum of acc[1].
+template <int N, int G, int NW, int K, bool MINMAX = false>
 __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
-                                   CoopCtx& cc) {
+                                   CoopCtx& cc, double* acc, double* red) {
   using C = GeoC<N, G, NW>;
   double* xg = cc.xg + (int64_t)N * N * cc.xsel;
   cc.xsel ^= 1;
+  constexpr int R = C::B * N / C::NT;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // transpose through LDS (8 x 8 tiles) so that the global stores are
+  // row-contiguous 64-byte segments
+  __syncthreads();
+  slab_put<N, G, NW>(Xs, v);
+  __syncthreads();
 #pragma unroll
-  for (int s = 0; s < C::OWN; ++s) {
-    int row, col;
-    slab_rc<N, G, NW>(s, row, col);
-    xg[(int64_t)(cc.mem * C::B + col) * N + row] = v[s];
+  for (int j = 0; j < R; ++j) {
+    const int tile = w + NW * j, c = 8 * (tile % (C::B / 8)) + (l >> 3);
+    const int a = 8 * (tile / (C::B / 8)) + (l & 7);
+    xg[(int64_t)(cc.mem * C::B + c) * N + a] = Xs[a * C::LDB + c];
   }
-  group_barrier(cc);
-  for (int i = threadIdx.x; i < N * C::B; i += C::NT) {
-    const int k = i / C::B, c = i % C::B;
-    Xs[k * C::LDB + c] = __builtin_nontemporal_load(&xg[(int64_t)k * N + cc.mem * C::B + c]);
+  double* part = cc.part + 64 * cc.psel;
+  if constexpr (K > 0) {
+    double v2[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) v2[i] = acc[i];
+    if constexpr (MINMAX)
+      block_minmax<NW>(v2[0], v2[1], red);
+    else
+      block_sum<NW, K>(v2, red);
+    cc.psel ^= 1;
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int i = 0; i < K; ++i) part[i * 8 + cc.mem] = v2[i];
+  }
+  group_barrier<G>(cc);
+  double t[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = threadIdx.x + j * C::NT, k = i / C::B, c = i % C::B;
+    t[j] = __builtin_nontemporal_load(&xg[(int64_t)k * N + cc.mem * C::B + c]);
+  }
+  if constexpr (K > 0) {
+    // lane i G + m of every wave loads member m's value i; the wave then
+    // combines them by shuffles in member order
+    static_assert(K * G <= 64, "one value per lane");
+    const double pl = l < K * G ? __builtin_nontemporal_load(&part[(l / G) * 8 + l % G]) : 0.0;
+    if constexpr (MINMAX) {
+      double a = 1e300, b = -1e300;
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        a = fmin(a, __shfl(pl, m));
+        b = fmax(b, __shfl(pl, G + m));
+      }
+      acc[0] = a;
+      acc[1] = b;
+    } else {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < G; ++m) s += __shfl(pl, i * G + m);
+        acc[i] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = threadIdx.x + j * C::NT, k = i / C::B, c = i % C::B;
+    Xs[k * C::LDB + c] = t[j];
   }
   __syncthreads();
 }
 
+// y = S (q . S v S) S, the coupling part of K v = d v + tau S (q . S v S) S
+// (the SPD form of (2.4)), for v a column block in registers (two transposing
+// exchanges; v is not needed after the first stage).  acc[0], acc[2] hold this
+// thread's terms of two inner products on entry; acc[1] gets those of
+// (K v, v) = sum d v^2 + tau sum q (S v S)^2 (S is orthogonal and symmetric),
+// and all three come back as group sums, reduced on the second exchange's
+// barrier.
+template <int N, int G, int NW>
+__device__ __forceinline__ void coop_apply_K(double* Xs, const double* T, CoopCtx& cc,
+                                             const double (&v)[GeoC<N, G, NW>::OWN],
+                                             double (&y)[GeoC<N, G, NW>::OWN],
+                                             const double* Dl, const double* Ql, double tau,
+                                             double (&acc)[3], double* red) {
+  using C = GeoC<N, G, NW>;
+  const int t = threadIdx.x;
+  double dvv = 0.0, qyy = 0.0;
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) dvv += Dl[s * C::NT + t] * v[s] * v[s];
+  __syncthreads();
+  slab_put<N, G, NW>(Xs, v);
+  __syncthreads();
+  slab_stage<N, G, NW>(Xs, T, y);          // left: S v (column block)
+  xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
+  slab_stage<N, G, NW>(Xs, T, y);          // right: (S v S) row block
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    const double q = Ql[s * C::NT + t];
+    qyy += q * y[s] * y[s];
+    y[s] *= q;
+  }
+  acc[1] = dvv + tau * qyy;
+  __syncthreads();
+  slab_put<N, G, NW>(Xs, y);
+  __syncthreads();
+  slab_stage<N, G, NW>(Xs, T, y);          // right: (q . S v S) S
+  xchg_rowsT_to_cols<N, G, NW, 3>(y, Xs, cc, acc, red);
+  slab_stage<N, G, NW>(Xs, T, y);          // left: column block
+}
+
 // One solve of scheme (2.4) by the group.  On entry u holds the member's row
 // block of the state in slab form (element (a, c) = u[R_m[c]][a]); on exit it
-// holds the result in the same form.
+// holds the result in the same form.  Per-point tables live in LDS at
+// [s * NT + thread]: Dl = d of (2.4), Ml = the preconditioner, Ql = q = u^2.
+// The CG is the preconditioned Chronopoulos-Gear form (one group reduction
+// of three inner products per iteration; in exact arithmetic the iterates of
+// plain PCG), stopped when ||r|| <= rtol ||b|| as the one-workgroup solver.
 template <int N, int G, int NW>
 __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const double* T,
-                             double* red, CoopCtx& cc, const InstDev& P,
-                             const double (&dv)[GeoC<N, G, NW>::OWN],
-                             const double (&bv)[GeoC<N, G, NW>::OWN], int& status) {
+                             double* red, CoopCtx& cc, const InstDev& P, const double* Dl,
+                             double* Ml, double* Ql, const double* lamS, int& status) {
   using C = GeoC<N, G, NW>;
   const double tau = P.dT / P.m_coarse;
-  double y[C::OWN], q[C::OWN], pv[C::OWN], rv[C::OWN], xv[C::OWN], mv[C::OWN];
+  const int t = threadIdx.x;
+  double y[C::OWN], pv[C::OWN], rv[C::OWN], xv[C::OWN], sv[C::OWN];
   for (int sub = 0; sub < P.m_coarse; ++sub) {
     double mn = 1e300, mx = -1e300;
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) {
-      q[s] = P.f_zero ? 0.0 : u[s] * u[s];
-      mn = fmin(mn, q[s]);
-      mx = fmax(mx, q[s]);
+      const double q = P.f_zero ? 0.0 : u[s] * u[s];
+      Ql[s * C::NT + t] = q;
+      mn = fmin(mn, q);
+      mx = fmax(mx, q);
     }
-    group_minmax<NW>(mn, mx, red, cc);
-    const double cshift = 0.5 * (mn + mx);
-    // u_hat = S u S: right product on the row block, exchange, left product
+    // u_hat = S u S: right product on the row block, exchange, left product;
+    // the range of q rides on the exchange
     __syncthreads();
     slab_put<N, G, NW>(Xs, u);
     __syncthreads();
     slab_stage<N, G, NW>(Xs, T, y);
-    xchg_rowsT_to_cols<N, G, NW>(y, Xs, cc);
+    {
+      double mm[2] = {mn, mx};
+      xchg_rowsT_to_cols<N, G, NW, 2, true>(y, Xs, cc, mm, red);
+      mn = mm[0];
+      mx = mm[1];
+    }
+    const double cshift = 0.5 * (mn + mx);
     slab_stage<N, G, NW>(Xs, T, y);   // column block of u_hat
-    double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) {
-      const double b = (P.f_zero ? bv[s] - tau : bv[s]) * y[s];
-      mv[s] = 1.0 / (dv[s] + tau * cshift);
+      int row, col;
+      slab_rc<N, G, NW>(s, row, col);
+      const double mu = -(lamS[row] + lamS[cc.mem * C::B + col]);
+      const double bs = P.f_zero ? 1.0 / mu : 1.0 / mu + tau;
+      const double mi = 1.0 / (Dl[s * C::NT + t] + tau * cshift);
+      Ml[s * C::NT + t] = mi;
       xv[s] = 0.0;
-      rv[s] = b;
-      pv[s] = b * mv[s];
-      acc[0] += b * pv[s];
-      acc[1] += b * b;
+      rv[s] = bs * y[s];
+      pv[s] = rv[s] * mi;   // z_0 = M r_0
     }
-    group_sum<NW, 2>(acc, red, cc);
-    double rz = acc[0];
-    const double stop2 = P.krylov_rtol * P.krylov_rtol * acc[1];
-    bool done = !(acc[1] > 0.0);
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      acc[0] += rv[s] * pv[s];
+      acc[2] += rv[s] * rv[s];
+    }
+    coop_apply_K<N, G, NW>(Xs, T, cc, pv, sv, Dl, Ql, tau, acc, red);
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) sv[s] = Dl[s * C::NT + t] * pv[s] + tau * sv[s];   // w_0 = K z_0
+    double gam = acc[0];
+    const double stop2 = P.krylov_rtol * P.krylov_rtol * acc[2];
+    bool done = !(acc[2] > 0.0);
+    double alpha = gam / acc[1];
     for (int it = 1; !done && it <= P.krylov_max; ++it) {
-      // K p = d p + tau S (q . S p S) S
-      __syncthreads();
-      slab_put<N, G, NW>(Xs, pv);
-      __syncthreads();
-      slab_stage<N, G, NW>(Xs, T, y);          // left: S p (column block)
-      xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
-      slab_stage<N, G, NW>(Xs, T, y);          // right: (S p S) row block
-#pragma unroll
-      for (int s = 0; s < C::OWN; ++s) y[s] *= q[s];
-      __syncthreads();
-      slab_put<N, G, NW>(Xs, y);
-      __syncthreads();
-      slab_stage<N, G, NW>(Xs, T, y);          // right: (q . S p S) S
-      xchg_rowsT_to_cols<N, G, NW>(y, Xs, cc);
-      slab_stage<N, G, NW>(Xs, T, y);          // left: column block
-      double a1[1] = {0.0};
-#pragma unroll
-      for (int s = 0; s < C::OWN; ++s) {
-        y[s] = dv[s] * pv[s] + tau * y[s];
-        a1[0] += pv[s] * y[s];
-      }
-      group_sum<NW, 1>(a1, red, cc);
-      const double alpha = rz / a1[0];
-      double a2[2] = {0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < C::OWN; ++s) {
         xv[s] += alpha * pv[s];
-        rv[s] -= alpha * y[s];
-        y[s] = rv[s] * mv[s];
-        a2[0] += rv[s] * rv[s];
-        a2[1] += rv[s] * y[s];
+        rv[s] -= alpha * sv[s];
       }
-      group_sum<NW, 2>(a2, red, cc);
-      if (a2[0] <= stop2) { done = true; break; }
-      // a2 is the same in every member; cc.ok drops only on a barrier time-out
-      if (!(a2[0] == a2[0]) || !cc.ok) break;
-      const double beta = a2[1] / rz;
-      rz = a2[1];
+      double z[C::OWN];
+      double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-      for (int s = 0; s < C::OWN; ++s) pv[s] = y[s] + beta * pv[s];
+      for (int s = 0; s < C::OWN; ++s) {
+        z[s] = rv[s] * Ml[s * C::NT + t];
+        a3[0] += rv[s] * z[s];
+        a3[2] += rv[s] * rv[s];
+      }
+      coop_apply_K<N, G, NW>(Xs, T, cc, z, y, Dl, Ql, tau, a3, red);
+      if (a3[2] <= stop2) { done = true; break; }
+      // a3 is the same in every member; cc.ok drops only on a barrier time-out
+      if (!(a3[2] == a3[2]) || !cc.ok) break;
+      const double beta = a3[0] / gam;
+      alpha = a3[0] / (a3[1] - beta * a3[0] / alpha);
+      gam = a3[0];
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) {
+        const double zs = rv[s] * Ml[s * C::NT + t];
+        const double ws = Dl[s * C::NT + t] * zs + tau * y[s];   // w = K z
+        pv[s] = zs + beta * pv[s];
+        sv[s] = ws + beta * sv[s];
+      }
     }
     if (!done) status |= 1;
     // v = S x S: left product, exchange, right product -> row block
@@ -1277,7 +1413,11 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
   extern __shared__ double smem[];
   double* Xs = smem;
   double* T = smem + N * C::LDB;
-  double* red = T + C::P2;
+  double* lamS = T + C::P2;
+  double* red = lamS + N;
+  double* Dl = red + 4 * NW;
+  double* Ml = Dl + C::OWN * C::NT;
+  double* Ql = Ml + C::OWN * C::NT;
   if (kdev) k = *kdev;
   const int xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
   const int mem = rest % G, grp = rest / G;
@@ -1289,25 +1429,24 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
   if (P.coarse_kind != 0) return;
   CoopCtx cc;
   cc.cnt = sync + idx * 64;
-  cc.gen = cc.cnt + 32;
   cc.xg = P.work;                      // slice-0 work vectors of the instance
   cc.part = P.work + 2 * (int64_t)N * N;
-  cc.G = G;
   cc.mem = mem;
   cc.ok = 1;
   cc.xsel = 0;
   cc.psel = 0;
+  cc.nb = 0;
   for (int m = threadIdx.x; m < C::P2; m += C::NT) T[m] = Tg[m];
-  // spectral tables of the member's column block (owned slots)
+  for (int m = threadIdx.x; m < N; m += C::NT) lamS[m] = lam[m];
+  // d of (2.4) on the member's column block (owned slots)
   const double tau = P.dT / P.m_coarse;
-  double dv[C::OWN], bv[C::OWN], u[C::OWN];
+  double u[C::OWN];
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) {
     int row, col;
     slab_rc<N, G, NW>(s, row, col);
     const double mu = -(lam[row] + lam[mem * C::B + col]);
-    dv[s] = 1.0 / mu + tau * P.eps * P.eps * mu;
-    bv[s] = 1.0 / mu + tau;
+    Dl[s * C::NT + threadIdx.x] = 1.0 / mu + tau * P.eps * P.eps * mu;
   }
   __syncthreads();
   const int64_t NN = (int64_t)N * N;
@@ -1326,7 +1465,7 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) u[s] = Ui[gidx(s)];
     for (int n = 0; n < Ns; ++n) {
-      coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, dv, bv, status);
+      coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
 #pragma unroll
       for (int s = 0; s < C::OWN; ++s) {
         Ui[(n + 1) * NN + gidx(s)] = u[s];
@@ -1352,11 +1491,11 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
       Ui[(k + 1) * NN + o] = un;
       u[s] = un;
     }
-    group_sum<NW, 1>(acc, red, cc);
+    group_sum<NW, G, 1>(acc, red, cc);
     dmax = acc[0];
   }
   for (int n = k + 1; n < Ns; ++n) {
-    coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, dv, bv, status);
+    coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
     double acc[1] = {0.0};
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) {
@@ -1369,7 +1508,7 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
       Gi[n * NN + o] = gv;
       u[s] = un;
     }
-    group_sum<NW, 1>(acc, red, cc);
+    group_sum<NW, G, 1>(acc, red, cc);
     dmax = fmax(dmax, acc[0]);
   }
   if (threadIdx.x == 0 && mem == 0) {
@@ -2611,7 +2750,8 @@ static hipError_t chain_coop(int mode, const int32_t* insts, int n_insts, const 
                              double* G_old, double* delta, int32_t* status, const int32_t* active,
                              int k, const int32_t* kdev, int32_t* sync, hipStream_t s) {
   using C = GeoC<N, G, NW>;
-  const size_t lds = ((size_t)N * C::LDB + C::P2 + 4 * NW) * sizeof(double);
+  const size_t lds =
+      ((size_t)N * C::LDB + C::P2 + N + 4 * NW + 3 * (size_t)C::OWN * C::NT) * sizeof(double);
   const void* fn = (const void*)k_chain_coop<N, G, NW>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

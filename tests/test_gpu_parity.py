@@ -469,7 +469,9 @@ def test_chain_group_ragged_batch_matches_single_workgroup_chain():
         assert np.all(sa == 0) and np.all(sb == 0)
         for i in range(9):
             for j in range(len(Ua[i])):
-                assert gu.rel(Ua[i][j], Ub[i][j]) < 1e-12, (i, j)
+                # two CG forms (one and three reductions per iteration) agree
+                # to the solver tolerance, not bitwise
+                assert gu.rel(Ua[i][j], Ub[i][j]) < TOL, (i, j)
             if np.isfinite(db[i]):
                 assert abs(da[i] - db[i]) <= 1e-9 * max(db[i], 1e-300) + 1e-15
             else:   # no update norm yet after the prediction
