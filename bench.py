@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes of one fine-sweep launch of the 128x128 workload, from FETCH_SIZE and
 # WRITE_SIZE counter runs calibrated by a 1 GiB copy, for the kernel as it is now;
 # set to None whenever the fine kernel changes until the counters are taken again.
-FINE_LAUNCH_TRAFFIC_BYTES = 19167.5 * 1024
+FINE_LAUNCH_TRAFFIC_BYTES = (49982.3 * 2.0 + 25649598.1) * 1024
 
 
 def fine_flops_per_point_step(n: int) -> float:
@@ -323,7 +323,8 @@ def main():
            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                         "traffic": FINE_LAUNCH_TRAFFIC_BYTES,
-                        "kernel": "k_fine_linear_2d<128,8> (fine sweep, all 64 slices)"},
+                        "kernel": "k_fine_group<128,4,4> (fine sweep, all 64 slices, four "
+                                  "workgroups per slice)"},
            "extra": extra}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, u0)

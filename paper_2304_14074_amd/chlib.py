@@ -27,7 +27,7 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_nn_param_count", "ch_nn_layer", "ch_nn_workspace_bytes", "ch_nn_forward",
            "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind",
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
-           "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant")
+           "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups")
 
 
 class ChProblem(ctypes.Structure):
@@ -96,12 +96,13 @@ def load() -> ctypes.CDLL:
     lib.ch_set_iteration.argtypes = [vp, ctypes.POINTER(ChPrState), i32, vp]
     lib.ch_fine_variant.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     lib.ch_chain_variant.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
+    lib.ch_fine_groups.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     lib.ch_graph_destroy.argtypes = [vp]
     lib.ch_iteration_count.argtypes = [vp, ctypes.POINTER(ChPrState), vp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
                  "ch_nn_bind", "ch_set_coarse_kind", "ch_parareal_graph_create", "ch_graph_launch",
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
-                 "ch_set_iteration", "ch_chain_variant"):
+                 "ch_set_iteration", "ch_chain_variant", "ch_fine_groups"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -236,6 +237,11 @@ class Context:
     def ch_chain_variant(self, n, groups=None):
         g = ctypes.c_int32(0 if groups is None else groups)
         self._check(self.lib.ch_chain_variant(self.h, n, ctypes.byref(g), 0 if groups is None else 1))
+        return g.value
+
+    def ch_fine_groups(self, n, groups=None):
+        g = ctypes.c_int32(0 if groups is None else groups)
+        self._check(self.lib.ch_fine_groups(self.h, n, ctypes.byref(g), 0 if groups is None else 1))
         return g.value
 
     def autotune(self, U_in, F_out, cache_path=None, steps=20):

@@ -37,7 +37,8 @@ struct ClassPlan {      // all instances sharing (dim, n, fine kind, precision)
   Block items_blk, insts_blk;
   Block sine_blk;                // 2D: Se | So | lam ; 1D: S | lam
   int chain_groups = 1;          // workgroups per instance in the coarse chain
-  Block sync_blk;                // barrier words of the multi-workgroup chain
+  int fine_groups = 1;           // workgroups per work item in the fine sweep
+  Block sync_blk;                // barrier words of the multi-workgroup kernels
 };
 
 }  // namespace
@@ -239,7 +240,12 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     if (cp.dim != 2) continue;
     const int cap = chk::chain_coop_capacity(cp.n);
     if (cap > 0 && (int)cp.insts.size() <= cap) cp.chain_groups = 4;
-    cp.sync_blk = take(sizeof(int32_t) * 64 * 8 * ((cp.insts.size() + 7) / 8));
+    const int fcap = chk::fine_group_capacity(cp.n);
+    if (fcap > 0 && (int)cp.items.size() <= fcap && cp.fine_kind == CH_FINE_LINEAR &&
+        cp.precision == CH_PREC_FP64)
+      cp.fine_groups = 4;
+    const size_t units = std::max(cp.insts.size(), cp.items.size());
+    cp.sync_blk = take(sizeof(int32_t) * 64 * 8 * ((units + 7) / 8));
   }
   for (int i = 0; i < n_inst; ++i) {
     const size_t P = probs[i].dim == 2 ? (size_t)probs[i].n * probs[i].n : probs[i].n;
@@ -393,8 +399,18 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
       e = chk::launch_fine_split_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                                     mask, active, k_min, in_iter, s);
     } else if (cp.dim == 2) {
-      e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
-                              mask, active, k_min, in_iter, s, cp.waves);
+      e = hipErrorNotSupported;
+      if (cp.fine_groups > 1) {
+        e = chk::launch_fine_group(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
+                                   mask, active, k_min, in_iter,
+                                   (int32_t*)(c->ws + cp.sync_blk.off), s);
+        // a device that cannot hold every workgroup of the group launch at
+        // once takes the one-workgroup-per-item kernel
+        if (e == hipErrorCooperativeLaunchTooLarge) cp.fine_groups = 1;
+      }
+      if (cp.fine_groups == 1)
+        e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
+                                mask, active, k_min, in_iter, s, cp.waves);
     } else {
       e = chk::launch_fine_1d(cp.n, items, (int)cp.items.size(), inst, tab, nullptr, U_in, F_out,
                               mask, active, k_min, in_iter, s);
@@ -632,6 +648,27 @@ ch_status ch_fine_variant(ch_ctx* c, int32_t n, int32_t* waves, int32_t set) {
     }
   }
   return found ? CH_OK : fail(c, CH_ERR_ARG, "no tunable class with n = %d", n);
+}
+
+ch_status ch_fine_groups(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {
+  if (!c || !groups) return CH_ERR_ARG;
+  bool found = false;
+  for (auto& cp : c->classes) {
+    if (!tunable(cp) || cp.n != n) continue;
+    found = true;
+    if (set) {
+      if (*groups != 1 && *groups != 4)
+        return fail(c, CH_ERR_ARG, "fine groups must be 1 or 4, got %d", *groups);
+      const int cap = chk::fine_group_capacity(n);
+      if (*groups == 4 && (cap == 0 || (int)cp.items.size() > cap))
+        return fail(c, CH_ERR_UNSUPPORTED, "no multi-workgroup fine sweep for n = %d with %zu items",
+                    n, cp.items.size());
+      cp.fine_groups = *groups;
+    } else {
+      *groups = cp.fine_groups;
+    }
+  }
+  return found ? CH_OK : fail(c, CH_ERR_ARG, "no linear FP64 2D class with n = %d", n);
 }
 
 ch_status ch_chain_variant(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {

@@ -1092,13 +1092,18 @@ struct CoopCtx {
 };
 
 // Barrier of the G members of one group: barrier b is passed once the
-// counter reaches G (b + 1).  The spin is bounded by the wall clock (about
-// 0.2 s): on time-out the member clears cc.ok and every later barrier of the
-// launch returns at once, so a lost member can never hang the kernel; the
-// host sees the failure in the status word.
+// counter reaches G (b + 1).  Each wave first waits until its own stores are
+// acknowledged (s_waitcnt vmcnt(0): they have reached the L2); after the
+// workgroup barrier one thread arrives with an agent-scope release (an L2
+// write-back before the atomic), polls, and takes one agent-scope acquire
+// fence (L1/L2 invalidate) before the workgroup proceeds.
+// The spin is bounded by the wall clock (about 0.2 s): on time-out the member
+// clears cc.ok and every later barrier of the launch returns at once, so a
+// lost member can never hang the kernel; the host sees the failure in the
+// status word.
 template <int G>
 __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
-  __threadfence();   // every wave: its stores visible device-wide
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0) (gfx9 encoding; lgkm/exp not waited)
   __syncthreads();
   __shared__ int ok_s;
   if (threadIdx.x == 0) {
@@ -1114,7 +1119,7 @@ __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      __threadfence();   // acquire: later reads see every member's stores
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     ok_s = ok;
   }
@@ -1200,11 +1205,20 @@ __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], doubl
   __syncthreads();
   slab_put<N, G, NW>(Xs, v);
   __syncthreads();
+  {
+    double tv[R];
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const int tile = w + NW * j, c = 8 * (tile % (C::B / 8)) + (l >> 3);
-    const int a = 8 * (tile / (C::B / 8)) + (l & 7);
-    xg[(int64_t)(cc.mem * C::B + c) * N + a] = Xs[a * C::LDB + c];
+    for (int j = 0; j < R; ++j) {   // every LDS read before the first store
+      const int tile = w + NW * j, c = 8 * (tile % (C::B / 8)) + (l >> 3);
+      const int a = 8 * (tile / (C::B / 8)) + (l & 7);
+      tv[j] = Xs[a * C::LDB + c];
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int tile = w + NW * j, c = 8 * (tile % (C::B / 8)) + (l >> 3);
+      const int a = 8 * (tile / (C::B / 8)) + (l & 7);
+      xg[(int64_t)(cc.mem * C::B + c) * N + a] = tv[j];
+    }
   }
   double* part = cc.part + 64 * cc.psel;
   if constexpr (K > 0) {
@@ -1399,6 +1413,100 @@ __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const
     xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
     slab_stage<N, G, NW>(Xs, T, u);
   }
+}
+
+// Fine sweep of the linear step (2.5) on a group of G workgroups per work
+// item (same XCD mapping and barriers as the coarse sweep).  Since the 5-point
+// Laplacian is diagonal in the sine basis (eigenvalues lam_p + lam_q), one step
+//   (I + dt eps^2 Lap^2 - s dt Lap) v = u + dt Lap g,   g = f(u) - s u,
+// is, with hats for S . S,  v_hat = (u_hat + dt lam g_hat) / sigma:  one
+// forward transform of g and one inverse transform per step.  u_hat stays in
+// registers (column block); u in slab form (row block) for the pointwise g.
+// On a barrier time-out the instance's status word gets bit 4.
+template <int N, int G, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __restrict__ inst,
+             const double* __restrict__ Tg, const double* __restrict__ lam,
+             const double* __restrict__ U_in, double* __restrict__ F_out,
+             const uint8_t* __restrict__ mask, const int32_t* __restrict__ active,
+             const int32_t* __restrict__ kmin, int in_iter, int j_steps, int32_t* sync) {
+  using C = GeoC<N, G, NW>;
+  extern __shared__ double smem[];
+  double* Xs = smem;
+  double* T = smem + N * C::LDB;
+  double* Rs = T + C::P2;            // 1 / sigma      [s * NT + thread]
+  double* Tl = Rs + C::OWN * C::NT;  // dt * lam (2D) [s * NT + thread]
+  const int xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
+  const int mem = rest % G, grp = rest / G;
+  const int idx = grp * 8 + xcd;
+  if (idx >= n_items) return;
+  const WorkItem it = items[idx];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
+  const int64_t NN = (int64_t)N * N;
+  CoopCtx cc;
+  cc.cnt = sync + idx * 64;
+  cc.xg = P.work + (int64_t)it.slice * P.work_vecs * NN;   // the item's work vectors
+  cc.part = cc.xg + 2 * NN;
+  cc.mem = mem;
+  cc.ok = 1;
+  cc.xsel = 0;
+  cc.psel = 0;
+  cc.nb = 0;
+  const int t = threadIdx.x;
+  for (int m = t; m < C::P2; m += C::NT) T[m] = Tg[m];
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    const int64_t o = (int64_t)row * N + mem * C::B + col;
+    Rs[s * C::NT + t] = P.rsig_fine[o];
+    Tl[s * C::NT + t] = P.dt * (lam[row] + lam[mem * C::B + col]);
+  }
+  const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
+  // slab-form element (a, c) is u[R_m[c]][a]
+  auto gidx = [&](int s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    return (int64_t)(mem * C::B + col) * N + row;
+  };
+  double u[C::OWN], uh[C::OWN], y[C::OWN];
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) u[s] = U_in[off_in + gidx(s)];
+  __syncthreads();
+  // u_hat = S u S (right product on the row block, exchange, left product)
+  slab_put<N, G, NW>(Xs, u);
+  __syncthreads();
+  slab_stage<N, G, NW>(Xs, T, y);
+  xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
+  slab_stage<N, G, NW>(Xs, T, uh);
+  const int J = j_steps > 0 ? j_steps : P.j_fine;
+  const double s1 = 1.0 + P.s_fine;
+  for (int m = 0; m < J; ++m) {
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s)
+      y[s] = P.f_zero ? (-P.s_fine * u[s]) : (u[s] * u[s] * u[s] - s1 * u[s]);
+    __syncthreads();
+    slab_put<N, G, NW>(Xs, y);
+    __syncthreads();
+    slab_stage<N, G, NW>(Xs, T, y);
+    xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
+    slab_stage<N, G, NW>(Xs, T, y);   // g_hat, column block
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s)
+      uh[s] = Rs[s * C::NT + t] * (uh[s] + Tl[s * C::NT + t] * y[s]);
+    __syncthreads();
+    slab_put<N, G, NW>(Xs, uh);
+    __syncthreads();
+    slab_stage<N, G, NW>(Xs, T, y);
+    xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
+    slab_stage<N, G, NW>(Xs, T, u);   // new state, row block
+  }
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = u[s];
+  if (!cc.ok && t == 0 && mem == 0) atomicOr(P.status, 4);
 }
 
 // Cooperative chain (modes 1 and 2 of k_coarse_2d) for scheme (2.4), n = N.
@@ -2770,6 +2878,57 @@ static hipError_t chain_coop(int mode, const int32_t* insts, int n_insts, const 
   hipLaunchKernelGGL((k_chain_coop<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
                      n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync);
   return hipGetLastError();
+}
+
+template <int N, int G, int NW>
+static hipError_t fine_group(const WorkItem* items, int n_items, const InstDev* inst,
+                             const double* Tg, const double* U_in, double* F_out,
+                             const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                             int in_iter, int j_steps, int32_t* sync, hipStream_t s) {
+  using C = GeoC<N, G, NW>;
+  const size_t lds = ((size_t)N * C::LDB + C::P2 + 2 * (size_t)C::OWN * C::NT) * sizeof(double);
+  const void* fn = (const void*)k_fine_group<N, G, NW>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NW * 64, lds)) != hipSuccess)
+    return e;
+  const int groups = (n_items + 7) / 8;
+  const int grid = 8 * G * groups;
+  if (grid > cus * per_cu) return hipErrorCooperativeLaunchTooLarge;
+  const int words = 64 * 8 * groups;
+  hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
+  const double* lam = Tg + 2 * (N + 1);
+  hipLaunchKernelGGL((k_fine_group<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, items, n_items,
+                     inst, Tg, lam, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync);
+  return hipGetLastError();
+}
+
+// Largest work-item count the multi-workgroup fine sweep takes for class size n.
+int fine_group_capacity(int n) {
+  switch (n) {
+    case 128: return 64;
+    default: return 0;
+  }
+}
+
+// Fine sweep of the linear FP64 step on a group of four workgroups per item
+// (2D, n = 128, at most fine_group_capacity(n) items); hipErrorNotSupported
+// otherwise, hipErrorCooperativeLaunchTooLarge when the device cannot hold
+// every workgroup at once.
+hipError_t launch_fine_group(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                             const double* Tg, const double* U_in, double* F_out,
+                             const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                             int in_iter, int32_t* sync, hipStream_t s, int j_steps) {
+  if (n_items <= 0) return hipSuccess;
+  if (n_items > fine_group_capacity(n)) return hipErrorNotSupported;
+  switch (n) {
+    case 128: return fine_group<128, 4, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 // Largest instance count the cooperative chain takes for class size n (0: none).

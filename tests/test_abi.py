@@ -104,3 +104,30 @@ def test_chain_variant_selection_host_only():
     assert st == chlib.CH_OK
     assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     lib.ch_destroy(h)
+
+
+def test_fine_groups_selection_host_only():
+    import workloads
+    from paper_2304_14074_amd import chlib
+    lib, st, h = _create([workloads.Problem(dim=2, n=128, n_slices=64, j_fine=5),
+                          workloads.Problem(dim=2, n=64, n_slices=2, j_fine=5)])
+    assert st == chlib.CH_OK
+    g = ctypes.c_int32(0)
+    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 4
+    assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    g.value = 4
+    assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    g.value = 2
+    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_ERR_ARG
+    g.value = 1
+    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
+    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    lib.ch_destroy(h)
+    # 65 slices, a nonlinear class, a split-precision class: one workgroup per item
+    probs = [workloads.Problem(dim=2, n=128, n_slices=65, j_fine=5),
+             workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5, fine_kind="nonlinear"),
+             workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5, precision="split_bf16")]
+    lib, st, h = _create(probs)
+    assert st == chlib.CH_OK
+    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    lib.ch_destroy(h)

@@ -491,3 +491,43 @@ def test_chain_group_ragged_batch_matches_single_workgroup_chain():
         for i in range(3):
             for j in range(len(Ua[i])):
                 assert np.array_equal(Ua[i][j], Ub[i][j]), (i, j)
+
+
+@pytest.mark.parametrize("groups", [1, 4])
+def test_fine_groups_128_mask_and_oracle(groups):
+    # the n = 128 fine sweep on one workgroup per slice and on a group of
+    # four (spectral Laplacian): masked slices against the oracle, unmasked
+    # slices untouched; five slices fill one group slot set with three idle
+    from paper_2304_14074_amd import chlib
+    n, N, J = 128, 5, 12
+    p = workloads.Problem(dim=2, n=n, eps=0.02, T=N * J * 2e-5, n_slices=N, j_fine=J)
+    ctx = chlib.Context([p])
+    assert ctx.ch_fine_groups(n, groups) == groups
+    X = _states(n, 2, N, seed=5)
+    U = gu.pack_slices(ctx, [X])
+    F = torch.full_like(U, 7.0)
+    mask = torch.tensor([1, 0, 1, 1, 0], dtype=torch.uint8, device="cuda")
+    print(f"fine groups={groups}", flush=True)
+    ctx.ch_fine_propagate(U, F, mask)
+    torch.cuda.synchronize()
+    out = gu.unpack_slices(ctx, F)[0]
+    assert np.all(out[1] == 7.0) and np.all(out[4] == 7.0)
+    for s in (0, 2, 3):
+        ref = propagators.fine(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+
+
+def test_fine_groups_128_f_zero_mode_decay():
+    # f == 0 on the group path: a sine mode decays by rho^J
+    from paper_2304_14074_amd import chlib
+    n, J, dt, eps, s = 128, 40, 2e-5, 0.02, 2.0
+    p = workloads.Problem(dim=2, n=n, eps=eps, T=J * dt, n_slices=1, j_fine=J, f_zero=True)
+    ctx = chlib.Context([p])
+    assert ctx.ch_fine_groups(n) == 4
+    x = np.arange(1, n + 1) / (n + 1)
+    u = np.outer(np.sin(7 * np.pi * x), np.sin(2 * np.pi * x))
+    lam = lambda k: 2 * (n + 1) ** 2 * (np.cos(k * np.pi / (n + 1)) - 1)
+    L = lam(7) + lam(2)
+    rho = (1 - s * dt * L) / (1 + dt * eps ** 2 * L ** 2 - s * dt * L)
+    out = gu.fine(ctx, [u[None]])[0][0]
+    assert gu.rel(out, rho ** J * u) < 1e-12
