@@ -141,21 +141,22 @@ ch_status ch_autotune(ch_ctx* ctx, const double* U_in, double* F_out, int32_t st
 ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each slice of the
- * linear FP64 fine sweep (2.5) for the 2D grid-size class n: 1, or 4 (the
- * sine transforms of every step split over four workgroups that meet at
+ * linear FP64 fine sweep (2.5) for the 2D grid-size class n: 1, 4 or 8 (the
+ * sine transforms of every step split over that many workgroups that meet at
  * device-memory barriers, with the Laplacian applied in the sine basis where
- * it is diagonal; n = 128, at most 64 slices in the class, the default where
- * available; a device that cannot hold all workgroups at once falls back to
- * 1).  Both give the same states to rounding. */
+ * it is diagonal; n = 128, at most 64 slices in the class; 4 is the default
+ * where available, and a device that cannot hold all workgroups at once falls
+ * back to 1).  All give the same states to rounding. */
 ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each instance's
  * sequential coarse sweep of (2.2) for the 2D grid-size class n: 1 (one
- * workgroup per instance) or 4 (the 2D sine transforms of every solve of
- * (2.4) split over four workgroups that meet at device-memory barriers;
- * n = 128, at most 64 instances in the class, the default where available).
- * Both give the same iterates to rounding.  Instances with the stabilised
- * coarse step always use one workgroup. */
+ * workgroup per instance), 4 or 8 (the 2D sine transforms of every solve of
+ * (2.4) split over that many workgroups that meet at device-memory barriers;
+ * n = 128, at most 64 instances in the class; 8 is the default where
+ * available, and a device that cannot hold all workgroups at once falls back
+ * to 1).  All give the same iterates to rounding.  Instances with the
+ * stabilised coarse step always use one workgroup. */
 ch_status ch_chain_variant(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set);
 
 /* hipGraph of one Parareal iteration (after the prediction): captured on

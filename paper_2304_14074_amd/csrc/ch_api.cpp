@@ -239,7 +239,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   for (auto& cp : c->classes) {
     if (cp.dim != 2) continue;
     const int cap = chk::chain_coop_capacity(cp.n);
-    if (cap > 0 && (int)cp.insts.size() <= cap) cp.chain_groups = 4;
+    if (cap > 0 && (int)cp.insts.size() <= cap) cp.chain_groups = 8;
     const int fcap = chk::fine_group_capacity(cp.n);
     if (fcap > 0 && (int)cp.items.size() <= fcap && cp.fine_kind == CH_FINE_LINEAR &&
         cp.precision == CH_PREC_FP64)
@@ -401,8 +401,8 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
     } else if (cp.dim == 2) {
       e = hipErrorNotSupported;
       if (cp.fine_groups > 1) {
-        e = chk::launch_fine_group(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
-                                   mask, active, k_min, in_iter,
+        e = chk::launch_fine_group(cp.n, cp.fine_groups, items, (int)cp.items.size(), inst, tab,
+                                   U_in, F_out, mask, active, k_min, in_iter,
                                    (int32_t*)(c->ws + cp.sync_blk.off), s);
         // a device that cannot hold every workgroup of the group launch at
         // once takes the one-workgroup-per-item kernel
@@ -449,10 +449,19 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     hipError_t e;
     bool coop = cp.dim == 2 && mode != 0 && cp.chain_groups > 1;
     for (int32_t i : cp.insts) coop = coop && c->inst[i].coarse_kind != CH_COARSE_STAB;
+    e = hipErrorNotSupported;
     if (coop) {
-      e = chk::launch_chain_coop(cp.n, mode, insts, (int)cp.insts.size(), inst, tab, U, F, Gold,
-                                 delta, status, active, k, kdev,
+      e = chk::launch_chain_coop(cp.n, cp.chain_groups, mode, insts, (int)cp.insts.size(), inst,
+                                 tab, U, F, Gold, delta, status, active, k, kdev,
                                  (int32_t*)(c->ws + cp.sync_blk.off), s);
+      // a device that cannot hold every workgroup at once takes one per instance
+      if (e == hipErrorCooperativeLaunchTooLarge) {
+        cp.chain_groups = 1;
+        coop = false;
+      }
+    }
+    if (coop) {
+      // launched above
     } else if (cp.dim == 2) {
       e = chk::launch_coarse_2d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
                                 inst, tab, U_in, G_out, mask, U, F, Gold, delta, status,
@@ -657,10 +666,10 @@ ch_status ch_fine_groups(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {
     if (!tunable(cp) || cp.n != n) continue;
     found = true;
     if (set) {
-      if (*groups != 1 && *groups != 4)
-        return fail(c, CH_ERR_ARG, "fine groups must be 1 or 4, got %d", *groups);
+      if (*groups != 1 && *groups != 4 && *groups != 8)
+        return fail(c, CH_ERR_ARG, "fine groups must be 1, 4 or 8, got %d", *groups);
       const int cap = chk::fine_group_capacity(n);
-      if (*groups == 4 && (cap == 0 || (int)cp.items.size() > cap))
+      if (*groups > 1 && (cap == 0 || (int)cp.items.size() > cap))
         return fail(c, CH_ERR_UNSUPPORTED, "no multi-workgroup fine sweep for n = %d with %zu items",
                     n, cp.items.size());
       cp.fine_groups = *groups;
@@ -678,10 +687,10 @@ ch_status ch_chain_variant(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {
     if (cp.dim != 2 || cp.n != n) continue;
     found = true;
     if (set) {
-      if (*groups != 1 && *groups != 4)
-        return fail(c, CH_ERR_ARG, "chain groups must be 1 or 4, got %d", *groups);
+      if (*groups != 1 && *groups != 4 && *groups != 8)
+        return fail(c, CH_ERR_ARG, "chain groups must be 1, 4 or 8, got %d", *groups);
       const int cap = chk::chain_coop_capacity(n);
-      if (*groups == 4 && (cap == 0 || (int)cp.insts.size() > cap))
+      if (*groups > 1 && (cap == 0 || (int)cp.insts.size() > cap))
         return fail(c, CH_ERR_UNSUPPORTED, "no multi-workgroup chain for n = %d with %zu instances",
                     n, cp.insts.size());
       cp.chain_groups = *groups;

@@ -72,14 +72,15 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
 // Linear FP64 fine sweep on a group of four workgroups per work item (2D,
 // n = 128); sync: 512 ints per 8 items (cleared by the launch).
 int fine_group_capacity(int n);
-hipError_t launch_fine_group(int n, const WorkItem* items, int n_items, const InstDev* inst,
-                             const double* Tsin, const double* U_in, double* F_out,
-                             const uint8_t* mask, const int32_t* active, const int32_t* kmin,
-                             int in_iter, int32_t* sync, hipStream_t s, int j_steps = 0);
+hipError_t launch_fine_group(int n, int groups, const WorkItem* items, int n_items,
+                             const InstDev* inst, const double* Tsin, const double* U_in,
+                             double* F_out, const uint8_t* mask, const int32_t* active,
+                             const int32_t* kmin, int in_iter, int32_t* sync, hipStream_t s,
+                             int j_steps = 0);
 // Coarse chain (modes 1, 2) on a group of workgroups per instance (2D n = 128,
 // scheme (2.4)); sync: 512 ints per 8 instances (cleared by the launch).
 int chain_coop_capacity(int n);
-hipError_t launch_chain_coop(int n, int mode, const int32_t* insts, int n_insts,
+hipError_t launch_chain_coop(int n, int groups, int mode, const int32_t* insts, int n_insts,
                              const InstDev* inst, const double* Tsin, double* U, const double* F,
                              double* G_old, double* delta, int32_t* status, const int32_t* active,
                              int k, const int32_t* kdev, int32_t* sync, hipStream_t s);

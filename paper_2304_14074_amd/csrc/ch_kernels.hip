@@ -1152,9 +1152,21 @@ __device__ __forceinline__ void group_sum(double (&v)[K], double* red, CoopCtx& 
     v[i] = s;
   }
 }
+// Store of exchanged data.  With WT the store is a relaxed agent-scope atomic
+// store, which writes through the L2: the release at the next barrier then has
+// no dirty lines of it to write back, which matters when many groups share an
+// XCD's L2 (the write-backs of one group's release then stall the others).
+template <bool WT>
+__device__ __forceinline__ void xg_store(double* p, double v) {
+  if constexpr (WT)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
 // Exchange A: from a column block (left-product output v: rows 0..N-1, block
 // columns C_m) to the transposed row block slab[k][r'] = M[R_m[r']][k].
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool WT = false>
 __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
                                    CoopCtx& cc) {
   using C = GeoC<N, G, NW>;
@@ -1164,7 +1176,7 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
   for (int s = 0; s < C::OWN; ++s) {
     int row, col;
     slab_rc<N, G, NW>(s, row, col);
-    xg[(int64_t)row * N + cc.mem * C::B + col] = v[s];
+    xg_store<WT>(&xg[(int64_t)row * N + cc.mem * C::B + col], v[s]);
   }
   group_barrier<G>(cc);
   // 8 x 8 tiles (8 consecutive k per row, 8 rows per wave instruction): 64-byte
@@ -1192,7 +1204,7 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
 // group reduction of acc[0..K) rides on the same barrier (per-member values
 // posted before it, combined in member order after it): sums, or with MINMAX
 // (K = 2) the minimum of acc[0] and the maximum of acc[1].
-template <int N, int G, int NW, int K, bool MINMAX = false>
+template <int N, int G, int NW, int K, bool MINMAX = false, bool WT = false>
 __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
                                    CoopCtx& cc, double* acc, double* red) {
   using C = GeoC<N, G, NW>;
@@ -1217,7 +1229,7 @@ __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], doubl
     for (int j = 0; j < R; ++j) {
       const int tile = w + NW * j, c = 8 * (tile % (C::B / 8)) + (l >> 3);
       const int a = 8 * (tile / (C::B / 8)) + (l & 7);
-      xg[(int64_t)(cc.mem * C::B + c) * N + a] = tv[j];
+      xg_store<WT>(&xg[(int64_t)(cc.mem * C::B + c) * N + a], tv[j]);
     }
   }
   double* part = cc.part + 64 * cc.psel;
@@ -1480,7 +1492,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
   slab_put<N, G, NW>(Xs, u);
   __syncthreads();
   slab_stage<N, G, NW>(Xs, T, y);
-  xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
+  xchg_rowsT_to_cols<N, G, NW, 0, false, true>(y, Xs, cc, nullptr, nullptr);
   slab_stage<N, G, NW>(Xs, T, uh);
   const int J = j_steps > 0 ? j_steps : P.j_fine;
   const double s1 = 1.0 + P.s_fine;
@@ -1492,7 +1504,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
     slab_put<N, G, NW>(Xs, y);
     __syncthreads();
     slab_stage<N, G, NW>(Xs, T, y);
-    xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
+    xchg_rowsT_to_cols<N, G, NW, 0, false, true>(y, Xs, cc, nullptr, nullptr);
     slab_stage<N, G, NW>(Xs, T, y);   // g_hat, column block
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s)
@@ -1501,7 +1513,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
     slab_put<N, G, NW>(Xs, uh);
     __syncthreads();
     slab_stage<N, G, NW>(Xs, T, y);
-    xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
+    xchg_cols_to_rowsT<N, G, NW, true>(y, Xs, cc);
     slab_stage<N, G, NW>(Xs, T, u);   // new state, row block
   }
 #pragma unroll
@@ -2919,14 +2931,16 @@ int fine_group_capacity(int n) {
 // (2D, n = 128, at most fine_group_capacity(n) items); hipErrorNotSupported
 // otherwise, hipErrorCooperativeLaunchTooLarge when the device cannot hold
 // every workgroup at once.
-hipError_t launch_fine_group(int n, const WorkItem* items, int n_items, const InstDev* inst,
-                             const double* Tg, const double* U_in, double* F_out,
-                             const uint8_t* mask, const int32_t* active, const int32_t* kmin,
-                             int in_iter, int32_t* sync, hipStream_t s, int j_steps) {
+hipError_t launch_fine_group(int n, int groups, const WorkItem* items, int n_items,
+                             const InstDev* inst, const double* Tg, const double* U_in,
+                             double* F_out, const uint8_t* mask, const int32_t* active,
+                             const int32_t* kmin, int in_iter, int32_t* sync, hipStream_t s,
+                             int j_steps) {
   if (n_items <= 0) return hipSuccess;
   if (n_items > fine_group_capacity(n)) return hipErrorNotSupported;
-  switch (n) {
-    case 128: return fine_group<128, 4, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+  switch (n * 100 + groups) {
+    case 12804: return fine_group<128, 4, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+    case 12808: return fine_group<128, 8, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
     default: return hipErrorNotSupported;
   }
 }
@@ -2941,15 +2955,16 @@ int chain_coop_capacity(int n) {
 
 // Coarse chain on a group of workgroups per instance (2D, n = 128, scheme
 // (2.4) only); hipErrorNotSupported for other sizes.
-hipError_t launch_chain_coop(int n, int mode, const int32_t* insts, int n_insts,
+hipError_t launch_chain_coop(int n, int groups, int mode, const int32_t* insts, int n_insts,
                              const InstDev* inst, const double* Tg, double* U, const double* F,
                              double* G_old, double* delta, int32_t* status, const int32_t* active,
                              int k, const int32_t* kdev, int32_t* sync, hipStream_t s) {
   if (n_insts <= 0) return hipSuccess;
   if (n_insts > chain_coop_capacity(n)) return hipErrorNotSupported;
   const double* lam = Tg + 2 * (n + 1);
-  switch (n) {
-    case 128: return chain_coop<128, 4, 4>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
+  switch (n * 100 + groups) {
+    case 12804: return chain_coop<128, 4, 4>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
+    case 12808: return chain_coop<128, 8, 4>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
     default: return hipErrorNotSupported;
   }
 }

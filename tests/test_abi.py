@@ -88,12 +88,14 @@ def test_chain_variant_selection_host_only():
     lib, st, h = _create(probs)
     assert st == chlib.CH_OK
     g = ctypes.c_int32(0)
-    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 4
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 8
     assert lib.ch_chain_variant(h, 64, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     g.value = 4
     assert lib.ch_chain_variant(h, 64, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
     g.value = 3
     assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 1) == chlib.CH_ERR_ARG
+    g.value = 8
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
     g.value = 1
     assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
     assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
@@ -119,6 +121,8 @@ def test_fine_groups_selection_host_only():
     assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
     g.value = 2
     assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_ERR_ARG
+    g.value = 8
+    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
     g.value = 1
     assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
     assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1

@@ -408,10 +408,10 @@ def test_streamed_256_nonlinear_energy_decays():
     assert np.all(np.isfinite(out)) and e1 < e0
 
 
-@pytest.mark.parametrize("groups", [1, 4])
+@pytest.mark.parametrize("groups", [1, 4, 8])
 def test_chain_variants_parareal_128_match_oracle(groups):
     # the coarse sweep of (2.2) on one workgroup per instance and split over a
-    # group of four workgroups: both against the oracle's iterates
+    # group of four or eight workgroups: all against the oracle's iterates
     from paper_2304_14074_amd import chlib
     N, J, n = 4, 8, 128
     p = workloads.Problem(dim=2, n=n, eps=0.02, T=N * J * 2e-5, n_slices=N, j_fine=J)
@@ -493,10 +493,10 @@ def test_chain_group_ragged_batch_matches_single_workgroup_chain():
                 assert np.array_equal(Ua[i][j], Ub[i][j]), (i, j)
 
 
-@pytest.mark.parametrize("groups", [1, 4])
+@pytest.mark.parametrize("groups", [1, 4, 8])
 def test_fine_groups_128_mask_and_oracle(groups):
-    # the n = 128 fine sweep on one workgroup per slice and on a group of
-    # four (spectral Laplacian): masked slices against the oracle, unmasked
+    # the n = 128 fine sweep on one workgroup per slice and on groups of four
+    # or eight (spectral Laplacian): masked slices against the oracle, unmasked
     # slices untouched; five slices fill one group slot set with three idle
     from paper_2304_14074_amd import chlib
     n, N, J = 128, 5, 12
