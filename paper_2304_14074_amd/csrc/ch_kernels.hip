@@ -2939,7 +2939,9 @@ hipError_t launch_fine_group(int n, int groups, const WorkItem* items, int n_ite
   if (n_items <= 0) return hipSuccess;
   if (n_items > fine_group_capacity(n)) return hipErrorNotSupported;
   switch (n * 100 + groups) {
-    case 12804: return fine_group<128, 4, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+    // eight waves per workgroup at G = 4 (two per SIMD hide LDS and exchange
+    // latency; measured 9% faster than four); G = 8 allows only four
+    case 12804: return fine_group<128, 4, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
     case 12808: return fine_group<128, 8, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
     default: return hipErrorNotSupported;
   }
