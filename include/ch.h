@@ -141,12 +141,14 @@ ch_status ch_autotune(ch_ctx* ctx, const double* U_in, double* F_out, int32_t st
 ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each slice of the
- * linear FP64 fine sweep (2.5) for the 2D grid-size class n: 1, 4 or 8 (the
- * sine transforms of every step split over that many workgroups that meet at
- * device-memory barriers, with the Laplacian applied in the sine basis where
- * it is diagonal; n = 128, at most 64 slices in the class; 4 is the default
- * where available, and a device that cannot hold all workgroups at once falls
- * back to 1).  All give the same states to rounding. */
+ * linear FP64 fine sweep (2.5) for the 2D grid-size class n: 1, or a group of
+ * 4 or 8 (n = 128) or 8 (n = 256) that splits the sine transforms of every
+ * step and meets at device-memory barriers, with the Laplacian applied in
+ * the sine basis where it is diagonal.  The group kernel is persistent over
+ * the slices.  Defaults: 4 at n = 128 with at most 64 slices in the class, 8
+ * at n = 256, else 1; a device that cannot hold a group falls back to 1.
+ * All give the same states to rounding.  CH_ERR_UNSUPPORTED for a group
+ * size the grid size has no kernel for. */
 ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each instance's

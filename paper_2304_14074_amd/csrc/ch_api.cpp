@@ -243,7 +243,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     const int fcap = chk::fine_group_capacity(cp.n);
     if (fcap > 0 && (int)cp.items.size() <= fcap && cp.fine_kind == CH_FINE_LINEAR &&
         cp.precision == CH_PREC_FP64)
-      cp.fine_groups = 4;
+      cp.fine_groups = chk::fine_group_default(cp.n);
     const size_t units = std::max(cp.insts.size(), cp.items.size());
     cp.sync_blk = take(sizeof(int32_t) * 64 * 8 * ((units + 7) / 8));
   }
@@ -663,15 +663,17 @@ ch_status ch_fine_groups(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {
   if (!c || !groups) return CH_ERR_ARG;
   bool found = false;
   for (auto& cp : c->classes) {
-    if (!tunable(cp) || cp.n != n) continue;
+    if (cp.dim != 2 || cp.fine_kind != CH_FINE_LINEAR || cp.precision != CH_PREC_FP64 ||
+        cp.n != n)
+      continue;
     found = true;
     if (set) {
+      const bool ok = *groups == 1 || (n == 128 && (*groups == 4 || *groups == 8)) ||
+                      (n == 256 && *groups == 8);
       if (*groups != 1 && *groups != 4 && *groups != 8)
         return fail(c, CH_ERR_ARG, "fine groups must be 1, 4 or 8, got %d", *groups);
-      const int cap = chk::fine_group_capacity(n);
-      if (*groups > 1 && (cap == 0 || (int)cp.items.size() > cap))
-        return fail(c, CH_ERR_UNSUPPORTED, "no multi-workgroup fine sweep for n = %d with %zu items",
-                    n, cp.items.size());
+      if (!ok)
+        return fail(c, CH_ERR_UNSUPPORTED, "no %d-workgroup fine sweep for n = %d", *groups, n);
       cp.fine_groups = *groups;
     } else {
       *groups = cp.fine_groups;

@@ -69,9 +69,12 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
                             const uint8_t* mask, double* U, const double* F, double* G_old,
                             double* delta, int32_t* status, const int32_t* active, int k,
                             const int32_t* kdev, hipStream_t s);
-// Linear FP64 fine sweep on a group of four workgroups per work item (2D,
-// n = 128); sync: 512 ints per 8 items (cleared by the launch).
+// Linear FP64 fine sweep on groups of workgroups (2D, n = 128 or 256),
+// persistent over the work items; sync: 512 ints per 8 items (cleared by the
+// launch).  fine_group_capacity: largest item count for which it is the
+// default; fine_group_default: the default group size.
 int fine_group_capacity(int n);
+int fine_group_default(int n);
 hipError_t launch_fine_group(int n, int groups, const WorkItem* items, int n_items,
                              const InstDev* inst, const double* Tsin, const double* U_in,
                              double* F_out, const uint8_t* mask, const int32_t* active,

@@ -17,6 +17,7 @@
 // S[a][b] depends only on (a+1)(b+1) mod 2(n+1), so each lane walks the table
 // with an incremental index instead of holding rows of S in registers.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 #include "ch_internal.h"
 
@@ -1035,6 +1036,10 @@ __device__ __forceinline__ void slab_stage(const double* Xs, const double* T,
       ie -= (ie >= C::P2) ? C::P2 : 0;
       io += step;
       io -= (io >= C::P2) ? C::P2 : 0;
+      // at 32 k-steps keep the compiler from precomputing every k-step's
+      // table index up front (64 index registers held through the stage
+      // spill at n = 256; at 16 k-steps the precomputed indices are faster)
+      if constexpr (C::KS > 16) asm volatile("" : "+v"(ie), "+v"(io));
       nse = T[ie];
       nso = T[io];
       const double* pe = base + (8 * (ks + 1)) * C::LDB;
@@ -1427,14 +1432,16 @@ __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const
   }
 }
 
-// Fine sweep of the linear step (2.5) on a group of G workgroups per work
-// item (same XCD mapping and barriers as the coarse sweep).  Since the 5-point
-// Laplacian is diagonal in the sine basis (eigenvalues lam_p + lam_q), one step
+// Fine sweep of the linear step (2.5) on groups of G workgroups (same XCD
+// mapping and barriers as the coarse sweep).  Since the 5-point Laplacian is
+// diagonal in the sine basis (eigenvalues lam_p + lam_q), one step
 //   (I + dt eps^2 Lap^2 - s dt Lap) v = u + dt Lap g,   g = f(u) - s u,
 // is, with hats for S . S,  v_hat = (u_hat + dt lam g_hat) / sigma:  one
 // forward transform of g and one inverse transform per step.  u_hat stays in
 // registers (column block); u in slab form (row block) for the pointwise g.
-// On a barrier time-out the instance's status word gets bit 4.
+// Persistent: the grid holds as many groups as can be resident at once and
+// group q takes work items q, q + groups, ...  On a barrier time-out the
+// instance's status word gets bit 4.
 template <int N, int G, int NW>
 __global__ void __launch_bounds__(NW * 64)
 k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __restrict__ inst,
@@ -1446,79 +1453,84 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
   extern __shared__ double smem[];
   double* Xs = smem;
   double* T = smem + N * C::LDB;
-  double* Rs = T + C::P2;            // 1 / sigma      [s * NT + thread]
-  double* Tl = Rs + C::OWN * C::NT;  // dt * lam (2D) [s * NT + thread]
+  double* lamS = T + C::P2;
+  double* Rs = lamS + N;             // 1 / sigma of the current item [s * NT + thread]
   const int xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
   const int mem = rest % G, grp = rest / G;
-  const int idx = grp * 8 + xcd;
-  if (idx >= n_items) return;
-  const WorkItem it = items[idx];
-  const InstDev P = inst[it.inst];
-  if (mask && !mask[P.slice_base + it.slice]) return;
-  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
+  const int idx = grp * 8 + xcd;                  // group index
+  const int n_groups = gridDim.x / G;
   const int64_t NN = (int64_t)N * N;
+  const int t = threadIdx.x;
+  for (int m = t; m < C::P2; m += C::NT) T[m] = Tg[m];
+  for (int m = t; m < N; m += C::NT) lamS[m] = lam[m];
+  __syncthreads();
   CoopCtx cc;
   cc.cnt = sync + idx * 64;
-  cc.xg = P.work + (int64_t)it.slice * P.work_vecs * NN;   // the item's work vectors
-  cc.part = cc.xg + 2 * NN;
   cc.mem = mem;
   cc.ok = 1;
   cc.xsel = 0;
   cc.psel = 0;
   cc.nb = 0;
-  const int t = threadIdx.x;
-  for (int m = t; m < C::P2; m += C::NT) T[m] = Tg[m];
-#pragma unroll
-  for (int s = 0; s < C::OWN; ++s) {
-    int row, col;
-    slab_rc<N, G, NW>(s, row, col);
-    const int64_t o = (int64_t)row * N + mem * C::B + col;
-    Rs[s * C::NT + t] = P.rsig_fine[o];
-    Tl[s * C::NT + t] = P.dt * (lam[row] + lam[mem * C::B + col]);
-  }
-  const int64_t off = P.off_slices + (int64_t)it.slice * NN;
-  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
   // slab-form element (a, c) is u[R_m[c]][a]
   auto gidx = [&](int s) {
     int row, col;
     slab_rc<N, G, NW>(s, row, col);
     return (int64_t)(mem * C::B + col) * N + row;
   };
-  double u[C::OWN], uh[C::OWN], y[C::OWN];
+  for (int item = idx; item < n_items; item += n_groups) {
+    const WorkItem it = items[item];
+    const InstDev P = inst[it.inst];
+    if (mask && !mask[P.slice_base + it.slice]) continue;
+    if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) continue;
+    cc.xg = P.work + (int64_t)it.slice * P.work_vecs * NN;   // the item's work vectors
+    cc.part = cc.xg + 2 * NN;
+    const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+    const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
+    double u[C::OWN], uh[C::OWN], y[C::OWN];
+    __syncthreads();   // every wave is done with the slab and Rs of the previous item
 #pragma unroll
-  for (int s = 0; s < C::OWN; ++s) u[s] = U_in[off_in + gidx(s)];
-  __syncthreads();
-  // u_hat = S u S (right product on the row block, exchange, left product)
-  slab_put<N, G, NW>(Xs, u);
-  __syncthreads();
-  slab_stage<N, G, NW>(Xs, T, y);
-  xchg_rowsT_to_cols<N, G, NW, 0, false, true>(y, Xs, cc, nullptr, nullptr);
-  slab_stage<N, G, NW>(Xs, T, uh);
-  const int J = j_steps > 0 ? j_steps : P.j_fine;
-  const double s1 = 1.0 + P.s_fine;
-  for (int m = 0; m < J; ++m) {
-#pragma unroll
-    for (int s = 0; s < C::OWN; ++s)
-      y[s] = P.f_zero ? (-P.s_fine * u[s]) : (u[s] * u[s] * u[s] - s1 * u[s]);
-    __syncthreads();
-    slab_put<N, G, NW>(Xs, y);
+    for (int s = 0; s < C::OWN; ++s) {
+      int row, col;
+      slab_rc<N, G, NW>(s, row, col);
+      Rs[s * C::NT + t] = P.rsig_fine[(int64_t)row * N + mem * C::B + col];   // column block
+      u[s] = U_in[off_in + gidx(s)];
+    }
+    // u_hat = S u S (right product on the row block, exchange, left product)
+    slab_put<N, G, NW>(Xs, u);
     __syncthreads();
     slab_stage<N, G, NW>(Xs, T, y);
     xchg_rowsT_to_cols<N, G, NW, 0, false, true>(y, Xs, cc, nullptr, nullptr);
-    slab_stage<N, G, NW>(Xs, T, y);   // g_hat, column block
+    slab_stage<N, G, NW>(Xs, T, uh);
+    const int J = j_steps > 0 ? j_steps : P.j_fine;
+    const double s1 = 1.0 + P.s_fine;
+    for (int m = 0; m < J; ++m) {
 #pragma unroll
-    for (int s = 0; s < C::OWN; ++s)
-      uh[s] = Rs[s * C::NT + t] * (uh[s] + Tl[s * C::NT + t] * y[s]);
-    __syncthreads();
-    slab_put<N, G, NW>(Xs, uh);
-    __syncthreads();
-    slab_stage<N, G, NW>(Xs, T, y);
-    xchg_cols_to_rowsT<N, G, NW, true>(y, Xs, cc);
-    slab_stage<N, G, NW>(Xs, T, u);   // new state, row block
+      for (int s = 0; s < C::OWN; ++s)
+        y[s] = P.f_zero ? (-P.s_fine * u[s]) : (u[s] * u[s] * u[s] - s1 * u[s]);
+      __syncthreads();
+      slab_put<N, G, NW>(Xs, y);
+      __syncthreads();
+      slab_stage<N, G, NW>(Xs, T, y);
+      xchg_rowsT_to_cols<N, G, NW, 0, false, true>(y, Xs, cc, nullptr, nullptr);
+      slab_stage<N, G, NW>(Xs, T, y);   // g_hat, column block
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) {
+        int row, col;
+        slab_rc<N, G, NW>(s, row, col);
+        const double tl = P.dt * (lamS[row] + lamS[mem * C::B + col]);
+        uh[s] = Rs[s * C::NT + t] * (uh[s] + tl * y[s]);
+      }
+      __syncthreads();
+      slab_put<N, G, NW>(Xs, uh);
+      __syncthreads();
+      slab_stage<N, G, NW>(Xs, T, y);
+      xchg_cols_to_rowsT<N, G, NW, true>(y, Xs, cc);
+      slab_stage<N, G, NW>(Xs, T, u);   // new state, row block
+    }
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = u[s];
+    if (!cc.ok && t == 0 && mem == 0) atomicOr(P.status, 4);
   }
-#pragma unroll
-  for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = u[s];
-  if (!cc.ok && t == 0 && mem == 0) atomicOr(P.status, 4);
 }
 
 // Cooperative chain (modes 1 and 2 of k_coarse_2d) for scheme (2.4), n = N.
@@ -2898,7 +2910,7 @@ static hipError_t fine_group(const WorkItem* items, int n_items, const InstDev* 
                              const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                              int in_iter, int j_steps, int32_t* sync, hipStream_t s) {
   using C = GeoC<N, G, NW>;
-  const size_t lds = ((size_t)N * C::LDB + C::P2 + 2 * (size_t)C::OWN * C::NT) * sizeof(double);
+  const size_t lds = ((size_t)N * C::LDB + C::P2 + N + (size_t)C::OWN * C::NT) * sizeof(double);
   const void* fn = (const void*)k_fine_group<N, G, NW>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -2908,10 +2920,13 @@ static hipError_t fine_group(const WorkItem* items, int n_items, const InstDev* 
     return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NW * 64, lds)) != hipSuccess)
     return e;
-  const int groups = (n_items + 7) / 8;
-  const int grid = 8 * G * groups;
-  if (grid > cus * per_cu) return hipErrorCooperativeLaunchTooLarge;
-  const int words = 64 * 8 * groups;
+  // groups in multiples of eight (one per XCD), as many as fit at once, at
+  // most one per work item (rounded up to eight)
+  const int fit8 = cus * per_cu / (8 * G);
+  if (fit8 < 1) return hipErrorCooperativeLaunchTooLarge;
+  const int groups8 = std::min((n_items + 7) / 8, fit8);
+  const int grid = 8 * G * groups8;
+  const int words = 64 * 8 * groups8;
   hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
   const double* lam = Tg + 2 * (N + 1);
   hipLaunchKernelGGL((k_fine_group<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, items, n_items,
@@ -2919,30 +2934,37 @@ static hipError_t fine_group(const WorkItem* items, int n_items, const InstDev* 
   return hipGetLastError();
 }
 
-// Largest work-item count the multi-workgroup fine sweep takes for class size n.
+// Largest work-item count for which the multi-workgroup fine sweep is the
+// default for class size n (0: never).  The kernel is persistent and takes
+// any count; at n = 128 one workgroup per slice is faster once the slices
+// alone fill the device, at n = 256 the group kernel (state on chip in the
+// members' slabs) beats the streamed one-workgroup kernel at any count.
 int fine_group_capacity(int n) {
   switch (n) {
     case 128: return 64;
+    case 256: return 1 << 30;
     default: return 0;
   }
 }
 
-// Fine sweep of the linear FP64 step on a group of four workgroups per item
-// (2D, n = 128, at most fine_group_capacity(n) items); hipErrorNotSupported
-// otherwise, hipErrorCooperativeLaunchTooLarge when the device cannot hold
-// every workgroup at once.
+// Default group size for class size n.
+int fine_group_default(int n) { return n == 256 ? 8 : 4; }
+
+// Fine sweep of the linear FP64 step on groups of workgroups (2D, n = 128:
+// G = 4 or 8; n = 256: G = 8); hipErrorNotSupported for other shapes,
+// hipErrorCooperativeLaunchTooLarge when no group fits on the device.
 hipError_t launch_fine_group(int n, int groups, const WorkItem* items, int n_items,
                              const InstDev* inst, const double* Tg, const double* U_in,
                              double* F_out, const uint8_t* mask, const int32_t* active,
                              const int32_t* kmin, int in_iter, int32_t* sync, hipStream_t s,
                              int j_steps) {
   if (n_items <= 0) return hipSuccess;
-  if (n_items > fine_group_capacity(n)) return hipErrorNotSupported;
   switch (n * 100 + groups) {
     // eight waves per workgroup at G = 4 (two per SIMD hide LDS and exchange
-    // latency; measured 9% faster than four); G = 8 allows only four
+    // latency; measured 9% faster than four); G = 8 allows only four at n = 128
     case 12804: return fine_group<128, 4, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
     case 12808: return fine_group<128, 8, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+    case 25608: return fine_group<256, 8, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
     default: return hipErrorNotSupported;
   }
 }

@@ -119,6 +119,8 @@ def test_fine_groups_selection_host_only():
     assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     g.value = 4
     assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    g.value = 1
+    assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 1) == chlib.CH_OK
     g.value = 2
     assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_ERR_ARG
     g.value = 8
@@ -127,11 +129,16 @@ def test_fine_groups_selection_host_only():
     assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
     assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     lib.ch_destroy(h)
-    # 65 slices, a nonlinear class, a split-precision class: one workgroup per item
+    # 65 slices, a nonlinear class, a split-precision class: one workgroup per
+    # item at n = 128; n = 256 takes groups of eight at any slice count
     probs = [workloads.Problem(dim=2, n=128, n_slices=65, j_fine=5),
              workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5, fine_kind="nonlinear"),
-             workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5, precision="split_bf16")]
+             workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5, precision="split_bf16"),
+             workloads.Problem(dim=2, n=256, n_slices=300, j_fine=5)]
     lib, st, h = _create(probs)
     assert st == chlib.CH_OK
     assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    assert lib.ch_fine_groups(h, 256, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 8
+    g.value = 4
+    assert lib.ch_fine_groups(h, 256, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
     lib.ch_destroy(h)

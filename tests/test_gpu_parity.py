@@ -312,12 +312,16 @@ def test_split_bf16_full_slice_128():
     assert err < SPLIT_TOL, err
 
 
-def test_streamed_256_fine_matches_oracle():
-    # n = 256 streams the state through global memory (does not fit on a CU)
+@pytest.mark.parametrize("groups", [1, 8])
+def test_streamed_256_fine_matches_oracle(groups):
+    # n = 256: one workgroup per slice streams the state through global memory
+    # (it does not fit on a CU); a group of eight keeps it in the members' LDS
     from paper_2304_14074_amd import chlib
     J = 8
     p = workloads.Problem(dim=2, n=256, eps=0.015, T=2 * J * 1e-5, n_slices=2, j_fine=J)
     ctx = chlib.Context([p])
+    assert ctx.ch_fine_groups(256, groups) == groups
+    print(f"n=256 fine groups={groups}", flush=True)
     rng = np.random.default_rng(256)
     X = np.stack([0.25 + 0.05 * rng.standard_normal((256, 256)), 0.9 * rng.uniform(-1, 1, (256, 256))])
     out = gu.fine(ctx, [X])[0]
@@ -531,3 +535,23 @@ def test_fine_groups_128_f_zero_mode_decay():
     rho = (1 - s * dt * L) / (1 + dt * eps ** 2 * L ** 2 - s * dt * L)
     out = gu.fine(ctx, [u[None]])[0][0]
     assert gu.rel(out, rho ** J * u) < 1e-12
+
+
+def test_fine_groups_persistent_over_more_slices_than_groups():
+    # 300 slices on groups of four: the resident groups (at most 64 on a
+    # 256-CU device) each take several slices in turn; every slice agrees with
+    # the one-workgroup kernel, two sampled ones with the oracle
+    from paper_2304_14074_amd import chlib
+    n, N, J = 128, 300, 3
+    p = workloads.Problem(dim=2, n=n, eps=0.02, T=N * J * 2e-5, n_slices=N, j_fine=J)
+    X = _states(n, 2, N, seed=17)
+    outs = {}
+    for groups in (4, 1):
+        ctx = chlib.Context([p])
+        assert ctx.ch_fine_groups(n, groups) == groups
+        print(f"persistent fine groups={groups}", flush=True)
+        outs[groups] = gu.fine(ctx, [X])[0]
+    for s_ in range(N):
+        assert gu.rel(outs[4][s_], outs[1][s_]) < TOL, s_
+    for s_ in (0, 299):
+        assert gu.rel(outs[4][s_], propagators.fine(p, X[s_])) < TOL, s_
