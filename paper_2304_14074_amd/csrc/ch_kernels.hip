@@ -1098,14 +1098,21 @@ struct CoopCtx {
 
 // Barrier of the G members of one group: barrier b is passed once the
 // counter reaches G (b + 1).  Each wave first waits until its own stores are
-// acknowledged (s_waitcnt vmcnt(0): they have reached the L2); after the
-// workgroup barrier one thread arrives with an agent-scope release (an L2
-// write-back before the atomic), polls, and takes one agent-scope acquire
-// fence (L1/L2 invalidate) before the workgroup proceeds.
-// The spin is bounded by the wall clock (about 0.2 s): on time-out the member
-// clears cc.ok and every later barrier of the launch returns at once, so a
-// lost member can never hang the kernel; the host sees the failure in the
-// status word.
+// acknowledged (s_waitcnt vmcnt(0)).  Then one thread arrives, polls and
+// leaves; the spin is bounded by the wall clock (about 0.2 s): on time-out
+// the member clears cc.ok and every later barrier of the launch returns at
+// once, so a lost member can never hang the kernel; the host sees the failure
+// in the status word.
+// Ordering of the exchanged data: every value that crosses members (exchange
+// matrices, partial sums) is written and read with agent-scope atomics
+// (xg_store, xg_load), which go to the device coherence point (write-through
+// stores, loads that bypass L1/L2).  A store's vmcnt acknowledgement comes
+// from that point, so after the waits every member's data is there before its
+// counter increment is issued, and loads issued after the counter was seen
+// return it.  No cache maintenance is needed: this is the acknowledgement the
+// compiler's agent-scope release sequence relies on, without the L2
+// write-back and invalidate that only non-atomic data needs (those stall the
+// other groups sharing an XCD's L2: measured 18% per fine step).
 template <int G>
 __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0) (gfx9 encoding; lgkm/exp not waited)
@@ -1116,7 +1123,7 @@ __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
     if (ok) {
       const int target = G * (cc.nb + 1);
       const int arrived =
-          __hip_atomic_fetch_add(cc.cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(cc.cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (arrived != target - 1) {
         const uint64_t t0 = wall_clock64();
         while (__hip_atomic_load(cc.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -1124,13 +1131,21 @@ __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     ok_s = ok;
   }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);   // no compiler motion across the poll
   __syncthreads();
   cc.ok = ok_s;
   cc.nb += 1;
+}
+
+// Store and load of data that crosses group members (see group_barrier).
+__device__ __forceinline__ void xg_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xg_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Group-wide sum of K values in a fixed order (partials exchanged in memory,
@@ -1142,13 +1157,13 @@ __device__ __forceinline__ void group_sum(double (&v)[K], double* red, CoopCtx& 
   cc.psel ^= 1;
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < K; ++i) part[i * 8 + cc.mem] = v[i];
+    for (int i = 0; i < K; ++i) xg_store(&part[i * 8 + cc.mem], v[i]);
   group_barrier<G>(cc);
   double pv[K][G];
 #pragma unroll
   for (int i = 0; i < K; ++i)
 #pragma unroll
-    for (int m = 0; m < G; ++m) pv[i][m] = __builtin_nontemporal_load(&part[i * 8 + m]);
+    for (int m = 0; m < G; ++m) pv[i][m] = xg_load(&part[i * 8 + m]);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     double s = 0.0;
@@ -1157,21 +1172,9 @@ __device__ __forceinline__ void group_sum(double (&v)[K], double* red, CoopCtx& 
     v[i] = s;
   }
 }
-// Store of exchanged data.  With WT the store is a relaxed agent-scope atomic
-// store, which writes through the L2: the release at the next barrier then has
-// no dirty lines of it to write back, which matters when many groups share an
-// XCD's L2 (the write-backs of one group's release then stall the others).
-template <bool WT>
-__device__ __forceinline__ void xg_store(double* p, double v) {
-  if constexpr (WT)
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else
-    *p = v;
-}
-
 // Exchange A: from a column block (left-product output v: rows 0..N-1, block
 // columns C_m) to the transposed row block slab[k][r'] = M[R_m[r']][k].
-template <int N, int G, int NW, bool WT = false>
+template <int N, int G, int NW>
 __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
                                    CoopCtx& cc) {
   using C = GeoC<N, G, NW>;
@@ -1181,7 +1184,7 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
   for (int s = 0; s < C::OWN; ++s) {
     int row, col;
     slab_rc<N, G, NW>(s, row, col);
-    xg_store<WT>(&xg[(int64_t)row * N + cc.mem * C::B + col], v[s]);
+    xg_store(&xg[(int64_t)row * N + cc.mem * C::B + col], v[s]);
   }
   group_barrier<G>(cc);
   // 8 x 8 tiles (8 consecutive k per row, 8 rows per wave instruction): 64-byte
@@ -1193,7 +1196,7 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
   for (int j = 0; j < R; ++j) {
     const int tile = w + NW * j, rr = 8 * (tile % (C::B / 8)) + (l >> 3);
     const int k = 8 * (tile / (C::B / 8)) + (l & 7);
-    t[j] = __builtin_nontemporal_load(&xg[(int64_t)(cc.mem * C::B + rr) * N + k]);
+    t[j] = xg_load(&xg[(int64_t)(cc.mem * C::B + rr) * N + k]);
   }
 #pragma unroll
   for (int j = 0; j < R; ++j) {
@@ -1209,7 +1212,7 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
 // group reduction of acc[0..K) rides on the same barrier (per-member values
 // posted before it, combined in member order after it): sums, or with MINMAX
 // (K = 2) the minimum of acc[0] and the maximum of acc[1].
-template <int N, int G, int NW, int K, bool MINMAX = false, bool WT = false>
+template <int N, int G, int NW, int K, bool MINMAX = false>
 __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
                                    CoopCtx& cc, double* acc, double* red) {
   using C = GeoC<N, G, NW>;
@@ -1234,7 +1237,7 @@ __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], doubl
     for (int j = 0; j < R; ++j) {
       const int tile = w + NW * j, c = 8 * (tile % (C::B / 8)) + (l >> 3);
       const int a = 8 * (tile / (C::B / 8)) + (l & 7);
-      xg_store<WT>(&xg[(int64_t)(cc.mem * C::B + c) * N + a], tv[j]);
+      xg_store(&xg[(int64_t)(cc.mem * C::B + c) * N + a], tv[j]);
     }
   }
   double* part = cc.part + 64 * cc.psel;
@@ -1249,20 +1252,20 @@ __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], doubl
     cc.psel ^= 1;
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int i = 0; i < K; ++i) part[i * 8 + cc.mem] = v2[i];
+      for (int i = 0; i < K; ++i) xg_store(&part[i * 8 + cc.mem], v2[i]);
   }
   group_barrier<G>(cc);
   double t[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     const int i = threadIdx.x + j * C::NT, k = i / C::B, c = i % C::B;
-    t[j] = __builtin_nontemporal_load(&xg[(int64_t)k * N + cc.mem * C::B + c]);
+    t[j] = xg_load(&xg[(int64_t)k * N + cc.mem * C::B + c]);
   }
   if constexpr (K > 0) {
     // lane i G + m of every wave loads member m's value i; the wave then
     // combines them by shuffles in member order
     static_assert(K * G <= 64, "one value per lane");
-    const double pl = l < K * G ? __builtin_nontemporal_load(&part[(l / G) * 8 + l % G]) : 0.0;
+    const double pl = l < K * G ? xg_load(&part[(l / G) * 8 + l % G]) : 0.0;
     if constexpr (MINMAX) {
       double a = 1e300, b = -1e300;
 #pragma unroll
@@ -1499,7 +1502,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
     slab_put<N, G, NW>(Xs, u);
     __syncthreads();
     slab_stage<N, G, NW>(Xs, T, y);
-    xchg_rowsT_to_cols<N, G, NW, 0, false, true>(y, Xs, cc, nullptr, nullptr);
+    xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
     slab_stage<N, G, NW>(Xs, T, uh);
     const int J = j_steps > 0 ? j_steps : P.j_fine;
     const double s1 = 1.0 + P.s_fine;
@@ -1511,7 +1514,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
       slab_put<N, G, NW>(Xs, y);
       __syncthreads();
       slab_stage<N, G, NW>(Xs, T, y);
-      xchg_rowsT_to_cols<N, G, NW, 0, false, true>(y, Xs, cc, nullptr, nullptr);
+      xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
       slab_stage<N, G, NW>(Xs, T, y);   // g_hat, column block
 #pragma unroll
       for (int s = 0; s < C::OWN; ++s) {
@@ -1524,7 +1527,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
       slab_put<N, G, NW>(Xs, uh);
       __syncthreads();
       slab_stage<N, G, NW>(Xs, T, y);
-      xchg_cols_to_rowsT<N, G, NW, true>(y, Xs, cc);
+      xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
       slab_stage<N, G, NW>(Xs, T, u);   // new state, row block
     }
 #pragma unroll
