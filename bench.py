@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes of one fine-sweep launch of the 128x128 workload, from FETCH_SIZE and
 # WRITE_SIZE counter runs calibrated by a 1 GiB copy, for the kernel as it is now;
 # set to None whenever the fine kernel changes until the counters are taken again.
-FINE_LAUNCH_TRAFFIC_BYTES = (12826381.6 * 2.0 + 25649592.0) * 1024
+FINE_LAUNCH_TRAFFIC_BYTES = (12826042.4 * 2.0 + 25649592.0) * 1024
 
 
 def fine_flops_per_point_step(n: int) -> float:
