@@ -141,15 +141,18 @@ ch_status ch_autotune(ch_ctx* ctx, const double* U_in, double* F_out, int32_t st
 ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each slice of the
- * linear FP64 fine sweep (2.5) for the 2D grid-size class n: 1, or a group of
- * 4 or 8 (n = 128) or 8 (n = 256) that splits the sine transforms of every
- * step and meets at device-memory barriers, with the Laplacian applied in
- * the sine basis where it is diagonal.  The group kernel is persistent over
- * the slices.  Defaults: 4 at n = 128 with at most 64 slices in the class, 8
- * at n = 256, else 1; a device that cannot hold a group falls back to 1.
- * All give the same states to rounding.  CH_ERR_UNSUPPORTED for a group
- * size the grid size has no kernel for. */
-ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set);
+ * FP64 fine sweep for the 2D class of grid size n and fine step fine_kind
+ * (CH_FINE_LINEAR or CH_FINE_NONLINEAR):
+ * 1, or a group that splits the sine transforms of every step and meets at
+ * device-memory barriers.  Linear step (2.5), with the Laplacian applied in
+ * the sine basis where it is diagonal: 4 or 8 at n = 128, 8 at n = 256.
+ * Implicit steps (Newton, the Krylov solves on the group): 8 at n = 128, 16
+ * at n = 256.  The group kernels are persistent over the slices.  Defaults:
+ * linear 4 at n = 128 with at most 64 slices in the class, 8 at n = 256;
+ * implicit 8 at n = 128 with at most 32 slices, 16 at n = 256; else 1.  A
+ * device that cannot hold a group falls back to 1.  All give the same states
+ * to rounding.  CH_ERR_UNSUPPORTED for a group size without a kernel. */
+ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t fine_kind, int32_t* groups, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each instance's
  * sequential coarse sweep of (2.2) for the 2D grid-size class n: 1 (one

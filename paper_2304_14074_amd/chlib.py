@@ -96,7 +96,7 @@ def load() -> ctypes.CDLL:
     lib.ch_set_iteration.argtypes = [vp, ctypes.POINTER(ChPrState), i32, vp]
     lib.ch_fine_variant.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     lib.ch_chain_variant.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
-    lib.ch_fine_groups.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
+    lib.ch_fine_groups.argtypes = [vp, i32, i32, ctypes.POINTER(i32), i32]
     lib.ch_graph_destroy.argtypes = [vp]
     lib.ch_iteration_count.argtypes = [vp, ctypes.POINTER(ChPrState), vp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
@@ -239,9 +239,10 @@ class Context:
         self._check(self.lib.ch_chain_variant(self.h, n, ctypes.byref(g), 0 if groups is None else 1))
         return g.value
 
-    def ch_fine_groups(self, n, groups=None):
+    def ch_fine_groups(self, n, groups=None, fine_kind="linear"):
         g = ctypes.c_int32(0 if groups is None else groups)
-        self._check(self.lib.ch_fine_groups(self.h, n, ctypes.byref(g), 0 if groups is None else 1))
+        self._check(self.lib.ch_fine_groups(self.h, n, FINE[fine_kind], ctypes.byref(g),
+                                            0 if groups is None else 1))
         return g.value
 
     def autotune(self, U_in, F_out, cache_path=None, steps=20):

@@ -244,6 +244,11 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     if (fcap > 0 && (int)cp.items.size() <= fcap && cp.fine_kind == CH_FINE_LINEAR &&
         cp.precision == CH_PREC_FP64)
       cp.fine_groups = chk::fine_group_default(cp.n);
+    // implicit step: groups of 16 at n = 256 always; groups of 8 at n = 128
+    // while the groups of the class fit on the device at once
+    if (cp.fine_kind == CH_FINE_NONLINEAR && cp.n == 256) cp.fine_groups = 16;
+    if (cp.fine_kind == CH_FINE_NONLINEAR && cp.n == 128 && cp.items.size() <= 32)
+      cp.fine_groups = 8;
     const size_t units = std::max(cp.insts.size(), cp.items.size());
     cp.sync_blk = take(sizeof(int32_t) * 64 * 8 * ((units + 7) / 8));
   }
@@ -393,8 +398,16 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
     const double* tab = class_sine(c, cp);
     hipError_t e;
     if (cp.dim == 2 && cp.fine_kind == CH_FINE_NONLINEAR) {
-      e = chk::launch_fine_newton_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
-                                     mask, active, k_min, in_iter, s);
+      e = hipErrorNotSupported;
+      if (cp.fine_groups > 1) {
+        e = chk::launch_fine_newton_group(cp.n, cp.fine_groups, items, (int)cp.items.size(), inst,
+                                          tab, U_in, F_out, mask, active, k_min, in_iter,
+                                          (int32_t*)(c->ws + cp.sync_blk.off), s);
+        if (e == hipErrorCooperativeLaunchTooLarge) cp.fine_groups = 1;
+      }
+      if (cp.fine_groups == 1)
+        e = chk::launch_fine_newton_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
+                                       mask, active, k_min, in_iter, s);
     } else if (cp.dim == 2 && cp.precision == CH_PREC_SPLIT_BF16) {
       e = chk::launch_fine_split_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                                     mask, active, k_min, in_iter, s);
@@ -659,27 +672,33 @@ ch_status ch_fine_variant(ch_ctx* c, int32_t n, int32_t* waves, int32_t set) {
   return found ? CH_OK : fail(c, CH_ERR_ARG, "no tunable class with n = %d", n);
 }
 
-ch_status ch_fine_groups(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {
+ch_status ch_fine_groups(ch_ctx* c, int32_t n, int32_t fine_kind, int32_t* groups, int32_t set) {
   if (!c || !groups) return CH_ERR_ARG;
+  if (fine_kind != CH_FINE_LINEAR && fine_kind != CH_FINE_NONLINEAR)
+    return fail(c, CH_ERR_ARG, "fine kind %d", fine_kind);
   bool found = false;
   for (auto& cp : c->classes) {
-    if (cp.dim != 2 || cp.fine_kind != CH_FINE_LINEAR || cp.precision != CH_PREC_FP64 ||
-        cp.n != n)
+    if (cp.dim != 2 || cp.precision != CH_PREC_FP64 || cp.n != n || cp.fine_kind != fine_kind)
       continue;
     found = true;
     if (set) {
-      const bool ok = *groups == 1 || (n == 128 && (*groups == 4 || *groups == 8)) ||
-                      (n == 256 && *groups == 8);
-      if (*groups != 1 && *groups != 4 && *groups != 8)
-        return fail(c, CH_ERR_ARG, "fine groups must be 1, 4 or 8, got %d", *groups);
+      const bool lin = cp.fine_kind == CH_FINE_LINEAR;
+      const bool ok = *groups == 1 ||
+                      (lin && n == 128 && (*groups == 4 || *groups == 8)) ||
+                      (lin && n == 256 && *groups == 8) ||
+                      (!lin && n == 128 && *groups == 8) || (!lin && n == 256 && *groups == 16);
+      if (*groups != 1 && *groups != 4 && *groups != 8 && *groups != 16)
+        return fail(c, CH_ERR_ARG, "fine groups must be 1, 4, 8 or 16, got %d", *groups);
       if (!ok)
-        return fail(c, CH_ERR_UNSUPPORTED, "no %d-workgroup fine sweep for n = %d", *groups, n);
+        return fail(c, CH_ERR_UNSUPPORTED, "no %d-workgroup fine sweep for this class (n = %d)",
+                    *groups, n);
       cp.fine_groups = *groups;
     } else {
       *groups = cp.fine_groups;
     }
   }
-  return found ? CH_OK : fail(c, CH_ERR_ARG, "no linear FP64 2D class with n = %d", n);
+  return found ? CH_OK
+               : fail(c, CH_ERR_ARG, "no FP64 2D class with n = %d and fine kind %d", n, fine_kind);
 }
 
 ch_status ch_chain_variant(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {

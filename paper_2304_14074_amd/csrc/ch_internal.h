@@ -80,6 +80,13 @@ hipError_t launch_fine_group(int n, int groups, const WorkItem* items, int n_ite
                              double* F_out, const uint8_t* mask, const int32_t* active,
                              const int32_t* kmin, int in_iter, int32_t* sync, hipStream_t s,
                              int j_steps = 0);
+// Implicit (Newton) fine sweep on groups of workgroups, persistent over the
+// work items (2D; n = 128: 8 per group, n = 256: 16).
+hipError_t launch_fine_newton_group(int n, int groups, const WorkItem* items, int n_items,
+                                    const InstDev* inst, const double* Tsin, const double* U_in,
+                                    double* F_out, const uint8_t* mask, const int32_t* active,
+                                    const int32_t* kmin, int in_iter, int32_t* sync,
+                                    hipStream_t s);
 // Coarse chain (modes 1, 2) on a group of workgroups per instance (2D n = 128,
 // scheme (2.4)); sync: 512 ints per 8 instances (cleared by the launch).
 int chain_coop_capacity(int n);

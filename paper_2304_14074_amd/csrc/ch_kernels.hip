@@ -1092,7 +1092,7 @@ __device__ __forceinline__ void slab_put(double* Xs, const double (&v)[GeoC<N, G
 struct CoopCtx {
   int32_t* cnt;     // arrivals, monotonic over the launch (zeroed before it)
   double* xg;       // two exchange matrices N x N (natural order)
-  double* part;     // two slots of 8 x 8 partial sums
+  double* part;     // two slots of 4 x 16 partial sums (value i of member m at i * 16 + m)
   int mem, ok, xsel, psel, nb;
 };
 
@@ -1152,18 +1152,19 @@ __device__ __forceinline__ double xg_load(const double* p) {
 // summed by every member in member order, so all members agree bitwise).
 template <int NW, int G, int K>
 __device__ __forceinline__ void group_sum(double (&v)[K], double* red, CoopCtx& cc) {
+  static_assert(K <= 4 && G <= 16, "partial slots");
   block_sum<NW, K>(v, red);
   double* part = cc.part + 64 * cc.psel;
   cc.psel ^= 1;
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < K; ++i) xg_store(&part[i * 8 + cc.mem], v[i]);
+    for (int i = 0; i < K; ++i) xg_store(&part[i * 16 + cc.mem], v[i]);
   group_barrier<G>(cc);
   double pv[K][G];
 #pragma unroll
   for (int i = 0; i < K; ++i)
 #pragma unroll
-    for (int m = 0; m < G; ++m) pv[i][m] = xg_load(&part[i * 8 + m]);
+    for (int m = 0; m < G; ++m) pv[i][m] = xg_load(&part[i * 16 + m]);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     double s = 0.0;
@@ -1242,7 +1243,7 @@ __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], doubl
     cc.psel ^= 1;
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int i = 0; i < K; ++i) xg_store(&part[i * 8 + cc.mem], v2[i]);
+      for (int i = 0; i < K; ++i) xg_store(&part[i * 16 + cc.mem], v2[i]);
   }
   group_barrier<G>(cc);
   double t[R];
@@ -1255,8 +1256,8 @@ __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], doubl
   if constexpr (K > 0) {
     // lane i G + m of every wave loads member m's value i; the wave then
     // combines them by shuffles in member order
-    static_assert(K * G <= 64, "one value per lane");
-    const double pl = l < K * G ? xg_load(&part[(l / G) * 8 + l % G]) : 0.0;
+    static_assert(K * G <= 64 && K <= 4 && G <= 16, "one value per lane, partial slots");
+    const double pl = l < K * G ? xg_load(&part[(l / G) * 16 + l % G]) : 0.0;
     if constexpr (MINMAX) {
       double a = 1e300, b = -1e300;
 #pragma unroll
@@ -1324,13 +1325,79 @@ __device__ __forceinline__ void coop_apply_K(double* Xs, const double* T, CoopCt
   slab_stage<N, G, NW>(Xs, T, y);          // left: column block
 }
 
+// Preconditioned CG for K x = b, K = diag(d) + tau S diag(q) S (the SPD form
+// shared by (2.4) and the Newton matrices of the implicit steps), on the
+// group: column blocks in registers, d, the preconditioner 1 / (d + tau c)
+// and q in LDS at [s * NT + thread] (q in the row-block layout of S v S).
+// Chronopoulos-Gear form: one operator application and one group reduction
+// of three inner products per iteration (in exact arithmetic the iterates of
+// plain PCG), from x = 0, stopped when ||r|| <= rtol ||b||.  On entry rv = b;
+// on exit xv = x (rv and y are overwritten).  Returns false if maxit was
+// reached or the residual is not finite.
+template <int N, int G, int NW>
+__device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, const double* Dl,
+                        const double* Ml, const double* Ql, double tau, double rtol, int maxit,
+                        double (&rv)[GeoC<N, G, NW>::OWN], double (&xv)[GeoC<N, G, NW>::OWN],
+                        double (&y)[GeoC<N, G, NW>::OWN]) {
+  using C = GeoC<N, G, NW>;
+  const int t = threadIdx.x;
+  double pv[C::OWN], sv[C::OWN];
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    xv[s] = 0.0;
+    pv[s] = rv[s] * Ml[s * C::NT + t];   // z_0 = M r_0
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    acc[0] += rv[s] * pv[s];
+    acc[2] += rv[s] * rv[s];
+  }
+  coop_apply_K<N, G, NW>(Xs, T, cc, pv, sv, Dl, Ql, tau, acc, red);
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) sv[s] = Dl[s * C::NT + t] * pv[s] + tau * sv[s];   // w_0 = K z_0
+  double gam = acc[0];
+  const double stop2 = rtol * rtol * acc[2];
+  bool done = !(acc[2] > 0.0);
+  double alpha = gam / acc[1];
+  for (int it = 1; !done && it <= maxit; ++it) {
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      xv[s] += alpha * pv[s];
+      rv[s] -= alpha * sv[s];
+    }
+    double z[C::OWN];
+    double a3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      z[s] = rv[s] * Ml[s * C::NT + t];
+      a3[0] += rv[s] * z[s];
+      a3[2] += rv[s] * rv[s];
+    }
+    coop_apply_K<N, G, NW>(Xs, T, cc, z, y, Dl, Ql, tau, a3, red);
+    if (a3[2] <= stop2) { done = true; break; }
+    // a3 is the same in every member; cc.ok drops only on a barrier time-out
+    if (!(a3[2] == a3[2]) || !cc.ok) break;
+    const double beta = a3[0] / gam;
+    alpha = a3[0] / (a3[1] - beta * a3[0] / alpha);
+    gam = a3[0];
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      const double zs = rv[s] * Ml[s * C::NT + t];
+      const double ws = Dl[s * C::NT + t] * zs + tau * y[s];   // w = K z
+      pv[s] = zs + beta * pv[s];
+      sv[s] = ws + beta * sv[s];
+    }
+  }
+  return done;
+}
+
 // One solve of scheme (2.4) by the group.  On entry u holds the member's row
 // block of the state in slab form (element (a, c) = u[R_m[c]][a]); on exit it
 // holds the result in the same form.  Per-point tables live in LDS at
 // [s * NT + thread]: Dl = d of (2.4), Ml = the preconditioner, Ql = q = u^2.
-// The CG is the preconditioned Chronopoulos-Gear form (one group reduction
-// of three inner products per iteration; in exact arithmetic the iterates of
-// plain PCG), stopped when ||r|| <= rtol ||b|| as the one-workgroup solver.
+// The linear solve is coop_cg, stopped when ||r|| <= rtol ||b|| as in the
+// one-workgroup solver.
 template <int N, int G, int NW>
 __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const double* T,
                              double* red, CoopCtx& cc, const InstDev& P, const double* Dl,
@@ -1338,7 +1405,7 @@ __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const
   using C = GeoC<N, G, NW>;
   const double tau = P.dT / P.m_coarse;
   const int t = threadIdx.x;
-  double y[C::OWN], pv[C::OWN], rv[C::OWN], xv[C::OWN], sv[C::OWN];
+  double y[C::OWN], rv[C::OWN], xv[C::OWN];
   for (int sub = 0; sub < P.m_coarse; ++sub) {
     double mn = 1e300, mx = -1e300;
 #pragma unroll
@@ -1368,55 +1435,12 @@ __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const
       slab_rc<N, G, NW>(s, row, col);
       const double mu = -(lamS[row] + lamS[cc.mem * C::B + col]);
       const double bs = P.f_zero ? 1.0 / mu : 1.0 / mu + tau;
-      const double mi = 1.0 / (Dl[s * C::NT + t] + tau * cshift);
-      Ml[s * C::NT + t] = mi;
-      xv[s] = 0.0;
+      Ml[s * C::NT + t] = 1.0 / (Dl[s * C::NT + t] + tau * cshift);
       rv[s] = bs * y[s];
-      pv[s] = rv[s] * mi;   // z_0 = M r_0
     }
-    double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < C::OWN; ++s) {
-      acc[0] += rv[s] * pv[s];
-      acc[2] += rv[s] * rv[s];
-    }
-    coop_apply_K<N, G, NW>(Xs, T, cc, pv, sv, Dl, Ql, tau, acc, red);
-#pragma unroll
-    for (int s = 0; s < C::OWN; ++s) sv[s] = Dl[s * C::NT + t] * pv[s] + tau * sv[s];   // w_0 = K z_0
-    double gam = acc[0];
-    const double stop2 = P.krylov_rtol * P.krylov_rtol * acc[2];
-    bool done = !(acc[2] > 0.0);
-    double alpha = gam / acc[1];
-    for (int it = 1; !done && it <= P.krylov_max; ++it) {
-#pragma unroll
-      for (int s = 0; s < C::OWN; ++s) {
-        xv[s] += alpha * pv[s];
-        rv[s] -= alpha * sv[s];
-      }
-      double z[C::OWN];
-      double a3[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < C::OWN; ++s) {
-        z[s] = rv[s] * Ml[s * C::NT + t];
-        a3[0] += rv[s] * z[s];
-        a3[2] += rv[s] * rv[s];
-      }
-      coop_apply_K<N, G, NW>(Xs, T, cc, z, y, Dl, Ql, tau, a3, red);
-      if (a3[2] <= stop2) { done = true; break; }
-      // a3 is the same in every member; cc.ok drops only on a barrier time-out
-      if (!(a3[2] == a3[2]) || !cc.ok) break;
-      const double beta = a3[0] / gam;
-      alpha = a3[0] / (a3[1] - beta * a3[0] / alpha);
-      gam = a3[0];
-#pragma unroll
-      for (int s = 0; s < C::OWN; ++s) {
-        const double zs = rv[s] * Ml[s * C::NT + t];
-        const double ws = Dl[s * C::NT + t] * zs + tau * y[s];   // w = K z
-        pv[s] = zs + beta * pv[s];
-        sv[s] = ws + beta * sv[s];
-      }
-    }
-    if (!done) status |= 1;
+    if (!coop_cg<N, G, NW>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.krylov_rtol, P.krylov_max, rv,
+                           xv, y))
+      status |= 1;
     // v = S x S: left product, exchange, right product -> row block
     __syncthreads();
     slab_put<N, G, NW>(Xs, xv);
@@ -1525,6 +1549,157 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = u[s];
     if (!cc.ok && t == 0 && mem == 0) atomicOr(P.status, 4);
+  }
+}
+
+// Implicit fine sweep on groups of G workgroups, persistent over the work
+// items as k_fine_group.  Each step solves scheme (2.3) (nl_variant 0) or
+// backward Euler (1) by Newton's method from Y_0 = u, exactly as the
+// one-workgroup kernel: in sine coordinates, with A = -Lap and mu its
+// eigenvalues, A^{-1} H(Y) = d Yh + tau S(Y^3)S - (1/mu + tau) uh (2.3), or
+// d Yh + tau S(Y^3)S - tau Yh - uh/mu (BE), d = 1/mu + tau eps^2 mu; the
+// Newton matrix d + tau S diag(q) S, q = 3Y^2 (2.3) or 3Y^2 - 1 (BE), is solved
+// by coop_cg; stop when ||Y_{m+1} - Y_m||_h <= newton_tol.  Yh and uh live in
+// registers (column block), Y in slab form (row block).  A Newton or CG cap
+// sets status bit 1, a barrier time-out bit 4.
+template <int N, int G, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
+                    const InstDev* __restrict__ inst, const double* __restrict__ Tg,
+                    const double* __restrict__ lam, const double* __restrict__ U_in,
+                    double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                    const int32_t* __restrict__ active, const int32_t* __restrict__ kmin,
+                    int in_iter, int32_t* sync) {
+  using C = GeoC<N, G, NW>;
+  extern __shared__ double smem[];
+  double* Xs = smem;
+  double* T = smem + N * C::LDB;
+  double* lamS = T + C::P2;
+  double* red = lamS + N;
+  double* Dl = red + 4 * NW;
+  double* Ml = Dl + C::OWN * C::NT;
+  double* Ql = Ml + C::OWN * C::NT;
+  const int xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
+  const int mem = rest % G, grp = rest / G;
+  const int idx = grp * 8 + xcd;
+  const int n_groups = gridDim.x / G;
+  const int64_t NN = (int64_t)N * N;
+  const int t = threadIdx.x;
+  for (int m = t; m < C::P2; m += C::NT) T[m] = Tg[m];
+  for (int m = t; m < N; m += C::NT) lamS[m] = lam[m];
+  __syncthreads();
+  CoopCtx cc;
+  cc.cnt = sync + idx * 64;
+  cc.mem = mem;
+  cc.ok = 1;
+  cc.xsel = 0;
+  cc.psel = 0;
+  cc.nb = 0;
+  auto gidx = [&](int s) {
+    int row, col;
+    slab_rc<N, G, NW>(s, row, col);
+    return (int64_t)(mem * C::B + col) * N + row;
+  };
+  for (int item = idx; item < n_items; item += n_groups) {
+    const WorkItem it = items[item];
+    const InstDev P = inst[it.inst];
+    if (mask && !mask[P.slice_base + it.slice]) continue;
+    if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) continue;
+    cc.xg = P.work + (int64_t)it.slice * P.work_vecs * NN;
+    cc.part = cc.xg + 2 * NN;
+    const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+    const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
+    const double tau = P.dt;
+    const bool be = P.nl_variant == 1;
+    const double a3q = P.f_zero ? 0.0 : 3.0, a0q = (be && !P.f_zero) ? -1.0 : 0.0;
+    double uh[C::OWN], yh[C::OWN], y[C::OWN], rv[C::OWN], xv[C::OWN];
+    __syncthreads();   // every wave is done with the LDS tables of the previous item
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      int row, col;
+      slab_rc<N, G, NW>(s, row, col);
+      const double mu = -(lamS[row] + lamS[mem * C::B + col]);
+      Dl[s * C::NT + t] = 1.0 / mu + tau * P.eps * P.eps * mu;
+      y[s] = U_in[off_in + gidx(s)];
+    }
+    // u_hat = S u S
+    slab_put<N, G, NW>(Xs, y);
+    __syncthreads();
+    slab_stage<N, G, NW>(Xs, T, rv);
+    xchg_rowsT_to_cols<N, G, NW, 0>(rv, Xs, cc, nullptr, nullptr);
+    slab_stage<N, G, NW>(Xs, T, uh);
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) yh[s] = uh[s];
+    bool ok = true;
+    for (int m = 0; m < P.j_fine; ++m) {
+      bool conv = false;
+      for (int nit = 0; nit < P.newton_max && !conv; ++nit) {
+        // Y = S Yh S (row block)
+        __syncthreads();
+        slab_put<N, G, NW>(Xs, yh);
+        __syncthreads();
+        slab_stage<N, G, NW>(Xs, T, y);
+        xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
+        slab_stage<N, G, NW>(Xs, T, y);
+        // q and Y^3; S (Y^3) S with the range of q on the exchange
+        double mn = 1e300, mx = -1e300;
+#pragma unroll
+        for (int s = 0; s < C::OWN; ++s) {
+          const double q = a3q * y[s] * y[s] + a0q;
+          Ql[s * C::NT + t] = q;
+          mn = fmin(mn, q);
+          mx = fmax(mx, q);
+          y[s] = P.f_zero ? 0.0 : y[s] * y[s] * y[s];
+        }
+        __syncthreads();
+        slab_put<N, G, NW>(Xs, y);
+        __syncthreads();
+        slab_stage<N, G, NW>(Xs, T, y);
+        double mm[2] = {mn, mx};
+        xchg_rowsT_to_cols<N, G, NW, 2, true>(y, Xs, cc, mm, red);
+        slab_stage<N, G, NW>(Xs, T, y);   // S (Y^3) S, column block
+        const double cshift = 0.5 * (mm[0] + mm[1]);
+#pragma unroll
+        for (int s = 0; s < C::OWN; ++s) {
+          int row, col;
+          slab_rc<N, G, NW>(s, row, col);
+          const double im = -1.0 / (lamS[row] + lamS[mem * C::B + col]);   // 1 / mu
+          const double d = Dl[s * C::NT + t];
+          double g;
+          if (P.f_zero) g = d * yh[s] - im * uh[s];
+          else if (be) g = d * yh[s] + tau * y[s] - tau * yh[s] - im * uh[s];
+          else g = d * yh[s] + tau * y[s] - (im + tau) * uh[s];
+          rv[s] = -g;
+          Ml[s * C::NT + t] = 1.0 / (d + tau * cshift);
+        }
+        if (!coop_cg<N, G, NW>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.nl_krylov_rtol, P.krylov_max,
+                               rv, xv, y))
+          ok = false;
+        double a[1] = {0.0};
+#pragma unroll
+        for (int s = 0; s < C::OWN; ++s) {
+          yh[s] += xv[s];
+          a[0] += xv[s] * xv[s];
+        }
+        group_sum<NW, G, 1>(a, red, cc);
+        const double step = sqrt(P.h * P.h * a[0]);   // ||S dYh S||_h = h ||dYh||_F
+        if (step <= P.newton_tol) conv = true;
+        else if (!(step == step) || !cc.ok) break;
+      }
+      if (!conv) ok = false;
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) uh[s] = yh[s];
+    }
+    // u = S uh S (row block)
+    __syncthreads();
+    slab_put<N, G, NW>(Xs, uh);
+    __syncthreads();
+    slab_stage<N, G, NW>(Xs, T, y);
+    xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
+    slab_stage<N, G, NW>(Xs, T, y);
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = y[s];
+    if (t == 0 && mem == 0 && (!ok || !cc.ok)) atomicOr(P.status, (ok ? 0 : 1) | (cc.ok ? 0 : 4));
   }
 }
 
@@ -2927,6 +3102,51 @@ static hipError_t fine_group(const WorkItem* items, int n_items, const InstDev* 
   hipLaunchKernelGGL((k_fine_group<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, items, n_items,
                      inst, Tg, lam, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync);
   return hipGetLastError();
+}
+
+template <int N, int G, int NW>
+static hipError_t newton_group(const WorkItem* items, int n_items, const InstDev* inst,
+                               const double* Tg, const double* U_in, double* F_out,
+                               const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                               int in_iter, int32_t* sync, hipStream_t s) {
+  using C = GeoC<N, G, NW>;
+  const size_t lds =
+      ((size_t)N * C::LDB + C::P2 + N + 4 * NW + 3 * (size_t)C::OWN * C::NT) * sizeof(double);
+  const void* fn = (const void*)k_fine_newton_group<N, G, NW>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NW * 64, lds)) != hipSuccess)
+    return e;
+  const int fit8 = cus * per_cu / (8 * G);
+  if (fit8 < 1) return hipErrorCooperativeLaunchTooLarge;
+  const int groups8 = std::min((n_items + 7) / 8, fit8);
+  const int grid = 8 * G * groups8;
+  const int words = 64 * 8 * groups8;
+  hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
+  const double* lam = Tg + 2 * (N + 1);
+  hipLaunchKernelGGL((k_fine_newton_group<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, items,
+                     n_items, inst, Tg, lam, U_in, F_out, mask, active, kmin, in_iter, sync);
+  return hipGetLastError();
+}
+
+// Implicit fine sweep on groups of workgroups (2D; n = 128: G = 8, n = 256:
+// G = 16); hipErrorNotSupported for other shapes, hipErrorCooperativeLaunchTooLarge
+// when no group fits on the device.
+hipError_t launch_fine_newton_group(int n, int groups, const WorkItem* items, int n_items,
+                                    const InstDev* inst, const double* Tg, const double* U_in,
+                                    double* F_out, const uint8_t* mask, const int32_t* active,
+                                    const int32_t* kmin, int in_iter, int32_t* sync,
+                                    hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (n * 100 + groups) {
+    case 12808: return newton_group<128, 8, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, sync, s);
+    case 25616: return newton_group<256, 16, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, sync, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 // Largest work-item count for which the multi-workgroup fine sweep is the

@@ -115,19 +115,19 @@ def test_fine_groups_selection_host_only():
                           workloads.Problem(dim=2, n=64, n_slices=2, j_fine=5)])
     assert st == chlib.CH_OK
     g = ctypes.c_int32(0)
-    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 4
-    assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 4
+    assert lib.ch_fine_groups(h, 64, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     g.value = 4
-    assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    assert lib.ch_fine_groups(h, 64, 0, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
     g.value = 1
-    assert lib.ch_fine_groups(h, 64, ctypes.byref(g), 1) == chlib.CH_OK
+    assert lib.ch_fine_groups(h, 64, 0, ctypes.byref(g), 1) == chlib.CH_OK
     g.value = 2
-    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_ERR_ARG
+    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 1) == chlib.CH_ERR_ARG
     g.value = 8
-    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
+    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 1) == chlib.CH_OK
     g.value = 1
-    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 1) == chlib.CH_OK
-    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 1) == chlib.CH_OK
+    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     lib.ch_destroy(h)
     # 65 slices, a nonlinear class, a split-precision class: one workgroup per
     # item at n = 128; n = 256 takes groups of eight at any slice count
@@ -137,8 +137,15 @@ def test_fine_groups_selection_host_only():
              workloads.Problem(dim=2, n=256, n_slices=300, j_fine=5)]
     lib, st, h = _create(probs)
     assert st == chlib.CH_OK
-    assert lib.ch_fine_groups(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
-    assert lib.ch_fine_groups(h, 256, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 8
+    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
+    assert lib.ch_fine_groups(h, 256, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 8
     g.value = 4
-    assert lib.ch_fine_groups(h, 256, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    assert lib.ch_fine_groups(h, 256, 0, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    # the implicit class of n = 128 (two slices) takes groups of eight
+    assert lib.ch_fine_groups(h, 128, 1, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 8
+    g.value = 4
+    assert lib.ch_fine_groups(h, 128, 1, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    g.value = 1
+    assert lib.ch_fine_groups(h, 128, 1, ctypes.byref(g), 1) == chlib.CH_OK
+    assert lib.ch_fine_groups(h, 128, 2, ctypes.byref(g), 0) == chlib.CH_ERR_ARG
     lib.ch_destroy(h)
