@@ -86,6 +86,60 @@ def trajectory_error(U, traj) -> float:
     return float((torch.linalg.norm(d, dim=1) / torch.linalg.norm(traj[1:], dim=1)).max().item())
 
 
+def bench_nonlinear(args):
+    """The 2D 256x256 implicit workload (eps = 0.015, N = 128, dt = 1e-5, scheme
+    (2.3) by Newton with spectral CG): the fine sweep over all 128 slices,
+    timed over the first `nl_steps` of each slice's J = 3125 steps from the
+    coarse prediction U^0.  Newton and CG iteration counts depend on the state,
+    so executed flops are not counted (roofline null); value is fine
+    grid-point-steps per second at the full shape."""
+    import dataclasses
+    import torch
+    import workloads
+    from paper_2304_14074_amd import chlib
+    prob = workloads.nonlinear_2d_256()
+    n, N = prob.n, prob.n_slices
+    P = n * n
+    ctx = chlib.Context([prob])
+    st = ctx.new_state()
+    st["U"][:P] = torch.from_numpy(workloads.nonlinear_2d_256_u0().reshape(-1)).cuda()
+    ctx.ch_parareal_iterate(st, 0.0)            # coarse prediction U^0
+    torch.cuda.synchronize()
+    q = dataclasses.replace(prob, j_fine=args.nl_steps, T=N * args.nl_steps * prob.dt)
+    cq = chlib.Context([q])
+    U_in = st["U"][: N * P].contiguous()
+    F = torch.empty_like(U_in)
+    s = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        cq.ch_fine_propagate(U_in, F)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.steps):
+        cq.ch_fine_propagate(U_in, F)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    point_steps = N * args.nl_steps * P
+    ok = bool(torch.isfinite(F).all().item())
+    return {"metric": METRIC, "value": point_steps / (ms / 1e3), "unit": "grid-point-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "2D CH 256x256 interior grid, eps=0.015, T=4, N=128 slices, "
+                                   "dt=1e-5, implicit fine step (2.3) by Newton (tol 1e-10) with "
+                                   "spectral CG, FP64, u0 = 0.25 + 0.05*N(0,1); one step = the fine "
+                                   f"sweep of all slices over the first {args.nl_steps} of 3125 "
+                                   "steps from the coarse prediction",
+                       "n": n, "slices": N, "fine_steps_timed": args.nl_steps,
+                       "fine_steps_per_slice": prob.j_fine,
+                       "fine_groups": cq.ch_fine_groups(n, fine_kind="nonlinear")},
+            "roofline": None,
+            "extra": {"ms_per_fine_step": ms / args.nl_steps,
+                      "projected_full_fine_sweep_s": ms / args.nl_steps * prob.j_fine / 1e3,
+                      "status": int(st["status"][0].item()), "finite": ok}}
+
+
 def bench_batched(args):
     """256 independent instances of uneven size (n in {64, 128, 256}, N in
     {32, 64, 128}, eps ~ U(0.01, 0.04), J = 1563), FP64 linear fine step,
@@ -168,7 +222,10 @@ def main():
     ap.add_argument("--no-neural", action="store_true", help="skip the learned coarse propagator leg")
     ap.add_argument("--nn-traj", type=int, default=256)
     ap.add_argument("--nn-steps", type=int, default=3000)
-    ap.add_argument("--workload", default="linear_2d_128", choices=["linear_2d_128", "batched"])
+    ap.add_argument("--workload", default="linear_2d_128",
+                    choices=["linear_2d_128", "batched", "nonlinear"])
+    ap.add_argument("--nl-steps", type=int, default=20,
+                    help="implicit steps per slice timed in --workload nonlinear")
     ap.add_argument("--profile-fine", action="store_true",
                     help="one fine-sweep launch and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
@@ -178,6 +235,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)))
+        return
+    if args.workload == "nonlinear":
+        print(json.dumps(bench_nonlinear(args)))
         return
     if args.profile_fine:
         # one fine-sweep launch of the workload plus a plain 1 GiB device copy
