@@ -459,10 +459,11 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     double* Gold = st ? st->G_old : nullptr;
     double* delta = st ? st->delta : nullptr;
     int32_t* status = st ? st->status : nullptr;
-    hipError_t e;
+    hipError_t e = hipErrorNotSupported;
+    // the sequential sweeps (modes 1, 2) on a group of workgroups per
+    // instance, unless an instance uses the stabilised coarse step
     bool coop = cp.dim == 2 && mode != 0 && cp.chain_groups > 1;
     for (int32_t i : cp.insts) coop = coop && c->inst[i].coarse_kind != CH_COARSE_STAB;
-    e = hipErrorNotSupported;
     if (coop) {
       e = chk::launch_chain_coop(cp.n, cp.chain_groups, mode, insts, (int)cp.insts.size(), inst,
                                  tab, U, F, Gold, delta, status, active, k, kdev,
@@ -474,7 +475,7 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
       }
     }
     if (coop) {
-      // launched above
+      // done: launched on the groups
     } else if (cp.dim == 2) {
       e = chk::launch_coarse_2d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
                                 inst, tab, U_in, G_out, mask, U, F, Gold, delta, status,
