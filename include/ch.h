@@ -151,7 +151,13 @@ ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
  * linear 4 at n = 128 with at most 64 slices in the class, 8 at n = 256;
  * implicit 8 at n = 128 with at most 32 slices, 16 at n = 256; else 1.  A
  * device that cannot hold a group falls back to 1.  All give the same states
- * to rounding.  CH_ERR_UNSUPPORTED for a group size without a kernel. */
+ * to rounding.  CH_ERR_UNSUPPORTED for a group size without a kernel.
+ * The members of a group wait for each other at device-memory barriers, so
+ * the group kernels need every workgroup resident at once: the launch checks
+ * the device's capacity, but kernels of other streams that hold CUs at the
+ * same time can delay members.  A member that waits longer than about 0.2 s
+ * gives up.  The instance's status word then gets bit 4 (read with the next
+ * Parareal correction), and the states of that launch are invalid. */
 ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t fine_kind, int32_t* groups, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each instance's
@@ -161,7 +167,8 @@ ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t fine_kind, int32_t* gro
  * n = 128, at most 64 instances in the class; 8 is the default where
  * available, and a device that cannot hold all workgroups at once falls back
  * to 1).  All give the same iterates to rounding.  Instances with the
- * stabilised coarse step always use one workgroup. */
+ * stabilised coarse step always use one workgroup.  Residency and time-out
+ * as for ch_fine_groups (status bit 4). */
 ch_status ch_chain_variant(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set);
 
 /* hipGraph of one Parareal iteration (after the prediction): captured on
