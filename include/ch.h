@@ -164,9 +164,9 @@ ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t fine_kind, int32_t* gro
  * sequential coarse sweep of (2.2) for the 2D grid-size class n: 1 (one
  * workgroup per instance), 4 or 8 (the 2D sine transforms of every solve of
  * (2.4) split over that many workgroups that meet at device-memory barriers;
- * n = 128, at most 64 instances in the class; 8 is the default where
- * available, and a device that cannot hold all workgroups at once falls back
- * to 1).  All give the same iterates to rounding.  Instances with the
+ * n = 128, at most 256 workgroups in all, i.e. 64 instances with 4 or 32
+ * with 8; the default is 8 up to 32 instances and 4 up to 64, and a device
+ * that cannot hold all workgroups at once falls back to 1).  All give the same iterates to rounding.  Instances with the
  * stabilised coarse step always use one workgroup.  Residency and time-out
  * as for ch_fine_groups (status bit 4). */
 ch_status ch_chain_variant(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set);

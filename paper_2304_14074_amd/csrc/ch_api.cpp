@@ -238,8 +238,12 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   c->host_init_bytes = off;
   for (auto& cp : c->classes) {
     if (cp.dim != 2) continue;
+    // coarse sweep: groups of eight while 8 x instances fit on a 256-CU
+    // device, else groups of four (the launch falls back to one workgroup per
+    // instance on a smaller device)
     const int cap = chk::chain_coop_capacity(cp.n);
-    if (cap > 0 && (int)cp.insts.size() <= cap) cp.chain_groups = 8;
+    if (cap > 0 && (int)cp.insts.size() <= cap / 2) cp.chain_groups = 8;
+    else if (cap > 0 && (int)cp.insts.size() <= cap) cp.chain_groups = 4;
     const int fcap = chk::fine_group_capacity(cp.n);
     if (fcap > 0 && (int)cp.items.size() <= fcap && cp.fine_kind == CH_FINE_LINEAR &&
         cp.precision == CH_PREC_FP64)
@@ -712,7 +716,7 @@ ch_status ch_chain_variant(ch_ctx* c, int32_t n, int32_t* groups, int32_t set) {
       if (*groups != 1 && *groups != 4 && *groups != 8)
         return fail(c, CH_ERR_ARG, "chain groups must be 1, 4 or 8, got %d", *groups);
       const int cap = chk::chain_coop_capacity(n);
-      if (*groups > 1 && (cap == 0 || (int)cp.insts.size() > cap))
+      if (*groups > 1 && (cap == 0 || (int)cp.insts.size() * *groups > 4 * cap))
         return fail(c, CH_ERR_UNSUPPORTED, "no multi-workgroup chain for n = %d with %zu instances",
                     n, cp.insts.size());
       cp.chain_groups = *groups;

@@ -101,7 +101,14 @@ def test_chain_variant_selection_host_only():
     assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     assert lib.ch_chain_variant(h, 32, ctypes.byref(g), 0) == chlib.CH_ERR_ARG
     lib.ch_destroy(h)
-    # more instances than the multi-workgroup chain takes: one workgroup each
+    # 33..64 instances: groups of four (eight would exceed 256 workgroups);
+    # more: one workgroup each
+    lib, st, h = _create([workloads.Problem(dim=2, n=128, n_slices=1, j_fine=1)] * 40)
+    assert st == chlib.CH_OK
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 4
+    g.value = 8
+    assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED
+    lib.ch_destroy(h)
     lib, st, h = _create([workloads.Problem(dim=2, n=128, n_slices=1, j_fine=1)] * 65)
     assert st == chlib.CH_OK
     assert lib.ch_chain_variant(h, 128, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
