@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes of one fine-sweep launch of the 128x128 workload, from FETCH_SIZE and
 # WRITE_SIZE counter runs calibrated by a 1 GiB copy, for the kernel as it is now;
 # set to None whenever the fine kernel changes until the counters are taken again.
-FINE_LAUNCH_TRAFFIC_BYTES = (12826042.4 * 2.0 + 25649592.0) * 1024
+FINE_LAUNCH_TRAFFIC_BYTES = (12843542.6 * 2.0 + 25674608.3) * 1024
 
 
 def fine_flops_per_point_step(n: int) -> float:
@@ -408,8 +408,8 @@ def main():
            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                         "traffic": FINE_LAUNCH_TRAFFIC_BYTES,
-                        "kernel": "k_fine_group<128,4,8> (fine sweep, all 64 slices, four "
-                                  "workgroups of eight waves per slice)"},
+                        "kernel": "k_fine_group<128,8,4> (fine sweep, all 64 slices, eight "
+                                  "workgroups of four waves per slice)"},
            "extra": extra}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, u0)

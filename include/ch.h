@@ -148,7 +148,7 @@ ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
  * the sine basis where it is diagonal: 4 or 8 at n = 128, 8 at n = 256.
  * Implicit steps (Newton, the Krylov solves on the group): 8 at n = 128, 16
  * at n = 256.  The group kernels are persistent over the slices.  Defaults:
- * linear 4 at n = 128 with at most 64 slices in the class, 8 at n = 256;
+ * linear 8 at n = 128 with at most 64 slices in the class, 8 at n = 256;
  * implicit 8 at n = 128 with at most 32 slices, 16 at n = 256; else 1.  A
  * device that cannot hold a group falls back to 1.  All give the same states
  * to rounding.  CH_ERR_UNSUPPORTED for a group size without a kernel.

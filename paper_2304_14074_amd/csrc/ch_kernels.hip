@@ -3162,8 +3162,10 @@ int fine_group_capacity(int n) {
   }
 }
 
-// Default group size for class size n.
-int fine_group_default(int n) { return n == 256 ? 8 : 4; }
+// Default group size for class size n: eight at both sizes (at n = 128 two
+// groups share a CU; measured 3% faster than four per slice with the
+// coherent exchange protocol).
+int fine_group_default(int) { return 8; }
 
 // Fine sweep of the linear FP64 step on groups of workgroups (2D, n = 128:
 // G = 4 or 8; n = 256: G = 8); hipErrorNotSupported for other shapes,

@@ -122,7 +122,7 @@ def test_fine_groups_selection_host_only():
                           workloads.Problem(dim=2, n=64, n_slices=2, j_fine=5)])
     assert st == chlib.CH_OK
     g = ctypes.c_int32(0)
-    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 4
+    assert lib.ch_fine_groups(h, 128, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 8
     assert lib.ch_fine_groups(h, 64, 0, ctypes.byref(g), 0) == chlib.CH_OK and g.value == 1
     g.value = 4
     assert lib.ch_fine_groups(h, 64, 0, ctypes.byref(g), 1) == chlib.CH_ERR_UNSUPPORTED

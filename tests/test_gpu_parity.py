@@ -528,13 +528,15 @@ def test_fine_groups_128_mask_and_oracle(groups):
         assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
 
 
-def test_fine_groups_128_f_zero_mode_decay():
+@pytest.mark.parametrize("groups", [4, 8])
+def test_fine_groups_128_f_zero_mode_decay(groups):
     # f == 0 on the group path: a sine mode decays by rho^J
     from paper_2304_14074_amd import chlib
     n, J, dt, eps, s = 128, 40, 2e-5, 0.02, 2.0
     p = workloads.Problem(dim=2, n=n, eps=eps, T=J * dt, n_slices=1, j_fine=J, f_zero=True)
     ctx = chlib.Context([p])
-    assert ctx.ch_fine_groups(n) == 4
+    assert ctx.ch_fine_groups(n) == 8
+    assert ctx.ch_fine_groups(n, groups) == groups
     x = np.arange(1, n + 1) / (n + 1)
     u = np.outer(np.sin(7 * np.pi * x), np.sin(2 * np.pi * x))
     lam = lambda k: 2 * (n + 1) ** 2 * (np.cos(k * np.pi / (n + 1)) - 1)
