@@ -130,6 +130,36 @@ ch_status ch_parareal_iterate(ch_ctx* ctx, ch_pr_state* st, double tol, ch_strea
  * call equals one ch_parareal_iterate. */
 ch_status ch_parareal_correct(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream);
 
+/* Up to max_iters steps of the Parareal iteration (2.2) in one launch, each
+ * equal to one ch_parareal_iterate call: iteration k sweeps the slices n >= k
+ * (finite termination) and the run stops after the first iteration whose
+ * update norm is below tol (the rule that ends an instance's iterations in
+ * ch_parareal_iterate), or once k reaches N.  Same states,
+ * update norms and G_old as that many ch_parareal_iterate calls, bit for bit;
+ * only the schedule differs: the fine solve of slice n for iteration k + 1
+ * starts as soon as the coarse sweep of iteration k has corrected slice n - 1,
+ * so fine solves and coarse sweeps of consecutive iterations overlap (one
+ * group of workgroups runs the sweeps, the others the fine solves; they hand
+ * states over through device memory).
+ * flags: CH_RUN_SWEEP_ALL sweeps every slice from the current k in every
+ * iteration (nothing skipped as final: the same iterates, equal work per
+ * iteration, used for timing).
+ * If the coarse prediction has not been formed, it is formed first (not
+ * counted).  The device iteration counter advances by the iterations done;
+ * st->k is not updated (ch_iteration_count reads it).  st->F is used as a
+ * buffer for the fine results of even iterations; its contents afterwards are
+ * unspecified.  No host synchronisation inside.
+ * Covers a context of one instance, 2D n = 128, linear FP64 fine step, coarse
+ * scheme (2.4), N >= 2; CH_ERR_UNSUPPORTED otherwise, and when the device
+ * cannot hold all workgroups of the launch at once (the launch needs one
+ * group of eight workgroups per slice, up to 64 groups at two per CU).  The
+ * groups wait for each other at device-memory counters, each wait bounded by
+ * about 10 s; a failure sets status bit 4 and the states of that call are
+ * invalid. */
+#define CH_RUN_SWEEP_ALL 1
+ch_status ch_parareal_run(ch_ctx* ctx, ch_pr_state* st, double tol, int32_t max_iters,
+                          int32_t flags, ch_stream stream);
+
 /* Autotuner of the on-chip FP64 linear fine kernels (2D, n <= 128): times
  * every workgroup-size variant over `steps` fine steps of all slices of each
  * grid-size class on the given inputs (slice layout; F_out is overwritten)

@@ -53,6 +53,10 @@ struct ch_ctx {
   std::vector<Block> rsig_fine_blk, rsig_stab_blk, tab_blk, work_blk;
   // learned coarse propagator
   Block nn_blk, nn_out_blk, nn_part_blk;
+  // pipelined iterations (one 2D n = 128 instance): fine inputs (2 N n^2),
+  // odd-iteration fine results (N n^2), hand-off counters
+  bool pipe = false;
+  Block pipe_blk, pipe_sync_blk;
   size_t nn_floats = 0;
   const uint16_t* nn_w = nullptr;
   bool nn_planned = false;
@@ -262,6 +266,15 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       c->tab_blk[i] = take(sizeof(double) * P * chk::TAB_VECS);
       c->work_blk[i] = take(sizeof(double) * P * (size_t)c->inst[i].work_vecs * (size_t)probs[i].n_slices);
     }
+  }
+  // pipelined iterations: one instance of a class the pipelined kernel covers
+  if (n_inst == 1 && probs[0].dim == 2 && chk::pipe_supported(probs[0].n) &&
+      probs[0].fine_kind == CH_FINE_LINEAR && probs[0].precision == CH_PREC_FP64 &&
+      probs[0].coarse_kind == CH_COARSE_APPROX2 && probs[0].n_slices >= 2) {
+    const size_t SN = (size_t)probs[0].n_slices * probs[0].n * probs[0].n;
+    c->pipe = true;
+    c->pipe_blk = take(sizeof(double) * 3 * SN);
+    c->pipe_sync_blk = take(sizeof(int32_t) * chk::pipe_sync_words(probs[0].n_slices));
   }
   // learned coarse propagator workspace: activations for a batch of all
   // slices of the largest neural instance, FP64 outputs, norm partials
@@ -599,6 +612,44 @@ ch_status ch_parareal_iterate(ch_ctx* c, ch_pr_state* st, double tol, ch_stream 
   ch_status r = pr_check(c, st);
   if (r != CH_OK) return r;
   return pr_step(c, st, tol, (hipStream_t)stream, 1);
+}
+
+ch_status ch_parareal_run(ch_ctx* c, ch_pr_state* st, double tol, int32_t max_iters,
+                          int32_t flags, ch_stream stream) {
+  if (!c) return CH_ERR_ARG;
+  // what the context covers is known on the host, before any binding
+  if (!c->pipe)
+    return fail(c, CH_ERR_UNSUPPORTED,
+                "pipelined iterations need one 2D n = 128 instance, linear FP64 fine step, "
+                "coarse scheme (2.4), N >= 2");
+  const InstDev& d = c->inst[0];
+  if (d.coarse_kind != CH_COARSE_APPROX2)
+    return fail(c, CH_ERR_UNSUPPORTED, "pipelined iterations need the coarse scheme (2.4)");
+  if (max_iters < 0) return fail(c, CH_ERR_ARG, "max_iters = %d", max_iters);
+  if (flags & ~CH_RUN_SWEEP_ALL) return fail(c, CH_ERR_ARG, "unknown flags 0x%x", flags);
+  ch_status r = pr_check(c, st);
+  if (r != CH_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  if (!st->predicted) {
+    r = pr_step(c, st, tol, s, 1);
+    if (r != CH_OK) return r;
+  }
+  if (max_iters == 0) return CH_OK;
+  int32_t* active = (int32_t*)(c->ws + c->active_blk.off);
+  int32_t* kdev = (int32_t*)(c->ws + c->k_blk.off);
+  r = hip_check(c, chk::launch_flag_active(st->delta, active, 1, tol, 0, kdev, s), "flags");
+  if (r != CH_OK) return r;
+  const size_t SN = (size_t)d.n_slices * d.n * d.n;
+  double* F1 = (double*)(c->ws + c->pipe_blk.off);
+  double* Uin = F1 + SN;
+  const ClassPlan& cp = c->classes[0];
+  hipError_t e = chk::launch_parareal_pipe(
+      d.n, (const InstDev*)(c->ws + c->inst_blk.off), 0, d.n_slices, class_sine(c, cp), st->U,
+      st->F, F1, Uin, st->G_old, st->delta, st->status, active, kdev, max_iters,
+      (flags & CH_RUN_SWEEP_ALL) ? 1 : 0, tol, (int32_t*)(c->ws + c->pipe_sync_blk.off), s);
+  if (e == hipErrorCooperativeLaunchTooLarge)
+    return fail(c, CH_ERR_UNSUPPORTED, "the device cannot hold the pipelined launch at once");
+  return hip_check(c, e, "pipelined iterations");
 }
 
 ch_status ch_parareal_correct(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream) {

@@ -94,6 +94,22 @@ hipError_t launch_chain_coop(int n, int groups, int mode, const int32_t* insts, 
                              const InstDev* inst, const double* Tsin, double* U, const double* F,
                              double* G_old, double* delta, int32_t* status, const int32_t* active,
                              int k, const int32_t* kdev, int32_t* sync, hipStream_t s);
+// Several Parareal iterations of one instance in one launch, the fine solves
+// of iteration k + 1 overlapped with the coarse sweep of iteration k (2D,
+// n = 128, scheme (2.4), linear FP64 fine step).  U: the instance's iterate
+// layout (its first N states are copied to Uin before the launch); F0: its
+// slice layout; F1 (N n^2 doubles), Uin (2 N n^2) scratch; sync:
+// pipe_sync_words(N) ints (cleared by the launch).  K iterations at most,
+// stopping after one whose update norm is below tol; sweep_all: no slice is
+// skipped as finished.  The device counter kdev advances by the iterations
+// done.
+bool pipe_supported(int n);
+int pipe_sync_words(int n_slices);
+hipError_t launch_parareal_pipe(int n, const InstDev* inst, int ii, int n_slices,
+                                const double* Tsin, double* U, double* F0, double* F1,
+                                double* Uin, double* G_old, double* delta, int32_t* status,
+                                const int32_t* active, int32_t* kdev, int K, int sweep_all,
+                                double tol, int32_t* sync, hipStream_t s);
 // Fill the per-instance CG tables (d and b-scale in the owned layout).
 hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts,
                             const InstDev* inst, const double* lam, hipStream_t s);

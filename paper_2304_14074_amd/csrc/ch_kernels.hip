@@ -977,6 +977,21 @@ k_cg_tables_2d(const int32_t* __restrict__ insts, const InstDev* __restrict__ in
 // operator application S diag(q) S ... S needs two transposing exchanges
 // through global memory per CG iteration; every CG vector of a group member
 // is a block of N x B values held in registers.
+// Lane index for the group kernels.  With OPQ it passes through an empty asm,
+// so the lane-dependent addresses derived from it (slab positions, exchange
+// tiles) are recomputed where they are used instead of being hoisted out of
+// the step and CG loops, where dozens of them stay live.  That trades a few
+// integer operations for registers: at n = 256 it removes the spills of the
+// Newton kernel (6.4 -> 5.0 ms per step), and it lets the pipelined kernel
+// hold the coarse sweep in 256 registers; the n = 128 linear kernels, which
+// fit either way, are 5-10% faster without it.
+template <bool OPQ>
+__device__ __forceinline__ int lane_tid() {
+  int t = threadIdx.x;
+  if constexpr (OPQ) asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <int N, int G, int NW>
 struct GeoC {
   static constexpr int B = N / G, H = N / 2, TR = H / 16, TCB = B / 16;
@@ -991,10 +1006,10 @@ struct GeoC {
 };
 
 // Owned slot s of a slab-stage output: row a' (0..N-1), slab column c (0..B-1).
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __device__ __forceinline__ void slab_rc(int s, int& row, int& col) {
   using C = GeoC<N, G, NW>;
-  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int t = lane_tid<OPQ>(), l = t & 63, w = t >> 6;
   const int g = l >> 4, j = l & 15, tr = w / C::WPR, c0 = (w % C::WPR) * C::CPW;
   const int qr = s >> 1, half = s & 1, q = qr >> 2, r = qr & 3;
   const int a = 16 * tr + g + 4 * r;
@@ -1005,7 +1020,7 @@ __device__ __forceinline__ void slab_rc(int s, int& row, int& col) {
 // y = S * slab (N x B in LDS), folded; owned results in y.  Software-
 // pipelined like the full-width stage: the sine and data operands of k-step
 // ks+1 are read from LDS while the MFMAs of k-step ks run.
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __device__ __forceinline__ void slab_stage(const double* Xs, const double* T,
                                            double (&y)[GeoC<N, G, NW>::OWN]) {
   using C = GeoC<N, G, NW>;
@@ -1074,13 +1089,13 @@ __device__ __forceinline__ void slab_stage(const double* Xs, const double* T,
     }
 }
 
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __device__ __forceinline__ void slab_put(double* Xs, const double (&v)[GeoC<N, G, NW>::OWN]) {
   using C = GeoC<N, G, NW>;
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) {
     int row, col;
-    slab_rc<N, G, NW>(s, row, col);
+    slab_rc<N, G, NW, OPQ>(s, row, col);
     Xs[row * C::LDB + col] = v[s];
   }
 }
@@ -1175,7 +1190,7 @@ __device__ __forceinline__ void group_sum(double (&v)[K], double* red, CoopCtx& 
 }
 // Exchange A: from a column block (left-product output v: rows 0..N-1, block
 // columns C_m) to the transposed row block slab[k][r'] = M[R_m[r']][k].
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
                                    CoopCtx& cc) {
   using C = GeoC<N, G, NW>;
@@ -1184,14 +1199,14 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) {
     int row, col;
-    slab_rc<N, G, NW>(s, row, col);
+    slab_rc<N, G, NW, OPQ>(s, row, col);
     xg_store(&xg[(int64_t)row * N + cc.mem * C::B + col], v[s]);
   }
   group_barrier<G>(cc);
   // 8 x 8 tiles (8 consecutive k per row, 8 rows per wave instruction): 64-byte
   // global segments and bank-conflict-free transposed LDS writes
   constexpr int R = C::B * N / C::NT;
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = lane_tid<OPQ>() & 63, w = lane_tid<OPQ>() >> 6;
   double t[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) {
@@ -1217,18 +1232,18 @@ __device__ void xchg_cols_to_rowsT(const double (&v)[GeoC<N, G, NW>::OWN], doubl
 // group reduction of acc[0..K) rides on the same barrier (per-member values
 // posted before it, combined in member order after it): sums, or with MINMAX
 // (K = 2) the minimum of acc[0] and the maximum of acc[1].
-template <int N, int G, int NW, int K, bool MINMAX = false>
+template <int N, int G, int NW, bool OPQ, int K, bool MINMAX = false>
 __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], double* Xs,
                                    CoopCtx& cc, double* acc, double* red) {
   using C = GeoC<N, G, NW>;
   double* xg = cc.xg + (int64_t)N * N * cc.xsel;
   cc.xsel ^= 1;
   constexpr int R = C::B * N / C::NT;
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = lane_tid<OPQ>() & 63, w = lane_tid<OPQ>() >> 6;
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) {
     int row, col;
-    slab_rc<N, G, NW>(s, row, col);
+    slab_rc<N, G, NW, OPQ>(s, row, col);
     xg_store(&xg[(int64_t)row * N + cc.mem * C::B + col], v[s]);
   }
   double* part = cc.part + 64 * cc.psel;
@@ -1293,7 +1308,7 @@ __device__ void xchg_rowsT_to_cols(const double (&v)[GeoC<N, G, NW>::OWN], doubl
 // (K v, v) = sum d v^2 + tau sum q (S v S)^2 (S is orthogonal and symmetric),
 // and all three come back as group sums, reduced on the second exchange's
 // barrier.
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __device__ __forceinline__ void coop_apply_K(double* Xs, const double* T, CoopCtx& cc,
                                              const double (&v)[GeoC<N, G, NW>::OWN],
                                              double (&y)[GeoC<N, G, NW>::OWN],
@@ -1305,11 +1320,11 @@ __device__ __forceinline__ void coop_apply_K(double* Xs, const double* T, CoopCt
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) dvv += Dl[s * C::NT + t] * v[s] * v[s];
   __syncthreads();
-  slab_put<N, G, NW>(Xs, v);
+  slab_put<N, G, NW, OPQ>(Xs, v);
   __syncthreads();
-  slab_stage<N, G, NW>(Xs, T, y);          // left: S v (column block)
-  xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
-  slab_stage<N, G, NW>(Xs, T, y);          // right: (S v S) row block
+  slab_stage<N, G, NW, OPQ>(Xs, T, y);          // left: S v (column block)
+  xchg_cols_to_rowsT<N, G, NW, OPQ>(y, Xs, cc);
+  slab_stage<N, G, NW, OPQ>(Xs, T, y);          // right: (S v S) row block
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) {
     const double q = Ql[s * C::NT + t];
@@ -1318,11 +1333,11 @@ __device__ __forceinline__ void coop_apply_K(double* Xs, const double* T, CoopCt
   }
   acc[1] = dvv + tau * qyy;
   __syncthreads();
-  slab_put<N, G, NW>(Xs, y);
+  slab_put<N, G, NW, OPQ>(Xs, y);
   __syncthreads();
-  slab_stage<N, G, NW>(Xs, T, y);          // right: (q . S v S) S
-  xchg_rowsT_to_cols<N, G, NW, 3>(y, Xs, cc, acc, red);
-  slab_stage<N, G, NW>(Xs, T, y);          // left: column block
+  slab_stage<N, G, NW, OPQ>(Xs, T, y);          // right: (q . S v S) S
+  xchg_rowsT_to_cols<N, G, NW, OPQ, 3>(y, Xs, cc, acc, red);
+  slab_stage<N, G, NW, OPQ>(Xs, T, y);          // left: column block
 }
 
 // Preconditioned CG for K x = b, K = diag(d) + tau S diag(q) S (the SPD form
@@ -1334,7 +1349,7 @@ __device__ __forceinline__ void coop_apply_K(double* Xs, const double* T, CoopCt
 // plain PCG), from x = 0, stopped when ||r|| <= rtol ||b||.  On entry rv = b;
 // on exit xv = x (rv and y are overwritten).  Returns false if maxit was
 // reached or the residual is not finite.
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, const double* Dl,
                         const double* Ml, const double* Ql, double tau, double rtol, int maxit,
                         double (&rv)[GeoC<N, G, NW>::OWN], double (&xv)[GeoC<N, G, NW>::OWN],
@@ -1353,7 +1368,7 @@ __device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, c
     acc[0] += rv[s] * pv[s];
     acc[2] += rv[s] * rv[s];
   }
-  coop_apply_K<N, G, NW>(Xs, T, cc, pv, sv, Dl, Ql, tau, acc, red);
+  coop_apply_K<N, G, NW, OPQ>(Xs, T, cc, pv, sv, Dl, Ql, tau, acc, red);
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) sv[s] = Dl[s * C::NT + t] * pv[s] + tau * sv[s];   // w_0 = K z_0
   double gam = acc[0];
@@ -1374,7 +1389,7 @@ __device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, c
       a3[0] += rv[s] * z[s];
       a3[2] += rv[s] * rv[s];
     }
-    coop_apply_K<N, G, NW>(Xs, T, cc, z, y, Dl, Ql, tau, a3, red);
+    coop_apply_K<N, G, NW, OPQ>(Xs, T, cc, z, y, Dl, Ql, tau, a3, red);
     if (a3[2] <= stop2) { done = true; break; }
     // a3 is the same in every member; cc.ok drops only on a barrier time-out
     if (!(a3[2] == a3[2]) || !cc.ok) break;
@@ -1398,7 +1413,7 @@ __device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, c
 // [s * NT + thread]: Dl = d of (2.4), Ml = the preconditioner, Ql = q = u^2.
 // The linear solve is coop_cg, stopped when ||r|| <= rtol ||b|| as in the
 // one-workgroup solver.
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const double* T,
                              double* red, CoopCtx& cc, const InstDev& P, const double* Dl,
                              double* Ml, double* Ql, const double* lamS, int& status) {
@@ -1418,36 +1433,36 @@ __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const
     // u_hat = S u S: right product on the row block, exchange, left product;
     // the range of q rides on the exchange
     __syncthreads();
-    slab_put<N, G, NW>(Xs, u);
+    slab_put<N, G, NW, OPQ>(Xs, u);
     __syncthreads();
-    slab_stage<N, G, NW>(Xs, T, y);
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);
     {
       double mm[2] = {mn, mx};
-      xchg_rowsT_to_cols<N, G, NW, 2, true>(y, Xs, cc, mm, red);
+      xchg_rowsT_to_cols<N, G, NW, OPQ, 2, true>(y, Xs, cc, mm, red);
       mn = mm[0];
       mx = mm[1];
     }
     const double cshift = 0.5 * (mn + mx);
-    slab_stage<N, G, NW>(Xs, T, y);   // column block of u_hat
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);   // column block of u_hat
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) {
       int row, col;
-      slab_rc<N, G, NW>(s, row, col);
+      slab_rc<N, G, NW, OPQ>(s, row, col);
       const double mu = -(lamS[row] + lamS[cc.mem * C::B + col]);
       const double bs = P.f_zero ? 1.0 / mu : 1.0 / mu + tau;
       Ml[s * C::NT + t] = 1.0 / (Dl[s * C::NT + t] + tau * cshift);
       rv[s] = bs * y[s];
     }
-    if (!coop_cg<N, G, NW>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.krylov_rtol, P.krylov_max, rv,
+    if (!coop_cg<N, G, NW, OPQ>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.krylov_rtol, P.krylov_max, rv,
                            xv, y))
       status |= 1;
     // v = S x S: left product, exchange, right product -> row block
     __syncthreads();
-    slab_put<N, G, NW>(Xs, xv);
+    slab_put<N, G, NW, OPQ>(Xs, xv);
     __syncthreads();
-    slab_stage<N, G, NW>(Xs, T, y);
-    xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
-    slab_stage<N, G, NW>(Xs, T, u);
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);
+    xchg_cols_to_rowsT<N, G, NW, OPQ>(y, Xs, cc);
+    slab_stage<N, G, NW, OPQ>(Xs, T, u);
   }
 }
 
@@ -1458,10 +1473,75 @@ __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const
 // is, with hats for S . S,  v_hat = (u_hat + dt lam g_hat) / sigma:  one
 // forward transform of g and one inverse transform per step.  u_hat stays in
 // registers (column block); u in slab form (row block) for the pointwise g.
-// Persistent: the grid holds as many groups as can be resident at once and
-// group q takes work items q, q + groups, ...  On a barrier time-out the
-// instance's status word gets bit 4.
-template <int N, int G, int NW>
+//
+// One work item on the group: J steps from the state at src to dst (both
+// N x N, row-major).  With COHERENT the state is read and written with the
+// agent-scope accesses of the exchanges, for producers and consumers in
+// other workgroups of the same launch.  Rs: LDS for 1 / sigma.
+template <int N, int G, int NW, bool OPQ, bool COHERENT>
+__device__ __forceinline__ void fine_group_item(const InstDev& P, double* Xs, const double* T,
+                                                const double* lamS, double* Rs, CoopCtx& cc,
+                                                const double* src, double* dst, int j_steps) {
+  using C = GeoC<N, G, NW>;
+  const int t = threadIdx.x, mem = cc.mem;
+  // slab-form element (a, c) is u[R_m[c]][a]
+  auto gidx = [&](int s) {
+    int row, col;
+    slab_rc<N, G, NW, OPQ>(s, row, col);
+    return (int64_t)(mem * C::B + col) * N + row;
+  };
+  double u[C::OWN], uh[C::OWN], y[C::OWN];
+  __syncthreads();   // every wave is done with the slab and Rs of the previous item
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    int row, col;
+    slab_rc<N, G, NW, OPQ>(s, row, col);
+    Rs[s * C::NT + t] = P.rsig_fine[(int64_t)row * N + mem * C::B + col];   // column block
+    u[s] = COHERENT ? xg_load(&src[gidx(s)]) : src[gidx(s)];
+  }
+  // u_hat = S u S (right product on the row block, exchange, left product)
+  slab_put<N, G, NW, OPQ>(Xs, u);
+  __syncthreads();
+  slab_stage<N, G, NW, OPQ>(Xs, T, y);
+  xchg_rowsT_to_cols<N, G, NW, OPQ, 0>(y, Xs, cc, nullptr, nullptr);
+  slab_stage<N, G, NW, OPQ>(Xs, T, uh);
+  const int J = j_steps > 0 ? j_steps : P.j_fine;
+  const double s1 = 1.0 + P.s_fine;
+  for (int m = 0; m < J; ++m) {
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s)
+      y[s] = P.f_zero ? (-P.s_fine * u[s]) : (u[s] * u[s] * u[s] - s1 * u[s]);
+    __syncthreads();
+    slab_put<N, G, NW, OPQ>(Xs, y);
+    __syncthreads();
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);
+    xchg_rowsT_to_cols<N, G, NW, OPQ, 0>(y, Xs, cc, nullptr, nullptr);
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);   // g_hat, column block
+#pragma unroll
+    for (int s = 0; s < C::OWN; ++s) {
+      int row, col;
+      slab_rc<N, G, NW, OPQ>(s, row, col);
+      const double tl = P.dt * (lamS[row] + lamS[mem * C::B + col]);
+      uh[s] = Rs[s * C::NT + t] * (uh[s] + tl * y[s]);
+    }
+    __syncthreads();
+    slab_put<N, G, NW, OPQ>(Xs, uh);
+    __syncthreads();
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);
+    xchg_cols_to_rowsT<N, G, NW, OPQ>(y, Xs, cc);
+    slab_stage<N, G, NW, OPQ>(Xs, T, u);   // new state, row block
+  }
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    if (COHERENT) xg_store(&dst[gidx(s)], u[s]);
+    else dst[gidx(s)] = u[s];
+  }
+}
+
+// The fine sweep: persistent, the grid holds as many groups as can be
+// resident at once and group q takes work items q, q + groups, ...  On a
+// barrier time-out the instance's status word gets bit 4.
+template <int N, int G, int NW, bool OPQ>
 __global__ void __launch_bounds__(NW * 64)
 k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __restrict__ inst,
              const double* __restrict__ Tg, const double* __restrict__ lam,
@@ -1490,12 +1570,6 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
   cc.xsel = 0;
   cc.psel = 0;
   cc.nb = 0;
-  // slab-form element (a, c) is u[R_m[c]][a]
-  auto gidx = [&](int s) {
-    int row, col;
-    slab_rc<N, G, NW>(s, row, col);
-    return (int64_t)(mem * C::B + col) * N + row;
-  };
   for (int item = idx; item < n_items; item += n_groups) {
     const WorkItem it = items[item];
     const InstDev P = inst[it.inst];
@@ -1505,49 +1579,8 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
     cc.part = cc.xg + 2 * NN;
     const int64_t off = P.off_slices + (int64_t)it.slice * NN;
     const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
-    double u[C::OWN], uh[C::OWN], y[C::OWN];
-    __syncthreads();   // every wave is done with the slab and Rs of the previous item
-#pragma unroll
-    for (int s = 0; s < C::OWN; ++s) {
-      int row, col;
-      slab_rc<N, G, NW>(s, row, col);
-      Rs[s * C::NT + t] = P.rsig_fine[(int64_t)row * N + mem * C::B + col];   // column block
-      u[s] = U_in[off_in + gidx(s)];
-    }
-    // u_hat = S u S (right product on the row block, exchange, left product)
-    slab_put<N, G, NW>(Xs, u);
-    __syncthreads();
-    slab_stage<N, G, NW>(Xs, T, y);
-    xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
-    slab_stage<N, G, NW>(Xs, T, uh);
-    const int J = j_steps > 0 ? j_steps : P.j_fine;
-    const double s1 = 1.0 + P.s_fine;
-    for (int m = 0; m < J; ++m) {
-#pragma unroll
-      for (int s = 0; s < C::OWN; ++s)
-        y[s] = P.f_zero ? (-P.s_fine * u[s]) : (u[s] * u[s] * u[s] - s1 * u[s]);
-      __syncthreads();
-      slab_put<N, G, NW>(Xs, y);
-      __syncthreads();
-      slab_stage<N, G, NW>(Xs, T, y);
-      xchg_rowsT_to_cols<N, G, NW, 0>(y, Xs, cc, nullptr, nullptr);
-      slab_stage<N, G, NW>(Xs, T, y);   // g_hat, column block
-#pragma unroll
-      for (int s = 0; s < C::OWN; ++s) {
-        int row, col;
-        slab_rc<N, G, NW>(s, row, col);
-        const double tl = P.dt * (lamS[row] + lamS[mem * C::B + col]);
-        uh[s] = Rs[s * C::NT + t] * (uh[s] + tl * y[s]);
-      }
-      __syncthreads();
-      slab_put<N, G, NW>(Xs, uh);
-      __syncthreads();
-      slab_stage<N, G, NW>(Xs, T, y);
-      xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
-      slab_stage<N, G, NW>(Xs, T, u);   // new state, row block
-    }
-#pragma unroll
-    for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = u[s];
+    fine_group_item<N, G, NW, OPQ, false>(P, Xs, T, lamS, Rs, cc, U_in + off_in, F_out + off,
+                                     j_steps);
     if (!cc.ok && t == 0 && mem == 0) atomicOr(P.status, 4);
   }
 }
@@ -1562,7 +1595,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
 // by coop_cg; stop when ||Y_{m+1} - Y_m||_h <= newton_tol.  Yh and uh live in
 // registers (column block), Y in slab form (row block).  A Newton or CG cap
 // sets status bit 1, a barrier time-out bit 4.
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __global__ void __launch_bounds__(NW * 64)
 k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
                     const InstDev* __restrict__ inst, const double* __restrict__ Tg,
@@ -1597,7 +1630,7 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
   cc.nb = 0;
   auto gidx = [&](int s) {
     int row, col;
-    slab_rc<N, G, NW>(s, row, col);
+    slab_rc<N, G, NW, OPQ>(s, row, col);
     return (int64_t)(mem * C::B + col) * N + row;
   };
   for (int item = idx; item < n_items; item += n_groups) {
@@ -1617,17 +1650,17 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) {
       int row, col;
-      slab_rc<N, G, NW>(s, row, col);
+      slab_rc<N, G, NW, OPQ>(s, row, col);
       const double mu = -(lamS[row] + lamS[mem * C::B + col]);
       Dl[s * C::NT + t] = 1.0 / mu + tau * P.eps * P.eps * mu;
       y[s] = U_in[off_in + gidx(s)];
     }
     // u_hat = S u S
-    slab_put<N, G, NW>(Xs, y);
+    slab_put<N, G, NW, OPQ>(Xs, y);
     __syncthreads();
-    slab_stage<N, G, NW>(Xs, T, rv);
-    xchg_rowsT_to_cols<N, G, NW, 0>(rv, Xs, cc, nullptr, nullptr);
-    slab_stage<N, G, NW>(Xs, T, uh);
+    slab_stage<N, G, NW, OPQ>(Xs, T, rv);
+    xchg_rowsT_to_cols<N, G, NW, OPQ, 0>(rv, Xs, cc, nullptr, nullptr);
+    slab_stage<N, G, NW, OPQ>(Xs, T, uh);
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) yh[s] = uh[s];
     bool ok = true;
@@ -1636,11 +1669,11 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
       for (int nit = 0; nit < P.newton_max && !conv; ++nit) {
         // Y = S Yh S (row block)
         __syncthreads();
-        slab_put<N, G, NW>(Xs, yh);
+        slab_put<N, G, NW, OPQ>(Xs, yh);
         __syncthreads();
-        slab_stage<N, G, NW>(Xs, T, y);
-        xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
-        slab_stage<N, G, NW>(Xs, T, y);
+        slab_stage<N, G, NW, OPQ>(Xs, T, y);
+        xchg_cols_to_rowsT<N, G, NW, OPQ>(y, Xs, cc);
+        slab_stage<N, G, NW, OPQ>(Xs, T, y);
         // q and Y^3; S (Y^3) S with the range of q on the exchange
         double mn = 1e300, mx = -1e300;
 #pragma unroll
@@ -1652,17 +1685,17 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
           y[s] = P.f_zero ? 0.0 : y[s] * y[s] * y[s];
         }
         __syncthreads();
-        slab_put<N, G, NW>(Xs, y);
+        slab_put<N, G, NW, OPQ>(Xs, y);
         __syncthreads();
-        slab_stage<N, G, NW>(Xs, T, y);
+        slab_stage<N, G, NW, OPQ>(Xs, T, y);
         double mm[2] = {mn, mx};
-        xchg_rowsT_to_cols<N, G, NW, 2, true>(y, Xs, cc, mm, red);
-        slab_stage<N, G, NW>(Xs, T, y);   // S (Y^3) S, column block
+        xchg_rowsT_to_cols<N, G, NW, OPQ, 2, true>(y, Xs, cc, mm, red);
+        slab_stage<N, G, NW, OPQ>(Xs, T, y);   // S (Y^3) S, column block
         const double cshift = 0.5 * (mm[0] + mm[1]);
 #pragma unroll
         for (int s = 0; s < C::OWN; ++s) {
           int row, col;
-          slab_rc<N, G, NW>(s, row, col);
+          slab_rc<N, G, NW, OPQ>(s, row, col);
           const double im = -1.0 / (lamS[row] + lamS[mem * C::B + col]);   // 1 / mu
           const double d = Dl[s * C::NT + t];
           double g;
@@ -1672,7 +1705,7 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
           rv[s] = -g;
           Ml[s * C::NT + t] = 1.0 / (d + tau * cshift);
         }
-        if (!coop_cg<N, G, NW>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.nl_krylov_rtol, P.krylov_max,
+        if (!coop_cg<N, G, NW, OPQ>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.nl_krylov_rtol, P.krylov_max,
                                rv, xv, y))
           ok = false;
         double a[1] = {0.0};
@@ -1692,11 +1725,11 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
     }
     // u = S uh S (row block)
     __syncthreads();
-    slab_put<N, G, NW>(Xs, uh);
+    slab_put<N, G, NW, OPQ>(Xs, uh);
     __syncthreads();
-    slab_stage<N, G, NW>(Xs, T, y);
-    xchg_cols_to_rowsT<N, G, NW>(y, Xs, cc);
-    slab_stage<N, G, NW>(Xs, T, y);
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);
+    xchg_cols_to_rowsT<N, G, NW, OPQ>(y, Xs, cc);
+    slab_stage<N, G, NW, OPQ>(Xs, T, y);
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = y[s];
     if (t == 0 && mem == 0 && (!ok || !cc.ok)) atomicOr(P.status, (ok ? 0 : 1) | (cc.ok ? 0 : 4));
@@ -1704,7 +1737,7 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
 }
 
 // Cooperative chain (modes 1 and 2 of k_coarse_2d) for scheme (2.4), n = N.
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 __global__ void __launch_bounds__(NW * 64)
 k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
              const InstDev* __restrict__ inst, const double* __restrict__ Tg,
@@ -1746,7 +1779,7 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) {
     int row, col;
-    slab_rc<N, G, NW>(s, row, col);
+    slab_rc<N, G, NW, OPQ>(s, row, col);
     const double mu = -(lam[row] + lam[mem * C::B + col]);
     Dl[s * C::NT + threadIdx.x] = 1.0 / mu + tau * P.eps * P.eps * mu;
   }
@@ -1760,14 +1793,14 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
   // state element (a, c) of the slab form is u[R_m[c]][a] = row mem*B + c, column a
   auto gidx = [&](int s) {
     int row, col;
-    slab_rc<N, G, NW>(s, row, col);
+    slab_rc<N, G, NW, OPQ>(s, row, col);
     return (int64_t)(mem * C::B + col) * N + row;
   };
   if (mode == 1) {
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) u[s] = Ui[gidx(s)];
     for (int n = 0; n < Ns; ++n) {
-      coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
+      coop_approx2<N, G, NW, OPQ>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
 #pragma unroll
       for (int s = 0; s < C::OWN; ++s) {
         Ui[(n + 1) * NN + gidx(s)] = u[s];
@@ -1797,7 +1830,7 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
     dmax = acc[0];
   }
   for (int n = k + 1; n < Ns; ++n) {
-    coop_approx2<N, G, NW>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
+    coop_approx2<N, G, NW, OPQ>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
     double acc[1] = {0.0};
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) {
@@ -1819,6 +1852,280 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
     if (!(dlt == dlt) || dlt > 1e300) status |= 2;
     status_out[ii] = status | *P.status | (cc.ok ? 0 : 4);
   }
+}
+
+// ------------------------------------------------- pipelined iteration
+// Several Parareal iterations (2.2) of one instance in one launch, with the
+// fine solves of iteration j + 1 overlapped with the coarse sweep of
+// iteration j.  The input U_n^{j+1} of a fine solve is final as soon as the
+// sweep of iteration j has corrected slice n - 1, so the solve can start then
+// rather than after the whole sweep; the sweep of iteration j + 1 in turn
+// waits slice by slice for F(U_n^{j+1}).  Every value comes from the same
+// code, in the same order, as in the two-launch iteration (fine_group_item,
+// coop_approx2, the update of (2.2), the update norm), so the iterates agree
+// bit for bit; only the schedule differs.
+//
+// Roles: group 0 runs the coarse sweep; groups 1..n_fine run the fine
+// solves, persistent over the items (j, n) taken in iteration-major order
+// (group q + 1 takes items q, q + n_fine, ...).  Iteration j covers slices
+// k_j..N-1, k_j = k0 + j (finished slices skipped) or k_j = k0 (sweep_all:
+// every slice from k0 in every iteration, the same iterates with equal work
+// per iteration).
+// Hand-off buffers, written and read with the coherent accesses of the
+// exchanges: Uin[j % 2] holds the fine inputs of iteration j, F0 / F1 the
+// fine results of even / odd iterations.  Uin[j % 2][n] is rewritten only by
+// the sweep of iteration j + 1, which starts after the sweep of iteration j
+// has consumed item (j, n); F[j % 2][n] only by item (j + 2, n), whose input
+// comes from that same later sweep.
+// Counters (zeroed before the launch): ucnt[n] counts coarse-sweep members
+// that have posted their part of a new input of slice n, fcnt[n] fine-group
+// members that have posted F of slice n; ctl[0] = 1 + completed sweeps, set
+// when the coarse sweep ends; ctl[1] = failure.
+// No wait can deadlock while every workgroup is resident: item i waits only
+// for the coarse sweep, which needs only items before i, and for its group's
+// previous item, which comes before i.  Every wait is bounded by the wall
+// clock as well (about 10 s).
+struct PipeArgs {
+  const InstDev* inst;
+  const double* Tg;
+  const double* lam;
+  double* U;          // iterate layout (the instance's U_0..U_N)
+  double* F0;         // slice layout: fine results of even iterations
+  double* F1;         // N x n^2: fine results of odd iterations
+  double* Uin;        // 2 x N x n^2: fine inputs
+  double* G_old;
+  double* delta;
+  int32_t* status_out;
+  const int32_t* active;
+  const int32_t* kdev;
+  int32_t* bar;       // barrier counters, 64 words per group
+  int32_t* ucnt;
+  int32_t* fcnt;
+  int32_t* ctl;
+  int ii, K, sweep_all, n_fine;
+  double tol;
+};
+
+constexpr uint64_t kPipeWaitTicks = 1000000000ull;   // 10 s of the 100 MHz clock
+
+__device__ __forceinline__ int32_t pipe_ld(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Producer side of a hand-off: every wave waits until its coherent stores
+// are acknowledged, then one thread adds the member's arrival.
+__device__ __forceinline__ void pipe_post(int32_t* cnt) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Consumer side: one thread polls until *cnt >= target, then the workgroup
+// reads the data with coherent loads.  Returns 1 when the count is reached;
+// 0 (with until_end) when the coarse sweep has ended and a last look still
+// finds the count short, so it will never come; -1 on a failure flagged by
+// another group, on a time-out, or when this member has already failed.
+__device__ int pipe_wait(const int32_t* cnt, int target, const int32_t* ctl, bool until_end,
+                         int ok) {
+  __shared__ int res_s;
+  if (threadIdx.x == 0) {
+    int res = -1;
+    if (ok) {
+      const uint64_t t0 = wall_clock64();
+      while (true) {
+        if (pipe_ld(cnt) >= target) { res = 1; break; }
+        if (pipe_ld(ctl + 1)) { res = -1; break; }
+        if (until_end && pipe_ld(ctl)) { res = pipe_ld(cnt) >= target ? 1 : 0; break; }
+        if (wall_clock64() - t0 > kPipeWaitTicks) { res = -1; break; }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    res_s = res;
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);   // no compiler motion across the poll
+  __syncthreads();
+  return res_s;
+}
+
+__device__ __forceinline__ void pipe_fail(int32_t* ctl) {
+  if (threadIdx.x == 0) __hip_atomic_store(ctl + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Coarse-sweep role: the correction sweeps of iterations 0..K-1 (the loop of
+// k_chain_coop's mode 2, with the hand-offs added).
+template <int N, int G, int NW, bool OPQ>
+__device__ void pipe_coarse(const PipeArgs& A, const InstDev& P, int k0, double* Xs,
+                            const double* T, const double* lamS, double* red, double* Dl,
+                            double* Ml, double* Ql, CoopCtx& cc) {
+  using C = GeoC<N, G, NW>;
+  const int t = threadIdx.x, mem = cc.mem;
+  const double tau = P.dT / P.m_coarse;
+#pragma unroll
+  for (int s = 0; s < C::OWN; ++s) {
+    int row, col;
+    slab_rc<N, G, NW, OPQ>(s, row, col);
+    const double mu = -(lamS[row] + lamS[mem * C::B + col]);
+    Dl[s * C::NT + t] = 1.0 / mu + tau * P.eps * P.eps * mu;
+  }
+  __syncthreads();
+  const int64_t NN = (int64_t)N * N;
+  const int Ns = P.n_slices;
+  double* Ui = A.U + P.off_iter;
+  double* Gi = A.G_old + P.off_slices;
+  auto gidx = [&](int s) {
+    int row, col;
+    slab_rc<N, G, NW, OPQ>(s, row, col);
+    return (int64_t)(mem * C::B + col) * N + row;
+  };
+  int status = 0, jdone = 0;
+  bool fail = false;
+  double u[C::OWN];
+  for (int j = 0; j < A.K; ++j) {
+    const int kj = A.sweep_all ? k0 : k0 + j;
+    if (kj >= Ns) break;
+    const double* Fj = (j & 1) ? A.F1 : A.F0 + P.off_slices;
+    double* Un = A.Uin + (int64_t)((j + 1) & 1) * Ns * NN;   // inputs of iteration j + 1
+    const int target = G * (j + 1);                          // members posting item (j, n)
+    if (pipe_wait(A.fcnt + kj, target, A.ctl, false, cc.ok) <= 0) { fail = true; break; }
+    double dmax;
+    {
+      // U_{k+1} = F_k (slices up to k are final)
+      double acc[1] = {0.0};
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) {
+        const int64_t o = gidx(s);
+        const double un = xg_load(&Fj[kj * NN + o]);
+        const double d = un - Ui[(kj + 1) * NN + o];
+        acc[0] += d * d;
+        Ui[(kj + 1) * NN + o] = un;
+        u[s] = un;
+        if (kj + 1 < Ns) xg_store(&Un[(kj + 1) * NN + o], un);
+      }
+      if (kj + 1 < Ns) pipe_post(A.ucnt + kj + 1);
+      group_sum<NW, G, 1>(acc, red, cc);
+      dmax = acc[0];
+    }
+    for (int n = kj + 1; n < Ns; ++n) {
+      coop_approx2<N, G, NW, OPQ>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
+      if (pipe_wait(A.fcnt + n, target, A.ctl, false, cc.ok) <= 0) { fail = true; break; }
+      double acc[1] = {0.0};
+#pragma unroll
+      for (int s = 0; s < C::OWN; ++s) {
+        const int64_t o = gidx(s);
+        const double gv = u[s];
+        const double un = xg_load(&Fj[n * NN + o]) + (gv - Gi[n * NN + o]);
+        const double d = un - Ui[(n + 1) * NN + o];
+        acc[0] += d * d;
+        Ui[(n + 1) * NN + o] = un;
+        Gi[n * NN + o] = gv;
+        u[s] = un;
+        if (n + 1 < Ns) xg_store(&Un[(n + 1) * NN + o], un);
+      }
+      if (n + 1 < Ns) pipe_post(A.ucnt + n + 1);
+      group_sum<NW, G, 1>(acc, red, cc);
+      dmax = fmax(dmax, acc[0]);
+    }
+    if (fail) break;
+    const double dlt = sqrt(P.h * P.h * dmax);
+    if (t == 0 && mem == 0) A.delta[A.ii] = dlt;
+    jdone = j + 1;
+    if (!(dlt == dlt) || dlt > 1e300) { status |= 2; break; }
+    if (!cc.ok || dlt < A.tol) break;   // the rule of the active flags (k_flag_active)
+  }
+  // every member's posts are done before the end is published
+  group_barrier<G>(cc);
+  if (t == 0 && mem == 0) {
+    const bool bad = fail || !cc.ok || pipe_ld(A.ctl + 1);
+    A.status_out[A.ii] = status | *P.status | (bad ? 4 : 0);
+    if (bad) __hip_atomic_store(A.ctl + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(A.ctl, jdone + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else if (fail || !cc.ok) {
+    pipe_fail(A.ctl);
+  }
+}
+
+// Fine role: fine group q's items (j, n) in iteration-major order.
+template <int N, int G, int NW, bool OPQ>
+__device__ void pipe_fine(const PipeArgs& A, const InstDev& P, int k0, int q, double* Xs,
+                          const double* T, const double* lamS, double* Rs, CoopCtx& cc) {
+  const int64_t NN = (int64_t)N * N;
+  const int Ns = P.n_slices;
+  auto count = [&](int j) { return Ns - (A.sweep_all ? k0 : k0 + j); };   // items of iteration j
+  int j = 0, r = q;
+  while (j < A.K && count(j) > 0 && r >= count(j)) r -= count(j++);
+  while (j < A.K && count(j) > 0) {
+    const int n = (A.sweep_all ? k0 : k0 + j) + r;
+    // the input comes from the copy made before the launch (iteration 0, and
+    // slice k0, which no sweep rewrites) or from the sweep of iteration j - 1
+    if (j > 0 && n > k0) {
+      const int w = pipe_wait(A.ucnt + n, G * j, A.ctl, true, cc.ok);
+      if (w < 0) pipe_fail(A.ctl);
+      if (w <= 0) break;
+    }
+    const double* src = A.Uin + (int64_t)(j & 1) * Ns * NN + n * NN;
+    double* dst = ((j & 1) ? A.F1 : A.F0 + P.off_slices) + n * NN;
+    fine_group_item<N, G, NW, OPQ, true>(P, Xs, T, lamS, Rs, cc, src, dst, 0);
+    if (!cc.ok) {
+      if (threadIdx.x == 0 && cc.mem == 0) atomicOr(P.status, 4);
+      pipe_fail(A.ctl);
+    }
+    pipe_post(A.fcnt + n);
+    r += A.n_fine;
+    while (j < A.K && count(j) > 0 && r >= count(j)) r -= count(j++);
+  }
+}
+
+// LDS: the coarse-sweep layout (the fine role uses the table region for 1 / sigma).
+// Two workgroups per CU (at most 256 registers per lane) so that one coarse
+// group and 63 fine groups fit a 256-CU device at once.
+template <int N, int G, int NW, bool OPQ>
+__global__ void __launch_bounds__(NW * 64, 2)
+k_parareal_pipe(PipeArgs A) {
+  using C = GeoC<N, G, NW>;
+  extern __shared__ double smem[];
+  double* Xs = smem;
+  double* T = smem + N * C::LDB;
+  double* lamS = T + C::P2;
+  double* red = lamS + N;
+  double* Dl = red + 4 * NW;
+  double* Ml = Dl + C::OWN * C::NT;
+  double* Ql = Ml + C::OWN * C::NT;
+  const int xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
+  const int mem = rest % G, grp = rest / G;
+  const int idx = grp * 8 + xcd;   // 0: coarse sweep, 1..n_fine: fine groups
+  if (idx > A.n_fine) return;
+  if (A.active && !A.active[A.ii]) return;
+  const InstDev P = A.inst[A.ii];
+  for (int m = threadIdx.x; m < C::P2; m += C::NT) T[m] = A.Tg[m];
+  for (int m = threadIdx.x; m < N; m += C::NT) lamS[m] = A.lam[m];
+  __syncthreads();
+  CoopCtx cc;
+  cc.cnt = A.bar + idx * 64;
+  cc.xg = P.work + (int64_t)idx * P.work_vecs * N * N;   // exchange area of the group
+  cc.part = cc.xg + 2 * (int64_t)N * N;
+  cc.mem = mem;
+  cc.ok = 1;
+  cc.xsel = 0;
+  cc.psel = 0;
+  cc.nb = 0;
+  const int k0 = *A.kdev;
+  if (idx == 0) pipe_coarse<N, G, NW, OPQ>(A, P, k0, Xs, T, lamS, red, Dl, Ml, Ql, cc);
+  else pipe_fine<N, G, NW, OPQ>(A, P, k0, idx - 1, Xs, T, lamS, Dl, cc);
+}
+
+__global__ void k_copy2(const double* __restrict__ src, double* __restrict__ d0,
+                        double* __restrict__ d1, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) {
+    const double v = src[i];
+    d0[i] = v;
+    d1[i] = v;
+  }
+}
+
+// The device iteration counter advances by the completed sweeps.
+__global__ void k_pipe_finish(int32_t* kdev, const int32_t* ctl) {
+  if (threadIdx.x == 0 && ctl[0] > 0) *kdev += ctl[0] - 1;
 }
 
 // ------------------------------------------------- streamed large grids
@@ -3046,7 +3353,7 @@ __global__ void k_zero_i32(int32_t* p, int count) {
   if (i < count) p[i] = 0;
 }
 
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 static hipError_t chain_coop(int mode, const int32_t* insts, int n_insts, const InstDev* inst,
                              const double* Tg, const double* lam, double* U, const double* F,
                              double* G_old, double* delta, int32_t* status, const int32_t* active,
@@ -3054,7 +3361,7 @@ static hipError_t chain_coop(int mode, const int32_t* insts, int n_insts, const 
   using C = GeoC<N, G, NW>;
   const size_t lds =
       ((size_t)N * C::LDB + C::P2 + N + 4 * NW + 3 * (size_t)C::OWN * C::NT) * sizeof(double);
-  const void* fn = (const void*)k_chain_coop<N, G, NW>;
+  const void* fn = (const void*)k_chain_coop<N, G, NW, OPQ>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   // every workgroup of the grid must be resident at once
@@ -3069,19 +3376,19 @@ static hipError_t chain_coop(int mode, const int32_t* insts, int n_insts, const 
   if (grid > cus * per_cu) return hipErrorCooperativeLaunchTooLarge;
   const int words = 64 * 8 * groups;
   hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
-  hipLaunchKernelGGL((k_chain_coop<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
+  hipLaunchKernelGGL((k_chain_coop<N, G, NW, OPQ>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
                      n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync);
   return hipGetLastError();
 }
 
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 static hipError_t fine_group(const WorkItem* items, int n_items, const InstDev* inst,
                              const double* Tg, const double* U_in, double* F_out,
                              const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                              int in_iter, int j_steps, int32_t* sync, hipStream_t s) {
   using C = GeoC<N, G, NW>;
   const size_t lds = ((size_t)N * C::LDB + C::P2 + N + (size_t)C::OWN * C::NT) * sizeof(double);
-  const void* fn = (const void*)k_fine_group<N, G, NW>;
+  const void* fn = (const void*)k_fine_group<N, G, NW, OPQ>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0, per_cu = 0;
@@ -3099,12 +3406,12 @@ static hipError_t fine_group(const WorkItem* items, int n_items, const InstDev* 
   const int words = 64 * 8 * groups8;
   hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
   const double* lam = Tg + 2 * (N + 1);
-  hipLaunchKernelGGL((k_fine_group<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, items, n_items,
+  hipLaunchKernelGGL((k_fine_group<N, G, NW, OPQ>), dim3(grid), dim3(NW * 64), lds, s, items, n_items,
                      inst, Tg, lam, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync);
   return hipGetLastError();
 }
 
-template <int N, int G, int NW>
+template <int N, int G, int NW, bool OPQ>
 static hipError_t newton_group(const WorkItem* items, int n_items, const InstDev* inst,
                                const double* Tg, const double* U_in, double* F_out,
                                const uint8_t* mask, const int32_t* active, const int32_t* kmin,
@@ -3112,7 +3419,7 @@ static hipError_t newton_group(const WorkItem* items, int n_items, const InstDev
   using C = GeoC<N, G, NW>;
   const size_t lds =
       ((size_t)N * C::LDB + C::P2 + N + 4 * NW + 3 * (size_t)C::OWN * C::NT) * sizeof(double);
-  const void* fn = (const void*)k_fine_newton_group<N, G, NW>;
+  const void* fn = (const void*)k_fine_newton_group<N, G, NW, OPQ>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0, per_cu = 0;
@@ -3128,7 +3435,7 @@ static hipError_t newton_group(const WorkItem* items, int n_items, const InstDev
   const int words = 64 * 8 * groups8;
   hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
   const double* lam = Tg + 2 * (N + 1);
-  hipLaunchKernelGGL((k_fine_newton_group<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, items,
+  hipLaunchKernelGGL((k_fine_newton_group<N, G, NW, OPQ>), dim3(grid), dim3(NW * 64), lds, s, items,
                      n_items, inst, Tg, lam, U_in, F_out, mask, active, kmin, in_iter, sync);
   return hipGetLastError();
 }
@@ -3143,8 +3450,8 @@ hipError_t launch_fine_newton_group(int n, int groups, const WorkItem* items, in
                                     hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (n * 100 + groups) {
-    case 12808: return newton_group<128, 8, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, sync, s);
-    case 25616: return newton_group<256, 16, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, sync, s);
+    case 12808: return newton_group<128, 8, 4, true>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, sync, s);
+    case 25616: return newton_group<256, 16, 8, true>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, sync, s);
     default: return hipErrorNotSupported;
   }
 }
@@ -3179,9 +3486,9 @@ hipError_t launch_fine_group(int n, int groups, const WorkItem* items, int n_ite
   switch (n * 100 + groups) {
     // eight waves per workgroup at G = 4 (two per SIMD hide LDS and exchange
     // latency; measured 9% faster than four); G = 8 allows only four at n = 128
-    case 12804: return fine_group<128, 4, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
-    case 12808: return fine_group<128, 8, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
-    case 25608: return fine_group<256, 8, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+    case 12804: return fine_group<128, 4, 8, false>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+    case 12808: return fine_group<128, 8, 4, false>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
+    case 25608: return fine_group<256, 8, 8, false>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps, sync, s);
     default: return hipErrorNotSupported;
   }
 }
@@ -3204,10 +3511,84 @@ hipError_t launch_chain_coop(int n, int groups, int mode, const int32_t* insts, 
   if (n_insts > chain_coop_capacity(n)) return hipErrorNotSupported;
   const double* lam = Tg + 2 * (n + 1);
   switch (n * 100 + groups) {
-    case 12804: return chain_coop<128, 4, 4>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
-    case 12808: return chain_coop<128, 8, 4>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
+    case 12804: return chain_coop<128, 4, 4, false>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
+    case 12808: return chain_coop<128, 8, 4, false>(mode, insts, n_insts, inst, Tg, lam, U, F, G_old, delta, status, active, k, kdev, sync, s);
     default: return hipErrorNotSupported;
   }
+}
+
+template <int N, int G, int NW, bool OPQ>
+static hipError_t parareal_pipe(PipeArgs A, int n_slices, int32_t* sync, hipStream_t s) {
+  using C = GeoC<N, G, NW>;
+  const size_t lds =
+      ((size_t)N * C::LDB + C::P2 + N + 4 * NW + 3 * (size_t)C::OWN * C::NT) * sizeof(double);
+  const void* fn = (const void*)k_parareal_pipe<N, G, NW, OPQ>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NW * 64, lds)) != hipSuccess)
+    return e;
+  // one coarse-sweep group and up to N - 1 fine groups, all resident at once
+  const int max_groups = 8 * (cus * per_cu / (8 * G));
+  const int n_fine = std::min(max_groups - 1, n_slices - 1);
+  if (n_fine < 1) return hipErrorCooperativeLaunchTooLarge;
+  const int grid = 8 * G * ((n_fine + 1 + 7) / 8);
+  const int bar_words = 64 * 8 * ((n_slices + 7) / 8);
+  A.bar = sync;
+  A.ucnt = sync + bar_words;
+  A.fcnt = A.ucnt + n_slices;
+  A.ctl = A.fcnt + n_slices;
+  A.n_fine = n_fine;
+  const int words = pipe_sync_words(n_slices);
+  hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
+  const int64_t count = (int64_t)n_slices * N * N;   // U_0..U_{N-1} into both input buffers
+  hipLaunchKernelGGL(k_copy2, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, A.U, A.Uin,
+                     A.Uin + count, count);
+  hipLaunchKernelGGL((k_parareal_pipe<N, G, NW, OPQ>), dim3(grid), dim3(NW * 64), lds, s, A);
+  hipLaunchKernelGGL(k_pipe_finish, dim3(1), dim3(64), 0, s, const_cast<int32_t*>(A.kdev), A.ctl);
+  return hipGetLastError();
+}
+
+// Sync words of the pipelined launch: barrier counters of up to N groups,
+// the two hand-off counters per slice, two control words.
+int pipe_sync_words(int n_slices) { return 64 * 8 * ((n_slices + 7) / 8) + 2 * n_slices + 2; }
+
+bool pipe_supported(int n) { return n == 128; }
+
+// Pipelined Parareal iterations of one instance (2D, n = 128, scheme (2.4),
+// linear FP64 fine step, groups of eight workgroups).  U is the instance's
+// iterate layout, F0 its slice layout; F1 (N n^2) and Uin (2 N n^2) are
+// scratch; sync holds pipe_sync_words(N) ints.  hipErrorNotSupported for other
+// shapes, hipErrorCooperativeLaunchTooLarge when the groups cannot all be
+// resident.
+hipError_t launch_parareal_pipe(int n, const InstDev* inst, int ii, int n_slices,
+                                const double* Tsin, double* U, double* F0, double* F1,
+                                double* Uin, double* G_old, double* delta, int32_t* status,
+                                const int32_t* active, int32_t* kdev, int K, int sweep_all,
+                                double tol, int32_t* sync, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  if (!pipe_supported(n) || n_slices < 2) return hipErrorNotSupported;
+  PipeArgs A{};
+  A.inst = inst;
+  A.Tg = Tsin;
+  A.lam = Tsin + 2 * (n + 1);
+  A.U = U;
+  A.F0 = F0;
+  A.F1 = F1;
+  A.Uin = Uin;
+  A.G_old = G_old;
+  A.delta = delta;
+  A.status_out = status;
+  A.active = active;
+  A.kdev = kdev;
+  A.ii = ii;
+  A.K = K;
+  A.sweep_all = sweep_all;
+  A.tol = tol;
+  return parareal_pipe<128, 8, 4, true>(A, n_slices, sync, s);
 }
 
 hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts, const InstDev* inst,

@@ -156,3 +156,33 @@ def test_fine_groups_selection_host_only():
     assert lib.ch_fine_groups(h, 128, 1, ctypes.byref(g), 1) == chlib.CH_OK
     assert lib.ch_fine_groups(h, 128, 2, ctypes.byref(g), 0) == chlib.CH_ERR_ARG
     lib.ch_destroy(h)
+
+
+def test_pipelined_run_coverage_host_only():
+    # ch_parareal_run covers one 2D n = 128 instance with the linear FP64 fine
+    # step and coarse scheme (2.4), N >= 2; other contexts are refused on the
+    # host, before any workspace exists; a covered context without a bound
+    # workspace gets the usual state error
+    import workloads
+    from paper_2304_14074_amd import chlib
+    st_struct = chlib.ChPrState()
+    cases = [
+        ([workloads.Problem(dim=2, n=64, n_slices=4, j_fine=5)], chlib.CH_ERR_UNSUPPORTED),
+        ([workloads.Problem(dim=2, n=128, n_slices=4, j_fine=5)] * 2, chlib.CH_ERR_UNSUPPORTED),
+        ([workloads.Problem(dim=2, n=128, n_slices=1, j_fine=5)], chlib.CH_ERR_UNSUPPORTED),
+        ([workloads.Problem(dim=2, n=128, n_slices=4, j_fine=5, coarse_kind="stab")],
+         chlib.CH_ERR_UNSUPPORTED),
+        ([workloads.Problem(dim=2, n=128, n_slices=4, j_fine=5, precision="split_bf16")],
+         chlib.CH_ERR_UNSUPPORTED),
+        ([workloads.Problem(dim=2, n=128, n_slices=4, j_fine=5)], chlib.CH_ERR_STATE),
+    ]
+    for probs, code in cases:
+        lib, st, h = _create(probs)
+        assert st == chlib.CH_OK
+        r = lib.ch_parareal_run(h, ctypes.byref(st_struct), 0.0, 3, 0, None)
+        assert r == code, (probs[0], len(probs), r)
+        lib.ch_destroy(h)
+    lib, st, h = _create([workloads.Problem(dim=2, n=128, n_slices=4, j_fine=5)])
+    assert lib.ch_parareal_run(h, ctypes.byref(st_struct), 0.0, -1, 0, None) == chlib.CH_ERR_ARG
+    assert lib.ch_parareal_run(h, ctypes.byref(st_struct), 0.0, 3, 2, None) == chlib.CH_ERR_ARG
+    lib.ch_destroy(h)

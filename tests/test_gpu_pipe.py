@@ -1,0 +1,144 @@
+"""Pipelined Parareal iterations (ch_parareal_run) through the C ABI.
+
+The pipelined launch computes the iterates of (2.2) with the same code as the
+two-launch iteration (fine sweep, then the coarse sweep and correction), only
+scheduled differently, so its states, G_old and update norms must equal those
+of ch_parareal_iterate bit for bit, and match the oracle to the FP64 bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import operators, parareal, propagators
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+N128 = 128
+
+
+def _setup(N, J, eps=0.02, dt=2e-5, seed=31, amp=0.3):
+    from paper_2304_14074_amd import chlib
+    p = workloads.Problem(dim=2, n=N128, eps=eps, T=N * J * dt, n_slices=N, j_fine=J)
+    u0 = workloads.u0_uniform(N128, 2, amp, seed)
+    ctx = chlib.Context([p])
+    # the two-launch reference on the same group kernels as the pipelined one
+    assert ctx.ch_fine_groups(N128, 8) == 8
+    assert ctx.ch_chain_variant(N128) == 8
+    st = ctx.new_state()
+    st["U"][: N128 * N128] = torch.from_numpy(u0.reshape(-1)).cuda()
+    return p, u0, ctx, st
+
+
+def _snap(st):
+    torch.cuda.synchronize()
+    return (st["U"].cpu().numpy().copy(), st["G_old"].cpu().numpy().copy(),
+            st["delta"].cpu().numpy().copy(), st["status"].cpu().numpy().copy())
+
+
+def _same(a, b, what):
+    for name, x, y in zip(("U", "G_old", "delta", "status"), a, b):
+        assert np.array_equal(x, y), (what, name, np.max(np.abs(x - y)) if x.dtype != np.int32 else None)
+
+
+def _reference(N, J, K, sweep_all, tol, **kw):
+    """K calls of ch_parareal_iterate after the prediction; with sweep_all the
+    counter is reset to 0 before each, so every slice is swept."""
+    _, _, ctx, st = _setup(N, J, **kw)
+    ctx.ch_parareal_iterate(st, tol)
+    snaps = [_snap(st)]
+    for _ in range(K):
+        if sweep_all:
+            ctx.ch_set_iteration(st, 0)
+        ctx.ch_parareal_iterate(st, tol)
+        snaps.append(_snap(st))
+    return snaps
+
+
+@pytest.mark.parametrize("N,J,K,sweep_all", [(8, 6, 3, False), (8, 6, 3, True), (2, 5, 2, False),
+                                             (9, 4, 4, True), (5, 4, 5, False)])
+def test_pipelined_run_equals_iterate_bitwise(N, J, K, sweep_all):
+    print(f"pipelined run N={N} J={J} K={K} sweep_all={sweep_all}", flush=True)
+    ref = _reference(N, J, K, sweep_all, -1.0)
+    _, _, ctx, st = _setup(N, J)
+    ctx.ch_parareal_run(st, -1.0, K, sweep_all=sweep_all)
+    got = _snap(st)
+    _same(got, ref[K], "after K iterations")
+    assert ctx.ch_iteration_count(st) == K
+    assert int(got[3][0]) == 0
+
+
+def test_pipelined_run_in_two_calls_continues_the_iteration():
+    # a second call picks up the device counter: 2 + 2 iterations == 4
+    N, J = 8, 5
+    ref = _reference(N, J, 4, False, -1.0)
+    _, _, ctx, st = _setup(N, J)
+    print("pipelined run 2 + 2", flush=True)
+    ctx.ch_parareal_run(st, -1.0, 2)
+    _same(_snap(st), ref[2], "first call")
+    ctx.ch_parareal_run(st, -1.0, 2)
+    _same(_snap(st), ref[4], "second call")
+    assert ctx.ch_iteration_count(st) == 4
+
+
+def test_pipelined_run_stops_at_n_slices():
+    # finite termination: with max_iters > N the run ends at k = N, where the
+    # iterate is the sequential fine solution
+    N, J = 4, 6
+    ref = _reference(N, J, N, False, -1.0)
+    _, _, ctx, st = _setup(N, J)
+    print("pipelined run to k = N", flush=True)
+    ctx.ch_parareal_run(st, -1.0, 10)
+    _same(_snap(st), ref[N], "k = N")
+    assert ctx.ch_iteration_count(st) == N
+
+
+def test_pipelined_run_stops_below_tolerance():
+    # a contracting regime (eps = 0.03, short slices): the run ends after the
+    # first iteration whose update norm is below tol, as the iterate loop does
+    N, J, dt = 12, 8, 2.5e-5
+    kw = dict(eps=0.03, dt=dt, amp=0.05)
+    full = _reference(N, J, 6, False, -1.0, **kw)
+    deltas = [s[2][0] for s in full[1:]]
+    print("update norms", deltas, flush=True)
+    k_stop = 3
+    tol = float(deltas[k_stop - 1]) * 1.0000001
+    stop = next(k for k, d in enumerate(deltas, start=1) if d < tol)
+    _, _, ctx, st = _setup(N, J, **kw)
+    ctx.ch_parareal_run(st, tol, 10)
+    got = _snap(st)
+    assert ctx.ch_iteration_count(st) == stop
+    _same(got, full[stop], "stopped")
+    # a later call does nothing: the instance has converged
+    ctx.ch_parareal_run(st, tol, 3)
+    _same(_snap(st), full[stop], "after convergence")
+    assert ctx.ch_iteration_count(st) == stop
+
+
+def test_pipelined_run_more_slices_than_fine_groups():
+    # 70 slices: the 63 fine groups of a 256-CU device take several items per
+    # iteration (persistent), in iteration-major order
+    N, J, K = 70, 3, 2
+    print(f"pipelined run N={N}", flush=True)
+    ref = _reference(N, J, K, True, -1.0)
+    _, _, ctx, st = _setup(N, J)
+    ctx.ch_parareal_run(st, -1.0, K, sweep_all=True)
+    _same(_snap(st), ref[K], "N = 70")
+
+
+def test_pipelined_run_matches_oracle():
+    N, J, K = 4, 8, 2
+    p, u0, ctx, st = _setup(N, J)
+    ref = parareal.parareal(u0, N, lambda u: propagators.fine(p, u),
+                            lambda u: propagators.coarse(p, u),
+                            lambda v: operators.norm_h(v, 2), tol=0.0, kmax=K)
+    print("pipelined run vs oracle", flush=True)
+    ctx.ch_parareal_run(st, -1.0, K)
+    torch.cuda.synchronize()
+    U = gu.unpack_iter(ctx, st["U"])[0]
+    for j in range(N + 1):
+        assert gu.rel(U[j], ref["U"][K][j]) < TOL, (j, gu.rel(U[j], ref["U"][K][j]))
+    d = st["delta"][0].item()
+    assert abs(d - ref["delta"][K - 1]) <= 1e-9 * ref["delta"][K - 1]
+    assert int(st["status"][0].item()) == 0
