@@ -1903,6 +1903,7 @@ struct PipeArgs {
   int32_t* fcnt;
   int32_t* ctl;
   int ii, K, sweep_all, n_fine;
+  int idle;           // group left without work (-1: none), see parareal_pipe
   double tol;
 };
 
@@ -2076,9 +2077,9 @@ __device__ void pipe_fine(const PipeArgs& A, const InstDev& P, int k0, int q, do
 }
 
 // LDS: the coarse-sweep layout (the fine role uses the table region for 1 / sigma).
-// Two workgroups per CU (at most 256 registers per lane) so that one coarse
-// group and 63 fine groups fit a 256-CU device at once.
-template <int N, int G, int NW, bool OPQ>
+// Two workgroups per CU (at most 256 registers per lane) so that the coarse
+// group and the fine groups fit a 256-CU device at once.
+template <int N, int G, int NW>
 __global__ void __launch_bounds__(NW * 64, 2)
 k_parareal_pipe(PipeArgs A) {
   using C = GeoC<N, G, NW>;
@@ -2092,16 +2093,19 @@ k_parareal_pipe(PipeArgs A) {
   double* Ql = Ml + C::OWN * C::NT;
   const int xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
   const int mem = rest % G, grp = rest / G;
-  const int idx = grp * 8 + xcd;   // 0: coarse sweep, 1..n_fine: fine groups
-  if (idx > A.n_fine) return;
+  const int idx = grp * 8 + xcd;   // 0: coarse sweep, then the fine groups
+  if (idx == A.idle) return;
+  const int q = idx - 1 - ((A.idle >= 0 && idx > A.idle) ? 1 : 0);   // fine group index
+  if (idx > 0 && q >= A.n_fine) return;
   if (A.active && !A.active[A.ii]) return;
+  const int slot = idx == 0 ? 0 : q + 1;   // barrier words and exchange area
   const InstDev P = A.inst[A.ii];
   for (int m = threadIdx.x; m < C::P2; m += C::NT) T[m] = A.Tg[m];
   for (int m = threadIdx.x; m < N; m += C::NT) lamS[m] = A.lam[m];
   __syncthreads();
   CoopCtx cc;
-  cc.cnt = A.bar + idx * 64;
-  cc.xg = P.work + (int64_t)idx * P.work_vecs * N * N;   // exchange area of the group
+  cc.cnt = A.bar + slot * 64;
+  cc.xg = P.work + (int64_t)slot * P.work_vecs * N * N;   // exchange area of the group
   cc.part = cc.xg + 2 * (int64_t)N * N;
   cc.mem = mem;
   cc.ok = 1;
@@ -2109,8 +2113,11 @@ k_parareal_pipe(PipeArgs A) {
   cc.psel = 0;
   cc.nb = 0;
   const int k0 = *A.kdev;
-  if (idx == 0) pipe_coarse<N, G, NW, OPQ>(A, P, k0, Xs, T, lamS, red, Dl, Ml, Ql, cc);
-  else pipe_fine<N, G, NW, OPQ>(A, P, k0, idx - 1, Xs, T, lamS, Dl, cc);
+  // the coarse sweep with recomputed lane addresses (it would need 370
+  // registers otherwise), the fine solves with hoisted ones (faster, and they
+  // fit the 256 registers of two workgroups per CU as they are)
+  if (idx == 0) pipe_coarse<N, G, NW, true>(A, P, k0, Xs, T, lamS, red, Dl, Ml, Ql, cc);
+  else pipe_fine<N, G, NW, false>(A, P, k0, q, Xs, T, lamS, Dl, cc);
 }
 
 __global__ void k_copy2(const double* __restrict__ src, double* __restrict__ d0,
@@ -3517,12 +3524,12 @@ hipError_t launch_chain_coop(int n, int groups, int mode, const int32_t* insts, 
   }
 }
 
-template <int N, int G, int NW, bool OPQ>
+template <int N, int G, int NW>
 static hipError_t parareal_pipe(PipeArgs A, int n_slices, int32_t* sync, hipStream_t s) {
   using C = GeoC<N, G, NW>;
   const size_t lds =
       ((size_t)N * C::LDB + C::P2 + N + 4 * NW + 3 * (size_t)C::OWN * C::NT) * sizeof(double);
-  const void* fn = (const void*)k_parareal_pipe<N, G, NW, OPQ>;
+  const void* fn = (const void*)k_parareal_pipe<N, G, NW>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0, per_cu = 0;
@@ -3533,21 +3540,30 @@ static hipError_t parareal_pipe(PipeArgs A, int n_slices, int32_t* sync, hipStre
     return e;
   // one coarse-sweep group and up to N - 1 fine groups, all resident at once
   const int max_groups = 8 * (cus * per_cu / (8 * G));
-  const int n_fine = std::min(max_groups - 1, n_slices - 1);
+  const int groups = std::min(max_groups, 8 * ((n_slices + 1 + 7) / 8));
+  const int grid = G * groups;
+  // With more workgroups than CUs the dispatcher gives block b + cus the CU of
+  // block b (measured: every block of a 512-block launch on a 256-CU device
+  // shares its CU with the block 256 later).  The group holding the partners
+  // of the coarse-sweep group (blocks 8m, m < G) is left idle, so the sweep,
+  // the latency-bound part, has its CUs to itself.  Only speed depends on this.
+  int idle = -1;
+  if (grid > cus && (cus / 8) % G == 0 && (cus / 8) / G * 8 < groups) idle = (cus / 8) / G * 8;
+  const int n_fine = std::min(groups - 1 - (idle >= 0 ? 1 : 0), n_slices - 1);
   if (n_fine < 1) return hipErrorCooperativeLaunchTooLarge;
-  const int grid = 8 * G * ((n_fine + 1 + 7) / 8);
   const int bar_words = 64 * 8 * ((n_slices + 7) / 8);
   A.bar = sync;
   A.ucnt = sync + bar_words;
   A.fcnt = A.ucnt + n_slices;
   A.ctl = A.fcnt + n_slices;
   A.n_fine = n_fine;
+  A.idle = idle;
   const int words = pipe_sync_words(n_slices);
   hipLaunchKernelGGL(k_zero_i32, dim3((words + 255) / 256), dim3(256), 0, s, sync, words);
   const int64_t count = (int64_t)n_slices * N * N;   // U_0..U_{N-1} into both input buffers
   hipLaunchKernelGGL(k_copy2, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, A.U, A.Uin,
                      A.Uin + count, count);
-  hipLaunchKernelGGL((k_parareal_pipe<N, G, NW, OPQ>), dim3(grid), dim3(NW * 64), lds, s, A);
+  hipLaunchKernelGGL((k_parareal_pipe<N, G, NW>), dim3(grid), dim3(NW * 64), lds, s, A);
   hipLaunchKernelGGL(k_pipe_finish, dim3(1), dim3(64), 0, s, const_cast<int32_t*>(A.kdev), A.ctl);
   return hipGetLastError();
 }
@@ -3588,7 +3604,7 @@ hipError_t launch_parareal_pipe(int n, const InstDev* inst, int ii, int n_slices
   A.K = K;
   A.sweep_all = sweep_all;
   A.tol = tol;
-  return parareal_pipe<128, 8, 4, true>(A, n_slices, sync, s);
+  return parareal_pipe<128, 8, 4>(A, n_slices, sync, s);
 }
 
 hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts, const InstDev* inst,
