@@ -34,10 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes of one fine-sweep launch of the 128x128 workload, from FETCH_SIZE and
 # WRITE_SIZE counter runs calibrated by a 1 GiB copy, for the kernel as it is now;
 # set to None whenever the fine kernel changes until the counters are taken again.
-FINE_LAUNCH_TRAFFIC_BYTES = (12843542.6 * 2.0 + 25674608.3) * 1024
+FINE_LAUNCH_TRAFFIC_BYTES = (12842892.6 * 2.0 + 25674608.1) * 1024
 # the same for the pipelined launch, per iteration (counters over a 4-iteration
 # launch, divided by 4); None until taken for the kernel as it is now
-PIPE_TRAFFIC_BYTES_PER_ITERATION = None
+PIPE_TRAFFIC_BYTES_PER_ITERATION = (52372317.1 * 2.0 + 104752317.4) * 1024 / 4
 
 
 def fine_flops_per_point_step(n: int) -> float:
@@ -348,6 +348,7 @@ def main():
              "fine_sweep_ms": fine_avg, "correction_ms": corr_avg,
              "fine_only_point_steps_per_s": point_steps / (fine_avg / 1e3),
              "fine_sweep_tflops": flops / (fine_avg / 1e3) / 1e12,
+             "fine_sweep_traffic_bytes": FINE_LAUNCH_TRAFFIC_BYTES,
              "fine_kernel_flops_per_iteration": flops}
     if not args.no_split:
         # the same fine sweep with split-BF16 transforms inside FP64 defect
