@@ -117,7 +117,7 @@ def test_pipelined_run_stops_below_tolerance():
 
 
 def test_pipelined_run_more_slices_than_fine_groups():
-    # 70 slices: the 63 fine groups of a 256-CU device take several items per
+    # 70 slices: the 62 fine groups of a 256-CU device take several items per
     # iteration (persistent), in iteration-major order
     N, J, K = 70, 3, 2
     print(f"pipelined run N={N}", flush=True)
@@ -142,3 +142,42 @@ def test_pipelined_run_matches_oracle():
     d = st["delta"][0].item()
     assert abs(d - ref["delta"][K - 1]) <= 1e-9 * ref["delta"][K - 1]
     assert int(st["status"][0].item()) == 0
+
+
+def test_pipelined_run_with_coarse_substeps_and_after_iterate_calls():
+    # m_c = 2 coarse substeps per slice, and a run that continues an iteration
+    # begun with ch_parareal_iterate: 2 iterate calls + a 2-iteration run
+    # equal 4 iterate calls
+    from paper_2304_14074_amd import chlib
+    N, J = 6, 5
+    p = workloads.Problem(dim=2, n=N128, eps=0.02, T=N * J * 2e-5, n_slices=N, j_fine=J,
+                          m_coarse=2)
+    u0 = workloads.u0_uniform(N128, 2, 0.3, 41)
+
+    def fresh():
+        ctx = chlib.Context([p])
+        assert ctx.ch_fine_groups(N128, 8) == 8
+        st = ctx.new_state()
+        st["U"][: N128 * N128] = torch.from_numpy(u0.reshape(-1)).cuda()
+        return ctx, st
+
+    ctx, st = fresh()
+    print("pipelined run m_c = 2 after iterate calls", flush=True)
+    for _ in range(5):              # prediction + 4 iterations
+        ctx.ch_parareal_iterate(st, -1.0)
+    ref = _snap(st)
+    ctx, st = fresh()
+    for _ in range(3):              # prediction + 2 iterations
+        ctx.ch_parareal_iterate(st, -1.0)
+    ctx.ch_parareal_run(st, -1.0, 2)
+    _same(_snap(st), ref, "m_c = 2, 2 + 2")
+    assert ctx.ch_iteration_count(st) == 4
+
+
+def test_pipelined_run_zero_iterations_forms_only_the_prediction():
+    N, J = 4, 5
+    ref = _reference(N, J, 0, False, -1.0)
+    _, _, ctx, st = _setup(N, J)
+    ctx.ch_parareal_run(st, -1.0, 0)
+    _same(_snap(st), ref[0], "prediction only")
+    assert ctx.ch_iteration_count(st) == 0
