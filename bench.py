@@ -466,7 +466,7 @@ def main():
                         "traffic": (PIPE_TRAFFIC_BYTES_PER_ITERATION * args.steps
                                     if PIPE_TRAFFIC_BYTES_PER_ITERATION else None),
                         "kernel": "k_parareal_pipe<128,8,4> (pipelined iterations: one coarse-"
-                                  "sweep group and 63 fine groups of eight workgroups); flops "
+                                  "sweep group and 62 fine groups of eight workgroups); flops "
                                   "counted: the fine solves' 4n per point-step only"},
            "extra": extra}
     if not args.no_cpu_baseline:

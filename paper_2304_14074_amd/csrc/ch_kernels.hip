@@ -1865,9 +1865,10 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
 // coop_approx2, the update of (2.2), the update norm), so the iterates agree
 // bit for bit; only the schedule differs.
 //
-// Roles: group 0 runs the coarse sweep; groups 1..n_fine run the fine
-// solves, persistent over the items (j, n) taken in iteration-major order
-// (group q + 1 takes items q, q + n_fine, ...).  Iteration j covers slices
+// Roles: group 0 runs the coarse sweep; the other groups (one may be left
+// idle, see parareal_pipe) are fine groups 0..n_fine-1, persistent over the
+// items (j, n) taken in iteration-major order (fine group q takes items q,
+// q + n_fine, ...).  Iteration j covers slices
 // k_j..N-1, k_j = k0 + j (finished slices skipped) or k_j = k0 (sweep_all:
 // every slice from k0 in every iteration, the same iterates with equal work
 // per iteration).
