@@ -18,6 +18,12 @@ Readings taken here:
   * a learned coarse propagator falls back to the plain one once the update
     norm stops contracting (delta^{k+1} >= delta^k, or not finite); G_old is
     then recomputed with the plain propagator at the current iterate.
+  * the plain propagator also judges the learned one's error: before each
+    correction, r^k = mean over the swept slices n >= k of
+    ||G(U_n^k) - F(U_n^k)|| / ||G_plain(U_n^k) - F(U_n^k)|| (G(U_n^k) is
+    G_old_n), and two consecutive iterations with r > 1 (the learned G
+    further from F than the plain one) trigger the same fallback.  Slices
+    where G_plain(U_n^k) equals F(U_n^k) are left out of the mean.
 """
 from __future__ import annotations
 
@@ -43,7 +49,7 @@ def parareal(u0: np.ndarray, n_slices: int, F: Callable, G: Callable,
         U.append(G(U[n]))
     G_old = [U[n + 1].copy() for n in range(N)]
     out = {"U": [list(U)] if keep_iterates else [], "delta": [], "k": 0,
-           "fallback_at": None}
+           "fallback_at": None, "judge": []}
     Fk = [None] * N
     G_cur = G
     prev_delta = np.inf
@@ -53,6 +59,8 @@ def parareal(u0: np.ndarray, n_slices: int, F: Callable, G: Callable,
             if skip_converged and n < k and Fk[n] is not None:
                 continue
             Fk[n] = F(U[n])
+        if fallback_G is not None and G_cur is not fallback_G:
+            out["judge"].append(judge_ratio(U, Fk, G_old, fallback_G, norm, k))
         new = [U[0]]
         for n in range(N):
             g = G_cur(new[n])
@@ -66,8 +74,9 @@ def parareal(u0: np.ndarray, n_slices: int, F: Callable, G: Callable,
             out["U"].append(list(U))
         if delta < tol:
             break
+        judged_worse = len(out["judge"]) >= 2 and min(out["judge"][-2:]) > 1.0
         if (fallback_G is not None and G_cur is not fallback_G
-                and (not np.isfinite(delta) or delta >= prev_delta)):
+                and (not np.isfinite(delta) or delta >= prev_delta or judged_worse)):
             G_cur = fallback_G
             G_old = [fallback_G(U[n]) for n in range(N)]
             out["fallback_at"] = k
@@ -75,3 +84,14 @@ def parareal(u0: np.ndarray, n_slices: int, F: Callable, G: Callable,
     out["k"] = k
     out["final"] = U
     return out
+
+
+def judge_ratio(U, Fk, G_old, G_plain, norm, k) -> float:
+    """Mean over n = k..N-1 of ||G_old_n - F_n|| / ||G_plain(U_n) - F_n||, the
+    slices with a zero denominator left out (nan if none remain)."""
+    r = []
+    for n in range(k, len(Fk)):
+        den = norm(G_plain(U[n]) - Fk[n])
+        if den > 0:
+            r.append(norm(G_old[n] - Fk[n]) / den)
+    return float(np.mean(r)) if r else float("nan")

@@ -125,3 +125,46 @@ def test_toeplitz_power_first_column_lemma_3_4():
             assert abs(Tk[i - 1, 0] - ref) < 1e-13
         # Lemma 3.5
         assert np.max(np.sum(np.abs(Tk), axis=1)) <= min(((1 - beta ** (N - 1)) / (1 - beta)) ** k, math.comb(N - 1, k)) + 1e-12
+
+
+def test_judge_ratio_closed_form_on_a_linear_mode():
+    # on one sine mode F, G and G_plain are scalars phi, gam, gp, so every
+    # slice's ratio is |gam - phi| / |gp - phi| and so is their mean
+    n, N, dT, J, eps = 15, 7, 0.05, 12, 0.08
+    PJ = lm.propagator_matrix(n, 1, dT / J, eps, 2.0, J)   # fine (2.5) form
+    P = lm.propagator_matrix(n, 1, dT, eps, 1.0, 1)        # plain coarse (2.4) form
+    S = ops.sine_matrix(n)
+    u0 = S[:, 2].copy()
+    phi, gp = float(u0 @ PJ @ u0), float(u0 @ P @ u0)
+    for scale in (0.9, 1.3):
+        gam = scale * gp
+        out = parareal.parareal(u0, N, lambda u: PJ @ u, lambda u: scale * (P @ u), _norm1,
+                                tol=0.0, kmax=2, fallback_G=lambda u: P @ u)
+        want = abs(gam - phi) / abs(gp - phi)
+        assert abs(out["judge"][0] - want) < 1e-12 * want, (scale, out["judge"][0], want)
+
+
+def test_judge_triggers_fallback_while_delta_contracts():
+    # a surrogate 10% too large: the update norm still contracts, but the plain
+    # propagator judges it worse in two consecutive iterations -> fallback
+    prob, u0 = _small_problem()
+    Ff = lambda u: propagators.fine(prob, u)
+    Gp = lambda u: propagators.coarse(prob, u)
+    biased = lambda u: 1.1 * propagators.coarse(prob, u)
+    plain_rule = parareal.parareal(u0, prob.n_slices, Ff, biased, _norm1, tol=1e-12)
+    d = plain_rule["delta"]
+    assert all(d[i + 1] < d[i] for i in range(3))          # delta alone would not switch
+    out = parareal.parareal(u0, prob.n_slices, Ff, biased, _norm1, tol=1e-12, fallback_G=Gp)
+    assert out["judge"][0] > 1.0 and out["judge"][1] > 1.0
+    assert out["fallback_at"] == 2
+    seq = propagators.fine_sequential(prob, u0)
+    err = max(_norm1(out["final"][i] - seq[i]) for i in range(prob.n_slices + 1))
+    assert err < 1e-10
+
+
+def test_judge_ratio_zero_for_an_exact_coarse_propagator():
+    prob, u0 = _small_problem()
+    Ff = lambda u: propagators.fine(prob, u)
+    Gp = lambda u: propagators.coarse(prob, u)
+    out = parareal.parareal(u0, prob.n_slices, Ff, Ff, _norm1, tol=1e-12, fallback_G=Gp)
+    assert out["judge"][0] == 0.0 and out["fallback_at"] is None
