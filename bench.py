@@ -405,6 +405,7 @@ def main():
                 r = surrogate.run_parareal(cq, ue, 1e-8)
                 row[kind] = {"iterations": r["iterations"], "seconds": r["seconds"],
                              "fallback_at": r["fallback_at"], "final_delta": r["deltas"][-1],
+                             "judge_ratios": r["judge"],
                              "max_slice_rel_err_vs_serial_fine": trajectory_error(r["U"], traj),
                              "effective_point_steps_per_s": N * J * P / r["seconds"]}
             runs.append(row)

@@ -130,6 +130,14 @@ ch_status ch_parareal_iterate(ch_ctx* ctx, ch_pr_state* st, double tol, ch_strea
  * call equals one ch_parareal_iterate. */
 ch_status ch_parareal_correct(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream);
 
+/* out[i] = ||A_i - B_i||_h (h^d-weighted L2 norm, the norm of the update norm,
+ * Section 4) for every slice i of the slice layout, in slice order over all
+ * instances (out holds the total slice count).  A, B and out are device
+ * memory; A and B use the slice layout.  Used to judge a coarse propagator's
+ * error against F slice by slice (see the learned propagator's driver). */
+ch_status ch_slice_distance(ch_ctx* ctx, const double* A, const double* B, double* out,
+                            ch_stream stream);
+
 /* Up to max_iters steps of the Parareal iteration (2.2) in one launch, each
  * equal to one ch_parareal_iterate call: iteration k sweeps the slices n >= k
  * (finite termination) and the run stops after the first iteration whose

@@ -28,7 +28,7 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind",
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
            "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups",
-           "ch_parareal_run")
+           "ch_parareal_run", "ch_slice_distance")
 
 
 class ChProblem(ctypes.Structure):
@@ -74,6 +74,7 @@ def load() -> ctypes.CDLL:
     lib.ch_parareal_iterate.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, vp]
     lib.ch_parareal_correct.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, vp]
     lib.ch_parareal_run.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.c_double, i32, i32, vp]
+    lib.ch_slice_distance.argtypes = [vp, vp, vp, vp, vp]
     lib.ch_energy.argtypes = [vp, i32, vp, i32, vp, vp]
     lib.ch_status_str.argtypes = [i32]
     lib.ch_status_str.restype = ctypes.c_char_p
@@ -104,7 +105,8 @@ def load() -> ctypes.CDLL:
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
                  "ch_nn_bind", "ch_set_coarse_kind", "ch_parareal_graph_create", "ch_graph_launch",
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
-                 "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run"):
+                 "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run",
+                 "ch_slice_distance"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -206,6 +208,9 @@ class Context:
         c = self._state_struct(state)
         self._check(self.lib.ch_parareal_run(self.h, ctypes.byref(c), float(tol), int(max_iters),
                                              1 if sweep_all else 0, _stream(stream)))
+
+    def ch_slice_distance(self, A, B, out, stream=None):
+        self._check(self.lib.ch_slice_distance(self.h, _ptr(A), _ptr(B), _ptr(out), _stream(stream)))
 
     def ch_energy(self, inst, u, count, E_out, stream=None):
         self._check(self.lib.ch_energy(self.h, inst, _ptr(u), count, _ptr(E_out), _stream(stream)))

@@ -913,6 +913,22 @@ ch_status ch_set_coarse_kind(ch_ctx* c, int32_t inst, int32_t kind, ch_stream st
                    "coarse kind update");
 }
 
+ch_status ch_slice_distance(ch_ctx* c, const double* A, const double* B, double* out,
+                            ch_stream stream) {
+  ch_status st = require_bound(c);
+  if (st != CH_OK) return st;
+  if (!A || !B || !out) return fail(c, CH_ERR_ARG, "null pointer");
+  const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
+  for (auto& cp : c->classes) {
+    st = hip_check(c, chk::launch_slice_dist((const WorkItem*)(c->ws + cp.items_blk.off),
+                                             (int)cp.items.size(), inst, A, B, out,
+                                             (hipStream_t)stream),
+                   "slice distance");
+    if (st != CH_OK) return st;
+  }
+  return CH_OK;
+}
+
 ch_status ch_energy(ch_ctx* c, int32_t inst, const double* u, int32_t count, double* E_out,
                     ch_stream stream) {
   ch_status st = require_bound(c);

@@ -115,6 +115,9 @@ hipError_t launch_cg_tables(int n, int dim, const int32_t* insts, int n_insts,
                             const InstDev* inst, const double* lam, hipStream_t s);
 hipError_t launch_energy(int n, int dim, const double* u, int count, double eps, double* E,
                          hipStream_t s);
+// out[slice_base + slice] = ||A - B||_h per work item (slice layout).
+hipError_t launch_slice_dist(const WorkItem* items, int n_items, const InstDev* inst,
+                             const double* A, const double* B, double* out, hipStream_t s);
 hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
                               int first, const int32_t* kdev, hipStream_t s);
 hipError_t launch_counter(int32_t* kdev, int value, int add, hipStream_t s);

@@ -3116,6 +3116,37 @@ __global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
 
 // --------------------------------------------------------------- energy
 // E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u); one block per state.
+// Per-slice distance ||A_n - B_n||_h (h^d-weighted L2, the norm of the update
+// norm) for the work items of one class, slice layout; one block per item,
+// summed in a fixed order.  Streams both states once: 16 bytes per point.
+__global__ void __launch_bounds__(256)
+k_slice_dist(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+             const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ out) {
+  __shared__ double red[4];
+  const WorkItem it = items[blockIdx.x];
+  const InstDev& P = inst[it.inst];
+  const int64_t pts = P.dim == 2 ? (int64_t)P.n * P.n : P.n;
+  const int64_t off = P.off_slices + (int64_t)it.slice * pts;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < pts; i += 256) {
+    const double d = A[off + i] - B[off + i];
+    acc += d * d;
+  }
+  double v[1] = {acc};
+  block_sum<4, 1>(v, red);
+  if (threadIdx.x == 0) {
+    const double hd = P.dim == 2 ? P.h * P.h : P.h;
+    out[P.slice_base + it.slice] = sqrt(hd * v[0]);
+  }
+}
+
+hipError_t launch_slice_dist(const WorkItem* items, int n_items, const InstDev* inst,
+                             const double* A, const double* B, double* out, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_dist, dim3(n_items), dim3(256), 0, s, items, inst, A, B, out);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256)
 k_energy(int n, int dim, const double* __restrict__ u, double eps, double* __restrict__ E) {
   __shared__ double red[8];
