@@ -147,6 +147,59 @@ def bench_nonlinear(args):
                       "status": int(st["status"][0].item()), "finite": ok}}
 
 
+def bench_hbm(args):
+    """The library's streaming kernels on a large batch (1024 slices of 128^2,
+    134 MB per state set), against the 8 TB/s HBM peak: the per-slice distance
+    (k_slice_dist, the learned propagator's judge; reads two states, 16 B per
+    point) and the discrete energy (k_energy; one state, 8 B per point, the
+    5-point neighbours from cache).  The distance kernel reads 268 MB per call,
+    more than the 256 MB last-level cache; the energy kernel's 134 MB fits in
+    it, so repeated calls may be served from there and its rate is not an HBM
+    figure."""
+    import torch
+    import workloads
+    from paper_2304_14074_amd import chlib
+    n, N = 128, 1024
+    prob = workloads.Problem(dim=2, n=n, eps=0.02, T=N * 2e-5, n_slices=N, j_fine=1)
+    ctx = chlib.Context([prob])
+    P = n * n
+    g = torch.Generator(device="cuda").manual_seed(0)
+    A = torch.rand(N * P, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    B = torch.rand(N * P, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    out = torch.empty(N, dtype=torch.float64, device="cuda")
+    E = torch.empty(N, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.steps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms_d = timed(lambda: ctx.ch_slice_distance(A, B, out))
+    ms_e = timed(lambda: ctx.ch_energy(0, A, N, E))
+    gbs_d = 2 * N * P * 8 / (ms_d / 1e3) / 1e9
+    gbs_e = N * P * 8 / (ms_e / 1e3) / 1e9
+    return {"metric": "HBM GB/s of the streaming kernels (diagnostic mode)", "value": gbs_d,
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_d, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "1024 slices of a 128x128 grid, FP64, uniform(-0.5, 0.5)",
+                       "n": n, "slices": N},
+            "roofline": {"bound": "hbm", "achieved": gbs_d, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs_d / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_slice_dist (per-slice ||A_n - B_n||_h, 16 B per point)"},
+            "extra": {"slice_distance_ms": ms_d, "slice_distance_GBps": gbs_d,
+                      "energy_ms": ms_e, "energy_GBps": gbs_e,
+                      "energy_frac_of_hbm_peak": gbs_e / HBM_PEAK_GBS}}
+
+
 def bench_batched(args):
     """256 independent instances of uneven size (n in {64, 128, 256}, N in
     {32, 64, 128}, eps ~ U(0.01, 0.04), J = 1563), FP64 linear fine step,
@@ -230,7 +283,7 @@ def main():
     ap.add_argument("--nn-traj", type=int, default=256)
     ap.add_argument("--nn-steps", type=int, default=3000)
     ap.add_argument("--workload", default="linear_2d_128",
-                    choices=["linear_2d_128", "batched", "nonlinear"])
+                    choices=["linear_2d_128", "batched", "nonlinear", "hbm"])
     ap.add_argument("--nl-steps", type=int, default=20,
                     help="implicit steps per slice timed in --workload nonlinear")
     ap.add_argument("--profile-fine", action="store_true",
@@ -247,6 +300,9 @@ def main():
         return
     if args.workload == "nonlinear":
         print(json.dumps(bench_nonlinear(args)))
+        return
+    if args.workload == "hbm":
+        print(json.dumps(bench_hbm(args)))
         return
     if args.profile_fine:
         # one fine-sweep launch of the workload plus a plain 1 GiB device copy

@@ -3153,12 +3153,15 @@ k_energy(int n, int dim, const double* __restrict__ u, double eps, double* __res
   const double* s = u + (int64_t)blockIdx.x * (dim == 2 ? (int64_t)n * n : n);
   const double h = 1.0 / (n + 1), ih2 = 1.0 / (h * h);
   double bulk = 0.0, grad = 0.0;
-  const int64_t tot = dim == 2 ? (int64_t)n * n : n;
-  for (int64_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+  const int tot = dim == 2 ? n * n : n;
+  // 2D grids have n = 2^ln (32 .. 256): row and column by shift and mask
+  const int ln = 31 - __builtin_clz(n);
+#pragma unroll 4
+  for (int idx = threadIdx.x; idx < tot; idx += 256) {
     const double c = s[idx];
     double lap;
     if (dim == 2) {
-      const int iy = (int)(idx / n), ix = (int)(idx % n);
+      const int iy = idx >> ln, ix = idx & (n - 1);
       const double a = iy > 0 ? s[idx - n] : 0.0, b = iy < n - 1 ? s[idx + n] : 0.0;
       const double l = ix > 0 ? s[idx - 1] : 0.0, r = ix < n - 1 ? s[idx + 1] : 0.0;
       lap = ((a + b) + (l + r) - 4.0 * c) * ih2;

@@ -109,7 +109,8 @@ def test_f_zero_closed_form_mode_decay():
 
 def test_energy_matches_oracle():
     from paper_2304_14074_amd import chlib
-    for dim, n in [(2, 64), (2, 128), (1, 128)]:
+    # every 2D size (the row-walking kernel, including n = 32's partial wave) and 1D
+    for dim, n in [(2, 32), (2, 64), (2, 128), (2, 256), (1, 128), (1, 50)]:
         p = workloads.Problem(dim=dim, n=n, eps=0.02, T=1.0, n_slices=3, j_fine=1)
         ctx = chlib.Context([p])
         X = _states(n, dim, 3, seed=5)
