@@ -1868,10 +1868,9 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
 // Roles: group 0 runs the coarse sweep; the other groups (one may be left
 // idle, see parareal_pipe) are fine groups 0..n_fine-1, persistent over the
 // items (j, n) taken in iteration-major order (fine group q takes items q,
-// q + n_fine, ...).  Iteration j covers slices
-// k_j..N-1, k_j = k0 + j (finished slices skipped) or k_j = k0 (sweep_all:
-// every slice from k0 in every iteration, the same iterates with equal work
-// per iteration).
+// q + n_fine, ...).  Iteration j covers slices k_j..N-1, with k_j = k0 + j
+// (finished slices skipped) or k_j = k0 (sweep_all: every slice from k0 in
+// every iteration, the same iterates with equal work per iteration).
 // Hand-off buffers, written and read with the coherent accesses of the
 // exchanges: Uin[j % 2] holds the fine inputs of iteration j, F0 / F1 the
 // fine results of even / odd iterations.  Uin[j % 2][n] is rewritten only by
