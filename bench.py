@@ -129,6 +129,21 @@ def bench_nonlinear(args):
     ms = e0.elapsed_time(e1) / args.steps
     point_steps = N * args.nl_steps * P
     ok = bool(torch.isfinite(F).all().item())
+    # the fully implicit backward-Euler variant of the step on the same shape
+    qb = dataclasses.replace(q, nl_variant="be")
+    cb = chlib.Context([qb])
+    Fb = torch.empty_like(U_in)
+    cb.ch_fine_propagate(U_in, Fb)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(args.steps):
+        cb.ch_fine_propagate(U_in, Fb)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms_be = e0.elapsed_time(e1) / args.steps
+    be = {"ms_per_fine_step": ms_be / args.nl_steps,
+          "point_steps_per_s": point_steps / (ms_be / 1e3),
+          "finite": bool(torch.isfinite(Fb).all().item())}
     return {"metric": METRIC, "value": point_steps / (ms / 1e3), "unit": "grid-point-steps/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -144,7 +159,8 @@ def bench_nonlinear(args):
             "roofline": None,
             "extra": {"ms_per_fine_step": ms / args.nl_steps,
                       "projected_full_fine_sweep_s": ms / args.nl_steps * prob.j_fine / 1e3,
-                      "status": int(st["status"][0].item()), "finite": ok}}
+                      "status": int(st["status"][0].item()), "finite": ok,
+                      "backward_euler": be}}
 
 
 def bench_hbm(args):
