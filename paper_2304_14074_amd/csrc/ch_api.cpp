@@ -64,6 +64,17 @@ struct ch_ctx {
   size_t host_init_bytes = 0;       // leading part of the workspace uploaded at bind
   char* ws = nullptr;               // bound workspace
   std::string err;
+  // side streams that run the sequential coarse sweeps of the grid-size
+  // classes concurrently (each sweep alone fills few CUs), created on first
+  // use; forked from and joined to the caller's stream with events
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_done;
+  hipEvent_t fork_ev = nullptr;
+  ~ch_ctx() {
+    for (hipEvent_t e : side_done) hipEventDestroy(e);
+    for (hipStream_t q : side) hipStreamDestroy(q);
+    if (fork_ev) hipEventDestroy(fork_ev);
+  }
 };
 
 namespace {
@@ -462,12 +473,54 @@ ch_status ch_fine_propagate(ch_ctx* c, const double* U_in, double* F_out, const 
   return fine_all(c, U_in, F_out, mask, nullptr, nullptr, 0, (hipStream_t)stream);
 }
 
+// Fork the caller's stream into one side stream per class after the first
+// (default priority, non-blocking), so the classes' sequential coarse sweeps
+// run side by side; join_sides makes the caller's stream wait for all of them.
+// Both work inside a stream capture (the side streams join the capture).
+static ch_status fork_sides(ch_ctx* c, size_t count, hipStream_t s) {
+  ch_status r;
+  if (!c->fork_ev) {
+    r = hip_check(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "fork event");
+    if (r != CH_OK) return r;
+  }
+  while (c->side.size() < count) {
+    hipStream_t q = nullptr;
+    hipEvent_t e = nullptr;
+    r = hip_check(c, hipStreamCreateWithFlags(&q, hipStreamNonBlocking), "side stream");
+    if (r != CH_OK) return r;
+    c->side.push_back(q);
+    r = hip_check(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "side event");
+    if (r != CH_OK) return r;
+    c->side_done.push_back(e);
+  }
+  r = hip_check(c, hipEventRecord(c->fork_ev, s), "fork record");
+  for (size_t i = 0; i < count && r == CH_OK; ++i)
+    r = hip_check(c, hipStreamWaitEvent(c->side[i], c->fork_ev, 0), "fork wait");
+  return r;
+}
+static ch_status join_sides(ch_ctx* c, size_t count, hipStream_t s) {
+  ch_status r = CH_OK;
+  for (size_t i = 0; i < count && r == CH_OK; ++i) {
+    r = hip_check(c, hipEventRecord(c->side_done[i], c->side[i]), "join record");
+    if (r == CH_OK) r = hip_check(c, hipStreamWaitEvent(s, c->side_done[i], 0), "join wait");
+  }
+  return r;
+}
+
 static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_out,
-                            const uint8_t* mask, ch_pr_state* st, int k, hipStream_t s) {
+                            const uint8_t* mask, ch_pr_state* st, int k, hipStream_t s0) {
   const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
   const int32_t* active = mode == 0 ? nullptr : (const int32_t*)(c->ws + c->active_blk.off);
   const int32_t* kdev = mode == 2 ? (const int32_t*)(c->ws + c->k_blk.off) : nullptr;
-  for (auto& cp : c->classes) {
+  // sequential sweeps (modes 1, 2) of several classes: one stream per class
+  const size_t n_side = (mode != 0 && c->classes.size() > 1) ? c->classes.size() - 1 : 0;
+  if (n_side) {
+    ch_status r = fork_sides(c, n_side, s0);
+    if (r != CH_OK) return r;
+  }
+  for (size_t ci = 0; ci < c->classes.size(); ++ci) {
+    auto& cp = c->classes[ci];
+    hipStream_t s = (n_side && ci > 0) ? c->side[ci - 1] : s0;
     const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
     const int32_t* insts = (const int32_t*)(c->ws + cp.insts_blk.off);
     const double* tab = class_sine(c, cp);
@@ -505,6 +558,11 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     ch_status r = hip_check(c, e, "coarse launch");
     if (r != CH_OK) return r;
   }
+  if (n_side) {
+    ch_status r = join_sides(c, n_side, s0);
+    if (r != CH_OK) return r;
+  }
+  hipStream_t s = s0;
   // learned coarse propagator: host-driven sequence of network passes
   for (int i = 0; i < (int)c->probs.size(); ++i) {
     const InstDev& d = c->inst[i];
