@@ -7,7 +7,11 @@
  * equation, each split into N time slices of length dT = T/N (Section 2).
  * All device memory is owned by the caller: the library never allocates
  * device memory; it asks for a workspace size and works inside the buffer it
- * is given.  Every call is asynchronous on the given HIP stream.
+ * is given.  Every call is asynchronous on the given HIP stream.  The only HIP
+ * objects the library creates are side streams (default priority) and
+ * events, with which the coarse sweeps of several grid-size classes run side
+ * by side; they are forked from and joined back to the given stream, so the
+ * caller sees stream order, also under stream capture.
  *
  * Data layout (all float64, row-major, interior points only, y slowest):
  *   one state           : n^d values, index iy*n + ix;
