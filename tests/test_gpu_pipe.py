@@ -181,3 +181,42 @@ def test_pipelined_run_zero_iterations_forms_only_the_prediction():
     ctx.ch_parareal_run(st, -1.0, 0)
     _same(_snap(st), ref[0], "prediction only")
     assert ctx.ch_iteration_count(st) == 0
+
+
+def test_pipelined_full_size_matches_two_launch_and_oracle_samples():
+    # the benchmark's workload and launch shape (128^2, N = 64, J = 1563, one
+    # coarse group and 62 fine groups): two pipelined iterations (every slice
+    # swept) equal two two-launch iterations bit for bit, and sampled values
+    # of the first iteration match the oracle: U_1^1 = F(U_0) and
+    # U_2^1 = F(U_1^0) + G(U_1^1) - G(U_1^0)
+    from paper_2304_14074_amd import chlib
+    p = workloads.linear_2d_128()
+    u0 = workloads.linear_2d_128_u0(0)
+    n, N = p.n, p.n_slices
+    P = n * n
+
+    def fresh():
+        ctx = chlib.Context([p])
+        st = ctx.new_state()
+        st["U"][:P] = torch.from_numpy(u0.reshape(-1)).cuda()
+        ctx.ch_parareal_iterate(st, 0.0)          # the coarse prediction U^0
+        return ctx, st
+
+    print("full-size pipelined vs two-launch, 2 iterations", flush=True)
+    ctx, st = fresh()
+    U0 = st["U"].cpu().numpy().reshape(N + 1, n, n)
+    ctx.ch_parareal_run(st, -1.0, 1, sweep_all=True)
+    U1 = st["U"].cpu().numpy().reshape(N + 1, n, n)
+    ctx.ch_set_iteration(st, 0)
+    ctx.ch_parareal_run(st, -1.0, 1, sweep_all=True)
+    pipe2 = _snap(st)
+    ctx, st = fresh()
+    for _ in range(2):
+        ctx.ch_set_iteration(st, 0)
+        ctx.ch_parareal_iterate(st, -1.0)
+    _same(pipe2, _snap(st), "two iterations at full size")
+    # oracle samples of the first iteration
+    ref1 = propagators.fine(p, U0[0])
+    assert gu.rel(U1[1], ref1) < TOL, gu.rel(U1[1], ref1)
+    ref2 = propagators.fine(p, U0[1]) + (propagators.coarse(p, U1[1]) - propagators.coarse(p, U0[1]))
+    assert gu.rel(U1[2], ref2) < TOL, gu.rel(U1[2], ref2)
