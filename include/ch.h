@@ -138,7 +138,7 @@ ch_status ch_parareal_correct(ch_ctx* ctx, ch_pr_state* st, double tol, ch_strea
  * Section 4) for every slice i of the slice layout, in slice order over all
  * instances (out holds the total slice count).  A, B and out are device
  * memory; A and B use the slice layout.  Used to judge a coarse propagator's
- * error against F slice by slice (see the learned propagator's driver). */
+ * error against F slice by slice (the learned propagator's Parareal loop). */
 ch_status ch_slice_distance(ch_ctx* ctx, const double* A, const double* B, double* out,
                             ch_stream stream);
 

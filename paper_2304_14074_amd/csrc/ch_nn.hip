@@ -387,7 +387,7 @@ hipError_t masked_copy(double* dst, const double* src, const uint8_t* mask, int6
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- drivers
+// ---------------------------------------------------------------- host launchers
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
                       const NNPlan& p, double* out, hipStream_t s) {
   const int64_t cnt = (int64_t)batch * n * n;

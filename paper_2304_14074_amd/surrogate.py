@@ -7,7 +7,7 @@ whose "slices" are the S current states, so one ch_fine_propagate moves every
 trajectory by dT.  The network (ch_nn_*) is trained on the pairs
 (u(T_n), u(T_{n+1})) with Adam; weights are BF16 with an FP32 master copy.
 
-The Parareal driver implements the fallback: the learned propagator is used
+The Parareal loop implements the fallback: the learned propagator is used
 until the update norm stops contracting (delta^{k+1} >= delta^k, or a
 non-finite delta) or the plain propagator, its judge, finds it further from F
 than itself in two consecutive iterations; the instance then switches to the

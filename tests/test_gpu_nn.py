@@ -220,7 +220,7 @@ def test_slice_distance_matches_numpy():
 
 
 def test_plain_propagator_judges_the_learned_one_like_the_oracle():
-    # the driver's judge ratios (mean over the swept slices of the learned
+    # the Parareal loop's judge ratios (mean over the swept slices of the learned
     # G's distance from F over the plain G's) against the oracle's, with the
     # same BF16 weights; the fallback comes at the same iteration
     from paper_2304_14074_amd import chlib, surrogate
