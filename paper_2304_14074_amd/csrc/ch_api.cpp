@@ -71,9 +71,9 @@ struct ch_ctx {
   std::vector<hipEvent_t> side_done;
   hipEvent_t fork_ev = nullptr;
   ~ch_ctx() {
-    for (hipEvent_t e : side_done) hipEventDestroy(e);
-    for (hipStream_t q : side) hipStreamDestroy(q);
-    if (fork_ev) hipEventDestroy(fork_ev);
+    for (hipEvent_t e : side_done) (void)hipEventDestroy(e);
+    for (hipStream_t q : side) (void)hipStreamDestroy(q);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
   }
 };
 
@@ -118,6 +118,9 @@ bool supported_2d(int n) { return n == 32 || n == 64 || n == 128 || n == 256; }
 }  // namespace
 
 extern "C" {
+
+// side streams of the per-class coarse sweeps (defined with coarse_all)
+static ch_status make_sides(ch_ctx* c, size_t count);
 
 const char* ch_status_str(ch_status s) {
   switch (s) {
@@ -404,6 +407,12 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
                    "cg tables");
     if (st != CH_OK) return st;
   }
+  // side streams of the per-class coarse sweeps, made here so that no stream
+  // is created while a caller captures
+  if (c->classes.size() > 1) {
+    st = make_sides(c, c->classes.size() - 1);
+    if (st != CH_OK) return st;
+  }
   // the host image must outlive the copy
   return hip_check(c, hipStreamSynchronize(s), "bind synchronize");
 }
@@ -477,7 +486,7 @@ ch_status ch_fine_propagate(ch_ctx* c, const double* U_in, double* F_out, const 
 // (default priority, non-blocking), so the classes' sequential coarse sweeps
 // run side by side; join_sides makes the caller's stream wait for all of them.
 // Both work inside a stream capture (the side streams join the capture).
-static ch_status fork_sides(ch_ctx* c, size_t count, hipStream_t s) {
+static ch_status make_sides(ch_ctx* c, size_t count) {
   ch_status r;
   if (!c->fork_ev) {
     r = hip_check(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "fork event");
@@ -493,6 +502,11 @@ static ch_status fork_sides(ch_ctx* c, size_t count, hipStream_t s) {
     if (r != CH_OK) return r;
     c->side_done.push_back(e);
   }
+  return CH_OK;
+}
+static ch_status fork_sides(ch_ctx* c, size_t count, hipStream_t s) {
+  ch_status r = make_sides(c, count);
+  if (r != CH_OK) return r;
   r = hip_check(c, hipEventRecord(c->fork_ev, s), "fork record");
   for (size_t i = 0; i < count && r == CH_OK; ++i)
     r = hip_check(c, hipStreamWaitEvent(c->side[i], c->fork_ev, 0), "fork wait");
@@ -751,16 +765,16 @@ ch_status ch_autotune(ch_ctx* c, const double* U_in, double* F_out, int32_t step
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e != hipSuccess) {
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         return hip_check(c, e, "autotune run");
       }
       if (ms < best) { best = ms; best_w = opts[o]; }
     }
     cp.waves = best_w;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return CH_OK;
 }
 
@@ -856,7 +870,7 @@ ch_status ch_parareal_graph_create(ch_ctx* c, ch_pr_state* st, double tol, ch_st
   if (r != CH_OK) return r;
   hipGraphExec_t ex = nullptr;
   r = hip_check(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "instantiate");
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (r != CH_OK) return r;
   *graph_exec = (void*)ex;
   return CH_OK;
