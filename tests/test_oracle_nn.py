@@ -61,3 +61,40 @@ def test_network_layers_match_loop_convolutions():
     ref = u[0] + h[0]
     got = nn.forward(torch.tensor(th), torch.tensor(u), TINY)[0].numpy()
     assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def _constant_shift_theta(c):
+    # every weight and bias zero except the 1x1 head's bias: all hidden
+    # features vanish and the network adds the constant c to its input
+    th = np.zeros(nn.n_params())
+    o = 0
+    for name, ci, co, k, _, _, _ in nn.LAYERS:
+        o += co * ci * k * k
+        if name == "head":
+            th[o:o + co] = c
+        o += co
+    return th
+
+
+def test_surrogate_step_clips_only_outside_the_bound():
+    # with a zero network plus head bias c, forward(u) = u + c exactly; the
+    # coarse propagator clips that to [-1.5, 1.5] and leaves the rest as is
+    u = np.random.default_rng(5).uniform(-1, 1, (16, 16))
+    for c in (0.7, -0.7):
+        th = _constant_shift_theta(c)
+        raw = nn.forward(torch.tensor(th), torch.tensor(u[None]))[0].numpy()
+        assert np.max(np.abs(raw - (u + c))) == 0.0
+        got = nn.surrogate_step(th, u)
+        out = np.abs(u + c) > nn.OUT_BOUND
+        assert out.any() and (~out).any()
+        assert np.array_equal(got[~out], raw[~out])
+        assert np.all(got[out] == np.sign(c) * nn.OUT_BOUND)
+
+
+def test_surrogate_step_equals_forward_inside_the_bound():
+    rng = np.random.default_rng(6)
+    th = 0.05 * rng.standard_normal(nn.n_params())
+    u = rng.uniform(-0.5, 0.5, (16, 16))
+    raw = nn.forward(torch.tensor(th), torch.tensor(u[None]))[0].numpy()
+    assert np.max(np.abs(raw)) < nn.OUT_BOUND
+    assert np.array_equal(nn.surrogate_step(th, u), raw)

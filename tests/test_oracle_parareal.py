@@ -100,8 +100,7 @@ def test_linearised_error_bound(i_fine, i_coarse):
     n, N, dT, J, eps = 15, 10, 0.02, 20, 0.1
     PJ = lm.propagator_matrix(n, 1, dT / J, eps, i_fine, J)
     P = lm.propagator_matrix(n, 1, dT, eps, i_coarse, 1)
-    alpha = float(np.linalg.norm(PJ - P, 2))
-    beta = float(np.linalg.norm(P, 2))
+    alpha, beta = lm.alpha_beta(n, 1, dT, J, eps, i_fine, i_coarse)
     assert 0 < beta < 1  # Lemma 3.1
     u0 = np.random.default_rng(4).uniform(-1, 1, n)
     exact = [u0]
@@ -168,3 +167,69 @@ def test_judge_ratio_zero_for_an_exact_coarse_propagator():
     Gp = lambda u: propagators.coarse(prob, u)
     out = parareal.parareal(u0, prob.n_slices, Ff, Ff, _norm1, tol=1e-12, fallback_G=Gp)
     assert out["judge"][0] == 0.0 and out["fallback_at"] is None
+
+
+def _symbol(lam, tau, eps, i):
+    # eigenvalue of (I - i tau D + eps^2 tau D^2)^{-1} (I - i tau D) on the
+    # sine mode whose D_h eigenvalue is lam (Section 3)
+    return (1.0 - i * tau * lam) / (1.0 - i * tau * lam + eps * eps * tau * lam * lam)
+
+
+@pytest.mark.parametrize("dim,n,i_fine,i_coarse", [(1, 15, 2.0, 1.0), (1, 20, 1.0, 1.0),
+                                                   (2, 6, 2.0, 2.0), (2, 7, 2.0, 1.0)])
+def test_alpha_beta_from_the_sine_eigenvalues(dim, n, i_fine, i_coarse):
+    # P_i and P_{J_i} are symmetric and share the sine eigenvectors, so their
+    # 2-norms are the largest moduli of their symbols over the DST spectrum
+    dT, J, eps = 0.03, 9, 0.07
+    lam = ops.eigenvalues_paper(n)
+    Lam = lam if dim == 1 else (lam[:, None] + lam[None, :]).ravel()
+    gJ = _symbol(Lam, dT / J, eps, i_fine) ** J
+    g = _symbol(Lam, dT, eps, i_coarse)
+    alpha, beta = lm.alpha_beta(n, dim, dT, J, eps, i_fine, i_coarse)
+    assert abs(alpha - np.max(np.abs(gJ - g))) <= 1e-12 * alpha
+    assert abs(beta - np.max(np.abs(g))) <= 1e-12 * beta
+
+
+@pytest.mark.parametrize("kind,m", [("approx2", 3), ("stab", 4)])
+def test_coarse_substeps_take_tau_dT_over_m(kind, m):
+    # f == 0: the coarse step is diagonal on a sine mode, with factor
+    # 1 / (1 + eps^2 tau Lam^2) for (2.4) and (1 - s tau Lam) / (1 + eps^2 tau
+    # Lam^2 - s tau Lam) for the stabilised step; m substeps of tau = dT/m give
+    # that factor to the power m
+    n, eps, s = 24, 0.05, 2.0
+    p = workloads.Problem(dim=2, n=n, eps=eps, T=0.02, n_slices=2, j_fine=5, m_coarse=m,
+                          coarse_kind=kind, f_zero=True)
+    x = np.arange(1, n + 1) / (n + 1)
+    u = np.outer(np.sin(2 * np.pi * x), np.sin(3 * np.pi * x))
+    lam = ops.eigenvalues_paper(n)
+    Lam = lam[1] + lam[2]
+    tau = p.dT / m
+    sv = s if kind == "stab" else 0.0
+    rho = (1 - sv * tau * Lam) / (1 + eps * eps * tau * Lam * Lam - sv * tau * Lam)
+    v = propagators.coarse(p, u)
+    assert np.max(np.abs(v - rho ** m * u)) <= 1e-13 * np.max(np.abs(u))
+    # one coarse step of the whole slice differs (the substeps are taken)
+    rho1 = (1 - sv * p.dT * Lam) / (1 + eps * eps * p.dT * Lam * Lam - sv * p.dT * Lam)
+    assert abs(rho ** m - rho1) > 1e-3 * abs(rho1)
+
+
+def test_parareal_closed_form_with_coarse_substeps():
+    # the binomial closed form of the iterates on one sine mode, with the
+    # propagators themselves (f == 0, m_c = 3 coarse substeps)
+    n, N = 16, 6
+    p = workloads.Problem(dim=1, n=n, eps=0.06, T=0.06, n_slices=N, j_fine=7, m_coarse=3,
+                          f_zero=True)
+    S = ops.sine_matrix(n)
+    u0 = S[:, 3].copy()
+    Lam = ops.eigenvalues_paper(n)[3]
+    tf = p.dt
+    phi = ((1 - p.s_fine * tf * Lam) / (1 + p.eps ** 2 * tf * Lam ** 2 - p.s_fine * tf * Lam)) ** p.j_fine
+    tc = p.dT / p.m_coarse
+    gam = (1.0 / (1 + p.eps ** 2 * tc * Lam ** 2)) ** p.m_coarse
+    out = parareal.parareal(u0, N, lambda u: propagators.fine(p, u),
+                            lambda u: propagators.coarse(p, u), _norm1, tol=0.0)
+    for k, Uk in enumerate(out["U"]):
+        for nn in range(N + 1):
+            c = sum(math.comb(nn, j) * (phi - gam) ** j * gam ** (nn - j)
+                    for j in range(0, min(k, nn) + 1))
+            assert np.max(np.abs(Uk[nn] - c * u0)) < 1e-12, (k, nn)

@@ -128,3 +128,21 @@ def test_energy_non_increasing(scheme):
     E = np.array(E)
     assert np.all(np.diff(E) <= 1e-14 * np.abs(E[:-1]))
     assert E[-1] < E[0]
+
+
+@pytest.mark.parametrize("variant,dim,n", [("eyre", 1, 12), ("eyre", 2, 6), ("be", 1, 12), ("be", 2, 6)])
+def test_newton_residual_is_the_scheme_defect(variant, dim, n):
+    # H(Y) at an arbitrary Y against the scheme written with loop stencils,
+    # and H vanishes (to the Newton stop) at the step's result
+    u = _u0(n, dim, amp=0.8, seed=13)
+    y = _u0(n, dim, amp=0.8, seed=14)
+    tau, eps = 4e-4, 0.05
+    L = lap_loops
+    if variant == "eyre":
+        want = y + eps ** 2 * tau * L(L(y)) - tau * L(y ** 3) - (u - tau * L(u))
+    else:
+        want = y + eps ** 2 * tau * L(L(y)) - tau * L(y ** 3 - y) - u
+    got = schemes.newton_residual(y, u, tau, eps, variant)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    v = schemes.step_newton(u, tau, eps, variant, tol=1e-13)
+    assert np.max(np.abs(schemes.newton_residual(v, u, tau, eps, variant))) < 1e-9
