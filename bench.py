@@ -409,8 +409,8 @@ def main():
     wall = time.perf_counter() - t0
     run_ms = e0.elapsed_time(e1)
     done = ctx.ch_iteration_count(st)
-    status = int(st["status"][0].item())
-    assert done == args.steps and status == 0, (done, status)
+    ctx.ch_check_status(st)                     # raises on any device-side failure
+    assert done == args.steps, done
     ms_per_step = wall * 1e3 / args.steps
     value = point_steps / (ms_per_step / 1e3)
     achieved = flops * args.steps / (run_ms / 1e3) / 1e12

@@ -9,9 +9,11 @@
  * device memory; it asks for a workspace size and works inside the buffer it
  * is given.  Every call is asynchronous on the given HIP stream.  The only HIP
  * objects the library creates are side streams (default priority) and
- * events, with which the coarse sweeps of several grid-size classes run side
- * by side; they are forked from and joined back to the given stream, so the
- * caller sees stream order, also under stream capture.
+ * events, with which the one-workgroup-per-instance coarse sweeps of several
+ * grid-size classes run side by side; they are forked from and joined back
+ * to the given stream, so the caller sees stream order, also under stream
+ * capture.  Launches whose workgroups wait for each other (group launches)
+ * never run beside other launches of the same call.
  *
  * Data layout (all float64, row-major, interior points only, y slowest):
  *   one state           : n^d values, index iy*n + ix;
@@ -41,7 +43,10 @@ typedef enum ch_status {
   CH_ERR_HIP = 2,          /* a HIP runtime call or kernel launch failed       */
   CH_ERR_UNSUPPORTED = 3,  /* valid problem the kernels do not cover (n, dim) */
   CH_ERR_NOCONV = 4,       /* Newton or Krylov iteration cap, or non-finite   */
-  CH_ERR_STATE = 5         /* call order violated (e.g. workspace not bound)  */
+  CH_ERR_STATE = 5,        /* call order violated (e.g. workspace not bound)  */
+  CH_ERR_TIMEOUT = 6       /* a workgroup of a group launch waited past its
+                              limit for the others (device oversubscribed):
+                              the states that launch wrote are invalid       */
 } ch_status;
 
 /* fine propagator: linear stabilised step (scheme (2.5) for s = 2), or the
@@ -85,7 +90,10 @@ typedef struct ch_pr_state {
   double* F;          /* slice layout: F(U_n^k) of the latest fine sweep        */
   double* G_old;      /* slice layout: G(U_n^k) kept for the correction         */
   double* delta;      /* [n_inst]: update norm max_n ||U_n^{k+1}-U_n^k||_h      */
-  int32_t* status;    /* [n_inst]: 0 ok; 1 = solver cap hit; 2 = non-finite     */
+  int32_t* status;    /* [n_inst]: flags of every call since the prediction
+                         (cleared there): bit 1 = Newton/Krylov cap hit,
+                         bit 2 = non-finite update norm, bit 4 = a group wait
+                         timed out (states invalid); ch_check_status reads it */
   int32_t k;          /* host: corrections done so far                          */
   int32_t predicted;  /* host: 1 once the coarse prediction U^0 has been formed */
 } ch_pr_state;
@@ -166,7 +174,8 @@ ch_status ch_slice_distance(ch_ctx* ctx, const double* A, const double* B, doubl
  * cannot hold all workgroups of the launch at once (the launch needs one
  * group of eight workgroups per slice, up to 64 groups at two per CU).  The
  * groups wait for each other at device-memory counters, each wait bounded by
- * about 10 s; a failure sets status bit 4 and the states of that call are
+ * a limit (ch_set_wait_limit, 10 s by default); a failure sets status bit 4
+ * (ch_check_status: CH_ERR_TIMEOUT) and the states of that call are
  * invalid. */
 #define CH_RUN_SWEEP_ALL 1
 ch_status ch_parareal_run(ch_ctx* ctx, ch_pr_state* st, double tol, int32_t max_iters,
@@ -197,9 +206,10 @@ ch_status ch_fine_variant(ch_ctx* ctx, int32_t n, int32_t* waves, int32_t set);
  * The members of a group wait for each other at device-memory barriers, so
  * the group kernels need every workgroup resident at once: the launch checks
  * the device's capacity, but kernels of other streams that hold CUs at the
- * same time can delay members.  A member that waits longer than about 0.2 s
- * gives up.  The instance's status word then gets bit 4 (read with the next
- * Parareal correction), and the states of that launch are invalid. */
+ * same time can delay members.  A member that waits longer than the limit
+ * (ch_set_wait_limit, 0.2 s by default) gives up.  The instance's status
+ * word then gets bit 4 (ch_check_status reports CH_ERR_TIMEOUT), and the
+ * states of that launch are invalid. */
 ch_status ch_fine_groups(ch_ctx* ctx, int32_t n, int32_t fine_kind, int32_t* groups, int32_t set);
 
 /* Query (set = 0) or set (set = 1) how many workgroups run each instance's
@@ -227,6 +237,27 @@ ch_status ch_graph_destroy(void* graph_exec);
 ch_status ch_iteration_count(ch_ctx* ctx, ch_pr_state* st, ch_stream stream);
 /* Set the iteration counter (device and st->k), e.g. to repeat an iteration. */
 ch_status ch_set_iteration(ch_ctx* ctx, ch_pr_state* st, int32_t k, ch_stream stream);
+
+/* Synchronous check of the flags the device raised.  Reads, for every
+ * instance, the flags of the latest call that launched fine or coarse kernels
+ * (ch_fine_propagate, ch_coarse_propagate, ch_parareal_iterate,
+ * ch_parareal_run; ch_parareal_correct adds to those of the preceding call)
+ * and, when st is given, st->status (the whole run).  bits (host memory,
+ * n_inst values, may be NULL) receives their OR per instance.  Returns
+ * CH_ERR_TIMEOUT if any bit 4 is set, else CH_ERR_NOCONV if any bit 1 or 2
+ * is set (cap reached or non-finite), else CH_OK; ch_last_error names the
+ * first instance.  Compute calls never synchronise, so this is how a caller
+ * learns of device-side failures. */
+ch_status ch_check_status(ch_ctx* ctx, const ch_pr_state* st, int32_t* bits, ch_stream stream);
+
+/* Bounds of the inter-workgroup waits of this context's group kernels: a
+ * group barrier gives up after group_seconds (default 0.2) and a hand-off of
+ * the pipelined launch after pipe_seconds (default 10); both in [0, 60].  A
+ * wait that gives up sets status bit 4 and lets its kernel run to its end, so
+ * a limit of 0 forces the failure path (for tests of error reporting).
+ * Synchronous. */
+ch_status ch_set_wait_limit(ch_ctx* ctx, double group_seconds, double pipe_seconds,
+                            ch_stream stream);
 
 /* Discrete energy (Section 1, (1.2)) of `count` states of instance `inst`:
  * E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u).  E_out is

@@ -14,7 +14,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libch.so")
 
-CH_OK, CH_ERR_ARG, CH_ERR_HIP, CH_ERR_UNSUPPORTED, CH_ERR_NOCONV, CH_ERR_STATE = range(6)
+CH_OK, CH_ERR_ARG, CH_ERR_HIP, CH_ERR_UNSUPPORTED, CH_ERR_NOCONV, CH_ERR_STATE, CH_ERR_TIMEOUT = range(7)
 FINE = {"linear": 0, "nonlinear": 1}
 NL = {"eyre": 0, "be": 1}
 COARSE = {"approx2": 0, "stab": 1, "neural": 2}
@@ -28,7 +28,7 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind",
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
            "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups",
-           "ch_parareal_run", "ch_slice_distance")
+           "ch_parareal_run", "ch_slice_distance", "ch_check_status", "ch_set_wait_limit")
 
 
 class ChProblem(ctypes.Structure):
@@ -49,7 +49,11 @@ class ChPrState(ctypes.Structure):
 
 
 class CHError(RuntimeError):
-    pass
+    """A failed call; ``status`` holds the ch_status code."""
+
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
 
 
 _lib = None
@@ -102,11 +106,13 @@ def load() -> ctypes.CDLL:
     lib.ch_fine_groups.argtypes = [vp, i32, i32, ctypes.POINTER(i32), i32]
     lib.ch_graph_destroy.argtypes = [vp]
     lib.ch_iteration_count.argtypes = [vp, ctypes.POINTER(ChPrState), vp]
+    lib.ch_check_status.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.POINTER(i32), vp]
+    lib.ch_set_wait_limit.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
                  "ch_nn_bind", "ch_set_coarse_kind", "ch_parareal_graph_create", "ch_graph_launch",
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
                  "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run",
-                 "ch_slice_distance"):
+                 "ch_slice_distance", "ch_check_status", "ch_set_wait_limit"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -164,7 +170,7 @@ class Context:
     def _check(self, st):
         if st != CH_OK:
             msg = self.lib.ch_last_error(self.h).decode() if getattr(self, "h", None) else ""
-            raise CHError(f"{self.lib.ch_status_str(st).decode()}: {msg}")
+            raise CHError(f"{self.lib.ch_status_str(st).decode()}: {msg}", st)
 
     def layout(self, inst):
         a, b, c, d = (ctypes.c_int64() for _ in range(4))
@@ -233,6 +239,18 @@ class Context:
         c = self._state_struct(state)
         self._check(self.lib.ch_iteration_count(self.h, ctypes.byref(c), _stream(stream)))
         return c.k
+
+    def ch_check_status(self, state=None, stream=None):
+        """Per-instance device flags (list of ints); raises CHError with
+        CH_ERR_TIMEOUT or CH_ERR_NOCONV when any is set."""
+        bits = (ctypes.c_int32 * len(self.problems))()
+        c = ctypes.byref(self._state_struct(state)) if state is not None else None
+        self._check(self.lib.ch_check_status(self.h, c, bits, _stream(stream)))
+        return list(bits)
+
+    def ch_set_wait_limit(self, group_seconds=0.2, pipe_seconds=10.0, stream=None):
+        self._check(self.lib.ch_set_wait_limit(self.h, float(group_seconds), float(pipe_seconds),
+                                               _stream(stream)))
 
     def ch_set_iteration(self, state, k, stream=None):
         c = self._state_struct(state)

@@ -130,6 +130,7 @@ const char* ch_status_str(ch_status s) {
     case CH_ERR_UNSUPPORTED: return "CH_ERR_UNSUPPORTED";
     case CH_ERR_NOCONV: return "CH_ERR_NOCONV";
     case CH_ERR_STATE: return "CH_ERR_STATE";
+    case CH_ERR_TIMEOUT: return "CH_ERR_TIMEOUT";
   }
   return "CH_ERR_UNKNOWN";
 }
@@ -205,6 +206,8 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     d.h = 1.0 / (p.n + 1); d.newton_tol = p.newton_tol; d.krylov_rtol = p.krylov_rtol;
     d.nl_krylov_rtol = p.nl_krylov_rtol;
     d.work_vecs = (p.dim == 2 && p.n == 256 && p.fine_kind == CH_FINE_NONLINEAR) ? 9 : chk::WORK_VECS;
+    d.wait_ticks = chk::WAIT_TICKS_DEFAULT;
+    d.pipe_wait_ticks = chk::PIPE_WAIT_TICKS_DEFAULT;
     d.off_slices = so; d.off_iter = io; d.slice_base = slice_base;
     so += (int64_t)p.n_slices * P;
     io += (int64_t)(p.n_slices + 1) * P;
@@ -423,6 +426,14 @@ static ch_status require_bound(ch_ctx* c) {
   return CH_OK;
 }
 
+// The workspace status words collect the flags the kernels of one call
+// raise (bit 1 solver cap, 2 non-finite, 4 group wait timed out); every call
+// that launches fine or coarse kernels of its own clears them first.
+static int32_t* ws_status(ch_ctx* c) { return (int32_t*)(c->ws + c->status_blk.off); }
+static ch_status clear_ws_status(ch_ctx* c, hipStream_t s) {
+  return hip_check(c, chk::launch_zero_i32(ws_status(c), (int)c->probs.size(), s), "status clear");
+}
+
 static const double* class_sine(const ch_ctx* c, const ClassPlan& cp) {
   return (const double*)(c->ws + cp.sine_blk.off);
 }
@@ -479,6 +490,8 @@ ch_status ch_fine_propagate(ch_ctx* c, const double* U_in, double* F_out, const 
   const size_t bytes = sizeof(double) * c->slice_total;
   const char *a = (const char*)U_in, *b = (const char*)F_out;
   if (a < b + bytes && b < a + bytes) return fail(c, CH_ERR_ARG, "U_in and F_out overlap");
+  st = clear_ws_status(c, (hipStream_t)stream);
+  if (st != CH_OK) return st;
   return fine_all(c, U_in, F_out, mask, nullptr, nullptr, 0, (hipStream_t)stream);
 }
 
@@ -526,41 +539,50 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
   const InstDev* inst = (const InstDev*)(c->ws + c->inst_blk.off);
   const int32_t* active = mode == 0 ? nullptr : (const int32_t*)(c->ws + c->active_blk.off);
   const int32_t* kdev = mode == 2 ? (const int32_t*)(c->ws + c->k_blk.off) : nullptr;
-  // sequential sweeps (modes 1, 2) of several classes: one stream per class
-  const size_t n_side = (mode != 0 && c->classes.size() > 1) ? c->classes.size() - 1 : 0;
+  double* U = st ? st->U : nullptr;
+  const double* F = st ? st->F : nullptr;
+  double* Gold = st ? st->G_old : nullptr;
+  double* delta = st ? st->delta : nullptr;
+  int32_t* status = st ? st->status : nullptr;
+  // Phase 1: the sequential sweeps (modes 1, 2) that run on a group of
+  // workgroups per instance.  Their members meet at device-memory barriers,
+  // so each such launch needs every workgroup resident at once: they run on
+  // the caller's stream, one class after another, with nothing of this call
+  // beside them.
+  std::vector<size_t> rest;
+  for (size_t ci = 0; ci < c->classes.size(); ++ci) {
+    auto& cp = c->classes[ci];
+    bool coop = cp.dim == 2 && mode != 0 && cp.chain_groups > 1;
+    for (int32_t i : cp.insts) coop = coop && c->inst[i].coarse_kind != CH_COARSE_STAB;
+    if (!coop) { rest.push_back(ci); continue; }
+    const int32_t* insts = (const int32_t*)(c->ws + cp.insts_blk.off);
+    hipError_t e = chk::launch_chain_coop(cp.n, cp.chain_groups, mode, insts, (int)cp.insts.size(),
+                                          inst, class_sine(c, cp), U, F, Gold, delta, status,
+                                          active, k, kdev, (int32_t*)(c->ws + cp.sync_blk.off), s0);
+    // a device that cannot hold every workgroup at once takes one per instance
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+      cp.chain_groups = 1;
+      rest.push_back(ci);
+      continue;
+    }
+    ch_status r = hip_check(c, e, "coarse launch");
+    if (r != CH_OK) return r;
+  }
+  // Phase 2: one workgroup per instance (no inter-workgroup waits).  The
+  // sequential sweeps of several classes run side by side, one stream each.
+  const size_t n_side = (mode != 0 && rest.size() > 1) ? rest.size() - 1 : 0;
   if (n_side) {
     ch_status r = fork_sides(c, n_side, s0);
     if (r != CH_OK) return r;
   }
-  for (size_t ci = 0; ci < c->classes.size(); ++ci) {
-    auto& cp = c->classes[ci];
-    hipStream_t s = (n_side && ci > 0) ? c->side[ci - 1] : s0;
+  for (size_t ri = 0; ri < rest.size(); ++ri) {
+    auto& cp = c->classes[rest[ri]];
+    hipStream_t s = (n_side && ri > 0) ? c->side[ri - 1] : s0;
     const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
     const int32_t* insts = (const int32_t*)(c->ws + cp.insts_blk.off);
     const double* tab = class_sine(c, cp);
-    double* U = st ? st->U : nullptr;
-    const double* F = st ? st->F : nullptr;
-    double* Gold = st ? st->G_old : nullptr;
-    double* delta = st ? st->delta : nullptr;
-    int32_t* status = st ? st->status : nullptr;
-    hipError_t e = hipErrorNotSupported;
-    // the sequential sweeps (modes 1, 2) on a group of workgroups per
-    // instance, unless an instance uses the stabilised coarse step
-    bool coop = cp.dim == 2 && mode != 0 && cp.chain_groups > 1;
-    for (int32_t i : cp.insts) coop = coop && c->inst[i].coarse_kind != CH_COARSE_STAB;
-    if (coop) {
-      e = chk::launch_chain_coop(cp.n, cp.chain_groups, mode, insts, (int)cp.insts.size(), inst,
-                                 tab, U, F, Gold, delta, status, active, k, kdev,
-                                 (int32_t*)(c->ws + cp.sync_blk.off), s);
-      // a device that cannot hold every workgroup at once takes one per instance
-      if (e == hipErrorCooperativeLaunchTooLarge) {
-        cp.chain_groups = 1;
-        coop = false;
-      }
-    }
-    if (coop) {
-      // done: launched on the groups
-    } else if (cp.dim == 2) {
+    hipError_t e;
+    if (cp.dim == 2) {
       e = chk::launch_coarse_2d(cp.n, mode, insts, (int)cp.insts.size(), items, (int)cp.items.size(),
                                 inst, tab, U_in, G_out, mask, U, F, Gold, delta, status,
                                 active, k, kdev, s);
@@ -633,6 +655,8 @@ ch_status ch_coarse_propagate(ch_ctx* c, const double* U_in, double* G_out, cons
   const size_t bytes = sizeof(double) * c->slice_total;
   const char *a = (const char*)U_in, *b = (const char*)G_out;
   if (a < b + bytes && b < a + bytes) return fail(c, CH_ERR_ARG, "U_in and G_out overlap");
+  st = clear_ws_status(c, (hipStream_t)stream);
+  if (st != CH_OK) return st;
   return coarse_all(c, 0, U_in, G_out, mask, nullptr, 0, (hipStream_t)stream);
 }
 
@@ -656,11 +680,17 @@ static ch_status pr_step(ch_ctx* c, ch_pr_state* st, double tol, hipStream_t s, 
   const int n_inst = (int)c->probs.size();
   ch_status r;
   if (!st->predicted) {
+    // a new run: st->status starts from zero and collects the flags of every
+    // later call of the run
     r = hip_check(c, chk::launch_counter(kdev, 0, 0, s), "iteration counter");
+    if (r == CH_OK) r = hip_check(c, chk::launch_zero_i32(st->status, n_inst, s), "status clear");
+    if (r == CH_OK) r = clear_ws_status(c, s);
     if (r != CH_OK) return r;
     r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 1, kdev, s), "flags");
     if (r != CH_OK) return r;
     r = coarse_all(c, 1, nullptr, nullptr, nullptr, st, 0, s);
+    if (r == CH_OK)
+      r = hip_check(c, chk::launch_status_merge(st->status, ws_status(c), n_inst, s), "status");
     if (r != CH_OK) return r;
     st->predicted = 1;
     st->k = 0;
@@ -669,10 +699,15 @@ static ch_status pr_step(ch_ctx* c, ch_pr_state* st, double tol, hipStream_t s, 
   r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 0, kdev, s), "flags");
   if (r != CH_OK) return r;
   if (with_fine) {
-    r = fine_all(c, st->U, st->F, nullptr, active, kdev, 1, s);
+    // the correction alone (with_fine == 0) keeps the flags of the caller's
+    // preceding ch_fine_propagate
+    r = clear_ws_status(c, s);
+    if (r == CH_OK) r = fine_all(c, st->U, st->F, nullptr, active, kdev, 1, s);
     if (r != CH_OK) return r;
   }
   r = coarse_all(c, 2, nullptr, nullptr, nullptr, st, st->k, s);
+  if (r == CH_OK)
+    r = hip_check(c, chk::launch_status_merge(st->status, ws_status(c), n_inst, s), "status");
   if (r != CH_OK) return r;
   r = hip_check(c, chk::launch_counter(kdev, 1, 1, s), "iteration counter");
   if (r != CH_OK) return r;
@@ -710,6 +745,7 @@ ch_status ch_parareal_run(ch_ctx* c, ch_pr_state* st, double tol, int32_t max_it
   int32_t* active = (int32_t*)(c->ws + c->active_blk.off);
   int32_t* kdev = (int32_t*)(c->ws + c->k_blk.off);
   r = hip_check(c, chk::launch_flag_active(st->delta, active, 1, tol, 0, kdev, s), "flags");
+  if (r == CH_OK) r = clear_ws_status(c, s);
   if (r != CH_OK) return r;
   const size_t SN = (size_t)d.n_slices * d.n * d.n;
   double* F1 = (double*)(c->ws + c->pipe_blk.off);
@@ -721,7 +757,9 @@ ch_status ch_parareal_run(ch_ctx* c, ch_pr_state* st, double tol, int32_t max_it
       (flags & CH_RUN_SWEEP_ALL) ? 1 : 0, tol, (int32_t*)(c->ws + c->pipe_sync_blk.off), s);
   if (e == hipErrorCooperativeLaunchTooLarge)
     return fail(c, CH_ERR_UNSUPPORTED, "the device cannot hold the pipelined launch at once");
-  return hip_check(c, e, "pipelined iterations");
+  r = hip_check(c, e, "pipelined iterations");
+  if (r != CH_OK) return r;
+  return hip_check(c, chk::launch_status_merge(st->status, ws_status(c), 1, s), "status");
 }
 
 ch_status ch_parareal_correct(ch_ctx* c, ch_pr_state* st, double tol, ch_stream stream) {
@@ -910,6 +948,54 @@ ch_status ch_set_iteration(ch_ctx* c, ch_pr_state* st, int32_t k, ch_stream stre
                 "iteration counter");
   if (r == CH_OK) st->k = k;
   return r;
+}
+
+ch_status ch_check_status(ch_ctx* c, const ch_pr_state* st, int32_t* bits, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  const int n_inst = (int)c->probs.size();
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> a(n_inst, 0), b(n_inst, 0);
+  r = hip_check(c, hipMemcpyAsync(a.data(), ws_status(c), sizeof(int32_t) * n_inst,
+                                  hipMemcpyDeviceToHost, s), "status read");
+  if (r == CH_OK && st && st->status)
+    r = hip_check(c, hipMemcpyAsync(b.data(), st->status, sizeof(int32_t) * n_inst,
+                                    hipMemcpyDeviceToHost, s), "status read");
+  if (r == CH_OK) r = hip_check(c, hipStreamSynchronize(s), "status sync");
+  if (r != CH_OK) return r;
+  int32_t all = 0, first = -1;
+  for (int i = 0; i < n_inst; ++i) {
+    const int32_t v = a[i] | b[i];
+    if (bits) bits[i] = v;
+    if (v && first < 0) first = i;
+    all |= v;
+  }
+  if (all & 4)
+    return fail(c, CH_ERR_TIMEOUT,
+                "instance %d: a workgroup of a group launch waited past its limit (status 0x%x); "
+                "the states of that launch are invalid", first, all);
+  if (all & 3)
+    return fail(c, CH_ERR_NOCONV, "instance %d: %s (status 0x%x)", first,
+                (all & 2) ? "non-finite update norm" : "Newton or Krylov iteration cap reached", all);
+  return CH_OK;
+}
+
+ch_status ch_set_wait_limit(ch_ctx* c, double group_seconds, double pipe_seconds,
+                            ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (!(group_seconds >= 0 && group_seconds <= 60) || !(pipe_seconds >= 0 && pipe_seconds <= 60))
+    return fail(c, CH_ERR_ARG, "wait limits must lie in [0, 60] s");
+  for (auto& d : c->inst) {
+    d.wait_ticks = (uint64_t)(group_seconds * 1e8);
+    d.pipe_wait_ticks = (uint64_t)(pipe_seconds * 1e8);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  r = hip_check(c, hipMemcpyAsync(c->ws + c->inst_blk.off, c->inst.data(),
+                                  sizeof(InstDev) * c->inst.size(), hipMemcpyHostToDevice, s),
+                "limit upload");
+  if (r != CH_OK) return r;
+  return hip_check(c, hipStreamSynchronize(s), "limit sync");
 }
 
 int64_t ch_nn_param_count(void) { return chk::nn_param_count(); }

@@ -26,7 +26,13 @@ struct InstDev {
   double nl_krylov_rtol;     // CG target inside Newton
   int32_t work_vecs;         // solver vectors per slice in `work`
   int32_t pad2;
+  // bounds of the inter-workgroup waits, in ticks of the 100 MHz wall clock:
+  // a group barrier (default 0.2 s) and a hand-off of the pipelined launch
+  // (default 10 s); a wait that runs out flags status bit 4
+  uint64_t wait_ticks, pipe_wait_ticks;
 };
+constexpr uint64_t WAIT_TICKS_DEFAULT = 20000000ull;
+constexpr uint64_t PIPE_WAIT_TICKS_DEFAULT = 1000000000ull;
 constexpr int TAB_VECS = 4;   // d(coarse), 1/mu + tau(coarse), d(fine), 1/mu
 constexpr int WORK_VECS = 7;  // x, r, p, q, minv, u_hat, y_hat (streamed Newton: 9)
 
@@ -121,6 +127,10 @@ hipError_t launch_slice_dist(const WorkItem* items, int n_items, const InstDev* 
 hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
                               int first, const int32_t* kdev, hipStream_t s);
 hipError_t launch_counter(int32_t* kdev, int value, int add, hipStream_t s);
+// p[0..count) = 0 (a fill kernel, safe under stream capture)
+hipError_t launch_zero_i32(int32_t* p, int count, hipStream_t s);
+// dst[i] |= src[i], i < count
+hipError_t launch_status_merge(int32_t* dst, const int32_t* src, int count, hipStream_t s);
 
 // ---- learned coarse propagator (ch_nn.hip)
 struct NNLayer { int c_in, c_out, k, stride, act, cat; };

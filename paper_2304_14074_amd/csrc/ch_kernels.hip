@@ -938,7 +938,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
     const double dlt = sqrt(P.h * P.h * dmax);
     delta[ii] = dlt;
     if (!(dlt == dlt) || dlt > 1e300) status |= 2;
-    status_out[ii] = status | *P.status;
+    status_out[ii] |= status | *P.status;
   }
 }
 
@@ -1109,12 +1109,13 @@ struct CoopCtx {
   double* xg;       // two exchange matrices N x N (natural order)
   double* part;     // two slots of 4 x 16 partial sums (value i of member m at i * 16 + m)
   int mem, ok, xsel, psel, nb;
+  uint64_t limit;   // wall-clock ticks a barrier waits before it gives up
 };
 
 // Barrier of the G members of one group: barrier b is passed once the
 // counter reaches G (b + 1).  Each wave first waits until its own stores are
 // acknowledged (s_waitcnt vmcnt(0)).  Then one thread arrives, polls and
-// leaves; the spin is bounded by the wall clock (about 0.2 s): on time-out
+// leaves; the spin is bounded by the wall clock (cc.limit, 0.2 s by default): on time-out
 // the member clears cc.ok and every later barrier of the launch returns at
 // once, so a lost member can never hang the kernel; the host sees the failure
 // in the status word.
@@ -1142,7 +1143,7 @@ __device__ __forceinline__ void group_barrier(CoopCtx& cc) {
       if (arrived != target - 1) {
         const uint64_t t0 = wall_clock64();
         while (__hip_atomic_load(cc.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-          if (wall_clock64() - t0 > 20000000ull) { ok = 0; break; }
+          if (wall_clock64() - t0 > cc.limit) { ok = 0; break; }
           __builtin_amdgcn_s_sleep(1);
         }
       }
@@ -1570,6 +1571,7 @@ k_fine_group(const WorkItem* __restrict__ items, int n_items, const InstDev* __r
   cc.xsel = 0;
   cc.psel = 0;
   cc.nb = 0;
+  cc.limit = inst[0].wait_ticks;   // the same for every instance of a context
   for (int item = idx; item < n_items; item += n_groups) {
     const WorkItem it = items[item];
     const InstDev P = inst[it.inst];
@@ -1628,6 +1630,7 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
   cc.xsel = 0;
   cc.psel = 0;
   cc.nb = 0;
+  cc.limit = inst[0].wait_ticks;   // the same for every instance of a context
   auto gidx = [&](int s) {
     int row, col;
     slab_rc<N, G, NW, OPQ>(s, row, col);
@@ -1771,6 +1774,7 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
   cc.xsel = 0;
   cc.psel = 0;
   cc.nb = 0;
+  cc.limit = P.wait_ticks;
   for (int m = threadIdx.x; m < C::P2; m += C::NT) T[m] = Tg[m];
   for (int m = threadIdx.x; m < N; m += C::NT) lamS[m] = lam[m];
   // d of (2.4) on the member's column block (owned slots)
@@ -1850,7 +1854,7 @@ k_chain_coop(int mode, const int32_t* __restrict__ insts, int n_insts,
     const double dlt = sqrt(P.h * P.h * dmax);
     delta[ii] = dlt;
     if (!(dlt == dlt) || dlt > 1e300) status |= 2;
-    status_out[ii] = status | *P.status | (cc.ok ? 0 : 4);
+    status_out[ii] |= status | *P.status | (cc.ok ? 0 : 4);
   }
 }
 
@@ -1907,8 +1911,6 @@ struct PipeArgs {
   double tol;
 };
 
-constexpr uint64_t kPipeWaitTicks = 1000000000ull;   // 10 s of the 100 MHz clock
-
 __device__ __forceinline__ int32_t pipe_ld(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1927,7 +1929,7 @@ __device__ __forceinline__ void pipe_post(int32_t* cnt) {
 // finds the count short, so it will never come; -1 on a failure flagged by
 // another group, on a time-out, or when this member has already failed.
 __device__ int pipe_wait(const int32_t* cnt, int target, const int32_t* ctl, bool until_end,
-                         int ok) {
+                         int ok, uint64_t limit) {
   __shared__ int res_s;
   if (threadIdx.x == 0) {
     int res = -1;
@@ -1937,7 +1939,7 @@ __device__ int pipe_wait(const int32_t* cnt, int target, const int32_t* ctl, boo
         if (pipe_ld(cnt) >= target) { res = 1; break; }
         if (pipe_ld(ctl + 1)) { res = -1; break; }
         if (until_end && pipe_ld(ctl)) { res = pipe_ld(cnt) >= target ? 1 : 0; break; }
-        if (wall_clock64() - t0 > kPipeWaitTicks) { res = -1; break; }
+        if (wall_clock64() - t0 > limit) { res = -1; break; }
         __builtin_amdgcn_s_sleep(2);
       }
     }
@@ -1987,7 +1989,7 @@ __device__ void pipe_coarse(const PipeArgs& A, const InstDev& P, int k0, double*
     const double* Fj = (j & 1) ? A.F1 : A.F0 + P.off_slices;
     double* Un = A.Uin + (int64_t)((j + 1) & 1) * Ns * NN;   // inputs of iteration j + 1
     const int target = G * (j + 1);                          // members posting item (j, n)
-    if (pipe_wait(A.fcnt + kj, target, A.ctl, false, cc.ok) <= 0) { fail = true; break; }
+    if (pipe_wait(A.fcnt + kj, target, A.ctl, false, cc.ok, P.pipe_wait_ticks) <= 0) { fail = true; break; }
     double dmax;
     {
       // U_{k+1} = F_k (slices up to k are final)
@@ -2008,7 +2010,7 @@ __device__ void pipe_coarse(const PipeArgs& A, const InstDev& P, int k0, double*
     }
     for (int n = kj + 1; n < Ns; ++n) {
       coop_approx2<N, G, NW, OPQ>(Xs, u, T, red, cc, P, Dl, Ml, Ql, lamS, status);
-      if (pipe_wait(A.fcnt + n, target, A.ctl, false, cc.ok) <= 0) { fail = true; break; }
+      if (pipe_wait(A.fcnt + n, target, A.ctl, false, cc.ok, P.pipe_wait_ticks) <= 0) { fail = true; break; }
       double acc[1] = {0.0};
 #pragma unroll
       for (int s = 0; s < C::OWN; ++s) {
@@ -2037,7 +2039,7 @@ __device__ void pipe_coarse(const PipeArgs& A, const InstDev& P, int k0, double*
   group_barrier<G>(cc);
   if (t == 0 && mem == 0) {
     const bool bad = fail || !cc.ok || pipe_ld(A.ctl + 1);
-    A.status_out[A.ii] = status | *P.status | (bad ? 4 : 0);
+    A.status_out[A.ii] |= status | *P.status | (bad ? 4 : 0);
     if (bad) __hip_atomic_store(A.ctl + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(A.ctl, jdone + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else if (fail || !cc.ok) {
@@ -2059,7 +2061,7 @@ __device__ void pipe_fine(const PipeArgs& A, const InstDev& P, int k0, int q, do
     // the input comes from the copy made before the launch (iteration 0, and
     // slice k0, which no sweep rewrites) or from the sweep of iteration j - 1
     if (j > 0 && n > k0) {
-      const int w = pipe_wait(A.ucnt + n, G * j, A.ctl, true, cc.ok);
+      const int w = pipe_wait(A.ucnt + n, G * j, A.ctl, true, cc.ok, P.pipe_wait_ticks);
       if (w < 0) pipe_fail(A.ctl);
       if (w <= 0) break;
     }
@@ -2112,6 +2114,7 @@ k_parareal_pipe(PipeArgs A) {
   cc.xsel = 0;
   cc.psel = 0;
   cc.nb = 0;
+  cc.limit = P.wait_ticks;
   const int k0 = *A.kdev;
   // the coarse sweep with recomputed lane addresses (it would need 370
   // registers otherwise), the fine solves with hoisted ones (faster, and they
@@ -2577,7 +2580,7 @@ k_coarse_stream(int mode, const int32_t* __restrict__ insts, const WorkItem* __r
     const double dlt = sqrt(P.h * P.h * dmax);
     delta[ii] = dlt;
     if (!(dlt == dlt) || dlt > 1e300) status |= 2;
-    status_out[ii] = status | *P.status;
+    status_out[ii] |= status | *P.status;
   }
 }
 
@@ -3109,7 +3112,7 @@ __global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
     const double dlt = sqrt(P.h * dmax);
     delta[ii] = dlt;
     if (!(dlt == dlt) || dlt > 1e300) status |= 2;
-    status_out[ii] = status;
+    status_out[ii] |= status;
   }
 }
 
@@ -3392,6 +3395,21 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
 __global__ void k_zero_i32(int32_t* p, int count) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < count) p[i] = 0;
+}
+hipError_t launch_zero_i32(int32_t* p, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+__global__ void k_status_merge(int32_t* __restrict__ dst, const int32_t* __restrict__ src,
+                               int count) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < count) dst[i] |= src[i];
+}
+hipError_t launch_status_merge(int32_t* dst, const int32_t* src, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_status_merge, dim3((count + 255) / 256), dim3(256), 0, s, dst, src, count);
+  return hipGetLastError();
 }
 
 template <int N, int G, int NW, bool OPQ>

@@ -166,6 +166,9 @@ def run_parareal(ctx: "chlib.Context", u0: np.ndarray, tol: float, fallback: boo
             ctx.ch_coarse_propagate(U_in, st["G_old"])
             fell_back = st["c"].k
     torch.cuda.synchronize()
+    ctx.ch_check_status(st)          # raises on a solver cap, non-finite state or time-out
+    if judging:
+        plain.ch_check_status()
     return {"iterations": len(deltas), "deltas": deltas, "judge": judge,
             "seconds": time.perf_counter() - t0, "fallback_at": fell_back, "U": st["U"],
             "status": int(st["status"][0].item())}

@@ -78,6 +78,19 @@ def test_status_strings():
     lib = chlib.load()
     assert lib.ch_status_str(0) == b"CH_OK"
     assert lib.ch_status_str(4) == b"CH_ERR_NOCONV"
+    assert lib.ch_status_str(6) == b"CH_ERR_TIMEOUT"
+
+
+def test_status_calls_need_a_workspace():
+    import workloads
+    from paper_2304_14074_amd import chlib
+    lib, st, h = _create([workloads.Problem(dim=2, n=128, n_slices=2, j_fine=5)])
+    assert st == chlib.CH_OK
+    bits = (ctypes.c_int32 * 1)()
+    assert lib.ch_check_status(h, None, bits, None) == chlib.CH_ERR_STATE
+    assert lib.ch_set_wait_limit(h, 0.2, 10.0, None) == chlib.CH_ERR_STATE
+    lib.ch_destroy(h)
+
 
 
 def test_chain_variant_selection_host_only():
