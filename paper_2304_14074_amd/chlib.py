@@ -28,7 +28,8 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16", "ch_nn_bind", "ch_set_coarse_kind",
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
            "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups",
-           "ch_parareal_run", "ch_slice_distance", "ch_check_status", "ch_set_wait_limit")
+           "ch_parareal_run", "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
+           "ch_nn_forward_static")
 
 
 class ChProblem(ctypes.Structure):
@@ -91,6 +92,7 @@ def load() -> ctypes.CDLL:
     lib.ch_nn_workspace_bytes.argtypes = [i32, i32]
     lib.ch_nn_workspace_bytes.restype = ctypes.c_size_t
     lib.ch_nn_forward.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    lib.ch_nn_forward_static.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.ch_nn_train_step.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
     lib.ch_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
     lib.ch_nn_to_bf16.argtypes = [vp, vp, i64, vp]
@@ -108,7 +110,7 @@ def load() -> ctypes.CDLL:
     lib.ch_iteration_count.argtypes = [vp, ctypes.POINTER(ChPrState), vp]
     lib.ch_check_status.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.POINTER(i32), vp]
     lib.ch_set_wait_limit.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
-    for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
+    for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_forward_static", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
                  "ch_nn_bind", "ch_set_coarse_kind", "ch_parareal_graph_create", "ch_graph_launch",
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
                  "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run",
@@ -357,6 +359,15 @@ def ch_nn_forward(w_bf16, u, out, ws: NNWorkspace, stream=None):
     b, n = u.shape[0], u.shape[-1]
     _nn_check(load().ch_nn_forward(_ptr(w_bf16), _ptr(u), b, n, _ptr(ws.buf), _ptr(out),
                                    _stream(stream)), "ch_nn_forward")
+
+
+def ch_nn_forward_static(w_bf16, u, out, stream=None):
+    """The forward pass without a workspace (the library's static device
+    scratch); raises CHError (CH_ERR_ARG) when the batch exceeds it."""
+    b, n = u.shape[0], u.shape[-1]
+    st = load().ch_nn_forward_static(_ptr(w_bf16), _ptr(u), b, n, _ptr(out), _stream(stream))
+    if st != CH_OK:
+        raise CHError(f"ch_nn_forward_static: {load().ch_status_str(st).decode()}", st)
 
 
 def ch_nn_train_step(w_bf16, u, target, grad, loss, ws: NNWorkspace, stream=None):

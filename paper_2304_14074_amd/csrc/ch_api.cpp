@@ -1026,6 +1026,22 @@ ch_status ch_nn_forward(const uint16_t* w, const double* u, int32_t batch, int32
              ? CH_OK : CH_ERR_HIP;
 }
 
+ch_status ch_nn_forward_static(const uint16_t* w, const double* u, int32_t batch, int32_t n,
+                               double* out, ch_stream stream) {
+  if (!w || !u || !out || batch < 1 || n < 8 || n % 8) return CH_ERR_ARG;
+  const size_t need = chk::nn_forward_floats(batch, n);
+  if (need > chk::NN_STATIC_FLOATS) {
+    fprintf(stderr, "ch_nn_forward_static: batch %d at n = %d needs %zu floats of activations, "
+            "more than the %zu of the static scratch\n", batch, n, need, chk::NN_STATIC_FLOATS);
+    return CH_ERR_ARG;
+  }
+  float* ws = nullptr;
+  if (chk::nn_static_scratch(&ws) != hipSuccess) return CH_ERR_HIP;
+  const chk::NNPlan pl = chk::nn_plan(batch, n);
+  return chk::nn_forward(w, u, batch, n, ws, pl, out, (hipStream_t)stream) == hipSuccess
+             ? CH_OK : CH_ERR_HIP;
+}
+
 ch_status ch_nn_train_step(const uint16_t* w, const double* u, const double* target, int32_t batch,
                            int32_t n, void* ws, float* grad, float* loss, ch_stream stream) {
   if (!w || !u || !target || !ws || !grad || !loss || batch < 1 || n < 8 || n % 8) return CH_ERR_ARG;

@@ -144,6 +144,13 @@ int64_t nn_param_count();
 int64_t nn_param_offset(int layer);
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
                       const NNPlan& p, double* out, hipStream_t s);
+// floats of workspace the forward pass alone uses (x0 and the activations)
+size_t nn_forward_floats(int batch, int n);
+// the allocation-free forward pass: the file-scope device array of
+// NN_STATIC_FLOATS floats; nn_static_scratch returns its address on the
+// current device (looked up once per device)
+constexpr size_t NN_STATIC_FLOATS = (size_t)8 << 20;
+hipError_t nn_static_scratch(float** out);
 hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, int batch, int n,
                          float* ws, const NNPlan& p, float* grad, float* loss, hipStream_t s);
 hipError_t nn_adam(float* wm, uint16_t* wb, float* m, float* v, const float* g, int64_t count,

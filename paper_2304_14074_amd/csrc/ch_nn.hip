@@ -9,7 +9,16 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include "ch_internal.h"
+
+// Activations of the allocation-free forward pass (ch_nn_forward_static):
+// NN_STATIC_FLOATS floats (32 MiB) in a file-scope device array.  Every GPU
+// the library runs on holds its own copy, at its own address, until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): it passes the device address
+// that hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) float scratch[chk::NN_STATIC_FLOATS];
 
 namespace chk {
 
@@ -431,6 +440,30 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     hipLaunchKernelGGL(k_residual_out, dim3(blocks(cnt)), dim3(256), 0, s, u,
                        ws + p.act[NN_LAYERS - 1], out, cnt);
   return hipGetLastError();
+}
+
+size_t nn_forward_floats(int batch, int n) {
+  // the forward pass touches x0 and the activations, which come first in
+  // the plan; the gradient buffers start right after them
+  return nn_plan(batch, n).grad[0];
+}
+
+hipError_t nn_static_scratch(float** out) {
+  static std::mutex mu;
+  static float* ptr[64] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = (float*)p;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, int batch, int n,

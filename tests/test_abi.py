@@ -92,6 +92,17 @@ def test_status_calls_need_a_workspace():
     lib.ch_destroy(h)
 
 
+def test_static_forward_refuses_bad_shapes_on_the_host():
+    # shapes are checked before any device work: n not divisible by 8, an
+    # empty batch, and a batch past the 32 MiB static scratch
+    from paper_2304_14074_amd import chlib
+    lib = chlib.load()
+    p = ctypes.c_void_p(1 << 20)
+    assert lib.ch_nn_forward_static(p, p, 1, 100, p, None) == chlib.CH_ERR_ARG
+    assert lib.ch_nn_forward_static(p, p, 0, 128, p, None) == chlib.CH_ERR_ARG
+    assert lib.ch_nn_forward_static(p, p, 6, 128, p, None) == chlib.CH_ERR_ARG
+    assert lib.ch_nn_forward_static(p, p, 2, 256, p, None) == chlib.CH_ERR_ARG
+
 
 def test_chain_variant_selection_host_only():
     import workloads
