@@ -49,13 +49,17 @@ typedef enum ch_status {
                               the states that launch wrote are invalid       */
 } ch_status;
 
-/* fine propagator: linear stabilised step (scheme (2.5) for s = 2), or the
- * implicit step solved by Newton's method (scheme (2.3), or backward Euler) */
-enum { CH_FINE_LINEAR = 0, CH_FINE_NONLINEAR = 1 };
+/* fine propagator (Section 2.1): the linear stabilised step (scheme (2.5)
+ * for s = 2; PA-II, PA-III), the implicit step solved by Newton's method
+ * (scheme (2.3), or backward Euler; NPA-I, NPA-II), or scheme (2.4) with
+ * tau = dt (PA-I: a variable-coefficient linear solve every fine step) */
+enum { CH_FINE_LINEAR = 0, CH_FINE_NONLINEAR = 1, CH_FINE_APPROX2 = 2 };
 enum { CH_NL_EYRE = 0, CH_NL_FULL_BE = 1 };
-/* coarse propagator: scheme (2.4) (default), the stabilised step, or the
- * learned surrogate (weights bound with ch_nn_bind) */
-enum { CH_COARSE_APPROX2 = 0, CH_COARSE_STAB = 1, CH_COARSE_NEURAL = 2 };
+/* coarse propagator: scheme (2.4) (default; PA-I, PA-III, NPA-I), the
+ * stabilised step (PA-II), the learned surrogate (weights bound with
+ * ch_nn_bind), or scheme (2.3) solved by Newton's method (NPA-II; 2D, the
+ * Newton parameters of the problem, one workgroup per instance) */
+enum { CH_COARSE_APPROX2 = 0, CH_COARSE_STAB = 1, CH_COARSE_NEURAL = 2, CH_COARSE_EYRE = 3 };
 /* arithmetic of the sine transforms of the linear fine step */
 enum { CH_PREC_FP64 = 0, CH_PREC_SPLIT_BF16 = 1 };
 
@@ -74,7 +78,9 @@ typedef struct ch_problem {
   int32_t precision;    /* CH_PREC_*                                           */
   double newton_tol;    /* Newton stop: ||Y_{m+1}-Y_m||_h <= tol (1e-10)       */
   int32_t newton_max;   /* Newton iteration cap (20)                           */
-  double krylov_rtol;   /* relative residual target of the coarse CG solves   */
+  double krylov_rtol;   /* relative residual target of the CG solves of (2.4)
+                           (coarse step, and the PA-I fine step); 1e-13 keeps
+                           their error below 1e-12 relative                   */
   int32_t krylov_max;   /* CG iteration cap                                    */
   int32_t f_zero;       /* test hook: f(u) == 0                                */
   double nl_krylov_rtol;/* relative residual target of the CG inside Newton    */

@@ -1,9 +1,10 @@
 """Fine and coarse propagators (Section 2: F advances one slice of length
 dT = T/N with J steps of dt = dT/J; G advances it with coarse steps).
 
-Pairings of Section 2.1: PA-III is F = (2.5), G = (2.4); NPA-I is F = (2.3),
-G = (2.4); PA-II is F = G = (2.5).  ``m_coarse`` coarse sub-steps of dT/m are
-allowed (the paper uses one).
+Pairings of Section 2.1: PA-I is F = G = (2.4); PA-II is F = G = (2.5);
+PA-III is F = (2.5), G = (2.4); NPA-I is F = (2.3), G = (2.4); NPA-II is
+F = G = (2.3).  ``m_coarse`` coarse sub-steps of dT/m are allowed (the paper
+uses one).
 """
 from __future__ import annotations
 
@@ -12,17 +13,27 @@ import numpy as np
 from . import schemes
 
 
-def fine(prob, u: np.ndarray, steps: int | None = None) -> np.ndarray:
-    """F(T_{n+1}, T_n, u): J steps of the fine scheme with tau = dT/J."""
+def fine(prob, u: np.ndarray, steps: int | None = None, route: str = "lu") -> np.ndarray:
+    """F(T_{n+1}, T_n, u): J steps of the fine scheme with tau = dT/J.
+    route "lu": the sparse-LU solves; "sine": the same steps solved in the
+    sine basis (faster, equal up to rounding)."""
     J = prob.j_fine if steps is None else steps
     tau = prob.dt
     v = np.array(u, dtype=np.float64, copy=True)
+    fast = route == "sine"
+    if route not in ("lu", "sine"):
+        raise ValueError(route)
     for _ in range(J):
         if prob.fine_kind == "linear":
-            v = schemes.step_stab(v, tau, prob.eps, prob.s_fine, prob.f_zero)
+            step = schemes.step_stab_dst if fast else schemes.step_stab
+            v = step(v, tau, prob.eps, prob.s_fine, prob.f_zero)
         elif prob.fine_kind == "nonlinear":
-            v = schemes.step_newton(v, tau, prob.eps, prob.nl_variant,
-                                    prob.newton_tol, prob.newton_max, prob.f_zero)
+            step = schemes.step_newton_pcg if fast else schemes.step_newton
+            v = step(v, tau, prob.eps, prob.nl_variant, prob.newton_tol, prob.newton_max,
+                     f_zero=prob.f_zero)
+        elif prob.fine_kind == "approx2":
+            # PA-I: scheme (2.4) as the fine step
+            v = schemes.step_approx2(v, tau, prob.eps, prob.f_zero)
         else:
             raise ValueError(prob.fine_kind)
     return v
@@ -30,7 +41,8 @@ def fine(prob, u: np.ndarray, steps: int | None = None) -> np.ndarray:
 
 def coarse(prob, u: np.ndarray, kind: str | None = None, nn_params=None) -> np.ndarray:
     """G(T_{n+1}, T_n, u): m_coarse steps of tau = dT/m_coarse of scheme (2.4)
-    ("approx2"), of the stabilised step ("stab"), or the learned surrogate."""
+    ("approx2"), of the stabilised step ("stab"), of scheme (2.3) by Newton
+    ("eyre", NPA-II), or the learned surrogate."""
     kind = prob.coarse_kind if kind is None else kind
     v = np.array(u, dtype=np.float64, copy=True)
     if kind == "neural":
@@ -43,6 +55,9 @@ def coarse(prob, u: np.ndarray, kind: str | None = None, nn_params=None) -> np.n
             v = schemes.step_approx2(v, tau, prob.eps, prob.f_zero)
         elif kind == "stab":
             v = schemes.step_stab(v, tau, prob.eps, prob.s_fine, prob.f_zero)
+        elif kind == "eyre":
+            v = schemes.step_newton(v, tau, prob.eps, "eyre", prob.newton_tol, prob.newton_max,
+                                    prob.f_zero)
         else:
             raise ValueError(kind)
     return v

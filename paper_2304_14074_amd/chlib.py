@@ -15,9 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libch.so")
 
 CH_OK, CH_ERR_ARG, CH_ERR_HIP, CH_ERR_UNSUPPORTED, CH_ERR_NOCONV, CH_ERR_STATE, CH_ERR_TIMEOUT = range(7)
-FINE = {"linear": 0, "nonlinear": 1}
+FINE = {"linear": 0, "nonlinear": 1, "approx2": 2}
 NL = {"eyre": 0, "be": 1}
-COARSE = {"approx2": 0, "stab": 1, "neural": 2}
+COARSE = {"approx2": 0, "stab": 1, "neural": 2, "eyre": 3}
 PREC = {"fp64": 0, "split_bf16": 1}
 
 # every symbol include/ch.h declares

@@ -154,15 +154,13 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       bad = fail(c, CH_ERR_ARG, "instance %d: n_slices, j_fine, m_coarse must be >= 1", i);
     else if (p.krylov_max < 1 || !(p.krylov_rtol > 0))
       bad = fail(c, CH_ERR_ARG, "instance %d: krylov_max >= 1 and krylov_rtol > 0 needed", i);
-    else if (p.fine_kind != CH_FINE_LINEAR && p.fine_kind != CH_FINE_NONLINEAR)
+    else if (p.fine_kind < CH_FINE_LINEAR || p.fine_kind > CH_FINE_APPROX2)
       bad = fail(c, CH_ERR_ARG, "instance %d: fine_kind %d", i, p.fine_kind);
-    else if (p.coarse_kind < CH_COARSE_APPROX2 || p.coarse_kind > CH_COARSE_NEURAL)
+    else if (p.coarse_kind < CH_COARSE_APPROX2 || p.coarse_kind > CH_COARSE_EYRE)
       bad = fail(c, CH_ERR_ARG, "instance %d: coarse_kind %d", i, p.coarse_kind);
     else if (p.precision != CH_PREC_FP64 && p.precision != CH_PREC_SPLIT_BF16)
       bad = fail(c, CH_ERR_ARG, "instance %d: precision %d", i, p.precision);
-    else if (p.fine_kind == CH_FINE_NONLINEAR && p.dim != 2)
-      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: nonlinear fine step is built for 2D", i);
-    else if (p.fine_kind == CH_FINE_NONLINEAR &&
+    else if ((p.fine_kind == CH_FINE_NONLINEAR || p.coarse_kind == CH_COARSE_EYRE) &&
              (p.nl_variant < CH_NL_EYRE || p.nl_variant > CH_NL_FULL_BE || p.newton_max < 1 ||
               !(p.newton_tol > 0) || !(p.nl_krylov_rtol > 0)))
       bad = fail(c, CH_ERR_ARG, "instance %d: Newton parameters", i);
@@ -175,8 +173,8 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
                  "instance %d: split-bf16 covers the 2D linear step with n = 64, 128", i);
     else if (p.dim == 2 && !supported_2d(p.n))
       bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 2D n = %d (kernels cover 32, 64, 128, 256)", i, p.n);
-    else if (p.dim == 1 && (p.n > 128 || p.n % 2))
-      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 1D n = %d (even n <= 128)", i, p.n);
+    else if (p.dim == 1 && p.n > 128)
+      bad = fail(c, CH_ERR_UNSUPPORTED, "instance %d: 1D n = %d (n <= 128)", i, p.n);
     if (bad != CH_OK) {
       ch_status s = bad;
       // keep the message for the caller: the context is not returned, so
@@ -205,7 +203,10 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     d.eps = p.eps; d.dT = p.T / p.n_slices; d.dt = d.dT / p.j_fine; d.s_fine = p.s_fine;
     d.h = 1.0 / (p.n + 1); d.newton_tol = p.newton_tol; d.krylov_rtol = p.krylov_rtol;
     d.nl_krylov_rtol = p.nl_krylov_rtol;
-    d.work_vecs = (p.dim == 2 && p.n == 256 && p.fine_kind == CH_FINE_NONLINEAR) ? 9 : chk::WORK_VECS;
+    // streamed Newton solves (n = 256) carry two more vectors
+    d.work_vecs = (p.dim == 2 && p.n == 256 &&
+                   (p.fine_kind == CH_FINE_NONLINEAR || p.coarse_kind == CH_COARSE_EYRE))
+                      ? 9 : chk::WORK_VECS;
     d.wait_ticks = chk::WAIT_TICKS_DEFAULT;
     d.pipe_wait_ticks = chk::PIPE_WAIT_TICKS_DEFAULT;
     d.off_slices = so; d.off_iter = io; d.slice_base = slice_base;
@@ -456,6 +457,9 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
       if (cp.fine_groups == 1)
         e = chk::launch_fine_newton_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                                        mask, active, k_min, in_iter, s);
+    } else if (cp.dim == 2 && cp.fine_kind == CH_FINE_APPROX2) {
+      e = chk::launch_fine_approx2_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
+                                      mask, active, k_min, in_iter, s);
     } else if (cp.dim == 2 && cp.precision == CH_PREC_SPLIT_BF16) {
       e = chk::launch_fine_split_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                                     mask, active, k_min, in_iter, s);
@@ -553,7 +557,9 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
   for (size_t ci = 0; ci < c->classes.size(); ++ci) {
     auto& cp = c->classes[ci];
     bool coop = cp.dim == 2 && mode != 0 && cp.chain_groups > 1;
-    for (int32_t i : cp.insts) coop = coop && c->inst[i].coarse_kind != CH_COARSE_STAB;
+    for (int32_t i : cp.insts)
+      coop = coop && c->inst[i].coarse_kind != CH_COARSE_STAB &&
+             c->inst[i].coarse_kind != CH_COARSE_EYRE;
     if (!coop) { rest.push_back(ci); continue; }
     const int32_t* insts = (const int32_t*)(c->ws + cp.insts_blk.off);
     hipError_t e = chk::launch_chain_coop(cp.n, cp.chain_groups, mode, insts, (int)cp.insts.size(),
@@ -840,7 +846,7 @@ ch_status ch_fine_variant(ch_ctx* c, int32_t n, int32_t* waves, int32_t set) {
 
 ch_status ch_fine_groups(ch_ctx* c, int32_t n, int32_t fine_kind, int32_t* groups, int32_t set) {
   if (!c || !groups) return CH_ERR_ARG;
-  if (fine_kind != CH_FINE_LINEAR && fine_kind != CH_FINE_NONLINEAR)
+  if (fine_kind < CH_FINE_LINEAR || fine_kind > CH_FINE_APPROX2)
     return fail(c, CH_ERR_ARG, "fine kind %d", fine_kind);
   bool found = false;
   for (auto& cp : c->classes) {
@@ -849,10 +855,11 @@ ch_status ch_fine_groups(ch_ctx* c, int32_t n, int32_t fine_kind, int32_t* group
     found = true;
     if (set) {
       const bool lin = cp.fine_kind == CH_FINE_LINEAR;
+      const bool nl = cp.fine_kind == CH_FINE_NONLINEAR;
       const bool ok = *groups == 1 ||
                       (lin && n == 128 && (*groups == 4 || *groups == 8)) ||
                       (lin && n == 256 && *groups == 8) ||
-                      (!lin && n == 128 && *groups == 8) || (!lin && n == 256 && *groups == 16);
+                      (nl && n == 128 && *groups == 8) || (nl && n == 256 && *groups == 16);
       if (*groups != 1 && *groups != 4 && *groups != 8 && *groups != 16)
         return fail(c, CH_ERR_ARG, "fine groups must be 1, 4, 8 or 16, got %d", *groups);
       if (!ok)
@@ -1075,7 +1082,10 @@ ch_status ch_set_coarse_kind(ch_ctx* c, int32_t inst, int32_t kind, ch_stream st
   ch_status r = require_bound(c);
   if (r != CH_OK) return r;
   if (inst < 0 || inst >= (int32_t)c->probs.size()) return fail(c, CH_ERR_ARG, "instance index");
-  if (kind < CH_COARSE_APPROX2 || kind > CH_COARSE_NEURAL) return fail(c, CH_ERR_ARG, "kind");
+  if (kind < CH_COARSE_APPROX2 || kind > CH_COARSE_EYRE) return fail(c, CH_ERR_ARG, "kind");
+  if ((kind == CH_COARSE_EYRE) != (c->probs[inst].coarse_kind == CH_COARSE_EYRE))
+    return fail(c, CH_ERR_UNSUPPORTED,
+                "the (2.3) coarse step is chosen at creation (its Newton workspace)");
   if (c->probs[inst].dim != 2 && kind == CH_COARSE_NEURAL)
     return fail(c, CH_ERR_UNSUPPORTED, "learned coarse propagator needs 2D");
   if (kind == CH_COARSE_NEURAL && !c->nn_planned)

@@ -53,6 +53,12 @@ hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, cons
                                  const double* Tsin, const double* U_in, double* F_out,
                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                                  int in_iter, hipStream_t s);
+// PA-I fine sweep: J steps of scheme (2.4) with tau = dt per item (2D, one
+// workgroup per item; n = 256 streamed).
+hipError_t launch_fine_approx2_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                                  const double* Tsin, const double* U_in, double* F_out,
+                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                                  int in_iter, hipStream_t s);
 hipError_t launch_fine_split_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                 const double* Tsin, const double* U_in, double* F_out,
                                 const uint8_t* mask, const int32_t* active, const int32_t* kmin,

@@ -665,27 +665,32 @@ __device__ __forceinline__ double set_q(const OVec& cq, double* red,
 
 // Scheme (2.4): (I - tau Lap diag(u^2) + eps^2 tau Lap^2) v = (I - tau Lap) u,
 // i.e. K v = A^{-1} u + tau u with q = u^2 (f == 0: q = 0 and K v = A^{-1} u).
-// The state u is in X (state orientation) on entry; v is left there.
+// The state u is in X (state orientation) on entry; v is left there after
+// `steps` steps of tau.  d: the table 1/mu + tau eps^2 mu of this tau; the
+// right-hand side scale is bt + boff (bt a table, boff a constant), i.e.
+// 1/mu + tau (f == 0: 1/mu): the coarse step passes the table 1/mu + tau with
+// boff = 0 (f == 0: -tau), the fine step (PA-I) the table 1/mu with boff =
+// tau (f == 0: 0).  rtol: the CG stop.
 template <int N, int NW>
-__device__ void approx2_solve(double* X, double* red, const double* T, const SineWalk& sw,
-                              const Lane<N, NW>& L, const InstDev& P, const Work& W,
+__device__ void approx2_steps(double* X, double* red, const double* T, const SineWalk& sw,
+                              const Lane<N, NW>& L, const InstDev& P, const Work& W, double tau,
+                              int steps, const OVec& d, const OVec& bt, double boff, double rtol,
                               int& status) {
   using G = Geo<N, NW>;
   const int vo = threadIdx.x * 8;
-  const double tau = P.dT / P.m_coarse;
   double y[G::OWN], b[G::OWN];
-  for (int sub = 0; sub < P.m_coarse; ++sub) {
+  for (int sub = 0; sub < steps; ++sub) {
     load_owned<N, NW>(X, L, y);
     const double cshift = set_q<N, NW>(W.q, red, y, P.f_zero ? 0.0 : 1.0, 0.0);
     stage<N, NW>(X, T, sw, L, nullptr);
     stage_regs<N, NW>(X, T, sw, L, y);   // u_hat
 #pragma unroll
     for (int s = 0; s < G::OWN; ++s) {
-      const double cb = W.b_coarse.ld(s * G::NT, vo);
-      b[s] = (P.f_zero ? (cb - tau) : cb) * y[s];
+      const double cb = bt.ld(s * G::NT, vo);
+      b[s] = (cb + boff) * y[s];
     }
-    const int its = spectral_cg<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, W.d_coarse, tau,
-                                       cshift, P.krylov_rtol, P.krylov_max, b);
+    const int its = spectral_cg<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, d, tau,
+                                       cshift, rtol, P.krylov_max, b);
     if (its < 0) status |= 1;
 #pragma unroll
     for (int s = 0; s < G::OWN; ++s) y[s] = W.x.ld(s * G::NT, vo);
@@ -709,13 +714,14 @@ __device__ void approx2_solve(double* X, double* red, const double* T, const Sin
 // d Yh + tau S(Y^3)S - tau Yh - uh/mu (BE), with d = 1/mu + tau eps^2 mu.
 // The state is carried in sine coordinates (Yh, uh in the work vectors).
 // Returns false if Newton or CG hit a cap.
+// tau: the step; dtab: the table 1/mu + tau eps^2 mu of that tau; be: the
+// backward-Euler variant.
 template <int N, int NW>
 __device__ bool newton_step(double* X, double* red, const double* T, const SineWalk& sw,
-                            const Lane<N, NW>& L, const InstDev& P, const Work& W) {
+                            const Lane<N, NW>& L, const InstDev& P, const Work& W, double tau,
+                            const OVec& dtab, bool be) {
   using G = Geo<N, NW>;
   const int vo = threadIdx.x * 8;
-  const double tau = P.dt;
-  const bool be = P.nl_variant == 1;
   double y[G::OWN], b[G::OWN];
   bool ok = true;
   for (int it = 0; it < P.newton_max; ++it) {
@@ -741,14 +747,14 @@ __device__ bool newton_step(double* X, double* red, const double* T, const SineW
     for (int s = 0; s < G::OWN; ++s) {
       const int o = s * G::NT;
       const double yh = W.yh.ld(o, vo), uh = W.uh.ld(o, vo);
-      const double d = W.d_fine.ld(o, vo), im = W.imu.ld(o, vo);
+      const double d = dtab.ld(o, vo), im = W.imu.ld(o, vo);
       double g;
       if (P.f_zero) g = d * yh - im * uh;
       else if (be) g = d * yh + tau * y[s] - tau * yh - im * uh;
       else g = d * yh + tau * y[s] - (im + tau) * uh;
       b[s] = -g;
     }
-    const int its = spectral_cg_mem<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, W.d_fine,
+    const int its = spectral_cg_mem<N, NW>(X, red, T, sw, L, W.x, W.r, W.p, W.q, W.m, dtab,
                                            tau, cshift, P.nl_krylov_rtol, P.krylov_max, b);
     if (its < 0) ok = false;
     double a[1] = {0.0};
@@ -804,7 +810,7 @@ k_fine_newton_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__
   }
   bool ok = true;
   for (int m = 0; m < P.j_fine; ++m) {
-    ok = newton_step<N, NW>(X, red, T, sw, L, P, W) && ok;
+    ok = newton_step<N, NW>(X, red, T, sw, L, P, W, P.dt, W.d_fine, P.nl_variant == 1) && ok;
 #pragma unroll
     for (int s = 0; s < G::OWN; ++s) W.uh.st(s * G::NT, vo, W.yh.ld(s * G::NT, vo));
   }
@@ -819,6 +825,35 @@ k_fine_newton_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__
   if (!ok && threadIdx.x == 0) atomicOr(P.status, 1);
 }
 
+// Scheme (2.3) as the coarse step (NPA-II): m_coarse Newton-solved steps of
+// tau = dT/m_coarse (the Newton iteration of newton_step with the coarse
+// tables).  State in X (state orientation) on entry and exit.
+template <int N, int NW>
+__device__ void eyre_coarse(double* X, double* red, const double* T, const SineWalk& sw,
+                            const Lane<N, NW>& L, const InstDev& P, const Work& W, int& status) {
+  using G = Geo<N, NW>;
+  const int vo = threadIdx.x * 8;
+  const double tau = P.dT / P.m_coarse;
+  double y[G::OWN];
+  for (int sub = 0; sub < P.m_coarse; ++sub) {
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage_regs<N, NW>(X, T, sw, L, y);   // u_hat
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) {
+      W.uh.st(s * G::NT, vo, y[s]);
+      W.yh.st(s * G::NT, vo, y[s]);
+    }
+    if (!newton_step<N, NW>(X, red, T, sw, L, P, W, tau, W.d_coarse, false)) status |= 1;
+#pragma unroll
+    for (int s = 0; s < G::OWN; ++s) y[s] = W.yh.ld(s * G::NT, vo);
+    __syncthreads();
+    store_owned<N, NW>(X, L, y);
+    __syncthreads();
+    stage<N, NW>(X, T, sw, L, nullptr);
+    stage<N, NW>(X, T, sw, L, nullptr);
+  }
+}
+
 // One coarse propagation of the state in X (state orientation), result in X.
 template <int N, int NW>
 __device__ void coarse_apply(double* X, double* red, const double* T, const SineWalk& sw,
@@ -828,9 +863,49 @@ __device__ void coarse_apply(double* X, double* red, const double* T, const Sine
     const double tau = P.dT / P.m_coarse;
     linear_steps<N, NW>(X, T, sw, L, v, P.m_coarse, tau / (P.h * P.h), P.s_fine, P.f_zero,
                         P.rsig_stab);
+  } else if (P.coarse_kind == 3) {
+    eyre_coarse<N, NW>(X, red, T, sw, L, P, W, status);
   } else {
-    approx2_solve<N, NW>(X, red, T, sw, L, P, W, status);
+    const double tau = P.dT / P.m_coarse;
+    approx2_steps<N, NW>(X, red, T, sw, L, P, W, tau, P.m_coarse, W.d_coarse, W.b_coarse,
+                         P.f_zero ? -tau : 0.0, P.krylov_rtol, status);
   }
+}
+
+// PA-I fine sweep: J steps of scheme (2.4) with tau = dt per work item, one
+// workgroup each (variable-coefficient solve by spectral CG every step).
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_approx2_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                  const double* __restrict__ Tg, const double* __restrict__ U_in,
+                  double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                  const int32_t* __restrict__ active, const int32_t* __restrict__ kmin,
+                  int in_iter) {
+  using G = Geo<N, NW>;
+  extern __shared__ double smem[];
+  double* X = smem + G::XOFF;
+  double* T = smem + G::XSZ;
+  double* red = T + G::P2;
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
+  const int64_t off = P.off_slices + (int64_t)it.slice * N * N;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * N * N;
+  Lane<N, NW> L;
+  const SineWalk sw = sine_walk<N, NW>(L);
+  const Work W = work_vectors(P, it.slice);
+  load_sine_table<N, NW>(T, Tg);
+  zero_state<N, NW>(smem);
+  __syncthreads();
+  load_state<N, NW>(X, U_in + off_in);
+  __syncthreads();
+  int status = 0;
+  approx2_steps<N, NW>(X, red, T, sw, L, P, W, P.dt, P.j_fine, W.d_fine, W.imu,
+                       P.f_zero ? 0.0 : P.dt, P.krylov_rtol, status);
+  __syncthreads();
+  store_state<N, NW>(X, F_out + off);
+  if (status && threadIdx.x == 0) atomicOr(P.status, status);
 }
 
 // mode 0: G on each masked work item independently.
@@ -2349,15 +2424,14 @@ __device__ int stream_spectral_cg(double* b0, double* b1, double* cx, double* cr
 
 // Scheme (2.4) on the streamed state in b0 (global), result in b0.  Tables
 // d (coarse tau) and 1/mu + tau in P.tab (natural order for n = 256).
+// `steps` steps of tau; cd, cb, boff as in approx2_steps.
 template <int N, int NW>
 __device__ void stream_approx2(double* b0, double* b1, double* cx, double* cr, double* cp,
                                double* cq, double* cm, double* Lc, const double* T, double* red,
-                               const InstDev& P, int& status) {
+                               const InstDev& P, double tau, int steps, const double* cd,
+                               const double* cb, double boff, int& status) {
   const int NN = N * N, NT = NW * 64, t = threadIdx.x;
-  const double* cd = P.tab;
-  const double* cb = P.tab + NN;
-  const double tau = P.dT / P.m_coarse;
-  for (int sub = 0; sub < P.m_coarse; ++sub) {
+  for (int sub = 0; sub < steps; ++sub) {
     double mn = 1e300, mx = -1e300;
     for (int i = t; i < NN; i += NT) {
       const double q = P.f_zero ? 0.0 : b0[i] * b0[i];
@@ -2369,7 +2443,7 @@ __device__ void stream_approx2(double* b0, double* b1, double* cx, double* cr, d
     const double cshift = 0.5 * (mn + mx);
     stream_stage<N, NW>(b0, b1, nullptr, Lc, T);
     stream_stage<N, NW>(b1, b0, nullptr, Lc, T);   // b0 = u_hat
-    for (int i = t; i < NN; i += NT) cr[i] = (P.f_zero ? cb[i] - tau : cb[i]) * b0[i];
+    for (int i = t; i < NN; i += NT) cr[i] = (cb[i] + boff) * b0[i];
     __syncthreads();
     const int its = stream_spectral_cg<N, NW>(b0, b1, cx, cr, cp, cq, cm, cd, tau, cshift,
                                               P.krylov_rtol, P.krylov_max, Lc, T, red);
@@ -2381,15 +2455,14 @@ __device__ void stream_approx2(double* b0, double* b1, double* cx, double* cr, d
 
 // Implicit fine step (see newton_step) on streamed vectors: the state is
 // carried in sine coordinates (uh, yh, natural order).
+// tau, cd (the table 1/mu + tau eps^2 mu of that tau), be: as in newton_step.
 template <int N, int NW>
 __device__ bool stream_newton_step(double* b0, double* b1, double* cx, double* cr, double* cp,
                                    double* cq, double* cm, double* uh, double* yh, double* Lc,
-                                   const double* T, double* red, const InstDev& P) {
+                                   const double* T, double* red, const InstDev& P, double tau,
+                                   const double* cd, bool be) {
   const int NN = N * N, NT = NW * 64, t = threadIdx.x;
-  const double* cd = P.tab + 2 * NN;
   const double* imu = P.tab + 3 * NN;
-  const double tau = P.dt;
-  const bool be = P.nl_variant == 1;
   bool ok = true;
   for (int it = 0; it < P.newton_max; ++it) {
     stream_stage<N, NW>(yh, b1, nullptr, Lc, T);
@@ -2463,7 +2536,8 @@ k_fine_newton_stream(const WorkItem* __restrict__ items, const InstDev* __restri
   __syncthreads();
   bool ok = true;
   for (int m = 0; m < P.j_fine; ++m) {
-    ok = stream_newton_step<N, NW>(b0, b1, cx, cr, cp, cq, cm, uh, yh, Lc, T, red, P) && ok;
+    ok = stream_newton_step<N, NW>(b0, b1, cx, cr, cp, cq, cm, uh, yh, Lc, T, red, P, P.dt,
+                                   P.tab + 2 * NN, P.nl_variant == 1) && ok;
     for (int64_t i = t; i < NN; i += G::NT) uh[i] = yh[i];
     __syncthreads();
   }
@@ -2473,18 +2547,71 @@ k_fine_newton_stream(const WorkItem* __restrict__ items, const InstDev* __restri
   if (!ok && t == 0) atomicOr(P.status, 1);
 }
 
+// Coarse step on the streamed state in b0 = w (work vectors w: 7 for the
+// linear kinds, 9 for scheme (2.3)).
 template <int N, int NW>
 __device__ void stream_coarse_apply(double* b0, const InstDev& P, double* w, double* Lc,
                                     const double* T, double* red, int& status) {
   const int64_t NN = (int64_t)N * N;
+  const double tau = P.dT / P.m_coarse;
   if (P.coarse_kind == 1) {
-    const double tau = P.dT / P.m_coarse;
     stream_linear_steps<N, NW>(b0, w + NN, Lc, T, P.m_coarse, tau / (P.h * P.h), P.s_fine,
                                P.f_zero, P.rsig_stab);
+  } else if (P.coarse_kind == 3) {
+    // NPA-II: m_coarse steps of scheme (2.3) by Newton, state in sine
+    // coordinates (uh, yh) between the steps
+    double *b1 = w + NN, *uh = w + 7 * NN, *yh = w + 8 * NN;
+    const int t = threadIdx.x, NT = NW * 64;
+    for (int sub = 0; sub < P.m_coarse; ++sub) {
+      stream_stage<N, NW>(b0, b1, nullptr, Lc, T);
+      stream_stage<N, NW>(b1, uh, nullptr, Lc, T);   // u_hat
+      for (int64_t i = t; i < NN; i += NT) yh[i] = uh[i];
+      __syncthreads();
+      if (!stream_newton_step<N, NW>(b0, b1, w + 2 * NN, w + 3 * NN, w + 4 * NN, w + 5 * NN,
+                                     w + 6 * NN, uh, yh, Lc, T, red, P, tau, P.tab, false))
+        status |= 1;
+      stream_stage<N, NW>(yh, b1, nullptr, Lc, T);
+      stream_stage<N, NW>(b1, b0, nullptr, Lc, T);   // b0 = the new state
+    }
   } else {
     stream_approx2<N, NW>(b0, w + NN, w + 2 * NN, w + 3 * NN, w + 4 * NN, w + 5 * NN, w + 6 * NN,
-                          Lc, T, red, P, status);
+                          Lc, T, red, P, tau, P.m_coarse, P.tab, P.tab + NN,
+                          P.f_zero ? -tau : 0.0, status);
   }
+}
+
+// PA-I fine sweep on streamed vectors (n = 256): J steps of scheme (2.4)
+// with tau = dt per work item, one workgroup each.
+template <int N, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_fine_approx2_stream(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                      const double* __restrict__ Tg, const double* __restrict__ U_in,
+                      double* __restrict__ F_out, const uint8_t* __restrict__ mask,
+                      const int32_t* __restrict__ active, const int32_t* __restrict__ kmin,
+                      int in_iter) {
+  using G = GeoS<N, NW>;
+  extern __shared__ double smem[];
+  double* Lc = smem;
+  double* T = smem + 2 * G::CHUNK;
+  double* red = T + G::P2;
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t off = P.off_slices + (int64_t)it.slice * NN;
+  const int64_t off_in = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * NN;
+  double* w = P.work + (int64_t)it.slice * P.work_vecs * NN;
+  const int t = threadIdx.x;
+  for (int m = t; m < G::P2; m += G::NT) T[m] = Tg[m];
+  for (int64_t i = t; i < NN; i += G::NT) w[i] = U_in[off_in + i];
+  __syncthreads();
+  int status = 0;
+  stream_approx2<N, NW>(w, w + NN, w + 2 * NN, w + 3 * NN, w + 4 * NN, w + 5 * NN, w + 6 * NN,
+                        Lc, T, red, P, P.dt, P.j_fine, P.tab + 2 * NN, P.tab + 3 * NN,
+                        P.f_zero ? 0.0 : P.dt, status);
+  for (int64_t i = t; i < NN; i += G::NT) F_out[off + i] = w[i];
+  if (status && t == 0) atomicOr(P.status, status);
 }
 
 // Streamed counterpart of k_coarse_2d (same modes).  Work vectors: b0 =
@@ -2910,141 +3037,200 @@ hipError_t launch_fine_split_2d(int n, const WorkItem* items, int n_items, const
 }
 
 // ------------------------------------------------------------------- 1D
-// One workgroup of n threads per state; S (n x n) staged in LDS.  Thread i
-// owns grid point i (state) and sine index i (spectral).
-__device__ __forceinline__ double sine_apply_1d(const double* Sl, const double* vin, int n, int i) {
+// One workgroup per state, NT = n rounded up to 64 threads; thread i < n
+// owns grid point i (state) and sine index i (spectral), the others hold
+// zeros.  S (n x n) is staged in LDS.  Any n <= 128.
+struct Ctx1 {
+  const double* Sl;   // S in LDS, S[k][i] at k * n + i
+  double* buf;        // n values
+  double* red;        // 64 partials
+  int n, i;
+  bool on;            // i < n
+};
+
+// (S v)_i, v given per thread (zero off the grid)
+__device__ __forceinline__ double sine1(const Ctx1& c, double v) {
+  __syncthreads();
+  if (c.on) c.buf[c.i] = v;
+  __syncthreads();
   double acc = 0.0;
-  for (int k = 0; k < n; ++k) acc += Sl[k * n + i] * vin[k];
+  if (c.on)
+    for (int k = 0; k < c.n; ++k) acc += c.Sl[k * c.n + c.i] * c.buf[k];
   return acc;
 }
 
-__global__ void k_fine_linear_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
-                                 const double* __restrict__ S, const double* __restrict__ rsig1,
-                                 const double* __restrict__ U_in, double* __restrict__ F_out,
-                                 const uint8_t* __restrict__ mask,
-                                 const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
+// Deterministic block sum (fixed wave order); every thread gets the sum.
+__device__ __forceinline__ double bsum1(const Ctx1& c, double v) {
+  v = wave_sum<1>(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) c.red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int ww = 0; ww < nw; ++ww) s += c.red[ww];
+  return s;
+}
+
+// (min + max)/2 over the grid points of a per-thread value
+__device__ __forceinline__ double bmid1(const Ctx1& c, double v) {
+  double mn = c.on ? v : 1e300, mx = c.on ? v : -1e300;
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) { c.red[w] = mn; c.red[32 + w] = mx; }
+  __syncthreads();
+  mn = c.red[0]; mx = c.red[32];
+  for (int ww = 1; ww < nw; ++ww) { mn = fmin(mn, c.red[ww]); mx = fmax(mx, c.red[32 + ww]); }
+  return 0.5 * (mn + mx);
+}
+
+// u + c * Lap_h-stencil(w) * h^2 with zero ghosts: the right-hand side form
+// u + tau Lap_h w (c = tau / h^2)
+__device__ __forceinline__ double lap_rhs1(const Ctx1& c, double u, double w, double coef) {
+  __syncthreads();
+  if (c.on) c.buf[c.i] = w;
+  __syncthreads();
+  if (!c.on) return 0.0;
+  const double wl = c.i > 0 ? c.buf[c.i - 1] : 0.0, wr = c.i < c.n - 1 ? c.buf[c.i + 1] : 0.0;
+  return u + coef * ((wl + wr) - 2.0 * w);
+}
+
+// Linear stabilised steps: (I + tau eps^2 L^2 - s tau L) v = u + tau L (f(u) - s u),
+// diagonal on the sine modes with 1 / sigma = rsig[i].
+__device__ double stab1(const Ctx1& c, double u, const InstDev& P, double tau, int steps,
+                        const double* rsig) {
+  const double coef = tau / (P.h * P.h), s = P.s_fine;
+  const double rs = c.on ? rsig[c.i] : 0.0;
+  for (int m = 0; m < steps; ++m) {
+    const double w = P.f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
+    const double r = lap_rhs1(c, u, w, coef);
+    u = sine1(c, sine1(c, r) * rs);
+  }
+  return u;
+}
+
+// PCG in sine coordinates for K x = b, K = diag(d) + tau S diag(q) S (SPD),
+// preconditioner 1 / (d + tau cshift), from x = 0, stopped when
+// ||r|| <= rtol ||b||.  Returns false on the cap or a non-finite residual.
+__device__ bool cg1(const Ctx1& c, double b, double d, double q, double tau, double cshift,
+                    double rtol, int maxit, double& x) {
+  const double mi = c.on ? 1.0 / (d + tau * cshift) : 0.0;
+  x = 0.0;
+  double r = b, p = b * mi;
+  double rz = bsum1(c, r * p);
+  const double bb = bsum1(c, b * b);
+  if (!(bb > 0.0)) return true;
+  const double stop2 = rtol * rtol * bb;
+  for (int it = 1; it <= maxit; ++it) {
+    const double kp = d * p + tau * sine1(c, q * sine1(c, p));
+    const double alpha = rz / bsum1(c, p * kp);
+    x += alpha * p;
+    r -= alpha * kp;
+    const double rr = bsum1(c, r * r);
+    const double rzn = bsum1(c, r * (r * mi));
+    if (rr <= stop2) return true;
+    if (!(rr == rr)) return false;
+    p = r * mi + (rzn / rz) * p;
+    rz = rzn;
+  }
+  return false;
+}
+
+// Scheme (2.4) steps of tau: K v_hat = (1/mu + tau) u_hat with q = u^2
+// (f == 0: q = 0 and the right-hand side u_hat / mu), mu = -lam.
+__device__ double approx2_1(const Ctx1& c, double u, const InstDev& P, const double* lam,
+                            double tau, int steps, int& status) {
+  const double mu = c.on ? -lam[c.i] : 1.0;
+  const double d = 1.0 / mu + tau * P.eps * P.eps * mu;
+  for (int m = 0; m < steps; ++m) {
+    const double q = (P.f_zero || !c.on) ? 0.0 : u * u;
+    const double cs = bmid1(c, q);
+    const double uh = sine1(c, u);
+    const double b = (P.f_zero ? 1.0 / mu : 1.0 / mu + tau) * uh;
+    double x;
+    if (!cg1(c, b, d, q, tau, cs, P.krylov_rtol, P.krylov_max, x)) status |= 1;
+    u = sine1(c, x);
+  }
+  return u;
+}
+
+// Scheme (2.3) (be = false) or backward Euler (true) with step tau, by
+// Newton's method from Y_0 = u in sine coordinates (as newton_step in 2D):
+// A^{-1} H(Y) = d Yh + tau S(Y^3) - (1/mu + tau) uh (2.3) or
+// d Yh + tau S(Y^3) - tau Yh - uh/mu (BE), the Newton matrix
+// diag(d) + tau S diag(q) S with q = 3Y^2 (2.3) or 3Y^2 - 1 (BE); stop when
+// ||Y_{m+1} - Y_m||_h <= newton_tol.  Returns the new state.
+__device__ double newton1(const Ctx1& c, double u, const InstDev& P, const double* lam,
+                          double tau, bool be, int& status) {
+  const double mu = c.on ? -lam[c.i] : 1.0;
+  const double im = c.on ? 1.0 / mu : 0.0;
+  const double d = im + tau * P.eps * P.eps * mu;
+  const double uh = sine1(c, u);
+  double yh = uh;
+  bool conv = false;
+  for (int it = 0; it < P.newton_max; ++it) {
+    const double y = sine1(c, yh);
+    const double q = (P.f_zero || !c.on) ? 0.0 : 3.0 * y * y + (be ? -1.0 : 0.0);
+    const double cs = bmid1(c, q);
+    const double y3h = sine1(c, P.f_zero ? 0.0 : y * y * y);
+    double g;
+    if (P.f_zero) g = d * yh - im * uh;
+    else if (be) g = d * yh + tau * y3h - tau * yh - im * uh;
+    else g = d * yh + tau * y3h - (im + tau) * uh;
+    if (!c.on) g = 0.0;
+    double dx;
+    if (!cg1(c, -g, d, q, tau, cs, P.nl_krylov_rtol, P.krylov_max, dx)) status |= 1;
+    yh += dx;
+    const double step = sqrt(P.h * bsum1(c, dx * dx));   // ||S dYh||_h = sqrt(h) ||dYh||
+    if (step <= P.newton_tol) { conv = true; break; }
+    if (!(step == step)) break;
+  }
+  if (!conv) status |= 1;
+  return sine1(c, yh);
+}
+
+// Fine propagator of one work item: J steps of the instance's fine scheme.
+__global__ void k_fine_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                          const double* __restrict__ S, const double* __restrict__ lam,
+                          const double* __restrict__ U_in, double* __restrict__ F_out,
+                          const uint8_t* __restrict__ mask, const int32_t* __restrict__ active,
+                          const int32_t* __restrict__ kmin, int in_iter) {
   extern __shared__ double smem[];
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
   if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
-  const int n = P.n, i = threadIdx.x;
-  double* Sl = smem;
-  double* w = smem + n * n;
-  double* r = w + n;
-  for (int idx = i; idx < n * n; idx += n) Sl[idx] = S[idx];
-  const int64_t off = P.off_slices + (int64_t)it.slice * n;
-  double u = U_in[(in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * n + i];
-  const double c = P.dt / (P.h * P.h), s = P.s_fine;
-  const double rs = P.rsig_fine[i];
-  __syncthreads();
-  for (int m = 0; m < P.j_fine; ++m) {
-    w[i] = P.f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
-    __syncthreads();
-    const double wl = i > 0 ? w[i - 1] : 0.0, wr = i < n - 1 ? w[i + 1] : 0.0;
-    r[i] = u + c * ((wl + wr) - 2.0 * w[i]);
-    __syncthreads();
-    const double rh = sine_apply_1d(Sl, r, n, i) * rs;
-    __syncthreads();
-    w[i] = rh;
-    __syncthreads();
-    u = sine_apply_1d(Sl, w, n, i);
-    __syncthreads();
+  const int n = P.n;
+  Ctx1 c{smem, smem + n * n, smem + n * n + n, n, (int)threadIdx.x, (int)threadIdx.x < n};
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) smem[idx] = S[idx];
+  const int64_t in0 = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * n;
+  double u = c.on ? U_in[in0 + c.i] : 0.0;
+  int status = 0;
+  if (P.fine_kind == 0) {
+    u = stab1(c, u, P, P.dt, P.j_fine, P.rsig_fine);
+  } else if (P.fine_kind == 2) {
+    u = approx2_1(c, u, P, lam, P.dt, P.j_fine, status);
+  } else {
+    for (int m = 0; m < P.j_fine; ++m) u = newton1(c, u, P, lam, P.dt, P.nl_variant == 1, status);
   }
-  F_out[off + i] = u;
+  if (c.on) F_out[P.off_slices + (int64_t)it.slice * n + c.i] = u;
+  if (status && threadIdx.x == 0) atomicOr(P.status, status);
 }
 
-template <int NMAX>
-__device__ double block_sum_1d(double v, double* red) {
-  // n threads (<= NMAX, multiple of 64 not required): fixed tree over waves
-  v = wave_sum<1>(v);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int ww = 0; ww < nw; ++ww) s += red[ww];
-  return s;
-}
-
-// Scheme (2.4) (or the stabilised step) on the state u held by thread i.
-__device__ double coarse_apply_1d(double u, const InstDev& P, const double* Sl, double* buf,
-                                  double* red, const double* lam, const double* rsig_stab,
+// One coarse propagation: m_coarse steps of tau = dT/m_coarse of the
+// instance's coarse scheme.
+__device__ double coarse_apply_1d(const Ctx1& c, double u, const InstDev& P, const double* lam,
                                   int& status) {
-  const int n = P.n, i = threadIdx.x;
   const double tau = P.dT / P.m_coarse;
-  for (int sub = 0; sub < P.m_coarse; ++sub) {
-    if (P.coarse_kind == 1) {
-      const double c = tau / (P.h * P.h), s = P.s_fine;
-      buf[i] = P.f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
-      __syncthreads();
-      const double wl = i > 0 ? buf[i - 1] : 0.0, wr = i < n - 1 ? buf[i + 1] : 0.0;
-      const double r = u + c * ((wl + wr) - 2.0 * buf[i]);
-      __syncthreads();
-      buf[i] = r;
-      __syncthreads();
-      const double rh = sine_apply_1d(Sl, buf, n, i) * rsig_stab[i];
-      __syncthreads();
-      buf[i] = rh;
-      __syncthreads();
-      u = sine_apply_1d(Sl, buf, n, i);
-      __syncthreads();
-      continue;
-    }
-    const double mu = -lam[i];
-    const double d = 1.0 / mu + tau * P.eps * P.eps * mu;
-    const double q = P.f_zero ? 0.0 : u * u;
-    double mn = q, mx = q;
-    for (int o = 32; o > 0; o >>= 1) {
-      mn = fmin(mn, __shfl_xor(mn, o, 64));
-      mx = fmax(mx, __shfl_xor(mx, o, 64));
-    }
-    __syncthreads();
-    if ((i & 63) == 0) { red[i >> 6] = mn; red[32 + (i >> 6)] = mx; }
-    __syncthreads();
-    const int nw = (n + 63) >> 6;
-    mn = red[0]; mx = red[32];
-    for (int ww = 1; ww < nw; ++ww) { mn = fmin(mn, red[ww]); mx = fmax(mx, red[32 + ww]); }
-    const double mi = 1.0 / (d + tau * 0.5 * (mn + mx));
-    buf[i] = u;
-    __syncthreads();
-    const double uh = sine_apply_1d(Sl, buf, n, i);
-    const double b = (P.f_zero ? 1.0 / mu : 1.0 / mu + tau) * uh;
-    double x = 0.0, r = b, z = b * mi, p = z;
-    double rz = block_sum_1d<1024>(r * z, red);
-    const double bb = block_sum_1d<1024>(b * b, red);
-    const double stop2 = P.krylov_rtol * P.krylov_rtol * bb;
-    int it = 0;
-    bool go = bb > 0.0;
-    while (go) {
-      __syncthreads();
-      buf[i] = p;
-      __syncthreads();
-      const double ps = sine_apply_1d(Sl, buf, n, i) * q;
-      __syncthreads();
-      buf[i] = ps;
-      __syncthreads();
-      const double kp = d * p + tau * sine_apply_1d(Sl, buf, n, i);
-      const double pkp = block_sum_1d<1024>(p * kp, red);
-      const double alpha = rz / pkp;
-      x += alpha * p;
-      r -= alpha * kp;
-      const double rr = block_sum_1d<1024>(r * r, red);
-      const double rzn = block_sum_1d<1024>(r * (r * mi), red);
-      ++it;
-      if (rr <= stop2) break;
-      if (it >= P.krylov_max || !(rr == rr)) { status |= 1; break; }
-      const double beta = rzn / rz;
-      rz = rzn;
-      p = r * mi + beta * p;
-    }
-    __syncthreads();
-    buf[i] = x;
-    __syncthreads();
-    u = sine_apply_1d(Sl, buf, n, i);
-    __syncthreads();
+  if (P.coarse_kind == 1) return stab1(c, u, P, tau, P.m_coarse, P.rsig_stab);
+  if (P.coarse_kind == 3) {
+    for (int m = 0; m < P.m_coarse; ++m) u = newton1(c, u, P, lam, tau, false, status);
+    return u;
   }
-  return u;
+  return approx2_1(c, u, P, lam, tau, P.m_coarse, status);
 }
 
 __global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
@@ -3057,62 +3243,63 @@ __global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
                             const int32_t* __restrict__ kdev) {
   extern __shared__ double smem[];
   if (kdev) k = *kdev;
-  const int i = threadIdx.x;
   int status = 0;
-  if (mode == 0) {
-    const WorkItem it = items[blockIdx.x];
-    const InstDev P = inst[it.inst];
-    if (mask && !mask[P.slice_base + it.slice]) return;
-    const int n = P.n;
-    double* Sl = smem; double* buf = smem + n * n; double* red = buf + n;
-    for (int idx = i; idx < n * n; idx += n) Sl[idx] = S[idx];
-    __syncthreads();
+  const bool par = mode == 0;
+  const WorkItem it = par ? items[blockIdx.x] : WorkItem{insts[blockIdx.x], 0};
+  const int ii = it.inst;
+  const InstDev P = inst[ii];
+  if (par && mask && !mask[P.slice_base + it.slice]) return;
+  if (!par && active && !active[ii]) return;
+  const int n = P.n;
+  Ctx1 c{smem, smem + n * n, smem + n * n + n, n, (int)threadIdx.x, (int)threadIdx.x < n};
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) smem[idx] = S[idx];
+  const int i = c.i;
+  if (par) {
     const int64_t off = P.off_slices + (int64_t)it.slice * n;
-    G_out[off + i] = coarse_apply_1d(U_in[off + i], P, Sl, buf, red, lam, P.rsig_stab, status);
+    const double g = coarse_apply_1d(c, c.on ? U_in[off + i] : 0.0, P, lam, status);
+    if (c.on) G_out[off + i] = g;
+    if (status && threadIdx.x == 0) atomicOr(P.status, status);
     return;
   }
-  const int ii = insts[blockIdx.x];
-  if (active && !active[ii]) return;
-  const InstDev P = inst[ii];
-  const int n = P.n;
-  double* Sl = smem; double* buf = smem + n * n; double* red = buf + n;
-  for (int idx = i; idx < n * n; idx += n) Sl[idx] = S[idx];
-  __syncthreads();
   double* Ui = U + P.off_iter;
   const double* Fi = F + P.off_slices;
   double* Gi = G_old + P.off_slices;
   if (mode == 1) {
-    double u = Ui[i];
+    double u = c.on ? Ui[i] : 0.0;
     for (int s = 0; s < P.n_slices; ++s) {
-      u = coarse_apply_1d(u, P, Sl, buf, red, lam, P.rsig_stab, status);
-      Ui[(s + 1) * n + i] = u;
-      Gi[s * n + i] = u;
+      u = coarse_apply_1d(c, u, P, lam, status);
+      if (c.on) {
+        Ui[(s + 1) * n + i] = u;
+        Gi[s * n + i] = u;
+      }
     }
-    if (i == 0) status_out[ii] = status;
+    if (threadIdx.x == 0) status_out[ii] = status | *P.status;
     return;
   }
   if (k >= P.n_slices) {
-    if (i == 0) delta[ii] = 0.0;
+    if (threadIdx.x == 0) delta[ii] = 0.0;
     return;
   }
-  double u = Fi[k * n + i];
-  double dd = u - Ui[(k + 1) * n + i];
-  double dmax = block_sum_1d<1024>(dd * dd, red);
-  Ui[(k + 1) * n + i] = u;
+  double u = c.on ? Fi[k * n + i] : 0.0;
+  double dd = c.on ? u - Ui[(k + 1) * n + i] : 0.0;
+  double dmax = bsum1(c, dd * dd);
+  if (c.on) Ui[(k + 1) * n + i] = u;
   for (int s = k + 1; s < P.n_slices; ++s) {
-    const double g = coarse_apply_1d(u, P, Sl, buf, red, lam, P.rsig_stab, status);
-    const double un = Fi[s * n + i] + (g - Gi[s * n + i]);
-    dd = un - Ui[(s + 1) * n + i];
-    dmax = fmax(dmax, block_sum_1d<1024>(dd * dd, red));
-    Ui[(s + 1) * n + i] = un;
-    Gi[s * n + i] = g;
+    const double g = coarse_apply_1d(c, u, P, lam, status);
+    const double un = c.on ? Fi[s * n + i] + (g - Gi[s * n + i]) : 0.0;
+    dd = c.on ? un - Ui[(s + 1) * n + i] : 0.0;
+    dmax = fmax(dmax, bsum1(c, dd * dd));
+    if (c.on) {
+      Ui[(s + 1) * n + i] = un;
+      Gi[s * n + i] = g;
+    }
     u = un;
   }
-  if (i == 0) {
+  if (threadIdx.x == 0) {
     const double dlt = sqrt(P.h * dmax);
     delta[ii] = dlt;
     if (!(dlt == dlt) || dlt > 1e300) status |= 2;
-    status_out[ii] |= status;
+    status_out[ii] |= status | *P.status;
   }
 }
 
@@ -3295,6 +3482,49 @@ static hipError_t newton_stream(const WorkItem* items, int n_items, const InstDe
   return hipGetLastError();
 }
 
+template <int N, int NW>
+static hipError_t approx2f_2d(const WorkItem* items, int n_items, const InstDev* inst,
+                              const double* Tg, const double* U_in, double* F_out,
+                              const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                              int in_iter, hipStream_t s) {
+  const size_t lds = ((size_t)Geo<N, NW>::XSZ + Geo<N, NW>::P2 + 4 * NW) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_approx2_2d<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fine_approx2_2d<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items,
+                     inst, Tg, U_in, F_out, mask, active, kmin, in_iter);
+  return hipGetLastError();
+}
+
+template <int N, int NW>
+static hipError_t approx2f_stream(const WorkItem* items, int n_items, const InstDev* inst,
+                                  const double* Tg, const double* U_in, double* F_out,
+                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                                  int in_iter, hipStream_t s) {
+  const size_t lds =
+      ((size_t)2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2 + 4 * NW) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_approx2_stream<N, NW>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fine_approx2_stream<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items,
+                     inst, Tg, U_in, F_out, mask, active, kmin, in_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_approx2_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                                  const double* Tg, const double* U_in, double* F_out,
+                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                                  int in_iter, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (n) {
+    case 256: return approx2f_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 32: return approx2f_2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 64: return approx2f_2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 128: return approx2f_2d<128, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                  const double* Tg, const double* U_in, double* F_out,
                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,
@@ -3313,13 +3543,16 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
                           const double* S, const double* rsig1, const double* U_in, double* F_out,
                           const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
                           hipStream_t s) {
+  (void)rsig1;
   if (n_items <= 0) return hipSuccess;
-  const size_t lds = ((size_t)n * n + 2 * n) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_1d,
+  // lam for 1D is stored right after S (n x n) in the table block
+  const double* lam = S + (size_t)n * n;
+  const size_t lds = ((size_t)n * n + n + 64) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fine_1d,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fine_linear_1d, dim3(n_items), dim3(n), lds, s, items, inst, S, rsig1, U_in,
-                     F_out, mask, active, kmin, in_iter);
+  hipLaunchKernelGGL(k_fine_1d, dim3(n_items), dim3((n + 63) / 64 * 64), lds, s, items, inst, S,
+                     lam, U_in, F_out, mask, active, kmin, in_iter);
   return hipGetLastError();
 }
 
@@ -3387,7 +3620,7 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
   if (e != hipSuccess) return e;
   const int grid = mode == 0 ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_1d, dim3(grid), dim3(n), lds, s, mode, insts, items, inst, S, lam,
+  hipLaunchKernelGGL(k_coarse_1d, dim3(grid), dim3((n + 63) / 64 * 64), lds, s, mode, insts, items, inst, S, lam,
                      U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
   return hipGetLastError();
 }

@@ -190,7 +190,7 @@ def test_alpha_beta_from_the_sine_eigenvalues(dim, n, i_fine, i_coarse):
     assert abs(beta - np.max(np.abs(g))) <= 1e-12 * beta
 
 
-@pytest.mark.parametrize("kind,m", [("approx2", 3), ("stab", 4)])
+@pytest.mark.parametrize("kind,m", [("approx2", 3), ("stab", 4), ("eyre", 2)])
 def test_coarse_substeps_take_tau_dT_over_m(kind, m):
     # f == 0: the coarse step is diagonal on a sine mode, with factor
     # 1 / (1 + eps^2 tau Lam^2) for (2.4) and (1 - s tau Lam) / (1 + eps^2 tau
@@ -233,3 +233,44 @@ def test_parareal_closed_form_with_coarse_substeps():
             c = sum(math.comb(nn, j) * (phi - gam) ** j * gam ** (nn - j)
                     for j in range(0, min(k, nn) + 1))
             assert np.max(np.abs(Uk[nn] - c * u0)) < 1e-12, (k, nn)
+
+
+@pytest.mark.parametrize("pairing", ["PA-I", "NPA-II"])
+def test_finite_termination_of_the_other_pairings(pairing):
+    # PA-I (F = G = (2.4)) and NPA-II (F = G = (2.3), coarse by Newton):
+    # Parareal reproduces the serial fine solve bit for bit at k = N
+    kw = dict(fine_kind="approx2") if pairing == "PA-I" else dict(fine_kind="nonlinear",
+                                                                   coarse_kind="eyre")
+    p = workloads.Problem(dim=1, n=32, eps=0.05, T=0.12, n_slices=5, j_fine=10, **kw)
+    u0 = workloads.u0_uniform(32, 1, 0.3, 3)
+    seq = propagators.fine_sequential(p, u0)
+    out = parareal.parareal(u0, p.n_slices, lambda u: propagators.fine(p, u),
+                            lambda u: propagators.coarse(p, u), _norm1, tol=0.0)
+    for nn in range(p.n_slices + 1):
+        assert np.array_equal(out["final"][nn], seq[nn])
+    assert out["delta"][0] > 0
+
+
+def test_eyre_coarse_with_one_substep_is_one_newton_step_of_the_slice():
+    # the NPA-II coarse propagator with m_c = 1 is one step of (2.3) with
+    # tau = dT, i.e. the fine propagator of a one-step slice
+    p = workloads.Problem(dim=2, n=10, eps=0.05, T=0.02, n_slices=2, j_fine=7,
+                          fine_kind="nonlinear", coarse_kind="eyre")
+    q = workloads.Problem(dim=2, n=10, eps=0.05, T=0.02, n_slices=2, j_fine=1,
+                          fine_kind="nonlinear")
+    u = workloads.u0_uniform(10, 2, 0.5, 8)
+    assert np.array_equal(propagators.coarse(p, u), propagators.fine(q, u))
+
+
+def test_pa1_fine_propagator_closed_form():
+    # PA-I's fine propagator is J steps of (2.4) with tau = dt; with f == 0 a
+    # sine mode decays by 1 / (1 + eps^2 dt Lam^2) per step
+    n = 20
+    p = workloads.Problem(dim=2, n=n, eps=0.05, T=0.02, n_slices=2, j_fine=9,
+                          fine_kind="approx2", f_zero=True)
+    x = np.arange(1, n + 1) / (n + 1)
+    u = np.outer(np.sin(4 * np.pi * x), np.sin(1 * np.pi * x))
+    lam = ops.eigenvalues_paper(n)
+    rho = 1.0 / (1 + p.eps ** 2 * p.dt * (lam[3] + lam[0]) ** 2)
+    v = propagators.fine(p, u)
+    assert np.max(np.abs(v - rho ** p.j_fine * u)) <= 1e-13 * np.max(np.abs(u))

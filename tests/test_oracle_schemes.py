@@ -146,3 +146,48 @@ def test_newton_residual_is_the_scheme_defect(variant, dim, n):
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
     v = schemes.step_newton(u, tau, eps, variant, tol=1e-13)
     assert np.max(np.abs(schemes.newton_residual(v, u, tau, eps, variant))) < 1e-9
+
+
+# ---- the sine-basis routes reach the sparse-LU results up to rounding
+@pytest.mark.parametrize("dim,n", [(1, 31), (2, 24), (2, 64)])
+def test_sine_route_linear_step_equals_lu(dim, n):
+    u = _u0(n, dim, amp=0.7, seed=21)
+    for tau, eps, s in ((2e-5, 0.02, 2.0), (1e-3, 0.05, 0.0), (3e-4, 0.03, 3.0)):
+        a = schemes.step_stab(u, tau, eps, s)
+        b = schemes.step_stab_dst(u, tau, eps, s)
+        assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(a), (tau, eps, s)
+
+
+def test_sine_route_mode_decay_closed_form():
+    n, tau, eps, s, m = 40, 1e-4, 0.03, 2.0, 20
+    x = np.arange(1, n + 1) / (n + 1)
+    u = np.outer(np.sin(3 * math.pi * x), np.sin(5 * math.pi * x))
+    lam = lambda k: 2 * (n + 1) ** 2 * (math.cos(k * math.pi / (n + 1)) - 1)
+    Lam = lam(3) + lam(5)
+    rho = (1 - s * tau * Lam) / (1 + tau * eps ** 2 * Lam ** 2 - s * tau * Lam)
+    v = u.copy()
+    for _ in range(m):
+        v = schemes.step_stab_dst(v, tau, eps, s, f_zero=True)
+    assert np.max(np.abs(v - rho ** m * u)) <= 1e-12 * np.max(np.abs(u))
+
+
+@pytest.mark.parametrize("variant,n", [("eyre", 24), ("eyre", 48), ("be", 24), ("be", 48)])
+def test_pcg_route_newton_step_equals_lu(variant, n):
+    rng = np.random.default_rng(n)
+    u = 0.25 + 0.05 * rng.standard_normal((n, n))
+    for tau, eps in ((1e-5, 0.015), (2e-4, 0.05)):
+        a = schemes.step_newton(u, tau, eps, variant)
+        b = schemes.step_newton_pcg(u, tau, eps, variant)
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a), (tau, eps)
+
+
+def test_pcg_solves_a_dense_spd_system():
+    # the textbook PCG against numpy's dense solve on a random SPD matrix
+    rng = np.random.default_rng(2)
+    B = rng.standard_normal((30, 30))
+    K = B @ B.T + 30 * np.eye(30)
+    b = rng.standard_normal(30)
+    dinv = 1.0 / np.diag(K)
+    x, it = schemes.pcg(lambda v: K @ v, lambda v: dinv * v, b, np.zeros(30), 1e-14, 200)
+    ref = np.linalg.solve(K, b)
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref) and it > 0

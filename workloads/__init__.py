@@ -32,13 +32,14 @@ class Problem:
     j_fine: int = 1563        # fine steps per slice J
     m_coarse: int = 1         # coarse sub-steps per slice
     s_fine: float = 2.0       # stabilisation constant of the linear fine step
-    fine_kind: str = "linear"       # "linear" or "nonlinear"
+    fine_kind: str = "linear"       # "linear" (2.5), "nonlinear" (2.3) or "approx2" (2.4)
     nl_variant: str = "eyre"        # "eyre" (convex splitting) or "be" (fully implicit)
-    coarse_kind: str = "approx2"    # "approx2", "stab" or "neural"
+    coarse_kind: str = "approx2"    # "approx2" (2.4), "stab", "neural" or "eyre" (2.3)
     precision: str = "fp64"         # "fp64" or "split_bf16"
     newton_tol: float = 1e-10
     newton_max: int = 20
-    krylov_rtol: float = 1e-12
+    krylov_rtol: float = 1e-13     # CG target of the (2.4) solves (coarse, and PA-I fine)
+    nl_krylov_rtol: float = 1e-9    # CG target inside Newton
     krylov_max: int = 200
     f_zero: bool = False     # test hook: f(u) == 0
 
