@@ -287,6 +287,22 @@ def bench_batched(args):
                      "finite": ok}}
 
 
+def bench_study(args):
+    """The parameter studies of Section 4 (all five pairings, 1D at h = 1/64
+    and 2D) on the GPU path, each beside its convergence bound of Section 3;
+    parity-unpinned against the paper's figures (its initial data are not
+    stated)."""
+    from paper_2304_14074_amd import study
+    t0 = time.perf_counter()
+    res = study.run_study(log=lambda m: print(m, file=sys.stderr, flush=True))
+    return {"workload": "paper parameter studies (Section 4) with the Section 3 bounds",
+            "cases": res, "seconds": time.perf_counter() - t0,
+            "paper_context": {"PA-I/PA-III 1D, eps=0.0725, h=1/64, J=200": "4 iterations to 1e-6",
+                              "PA-I 1D T=8": "40x idealised speed-up (N/K)",
+                              "NPA-I 1D T=50, J=150, N=400": "80x idealised speed-up",
+                              "NPA-I / NPA-II fitted C1 (dT=1, N=20, J=200)": [0.1181, 0.1498]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,7 +315,7 @@ def main():
     ap.add_argument("--nn-traj", type=int, default=256)
     ap.add_argument("--nn-steps", type=int, default=3000)
     ap.add_argument("--workload", default="linear_2d_128",
-                    choices=["linear_2d_128", "batched", "nonlinear", "hbm"])
+                    choices=["linear_2d_128", "batched", "nonlinear", "hbm", "study"])
     ap.add_argument("--nl-steps", type=int, default=20,
                     help="implicit steps per slice timed in --workload nonlinear")
     ap.add_argument("--profile-fine", action="store_true",
@@ -319,6 +335,9 @@ def main():
         return
     if args.workload == "hbm":
         print(json.dumps(bench_hbm(args)))
+        return
+    if args.workload == "study":
+        print(json.dumps(bench_study(args)))
         return
     if args.profile_fine:
         # one fine-sweep launch of the workload plus a plain 1 GiB device copy

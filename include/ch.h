@@ -265,6 +265,19 @@ ch_status ch_check_status(ch_ctx* ctx, const ch_pr_state* st, int32_t* bits, ch_
 ch_status ch_set_wait_limit(ch_ctx* ctx, double group_seconds, double pipe_seconds,
                             ch_stream stream);
 
+/* Constants of the convergence theorems for the linear pairings (Section 3,
+ * Theorems 3.7, 3.9, 3.11): with diag(u^2) ~ I the fine and coarse steps
+ * become P_i = (I - i tau D_h + eps^2 tau D_h^2)^{-1} (I - i tau D_h), i = 1
+ * for scheme (2.4) and i = 2 for (2.5); alpha = ||P_{J,i_fine} - P_{i_coarse}||,
+ * beta = ||P_{i_coarse}|| (2-norms), where the fine operator is J steps of
+ * dT/J and the coarse one m_coarse steps of dT/m_coarse.  The Parareal error
+ * then obeys max_n ||E_n^k|| <= alpha^k min{((1 - beta^{N-1})/(1 - beta))^k,
+ * binom(N-1, k)} max_n ||E_n^0||.  Host-only; dim 1 or 2, n interior points
+ * per dimension. */
+ch_status ch_linear_bound(int32_t dim, int32_t n, double eps, double dT, int32_t J,
+                          int32_t m_coarse, double i_fine, double i_coarse, double* alpha,
+                          double* beta);
+
 /* Discrete energy (Section 1, (1.2)) of `count` states of instance `inst`:
  * E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u).  E_out is
  * device memory of `count` doubles. */

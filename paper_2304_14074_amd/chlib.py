@@ -29,7 +29,7 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
            "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups",
            "ch_parareal_run", "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
-           "ch_nn_forward_static")
+           "ch_nn_forward_static", "ch_linear_bound")
 
 
 class ChProblem(ctypes.Structure):
@@ -110,11 +110,15 @@ def load() -> ctypes.CDLL:
     lib.ch_iteration_count.argtypes = [vp, ctypes.POINTER(ChPrState), vp]
     lib.ch_check_status.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.POINTER(i32), vp]
     lib.ch_set_wait_limit.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.ch_linear_bound.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, i32, i32,
+                                    ctypes.c_double, ctypes.c_double, dp, dp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_forward_static", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
                  "ch_nn_bind", "ch_set_coarse_kind", "ch_parareal_graph_create", "ch_graph_launch",
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
                  "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run",
-                 "ch_slice_distance", "ch_check_status", "ch_set_wait_limit"):
+                 "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
+                 "ch_linear_bound"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -320,6 +324,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def ch_linear_bound(dim, n, eps, dT, J, i_fine, i_coarse, m_coarse=1):
+    """(alpha, beta) of the convergence theorems for linear pairings."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    st = load().ch_linear_bound(dim, n, eps, dT, J, m_coarse, i_fine, i_coarse, ctypes.byref(a),
+                                ctypes.byref(b))
+    if st != CH_OK:
+        raise CHError(f"ch_linear_bound: {load().ch_status_str(st).decode()}", st)
+    return a.value, b.value
 
 
 # ------------------------------------------------ learned coarse propagator

@@ -1005,6 +1005,35 @@ ch_status ch_set_wait_limit(ch_ctx* c, double group_seconds, double pipe_seconds
   return hip_check(c, hipStreamSynchronize(s), "limit sync");
 }
 
+ch_status ch_linear_bound(int32_t dim, int32_t n, double eps, double dT, int32_t J,
+                          int32_t m_coarse, double i_fine, double i_coarse, double* alpha,
+                          double* beta) {
+  if ((dim != 1 && dim != 2) || n < 1 || !(eps > 0) || !(dT > 0) || J < 1 || m_coarse < 1 ||
+      !alpha || !beta)
+    return CH_ERR_ARG;
+  // symbol of (I - i tau D + eps^2 tau D^2)^{-1} (I - i tau D) on the sine
+  // mode with D_h eigenvalue L (D_h symmetric: the 2-norm of a polynomial in
+  // it is the largest modulus over its spectrum)
+  auto g = [&](double L, double tau, double i) {
+    return (1.0 - i * tau * L) / (1.0 - i * tau * L + eps * eps * tau * L * L);
+  };
+  std::vector<double> lam(n);
+  for (int k = 0; k < n; ++k) lam[k] = lap_eig(k + 1, n);
+  double a = 0.0, b = 0.0;
+  const int nq = dim == 2 ? n : 1;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < nq; ++q) {
+      const double L = lam[p] + (dim == 2 ? lam[q] : 0.0);
+      const double gc = std::pow(g(L, dT / m_coarse, i_coarse), m_coarse);
+      const double gf = std::pow(g(L, dT / J, i_fine), J);
+      a = std::max(a, std::fabs(gf - gc));
+      b = std::max(b, std::fabs(gc));
+    }
+  *alpha = a;
+  *beta = b;
+  return CH_OK;
+}
+
 int64_t ch_nn_param_count(void) { return chk::nn_param_count(); }
 
 ch_status ch_nn_layer(int32_t layer, int32_t* c_in, int32_t* c_out, int32_t* k, int32_t* stride,

@@ -11,7 +11,8 @@ correct oracle routes of the same run (different rounding).
   c3_slice0_fine.npz -- the 2D 256x256 implicit workload (eps = 0.015,
       u0 = 0.25 + 0.05 N(0,1) seed 0, dt = 1e-5): F(u0) = all J = 3125 steps of
       slice 0, scheme (2.3) by Newton (stop 1e-10) with PCG solves, sine
-      transforms as dense products; floor against the FFT-computed transforms.
+      transforms as dense products; floor: the largest distance between it and
+      two more routes (FFT transforms; another preconditioner shift).
 
 Run:  python tests/golden/make_goldens.py [c2|c3]   (minutes to an hour)
 """
@@ -66,21 +67,28 @@ def make_c2():
 
 
 def make_c3():
+    """Three routes of the slice: PCG with dense transforms, with FFT
+    transforms, and with dense transforms and another preconditioner shift
+    (other CG iterates); the floor is the largest pairwise distance."""
     p = workloads.nonlinear_2d_256()
     u0 = workloads.nonlinear_2d_256_u0(0)
+    routes = {"dense": dict(transform="dense"), "fft": dict(transform="fft"),
+              "dense_shift1": dict(transform="dense", s_pc=1.0)}
     res = {}
-    for tr in ("dense", "fft"):
+    for name, kw in routes.items():
         u = u0.copy()
         t0 = time.time()
         for j in range(p.j_fine):
             u = schemes.step_newton_pcg(u, p.dt, p.eps, p.nl_variant, p.newton_tol, p.newton_max,
-                                        transform=tr)
+                                        **kw)
             if j % 500 == 0:
-                print(f"c3 {tr}: step {j} ({time.time() - t0:.0f} s)", flush=True)
-        res[tr] = u
-    np.savez(os.path.join(HERE, "c3_slice0_fine.npz"), F=res["dense"],
-             floor=rel(res["fft"], res["dense"]))
-    print("c3 floor", rel(res["fft"], res["dense"]))
+                print(f"c3 {name}: step {j} ({time.time() - t0:.0f} s)", flush=True)
+        res[name] = u
+    pairs = (("fft", "dense"), ("dense_shift1", "dense"), ("dense_shift1", "fft"))
+    d = [rel(res[a], res[b]) for a, b in pairs]
+    print("c3 route distances " + " ".join(f"{a}-{b} {x:.2e}" for (a, b), x in zip(pairs, d)))
+    np.savez(os.path.join(HERE, "c3_slice0_fine.npz"), F=res["dense"], floor=max(d),
+             routes=np.array(d))
 
 
 if __name__ == "__main__":

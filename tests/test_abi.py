@@ -210,3 +210,21 @@ def test_pipelined_run_coverage_host_only():
     assert lib.ch_parareal_run(h, ctypes.byref(st_struct), 0.0, -1, 0, None) == chlib.CH_ERR_ARG
     assert lib.ch_parareal_run(h, ctypes.byref(st_struct), 0.0, 3, 2, None) == chlib.CH_ERR_ARG
     lib.ch_destroy(h)
+
+
+@pytest.mark.parametrize("dim,n,i_f,i_c,m", [(1, 15, 1.0, 1.0, 1), (1, 63, 2.0, 1.0, 1),
+                                            (2, 6, 2.0, 2.0, 1), (1, 20, 2.0, 1.0, 3)])
+def test_linear_bound_constants_match_the_oracle(dim, n, i_f, i_c, m):
+    # host-only: alpha and beta of the convergence theorems against the
+    # oracle's dense matrix norms of the linearised propagators
+    import numpy as np
+    from oracle import linear_model as lm
+    from paper_2304_14074_amd import chlib
+    dT, J, eps = 0.05, 11, 0.0725
+    a, b = chlib.ch_linear_bound(dim, n, eps, dT, J, i_f, i_c, m)
+    PJ = lm.propagator_matrix(n, dim, dT / J, eps, i_f, J)
+    P = lm.propagator_matrix(n, dim, dT / m, eps, i_c, m)
+    # the oracle's dense solves carry the condition number of
+    # I - i dT D + eps^2 dT D^2 (up to ~1e5 here) times the unit roundoff
+    assert abs(a - np.linalg.norm(PJ - P, 2)) <= 1e-10 * a
+    assert abs(b - np.linalg.norm(P, 2)) <= 1e-10 * b

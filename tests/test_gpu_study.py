@@ -1,0 +1,28 @@
+"""The parameter-study harness of Section 4 on the GPU path: a PA-I run
+from a smooth profile at the paper's parameters (eps = 0.0725, h = 1/64,
+N = 20, J = 200, T = 1) reaches the 1e-6 stop with errors inside the bound of
+its convergence theorem, and a PA-II run at small eps, where its coarse
+step is unstable, is reported as diverged instead of failing.  The paper
+states no initial data: parity-unpinned against its figures."""
+import math
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_pa1_within_theorem_bound():
+    from paper_2304_14074_amd import study
+    r = study.run_case(study.Case("PA-I", amp=0.9, seed=None))
+    print({k: r[k] for k in ("iterations_to_1e-6", "alpha", "beta")}, flush=True)
+    assert not r["diverged"] and r["iterations_to_1e-6"] is not None
+    assert r["within_bound"]
+    assert 0 < r["alpha"] < 1 and 0 < r["beta"] < 1          # Lemma 3.1
+    assert r["errors"][-1] < 1e-6 <= r["errors"][-2]
+
+
+def test_pa2_small_eps_reported_as_diverged():
+    from paper_2304_14074_amd import study
+    r = study.run_case(study.Case("PA-II", N=50, eps=0.03))
+    assert r["diverged"] and r["iterations_to_1e-6"] is None
+    assert r["errors"][0] is not None and math.isfinite(r["errors"][0])

@@ -274,3 +274,12 @@ def test_pa1_fine_propagator_closed_form():
     rho = 1.0 / (1 + p.eps ** 2 * p.dt * (lam[3] + lam[0]) ** 2)
     v = propagators.fine(p, u)
     assert np.max(np.abs(v - rho ** p.j_fine * u)) <= 1e-13 * np.max(np.abs(u))
+
+
+def test_harness_bound_factor_equals_the_theorem_factor():
+    # the study harness's bound factor against the oracle's, incl. the
+    # binomial branch of the minimum
+    from paper_2304_14074_amd import study
+    for a, b, N, k in ((0.6, 0.98, 20, 3), (0.3, 0.5, 10, 7), (0.9, 0.999, 50, 1)):
+        assert abs(study.bound_factor(a, b, N, k) - lm.bound_factor(a, b, N, k)) <= \
+            1e-14 * lm.bound_factor(a, b, N, k)
