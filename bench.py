@@ -216,6 +216,51 @@ def bench_hbm(args):
                       "energy_frac_of_hbm_peak": gbs_e / HBM_PEAK_GBS}}
 
 
+def batched_fine_sweep() -> dict:
+    """One fine sweep (J = 1563 steps of every slice) of the 256-instance
+    batch in one ch_fine_propagate call, timed with HIP events on the stream
+    it runs on; a masked call (one slice per grid-size class) warms up first.
+    Inputs: 0.05 * Uniform(-1, 1) per slice (seeds 5000 + instance)."""
+    import torch
+    import workloads
+    from paper_2304_14074_amd import chlib
+    probs = workloads.batched_instances(256, 4)
+    ctx = chlib.Context(probs)
+    Us = torch.empty(ctx.slice_total, dtype=torch.float64, device="cuda")
+    for i, p in enumerate(probs):
+        so = ctx.layout(i)[2]
+        rng = np.random.default_rng(5000 + i)
+        Us[so:so + p.n_slices * p.n * p.n] = torch.from_numpy(
+            0.05 * rng.uniform(-1, 1, p.n_slices * p.n * p.n)).cuda()
+    Fs = torch.empty_like(Us)
+    mask = torch.zeros(sum(p.n_slices for p in probs), dtype=torch.uint8)
+    seen, base = set(), 0
+    for p in probs:
+        if p.n not in seen:
+            mask[base] = 1
+            seen.add(p.n)
+        base += p.n_slices
+    stream = torch.cuda.current_stream()
+    ctx.ch_fine_propagate(Us, Fs, mask.cuda())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.ch_fine_propagate(Us, Fs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.ch_check_status()
+    ms = e0.elapsed_time(e1)
+    pts = sum(p.n_slices * p.j_fine * p.n * p.n for p in probs)
+    flops = sum(p.n_slices * p.j_fine * p.n * p.n * fine_flops_per_point_step(p.n) for p in probs)
+    tf = flops / (ms / 1e3) / 1e12
+    return {"workload": "256 instances, n in {64,128,256}, N in {32,64,128}, J=1563, FP64 "
+                        "linear fine step, one ch_fine_propagate over all 20k slices",
+            "slices": sum(p.n_slices for p in probs), "ms": ms,
+            "point_steps_per_s": pts / (ms / 1e3), "tflops": tf,
+            "frac_fp64_peak": tf / FP64_PEAK_TFLOPS,
+            "finite": bool(torch.isfinite(Fs).all().item())}
+
+
 def bench_batched(args):
     """256 independent instances of uneven size (n in {64, 128, 256}, N in
     {32, 64, 128}, eps ~ U(0.01, 0.04), J = 1563), FP64 linear fine step,
@@ -312,6 +357,8 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance run")
     ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 fine sweep")
     ap.add_argument("--no-neural", action="store_true", help="skip the learned coarse propagator leg")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the fine sweep of the 256-instance batch")
     ap.add_argument("--nn-traj", type=int, default=256)
     ap.add_argument("--nn-steps", type=int, default=3000)
     ap.add_argument("--workload", default="linear_2d_128",
@@ -469,6 +516,8 @@ def main():
                       "split_bf16_point_steps_per_s": point_steps / (sms / 1e3),
                       "split_bf16_max_slice_rel_err_vs_fp64": rel,
                       "split_bf16_mfma_tflops": bflops / (sms / 1e3) / 1e12})
+    if not args.no_batched:
+        extra["batched_fine_sweep"] = batched_fine_sweep()
     if not args.no_neural:
         # learned coarse propagator: trajectories from the fine propagator
         # (seeds 10000+), training with the library's kernels, then Parareal

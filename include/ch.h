@@ -231,10 +231,10 @@ ch_status ch_chain_variant(ch_ctx* ctx, int32_t n, int32_t* groups, int32_t set)
 
 /* hipGraph of one Parareal iteration (after the prediction): captured on
  * the non-default `stream`, replayable with ch_graph_launch; each replay
- * performs the next iteration (the iteration index lives in device memory).
- * After replays, ch_iteration_count refreshes st->k from the device.  Not
- * available while an instance uses the learned coarse propagator (its coarse
- * sweep is driven from the host).  The caller owns the handle. */
+ * performs the next iteration (the iteration index, the judge of a learned
+ * propagator and its fallback live in device memory).  After replays,
+ * ch_iteration_count refreshes st->k from the device.  The caller owns the
+ * handle. */
 ch_status ch_parareal_graph_create(ch_ctx* ctx, ch_pr_state* st, double tol, ch_stream stream,
                                    void** graph_exec);
 ch_status ch_graph_launch(void* graph_exec, ch_stream stream);
@@ -329,10 +329,29 @@ ch_status ch_nn_adam(float* w_master, uint16_t* w_bf16, float* m, float* v, cons
 ch_status ch_nn_to_bf16(const float* w_master, uint16_t* w_bf16, int64_t count, ch_stream stream);
 /* weights used by instances whose coarse kind is CH_COARSE_NEURAL */
 ch_status ch_nn_bind(ch_ctx* ctx, const uint16_t* w_bf16);
-/* switch the coarse propagator of one instance (e.g. the fallback from the
- * learned to the plain propagator); the context must have been created with
- * a learned-propagator instance to switch one to it */
+/* switch the coarse propagator of one instance; the context must have been
+ * created with a learned-propagator instance to switch one to it.  (The
+ * fallback of a Parareal run needs no call: see ch_judge_read.) */
 ch_status ch_set_coarse_kind(ch_ctx* ctx, int32_t inst, int32_t kind, ch_stream stream);
+
+/* The plain coarse propagator (2.4) is the learned one's fallback and judge,
+ * inside ch_parareal_iterate (and its graph), on the device.  Before each
+ * correction of an instance still on the learned propagator it computes
+ * G_plain(U_n^k) for every slice and the ratio r^k = mean over the slices
+ * n >= k with ||G_plain(U_n^k) - F_n||_h > 0 of ||G(U_n^k) - F_n||_h /
+ * ||G_plain(U_n^k) - F_n||_h (G(U_n^k) = G_old_n).  After the correction the
+ * instance falls back to the plain propagator for the rest of the run when
+ * the update norm is not finite, or not smaller than the previous one, or r
+ * exceeded 1 in this and the previous iteration (unless the norm is already
+ * below tol); G_old is then recomputed with the plain propagator at the new
+ * iterate.  A new run (the prediction) starts on the learned propagator
+ * again.  This call reads, synchronously, instance inst's ratios (ratios:
+ * host memory of N doubles, NaN for iterations not judged; may be NULL),
+ * the number of corrections done when it fell back (-1: it has not), and
+ * whether it still uses the learned propagator.  CH_ERR_ARG for an
+ * instance created with another coarse propagator. */
+ch_status ch_judge_read(ch_ctx* ctx, int32_t inst, double* ratios, int32_t* fallback_at,
+                        int32_t* learned_now, ch_stream stream);
 
 const char* ch_status_str(ch_status s);
 const char* ch_last_error(const ch_ctx* ctx);

@@ -29,7 +29,7 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
            "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups",
            "ch_parareal_run", "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
-           "ch_nn_forward_static", "ch_linear_bound")
+           "ch_nn_forward_static", "ch_linear_bound", "ch_judge_read")
 
 
 class ChProblem(ctypes.Structure):
@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
     lib.ch_check_status.argtypes = [vp, ctypes.POINTER(ChPrState), ctypes.POINTER(i32), vp]
     lib.ch_set_wait_limit.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
     dp = ctypes.POINTER(ctypes.c_double)
+    lib.ch_judge_read.argtypes = [vp, i32, dp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
     lib.ch_linear_bound.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, i32, i32,
                                     ctypes.c_double, ctypes.c_double, dp, dp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_forward_static", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
@@ -118,7 +119,7 @@ def load() -> ctypes.CDLL:
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
                  "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run",
                  "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
-                 "ch_linear_bound"):
+                 "ch_linear_bound", "ch_judge_read"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -253,6 +254,16 @@ class Context:
         c = ctypes.byref(self._state_struct(state)) if state is not None else None
         self._check(self.lib.ch_check_status(self.h, c, bits, _stream(stream)))
         return list(bits)
+
+    def ch_judge_read(self, inst=0, stream=None):
+        """(ratios per iteration (NaN: not judged), fallback_at or None,
+        learned propagator still in use) of an instance with the learned G."""
+        N = self.problems[inst].n_slices
+        r = (ctypes.c_double * N)()
+        fb, now = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.ch_judge_read(self.h, inst, r, ctypes.byref(fb), ctypes.byref(now),
+                                           _stream(stream)))
+        return list(r), (fb.value if fb.value >= 0 else None), bool(now.value)
 
     def ch_set_wait_limit(self, group_seconds=0.2, pipe_seconds=10.0, stream=None):
         self._check(self.lib.ch_set_wait_limit(self.h, float(group_seconds), float(pipe_seconds),

@@ -53,6 +53,15 @@ struct ch_ctx {
   std::vector<Block> rsig_fine_blk, rsig_stab_blk, tab_blk, work_blk;
   // learned coarse propagator
   Block nn_blk, nn_out_blk, nn_part_blk;
+  // its judge (instances created with the learned propagator): the instance
+  // list (host-initialised), JudgeDev records, live and refresh flags (one
+  // per instance), ratios (one per iteration), the plain propagator's
+  // results and the two per-slice distances
+  std::vector<int32_t> judge_insts;
+  std::vector<int32_t> judge_enabled;
+  int judge_rstride = 0;
+  Block jinsts_blk, jdev_blk, jlive_blk, jrefresh_blk, jratio_blk, jgp_blk, jdist_blk, jgate_blk;
+  bool capturing = false;           // a graph of one iteration is being recorded
   // pipelined iterations (one 2D n = 128 instance): fine inputs (2 N n^2),
   // odd-iteration fine results (N n^2), hand-off counters
   bool pipe = false;
@@ -240,6 +249,16 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   c->active_blk = take(sizeof(int32_t) * n_inst);
   c->status_blk = take(sizeof(int32_t) * n_inst);
   c->k_blk = take(sizeof(int32_t));
+  for (int i = 0; i < n_inst; ++i)
+    if (probs[i].coarse_kind == CH_COARSE_NEURAL) {
+      c->judge_insts.push_back(i);
+      c->judge_enabled.push_back(1);
+      c->judge_rstride = std::max(c->judge_rstride, probs[i].n_slices);
+    }
+  if (!c->judge_insts.empty()) {
+    c->jinsts_blk = take(sizeof(int32_t) * c->judge_insts.size());
+    c->jdev_blk = take(sizeof(chk::JudgeDev) * c->judge_insts.size());
+  }
   for (auto& cp : c->classes) {
     cp.items_blk = take(sizeof(WorkItem) * cp.items.size());
     cp.insts_blk = take(sizeof(int32_t) * cp.insts.size());
@@ -311,6 +330,14 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       c->nn_blk = take(fl * sizeof(float));
       c->nn_out_blk = take(outd * sizeof(double));
       c->nn_part_blk = take(partd * sizeof(double));
+      int64_t n_slices_all = 0;
+      for (int i = 0; i < n_inst; ++i) n_slices_all += probs[i].n_slices;
+      c->jlive_blk = take(sizeof(int32_t) * n_inst);
+      c->jrefresh_blk = take(sizeof(int32_t) * n_inst);
+      c->jratio_blk = take(sizeof(double) * c->judge_insts.size() * (size_t)c->judge_rstride);
+      c->jgp_blk = take(sizeof(double) * (size_t)c->slice_total);
+      c->jdist_blk = take(sizeof(double) * 2 * (size_t)n_slices_all);
+      c->jgate_blk = take(sizeof(int32_t) * (size_t)n_slices_all);
     }
   }
   c->ws_bytes = off;
@@ -383,6 +410,16 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
     fill(c->rsig_stab_blk[i], d.dT / p.m_coarse);
   }
   memcpy(img.data() + c->inst_blk.off, c->inst.data(), sizeof(InstDev) * n_inst);
+  if (!c->judge_insts.empty()) {
+    memcpy(img.data() + c->jinsts_blk.off, c->judge_insts.data(),
+           sizeof(int32_t) * c->judge_insts.size());
+    chk::JudgeDev* jd = (chk::JudgeDev*)(img.data() + c->jdev_blk.off);
+    for (size_t t = 0; t < c->judge_insts.size(); ++t) {
+      jd[t].delta_prev = 0.0;
+      jd[t].fallback_at = -1;
+      jd[t].enabled = 1;
+    }
+  }
   for (auto& cp : c->classes) {
     memcpy(img.data() + cp.items_blk.off, cp.items.data(), sizeof(WorkItem) * cp.items.size());
     memcpy(img.data() + cp.insts_blk.off, cp.insts.data(), sizeof(int32_t) * cp.insts.size());
@@ -605,11 +642,26 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     if (r != CH_OK) return r;
   }
   hipStream_t s = s0;
-  // learned coarse propagator: host-driven sequence of network passes
+  // learned coarse propagator: a sequence of network passes per instance,
+  // each gated on the device by the instance's live flag (it still uses the
+  // learned propagator, and is active), so that a fallback taken on the
+  // device switches them off also inside a captured graph
+  int32_t* jlive = nullptr;
+  if (!c->judge_insts.empty()) {
+    jlive = (int32_t*)(c->ws + c->jlive_blk.off);
+    ch_status r = hip_check(
+        c, chk::launch_judge(1, (const int32_t*)(c->ws + c->jinsts_blk.off),
+                             (int)c->judge_insts.size(), (InstDev*)(c->ws + c->inst_blk.off),
+                             active, jlive, nullptr, nullptr, 0, nullptr, nullptr, nullptr,
+                             nullptr, 0.0, nullptr, s),
+        "live flags");
+    if (r != CH_OK) return r;
+  }
   for (int i = 0; i < (int)c->probs.size(); ++i) {
     const InstDev& d = c->inst[i];
     if (d.coarse_kind != CH_COARSE_NEURAL) continue;
     if (!c->nn_w) return fail(c, CH_ERR_STATE, "instance %d: no surrogate weights bound", i);
+    const int32_t* live = jlive + i;
     const int n = d.n, N = d.n_slices;
     const int64_t P = (int64_t)n * n;
     float* nws = (float*)(c->ws + c->nn_blk.off);
@@ -619,32 +671,39 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     hipError_t e = hipSuccess;
     if (mode == 0) {
       const chk::NNPlan pl = chk::nn_plan(N, n);
-      e = chk::nn_forward(c->nn_w, U_in + d.off_slices, N, n, nws, pl, g, s);
-      if (e == hipSuccess) e = chk::masked_copy(G_out + d.off_slices, g, mask, P, N, d.slice_base, s);
+      e = chk::nn_forward(c->nn_w, U_in + d.off_slices, N, n, nws, pl, g, s, live);
+      if (e == hipSuccess)
+        e = chk::masked_copy(G_out + d.off_slices, g, mask, P, N, d.slice_base, s, live);
     } else {
       const chk::NNPlan pl = chk::nn_plan(1, n);
-      const int32_t* act = active + i;
+      const int32_t* act = live;
       double* Ui = st->U + d.off_iter;
       const double* Fi = st->F + d.off_slices;
       double* Gi = st->G_old + d.off_slices;
       if (mode == 1) {
         for (int sl = 0; sl < N && e == hipSuccess; ++sl) {
-          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s);
+          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, act);
           if (e == hipSuccess) e = chk::pr_correct(Ui + (sl + 1) * P, nullptr, Gi + sl * P, g, P, part, 1, act, s);
         }
-      } else if (k >= N) {
-        e = chk::pr_delta(part, nb, 0, d.h * d.h, st->delta + i, st->status + i, act, s);
       } else {
-        // U_{k+1} = F_k + (G(U_k) - G_old_k), G(U_k) == G_old_k
-        e = chk::pr_correct(Ui + (k + 1) * P, Fi + k * P, Gi + k * P, Gi + k * P, P, part, 0, act, s);
-        for (int sl = k + 1; sl < N && e == hipSuccess; ++sl) {
-          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s);
+        // the correction sweep from slice k + 1, k = the device iteration
+        // counter: U_{k+1} = F_k (its G terms cancel), then for sl > k
+        // U_{sl+1} = F_sl + (G(U_sl) - G_old_sl); every launch is gated on
+        // the device (sl > k and the live flag), so a captured sweep serves
+        // every iteration.  Eagerly, the slices up to the host's k are not
+        // launched at all.  Row sl of part holds the change of U_{sl+1}.
+        int32_t* gates = (int32_t*)(c->ws + c->jgate_blk.off) + d.slice_base;
+        e = chk::slice_gates(act, kdev, N, gates, s);
+        if (e == hipSuccess) e = chk::pr_first(Ui, Fi, P, N, part, nb, kdev, act, s);
+        const int first = c->capturing ? 1 : k + 1;
+        for (int sl = first; sl < N && e == hipSuccess; ++sl) {
+          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, gates + sl);
           if (e == hipSuccess)
             e = chk::pr_correct(Ui + (sl + 1) * P, Fi + sl * P, Gi + sl * P, g, P,
-                                part + (int64_t)(sl - k) * nb, 0, act, s);
+                                part + (int64_t)sl * nb, 0, gates + sl, s);
         }
         if (e == hipSuccess)
-          e = chk::pr_delta(part, nb, N - k, d.h * d.h, st->delta + i, st->status + i, act, s);
+          e = chk::pr_delta(part, nb, N, d.h * d.h, st->delta + i, st->status + i, act, s, kdev);
       }
     }
     ch_status r = hip_check(c, e, "learned coarse propagator");
@@ -675,6 +734,78 @@ static ch_status pr_check(ch_ctx* c, ch_pr_state* st) {
   return CH_OK;
 }
 
+// The judge of the learned propagator, every step on the device (no host
+// decision, so a captured iteration replays it):
+//  what = 0 (new run): the learned propagator again for every instance
+//    created with it (unless switched on the host), no fallback yet;
+//  what = 1 (before the correction): the plain propagator (2.4) at the
+//    current iterate, G_plain(U_n^k), per-slice distances of it and of
+//    G_old_n = G(U_n^k) from F_n, and their ratio (k_judge_ratio);
+//  what = 2 (after the correction): the fallback decision (k_judge_decide)
+//    and, for an instance that fell back, G_old_n = G_plain(U_n^{k+1}).
+static ch_status judge_step(ch_ctx* c, int what, ch_pr_state* st, double tol, hipStream_t s) {
+  if (c->judge_insts.empty()) return CH_OK;
+  const int32_t* jl = (const int32_t*)(c->ws + c->jinsts_blk.off);
+  const int nj = (int)c->judge_insts.size();
+  InstDev* inst = (InstDev*)(c->ws + c->inst_blk.off);
+  int32_t* active = (int32_t*)(c->ws + c->active_blk.off);
+  int32_t* kdev = (int32_t*)(c->ws + c->k_blk.off);
+  int32_t* live = (int32_t*)(c->ws + c->jlive_blk.off);
+  int32_t* refresh = (int32_t*)(c->ws + c->jrefresh_blk.off);
+  chk::JudgeDev* J = (chk::JudgeDev*)(c->ws + c->jdev_blk.off);
+  double* ratios = (double*)(c->ws + c->jratio_blk.off);
+  double* gp = (double*)(c->ws + c->jgp_blk.off);
+  int64_t n_slices_all = 0;
+  for (const auto& p : c->probs) n_slices_all += p.n_slices;
+  double* d0 = (double*)(c->ws + c->jdist_blk.off);
+  double* d1 = d0 + n_slices_all;
+  const int rs = c->judge_rstride;
+  auto judge = [&](int k, const int32_t* act) {
+    return hip_check(c, chk::launch_judge(k, jl, nj, inst, act, live, J, ratios, rs, refresh, d0,
+                                          d1, st->delta, tol, kdev, s), "judge");
+  };
+  // the plain propagator (2.4) on every slice of the gated instances, inputs
+  // from the iterate layout (mode 3), in each class holding such instances
+  auto plain_all = [&](double* out, const int32_t* gate) {
+    for (auto& cp : c->classes) {
+      bool has = false;
+      for (int32_t i : cp.insts) has = has || c->probs[i].coarse_kind == CH_COARSE_NEURAL;
+      if (!has) continue;
+      ch_status r = hip_check(
+          c, chk::launch_coarse_2d(cp.n, 3, (const int32_t*)(c->ws + cp.insts_blk.off),
+                                   (int)cp.insts.size(), (const WorkItem*)(c->ws + cp.items_blk.off),
+                                   (int)cp.items.size(), inst, class_sine(c, cp), st->U, out,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                                   nullptr, s, gate),
+          "plain propagator");
+      if (r != CH_OK) return r;
+    }
+    return CH_OK;
+  };
+  ch_status r = CH_OK;
+  if (what == 0) return judge(0, nullptr);
+  if (what == 1) {
+    r = judge(1, active);
+    if (r == CH_OK) r = plain_all(gp, live);
+    for (auto& cp : c->classes) {
+      bool has = false;
+      for (int32_t i : cp.insts) has = has || c->probs[i].coarse_kind == CH_COARSE_NEURAL;
+      if (!has || r != CH_OK) continue;
+      const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
+      r = hip_check(c, chk::launch_slice_dist(items, (int)cp.items.size(), inst, st->G_old, st->F,
+                                              d0, s), "judge distances");
+      if (r == CH_OK)
+        r = hip_check(c, chk::launch_slice_dist(items, (int)cp.items.size(), inst, gp, st->F, d1,
+                                                s), "judge distances");
+    }
+    if (r == CH_OK) r = judge(2, active);
+    return r;
+  }
+  r = judge(3, active);
+  if (r == CH_OK) r = plain_all(st->G_old, refresh);
+  return r;
+}
+
 // One step of the iteration.  The iteration index the kernels use lives in
 // device memory (k_blk) and is advanced by a kernel, so a captured step can
 // be replayed for successive iterations; st->k mirrors it on the host
@@ -693,6 +824,7 @@ static ch_status pr_step(ch_ctx* c, ch_pr_state* st, double tol, hipStream_t s, 
     if (r == CH_OK) r = clear_ws_status(c, s);
     if (r != CH_OK) return r;
     r = hip_check(c, chk::launch_flag_active(st->delta, active, n_inst, tol, 1, kdev, s), "flags");
+    if (r == CH_OK) r = judge_step(c, 0, st, tol, s);
     if (r != CH_OK) return r;
     r = coarse_all(c, 1, nullptr, nullptr, nullptr, st, 0, s);
     if (r == CH_OK)
@@ -711,7 +843,9 @@ static ch_status pr_step(ch_ctx* c, ch_pr_state* st, double tol, hipStream_t s, 
     if (r == CH_OK) r = fine_all(c, st->U, st->F, nullptr, active, kdev, 1, s);
     if (r != CH_OK) return r;
   }
-  r = coarse_all(c, 2, nullptr, nullptr, nullptr, st, st->k, s);
+  r = judge_step(c, 1, st, tol, s);
+  if (r == CH_OK) r = coarse_all(c, 2, nullptr, nullptr, nullptr, st, st->k, s);
+  if (r == CH_OK) r = judge_step(c, 2, st, tol, s);
   if (r == CH_OK)
     r = hip_check(c, chk::launch_status_merge(st->status, ws_status(c), n_inst, s), "status");
   if (r != CH_OK) return r;
@@ -902,14 +1036,13 @@ ch_status ch_parareal_graph_create(ch_ctx* c, ch_pr_state* st, double tol, ch_st
   if (!graph_exec) return fail(c, CH_ERR_ARG, "null graph handle");
   if (!st->predicted) return fail(c, CH_ERR_STATE, "form the coarse prediction first");
   if (!stream) return fail(c, CH_ERR_ARG, "capture needs a non-default stream");
-  for (const auto& d : c->inst)
-    if (d.coarse_kind == CH_COARSE_NEURAL)
-      return fail(c, CH_ERR_UNSUPPORTED, "the learned coarse sweep is host-driven: no capture");
   hipStream_t s = (hipStream_t)stream;
   hipGraph_t g = nullptr;
   r = hip_check(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
   if (r != CH_OK) return r;
+  c->capturing = true;
   ch_status inner = pr_step(c, st, tol, s, 1, false);
+  c->capturing = false;
   r = hip_check(c, hipStreamEndCapture(s, &g), "end capture");
   if (inner != CH_OK) return inner;
   if (r != CH_OK) return r;
@@ -1120,10 +1253,50 @@ ch_status ch_set_coarse_kind(ch_ctx* c, int32_t inst, int32_t kind, ch_stream st
   if (kind == CH_COARSE_NEURAL && !c->nn_planned)
     return fail(c, CH_ERR_STATE, "context was created without a learned-propagator workspace");
   c->inst[inst].coarse_kind = kind;
+  for (size_t t = 0; t < c->judge_insts.size(); ++t)
+    if (c->judge_insts[t] == inst) {
+      // the judge restores the learned propagator at a new run only while
+      // the host keeps the instance on it
+      c->judge_enabled[t] = kind == CH_COARSE_NEURAL;
+      chk::JudgeDev* jd = (chk::JudgeDev*)(c->ws + c->jdev_blk.off) + t;
+      r = hip_check(c, hipMemcpyAsync(&jd->enabled, &c->judge_enabled[t], sizeof(int32_t),
+                                      hipMemcpyHostToDevice, (hipStream_t)stream),
+                    "judge flag update");
+      if (r != CH_OK) return r;
+    }
   InstDev* dev = (InstDev*)(c->ws + c->inst_blk.off) + inst;
   return hip_check(c, hipMemcpyAsync(&dev->coarse_kind, &c->inst[inst].coarse_kind, sizeof(int32_t),
                                      hipMemcpyHostToDevice, (hipStream_t)stream),
                    "coarse kind update");
+}
+
+ch_status ch_judge_read(ch_ctx* c, int32_t inst, double* ratios, int32_t* fallback_at,
+                        int32_t* learned_now, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (inst < 0 || inst >= (int32_t)c->probs.size()) return fail(c, CH_ERR_ARG, "instance index");
+  int t = -1;
+  for (size_t q = 0; q < c->judge_insts.size(); ++q)
+    if (c->judge_insts[q] == inst) t = (int)q;
+  if (t < 0) return fail(c, CH_ERR_ARG, "instance %d was not created with the learned propagator", inst);
+  hipStream_t s = (hipStream_t)stream;
+  const int N = c->probs[inst].n_slices;
+  chk::JudgeDev jd;
+  int32_t kind = 0;
+  r = hip_check(c, hipMemcpyAsync(&jd, (chk::JudgeDev*)(c->ws + c->jdev_blk.off) + t, sizeof jd,
+                                  hipMemcpyDeviceToHost, s), "judge read");
+  if (r == CH_OK)
+    r = hip_check(c, hipMemcpyAsync(&kind, &((InstDev*)(c->ws + c->inst_blk.off) + inst)->coarse_kind,
+                                    sizeof kind, hipMemcpyDeviceToHost, s), "judge read");
+  if (r == CH_OK && ratios)
+    r = hip_check(c, hipMemcpyAsync(ratios, (double*)(c->ws + c->jratio_blk.off) +
+                                                (int64_t)t * c->judge_rstride,
+                                    sizeof(double) * N, hipMemcpyDeviceToHost, s), "judge read");
+  if (r == CH_OK) r = hip_check(c, hipStreamSynchronize(s), "judge sync");
+  if (r != CH_OK) return r;
+  if (fallback_at) *fallback_at = jd.fallback_at;
+  if (learned_now) *learned_now = kind == CH_COARSE_NEURAL;
+  return CH_OK;
 }
 
 ch_status ch_slice_distance(ch_ctx* c, const double* A, const double* B, double* out,

@@ -38,6 +38,13 @@ constexpr int WORK_VECS = 7;  // x, r, p, q, minv, u_hat, y_hat (streamed Newton
 
 struct WorkItem { int32_t inst, slice; };
 
+// Device state of the judge of a learned-propagator instance.
+struct JudgeDev {
+  double delta_prev;     // update norm of the previous correction
+  int32_t fallback_at;   // corrections done when it fell back (-1: not yet)
+  int32_t enabled;       // the instance's kind on the host is the learned one
+};
+
 // Launch helpers implemented in ch_kernels.hip; return hipSuccess or an error.
 // Fine sweep.  Work items with slice < *kmin (kmin may be null) or of an
 // inactive instance are skipped; in_iter selects the iterate layout for the
@@ -68,13 +75,16 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
                           double* F_out, const uint8_t* mask, const int32_t* active,
                           const int32_t* kmin, int in_iter, hipStream_t s);
 // mode 0: independent G per masked slice (parallel); 1: prediction chain;
-// 2: correction chain starting at slice k+1 with U_{k+1} = F_k.
+// 2: correction chain starting at slice k+1 with U_{k+1} = F_k; 3: the plain
+// scheme (2.4) on every slice of the instances with gate[inst] != 0, inputs
+// from the iterate layout U_in (U_0..U_{N-1}), outputs in the slice layout.
 hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const WorkItem* items, int n_items, const InstDev* inst,
                             const double* Tsin, const double* U_in,
                             double* G_out, const uint8_t* mask, double* U, const double* F,
                             double* G_old, double* delta, int32_t* status,
-                            const int32_t* active, int k, const int32_t* kdev, hipStream_t s);
+                            const int32_t* active, int k, const int32_t* kdev, hipStream_t s,
+                            const int32_t* gate = nullptr);
 hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
                             const WorkItem* items, int n_items, const InstDev* inst,
                             const double* S, const double* U_in, double* G_out,
@@ -133,6 +143,12 @@ hipError_t launch_slice_dist(const WorkItem* items, int n_items, const InstDev* 
 hipError_t launch_flag_active(const double* delta, int32_t* active, int n_inst, double tol,
                               int first, const int32_t* kdev, hipStream_t s);
 hipError_t launch_counter(int32_t* kdev, int value, int add, hipStream_t s);
+// judge of the learned propagator over the instances insts[0..n): what = 0
+// reset, 1 live flags, 2 ratio of iteration *kdev, 3 fallback decision
+hipError_t launch_judge(int what, const int32_t* insts, int n, InstDev* inst, const int32_t* active,
+                        int32_t* live, JudgeDev* J, double* ratios, int rstride, int32_t* refresh,
+                        const double* d_learned, const double* d_plain, const double* delta,
+                        double tol, const int32_t* kdev, hipStream_t s);
 // p[0..count) = 0 (a fill kernel, safe under stream capture)
 hipError_t launch_zero_i32(int32_t* p, int count, hipStream_t s);
 // dst[i] |= src[i], i < count
@@ -148,8 +164,10 @@ struct NNPlan {   // float offsets inside an NN workspace
 NNPlan nn_plan(int batch, int n);
 int64_t nn_param_count();
 int64_t nn_param_offset(int layer);
+// gate (device, nullable): every kernel of the pass returns at once when
+// *gate == 0 (a graph-captured pass that the device switches off)
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
-                      const NNPlan& p, double* out, hipStream_t s);
+                      const NNPlan& p, double* out, hipStream_t s, const int32_t* gate = nullptr);
 // floats of workspace the forward pass alone uses (x0 and the activations)
 size_t nn_forward_floats(int batch, int n);
 // the allocation-free forward pass: the file-scope device array of
@@ -165,8 +183,13 @@ hipError_t nn_to_bf16(const float* wm, uint16_t* wb, int64_t count, hipStream_t 
 hipError_t pr_correct(double* Un1, const double* Fn, double* Gn, const double* g, int64_t count,
                       double* part, int predict, const int32_t* active, hipStream_t s);
 hipError_t pr_delta(const double* part, int nb, int nslices, double h2, double* delta,
-                    int32_t* status, const int32_t* active, hipStream_t s);
+                    int32_t* status, const int32_t* active, hipStream_t s,
+                    const int32_t* kdev = nullptr);
+hipError_t pr_first(double* Ui, const double* Fi, int64_t P, int nslices, double* part, int nb,
+                    const int32_t* kdev, const int32_t* gate, hipStream_t s);
+hipError_t slice_gates(const int32_t* live, const int32_t* kdev, int nslices, int32_t* gates,
+                       hipStream_t s);
 hipError_t masked_copy(double* dst, const double* src, const uint8_t* mask, int64_t P, int nslices,
-                       int64_t slice_base, hipStream_t s);
+                       int64_t slice_base, hipStream_t s, const int32_t* gate = nullptr);
 
 }  // namespace chk

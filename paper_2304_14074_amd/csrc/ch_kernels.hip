@@ -918,7 +918,8 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
             const double* __restrict__ U_in,
             double* __restrict__ G_out, const uint8_t* __restrict__ mask, double* U,
             const double* __restrict__ F, double* G_old, double* delta, int32_t* status_out,
-            const int32_t* __restrict__ active, int k, const int32_t* __restrict__ kdev) {
+            const int32_t* __restrict__ active, int k, const int32_t* __restrict__ kdev,
+            const int32_t* __restrict__ gate) {
   using G = Geo<N, NW>;
   if (kdev) k = *kdev;
   extern __shared__ double smem[];
@@ -929,16 +930,25 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
   const SineWalk sw = sine_walk<N, NW>(L);
   int status = 0;
   const int64_t NN = (int64_t)N * N;
-  if (mode == 0) {
+  if (mode == 0 || mode == 3) {
     const WorkItem it = items[blockIdx.x];
-    const InstDev P = inst[it.inst];
-    if (mask && !mask[P.slice_base + it.slice]) return;
-    if (P.coarse_kind == 2) return;  // learned propagator: separate path
+    InstDev P = inst[it.inst];
+    int64_t off_in = P.off_slices + (int64_t)it.slice * NN;
+    if (mode == 0) {
+      if (mask && !mask[P.slice_base + it.slice]) return;
+      if (P.coarse_kind == 2) return;  // learned propagator: separate path
+    } else {
+      // the plain propagator (2.4) of the slices of gated instances, from the
+      // iterate layout (U_in = U, states U_0..U_{N-1})
+      if (!gate[it.inst]) return;
+      P.coarse_kind = 0;
+      off_in = P.off_iter + (int64_t)it.slice * NN;
+    }
     load_sine_table<N, NW>(T, Tg);
     zero_state<N, NW>(smem);
     __syncthreads();
     const int64_t off = P.off_slices + (int64_t)it.slice * NN;
-    load_state<N, NW>(X, U_in + off);
+    load_state<N, NW>(X, U_in + off_in);
     __syncthreads();
     coarse_apply<N, NW>(X, red, T, sw, L, P, work_vectors(P, it.slice), status);
     store_state<N, NW>(X, G_out + off);
@@ -2623,7 +2633,8 @@ k_coarse_stream(int mode, const int32_t* __restrict__ insts, const WorkItem* __r
                 const double* __restrict__ U_in, double* __restrict__ G_out,
                 const uint8_t* __restrict__ mask, double* U, const double* __restrict__ F,
                 double* G_old, double* delta, int32_t* status_out,
-                const int32_t* __restrict__ active, int k, const int32_t* __restrict__ kdev) {
+                const int32_t* __restrict__ active, int k, const int32_t* __restrict__ kdev,
+                const int32_t* __restrict__ gate) {
   using G = GeoS<N, NW>;
   if (kdev) k = *kdev;
   extern __shared__ double smem[];
@@ -2634,14 +2645,21 @@ k_coarse_stream(int mode, const int32_t* __restrict__ insts, const WorkItem* __r
   const int t = threadIdx.x;
   int status = 0;
   for (int m = t; m < G::P2; m += G::NT) T[m] = Tg[m];
-  if (mode == 0) {
+  if (mode == 0 || mode == 3) {
     const WorkItem it = items[blockIdx.x];
-    const InstDev P = inst[it.inst];
-    if (mask && !mask[P.slice_base + it.slice]) return;
-    if (P.coarse_kind == 2) return;
+    InstDev P = inst[it.inst];
+    int64_t off_in = P.off_slices + (int64_t)it.slice * NN;
+    if (mode == 0) {
+      if (mask && !mask[P.slice_base + it.slice]) return;
+      if (P.coarse_kind == 2) return;
+    } else {   // plain (2.4) of gated instances from the iterate layout (see k_coarse_2d)
+      if (!gate[it.inst]) return;
+      P.coarse_kind = 0;
+      off_in = P.off_iter + (int64_t)it.slice * NN;
+    }
     double* w = P.work + (int64_t)it.slice * P.work_vecs * NN;
     const int64_t off = P.off_slices + (int64_t)it.slice * NN;
-    for (int64_t i = t; i < NN; i += G::NT) w[i] = U_in[off + i];
+    for (int64_t i = t; i < NN; i += G::NT) w[i] = U_in[off_in + i];
     __syncthreads();
     stream_coarse_apply<N, NW>(w, P, w, Lc, T, red, status);
     for (int64_t i = t; i < NN; i += G::NT) G_out[off + i] = w[i];
@@ -3561,15 +3579,17 @@ static hipError_t coarse2d(int mode, const int32_t* insts, int n_insts, const Wo
                            int n_items, const InstDev* inst, const double* Tg,
                            const double* U_in, double* G_out, const uint8_t* mask, double* U,
                            const double* F, double* G_old, double* delta, int32_t* status,
-                           const int32_t* active, int k, const int32_t* kdev, hipStream_t s) {
+                           const int32_t* active, int k, const int32_t* kdev, hipStream_t s,
+                           const int32_t* gate) {
   const size_t lds = ((size_t)Geo<N, NW>::XSZ + Geo<N, NW>::P2 + 4 * NW) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int grid = mode == 0 ? n_items : n_insts;
+  const int grid = (mode == 0 || mode == 3) ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_coarse_2d<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts, items,
-                     inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
+                     inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev,
+                     gate);
   return hipGetLastError();
 }
 
@@ -3578,16 +3598,18 @@ static hipError_t coarse_stream(int mode, const int32_t* insts, int n_insts, con
                                 int n_items, const InstDev* inst, const double* Tg,
                                 const double* U_in, double* G_out, const uint8_t* mask, double* U,
                                 const double* F, double* G_old, double* delta, int32_t* status,
-                                const int32_t* active, int k, const int32_t* kdev, hipStream_t s) {
+                                const int32_t* active, int k, const int32_t* kdev, hipStream_t s,
+                                const int32_t* gate) {
   const size_t lds =
       ((size_t)2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2 + 4 * NW) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_stream<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int grid = mode == 0 ? n_items : n_insts;
+  const int grid = (mode == 0 || mode == 3) ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_coarse_stream<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
-                     items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
+                     items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev,
+                     gate);
   return hipGetLastError();
 }
 
@@ -3596,12 +3618,13 @@ hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const double* Tg, const double* U_in,
                             double* G_out, const uint8_t* mask, double* U, const double* F,
                             double* G_old, double* delta, int32_t* status,
-                            const int32_t* active, int k, const int32_t* kdev, hipStream_t s) {
+                            const int32_t* active, int k, const int32_t* kdev, hipStream_t s,
+                            const int32_t* gate) {
   switch (n) {
-    case 256: return coarse_stream<256, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
-    case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
-    case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
-    case 128: return coarse2d<128, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s);
+    case 256: return coarse_stream<256, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s, gate);
+    case 32: return coarse2d<32, 2>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s, gate);
+    case 64: return coarse2d<64, 4>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s, gate);
+    case 128: return coarse2d<128, 8>(mode, insts, n_insts, items, n_items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev, s, gate);
     default: return hipErrorInvalidValue;
   }
 }
@@ -3622,6 +3645,98 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_coarse_1d, dim3(grid), dim3((n + 63) / 64 * 64), lds, s, mode, insts, items, inst, S, lam,
                      U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev);
+  return hipGetLastError();
+}
+
+// ------------------------------------------ judge of the learned propagator
+// Per learned-propagator instance t (global index insts[t]): live[i] = the
+// instance is active and still uses the learned propagator (the gate of its
+// network passes and of the plain propagator's judge pass).
+__global__ void k_judge_live(const int32_t* __restrict__ insts, int n, const InstDev* __restrict__ inst,
+                             const int32_t* __restrict__ active, int32_t* __restrict__ live) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= n) return;
+  const int i = insts[t];
+  live[i] = (!active || active[i]) && inst[i].coarse_kind == 2;
+}
+// A new run: the learned propagator again, no fallback, no previous norm.
+__global__ void k_judge_reset(const int32_t* __restrict__ insts, int n, InstDev* __restrict__ inst,
+                              JudgeDev* __restrict__ J, double* __restrict__ ratios, int rstride,
+                              int32_t* __restrict__ refresh) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= n) return;
+  const int i = insts[t];
+  if (J[t].enabled) inst[i].coarse_kind = 2;
+  J[t].delta_prev = __builtin_huge_val();
+  J[t].fallback_at = -1;
+  refresh[i] = 0;
+  for (int k = 0; k < rstride; ++k) ratios[(int64_t)t * rstride + k] = __builtin_nan("");
+}
+// The judge's ratio of iteration k = *kdev: the mean over the slices n >= k
+// with d_plain > 0 of d_learned / d_plain, d = ||G(U_n^k) - F_n||_h (NaN if
+// no slice qualifies); one thread per instance, slices summed in order.
+__global__ void k_judge_ratio(const int32_t* __restrict__ insts, int n,
+                              const InstDev* __restrict__ inst, const int32_t* __restrict__ live,
+                              const double* __restrict__ d_learned,
+                              const double* __restrict__ d_plain, const int32_t* __restrict__ kdev,
+                              double* __restrict__ ratios, int rstride) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= n) return;
+  const int i = insts[t];
+  if (!live[i]) return;
+  const InstDev& P = inst[i];
+  const int k = *kdev;
+  double acc = 0.0;
+  int cnt = 0;
+  for (int sl = k; sl < P.n_slices; ++sl) {
+    const double dp = d_plain[P.slice_base + sl];
+    if (dp > 0.0) {
+      acc += d_learned[P.slice_base + sl] / dp;
+      ++cnt;
+    }
+  }
+  if (k < rstride) ratios[(int64_t)t * rstride + k] = cnt ? acc / cnt : __builtin_nan("");
+}
+// After the correction of iteration k = *kdev: fall back to the plain
+// propagator when the update norm is not finite, or no smaller than the
+// previous one, or the judge's ratios of iterations k - 1 and k both exceed
+// 1 (unless the norm is already below tol).  A fallback switches the
+// instance's kind on the device and asks for G_old to be recomputed with the
+// plain propagator at the new iterate (refresh).
+__global__ void k_judge_decide(const int32_t* __restrict__ insts, int n, InstDev* __restrict__ inst,
+                               const int32_t* __restrict__ live, const double* __restrict__ delta,
+                               double tol, const int32_t* __restrict__ kdev,
+                               JudgeDev* __restrict__ J, const double* __restrict__ ratios,
+                               int rstride, int32_t* __restrict__ refresh) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= n) return;
+  const int i = insts[t];
+  refresh[i] = 0;
+  if (!live[i]) return;
+  const int k = *kdev;
+  const double d = delta[i];
+  const double* r = ratios + (int64_t)t * rstride;
+  const bool worse = k >= 1 && k < rstride && r[k] > 1.0 && r[k - 1] > 1.0;
+  if (!(d < tol) && (!(d == d) || d > 1e300 || d >= J[t].delta_prev || worse)) {
+    inst[i].coarse_kind = 0;
+    J[t].fallback_at = k + 1;
+    refresh[i] = 1;
+  }
+  J[t].delta_prev = d;
+}
+hipError_t launch_judge(int what, const int32_t* insts, int n, InstDev* inst, const int32_t* active,
+                        int32_t* live, JudgeDev* J, double* ratios, int rstride, int32_t* refresh,
+                        const double* d_learned, const double* d_plain, const double* delta,
+                        double tol, const int32_t* kdev, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + 63) / 64), blk(64);
+  switch (what) {
+    case 0: hipLaunchKernelGGL(k_judge_reset, grid, blk, 0, s, insts, n, inst, J, ratios, rstride, refresh); break;
+    case 1: hipLaunchKernelGGL(k_judge_live, grid, blk, 0, s, insts, n, inst, active, live); break;
+    case 2: hipLaunchKernelGGL(k_judge_ratio, grid, blk, 0, s, insts, n, inst, live, d_learned, d_plain, kdev, ratios, rstride); break;
+    case 3: hipLaunchKernelGGL(k_judge_decide, grid, blk, 0, s, insts, n, inst, live, delta, tol, kdev, J, ratios, rstride, refresh); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

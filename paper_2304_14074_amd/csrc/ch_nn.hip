@@ -112,8 +112,9 @@ template <int COB>
 __global__ void __launch_bounds__(256)
 k_conv_fwd(const float* __restrict__ A, int Ca, const float* __restrict__ B, int Cb, int H,
            const uint16_t* __restrict__ w, float* __restrict__ Y, int Co, int Ho, int k, int stride,
-           int act) {
+           int act, const int32_t* __restrict__ gate) {
   extern __shared__ float wl[];
+  if (gate && !*gate) return;
   const int Ci = Ca + Cb, kk = k * k, co0 = blockIdx.y * COB, b = blockIdx.z;
   const int nw = COB * Ci * kk;
   for (int i = threadIdx.x; i < nw; i += 256) wl[i] = bf2f(w[(int64_t)co0 * Ci * kk + i]);
@@ -252,7 +253,9 @@ k_conv_bwd_weight(const float* __restrict__ G, int Co, int Ho, const float* __re
     gw[(int64_t)Co * Ci * kk + co] = (red[9][0] + red[9][1]) + (red[9][2] + red[9][3]);
 }
 
-__global__ void k_to_f32(const double* __restrict__ u, float* __restrict__ x, int64_t count) {
+__global__ void k_to_f32(const double* __restrict__ u, float* __restrict__ x, int64_t count,
+                         const int32_t* __restrict__ gate) {
+  if (gate && !*gate) return;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < count) x[i] = (float)u[i];
 }
@@ -262,7 +265,9 @@ __global__ void k_to_f32(const double* __restrict__ u, float* __restrict__ x, in
 // inside it.  Training uses the unclipped output.
 constexpr double OUT_BOUND = 1.5;
 __global__ void k_residual_out(const double* __restrict__ u, const float* __restrict__ h,
-                               double* __restrict__ out, int64_t count) {
+                               double* __restrict__ out, int64_t count,
+                               const int32_t* __restrict__ gate) {
+  if (gate && !*gate) return;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < count) out[i] = fmin(fmax(u[i] + (double)h[i], -OUT_BOUND), OUT_BOUND);
 }
@@ -348,15 +353,17 @@ __global__ void k_pr_correct(double* __restrict__ Un1, const double* __restrict_
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
-// delta = sqrt(h^2 max_slices sum_blocks part) (fixed order); a NaN sets status bit 2.
+// delta = sqrt(h^2 max_slices sum_blocks part) over the slices k..nslices-1
+// (k = *kdev, 0 if kdev is null; part rows indexed by slice), fixed order; a
+// NaN sets status bit 2.
 __global__ void k_pr_delta(const double* __restrict__ part, int nb, int nslices, double h2,
                            double* __restrict__ delta, int32_t* __restrict__ status,
-                           const int32_t* __restrict__ active) {
+                           const int32_t* __restrict__ active, const int32_t* __restrict__ kdev) {
   if (threadIdx.x != 0) return;
   if (active && !*active) return;
   double mx = 0.0;
   bool bad = false;
-  for (int sl = 0; sl < nslices; ++sl) {
+  for (int sl = kdev ? *kdev : 0; sl < nslices; ++sl) {
     double s = 0.0;
     for (int b = 0; b < nb; ++b) s += part[(int64_t)sl * nb + b];
     if (!(s == s)) bad = true;
@@ -374,15 +381,59 @@ hipError_t pr_correct(double* Un1, const double* Fn, double* Gn, const double* g
   return hipGetLastError();
 }
 hipError_t pr_delta(const double* part, int nb, int nslices, double h2, double* delta,
-                    int32_t* status, const int32_t* active, hipStream_t s) {
+                    int32_t* status, const int32_t* active, hipStream_t s, const int32_t* kdev) {
   hipLaunchKernelGGL(k_pr_delta, dim3(1), dim3(64), 0, s, part, nb, nslices, h2, delta, status,
-                     active);
+                     active, kdev);
+  return hipGetLastError();
+}
+// The first corrected slice of iteration k = *kdev: U_{k+1} <- F_k (its
+// G terms cancel: G(U_k) = G_old_k, slice k being final), with the per-block
+// squares of the change in part row k.  Nothing when k >= nslices or the
+// gate is off.
+__global__ void k_pr_first(double* __restrict__ Ui, const double* __restrict__ Fi, int64_t P,
+                           int nslices, double* __restrict__ part, int nb,
+                           const int32_t* __restrict__ kdev, const int32_t* __restrict__ gate) {
+  __shared__ double red[4];
+  if (gate && !*gate) return;
+  const int k = *kdev;
+  if (k >= nslices) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double sq = 0.0;
+  if (i < P) {
+    const double un = Fi[(int64_t)k * P + i];
+    const double d = un - Ui[(int64_t)(k + 1) * P + i];
+    sq = d * d;
+    Ui[(int64_t)(k + 1) * P + i] = un;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)k * nb + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+hipError_t pr_first(double* Ui, const double* Fi, int64_t P, int nslices, double* part, int nb,
+                    const int32_t* kdev, const int32_t* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_pr_first, dim3(blocks(P)), dim3(256), 0, s, Ui, Fi, P, nslices, part, nb,
+                     kdev, gate);
+  return hipGetLastError();
+}
+// gates[sl] = *live && sl > *kdev for the slices of one correction sweep
+__global__ void k_slice_gates(const int32_t* __restrict__ live, const int32_t* __restrict__ kdev,
+                              int nslices, int32_t* __restrict__ gates) {
+  const int sl = blockIdx.x * 256 + threadIdx.x;
+  if (sl < nslices) gates[sl] = (*live && sl > *kdev) ? 1 : 0;
+}
+hipError_t slice_gates(const int32_t* live, const int32_t* kdev, int nslices, int32_t* gates,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_slice_gates, dim3(blocks(nslices)), dim3(256), 0, s, live, kdev, nslices,
+                     gates);
   return hipGetLastError();
 }
 // G_out <- g for masked slices (all when mask is null)
 __global__ void k_masked_copy(double* __restrict__ dst, const double* __restrict__ src,
                               const uint8_t* __restrict__ mask, int64_t P, int nslices,
-                              int64_t slice_base) {
+                              int64_t slice_base, const int32_t* __restrict__ gate) {
+  if (gate && !*gate) return;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= P * nslices) return;
   const int sl = (int)(i / P);
@@ -390,15 +441,15 @@ __global__ void k_masked_copy(double* __restrict__ dst, const double* __restrict
   dst[i] = src[i];
 }
 hipError_t masked_copy(double* dst, const double* src, const uint8_t* mask, int64_t P, int nslices,
-                       int64_t slice_base, hipStream_t s) {
+                       int64_t slice_base, hipStream_t s, const int32_t* gate) {
   hipLaunchKernelGGL(k_masked_copy, dim3(blocks(P * nslices)), dim3(256), 0, s, dst, src, mask, P,
-                     nslices, slice_base);
+                     nslices, slice_base, gate);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- host launchers
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
-                      const NNPlan& p, double* out, hipStream_t s) {
+                      const NNPlan& p, double* out, hipStream_t s, const int32_t* gate) {
   const int64_t cnt = (int64_t)batch * n * n;
   static bool attr = false;
   if (!attr) {
@@ -407,7 +458,7 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_to_f32, dim3(blocks(cnt)), dim3(256), 0, s, u, ws + p.x0, cnt);
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks(cnt)), dim3(256), 0, s, u, ws + p.x0, cnt, gate);
   for (int l = 0; l < NN_LAYERS; ++l) {
     const NNLayer& L = kNNLayers[l];
     const float* A;
@@ -428,17 +479,17 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
       const size_t lds = (size_t)16 * L.c_in * L.k * L.k * sizeof(float);
       hipLaunchKernelGGL(k_conv_fwd<16>, dim3(blocks((int64_t)Ho * Ho), L.c_out / 16, batch),
                          dim3(256), lds, s, A, Ca, B, Cb, H, wl, ws + p.act[l], L.c_out, Ho, L.k,
-                         L.stride, L.act);
+                         L.stride, L.act, gate);
     } else {
       const size_t lds = (size_t)L.c_in * L.k * L.k * sizeof(float);
       hipLaunchKernelGGL(k_conv_fwd<1>, dim3(blocks((int64_t)Ho * Ho), L.c_out, batch), dim3(256),
                          lds, s, A, Ca, B, Cb, H, wl, ws + p.act[l], L.c_out, Ho, L.k, L.stride,
-                         L.act);
+                         L.act, gate);
     }
   }
   if (out)
     hipLaunchKernelGGL(k_residual_out, dim3(blocks(cnt)), dim3(256), 0, s, u,
-                       ws + p.act[NN_LAYERS - 1], out, cnt);
+                       ws + p.act[NN_LAYERS - 1], out, cnt, gate);
   return hipGetLastError();
 }
 

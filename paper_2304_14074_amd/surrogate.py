@@ -7,11 +7,12 @@ whose "slices" are the S current states, so one ch_fine_propagate moves every
 trajectory by dT.  The network (ch_nn_*) is trained on the pairs
 (u(T_n), u(T_{n+1})) with Adam; weights are BF16 with an FP32 master copy.
 
-The Parareal loop implements the fallback: the learned propagator is used
-until the update norm stops contracting (delta^{k+1} >= delta^k, or a
-non-finite delta) or the plain propagator, its judge, finds it further from F
-than itself in two consecutive iterations; the instance then switches to the
-plain propagator and G_old is recomputed with it at the current iterate.
+The library implements the fallback on the device (ch_judge_read): the
+learned propagator is used until the update norm stops contracting
+(delta^{k+1} >= delta^k, or a non-finite delta) or the plain propagator, its
+judge, finds it further from F than itself in two consecutive iterations;
+the instance then switches to the plain propagator and G_old is recomputed
+with it at the current iterate.
 """
 from __future__ import annotations
 
@@ -107,70 +108,52 @@ def train(traj: torch.Tensor, steps: int = 3000, batch: int = 16, lr: float = 1e
     return wm, wb, {"steps": step, "loss": hist, "seconds": time.perf_counter() - t0}
 
 
-def run_parareal(ctx: "chlib.Context", u0: np.ndarray, tol: float, fallback: bool = True,
-                 max_iter: int | None = None):
-    """Single-instance Parareal to an update norm below tol (or k = N).
+def run_parareal(ctx: "chlib.Context", u0: np.ndarray, tol: float, max_iter: int | None = None,
+                 graph: bool = False):
+    """Single-instance Parareal to an update norm below tol (or k = N), one
+    ch_parareal_iterate per iteration (graph=True: one captured iteration,
+    replayed), reading the update norm after each.
 
-    With the learned propagator and the fallback on, the plain propagator
-    also judges the learned one before every correction: the mean over the
-    swept slices n >= k of ||G(U_n^k) - F_n||_h / ||G_plain(U_n^k) - F_n||_h
-    (G(U_n^k) is G_old_n; slices where G_plain equals F are left out).  The
-    instance falls back to the plain propagator when the update norm stops
-    contracting or when that ratio exceeds 1 in two consecutive iterations.
-    Returns iterations, update norms, the judge's ratios, wall time and the
-    fallback iteration."""
+    With the learned propagator, the library judges it against the plain
+    propagator and falls back to the plain one on the device (ch_judge_read).
+    Returns iterations, update norms, the judge's ratios of the judged
+    iterations, wall time (from the upload of U_0 to the last norm read) and
+    the fallback iteration."""
     p = ctx.problems[0]
     P = p.n ** p.dim
     N = p.n_slices
-    kind = p.coarse_kind
-    judging = fallback and kind == "neural"
     st = ctx.new_state()
-    st["U"][:P] = torch.from_numpy(np.ascontiguousarray(u0).reshape(-1)).to(ctx.device)
-    U_in = st["U"][: N * P]                       # slice inputs U_0..U_{N-1}
-    if judging:
-        # the plain propagator on a context of its own (no kind switching on
-        # the timed path); per-slice distances land in one small buffer
-        q = copy.copy(p)
-        q.coarse_kind = "approx2"
-        plain = chlib.Context([q], device=ctx.device)
-        Gp = torch.empty(N * P, dtype=torch.float64, device=ctx.device)
-        dist = torch.empty((2, N), dtype=torch.float64, device=ctx.device)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.ch_parareal_iterate(st, tol)
-    deltas, judge, fell_back = [], [], None
-    while st["c"].k < (max_iter or N):
-        k = st["c"].k
-        if judging and fell_back is None:
-            # one iteration as its two halves, with the judge in between
-            ctx.ch_fine_propagate(U_in, st["F"])
-            plain.ch_coarse_propagate(U_in, Gp)
-            ctx.ch_slice_distance(st["G_old"], st["F"], dist[0])
-            ctx.ch_slice_distance(Gp, st["F"], dist[1])
-            ctx.ch_parareal_correct(st, tol)
-            dn, dp = dist.cpu().numpy()
-            sel = dp[k:] > 0
-            judge.append(float(np.mean(dn[k:][sel] / dp[k:][sel])) if sel.any() else math.nan)
-        else:
-            ctx.ch_parareal_iterate(st, tol)
-        d = st["delta"][0].item()
-        deltas.append(d)
-        if d < tol:
-            break
-        worse = len(judge) >= 2 and min(judge[-2:]) > 1.0
-        if (judging and fell_back is None
-                and (not math.isfinite(d) or (len(deltas) >= 2 and d >= deltas[-2]) or worse)):
-            # plain propagator from now on, G_old recomputed with it at the
-            # current iterate U^{k}
-            ctx.ch_set_coarse_kind(0, "approx2")
-            ctx.ch_coarse_propagate(U_in, st["G_old"])
-            fell_back = st["c"].k
-    torch.cuda.synchronize()
-    ctx.ch_check_status(st)          # raises on a solver cap, non-finite state or time-out
-    if judging:
-        plain.ch_check_status()
+    s = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+    h = None
+    with torch.cuda.stream(s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st["U"][:P] = torch.from_numpy(np.ascontiguousarray(u0).reshape(-1)).to(ctx.device)
+        ctx.ch_parareal_iterate(st, tol, stream=s)
+        if graph:
+            h = ctx.ch_parareal_graph_create(st, tol, s)
+        deltas = []
+        while len(deltas) < (max_iter or N):
+            if graph:
+                ctx.ch_graph_launch(h, s)
+            else:
+                ctx.ch_parareal_iterate(st, tol, stream=s)
+            d = st["delta"][0].item()
+            deltas.append(d)
+            if d < tol:
+                break
+        s.synchronize()
+        secs = time.perf_counter() - t0
+        if h is not None:
+            ctx.ch_graph_destroy(h)
+        ctx.ch_iteration_count(st, stream=s)
+        ctx.ch_check_status(st, stream=s)  # raises on a cap, a non-finite state or a time-out
+        judge, fell_back = [], None
+        if p.coarse_kind == "neural":
+            ratios, fell_back, _ = ctx.ch_judge_read(0, stream=s)
+            judge = ratios[:fell_back if fell_back is not None else len(deltas)]
     return {"iterations": len(deltas), "deltas": deltas, "judge": judge,
-            "seconds": time.perf_counter() - t0, "fallback_at": fell_back, "U": st["U"],
+            "seconds": secs, "fallback_at": fell_back, "U": st["U"],
             "status": int(st["status"][0].item())}
 
 

@@ -1,0 +1,78 @@
+"""The judge and fallback of the learned coarse propagator run on the
+device, inside ch_parareal_iterate: against the oracle's loop (same BF16
+weights) for a network that is a constant shift of its input, and a
+graph-captured run against the eager one, bit for bit."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import nn as onn, operators, parareal, propagators
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+def _shift_weights(c):
+    th = np.zeros(onn.n_params())
+    o = 0
+    for name, ci, co, k, _, _, _ in onn.LAYERS:
+        o += co * ci * k * k
+        if name == "head":
+            th[o:o + co] = c
+        o += co
+    wb = torch.tensor(th, dtype=torch.float32).to(torch.bfloat16)
+    return wb.cuda(), wb.to(torch.float64).numpy()
+
+
+def _problem(N=6, J=20, n=32):
+    return workloads.Problem(dim=2, n=n, eps=0.03, T=N * J * 4e-5, n_slices=N, j_fine=J,
+                             coarse_kind="neural")
+
+
+@pytest.mark.parametrize("shift", [0.002, 0.05])
+def test_device_judge_and_fallback_match_the_oracle(shift):
+    from paper_2304_14074_amd import chlib, surrogate
+    p = _problem()
+    wb, th = _shift_weights(shift)
+    u0 = workloads.u0_uniform(p.n, 2, 0.3, 41)
+    ctx = chlib.Context([p])
+    ctx.ch_nn_bind(wb)
+    print(f"device judge, shift {shift}", flush=True)
+    r = surrogate.run_parareal(ctx, u0, 1e-12)
+    plain = copy.copy(p)
+    plain.coarse_kind = "approx2"
+    ref = parareal.parareal(u0, p.n_slices, lambda u: propagators.fine(p, u),
+                            lambda u: onn.surrogate_step(th, u),
+                            lambda v: operators.norm_h(v, 2), tol=1e-12,
+                            fallback_G=lambda u: propagators.coarse(plain, u))
+    print("gpu", r["judge"], r["fallback_at"], "oracle", ref["judge"], ref["fallback_at"],
+          flush=True)
+    assert r["fallback_at"] == ref["fallback_at"]
+    assert len(r["judge"]) == len(ref["judge"]) > 0
+    for a, b in zip(r["judge"], ref["judge"]):
+        assert abs(a - b) <= 1e-3 * abs(b), (r["judge"], ref["judge"])
+    assert r["iterations"] == ref["k"]
+    U = r["U"].view(p.n_slices + 1, p.n, p.n).cpu().numpy()
+    for j in range(p.n_slices + 1):
+        assert gu.rel(U[j], ref["final"][j]) < 1e-9, j
+
+
+def test_captured_learned_iteration_equals_eager():
+    from paper_2304_14074_amd import chlib, surrogate
+    p = _problem(N=5)
+    wb, _ = _shift_weights(0.05)
+    u0 = workloads.u0_uniform(p.n, 2, 0.3, 42)
+    outs = []
+    for graph in (False, True):
+        ctx = chlib.Context([p])
+        ctx.ch_nn_bind(wb)
+        print(f"learned G run, graph={graph}", flush=True)
+        r = surrogate.run_parareal(ctx, u0, 0.0, graph=graph)
+        outs.append(r)
+    a, b = outs
+    assert a["deltas"] == b["deltas"] and a["fallback_at"] == b["fallback_at"]
+    assert np.array_equal(np.array(a["judge"]), np.array(b["judge"]), equal_nan=True)
+    assert torch.equal(a["U"], b["U"])
