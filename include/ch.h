@@ -84,6 +84,9 @@ typedef struct ch_problem {
   int32_t krylov_max;   /* CG iteration cap                                    */
   int32_t f_zero;       /* test hook: f(u) == 0                                */
   double nl_krylov_rtol;/* relative residual target of the CG inside Newton    */
+  int32_t nn_base;      /* learned coarse propagator: 0 = clip(u + net(u)); 1 =
+                           clip(G_plain(u) + net(u)), the network learns the
+                           plain propagator's defect F - G_plain                 */
 } ch_problem;
 
 typedef struct ch_ctx ch_ctx;

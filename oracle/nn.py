@@ -79,12 +79,16 @@ def loss_and_grad(theta: np.ndarray, u: np.ndarray, target: np.ndarray, layers=L
 OUT_BOUND = 1.5
 
 
-def surrogate_step(theta, u: np.ndarray) -> np.ndarray:
-    """G_nn(u) for one state (n x n), FP64: the network output clipped to
-    [-1.5, 1.5] (the propagator is applied repeatedly in the coarse sweep,
-    possibly far from its training states; training uses the unclipped
-    output)."""
+def surrogate_step(theta, u: np.ndarray, base: np.ndarray | None = None) -> np.ndarray:
+    """G_nn(u) for one state (n x n), FP64: u + net(u), or base + net(u) when a
+    base state is given (the learned propagator on top of the plain one, base
+    = G_plain(u)), clipped to [-1.5, 1.5] (the propagator is applied
+    repeatedly in the coarse sweep, possibly far from its training states;
+    training uses the unclipped output)."""
     with torch.no_grad():
         th = torch.as_tensor(np.asarray(theta, dtype=np.float64))
-        out = forward(th, torch.tensor(u[None], dtype=torch.float64))[0].numpy()
+        ut = torch.tensor(u[None], dtype=torch.float64)
+        out = forward(th, ut)[0].numpy()
+        if base is not None:
+            out = base + (out - u)
         return np.clip(out, -OUT_BOUND, OUT_BOUND)

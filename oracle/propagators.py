@@ -47,7 +47,8 @@ def coarse(prob, u: np.ndarray, kind: str | None = None, nn_params=None) -> np.n
     v = np.array(u, dtype=np.float64, copy=True)
     if kind == "neural":
         from . import nn
-        return nn.surrogate_step(nn_params, v)
+        base = coarse(prob, v, kind="approx2") if getattr(prob, "nn_base", 0) else None
+        return nn.surrogate_step(nn_params, v, base)
     m = prob.m_coarse
     tau = prob.dT / m
     for _ in range(m):

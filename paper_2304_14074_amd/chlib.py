@@ -40,7 +40,8 @@ class ChProblem(ctypes.Structure):
                 ("coarse_kind", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("newton_tol", ctypes.c_double), ("newton_max", ctypes.c_int32),
                 ("krylov_rtol", ctypes.c_double), ("krylov_max", ctypes.c_int32),
-                ("f_zero", ctypes.c_int32), ("nl_krylov_rtol", ctypes.c_double)]
+                ("f_zero", ctypes.c_int32), ("nl_krylov_rtol", ctypes.c_double),
+                ("nn_base", ctypes.c_int32)]
 
 
 class ChPrState(ctypes.Structure):
@@ -142,7 +143,8 @@ def to_problem(p) -> ChProblem:
                      newton_tol=float(g("newton_tol", 1e-10)), newton_max=int(g("newton_max", 20)),
                      krylov_rtol=float(g("krylov_rtol", 1e-13)),
                      krylov_max=int(g("krylov_max", 200)), f_zero=int(bool(g("f_zero", False))),
-                     nl_krylov_rtol=float(g("nl_krylov_rtol", 1e-9)))
+                     nl_krylov_rtol=float(g("nl_krylov_rtol", 1e-9)),
+                     nn_base=int(g("nn_base", 0)))
 
 
 def _ptr(t):

@@ -61,6 +61,7 @@ struct ch_ctx {
   std::vector<int32_t> judge_enabled;
   int judge_rstride = 0;
   Block jinsts_blk, jdev_blk, jlive_blk, jrefresh_blk, jratio_blk, jgp_blk, jdist_blk, jgate_blk;
+  Block nn_gbase_blk;               // G_plain(u) under a learned propagator with a plain base
   bool capturing = false;           // a graph of one iteration is being recorded
   // pipelined iterations (one 2D n = 128 instance): fine inputs (2 N n^2),
   // odd-iteration fine results (N n^2), hand-off counters
@@ -173,6 +174,8 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
              (p.nl_variant < CH_NL_EYRE || p.nl_variant > CH_NL_FULL_BE || p.newton_max < 1 ||
               !(p.newton_tol > 0) || !(p.nl_krylov_rtol > 0)))
       bad = fail(c, CH_ERR_ARG, "instance %d: Newton parameters", i);
+    else if (p.nn_base != 0 && p.nn_base != 1)
+      bad = fail(c, CH_ERR_ARG, "instance %d: nn_base %d", i, p.nn_base);
     else if (p.coarse_kind == CH_COARSE_NEURAL && (p.dim != 2 || p.n % 8 != 0))
       bad = fail(c, CH_ERR_UNSUPPORTED,
                  "instance %d: the learned coarse propagator needs 2D with n divisible by 8", i);
@@ -216,6 +219,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     d.work_vecs = (p.dim == 2 && p.n == 256 &&
                    (p.fine_kind == CH_FINE_NONLINEAR || p.coarse_kind == CH_COARSE_EYRE))
                       ? 9 : chk::WORK_VECS;
+    d.nn_base = p.nn_base;
     d.wait_ticks = chk::WAIT_TICKS_DEFAULT;
     d.pipe_wait_ticks = chk::PIPE_WAIT_TICKS_DEFAULT;
     d.off_slices = so; d.off_iter = io; d.slice_base = slice_base;
@@ -338,6 +342,10 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       c->jgp_blk = take(sizeof(double) * (size_t)c->slice_total);
       c->jdist_blk = take(sizeof(double) * 2 * (size_t)n_slices_all);
       c->jgate_blk = take(sizeof(int32_t) * (size_t)n_slices_all);
+      bool base = false;
+      for (int i = 0; i < n_inst; ++i)
+        base = base || (probs[i].coarse_kind == CH_COARSE_NEURAL && probs[i].nn_base);
+      if (base) c->nn_gbase_blk = take(sizeof(double) * (size_t)c->slice_total);
     }
   }
   c->ws_bytes = off;
@@ -662,6 +670,25 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     if (d.coarse_kind != CH_COARSE_NEURAL) continue;
     if (!c->nn_w) return fail(c, CH_ERR_STATE, "instance %d: no surrogate weights bound", i);
     const int32_t* live = jlive + i;
+    // with a plain base: G_plain of slice sl (iterate layout) into gbase,
+    // gated by *gate, before the network pass of that slice
+    const ClassPlan* cpi = nullptr;
+    int item0 = 0;
+    for (const auto& cp : c->classes) {
+      int acc = 0;
+      for (int32_t j : cp.insts) {
+        if (j == i) { cpi = &cp; item0 = acc; }
+        acc += c->probs[j].n_slices;
+      }
+    }
+    double* gbase = d.nn_base ? (double*)(c->ws + c->nn_gbase_blk.off) + d.off_slices : nullptr;
+    auto plain = [&](int mode3, int first, int count, const double* src, const int32_t* gate) {
+      return chk::launch_coarse_2d(d.n, mode3, nullptr, 0,
+                                   (const WorkItem*)(c->ws + cpi->items_blk.off) + item0 + first,
+                                   count, inst, class_sine(c, *cpi), src,
+                                   (double*)(c->ws + c->nn_gbase_blk.off), nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr, s, gate);
+    };
     const int n = d.n, N = d.n_slices;
     const int64_t P = (int64_t)n * n;
     float* nws = (float*)(c->ws + c->nn_blk.off);
@@ -671,7 +698,9 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
     hipError_t e = hipSuccess;
     if (mode == 0) {
       const chk::NNPlan pl = chk::nn_plan(N, n);
-      e = chk::nn_forward(c->nn_w, U_in + d.off_slices, N, n, nws, pl, g, s, live);
+      if (gbase) e = plain(5, 0, N, U_in, jlive);
+      if (e == hipSuccess)
+        e = chk::nn_forward(c->nn_w, U_in + d.off_slices, N, n, nws, pl, g, s, live, gbase);
       if (e == hipSuccess)
         e = chk::masked_copy(G_out + d.off_slices, g, mask, P, N, d.slice_base, s, live);
     } else {
@@ -682,7 +711,10 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
       double* Gi = st->G_old + d.off_slices;
       if (mode == 1) {
         for (int sl = 0; sl < N && e == hipSuccess; ++sl) {
-          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, act);
+          if (gbase) e = plain(4, sl, 1, st->U, act);
+          if (e == hipSuccess)
+            e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, act,
+                                gbase ? gbase + sl * P : nullptr);
           if (e == hipSuccess) e = chk::pr_correct(Ui + (sl + 1) * P, nullptr, Gi + sl * P, g, P, part, 1, act, s);
         }
       } else {
@@ -697,7 +729,10 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
         if (e == hipSuccess) e = chk::pr_first(Ui, Fi, P, N, part, nb, kdev, act, s);
         const int first = c->capturing ? 1 : k + 1;
         for (int sl = first; sl < N && e == hipSuccess; ++sl) {
-          e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, gates + sl);
+          if (gbase) e = plain(4, sl, 1, st->U, gates + sl);
+          if (e == hipSuccess)
+            e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, gates + sl,
+                                gbase ? gbase + sl * P : nullptr);
           if (e == hipSuccess)
             e = chk::pr_correct(Ui + (sl + 1) * P, Fi + sl * P, Gi + sl * P, g, P,
                                 part + (int64_t)sl * nb, 0, gates + sl, s);

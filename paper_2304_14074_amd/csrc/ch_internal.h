@@ -25,7 +25,7 @@ struct InstDev {
   int32_t* status;           // solver flags raised by fine/parallel-coarse kernels
   double nl_krylov_rtol;     // CG target inside Newton
   int32_t work_vecs;         // solver vectors per slice in `work`
-  int32_t pad2;
+  int32_t nn_base;           // learned propagator on top of the plain one
   // bounds of the inter-workgroup waits, in ticks of the 100 MHz wall clock:
   // a group barrier (default 0.2 s) and a hand-off of the pipelined launch
   // (default 10 s); a wait that runs out flags status bit 4
@@ -75,9 +75,11 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
                           double* F_out, const uint8_t* mask, const int32_t* active,
                           const int32_t* kmin, int in_iter, hipStream_t s);
 // mode 0: independent G per masked slice (parallel); 1: prediction chain;
-// 2: correction chain starting at slice k+1 with U_{k+1} = F_k; 3: the plain
-// scheme (2.4) on every slice of the instances with gate[inst] != 0, inputs
-// from the iterate layout U_in (U_0..U_{N-1}), outputs in the slice layout.
+// 2: correction chain starting at slice k+1 with U_{k+1} = F_k; modes 3-5:
+// the plain scheme (2.4) of the given work items, outputs in the slice
+// layout: 3 -- items of instances with gate[inst] != 0, inputs from the
+// iterate layout U_in (U_0..U_{N-1}); 4 -- the items (one slice) when
+// gate[0] != 0, iterate layout; 5 -- as 3 with slice-layout inputs.
 hipError_t launch_coarse_2d(int n, int mode, const int32_t* insts, int n_insts,
                             const WorkItem* items, int n_items, const InstDev* inst,
                             const double* Tsin, const double* U_in,
@@ -166,8 +168,10 @@ int64_t nn_param_count();
 int64_t nn_param_offset(int layer);
 // gate (device, nullable): every kernel of the pass returns at once when
 // *gate == 0 (a graph-captured pass that the device switches off)
+// base (nullable): out = clip(base + net(u)) instead of clip(u + net(u))
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
-                      const NNPlan& p, double* out, hipStream_t s, const int32_t* gate = nullptr);
+                      const NNPlan& p, double* out, hipStream_t s, const int32_t* gate = nullptr,
+                      const double* base = nullptr);
 // floats of workspace the forward pass alone uses (x0 and the activations)
 size_t nn_forward_floats(int batch, int n);
 // the allocation-free forward pass: the file-scope device array of

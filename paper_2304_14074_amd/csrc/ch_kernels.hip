@@ -930,7 +930,7 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
   const SineWalk sw = sine_walk<N, NW>(L);
   int status = 0;
   const int64_t NN = (int64_t)N * N;
-  if (mode == 0 || mode == 3) {
+  if (mode == 0 || mode >= 3) {
     const WorkItem it = items[blockIdx.x];
     InstDev P = inst[it.inst];
     int64_t off_in = P.off_slices + (int64_t)it.slice * NN;
@@ -938,11 +938,10 @@ k_coarse_2d(int mode, const int32_t* __restrict__ insts, const WorkItem* __restr
       if (mask && !mask[P.slice_base + it.slice]) return;
       if (P.coarse_kind == 2) return;  // learned propagator: separate path
     } else {
-      // the plain propagator (2.4) of the slices of gated instances, from the
-      // iterate layout (U_in = U, states U_0..U_{N-1})
-      if (!gate[it.inst]) return;
+      // the plain propagator (2.4) of gated slices (see launch_coarse_2d)
+      if (!gate[mode == 4 ? 0 : it.inst]) return;
       P.coarse_kind = 0;
-      off_in = P.off_iter + (int64_t)it.slice * NN;
+      if (mode != 5) off_in = P.off_iter + (int64_t)it.slice * NN;
     }
     load_sine_table<N, NW>(T, Tg);
     zero_state<N, NW>(smem);
@@ -2645,17 +2644,17 @@ k_coarse_stream(int mode, const int32_t* __restrict__ insts, const WorkItem* __r
   const int t = threadIdx.x;
   int status = 0;
   for (int m = t; m < G::P2; m += G::NT) T[m] = Tg[m];
-  if (mode == 0 || mode == 3) {
+  if (mode == 0 || mode >= 3) {
     const WorkItem it = items[blockIdx.x];
     InstDev P = inst[it.inst];
     int64_t off_in = P.off_slices + (int64_t)it.slice * NN;
     if (mode == 0) {
       if (mask && !mask[P.slice_base + it.slice]) return;
       if (P.coarse_kind == 2) return;
-    } else {   // plain (2.4) of gated instances from the iterate layout (see k_coarse_2d)
-      if (!gate[it.inst]) return;
+    } else {   // plain (2.4) of gated slices (see k_coarse_2d)
+      if (!gate[mode == 4 ? 0 : it.inst]) return;
       P.coarse_kind = 0;
-      off_in = P.off_iter + (int64_t)it.slice * NN;
+      if (mode != 5) off_in = P.off_iter + (int64_t)it.slice * NN;
     }
     double* w = P.work + (int64_t)it.slice * P.work_vecs * NN;
     const int64_t off = P.off_slices + (int64_t)it.slice * NN;
@@ -3585,7 +3584,7 @@ static hipError_t coarse2d(int mode, const int32_t* insts, int n_insts, const Wo
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int grid = (mode == 0 || mode == 3) ? n_items : n_insts;
+  const int grid = (mode == 0 || mode >= 3) ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_coarse_2d<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts, items,
                      inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev,
@@ -3605,7 +3604,7 @@ static hipError_t coarse_stream(int mode, const int32_t* insts, int n_insts, con
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_stream<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int grid = (mode == 0 || mode == 3) ? n_items : n_insts;
+  const int grid = (mode == 0 || mode >= 3) ? n_items : n_insts;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_coarse_stream<N, NW>), dim3(grid), dim3(NW * 64), lds, s, mode, insts,
                      items, inst, Tg, U_in, G_out, mask, U, F, G_old, delta, status, active, k, kdev,

@@ -449,7 +449,8 @@ hipError_t masked_copy(double* dst, const double* src, const uint8_t* mask, int6
 
 // ---------------------------------------------------------------- host launchers
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
-                      const NNPlan& p, double* out, hipStream_t s, const int32_t* gate) {
+                      const NNPlan& p, double* out, hipStream_t s, const int32_t* gate,
+                      const double* base) {
   const int64_t cnt = (int64_t)batch * n * n;
   static bool attr = false;
   if (!attr) {
@@ -488,7 +489,7 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     }
   }
   if (out)
-    hipLaunchKernelGGL(k_residual_out, dim3(blocks(cnt)), dim3(256), 0, s, u,
+    hipLaunchKernelGGL(k_residual_out, dim3(blocks(cnt)), dim3(256), 0, s, base ? base : u,
                        ws + p.act[NN_LAYERS - 1], out, cnt, gate);
   return hipGetLastError();
 }

@@ -61,14 +61,34 @@ def init_weights(seed: int = 0, device="cuda") -> torch.Tensor:
     return torch.cat(parts).to(device)
 
 
+def plain_coarse_of(prob, traj: torch.Tensor) -> torch.Tensor:
+    """G_plain(u(T_n)) for every state of the trajectories (S, N+1, n, n):
+    the plain coarse propagator (2.4) of the problem, all states at once."""
+    S, N1, n, _ = traj.shape
+    batch = copy.copy(prob)
+    batch.n_slices = S * N1
+    batch.T = prob.dT * S * N1
+    batch.coarse_kind = "approx2"
+    ctx = chlib.Context([batch], device=traj.device)
+    out = torch.empty_like(traj)
+    ctx.ch_coarse_propagate(traj.reshape(-1), out.view(-1))
+    torch.cuda.synchronize()
+    ctx.ch_check_status()
+    return out
+
+
 def train(traj: torch.Tensor, steps: int = 3000, batch: int = 16, lr: float = 1e-3,
           seed: int = 0, time_budget_s: float | None = None, w_master=None, log=None,
-          k_min: int = 1):
+          k_min: int = 1, base: torch.Tensor | None = None):
     """Adam with a cosine learning-rate decay over `steps` mini-batches of
     (u(T_n) -> u(T_{n+1})) pairs of the trajectories, n >= k_min.
     The first slice maps seeded noise through the spinodal amplification
     (growth up to exp(dT / (4 eps^2))); Parareal makes that slice exact after
-    one iteration, so by default it is left out of the training pairs."""
+    one iteration, so by default it is left out of the training pairs.
+    With base = G_plain of every trajectory state (plain_coarse_of), the
+    network learns the plain propagator's defect: the loss of u + net(u)
+    against u(T_{n+1}) - G_plain(u) + u is that of G_plain(u) + net(u)
+    against u(T_{n+1})."""
     dev = traj.device
     S, N1, n, _ = traj.shape
     pairs = [(s, k) for s in range(S) for k in range(k_min, N1 - 1)]
@@ -93,6 +113,8 @@ def train(traj: torch.Tensor, steps: int = 3000, batch: int = 16, lr: float = 1e
             k_i = torch.tensor([b for _, b in sel], device=dev)
             u = traj[s_i, k_i].contiguous()
             tgt = traj[s_i, k_i + 1].contiguous()
+            if base is not None:
+                tgt = tgt - base[s_i, k_i] + u
             chlib.ch_nn_train_step(wb, u, tgt, grad, loss, ws)
             step += 1
             lr_t = lr * 0.5 * (1 + math.cos(math.pi * min((step - 1) / max(total, 1), 1.0)))

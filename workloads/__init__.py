@@ -42,6 +42,7 @@ class Problem:
     nl_krylov_rtol: float = 1e-9    # CG target inside Newton
     krylov_max: int = 200
     f_zero: bool = False     # test hook: f(u) == 0
+    nn_base: int = 0         # learned G: 0 = u + net(u), 1 = G_plain(u) + net(u)
 
     @property
     def h(self) -> float:
