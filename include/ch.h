@@ -79,8 +79,8 @@ typedef struct ch_problem {
   double newton_tol;    /* Newton stop: ||Y_{m+1}-Y_m||_h <= tol (1e-10)       */
   int32_t newton_max;   /* Newton iteration cap (20)                           */
   double krylov_rtol;   /* relative residual target of the CG solves of (2.4)
-                           (coarse step, and the PA-I fine step); 1e-13 keeps
-                           their error below 1e-12 relative                   */
+                           (coarse step, and the PA-I fine step); 0 = default:
+                           1e-12 with the linear fine step, 1e-13 otherwise   */
   int32_t krylov_max;   /* CG iteration cap                                    */
   int32_t f_zero;       /* test hook: f(u) == 0                                */
   double nl_krylov_rtol;/* relative residual target of the CG inside Newton    */

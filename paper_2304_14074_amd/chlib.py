@@ -141,7 +141,7 @@ def to_problem(p) -> ChProblem:
                      coarse_kind=COARSE[g("coarse_kind", "approx2")],
                      precision=PREC[g("precision", "fp64")],
                      newton_tol=float(g("newton_tol", 1e-10)), newton_max=int(g("newton_max", 20)),
-                     krylov_rtol=float(g("krylov_rtol", 1e-13)),
+                     krylov_rtol=float(g("krylov_rtol", 0.0)),
                      krylov_max=int(g("krylov_max", 200)), f_zero=int(bool(g("f_zero", False))),
                      nl_krylov_rtol=float(g("nl_krylov_rtol", 1e-9)),
                      nn_base=int(g("nn_base", 0)))

@@ -38,7 +38,7 @@ class Problem:
     precision: str = "fp64"         # "fp64" or "split_bf16"
     newton_tol: float = 1e-10
     newton_max: int = 20
-    krylov_rtol: float = 1e-13     # CG target of the (2.4) solves (coarse, and PA-I fine)
+    krylov_rtol: float = 0.0       # CG target of the (2.4) solves; 0: the library's default
     nl_krylov_rtol: float = 1e-9    # CG target inside Newton
     krylov_max: int = 200
     f_zero: bool = False     # test hook: f(u) == 0
