@@ -2885,10 +2885,13 @@ __device__ __forceinline__ void split_stage(const __bf16* SB, const SineB& A, co
 
 // Low-precision solve P^{-1} v of the owned FP64 values v (state orientation),
 // result (FP64 of the FP32 result) back in v.  Four stages; the symbol
-// 1/sigma is applied after the second.
+// 1/sigma is applied after the second, computed from the eigenvalues lamS
+// (LDS) as 1/(1 + tau eps^2 Lam^2 - s tau Lam), Lam = lam_p + lam_q, at the
+// owned spectral positions (no table reads from memory inside the step).
 template <int N, int NW>
 __device__ void split_solve(__bf16* SB, const SineB& A, const LaneB<N, NW>& L,
-                            double (&v)[GeoB<N, NW>::OWN], const double* __restrict__ rsig) {
+                            double (&v)[GeoB<N, NW>::OWN], const double* __restrict__ lamS,
+                            double tau, double e2, double sfine) {
   using G = GeoB<N, NW>;
   float y[G::OWN];
   __syncthreads();
@@ -2902,7 +2905,8 @@ __device__ void split_solve(__bf16* SB, const SineB& A, const LaneB<N, NW>& L,
       for (int s = 0; s < G::OWN; ++s) {
         const int qr = s >> 1, half = s & 1, q = qr >> 2, r = qr & 3;
         const int a = L.row_a(r), yr = half ? (N - 1 - a) : a, yc = L.col_c(q);
-        y[s] *= (float)rsig[yr * N + yc];
+        const double Lam = lamS[yr] + lamS[yc];
+        y[s] *= (float)(1.0 / (1.0 + tau * e2 * Lam * Lam - sfine * tau * Lam));
       }
     }
     if (st < 3) {
@@ -2944,6 +2948,22 @@ __device__ __forceinline__ void lap_owned(double* X, const LaneB<N, NW>& L,
   }
 }
 
+// Zero the halo ring of the FP64 stencil buffer (row -1, row N, columns -1
+// and N): the stencil reads nothing else outside the interior, and the
+// interior is rewritten before every stencil.
+template <int N, int NW>
+__device__ __forceinline__ void split_halo_zero(double* X) {
+  using G = GeoB<N, NW>;
+  for (int i = threadIdx.x; i < N + 2; i += G::NT) {
+    X[-G::LDX - 1 + i] = 0.0;
+    X[N * G::LDX - 1 + i] = 0.0;
+  }
+  for (int i = threadIdx.x; i < N; i += G::NT) {
+    X[i * G::LDX - 1] = 0.0;
+    X[i * G::LDX + N] = 0.0;
+  }
+}
+
 template <int N, int NW>
 __global__ void __launch_bounds__(NW * 64)
 k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
@@ -2954,6 +2974,7 @@ k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ 
   extern __shared__ double smem[];
   double* X = smem + G::XOFF;            // FP64 stencil buffer (interior origin)
   __bf16* SB = (__bf16*)smem;            // BF16 transform buffer (aliases X)
+  double* lamS = smem + G::XSZ;          // eigenvalues of the 1D Laplacian
   const WorkItem it = items[blockIdx.x];
   const InstDev P = inst[it.inst];
   if (mask && !mask[P.slice_base + it.slice]) return;
@@ -2966,6 +2987,7 @@ k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ 
   const double tau = P.dt, ih2 = 1.0 / (P.h * P.h), e2 = P.eps * P.eps, s = P.s_fine;
   double u[G::OWN], t1[G::OWN], t2[G::OWN];
   for (int i = threadIdx.x; i < G::XSZ; i += G::NT) smem[i] = 0.0;
+  for (int i = threadIdx.x; i < N; i += G::NT) lamS[i] = Tg[2 * (N + 1) + i];
   __syncthreads();
   for (int idx = threadIdx.x; idx < N * N; idx += G::NT)
     X[(idx / N) * G::LDX + idx % N] = U_in[off_in + idx];
@@ -2990,7 +3012,7 @@ k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ 
     }
     lap_owned<N, NW>(X, L, t1, t2, tau * ih2);
     // delta1 = P^{-1}_lp d
-    split_solve<N, NW>(SB, A, L, t2, P.rsig_fine);
+    split_solve<N, NW>(SB, A, L, t2, lamS, tau, e2, s);
     // u1 = u + delta1 (t2); w = f(u) - s u + s u1 (t1)
 #pragma unroll
     for (int k = 0; k < G::OWN; ++k) u[k] = W.x.ld(k * G::NT, vo);
@@ -3001,7 +3023,7 @@ k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ 
       t1[k] = (P.f_zero ? 0.0 : u[k] * u[k] * u[k] - u[k]) - s * u[k] + s * t2[k];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < G::XSZ; i += G::NT) smem[i] = 0.0;  // halo after BF16 use
+    split_halo_zero<N, NW>(X);   // the BF16 buffer overwrote part of the halo ring
     // residual r = (u - u1) + tau Lap(w - eps^2 Lap u1)
     lap_owned<N, NW>(X, L, t2, u, ih2);
 #pragma unroll
@@ -3010,11 +3032,11 @@ k_fine_split_2d(const WorkItem* __restrict__ items, const InstDev* __restrict__ 
 #pragma unroll
     for (int k = 0; k < G::OWN; ++k)
       t2[k] += W.x.ld(k * G::NT, vo) - W.r.ld(k * G::NT, vo);
-    split_solve<N, NW>(SB, A, L, t2, P.rsig_fine);
+    split_solve<N, NW>(SB, A, L, t2, lamS, tau, e2, s);
 #pragma unroll
     for (int k = 0; k < G::OWN; ++k) u[k] = W.r.ld(k * G::NT, vo) + t2[k];
     __syncthreads();
-    for (int i = threadIdx.x; i < G::XSZ; i += G::NT) smem[i] = 0.0;  // halo after BF16 use
+    split_halo_zero<N, NW>(X);   // the BF16 buffer overwrote part of the halo ring
   }
   __syncthreads();
 #pragma unroll
@@ -3032,7 +3054,7 @@ template <int N, int NW>
 static hipError_t split2d(const WorkItem* items, int n_items, const InstDev* inst, const double* Tg,
                           const double* U_in, double* F_out, const uint8_t* mask,
                           const int32_t* active, const int32_t* kmin, int in_iter, hipStream_t s) {
-  const size_t lds = (size_t)GeoB<N, NW>::XSZ * sizeof(double);
+  const size_t lds = ((size_t)GeoB<N, NW>::XSZ + N) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_split_2d<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
