@@ -38,7 +38,10 @@ HBM_PEAK_GBS = 8000.0
 FINE_LAUNCH_TRAFFIC_BYTES = (12842892.6 * 2.0 + 25674608.1) * 1024
 # the same for the pipelined launch, per iteration (counters over a 4-iteration
 # launch, divided by 4); None until taken for the kernel as it is now
-PIPE_TRAFFIC_BYTES_PER_ITERATION = (52372317.1 * 2.0 + 104752317.4) * 1024 / 4
+PIPE_TRAFFIC_BYTES_PER_ITERATION = (52384700.0 * 2.0 + 104752000.0) * 1024 / 4
+# the same for the fine sweep of the 256-instance batch (all three class launches)
+BATCHED_SWEEP_TRAFFIC_BYTES = ((6156784068.3 + 461061.6 + 105800.1) * 2.0
+                               + 12305827472.0 + 839680.0 + 190464.0) * 1024
 
 
 def fine_flops_per_point_step(n: int) -> float:
@@ -319,6 +322,7 @@ def batched_fine_sweep() -> dict:
             "slices": sum(p.n_slices for p in probs), "ms": ms,
             "point_steps_per_s": pts / (ms / 1e3), "tflops": tf,
             "frac_fp64_peak": tf / FP64_PEAK_TFLOPS,
+            "traffic_bytes": BATCHED_SWEEP_TRAFFIC_BYTES,
             "finite": bool(torch.isfinite(Fs).all().item())}
 
 
@@ -578,7 +582,6 @@ def main():
     if not args.no_split:
         # the same fine sweep with split-BF16 transforms inside FP64 defect
         # correction; error against the FP64 sweep of the same inputs
-        import copy
         ps = copy.copy(prob)
         ps.precision = "split_bf16"
         cs = chlib.Context([ps])
@@ -618,7 +621,6 @@ def main():
         # iteration included): plain coarse G (2.4) with m_c = 1, 2, 4, 8 substeps,
         # against the serial fine solve on the GPU; each result's error is its
         # largest per-slice relative L2 distance from the serial fine trajectory
-        import copy
         from paper_2304_14074_amd import surrogate
         traj, serial = serial_fine_trajectory(prob, u0)
         plain = []
