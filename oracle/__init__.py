@@ -16,6 +16,8 @@ Everything is float64 NumPy/SciPy, written from the paper:
   * ``energy``      -- the discrete Ginzburg-Landau energy of (1.2).
   * ``linear_model``-- the linearised propagators P_i, P_{J_i} of Section 3
                        and the convergence bound of Theorems 3.7/3.9/3.11.
+  * ``dd``          -- the Neumann-Neumann domain-decomposition solve of the
+                       PA-I fine step (2.4) in 1D (Section 4).
   * ``nn``          -- FP64 reference forward/backward of the convolutional
                        surrogate used as a learned coarse propagator.
 Each function cites the passage it follows.

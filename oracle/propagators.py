@@ -13,10 +13,12 @@ import numpy as np
 from . import schemes
 
 
-def fine(prob, u: np.ndarray, steps: int | None = None, route: str = "lu") -> np.ndarray:
+def fine(prob, u: np.ndarray, steps: int | None = None, route: str = "lu",
+         dd_iters: list | None = None) -> np.ndarray:
     """F(T_{n+1}, T_n, u): J steps of the fine scheme with tau = dT/J.
     route "lu": the sparse-LU solves; "sine": the same steps solved in the
-    sine basis (faster, equal up to rounding)."""
+    sine basis (faster, equal up to rounding).  With the Neumann-Neumann fine
+    step, ``dd_iters`` receives each step's iteration count."""
     J = prob.j_fine if steps is None else steps
     tau = prob.dt
     v = np.array(u, dtype=np.float64, copy=True)
@@ -34,6 +36,15 @@ def fine(prob, u: np.ndarray, steps: int | None = None, route: str = "lu") -> np
         elif prob.fine_kind == "approx2":
             # PA-I: scheme (2.4) as the fine step
             v = schemes.step_approx2(v, tau, prob.eps, prob.f_zero)
+        elif prob.fine_kind == "approx2_dd":
+            # PA-I with the Neumann-Neumann solve of (2.4) (Section 4, 1D)
+            from . import dd
+            if prob.f_zero:
+                raise ValueError("the Neumann-Neumann step has no f == 0 form")
+            v, it = dd.step_approx2_dd(v, tau, prob.eps, prob.dd_subdomains, prob.dd_theta,
+                                       prob.dd_tol, prob.dd_max)
+            if dd_iters is not None:
+                dd_iters.append(it)
         else:
             raise ValueError(prob.fine_kind)
     return v

@@ -32,7 +32,8 @@ class Problem:
     j_fine: int = 1563        # fine steps per slice J
     m_coarse: int = 1         # coarse sub-steps per slice
     s_fine: float = 2.0       # stabilisation constant of the linear fine step
-    fine_kind: str = "linear"       # "linear" (2.5), "nonlinear" (2.3) or "approx2" (2.4)
+    fine_kind: str = "linear"       # "linear" (2.5), "nonlinear" (2.3), "approx2" (2.4) or
+                                    # "approx2_dd" ((2.4) by Neumann-Neumann, 1D)
     nl_variant: str = "eyre"        # "eyre" (convex splitting) or "be" (fully implicit)
     coarse_kind: str = "approx2"    # "approx2" (2.4), "stab", "neural" or "eyre" (2.3)
     precision: str = "fp64"         # "fp64" or "split_bf16"
@@ -43,6 +44,10 @@ class Problem:
     krylov_max: int = 200
     f_zero: bool = False     # test hook: f(u) == 0
     nn_base: int = 0         # learned G: 0 = u + net(u), 1 = G_plain(u) + net(u)
+    dd_subdomains: int = 8   # Neumann-Neumann fine step: equal subdomains N0
+    dd_theta: float = 0.25   # relaxation of the trace update
+    dd_tol: float = 1e-10    # stop: max trace change per iteration
+    dd_max: int = 100        # iteration cap per step
 
     @property
     def h(self) -> float:
