@@ -52,8 +52,10 @@ typedef enum ch_status {
 /* fine propagator (Section 2.1): the linear stabilised step (scheme (2.5)
  * for s = 2; PA-II, PA-III), the implicit step solved by Newton's method
  * (scheme (2.3), or backward Euler; NPA-I, NPA-II), or scheme (2.4) with
- * tau = dt (PA-I: a variable-coefficient linear solve every fine step) */
-enum { CH_FINE_LINEAR = 0, CH_FINE_NONLINEAR = 1, CH_FINE_APPROX2 = 2 };
+ * tau = dt (PA-I: a variable-coefficient linear solve every fine step), the
+ * latter also solved by the Neumann-Neumann domain decomposition of
+ * Section 4 (1D; subdomain count, relaxation and stop in ch_problem) */
+enum { CH_FINE_LINEAR = 0, CH_FINE_NONLINEAR = 1, CH_FINE_APPROX2 = 2, CH_FINE_APPROX2_DD = 3 };
 enum { CH_NL_EYRE = 0, CH_NL_FULL_BE = 1 };
 /* coarse propagator: scheme (2.4) (default; PA-I, PA-III, NPA-I), the
  * stabilised step (PA-II), the learned surrogate (weights bound with
@@ -87,6 +89,15 @@ typedef struct ch_problem {
   int32_t nn_base;      /* learned coarse propagator: 0 = clip(u + net(u)); 1 =
                            clip(G_plain(u) + net(u)), the network learns the
                            plain propagator's defect F - G_plain                 */
+  /* CH_FINE_APPROX2_DD (1D only): each fine step (2.4) solved by the
+   * Neumann-Neumann iteration of Section 4 on equal subdomains; 0 picks the
+   * default in brackets                                                      */
+  int32_t dd_subdomains;/* N0, with (n + 1) divisible by N0 and (n+1)/N0 >= 2 (8) */
+  double dd_theta;      /* relaxation theta of the trace update, 0 < theta < 1 (1/4) */
+  double dd_tol;        /* stop: every interface trace (u and v) changed by at
+                           most dd_tol in the last iteration (1e-10)            */
+  int32_t dd_max;       /* iteration cap per step; reaching it is status bit 1
+                           (100)                                                */
 } ch_problem;
 
 typedef struct ch_ctx ch_ctx;
@@ -355,6 +366,13 @@ ch_status ch_set_coarse_kind(ch_ctx* ctx, int32_t inst, int32_t kind, ch_stream 
  * instance created with another coarse propagator. */
 ch_status ch_judge_read(ch_ctx* ctx, int32_t inst, double* ratios, int32_t* fallback_at,
                         int32_t* learned_now, ch_stream stream);
+
+/* Neumann-Neumann fine step (Section 4): the number of iterations the J
+ * steps of each slice of instance inst took in the latest fine sweep that
+ * processed that slice (slices a sweep skipped keep their earlier count; 0
+ * before any).  iters: host memory of N int32, written synchronously after
+ * `stream` drains.  CH_ERR_ARG for an instance of another fine kind. */
+ch_status ch_dd_iterations(ch_ctx* ctx, int32_t inst, int32_t* iters, ch_stream stream);
 
 const char* ch_status_str(ch_status s);
 const char* ch_last_error(const ch_ctx* ctx);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libch.so")
 
 CH_OK, CH_ERR_ARG, CH_ERR_HIP, CH_ERR_UNSUPPORTED, CH_ERR_NOCONV, CH_ERR_STATE, CH_ERR_TIMEOUT = range(7)
-FINE = {"linear": 0, "nonlinear": 1, "approx2": 2}
+FINE = {"linear": 0, "nonlinear": 1, "approx2": 2, "approx2_dd": 3}
 NL = {"eyre": 0, "be": 1}
 COARSE = {"approx2": 0, "stab": 1, "neural": 2, "eyre": 3}
 PREC = {"fp64": 0, "split_bf16": 1}
@@ -29,7 +29,7 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
            "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups",
            "ch_parareal_run", "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
-           "ch_nn_forward_static", "ch_linear_bound", "ch_judge_read")
+           "ch_nn_forward_static", "ch_linear_bound", "ch_judge_read", "ch_dd_iterations")
 
 
 class ChProblem(ctypes.Structure):
@@ -41,7 +41,9 @@ class ChProblem(ctypes.Structure):
                 ("newton_tol", ctypes.c_double), ("newton_max", ctypes.c_int32),
                 ("krylov_rtol", ctypes.c_double), ("krylov_max", ctypes.c_int32),
                 ("f_zero", ctypes.c_int32), ("nl_krylov_rtol", ctypes.c_double),
-                ("nn_base", ctypes.c_int32)]
+                ("nn_base", ctypes.c_int32), ("dd_subdomains", ctypes.c_int32),
+                ("dd_theta", ctypes.c_double), ("dd_tol", ctypes.c_double),
+                ("dd_max", ctypes.c_int32)]
 
 
 class ChPrState(ctypes.Structure):
@@ -113,6 +115,7 @@ def load() -> ctypes.CDLL:
     lib.ch_set_wait_limit.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
     dp = ctypes.POINTER(ctypes.c_double)
     lib.ch_judge_read.argtypes = [vp, i32, dp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.ch_dd_iterations.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
     lib.ch_linear_bound.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, i32, i32,
                                     ctypes.c_double, ctypes.c_double, dp, dp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_forward_static", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
@@ -120,7 +123,7 @@ def load() -> ctypes.CDLL:
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
                  "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run",
                  "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
-                 "ch_linear_bound", "ch_judge_read"):
+                 "ch_linear_bound", "ch_judge_read", "ch_dd_iterations"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -144,7 +147,9 @@ def to_problem(p) -> ChProblem:
                      krylov_rtol=float(g("krylov_rtol", 0.0)),
                      krylov_max=int(g("krylov_max", 200)), f_zero=int(bool(g("f_zero", False))),
                      nl_krylov_rtol=float(g("nl_krylov_rtol", 1e-9)),
-                     nn_base=int(g("nn_base", 0)))
+                     nn_base=int(g("nn_base", 0)),
+                     dd_subdomains=int(g("dd_subdomains", 0)), dd_theta=float(g("dd_theta", 0.0)),
+                     dd_tol=float(g("dd_tol", 0.0)), dd_max=int(g("dd_max", 0)))
 
 
 def _ptr(t):
@@ -266,6 +271,14 @@ class Context:
         self._check(self.lib.ch_judge_read(self.h, inst, r, ctypes.byref(fb), ctypes.byref(now),
                                            _stream(stream)))
         return list(r), (fb.value if fb.value >= 0 else None), bool(now.value)
+
+    def ch_dd_iterations(self, inst=0, stream=None):
+        """Neumann-Neumann iterations of each slice's J fine steps in the
+        latest fine sweep (list of N ints)."""
+        N = self.problems[inst].n_slices
+        r = (ctypes.c_int32 * N)()
+        self._check(self.lib.ch_dd_iterations(self.h, inst, r, _stream(stream)))
+        return list(r)
 
     def ch_set_wait_limit(self, group_seconds=0.2, pipe_seconds=10.0, stream=None):
         self._check(self.lib.ch_set_wait_limit(self.h, float(group_seconds), float(pipe_seconds),

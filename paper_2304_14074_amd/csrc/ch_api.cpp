@@ -50,6 +50,7 @@ struct ch_ctx {
   int64_t slice_total = 0, iter_total = 0;
   std::vector<ClassPlan> classes;
   Block inst_blk, active_blk, status_blk, k_blk;
+  Block dd_blk;                     // Neumann-Neumann iteration counts per slice
   std::vector<Block> rsig_fine_blk, rsig_stab_blk, tab_blk, work_blk;
   // learned coarse propagator
   Block nn_blk, nn_out_blk, nn_part_blk;
@@ -147,6 +148,9 @@ const char* ch_status_str(ch_status s) {
 
 const char* ch_last_error(const ch_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+// Neumann-Neumann parameters with their defaults (0 selects the default)
+static int dd_sub(const ch_problem& p) { return p.dd_subdomains > 0 ? p.dd_subdomains : 8; }
+
 ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
   if (!out) return CH_ERR_ARG;
   *out = nullptr;
@@ -164,8 +168,19 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
       bad = fail(c, CH_ERR_ARG, "instance %d: n_slices, j_fine, m_coarse must be >= 1", i);
     else if (p.krylov_max < 1 || !(p.krylov_rtol >= 0))
       bad = fail(c, CH_ERR_ARG, "instance %d: krylov_max >= 1 and krylov_rtol >= 0 needed", i);
-    else if (p.fine_kind < CH_FINE_LINEAR || p.fine_kind > CH_FINE_APPROX2)
+    else if (p.fine_kind < CH_FINE_LINEAR || p.fine_kind > CH_FINE_APPROX2_DD)
       bad = fail(c, CH_ERR_ARG, "instance %d: fine_kind %d", i, p.fine_kind);
+    else if (p.fine_kind == CH_FINE_APPROX2_DD && (p.dim != 1 || p.f_zero))
+      bad = fail(c, CH_ERR_UNSUPPORTED,
+                 "instance %d: the Neumann-Neumann fine step is 1D and has no f == 0 form", i);
+    else if (p.fine_kind == CH_FINE_APPROX2_DD &&
+             (p.dd_subdomains < 0 || p.dd_max < 0 || !(p.dd_tol >= 0) ||
+              !(p.dd_theta >= 0 && p.dd_theta < 1) ||
+              (p.n + 1) % dd_sub(p) != 0 || (p.n + 1) / dd_sub(p) < 2))
+      bad = fail(c, CH_ERR_ARG,
+                 "instance %d: Neumann-Neumann parameters (n + 1 = %d must split into N0 = %d "
+                 "pieces of >= 2 intervals; 0 <= theta < 1, tol >= 0, max >= 0)",
+                 i, p.n + 1, dd_sub(p));
     else if (p.coarse_kind < CH_COARSE_APPROX2 || p.coarse_kind > CH_COARSE_EYRE)
       bad = fail(c, CH_ERR_ARG, "instance %d: coarse_kind %d", i, p.coarse_kind);
     else if (p.precision != CH_PREC_FP64 && p.precision != CH_PREC_SPLIT_BF16)
@@ -225,6 +240,10 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
                    (p.fine_kind == CH_FINE_NONLINEAR || p.coarse_kind == CH_COARSE_EYRE))
                       ? 9 : chk::WORK_VECS;
     d.nn_base = p.nn_base;
+    d.dd_sub = dd_sub(p);
+    d.dd_max = p.dd_max > 0 ? p.dd_max : 100;
+    d.dd_theta = p.dd_theta > 0 ? p.dd_theta : 0.25;
+    d.dd_tol = p.dd_tol > 0 ? p.dd_tol : 1e-10;
     d.wait_ticks = chk::WAIT_TICKS_DEFAULT;
     d.pipe_wait_ticks = chk::PIPE_WAIT_TICKS_DEFAULT;
     d.off_slices = so; d.off_iter = io; d.slice_base = slice_base;
@@ -285,6 +304,9 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     c->rsig_fine_blk[i] = take(sizeof(double) * P);
     c->rsig_stab_blk[i] = take(sizeof(double) * P);
   }
+  // iteration counts of the Neumann-Neumann fine step, one per slice (zeroed
+  // with the host image)
+  c->dd_blk = take(sizeof(int32_t) * (size_t)slice_base);
   c->host_init_bytes = off;
   for (auto& cp : c->classes) {
     if (cp.dim != 2) continue;
@@ -400,6 +422,7 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
     d.tab = p.dim == 2 ? (double*)(ws + c->tab_blk[i].off) : nullptr;
     d.work = p.dim == 2 ? (double*)(ws + c->work_blk[i].off) : nullptr;
     d.status = (int32_t*)(ws + c->status_blk.off) + i;
+    d.dd_iters = (int32_t*)(ws + c->dd_blk.off) + d.slice_base;
     // inverse symbols 1/(1 + tau eps^2 Lam^2 - s tau Lam) of the linear step
     const int n = p.n;
     std::vector<double> lam(n);
@@ -526,6 +549,9 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
       if (cp.fine_groups == 1)
         e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
                                 mask, active, k_min, in_iter, s, cp.waves);
+    } else if (cp.fine_kind == CH_FINE_APPROX2_DD) {
+      e = chk::launch_fine_dd_1d(cp.n, items, (int)cp.items.size(), inst, U_in, F_out, mask,
+                                 active, k_min, in_iter, s);
     } else {
       e = chk::launch_fine_1d(cp.n, items, (int)cp.items.size(), inst, tab, nullptr, U_in, F_out,
                               mask, active, k_min, in_iter, s);
@@ -1337,6 +1363,21 @@ ch_status ch_judge_read(ch_ctx* c, int32_t inst, double* ratios, int32_t* fallba
   if (fallback_at) *fallback_at = jd.fallback_at;
   if (learned_now) *learned_now = kind == CH_COARSE_NEURAL;
   return CH_OK;
+}
+
+ch_status ch_dd_iterations(ch_ctx* c, int32_t inst, int32_t* iters, ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (inst < 0 || inst >= (int32_t)c->probs.size()) return fail(c, CH_ERR_ARG, "instance index");
+  if (!iters) return fail(c, CH_ERR_ARG, "null pointer");
+  if (c->probs[inst].fine_kind != CH_FINE_APPROX2_DD)
+    return fail(c, CH_ERR_ARG, "instance %d does not use the Neumann-Neumann fine step", inst);
+  hipStream_t s = (hipStream_t)stream;
+  r = hip_check(c, hipMemcpyAsync(iters, (int32_t*)(c->ws + c->dd_blk.off) + c->inst[inst].slice_base,
+                                  sizeof(int32_t) * c->probs[inst].n_slices, hipMemcpyDeviceToHost, s),
+                "iteration count read");
+  if (r == CH_OK) r = hip_check(c, hipStreamSynchronize(s), "iteration count sync");
+  return r;
 }
 
 ch_status ch_slice_distance(ch_ctx* c, const double* A, const double* B, double* out,

@@ -30,6 +30,11 @@ struct InstDev {
   // a group barrier (default 0.2 s) and a hand-off of the pipelined launch
   // (default 10 s); a wait that runs out flags status bit 4
   uint64_t wait_ticks, pipe_wait_ticks;
+  // Neumann-Neumann fine step: subdomains, iteration cap, relaxation, stop,
+  // per-slice iteration counts of the latest sweep
+  int32_t dd_sub, dd_max;
+  double dd_theta, dd_tol;
+  int32_t* dd_iters;
 };
 constexpr uint64_t WAIT_TICKS_DEFAULT = 20000000ull;
 constexpr uint64_t PIPE_WAIT_TICKS_DEFAULT = 1000000000ull;
@@ -70,6 +75,12 @@ hipError_t launch_fine_split_2d(int n, const WorkItem* items, int n_items, const
                                 const double* Tsin, const double* U_in, double* F_out,
                                 const uint8_t* mask, const int32_t* active, const int32_t* kmin,
                                 int in_iter, hipStream_t s);
+// 1D fine sweep with the Neumann-Neumann step (n <= 128, one workgroup of
+// 128 threads per item).
+hipError_t launch_fine_dd_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                             const double* U_in, double* F_out, const uint8_t* mask,
+                             const int32_t* active, const int32_t* kmin, int in_iter,
+                             hipStream_t s);
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                           const double* S, const double* rsig1, const double* U_in,
                           double* F_out, const uint8_t* mask, const int32_t* active,

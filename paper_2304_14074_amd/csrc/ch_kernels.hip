@@ -3342,6 +3342,256 @@ __global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
   }
 }
 
+// ------------------------------------------------ 1D Neumann-Neumann step
+// Scheme (2.4) in mixed form, [I, -tau L; eps^2 L - diag(c), I][u; v] =
+// [u_n; -u_n] with c = u_n^2, solved by the Neumann-Neumann iteration on N0
+// equal subdomains (Section 4).  Nodes 0..n+1, interfaces at p_q = q m,
+// m = (n+1)/N0.  Per node the unknowns form a 2-vector (u, v); the matrix is
+// block tridiagonal with the coupling E = [[0, -a], [b, 0]] (a = tau/h^2,
+// b = eps^2/h^2) to both neighbours and the diagonal block
+// [[w, e a], [-e b - w c_j, w]]: w = 1, e = 2 inside (and next to the
+// physical boundary), w = 1/2, e = 1 at an interface node of a Neumann
+// problem (half of the shared node, one edge of the subdomain).
+//
+// The subdomain matrices do not change during a step, so they are factored
+// once (block Thomas, 2x2 pivots) and the iteration runs on the interface
+// traces: the Dirichlet solution next to an interface is an affine function
+// of the subdomain's traces (its response to u_n and to a unit value of each
+// trace), and the Neumann solution at an interface is a linear function of
+// the subdomain's interface residuals (its response to unit residuals).  Each
+// iteration then computes the residuals, the Neumann corrections and the
+// trace update for all interfaces at once, one lane per interface; the
+// iterates are the method's own (up to rounding).  The step ends with the
+// subdomain states of the final traces.
+struct DD1 {
+  int n, N0, m, MD, MN;
+  double a, b;
+  double *ub, *fD, *fN, *rD, *tN, *nr, *tg, *th;
+};
+
+__device__ __forceinline__ DD1 dd1_layout(const InstDev& P, double tau, double* L) {
+  DD1 d;
+  d.n = P.n; d.N0 = P.dd_sub; d.m = (P.n + 1) / P.dd_sub; d.MD = d.m - 1; d.MN = d.m + 1;
+  d.a = tau / (P.h * P.h); d.b = P.eps * P.eps / (P.h * P.h);
+  d.ub = L;                                 // u_n on nodes 0..n+1
+  d.fD = d.ub + d.n + 2;                    // Dirichlet pivots: N0 x MD x 4
+  d.fN = d.fD + d.N0 * d.MD * 4;            // Neumann pivots:   N0 x MN x 4
+  d.rD = d.fN + d.N0 * d.MN * 4;            // Dirichlet responses: N0 x 5 x MD x 2
+  d.tN = d.rD + d.N0 * 5 * d.MD * 2;        // Neumann solves: N0 x 4 x MN x 2
+  d.nr = d.tN + d.N0 * 4 * d.MN * 2;        // Neumann interface responses: N0 x 4 x 4
+  d.tg = d.nr + d.N0 * 16;                  // traces g_q, q = 0..N0 (ends 0)
+  d.th = d.tg + d.N0 + 1;                   // traces h_q
+  return d;
+}
+
+// LDS doubles of the layout above for n (any N0 with m >= 2)
+__host__ __device__ constexpr size_t dd1_lds_doubles(int n) {
+  return (size_t)(n + 2) + 26 * (size_t)(n + 1) + 18 * (size_t)((n + 1) / 2) + 2 + 64;
+}
+
+// Block Thomas over M nodes with pivots F (inverse 2x2 blocks, row-major) and
+// the coupling E: X holds d on entry and the solution on exit.
+__device__ void dd1_solve(const DD1& d, const double* F, double* X, int M) {
+  for (int k = 1; k < M; ++k) {
+    // y_k = d_k - E Binv_{k-1} y_{k-1}
+    const double* p = F + (k - 1) * 4;
+    const double y0 = X[2 * k - 2], y1 = X[2 * k - 1];
+    const double t0 = p[2] * y0 + p[3] * y1, t1 = p[0] * y0 + p[1] * y1;
+    X[2 * k] += d.a * t0;
+    X[2 * k + 1] -= d.b * t1;
+  }
+  const double* p = F + (M - 1) * 4;
+  double x0 = p[0] * X[2 * M - 2] + p[1] * X[2 * M - 1];
+  double x1 = p[2] * X[2 * M - 2] + p[3] * X[2 * M - 1];
+  X[2 * M - 2] = x0; X[2 * M - 1] = x1;
+  for (int k = M - 2; k >= 0; --k) {
+    // x_k = Binv_k (y_k - E x_{k+1}),  E x = (-a x1, b x0)
+    const double r0 = X[2 * k] + d.a * x1, r1 = X[2 * k + 1] - d.b * x0;
+    p = F + k * 4;
+    x0 = p[0] * r0 + p[1] * r1;
+    x1 = p[2] * r0 + p[3] * r1;
+    X[2 * k] = x0; X[2 * k + 1] = x1;
+  }
+}
+
+// Factor one subdomain problem: nodes lo..hi, pivots to F.
+__device__ void dd1_factor(const DD1& d, double* F, int lo, int hi, bool neumann) {
+  double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+  for (int j = lo; j <= hi; ++j) {
+    const bool iface = neumann && (j % d.m == 0);
+    const double w = iface ? 0.5 : 1.0, e = iface ? 1.0 : 2.0;
+    const double cj = d.ub[j] * d.ub[j];
+    double B0 = w, B1 = e * d.a, B2 = -e * d.b - w * cj, B3 = w;
+    if (j > lo) {
+      // B -= (E Binv_prev) E;  E Binv = [[-a p2, -a p3], [b p0, b p1]]
+      const double W0 = -d.a * p2, W1 = -d.a * p3, W2 = d.b * p0, W3 = d.b * p1;
+      B0 -= d.b * W1; B1 += d.a * W0; B2 -= d.b * W3; B3 += d.a * W2;
+    }
+    const double det = B0 * B3 - B1 * B2, id = 1.0 / det;
+    p0 = B3 * id; p1 = -B1 * id; p2 = -B2 * id; p3 = B0 * id;
+    double* q = F + (j - lo) * 4;
+    q[0] = p0; q[1] = p1; q[2] = p2; q[3] = p3;
+  }
+}
+
+// One (2.4) step of the thread's node value u (node tid + 1); iters counts
+// the iterations, status bit 1 flags the cap or a non-finite update.
+__device__ double dd1_step(double u, const InstDev& P, double tau, double* L, int& iters,
+                           int& status) {
+  const DD1 d = dd1_layout(P, tau, L);
+  const int tid = threadIdx.x, N0 = d.N0, m = d.m, MD = d.MD, MN = d.MN, n = d.n;
+  __syncthreads();
+  if (tid < n) d.ub[tid + 1] = u;
+  if (tid == 0) { d.ub[0] = 0.0; d.ub[n + 1] = 0.0; }
+  __syncthreads();
+  for (int t = tid; t < 2 * N0; t += blockDim.x) {
+    const int i = t % N0;
+    if (t < N0) dd1_factor(d, d.fD + i * MD * 4, i * m + 1, (i + 1) * m - 1, false);
+    else if (N0 > 1) dd1_factor(d, d.fN + i * MN * 4, max(i * m, 1), min((i + 1) * m, n), true);
+  }
+  __syncthreads();
+  const int nd = 5 * N0;
+  for (int t = tid; t < 9 * N0; t += blockDim.x) {
+    if (t < nd) {
+      // Dirichlet responses of subdomain i: 0 = to u_n (traces zero), 1..4 =
+      // to a unit g, h of the left interface, g, h of the right one
+      const int i = t / 5, k = t % 5;
+      double* X = d.rD + (i * 5 + k) * MD * 2;
+      const int lo = i * m + 1;
+      for (int j = 0; j < MD; ++j) {
+        X[2 * j] = k == 0 ? d.ub[lo + j] : 0.0;
+        X[2 * j + 1] = k == 0 ? -d.ub[lo + j] : 0.0;
+      }
+      if ((i == 0 && (k == 1 || k == 2)) || (i == N0 - 1 && (k == 3 || k == 4))) continue;
+      // the coupling -E (g, h) of a trace moves to the right-hand side: (a h, -b g)
+      const int at = k <= 2 ? 0 : MD - 1;
+      if (k == 1 || k == 3) X[2 * at + 1] = -d.b;
+      if (k == 2 || k == 4) X[2 * at] = d.a;
+      dd1_solve(d, d.fD + i * MD * 4, X, MD);
+    } else {
+      // Neumann responses of subdomain i to a unit residual: 0, 1 = u, v rows
+      // of its left interface node, 2, 3 = of its right one; kept at both ends
+      const int i = (t - nd) / 4, e = (t - nd) % 4;
+      double* out = d.nr + (i * 4 + e) * 4;
+      if (N0 == 1 || (i == 0 && e < 2) || (i == N0 - 1 && e >= 2)) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        continue;
+      }
+      const int lo = max(i * m, 1), M = min((i + 1) * m, n) - lo + 1;
+      double* X = d.tN + (i * 4 + e) * MN * 2;
+      for (int j = 0; j < 2 * M; ++j) X[j] = 0.0;
+      X[(e < 2 ? 0 : 2 * (M - 1)) + (e & 1)] = 1.0;
+      dd1_solve(d, d.fN + i * MN * 4, X, M);
+      out[0] = X[0]; out[1] = X[1]; out[2] = X[2 * M - 2]; out[3] = X[2 * M - 1];
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // lane q: interface q (1..N0-1); the other lanes carry zeros
+    const int q = tid;
+    const bool on = q >= 1 && q < N0;
+    double g = 0.0, h = 0.0, up = 0.0, cp = 0.0;
+    double RL[5][2], RR[5][2], NL[4][2], NRt[4][2];
+    if (on) {
+      const int p = q * m;
+      up = d.ub[p];
+      cp = up * up;
+      g = up;
+      h = -d.b * (d.ub[p - 1] - 2.0 * up + d.ub[p + 1]) + up * up * up - up;
+      for (int k = 0; k < 5; ++k)
+        for (int s = 0; s < 2; ++s) {
+          RL[k][s] = d.rD[(((q - 1) * 5 + k) * MD + MD - 1) * 2 + s];
+          RR[k][s] = d.rD[((q * 5 + k) * MD) * 2 + s];
+        }
+      for (int e = 0; e < 4; ++e)
+        for (int s = 0; s < 2; ++s) {
+          NL[e][s] = d.nr[((q - 1) * 4 + e) * 4 + 2 + s];
+          NRt[e][s] = d.nr[(q * 4 + e) * 4 + s];
+        }
+    } else {
+      for (int k = 0; k < 5; ++k) RL[k][0] = RL[k][1] = RR[k][0] = RR[k][1] = 0.0;
+      for (int e = 0; e < 4; ++e) NL[e][0] = NL[e][1] = NRt[e][0] = NRt[e][1] = 0.0;
+    }
+    const double th = P.dd_theta;
+    int it = 0;
+    while (N0 > 1) {
+      // Dirichlet states next to the interface from the current traces
+      const double gl = __shfl(g, (q + 63) & 63, 64), hl = __shfl(h, (q + 63) & 63, 64);
+      const double gr = __shfl(g, (q + 1) & 63, 64), hr = __shfl(h, (q + 1) & 63, 64);
+      double Lv[2], Rv[2];
+      for (int s = 0; s < 2; ++s) {
+        Lv[s] = RL[0][s] + gl * RL[1][s] + hl * RL[2][s] + g * RL[3][s] + h * RL[4][s];
+        Rv[s] = RR[0][s] + g * RR[1][s] + h * RR[2][s] + gr * RR[3][s] + hr * RR[4][s];
+      }
+      // residual of the global equations at p_q: the jump of the Neumann traces
+      double ru = up - (g - d.a * (Lv[1] - 2.0 * h + Rv[1]));
+      double rv = -up - (d.b * (Lv[0] - 2.0 * g + Rv[0]) - cp * g + h);
+      if (!on) ru = rv = 0.0;
+      const double rul = __shfl(ru, (q + 63) & 63, 64), rvl = __shfl(rv, (q + 63) & 63, 64);
+      const double rur = __shfl(ru, (q + 1) & 63, 64), rvr = __shfl(rv, (q + 1) & 63, 64);
+      // Neumann corrections of both neighbours at p_q, relaxed by theta
+      double dg = 0.0, dh = 0.0;
+      if (on) {
+        dg = th * (NL[0][0] * rul + NL[1][0] * rvl + NL[2][0] * ru + NL[3][0] * rv +
+                   NRt[0][0] * ru + NRt[1][0] * rv + NRt[2][0] * rur + NRt[3][0] * rvr);
+        dh = th * (NL[0][1] * rul + NL[1][1] * rvl + NL[2][1] * ru + NL[3][1] * rv +
+                   NRt[0][1] * ru + NRt[1][1] * rv + NRt[2][1] * rur + NRt[3][1] * rvr);
+      }
+      g += dg;
+      h += dh;
+      ++it;
+      // max |dg|, max |dh| over the interfaces; a NaN anywhere survives the sum
+      double mg = fabs(dg), mh = fabs(dh), bad = dg * 0.0 + dh * 0.0;
+      for (int o = 32; o > 0; o >>= 1) {
+        mg = fmax(mg, __shfl_xor(mg, o, 64));
+        mh = fmax(mh, __shfl_xor(mh, o, 64));
+        bad += __shfl_xor(bad, o, 64);
+      }
+      if (!(bad == 0.0)) { status |= 1; break; }
+      if (mg <= P.dd_tol && mh <= P.dd_tol) break;
+      if (it >= P.dd_max) { status |= 1; break; }
+    }
+    iters += it;
+    if (on) { d.tg[q] = g; d.th[q] = h; }
+    if (tid == 0) { d.tg[0] = d.th[0] = d.tg[N0] = d.th[N0] = 0.0; }
+  }
+  __syncthreads();
+  if (tid < n) {
+    const int j = tid + 1, i = j / m;
+    if (j % m == 0) return d.tg[i];
+    const int k = j - i * m - 1;
+    const double c[5] = {1.0, d.tg[i], d.th[i], d.tg[i + 1], d.th[i + 1]};
+    double v = 0.0;
+    for (int r = 0; r < 5; ++r) v += c[r] * d.rD[((i * 5 + r) * MD + k) * 2];
+    return v;
+  }
+  return 0.0;
+}
+
+// Fine propagator of one work item with the Neumann-Neumann step: J steps;
+// the iterations of the J steps go to dd_iters[slice].
+__global__ void __launch_bounds__(128)
+k_fine_dd_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+             const double* __restrict__ U_in, double* __restrict__ F_out,
+             const uint8_t* __restrict__ mask, const int32_t* __restrict__ active,
+             const int32_t* __restrict__ kmin, int in_iter) {
+  extern __shared__ double smem[];
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
+  const int n = P.n;
+  const int64_t in0 = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * n;
+  double u = (int)threadIdx.x < n ? U_in[in0 + threadIdx.x] : 0.0;
+  int status = 0, iters = 0;
+  for (int s = 0; s < P.j_fine; ++s) u = dd1_step(u, P, P.dt, smem, iters, status);
+  if ((int)threadIdx.x < n) F_out[P.off_slices + (int64_t)it.slice * n + threadIdx.x] = u;
+  if (threadIdx.x == 0) {
+    P.dd_iters[it.slice] = iters;
+    if (status) atomicOr(P.status, status);
+  }
+}
+
 // --------------------------------------------------------------- energy
 // E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u); one block per state.
 // Per-slice distance ||A_n - B_n||_h (h^d-weighted L2, the norm of the update
@@ -3592,6 +3842,18 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fine_1d, dim3(n_items), dim3((n + 63) / 64 * 64), lds, s, items, inst, S,
                      lam, U_in, F_out, mask, active, kmin, in_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_dd_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
+                             const double* U_in, double* F_out, const uint8_t* mask,
+                             const int32_t* active, const int32_t* kmin, int in_iter,
+                             hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (n < 1 || n > 128) return hipErrorInvalidValue;
+  const size_t lds = dd1_lds_doubles(n) * sizeof(double);
+  hipLaunchKernelGGL(k_fine_dd_1d, dim3(n_items), dim3(128), lds, s, items, inst, U_in, F_out,
+                     mask, active, kmin, in_iter);
   return hipGetLastError();
 }
 

@@ -3,7 +3,8 @@ convergence bounds of Section 3.
 
 For each of the five pairings of Section 2.1 (PA-I: F = G = (2.4); PA-II:
 F = G = (2.5); PA-III: F = (2.5), G = (2.4); NPA-I: F = (2.3), G = (2.4);
-NPA-II: F = G = (2.3)) a case runs the Parareal iteration (2.2) and records,
+NPA-II: F = G = (2.3)), and PA-I with the Neumann-Neumann solve of the fine
+step (Section 4, "PA-I-NN"), a case runs the Parareal iteration (2.2) and records,
 per iteration k, the update norm and the error against the fine solution,
 E^k = max_n ||U(T_n) - U_n^k||_h (the L^inf(0,T; L^2) norm of Section 4 at the
 T_n), until E^k < 1e-6 (the paper's stop) or k = N.  U(T_n) is the serial
@@ -36,6 +37,8 @@ PAIRINGS = {
     "PA-III": ("linear", "approx2", (2.0, 1.0)),
     "NPA-I": ("nonlinear", "approx2", None),
     "NPA-II": ("nonlinear", "eyre", None),
+    # the fine step (2.4) solved by Neumann-Neumann (8 subdomains, theta = 1/4)
+    "PA-I-NN": ("approx2_dd", "approx2", (1.0, 1.0)),
 }
 
 
@@ -215,6 +218,12 @@ def paper_cases() -> list:
     # 2D: T = 1, N = 20, J = 200
     for p in ("PA-I", "PA-II", "PA-III", "NPA-I"):
         cases.append(Case(p, dim=2, n=32))
+    # Neumann-Neumann fine solver in PA-I (h = 1/128, N0 = 8, theta = 1/4):
+    # T, N sweep at J = 200 (dT = 0.05) and a dT sweep at T = 1, J = 150
+    for T in (1.0, 2.0, 8.0):
+        cases.append(Case("PA-I-NN", n=127, T=T, N=int(round(20 * T))))
+    for N in (10, 40):
+        cases.append(Case("PA-I-NN", n=127, N=N, J=150))
     return cases
 
 

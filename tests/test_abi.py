@@ -62,7 +62,15 @@ def test_create_and_layout_host_only():
 
 @pytest.mark.parametrize("kw,code", [
     (dict(dim=3), 3), (dict(n=96), 3), (dict(eps=0.0), 1), (dict(n_slices=0), 1),
-    (dict(j_fine=0), 1), (dict(dim=1, n=129), 3), (dict(m_coarse=0), 1)])
+    (dict(j_fine=0), 1), (dict(dim=1, n=129), 3), (dict(m_coarse=0), 1),
+    # Neumann-Neumann fine step: 1D only, no f == 0 form, n + 1 split into
+    # N0 pieces of >= 2 intervals, 0 <= theta < 1
+    (dict(fine_kind="approx2_dd"), 3), (dict(dim=1, n=63, fine_kind="approx2_dd", f_zero=True), 3),
+    (dict(dim=1, n=63, fine_kind="approx2_dd", dd_subdomains=3), 1),
+    (dict(dim=1, n=63, fine_kind="approx2_dd", dd_subdomains=64), 1),
+    (dict(dim=1, n=63, fine_kind="approx2_dd", dd_theta=1.0), 1),
+    (dict(dim=1, n=63, fine_kind="approx2_dd", dd_tol=-1.0), 1),
+    (dict(dim=1, n=63, fine_kind="approx2_dd", dd_max=-1), 1)])
 def test_create_rejects_bad_problems(kw, code):
     import workloads
     p = workloads.Problem(dim=2, n=64, n_slices=2, j_fine=2)
@@ -71,6 +79,18 @@ def test_create_rejects_bad_problems(kw, code):
     lib, st, h = _create([p])
     assert st == code
     assert not h.value
+
+
+def test_dd_problems_accepted_host_only():
+    import workloads
+    from paper_2304_14074_amd import chlib
+    for n, k in ((127, 8), (127, 64), (63, 1), (15, 2), (31, 16)):
+        lib, st, h = _create([workloads.Problem(dim=1, n=n, n_slices=3, j_fine=2,
+                                                fine_kind="approx2_dd", dd_subdomains=k)])
+        assert st == chlib.CH_OK, (n, k)
+        it = (ctypes.c_int32 * 3)()
+        assert lib.ch_dd_iterations(h, 0, it, None) == chlib.CH_ERR_STATE
+        lib.ch_destroy(h)
 
 
 def test_status_strings():

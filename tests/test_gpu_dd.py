@@ -1,0 +1,172 @@
+"""The Neumann-Neumann fine step (Section 4, NN method as fine solver of
+PA-I) on the GPU through the C ABI, against the FP64 oracle: fine sweeps over
+several subdomain counts (one subdomain up to the maximum of two intervals
+each), the iteration counts, the closed forms (one subdomain = the direct
+solve of (2.4); mirror-image halves = two iterations per step), Parareal
+iterates, and at the paper's size (h = 1/128, N0 = 8, theta = 1/4,
+eps = 0.0725, T = 1, N = 20, J = 200) the converged run against the serial
+Neumann-Neumann solution with the first slice checked against the oracle."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import operators, parareal, propagators
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+EPS = 0.0725
+
+
+def _prob(n, n_sub, N, J, dt=2.5e-4, **kw):
+    return workloads.Problem(dim=1, n=n, eps=EPS, T=N * J * dt, n_slices=N, j_fine=J,
+                             fine_kind="approx2_dd", dd_subdomains=n_sub, **kw)
+
+
+def _states(n, k, seed):
+    rng = np.random.default_rng(seed)
+    x = np.arange(1, n + 1) / (n + 1)
+    out = [0.5 * rng.uniform(-1, 1, n) for _ in range(k - 1)]
+    out.append(0.8 * np.sin(3 * np.pi * x) + 0.1 * rng.uniform(-1, 1, n))
+    return np.stack(out)
+
+
+def _oracle_fine(p, u):
+    its = []
+    v = propagators.fine(p, u, dd_iters=its)
+    return v, sum(its)
+
+
+@pytest.mark.parametrize("n,n_sub,J,dt", [(127, 8, 6, 2.5e-4), (127, 8, 4, 1e-3), (63, 4, 6, 2.5e-4),
+                                          (31, 16, 5, 1e-5), (15, 2, 8, 1e-3), (127, 64, 2, 1e-6),
+                                          (63, 1, 4, 1e-3)])
+def test_dd_fine_sweep_matches_oracle(n, n_sub, J, dt):
+    from paper_2304_14074_amd import chlib
+    p = _prob(n, n_sub, 3, J, dt)
+    ctx = chlib.Context([p])
+    X = _states(n, 3, 700 + n + n_sub)
+    print(f"dd fine n={n} N0={n_sub} J={J} dt={dt}", flush=True)
+    out = gu.fine(ctx, [X])[0]
+    assert ctx.ch_check_status() == [0]
+    its = ctx.ch_dd_iterations(0)
+    for s in range(3):
+        ref, it = _oracle_fine(p, X[s])
+        assert gu.rel(out[s], ref) < TOL, (s, gu.rel(out[s], ref))
+        # floating point decides the counts on both sides (same FP64 stop
+        # test, different rounding order): equal unless an update lands
+        # within rounding of the tolerance
+        assert abs(its[s] - it) <= 1, (s, its[s], it)
+        if n_sub == 1:
+            assert its[s] == 0
+
+
+def test_dd_single_subdomain_equals_the_cg_solved_pa_i_step():
+    from paper_2304_14074_amd import chlib
+    n, J = 127, 5
+    p = _prob(n, 1, 2, J, 1e-3)
+    q = copy.copy(p)
+    q.fine_kind = "approx2"
+    X = _states(n, 2, 41)
+    a = gu.fine(chlib.Context([p]), [X])[0]
+    b = gu.fine(chlib.Context([q]), [X])[0]
+    for s in range(2):
+        assert gu.rel(a[s], b[s]) < TOL
+
+
+def test_dd_mirror_halves_take_two_iterations_per_step():
+    # mirror-symmetric data on two equal subdomains: the two local Neumann
+    # maps coincide, theta = 1/4 makes the first update exact, the second is
+    # zero up to rounding
+    from paper_2304_14074_amd import chlib
+    n, J = 127, 7
+    x = np.arange(1, n + 1) / (n + 1)
+    u = 0.6 * np.cos(2 * np.pi * x) + 0.2 * np.sin(np.pi * x)
+    p = _prob(n, 2, 1, J, 1e-3)
+    ctx = chlib.Context([p])
+    out = gu.fine(ctx, [u[None]])[0][0]
+    assert ctx.ch_dd_iterations(0) == [2 * J]
+    assert np.max(np.abs(out - out[::-1])) < 1e-13
+    assert gu.rel(out, propagators.fine(p, u)) < TOL
+
+
+def test_dd_parareal_iterates_match_oracle():
+    from paper_2304_14074_amd import chlib
+    n, N, J = 63, 4, 5
+    p = _prob(n, 8, N, J, 5e-4)
+    u0 = workloads.u0_uniform(n, 1, 0.4, 23)
+    ctx = chlib.Context([p])
+    st = ctx.new_state()
+    st["U"][:n] = torch.from_numpy(u0).cuda()
+    ref = parareal.parareal(u0, N, lambda u: propagators.fine(p, u),
+                            lambda u: propagators.coarse(p, u),
+                            lambda v: operators.norm_h(v, 1), tol=0.0, kmax=N)
+    print("dd parareal n=63", flush=True)
+    ctx.ch_parareal_iterate(st, 0.0)
+    for k in range(1, N + 1):
+        ctx.ch_parareal_iterate(st, 0.0)
+        torch.cuda.synchronize()
+        U = gu.unpack_iter(ctx, st["U"])[0]
+        for j in range(N + 1):
+            assert gu.rel(U[j], ref["U"][k][j]) < TOL, (k, j, gu.rel(U[j], ref["U"][k][j]))
+    assert ctx.ch_check_status(st) == [0]
+
+
+def test_dd_paper_size_run_reaches_the_serial_nn_solution():
+    # h = 1/128, N0 = 8, theta = 1/4, eps = 0.0725, T = 1, N = 20, J = 200
+    from paper_2304_14074_amd import chlib
+    n, N, J = 127, 20, 200
+    p = workloads.Problem(dim=1, n=n, eps=EPS, T=1.0, n_slices=N, j_fine=J,
+                          fine_kind="approx2_dd", dd_subdomains=8)
+    x = np.arange(1, n + 1) / (n + 1)
+    u0 = 0.9 * np.sin(2 * np.pi * x)
+    # serial fine solution on the GPU, slice by slice
+    one = copy.copy(p)
+    one.n_slices, one.T = 1, p.dT
+    c1 = chlib.Context([one])
+    cur = torch.from_numpy(u0).cuda()
+    serial = [u0]
+    nxt = torch.empty_like(cur)
+    for _ in range(N):
+        c1.ch_fine_propagate(cur, nxt)
+        cur, nxt = nxt, cur
+        serial.append(cur.cpu().numpy().copy())
+    assert c1.ch_check_status() == [0]
+    # the first slice against the oracle (200 Neumann-Neumann steps)
+    ref1, _ = _oracle_fine(p, u0)
+    assert gu.rel(serial[1], ref1) < TOL
+    ctx = chlib.Context([p])
+    st = ctx.new_state()
+    st["U"][:n] = torch.from_numpy(u0).cuda()
+    print("dd parareal paper size", flush=True)
+    ctx.ch_parareal_iterate(st, 1e-10)
+    k = 0
+    while k < N:
+        ctx.ch_parareal_iterate(st, 1e-10)
+        k += 1
+        if st["delta"][0].item() < 1e-10:
+            break
+    assert ctx.ch_check_status(st) == [0]
+    U = gu.unpack_iter(ctx, st["U"])[0]
+    err = max(operators.norm_h(U[j] - serial[j], 1) for j in range(N + 1))
+    print(f"k = {k}, error against the serial solution {err:.2e}", flush=True)
+    # the last update is below 1e-10 and the iteration contracts: the error
+    # is of that order
+    assert err < 1e-9, err
+    assert k < N      # converges before finite termination
+
+
+def test_dd_cap_is_reported():
+    from paper_2304_14074_amd import chlib
+    n = 127
+    p = _prob(n, 8, 2, 2, 1e-2, dd_max=2)
+    ctx = chlib.Context([p])
+    X = _states(n, 2, 5)
+    gu.fine(ctx, [X])
+    with pytest.raises(chlib.CHError) as e:
+        ctx.ch_check_status()
+    assert e.value.status == chlib.CH_ERR_NOCONV
+    assert ctx.ch_dd_iterations(0) == [4, 4]

@@ -26,3 +26,17 @@ def test_pa2_small_eps_reported_as_diverged():
     r = study.run_case(study.Case("PA-II", N=50, eps=0.03))
     assert r["diverged"] and r["iterations_to_1e-6"] is None
     assert r["errors"][0] is not None and math.isfinite(r["errors"][0])
+
+
+def test_pa1_nn_matches_pa1_iterations():
+    # PA-I with the Neumann-Neumann fine solve (h = 1/128, N0 = 8) converges
+    # like PA-I with the direct fine solve (the paper's observation): the same
+    # number of iterations to the 1e-6 stop, errors within the PA-I bound
+    from paper_2304_14074_amd import study
+    a = study.run_case(study.Case("PA-I-NN", n=127, amp=0.9, seed=None))
+    b = study.run_case(study.Case("PA-I", n=127, amp=0.9, seed=None))
+    print(a["iterations_to_1e-6"], b["iterations_to_1e-6"], flush=True)
+    assert a["iterations_to_1e-6"] == b["iterations_to_1e-6"] is not None
+    assert a["within_bound"]
+    for ea, eb in zip(a["errors"], b["errors"]):
+        assert abs(ea - eb) <= 1e-3 * eb + 1e-9
