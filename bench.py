@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import copy
 import json
+import math
 import os
 import sys
 import time
@@ -31,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fine grid-point-steps/s; Parareal time-to-1e-8 (neural G vs plain G), 1 GPU"
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
+FP64_VECTOR_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 flop/clk)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes of one fine-sweep launch of the 128x128 workload, from FETCH_SIZE and
 # WRITE_SIZE counter runs calibrated by a 1 GiB copy, for the kernel as it is now;
@@ -326,6 +328,98 @@ def batched_fine_sweep() -> dict:
             "finite": bool(torch.isfinite(Fs).all().item())}
 
 
+def dd_flops_per_step(n: int, n_sub: int, iters: float) -> float:
+    """Floating-point operations of one Neumann-Neumann step (2.4) as the
+    kernel performs them: 2 N0 block-Thomas factorisations (20 flop per node),
+    9 N0 solves (16 flop per node: 6 forward, 10 back), 60 flop per interface
+    and iteration (residual, two Neumann corrections, update), 10 per node to
+    assemble the result."""
+    return 20.0 * 2 * (n + 1) + 16.0 * 9 * (n + 1) + 60.0 * (n_sub - 1) * iters + 10.0 * n
+
+
+def dd_fine_leg(n_slices: int = 1024) -> dict:
+    """Neumann-Neumann fine solver of PA-I (Section 4) at the paper's setting
+    (1D, h = 1/128, N0 = 8, theta = 1/4, tol 1e-10, eps = 0.0725, dT = 0.05,
+    J = 200): one ch_fine_propagate over n_slices slices of 0.5 * Uniform(-1, 1)
+    states (seed 9000), HIP events on its stream; and a PA-I-NN Parareal run
+    (T = 1, N = 20, u0 = 0.9 sin(2 pi x)) to an update norm below 1e-10,
+    timed against the serial fine solve on the GPU."""
+    import torch
+    import workloads
+    from paper_2304_14074_amd import chlib
+    n, J = 127, 200
+    p = workloads.Problem(dim=1, n=n, eps=0.0725, T=0.05 * n_slices, n_slices=n_slices, j_fine=J,
+                          fine_kind="approx2_dd", dd_subdomains=8)
+    ctx = chlib.Context([p])
+    rng = np.random.default_rng(9000)
+    U = torch.from_numpy(0.5 * rng.uniform(-1, 1, n_slices * n)).cuda()
+    F = torch.empty_like(U)
+    stream = torch.cuda.current_stream()
+    ctx.ch_fine_propagate(U, F)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.ch_fine_propagate(U, F)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.ch_check_status()
+    ms = e0.elapsed_time(e1)
+    its = ctx.ch_dd_iterations(0)
+    it_per_step = sum(its) / (n_slices * J)
+    flops = n_slices * J * dd_flops_per_step(n, 8, it_per_step)
+    tf = flops / (ms / 1e3) / 1e12
+    # PA-I-NN run at T = 1, N = 20
+    q = workloads.Problem(dim=1, n=n, eps=0.0725, T=1.0, n_slices=20, j_fine=J,
+                          fine_kind="approx2_dd", dd_subdomains=8)
+    x = np.arange(1, n + 1) / (n + 1)
+    u0 = 0.9 * np.sin(2 * np.pi * x)
+    one = copy.copy(q)
+    one.n_slices, one.T = 1, q.dT
+    c1 = chlib.Context([one])
+    traj = torch.empty((21, n), dtype=torch.float64, device="cuda")
+    traj[0] = torch.from_numpy(u0).cuda()
+    c1.ch_fine_propagate(traj[0], traj[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(20):
+        c1.ch_fine_propagate(traj[k], traj[k + 1])
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - t0
+    c2 = chlib.Context([q])
+    st = c2.new_state()
+    st["U"][:n] = traj[0]
+    c2.ch_parareal_iterate(st, 1e-10)
+    c2.ch_parareal_iterate(st, 1e-10)
+    torch.cuda.synchronize()
+    st = c2.new_state()
+    st["U"][:n] = traj[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c2.ch_parareal_iterate(st, 1e-10)
+    k = 0
+    while k < 20:
+        c2.ch_parareal_iterate(st, 1e-10)
+        k += 1
+        if st["delta"][0].item() < 1e-10:
+            break
+    torch.cuda.synchronize()
+    par_s = time.perf_counter() - t0
+    c2.ch_check_status(st)
+    err = float((st["U"][20 * n:21 * n] - traj[20]).norm().item() * math.sqrt(1.0 / (n + 1)))
+    return {"workload": f"Neumann-Neumann fine step of PA-I, 1D h=1/128, N0=8, theta=1/4, "
+                        f"tol 1e-10, eps=0.0725, dT=0.05, J=200; {n_slices} slices in one "
+                        "ch_fine_propagate",
+            "ms": ms, "fine_steps_per_s": n_slices * J / (ms / 1e3),
+            "us_per_step_per_slice": ms * 1e3 / J, "nn_iterations_per_step": it_per_step,
+            "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf / FP64_VECTOR_TFLOPS, "traffic": None,
+                         "kernel": "k_fine_dd_1d"},
+            "pa1_nn_run": {"config": "T=1, N=20, u0=0.9 sin(2 pi x), stop: update norm < 1e-10",
+                           "iterations": k, "parareal_s": par_s, "serial_fine_s": serial_s,
+                           "speedup_vs_serial_on_gpu": serial_s / par_s,
+                           "final_error_vs_serial": err}}
+
+
 def bench_batched(args):
     """256 independent instances of uneven size (n in {64, 128, 256}, N in
     {32, 64, 128}, eps ~ U(0.01, 0.04), J = 1563), FP64 linear fine step,
@@ -424,10 +518,12 @@ def main():
     ap.add_argument("--no-neural", action="store_true", help="skip the learned coarse propagator leg")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the fine sweep of the 256-instance batch")
+    ap.add_argument("--no-dd", action="store_true",
+                    help="skip the Neumann-Neumann fine solver leg")
     ap.add_argument("--nn-traj", type=int, default=2000)
     ap.add_argument("--nn-steps", type=int, default=3000)
     ap.add_argument("--workload", default="linear_2d_128",
-                    choices=["linear_2d_128", "batched", "nonlinear", "hbm", "study"])
+                    choices=["linear_2d_128", "batched", "nonlinear", "hbm", "study", "dd"])
     ap.add_argument("--nl-steps", type=int, default=20,
                     help="implicit steps per slice timed in --workload nonlinear")
     ap.add_argument("--profile-fine", action="store_true",
@@ -454,6 +550,9 @@ def main():
         return
     if args.workload == "study":
         print(json.dumps(bench_study(args)))
+        return
+    if args.workload == "dd":
+        print(json.dumps(dd_fine_leg()))
         return
     if args.profile_fine:
         # one fine-sweep launch of the workload plus a plain 1 GiB device copy
@@ -608,6 +707,8 @@ def main():
                       "split_bf16_mfma_tflops": bflops / (sms / 1e3) / 1e12})
     if not args.no_batched:
         extra["batched_fine_sweep"] = batched_fine_sweep()
+    if not args.no_dd:
+        extra["nn_dd_fine"] = dd_fine_leg()
     if not args.no_neural:
         # learned coarse propagator at the configured workload (2000
         # trajectories, eps = 0.02) and at the paper's eps = 0.0725, where the

@@ -3392,17 +3392,20 @@ __host__ __device__ constexpr size_t dd1_lds_doubles(int n) {
 // Block Thomas over M nodes with pivots F (inverse 2x2 blocks, row-major) and
 // the coupling E: X holds d on entry and the solution on exit.
 __device__ void dd1_solve(const DD1& d, const double* F, double* X, int M) {
+  // the running y_k stays in registers (no LDS round trip on the chain)
+  double y0 = X[0], y1 = X[1];
   for (int k = 1; k < M; ++k) {
     // y_k = d_k - E Binv_{k-1} y_{k-1}
     const double* p = F + (k - 1) * 4;
-    const double y0 = X[2 * k - 2], y1 = X[2 * k - 1];
     const double t0 = p[2] * y0 + p[3] * y1, t1 = p[0] * y0 + p[1] * y1;
-    X[2 * k] += d.a * t0;
-    X[2 * k + 1] -= d.b * t1;
+    y0 = X[2 * k] + d.a * t0;
+    y1 = X[2 * k + 1] - d.b * t1;
+    X[2 * k] = y0;
+    X[2 * k + 1] = y1;
   }
   const double* p = F + (M - 1) * 4;
-  double x0 = p[0] * X[2 * M - 2] + p[1] * X[2 * M - 1];
-  double x1 = p[2] * X[2 * M - 2] + p[3] * X[2 * M - 1];
+  double x0 = p[0] * y0 + p[1] * y1;
+  double x1 = p[2] * y0 + p[3] * y1;
   X[2 * M - 2] = x0; X[2 * M - 1] = x1;
   for (int k = M - 2; k >= 0; --k) {
     // x_k = Binv_k (y_k - E x_{k+1}),  E x = (-a x1, b x0)
@@ -3513,6 +3516,8 @@ __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, in
       for (int e = 0; e < 4; ++e) NL[e][0] = NL[e][1] = NRt[e][0] = NRt[e][1] = 0.0;
     }
     const double th = P.dd_theta;
+    int W = 1;                            // power of two >= N0 (<= 64)
+    while (W < N0) W <<= 1;
     int it = 0;
     while (N0 > 1) {
       // Dirichlet states next to the interface from the current traces
@@ -3540,15 +3545,14 @@ __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, in
       g += dg;
       h += dh;
       ++it;
-      // max |dg|, max |dh| over the interfaces; a NaN anywhere survives the sum
-      double mg = fabs(dg), mh = fabs(dh), bad = dg * 0.0 + dh * 0.0;
-      for (int o = 32; o > 0; o >>= 1) {
-        mg = fmax(mg, __shfl_xor(mg, o, 64));
-        mh = fmax(mh, __shfl_xor(mh, o, 64));
-        bad += __shfl_xor(bad, o, 64);
-      }
-      if (!(bad == 0.0)) { status |= 1; break; }
-      if (mg <= P.dd_tol && mh <= P.dd_tol) break;
+      // max over the interfaces of max(|dg|, |dh|) (both traces meet the
+      // tolerance iff it does; a non-finite change counts as infinite),
+      // reduced over the lanes 0..W-1 holding them and broadcast from lane 0
+      double mx = (dg == dg && dh == dh) ? fmax(fabs(dg), fabs(dh)) : INFINITY;
+      for (int o = 1; o < W; o <<= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+      mx = __shfl(mx, 0, 64);
+      if (!(mx < INFINITY)) { status |= 1; break; }
+      if (mx <= P.dd_tol) break;
       if (it >= P.dd_max) { status |= 1; break; }
     }
     iters += it;
