@@ -53,22 +53,54 @@ def fine_flops_per_point_step(n: int) -> float:
     return 4.0 * n
 
 
-def cpu_baseline(prob, u0, budget_s: float = 12.0) -> dict:
-    """The oracle's fine propagator (sparse-LU linear step), timed as it is
-    on a bounded sample of the same workload: one slice, S fine steps."""
-    import numpy as np
+def _oracle_fine_worker(job):
+    """One CPU-baseline worker: the oracle's fine propagator on one slice for
+    `steps` steps; returns its seconds."""
+    prob, u0, steps = job
     from oracle import propagators
-    t0 = time.perf_counter()
-    propagators.fine(prob, u0, steps=10)
-    per = (time.perf_counter() - t0) / 10
-    steps = max(20, int(budget_s / max(per, 1e-6)))
+    propagators.fine(prob, u0, steps=1)        # the factorisation, cached
     t0 = time.perf_counter()
     propagators.fine(prob, u0, steps=steps)
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(prob, u0s, budget_s: float = 12.0) -> dict:
+    """The oracle's fine propagator (sparse-LU linear step) as it is, on a
+    bounded sample of the same workload: one slice per worker process (the
+    slices are independent, as on the GPU), S fine steps each, W workers
+    (the host's cores, at most 16) each with one thread."""
+    import multiprocessing
+    from oracle import propagators
+    propagators.fine(prob, u0s[0], steps=1)    # the factorisation, cached
+    t0 = time.perf_counter()
+    propagators.fine(prob, u0s[0], steps=10)
+    per = (time.perf_counter() - t0) / 10
+    steps = max(20, int(budget_s / max(per, 1e-6)))
+    workers = max(1, min(16, os.cpu_count() or 1))
+    jobs = [(prob, u0s[i % len(u0s)], steps) for i in range(workers)]
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    os.environ.update({"OMP_NUM_THREADS": "1", "OPENBLAS_NUM_THREADS": "1"})
+    try:
+        # forked before the process touches the GPU (main() runs this first)
+        with multiprocessing.get_context("fork").Pool(workers) as pool:
+            t0 = time.perf_counter()
+            secs = pool.map(_oracle_fine_worker, jobs, chunksize=1)
+            wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     pts = prob.n ** prob.dim
-    return {"value": steps * pts / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 slice x {steps} fine steps of the {prob.n}x{prob.n} linear step "
-                      f"(scipy sparse LU, single thread); host os.cpu_count()={os.cpu_count()}"}
+    # the rate of the timed steps: every worker's S steps over the slowest
+    # worker's time (the workers' start-up and factorisation are not counted)
+    return {"value": workers * steps * pts / max(secs), "unit": "grid-point-steps/s",
+            "cores": workers,
+            "kind": "oracle",
+            "sample": f"{workers} slices x {steps} fine steps of the {prob.n}x{prob.n} linear step, "
+                      f"one slice per process (scipy sparse LU, one thread each); slowest worker "
+                      f"{max(secs):.1f} s, wall {wall:.1f} s; host os.cpu_count()={os.cpu_count()}"}
 
 
 def serial_fine_trajectory(prob, u0):
@@ -366,6 +398,20 @@ def dd_fine_leg(n_slices: int = 1024) -> dict:
     ms = e0.elapsed_time(e1)
     its = ctx.ch_dd_iterations(0)
     it_per_step = sum(its) / (n_slices * J)
+    # the same sweep with the direct (2.4) step (one-lane block elimination)
+    pd = copy.copy(p)
+    pd.fine_kind = "approx2"
+    cd = chlib.Context([pd])
+    Fd = torch.empty_like(U)
+    cd.ch_fine_propagate(U, Fd)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    cd.ch_fine_propagate(U, Fd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    cd.ch_check_status()
+    ms_direct = e0.elapsed_time(e1)
+    dd_vs_direct = float(((F - Fd).norm() / Fd.norm()).item())
     flops = n_slices * J * dd_flops_per_step(n, 8, it_per_step)
     tf = flops / (ms / 1e3) / 1e12
     # PA-I-NN run at T = 1, N = 20
@@ -411,6 +457,7 @@ def dd_fine_leg(n_slices: int = 1024) -> dict:
                         "ch_fine_propagate",
             "ms": ms, "fine_steps_per_s": n_slices * J / (ms / 1e3),
             "us_per_step_per_slice": ms * 1e3 / J, "nn_iterations_per_step": it_per_step,
+            "direct_solve_sweep_ms": ms_direct, "rel_distance_nn_vs_direct": dd_vs_direct,
             "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_TFLOPS,
                          "unit": "TFLOP/s", "frac": tf / FP64_VECTOR_TFLOPS, "traffic": None,
                          "kernel": "k_fine_dd_1d"},
@@ -618,9 +665,21 @@ def main():
     import workloads
     from paper_2304_14074_amd import chlib
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     prob = workloads.linear_2d_128()
     u0 = workloads.linear_2d_128_u0(0)
+    t_start = time.perf_counter()
+
+    def progress(what):
+        print(f"bench: {what} done ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr,
+              flush=True)
+
+    # the CPU baseline first: its worker processes are forked before this
+    # process initialises the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, [workloads.u0_uniform(prob.n, 2, 0.05, i) for i in range(16)])
+        progress("CPU baseline")
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
     n, N, J = prob.n, prob.n_slices, prob.j_fine
     P = n * n
     ctx = chlib.Context([prob])
@@ -667,6 +726,7 @@ def main():
     done = ctx.ch_iteration_count(st)
     ctx.ch_check_status(st)                     # raises on any device-side failure
     assert done == args.steps, done
+    progress("timed pipelined run")
     ms_per_step = wall * 1e3 / args.steps
     value = point_steps / (ms_per_step / 1e3)
     achieved = flops * args.steps / (run_ms / 1e3) / 1e12
@@ -705,18 +765,23 @@ def main():
                       "split_bf16_point_steps_per_s": point_steps / (sms / 1e3),
                       "split_bf16_max_slice_rel_err_vs_fp64": rel,
                       "split_bf16_mfma_tflops": bflops / (sms / 1e3) / 1e12})
+        progress("split-BF16 sweep")
     if not args.no_batched:
         extra["batched_fine_sweep"] = batched_fine_sweep()
+        progress("batched fine sweep")
     if not args.no_dd:
         extra["nn_dd_fine"] = dd_fine_leg()
+        progress("Neumann-Neumann fine solver")
     if not args.no_neural:
         # learned coarse propagator at the configured workload (2000
         # trajectories, eps = 0.02) and at the paper's eps = 0.0725, where the
         # plain propagator contracts
         extra["neural_G"] = neural_leg(prob, args.nn_traj, args.nn_steps, k_min=1)
+        progress("learned G")
         wide = copy.copy(prob)
         wide.eps = 0.0725
         extra["neural_G_eps_0.0725"] = neural_leg(wide, 512, args.nn_steps, k_min=0)
+        progress("learned G at eps = 0.0725")
     if not args.no_ttt:
         # time to an update norm below 1e-8 (host read of delta after every
         # iteration included): plain coarse G (2.4) with m_c = 1, 2, 4, 8 substeps,
@@ -781,6 +846,7 @@ def main():
                                  "timing": "wall clock from U^0 upload to the last delta read; "
                                            "one device-to-host delta read per iteration included; "
                                            "pipelined: one ch_parareal_run call, no host reads"}
+        progress("time to tolerance")
 
     out = {"metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -799,8 +865,8 @@ def main():
                                   "sweep group and 62 fine groups of eight workgroups); flops "
                                   "counted: the fine solves' 4n per point-step only"},
            "extra": extra}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, u0)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

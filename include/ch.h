@@ -81,8 +81,10 @@ typedef struct ch_problem {
   double newton_tol;    /* Newton stop: ||Y_{m+1}-Y_m||_h <= tol (1e-10)       */
   int32_t newton_max;   /* Newton iteration cap (20)                           */
   double krylov_rtol;   /* relative residual target of the CG solves of (2.4)
-                           (coarse step, and the PA-I fine step); 0 = default:
-                           1e-12 with the linear fine step, 1e-13 otherwise   */
+                           (coarse step, and the PA-I fine step) in 2D; 0 =
+                           default: 1e-12 with the linear fine step, 1e-13
+                           otherwise.  In 1D the (2.4) steps are solved
+                           directly (block-tridiagonal elimination)            */
   int32_t krylov_max;   /* CG iteration cap                                    */
   int32_t f_zero;       /* test hook: f(u) == 0                                */
   double nl_krylov_rtol;/* relative residual target of the CG inside Newton    */

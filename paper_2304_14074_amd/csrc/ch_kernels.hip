@@ -3085,6 +3085,7 @@ struct Ctx1 {
   double* red;        // 64 partials
   int n, i;
   bool on;            // i < n
+  double* dl;         // scratch of the direct (2.4) solve
 };
 
 // (S v)_i, v given per thread (zero off the grid)
@@ -3135,211 +3136,6 @@ __device__ __forceinline__ double lap_rhs1(const Ctx1& c, double u, double w, do
   if (!c.on) return 0.0;
   const double wl = c.i > 0 ? c.buf[c.i - 1] : 0.0, wr = c.i < c.n - 1 ? c.buf[c.i + 1] : 0.0;
   return u + coef * ((wl + wr) - 2.0 * w);
-}
-
-// Linear stabilised steps: (I + tau eps^2 L^2 - s tau L) v = u + tau L (f(u) - s u),
-// diagonal on the sine modes with 1 / sigma = rsig[i].
-__device__ double stab1(const Ctx1& c, double u, const InstDev& P, double tau, int steps,
-                        const double* rsig) {
-  const double coef = tau / (P.h * P.h), s = P.s_fine;
-  const double rs = c.on ? rsig[c.i] : 0.0;
-  for (int m = 0; m < steps; ++m) {
-    const double w = P.f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
-    const double r = lap_rhs1(c, u, w, coef);
-    u = sine1(c, sine1(c, r) * rs);
-  }
-  return u;
-}
-
-// PCG in sine coordinates for K x = b, K = diag(d) + tau S diag(q) S (SPD),
-// preconditioner 1 / (d + tau cshift), from x = 0, stopped when
-// ||r|| <= rtol ||b||.  Returns false on the cap or a non-finite residual.
-__device__ bool cg1(const Ctx1& c, double b, double d, double q, double tau, double cshift,
-                    double rtol, int maxit, double& x) {
-  const double mi = c.on ? 1.0 / (d + tau * cshift) : 0.0;
-  x = 0.0;
-  double r = b, p = b * mi;
-  double rz = bsum1(c, r * p);
-  const double bb = bsum1(c, b * b);
-  if (!(bb > 0.0)) return true;
-  const double stop2 = rtol * rtol * bb;
-  for (int it = 1; it <= maxit; ++it) {
-    const double kp = d * p + tau * sine1(c, q * sine1(c, p));
-    const double alpha = rz / bsum1(c, p * kp);
-    x += alpha * p;
-    r -= alpha * kp;
-    const double rr = bsum1(c, r * r);
-    const double rzn = bsum1(c, r * (r * mi));
-    if (rr <= stop2) return true;
-    if (!(rr == rr)) return false;
-    p = r * mi + (rzn / rz) * p;
-    rz = rzn;
-  }
-  return false;
-}
-
-// Scheme (2.4) steps of tau: K v_hat = (1/mu + tau) u_hat with q = u^2
-// (f == 0: q = 0 and the right-hand side u_hat / mu), mu = -lam.
-__device__ double approx2_1(const Ctx1& c, double u, const InstDev& P, const double* lam,
-                            double tau, int steps, int& status) {
-  const double mu = c.on ? -lam[c.i] : 1.0;
-  const double d = 1.0 / mu + tau * P.eps * P.eps * mu;
-  for (int m = 0; m < steps; ++m) {
-    const double q = (P.f_zero || !c.on) ? 0.0 : u * u;
-    const double cs = bmid1(c, q);
-    const double uh = sine1(c, u);
-    const double b = (P.f_zero ? 1.0 / mu : 1.0 / mu + tau) * uh;
-    double x;
-    if (!cg1(c, b, d, q, tau, cs, P.krylov_rtol, P.krylov_max, x)) status |= 1;
-    u = sine1(c, x);
-  }
-  return u;
-}
-
-// Scheme (2.3) (be = false) or backward Euler (true) with step tau, by
-// Newton's method from Y_0 = u in sine coordinates (as newton_step in 2D):
-// A^{-1} H(Y) = d Yh + tau S(Y^3) - (1/mu + tau) uh (2.3) or
-// d Yh + tau S(Y^3) - tau Yh - uh/mu (BE), the Newton matrix
-// diag(d) + tau S diag(q) S with q = 3Y^2 (2.3) or 3Y^2 - 1 (BE); stop when
-// ||Y_{m+1} - Y_m||_h <= newton_tol.  Returns the new state.
-__device__ double newton1(const Ctx1& c, double u, const InstDev& P, const double* lam,
-                          double tau, bool be, int& status) {
-  const double mu = c.on ? -lam[c.i] : 1.0;
-  const double im = c.on ? 1.0 / mu : 0.0;
-  const double d = im + tau * P.eps * P.eps * mu;
-  const double uh = sine1(c, u);
-  double yh = uh;
-  bool conv = false;
-  for (int it = 0; it < P.newton_max; ++it) {
-    const double y = sine1(c, yh);
-    const double q = (P.f_zero || !c.on) ? 0.0 : 3.0 * y * y + (be ? -1.0 : 0.0);
-    const double cs = bmid1(c, q);
-    const double y3h = sine1(c, P.f_zero ? 0.0 : y * y * y);
-    double g;
-    if (P.f_zero) g = d * yh - im * uh;
-    else if (be) g = d * yh + tau * y3h - tau * yh - im * uh;
-    else g = d * yh + tau * y3h - (im + tau) * uh;
-    if (!c.on) g = 0.0;
-    double dx;
-    if (!cg1(c, -g, d, q, tau, cs, P.nl_krylov_rtol, P.krylov_max, dx)) status |= 1;
-    yh += dx;
-    const double step = sqrt(P.h * bsum1(c, dx * dx));   // ||S dYh||_h = sqrt(h) ||dYh||
-    if (step <= P.newton_tol) { conv = true; break; }
-    if (!(step == step)) break;
-  }
-  if (!conv) status |= 1;
-  return sine1(c, yh);
-}
-
-// Fine propagator of one work item: J steps of the instance's fine scheme.
-__global__ void k_fine_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
-                          const double* __restrict__ S, const double* __restrict__ lam,
-                          const double* __restrict__ U_in, double* __restrict__ F_out,
-                          const uint8_t* __restrict__ mask, const int32_t* __restrict__ active,
-                          const int32_t* __restrict__ kmin, int in_iter) {
-  extern __shared__ double smem[];
-  const WorkItem it = items[blockIdx.x];
-  const InstDev P = inst[it.inst];
-  if (mask && !mask[P.slice_base + it.slice]) return;
-  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
-  const int n = P.n;
-  Ctx1 c{smem, smem + n * n, smem + n * n + n, n, (int)threadIdx.x, (int)threadIdx.x < n};
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) smem[idx] = S[idx];
-  const int64_t in0 = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * n;
-  double u = c.on ? U_in[in0 + c.i] : 0.0;
-  int status = 0;
-  if (P.fine_kind == 0) {
-    u = stab1(c, u, P, P.dt, P.j_fine, P.rsig_fine);
-  } else if (P.fine_kind == 2) {
-    u = approx2_1(c, u, P, lam, P.dt, P.j_fine, status);
-  } else {
-    for (int m = 0; m < P.j_fine; ++m) u = newton1(c, u, P, lam, P.dt, P.nl_variant == 1, status);
-  }
-  if (c.on) F_out[P.off_slices + (int64_t)it.slice * n + c.i] = u;
-  if (status && threadIdx.x == 0) atomicOr(P.status, status);
-}
-
-// One coarse propagation: m_coarse steps of tau = dT/m_coarse of the
-// instance's coarse scheme.
-__device__ double coarse_apply_1d(const Ctx1& c, double u, const InstDev& P, const double* lam,
-                                  int& status) {
-  const double tau = P.dT / P.m_coarse;
-  if (P.coarse_kind == 1) return stab1(c, u, P, tau, P.m_coarse, P.rsig_stab);
-  if (P.coarse_kind == 3) {
-    for (int m = 0; m < P.m_coarse; ++m) u = newton1(c, u, P, lam, tau, false, status);
-    return u;
-  }
-  return approx2_1(c, u, P, lam, tau, P.m_coarse, status);
-}
-
-__global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
-                            const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
-                            const double* __restrict__ S, const double* __restrict__ lam,
-                            const double* __restrict__ U_in, double* __restrict__ G_out,
-                            const uint8_t* __restrict__ mask, double* U,
-                            const double* __restrict__ F, double* G_old, double* delta,
-                            int32_t* status_out, const int32_t* __restrict__ active, int k,
-                            const int32_t* __restrict__ kdev) {
-  extern __shared__ double smem[];
-  if (kdev) k = *kdev;
-  int status = 0;
-  const bool par = mode == 0;
-  const WorkItem it = par ? items[blockIdx.x] : WorkItem{insts[blockIdx.x], 0};
-  const int ii = it.inst;
-  const InstDev P = inst[ii];
-  if (par && mask && !mask[P.slice_base + it.slice]) return;
-  if (!par && active && !active[ii]) return;
-  const int n = P.n;
-  Ctx1 c{smem, smem + n * n, smem + n * n + n, n, (int)threadIdx.x, (int)threadIdx.x < n};
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) smem[idx] = S[idx];
-  const int i = c.i;
-  if (par) {
-    const int64_t off = P.off_slices + (int64_t)it.slice * n;
-    const double g = coarse_apply_1d(c, c.on ? U_in[off + i] : 0.0, P, lam, status);
-    if (c.on) G_out[off + i] = g;
-    if (status && threadIdx.x == 0) atomicOr(P.status, status);
-    return;
-  }
-  double* Ui = U + P.off_iter;
-  const double* Fi = F + P.off_slices;
-  double* Gi = G_old + P.off_slices;
-  if (mode == 1) {
-    double u = c.on ? Ui[i] : 0.0;
-    for (int s = 0; s < P.n_slices; ++s) {
-      u = coarse_apply_1d(c, u, P, lam, status);
-      if (c.on) {
-        Ui[(s + 1) * n + i] = u;
-        Gi[s * n + i] = u;
-      }
-    }
-    if (threadIdx.x == 0) status_out[ii] = status | *P.status;
-    return;
-  }
-  if (k >= P.n_slices) {
-    if (threadIdx.x == 0) delta[ii] = 0.0;
-    return;
-  }
-  double u = c.on ? Fi[k * n + i] : 0.0;
-  double dd = c.on ? u - Ui[(k + 1) * n + i] : 0.0;
-  double dmax = bsum1(c, dd * dd);
-  if (c.on) Ui[(k + 1) * n + i] = u;
-  for (int s = k + 1; s < P.n_slices; ++s) {
-    const double g = coarse_apply_1d(c, u, P, lam, status);
-    const double un = c.on ? Fi[s * n + i] + (g - Gi[s * n + i]) : 0.0;
-    dd = c.on ? un - Ui[(s + 1) * n + i] : 0.0;
-    dmax = fmax(dmax, bsum1(c, dd * dd));
-    if (c.on) {
-      Ui[(s + 1) * n + i] = un;
-      Gi[s * n + i] = g;
-    }
-    u = un;
-  }
-  if (threadIdx.x == 0) {
-    const double dlt = sqrt(P.h * dmax);
-    delta[ii] = dlt;
-    if (!(dlt == dlt) || dlt > 1e300) status |= 2;
-    status_out[ii] |= status | *P.status;
-  }
 }
 
 // ------------------------------------------------ 1D Neumann-Neumann step
@@ -3596,6 +3392,232 @@ k_fine_dd_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ ins
   }
 }
 
+// Scheme (2.4) steps of tau solved directly: the mixed block-tridiagonal
+// system [I, -tau L; eps^2 L - diag(c), I][u; v] = [u_n; -u_n] with
+// c = u_n^2 (f == 0: c = 0 and right-hand side [u_n; 0]) eliminated by
+// 2x2-block Thomas on one lane.  Its chain of 2n pivots is far shorter than
+// the transforms and reductions of the CG iterations the sine-basis solve
+// needs, and the result is exact up to rounding.
+__device__ double approx2_direct1(const Ctx1& c, double u, const InstDev& P, double tau,
+                                  int steps) {
+  DD1 d;
+  d.n = c.n; d.N0 = 1; d.m = c.n + 1; d.MD = c.n; d.MN = 0;
+  d.a = tau / (P.h * P.h); d.b = P.eps * P.eps / (P.h * P.h);
+  d.ub = c.dl;                      // c_j = ub[j]^2, nodes 1..n
+  double* F = d.ub + c.n + 2;       // pivots, 4 per node
+  double* X = F + 4 * c.n;          // right-hand side, then the solution
+  for (int m = 0; m < steps; ++m) {
+    __syncthreads();
+    if (c.on) {
+      d.ub[c.i + 1] = P.f_zero ? 0.0 : u;
+      X[2 * c.i] = u;
+      X[2 * c.i + 1] = P.f_zero ? 0.0 : -u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      dd1_factor(d, F, 1, c.n, false);
+      dd1_solve(d, F, X, c.n);
+    }
+    __syncthreads();
+    u = c.on ? X[2 * c.i] : 0.0;
+  }
+  return u;
+}
+
+// LDS doubles of the direct (2.4) solve after S, buf and red
+__host__ __device__ constexpr size_t direct1_lds_doubles(int n) { return 7 * (size_t)n + 2; }
+
+// Linear stabilised steps: (I + tau eps^2 L^2 - s tau L) v = u + tau L (f(u) - s u),
+// diagonal on the sine modes with 1 / sigma = rsig[i].
+__device__ double stab1(const Ctx1& c, double u, const InstDev& P, double tau, int steps,
+                        const double* rsig) {
+  const double coef = tau / (P.h * P.h), s = P.s_fine;
+  const double rs = c.on ? rsig[c.i] : 0.0;
+  for (int m = 0; m < steps; ++m) {
+    const double w = P.f_zero ? (-s * u) : (u * u * u - (1.0 + s) * u);
+    const double r = lap_rhs1(c, u, w, coef);
+    u = sine1(c, sine1(c, r) * rs);
+  }
+  return u;
+}
+
+// PCG in sine coordinates for K x = b, K = diag(d) + tau S diag(q) S (SPD),
+// preconditioner 1 / (d + tau cshift), from x = 0, stopped when
+// ||r|| <= rtol ||b||.  Returns false on the cap or a non-finite residual.
+__device__ bool cg1(const Ctx1& c, double b, double d, double q, double tau, double cshift,
+                    double rtol, int maxit, double& x) {
+  const double mi = c.on ? 1.0 / (d + tau * cshift) : 0.0;
+  x = 0.0;
+  double r = b, p = b * mi;
+  double rz = bsum1(c, r * p);
+  const double bb = bsum1(c, b * b);
+  if (!(bb > 0.0)) return true;
+  const double stop2 = rtol * rtol * bb;
+  for (int it = 1; it <= maxit; ++it) {
+    const double kp = d * p + tau * sine1(c, q * sine1(c, p));
+    const double alpha = rz / bsum1(c, p * kp);
+    x += alpha * p;
+    r -= alpha * kp;
+    const double rr = bsum1(c, r * r);
+    const double rzn = bsum1(c, r * (r * mi));
+    if (rr <= stop2) return true;
+    if (!(rr == rr)) return false;
+    p = r * mi + (rzn / rz) * p;
+    rz = rzn;
+  }
+  return false;
+}
+
+// Scheme (2.3) (be = false) or backward Euler (true) with step tau, by
+// Newton's method from Y_0 = u in sine coordinates (as newton_step in 2D):
+// A^{-1} H(Y) = d Yh + tau S(Y^3) - (1/mu + tau) uh (2.3) or
+// d Yh + tau S(Y^3) - tau Yh - uh/mu (BE), the Newton matrix
+// diag(d) + tau S diag(q) S with q = 3Y^2 (2.3) or 3Y^2 - 1 (BE); stop when
+// ||Y_{m+1} - Y_m||_h <= newton_tol.  Returns the new state.
+__device__ double newton1(const Ctx1& c, double u, const InstDev& P, const double* lam,
+                          double tau, bool be, int& status) {
+  const double mu = c.on ? -lam[c.i] : 1.0;
+  const double im = c.on ? 1.0 / mu : 0.0;
+  const double d = im + tau * P.eps * P.eps * mu;
+  const double uh = sine1(c, u);
+  double yh = uh;
+  bool conv = false;
+  for (int it = 0; it < P.newton_max; ++it) {
+    const double y = sine1(c, yh);
+    const double q = (P.f_zero || !c.on) ? 0.0 : 3.0 * y * y + (be ? -1.0 : 0.0);
+    const double cs = bmid1(c, q);
+    const double y3h = sine1(c, P.f_zero ? 0.0 : y * y * y);
+    double g;
+    if (P.f_zero) g = d * yh - im * uh;
+    else if (be) g = d * yh + tau * y3h - tau * yh - im * uh;
+    else g = d * yh + tau * y3h - (im + tau) * uh;
+    if (!c.on) g = 0.0;
+    double dx;
+    if (!cg1(c, -g, d, q, tau, cs, P.nl_krylov_rtol, P.krylov_max, dx)) status |= 1;
+    yh += dx;
+    const double step = sqrt(P.h * bsum1(c, dx * dx));   // ||S dYh||_h = sqrt(h) ||dYh||
+    if (step <= P.newton_tol) { conv = true; break; }
+    if (!(step == step)) break;
+  }
+  if (!conv) status |= 1;
+  return sine1(c, yh);
+}
+
+// Fine propagator of one work item: J steps of the instance's fine scheme.
+__global__ void k_fine_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                          const double* __restrict__ S, const double* __restrict__ lam,
+                          const double* __restrict__ U_in, double* __restrict__ F_out,
+                          const uint8_t* __restrict__ mask, const int32_t* __restrict__ active,
+                          const int32_t* __restrict__ kmin, int in_iter) {
+  extern __shared__ double smem[];
+  const WorkItem it = items[blockIdx.x];
+  const InstDev P = inst[it.inst];
+  if (mask && !mask[P.slice_base + it.slice]) return;
+  if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
+  const int n = P.n;
+  Ctx1 c{smem, smem + n * n, smem + n * n + n, n, (int)threadIdx.x, (int)threadIdx.x < n,
+         smem + n * n + n + 64};
+  if (P.fine_kind != 2)   // the direct (2.4) solve needs no sine matrix
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) smem[idx] = S[idx];
+  const int64_t in0 = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * n;
+  double u = c.on ? U_in[in0 + c.i] : 0.0;
+  int status = 0;
+  if (P.fine_kind == 0) {
+    u = stab1(c, u, P, P.dt, P.j_fine, P.rsig_fine);
+  } else if (P.fine_kind == 2) {
+    u = approx2_direct1(c, u, P, P.dt, P.j_fine);
+  } else {
+    for (int m = 0; m < P.j_fine; ++m) u = newton1(c, u, P, lam, P.dt, P.nl_variant == 1, status);
+  }
+  if (c.on) F_out[P.off_slices + (int64_t)it.slice * n + c.i] = u;
+  if (status && threadIdx.x == 0) atomicOr(P.status, status);
+}
+
+// One coarse propagation: m_coarse steps of tau = dT/m_coarse of the
+// instance's coarse scheme.
+__device__ double coarse_apply_1d(const Ctx1& c, double u, const InstDev& P, const double* lam,
+                                  int& status) {
+  const double tau = P.dT / P.m_coarse;
+  if (P.coarse_kind == 1) return stab1(c, u, P, tau, P.m_coarse, P.rsig_stab);
+  if (P.coarse_kind == 3) {
+    for (int m = 0; m < P.m_coarse; ++m) u = newton1(c, u, P, lam, tau, false, status);
+    return u;
+  }
+  return approx2_direct1(c, u, P, tau, P.m_coarse);
+}
+
+__global__ void k_coarse_1d(int mode, const int32_t* __restrict__ insts,
+                            const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
+                            const double* __restrict__ S, const double* __restrict__ lam,
+                            const double* __restrict__ U_in, double* __restrict__ G_out,
+                            const uint8_t* __restrict__ mask, double* U,
+                            const double* __restrict__ F, double* G_old, double* delta,
+                            int32_t* status_out, const int32_t* __restrict__ active, int k,
+                            const int32_t* __restrict__ kdev) {
+  extern __shared__ double smem[];
+  if (kdev) k = *kdev;
+  int status = 0;
+  const bool par = mode == 0;
+  const WorkItem it = par ? items[blockIdx.x] : WorkItem{insts[blockIdx.x], 0};
+  const int ii = it.inst;
+  const InstDev P = inst[ii];
+  if (par && mask && !mask[P.slice_base + it.slice]) return;
+  if (!par && active && !active[ii]) return;
+  const int n = P.n;
+  Ctx1 c{smem, smem + n * n, smem + n * n + n, n, (int)threadIdx.x, (int)threadIdx.x < n,
+         smem + n * n + n + 64};
+  if (P.coarse_kind != 0)   // the direct (2.4) solve needs no sine matrix
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) smem[idx] = S[idx];
+  const int i = c.i;
+  if (par) {
+    const int64_t off = P.off_slices + (int64_t)it.slice * n;
+    const double g = coarse_apply_1d(c, c.on ? U_in[off + i] : 0.0, P, lam, status);
+    if (c.on) G_out[off + i] = g;
+    if (status && threadIdx.x == 0) atomicOr(P.status, status);
+    return;
+  }
+  double* Ui = U + P.off_iter;
+  const double* Fi = F + P.off_slices;
+  double* Gi = G_old + P.off_slices;
+  if (mode == 1) {
+    double u = c.on ? Ui[i] : 0.0;
+    for (int s = 0; s < P.n_slices; ++s) {
+      u = coarse_apply_1d(c, u, P, lam, status);
+      if (c.on) {
+        Ui[(s + 1) * n + i] = u;
+        Gi[s * n + i] = u;
+      }
+    }
+    if (threadIdx.x == 0) status_out[ii] = status | *P.status;
+    return;
+  }
+  if (k >= P.n_slices) {
+    if (threadIdx.x == 0) delta[ii] = 0.0;
+    return;
+  }
+  double u = c.on ? Fi[k * n + i] : 0.0;
+  double dd = c.on ? u - Ui[(k + 1) * n + i] : 0.0;
+  double dmax = bsum1(c, dd * dd);
+  if (c.on) Ui[(k + 1) * n + i] = u;
+  for (int s = k + 1; s < P.n_slices; ++s) {
+    const double g = coarse_apply_1d(c, u, P, lam, status);
+    const double un = c.on ? Fi[s * n + i] + (g - Gi[s * n + i]) : 0.0;
+    dd = c.on ? un - Ui[(s + 1) * n + i] : 0.0;
+    dmax = fmax(dmax, bsum1(c, dd * dd));
+    if (c.on) {
+      Ui[(s + 1) * n + i] = un;
+      Gi[s * n + i] = g;
+    }
+    u = un;
+  }
+  if (threadIdx.x == 0) {
+    const double dlt = sqrt(P.h * dmax);
+    delta[ii] = dlt;
+    if (!(dlt == dlt) || dlt > 1e300) status |= 2;
+    status_out[ii] |= status | *P.status;
+  }
+}
+
 // --------------------------------------------------------------- energy
 // E_h = h^d sum (u^2-1)^2/4 + (eps^2/2) h^d sum u (-Lap_h u); one block per state.
 // Per-slice distance ||A_n - B_n||_h (h^d-weighted L2, the norm of the update
@@ -3840,7 +3862,7 @@ hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstD
   if (n_items <= 0) return hipSuccess;
   // lam for 1D is stored right after S (n x n) in the table block
   const double* lam = S + (size_t)n * n;
-  const size_t lds = ((size_t)n * n + n + 64) * sizeof(double);
+  const size_t lds = ((size_t)n * n + n + 64 + direct1_lds_doubles(n)) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_1d,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -3924,7 +3946,7 @@ hipError_t launch_coarse_1d(int n, int mode, const int32_t* insts, int n_insts,
                             const int32_t* kdev, hipStream_t s) {
   // lam for 1D is stored right after S (n x n) in the table block
   const double* lam = S + (size_t)n * n;
-  const size_t lds = ((size_t)n * n + n + 64) * sizeof(double);
+  const size_t lds = ((size_t)n * n + n + 64 + direct1_lds_doubles(n)) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_1d,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -64,7 +64,7 @@ def test_dd_fine_sweep_matches_oracle(n, n_sub, J, dt):
             assert its[s] == 0
 
 
-def test_dd_single_subdomain_equals_the_cg_solved_pa_i_step():
+def test_dd_single_subdomain_equals_the_direct_pa_i_step():
     from paper_2304_14074_amd import chlib
     n, J = 127, 5
     p = _prob(n, 1, 2, J, 1e-3)

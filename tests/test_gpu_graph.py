@@ -54,7 +54,10 @@ def test_graph_replays_match_eager_iterations():
         ctx.ch_graph_destroy(h)
 
 
-def test_graph_refused_for_learned_coarse():
+def test_graph_accepts_learned_coarse():
+    # the judge and the fallback run on the device, so a learned-propagator
+    # iteration can be captured (replays against eager iterations: the judge
+    # tests)
     from paper_2304_14074_amd import chlib
     p = workloads.Problem(dim=2, n=32, eps=0.02, T=2 * 5 * 4e-5, n_slices=2, j_fine=5,
                           coarse_kind="neural")
@@ -65,5 +68,8 @@ def test_graph_refused_for_learned_coarse():
     ctx.ch_nn_bind(w)
     with torch.cuda.stream(s):
         ctx.ch_parareal_iterate(st, 0.0, stream=s)
-        with pytest.raises(chlib.CHError):
-            ctx.ch_parareal_graph_create(st, 0.0, s)
+        h = ctx.ch_parareal_graph_create(st, 0.0, s)
+        ctx.ch_graph_launch(h, s)
+        s.synchronize()
+        ctx.ch_graph_destroy(h)
+    assert ctx.ch_check_status(st) == [0]
