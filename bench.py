@@ -339,6 +339,9 @@ def batched_fine_sweep() -> dict:
             seen.add(p.n)
         base += p.n_slices
     stream = torch.cuda.current_stream()
+    # launch configuration per grid-size class by the autotuner (20 steps of
+    # every slice per candidate)
+    tuned, _ = ctx.autotune(Us, Fs, cache_path=None, steps=20)
     ctx.ch_fine_propagate(Us, Fs, mask.cuda())
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -354,6 +357,7 @@ def batched_fine_sweep() -> dict:
     return {"workload": "256 instances, n in {64,128,256}, N in {32,64,128}, J=1563, FP64 "
                         "linear fine step, one ch_fine_propagate over all 20k slices",
             "slices": sum(p.n_slices for p in probs), "ms": ms,
+            "tuned_waves_groups": {str(n): list(v) for n, v in tuned.items()},
             "point_steps_per_s": pts / (ms / 1e3), "tflops": tf,
             "frac_fp64_peak": tf / FP64_PEAK_TFLOPS,
             "traffic_bytes": BATCHED_SWEEP_TRAFFIC_BYTES,
@@ -534,7 +538,7 @@ def bench_batched(args):
            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                         "kernel": "fine sweep (all classes, one ch_fine_propagate)"},
-           "extra": {"fine_sweep_ms": fine_ms, "tuned_waves": tuned, "tuning_from_cache": cached,
+           "extra": {"fine_sweep_ms": fine_ms, "tuned_waves_groups": tuned, "tuning_from_cache": cached,
                      "finite": ok}}
 
 

@@ -203,10 +203,13 @@ ch_status ch_slice_distance(ch_ctx* ctx, const double* A, const double* B, doubl
 ch_status ch_parareal_run(ch_ctx* ctx, ch_pr_state* st, double tol, int32_t max_iters,
                           int32_t flags, ch_stream stream);
 
-/* Autotuner of the on-chip FP64 linear fine kernels (2D, n <= 128): times
- * every workgroup-size variant over `steps` fine steps of all slices of each
- * grid-size class on the given inputs (slice layout; F_out is overwritten)
- * and keeps the fastest.  Synchronous. */
+/* Autotuner of the FP64 linear fine sweep (2D): for each grid-size class it
+ * times every launch configuration over `steps` fine steps of all slices of
+ * the class on the given inputs (slice layout; F_out is overwritten) and
+ * keeps the fastest: one workgroup per slice with each wave count
+ * (ch_fine_variant), and groups of workgroups per slice with each group size
+ * the class has (ch_fine_groups: 4 or 8 at n = 128, 8 at n = 256).
+ * Synchronous. */
 ch_status ch_autotune(ch_ctx* ctx, const double* U_in, double* F_out, int32_t steps,
                       ch_stream stream);
 /* Query (set = 0) or set (set = 1) the waves per workgroup of the fine

@@ -308,11 +308,12 @@ class Context:
         return g.value
 
     def autotune(self, U_in, F_out, cache_path=None, steps=20):
-        """Tuned fine-kernel variants, from a JSON cache keyed by GPU
+        """Tuned launch configurations of the linear FP64 fine sweep per grid
+        size, {n: (waves, groups)}, from a JSON cache keyed by GPU
         architecture and grid size when present, else measured and cached."""
         import json
         arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
-        sizes = sorted({p.n for p in self.problems if p.dim == 2 and p.n <= 128
+        sizes = sorted({p.n for p in self.problems if p.dim == 2
                         and getattr(p, "fine_kind", "linear") == "linear"
                         and getattr(p, "precision", "fp64") == "fp64"})
         cache = {}
@@ -320,14 +321,16 @@ class Context:
             with open(cache_path) as f:
                 cache = json.load(f)
         entry = cache.get(arch, {})
-        if all(f"linear-fp64-n{n}" in entry for n in sizes):
+        key = lambda n: f"linear-fp64-n{n}-launch"
+        if all(key(n) in entry for n in sizes):
             for n in sizes:
-                self.ch_fine_variant(n, entry[f"linear-fp64-n{n}"])
-            return {n: entry[f"linear-fp64-n{n}"] for n in sizes}, True
+                self.ch_fine_variant(n, entry[key(n)]["waves"])
+                self.ch_fine_groups(n, entry[key(n)]["groups"])
+            return {n: (entry[key(n)]["waves"], entry[key(n)]["groups"]) for n in sizes}, True
         self.ch_autotune(U_in, F_out, steps)
-        chosen = {n: self.ch_fine_variant(n) for n in sizes}
+        chosen = {n: (self.ch_fine_variant(n), self.ch_fine_groups(n)) for n in sizes}
         if cache_path:
-            entry.update({f"linear-fp64-n{n}": w for n, w in chosen.items()})
+            entry.update({key(n): {"waves": w, "groups": g} for n, (w, g) in chosen.items()})
             cache[arch] = entry
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1)

@@ -148,6 +148,21 @@ const char* ch_status_str(ch_status s) {
 
 const char* ch_last_error(const ch_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+// Subdomains of the direct 1D (2.4) solve: the divisor N0 <= 64 of n + 1
+// (at least two intervals each) with the shortest elimination chains, about
+// 2 (n+1)/N0 (a subdomain's factorisation and solve) + 2 N0 (the interface
+// elimination, forward and back); 1 when n + 1 has none.
+static int direct_sub(int n) {
+  int best = 1;
+  double cost = 2.0 * (n + 1) + 2.0;
+  for (int k = 2; k <= 64 && 2 * k <= n + 1; ++k) {
+    if ((n + 1) % k) continue;
+    const double c = 2.0 * (n + 1) / k + 2.0 * k;
+    if (c < cost) { cost = c; best = k; }
+  }
+  return best;
+}
+
 // Neumann-Neumann parameters with their defaults (0 selects the default)
 static int dd_sub(const ch_problem& p) { return p.dd_subdomains > 0 ? p.dd_subdomains : 8; }
 
@@ -241,6 +256,7 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
                       ? 9 : chk::WORK_VECS;
     d.nn_base = p.nn_base;
     d.dd_sub = dd_sub(p);
+    d.direct_sub = direct_sub(p.n);
     d.dd_max = p.dd_max > 0 ? p.dd_max : 100;
     d.dd_theta = p.dd_theta > 0 ? p.dd_theta : 0.25;
     d.dd_tol = p.dd_tol > 0 ? p.dd_tol : 1e-10;
@@ -553,8 +569,8 @@ static ch_status fine_all(ch_ctx* c, const double* U_in, double* F_out, const ui
       e = chk::launch_fine_dd_1d(cp.n, items, (int)cp.items.size(), inst, U_in, F_out, mask,
                                  active, k_min, in_iter, s);
     } else {
-      e = chk::launch_fine_1d(cp.n, items, (int)cp.items.size(), inst, tab, nullptr, U_in, F_out,
-                              mask, active, k_min, in_iter, s);
+      e = chk::launch_fine_1d(cp.n, items, (int)cp.items.size(), inst, tab, U_in, F_out,
+                              mask, active, k_min, in_iter, s, cp.fine_kind != CH_FINE_APPROX2);
     }
     ch_status st = hip_check(c, e, "fine sweep launch");
     if (st != CH_OK) return st;
@@ -976,10 +992,12 @@ ch_status ch_parareal_correct(ch_ctx* c, ch_pr_state* st, double tol, ch_stream 
 }
 
 static bool tunable(const ClassPlan& cp) {
-  return cp.dim == 2 && cp.fine_kind == CH_FINE_LINEAR && cp.precision == CH_PREC_FP64 &&
-         cp.n <= 128;
+  return cp.dim == 2 && cp.fine_kind == CH_FINE_LINEAR && cp.precision == CH_PREC_FP64;
 }
 
+// Launch configurations of a class's linear fine sweep, timed by the
+// autotuner: one workgroup per slice with each wave count, and groups of G
+// workgroups per slice with each group size.
 ch_status ch_autotune(ch_ctx* c, const double* U_in, double* F_out, int32_t steps, ch_stream stream) {
   ch_status r = require_bound(c);
   if (r != CH_OK) return r;
@@ -991,19 +1009,31 @@ ch_status ch_autotune(ch_ctx* c, const double* U_in, double* F_out, int32_t step
     return fail(c, CH_ERR_HIP, "event create");
   for (auto& cp : c->classes) {
     if (!tunable(cp)) continue;
-    int opts[8];
-    const int no = chk::fine_wave_options(cp.n, opts);
+    int wopt[8], gopt[8];
+    const int nw = chk::fine_wave_options(cp.n, wopt);
+    const int ng = chk::fine_group_options(cp.n, gopt);
     float best = 1e30f;
-    int best_w = opts[0];
+    int best_w = wopt[0], best_g = 1;
     const WorkItem* items = (const WorkItem*)(c->ws + cp.items_blk.off);
-    for (int o = 0; o < no; ++o) {
+    const int n_items = (int)cp.items.size();
+    int32_t* sync = (int32_t*)(c->ws + cp.sync_blk.off);
+    for (int o = 0; o < nw + ng; ++o) {
+      const bool grp = o >= nw;
+      auto launch = [&](int j) {
+        return grp ? chk::launch_fine_group(cp.n, gopt[o - nw], items, n_items, inst,
+                                            class_sine(c, cp), U_in, F_out, nullptr, nullptr,
+                                            nullptr, 0, sync, s, j)
+                   : chk::launch_fine_2d(cp.n, items, n_items, inst, class_sine(c, cp), U_in,
+                                         F_out, nullptr, nullptr, nullptr, 0, s, wopt[o], j);
+      };
       // warm-up then timed launch of `steps` fine steps over the class
-      hipError_t e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, class_sine(c, cp),
-                                         U_in, F_out, nullptr, nullptr, nullptr, 0, s, opts[o], 1);
+      hipError_t e = launch(1);
+      if (grp && (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorNotSupported)) {
+        (void)hipGetLastError();
+        continue;             // this group size does not fit on the device
+      }
       if (e == hipSuccess) e = hipEventRecord(e0, s);
-      if (e == hipSuccess)
-        e = chk::launch_fine_2d(cp.n, items, (int)cp.items.size(), inst, class_sine(c, cp), U_in,
-                                F_out, nullptr, nullptr, nullptr, 0, s, opts[o], steps);
+      if (e == hipSuccess) e = launch(steps);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -1013,9 +1043,14 @@ ch_status ch_autotune(ch_ctx* c, const double* U_in, double* F_out, int32_t step
         (void)hipEventDestroy(e1);
         return hip_check(c, e, "autotune run");
       }
-      if (ms < best) { best = ms; best_w = opts[o]; }
+      if (ms < best) {
+        best = ms;
+        best_w = grp ? wopt[0] : wopt[o];
+        best_g = grp ? gopt[o - nw] : 1;
+      }
     }
     cp.waves = best_w;
+    cp.fine_groups = best_g;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -33,6 +33,7 @@ struct InstDev {
   // Neumann-Neumann fine step: subdomains, iteration cap, relaxation, stop,
   // per-slice iteration counts of the latest sweep
   int32_t dd_sub, dd_max;
+  int32_t direct_sub;        // subdomains of the direct 1D (2.4) solve
   double dd_theta, dd_tol;
   int32_t* dd_iters;
 };
@@ -61,6 +62,7 @@ hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstD
                           const int32_t* kmin, int in_iter, hipStream_t s, int waves = 0,
                           int j_steps = 0);
 int fine_wave_options(int n, int* out);
+int fine_group_options(int n, int* out);
 hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, const InstDev* inst,
                                  const double* Tsin, const double* U_in, double* F_out,
                                  const uint8_t* mask, const int32_t* active, const int32_t* kmin,
@@ -81,10 +83,12 @@ hipError_t launch_fine_dd_1d(int n, const WorkItem* items, int n_items, const In
                              const double* U_in, double* F_out, const uint8_t* mask,
                              const int32_t* active, const int32_t* kmin, int in_iter,
                              hipStream_t s);
+// sine = 0: the class's fine step needs no sine matrix in LDS (scheme (2.4),
+// solved directly).
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
-                          const double* S, const double* rsig1, const double* U_in,
-                          double* F_out, const uint8_t* mask, const int32_t* active,
-                          const int32_t* kmin, int in_iter, hipStream_t s);
+                          const double* S, const double* U_in, double* F_out,
+                          const uint8_t* mask, const int32_t* active, const int32_t* kmin,
+                          int in_iter, hipStream_t s, int sine);
 // mode 0: independent G per masked slice (parallel); 1: prediction chain;
 // 2: correction chain starting at slice k+1 with U_{k+1} = F_k; modes 3-5:
 // the plain scheme (2.4) of the given work items, outputs in the slice

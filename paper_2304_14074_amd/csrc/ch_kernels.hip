@@ -2350,7 +2350,8 @@ __global__ void __launch_bounds__(NW * 64)
 k_fine_linear_stream(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
                      const double* __restrict__ Tg, const double* __restrict__ U_in,
                      double* __restrict__ F_out, const uint8_t* __restrict__ mask,
-                     const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter) {
+                     const int32_t* __restrict__ active, const int32_t* __restrict__ kmin, int in_iter,
+                     int j_steps) {
   using G = GeoS<N, NW>;
   extern __shared__ double smem[];
   double* Lc = smem;
@@ -2367,8 +2368,8 @@ k_fine_linear_stream(const WorkItem* __restrict__ items, const InstDev* __restri
   for (int m = threadIdx.x; m < G::P2; m += G::NT) T[m] = Tg[m];
   for (int idx = threadIdx.x; idx < NN; idx += G::NT) b0[idx] = U_in[off_in + idx];
   __syncthreads();
-  stream_linear_steps<N, NW>(b0, b1, Lc, T, P.j_fine, P.dt / (P.h * P.h), P.s_fine, P.f_zero,
-                             P.rsig_fine);
+  stream_linear_steps<N, NW>(b0, b1, Lc, T, j_steps > 0 ? j_steps : P.j_fine, P.dt / (P.h * P.h),
+                             P.s_fine, P.f_zero, P.rsig_fine);
   for (int idx = threadIdx.x; idx < NN; idx += G::NT) F_out[off + idx] = b0[idx];
 }
 
@@ -3138,9 +3139,9 @@ __device__ __forceinline__ double lap_rhs1(const Ctx1& c, double u, double w, do
   return u + coef * ((wl + wr) - 2.0 * w);
 }
 
-// ------------------------------------------------ 1D Neumann-Neumann step
+// ------------------------------------------ 1D subdomain solves of (2.4)
 // Scheme (2.4) in mixed form, [I, -tau L; eps^2 L - diag(c), I][u; v] =
-// [u_n; -u_n] with c = u_n^2, solved by the Neumann-Neumann iteration on N0
+// [u_n; f_v] with c = u_n^2 and f_v = -u_n (f == 0: c = 0, f_v = 0), on N0
 // equal subdomains (Section 4).  Nodes 0..n+1, interfaces at p_q = q m,
 // m = (n+1)/N0.  Per node the unknowns form a 2-vector (u, v); the matrix is
 // block tridiagonal with the coupling E = [[0, -a], [b, 0]] (a = tau/h^2,
@@ -3149,40 +3150,56 @@ __device__ __forceinline__ double lap_rhs1(const Ctx1& c, double u, double w, do
 // physical boundary), w = 1/2, e = 1 at an interface node of a Neumann
 // problem (half of the shared node, one edge of the subdomain).
 //
-// The subdomain matrices do not change during a step, so they are factored
-// once (block Thomas, 2x2 pivots) and the iteration runs on the interface
-// traces: the Dirichlet solution next to an interface is an affine function
-// of the subdomain's traces (its response to u_n and to a unit value of each
-// trace), and the Neumann solution at an interface is a linear function of
-// the subdomain's interface residuals (its response to unit residuals).  Each
-// iteration then computes the residuals, the Neumann corrections and the
-// trace update for all interfaces at once, one lane per interface; the
-// iterates are the method's own (up to rounding).  The step ends with the
-// subdomain states of the final traces.
+// The subdomain matrices are factored once per step (block Thomas, 2x2
+// pivots).  The Dirichlet solution of a subdomain is an affine function of
+// its four trace values (its responses to the data and to a unit value of
+// each trace), and the Neumann solution at an interface is linear in the
+// subdomain's interface residuals (its responses to unit residuals).  Two
+// uses:
+//  * the Neumann-Neumann iteration of Section 4 (dd1_step) runs on the
+//    interface traces, one lane per interface: each iteration computes the
+//    residuals, the Neumann corrections and the trace update for all
+//    interfaces at once; the iterates are the method's own (up to rounding);
+//  * the direct solve (dd1_direct_step) eliminates the interface equations
+//    themselves (block tridiagonal in the traces) on one lane: a
+//    substructured elimination of the whole system.
+// Both end with the subdomain states of the final traces.
 struct DD1 {
   int n, N0, m, MD, MN;
   double a, b;
-  double *ub, *fD, *fN, *rD, *tN, *nr, *tg, *th;
+  double fvs;   // f_v = fvs u_n
+  bool cz;      // c = 0
+  double *ub, *fD, *fN, *rD, *tN, *nr, *ib, *tg, *th;
 };
 
-__device__ __forceinline__ DD1 dd1_layout(const InstDev& P, double tau, double* L) {
+// nn: with the Neumann parts (else they take no space and ib holds the
+// interface blocks of the direct solve)
+__device__ __forceinline__ DD1 dd1_layout(const InstDev& P, int N0, double tau, double* L,
+                                          bool nn) {
   DD1 d;
-  d.n = P.n; d.N0 = P.dd_sub; d.m = (P.n + 1) / P.dd_sub; d.MD = d.m - 1; d.MN = d.m + 1;
+  d.n = P.n; d.N0 = N0; d.m = (P.n + 1) / N0; d.MD = d.m - 1; d.MN = nn ? d.m + 1 : 0;
   d.a = tau / (P.h * P.h); d.b = P.eps * P.eps / (P.h * P.h);
+  d.fvs = P.f_zero ? 0.0 : -1.0;
+  d.cz = P.f_zero != 0;
   d.ub = L;                                 // u_n on nodes 0..n+1
   d.fD = d.ub + d.n + 2;                    // Dirichlet pivots: N0 x MD x 4
-  d.fN = d.fD + d.N0 * d.MD * 4;            // Neumann pivots:   N0 x MN x 4
-  d.rD = d.fN + d.N0 * d.MN * 4;            // Dirichlet responses: N0 x 5 x MD x 2
-  d.tN = d.rD + d.N0 * 5 * d.MD * 2;        // Neumann solves: N0 x 4 x MN x 2
-  d.nr = d.tN + d.N0 * 4 * d.MN * 2;        // Neumann interface responses: N0 x 4 x 4
-  d.tg = d.nr + d.N0 * 16;                  // traces g_q, q = 0..N0 (ends 0)
-  d.th = d.tg + d.N0 + 1;                   // traces h_q
+  d.fN = d.fD + N0 * d.MD * 4;              // Neumann pivots:   N0 x MN x 4
+  d.rD = d.fN + N0 * d.MN * 4;              // Dirichlet responses: N0 x 5 x MD x 2
+  d.tN = d.rD + N0 * 5 * d.MD * 2;          // Neumann solves: N0 x 4 x MN x 2
+  d.nr = d.tN + N0 * 4 * d.MN * 2;          // Neumann interface responses: N0 x 4 x 4
+  d.ib = d.nr + (nn ? N0 * 16 : 0);         // direct: interface blocks, 14 per interface
+  d.tg = d.ib + (nn ? 0 : 14 * (N0 + 1));   // traces g_q, q = 0..N0 (ends 0)
+  d.th = d.tg + N0 + 1;                     // traces h_q
   return d;
 }
 
-// LDS doubles of the layout above for n (any N0 with m >= 2)
+// LDS doubles of the Neumann-Neumann layout for n (any N0 with m >= 2)
 __host__ __device__ constexpr size_t dd1_lds_doubles(int n) {
   return (size_t)(n + 2) + 26 * (size_t)(n + 1) + 18 * (size_t)((n + 1) / 2) + 2 + 64;
+}
+// ... and of the direct layout (any N0 <= 64 with m >= 2, or N0 = 1)
+__host__ __device__ constexpr size_t direct1_lds_doubles(int n) {
+  return (size_t)(n + 2) + 14 * (size_t)(n + 1) + 16 * 65 + 64;
 }
 
 // Block Thomas over M nodes with pivots F (inverse 2x2 blocks, row-major) and
@@ -3219,7 +3236,7 @@ __device__ void dd1_factor(const DD1& d, double* F, int lo, int hi, bool neumann
   for (int j = lo; j <= hi; ++j) {
     const bool iface = neumann && (j % d.m == 0);
     const double w = iface ? 0.5 : 1.0, e = iface ? 1.0 : 2.0;
-    const double cj = d.ub[j] * d.ub[j];
+    const double cj = d.cz ? 0.0 : d.ub[j] * d.ub[j];
     double B0 = w, B1 = e * d.a, B2 = -e * d.b - w * cj, B3 = w;
     if (j > lo) {
       // B -= (E Binv_prev) E;  E Binv = [[-a p2, -a p3], [b p0, b p1]]
@@ -3233,33 +3250,32 @@ __device__ void dd1_factor(const DD1& d, double* F, int lo, int hi, bool neumann
   }
 }
 
-// One (2.4) step of the thread's node value u (node tid + 1); iters counts
-// the iterations, status bit 1 flags the cap or a non-finite update.
-__device__ double dd1_step(double u, const InstDev& P, double tau, double* L, int& iters,
-                           int& status) {
-  const DD1 d = dd1_layout(P, tau, L);
+// Stage u_n (the thread's node value u, node tid + 1), factor the subdomain
+// problems and solve for the responses.
+__device__ void dd1_prepare(const DD1& d, double u, bool nn) {
   const int tid = threadIdx.x, N0 = d.N0, m = d.m, MD = d.MD, MN = d.MN, n = d.n;
-  __syncthreads();
+  __syncthreads();   // the previous step's readers are done
   if (tid < n) d.ub[tid + 1] = u;
   if (tid == 0) { d.ub[0] = 0.0; d.ub[n + 1] = 0.0; }
   __syncthreads();
-  for (int t = tid; t < 2 * N0; t += blockDim.x) {
+  const int nf = nn && N0 > 1 ? 2 * N0 : N0;
+  for (int t = tid; t < nf; t += blockDim.x) {
     const int i = t % N0;
     if (t < N0) dd1_factor(d, d.fD + i * MD * 4, i * m + 1, (i + 1) * m - 1, false);
-    else if (N0 > 1) dd1_factor(d, d.fN + i * MN * 4, max(i * m, 1), min((i + 1) * m, n), true);
+    else dd1_factor(d, d.fN + i * MN * 4, max(i * m, 1), min((i + 1) * m, n), true);
   }
   __syncthreads();
   const int nd = 5 * N0;
-  for (int t = tid; t < 9 * N0; t += blockDim.x) {
+  for (int t = tid; t < (nn ? 9 : 5) * N0; t += blockDim.x) {
     if (t < nd) {
-      // Dirichlet responses of subdomain i: 0 = to u_n (traces zero), 1..4 =
-      // to a unit g, h of the left interface, g, h of the right one
+      // Dirichlet responses of subdomain i: 0 = to the data (traces zero),
+      // 1..4 = to a unit g, h of the left interface, g, h of the right one
       const int i = t / 5, k = t % 5;
       double* X = d.rD + (i * 5 + k) * MD * 2;
       const int lo = i * m + 1;
       for (int j = 0; j < MD; ++j) {
         X[2 * j] = k == 0 ? d.ub[lo + j] : 0.0;
-        X[2 * j + 1] = k == 0 ? -d.ub[lo + j] : 0.0;
+        X[2 * j + 1] = k == 0 ? d.fvs * d.ub[lo + j] : 0.0;
       }
       if ((i == 0 && (k == 1 || k == 2)) || (i == N0 - 1 && (k == 3 || k == 4))) continue;
       // the coupling -E (g, h) of a trace moves to the right-hand side: (a h, -b g)
@@ -3285,6 +3301,39 @@ __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, in
     }
   }
   __syncthreads();
+}
+
+// Dirichlet responses next to interface q (1..N0-1): RL of the left
+// subdomain's last interior node, RR of the right one's first (u, v each).
+__device__ __forceinline__ void dd1_near(const DD1& d, int q, double (&RL)[5][2],
+                                         double (&RR)[5][2]) {
+  for (int k = 0; k < 5; ++k)
+    for (int s = 0; s < 2; ++s) {
+      RL[k][s] = d.rD[(((q - 1) * 5 + k) * d.MD + d.MD - 1) * 2 + s];
+      RR[k][s] = d.rD[((q * 5 + k) * d.MD) * 2 + s];
+    }
+}
+
+// The step's result at the thread's node from the traces tg, th.
+__device__ __forceinline__ double dd1_result(const DD1& d) {
+  const int tid = threadIdx.x;
+  if (tid >= d.n) return 0.0;
+  const int j = tid + 1, i = j / d.m;
+  if (j % d.m == 0) return d.tg[i];
+  const int k = j - i * d.m - 1;
+  const double c[5] = {1.0, d.tg[i], d.th[i], d.tg[i + 1], d.th[i + 1]};
+  double v = 0.0;
+  for (int r = 0; r < 5; ++r) v += c[r] * d.rD[((i * 5 + r) * d.MD + k) * 2];
+  return v;
+}
+
+// One Neumann-Neumann step (2.4) of the thread's node value u; iters counts
+// the iterations, status bit 1 flags the cap or a non-finite update.
+__device__ double dd1_step(double u, const InstDev& P, double tau, double* L, int& iters,
+                           int& status) {
+  const DD1 d = dd1_layout(P, P.dd_sub, tau, L, true);
+  const int tid = threadIdx.x, N0 = d.N0, m = d.m;
+  dd1_prepare(d, u, true);
   if (tid < 64) {
     // lane q: interface q (1..N0-1); the other lanes carry zeros
     const int q = tid;
@@ -3294,14 +3343,11 @@ __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, in
     if (on) {
       const int p = q * m;
       up = d.ub[p];
-      cp = up * up;
+      cp = d.cz ? 0.0 : up * up;
+      // initial traces: the mixed variables of u_n (v = -eps^2 Lap u + c u + f_v)
       g = up;
-      h = -d.b * (d.ub[p - 1] - 2.0 * up + d.ub[p + 1]) + up * up * up - up;
-      for (int k = 0; k < 5; ++k)
-        for (int s = 0; s < 2; ++s) {
-          RL[k][s] = d.rD[(((q - 1) * 5 + k) * MD + MD - 1) * 2 + s];
-          RR[k][s] = d.rD[((q * 5 + k) * MD) * 2 + s];
-        }
+      h = -d.b * (d.ub[p - 1] - 2.0 * up + d.ub[p + 1]) + cp * up + d.fvs * up;
+      dd1_near(d, q, RL, RR);
       for (int e = 0; e < 4; ++e)
         for (int s = 0; s < 2; ++s) {
           NL[e][s] = d.nr[((q - 1) * 4 + e) * 4 + 2 + s];
@@ -3326,7 +3372,7 @@ __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, in
       }
       // residual of the global equations at p_q: the jump of the Neumann traces
       double ru = up - (g - d.a * (Lv[1] - 2.0 * h + Rv[1]));
-      double rv = -up - (d.b * (Lv[0] - 2.0 * g + Rv[0]) - cp * g + h);
+      double rv = d.fvs * up - (d.b * (Lv[0] - 2.0 * g + Rv[0]) - cp * g + h);
       if (!on) ru = rv = 0.0;
       const double rul = __shfl(ru, (q + 63) & 63, 64), rvl = __shfl(rv, (q + 63) & 63, 64);
       const double rur = __shfl(ru, (q + 1) & 63, 64), rvr = __shfl(rv, (q + 1) & 63, 64);
@@ -3356,16 +3402,79 @@ __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, in
     if (tid == 0) { d.tg[0] = d.th[0] = d.tg[N0] = d.th[N0] = 0.0; }
   }
   __syncthreads();
-  if (tid < n) {
-    const int j = tid + 1, i = j / m;
-    if (j % m == 0) return d.tg[i];
-    const int k = j - i * m - 1;
-    const double c[5] = {1.0, d.tg[i], d.th[i], d.tg[i + 1], d.th[i + 1]};
-    double v = 0.0;
-    for (int r = 0; r < 5; ++r) v += c[r] * d.rD[((i * 5 + r) * MD + k) * 2];
-    return v;
+  return dd1_result(d);
+}
+
+// 2x2 helpers (row-major)
+__device__ __forceinline__ void m2_inv(const double* A, double* R) {
+  const double id = 1.0 / (A[0] * A[3] - A[1] * A[2]);
+  const double r0 = A[3] * id, r1 = -A[1] * id, r2 = -A[2] * id, r3 = A[0] * id;
+  R[0] = r0; R[1] = r1; R[2] = r2; R[3] = r3;
+}
+__device__ __forceinline__ void m2_mul(const double* A, const double* B, double* R) {
+  const double r0 = A[0] * B[0] + A[1] * B[2], r1 = A[0] * B[1] + A[1] * B[3];
+  const double r2 = A[2] * B[0] + A[3] * B[2], r3 = A[2] * B[1] + A[3] * B[3];
+  R[0] = r0; R[1] = r1; R[2] = r2; R[3] = r3;
+}
+
+// One (2.4) step solved directly by substructuring on P.direct_sub equal
+// subdomains: the global equations at the interface nodes, written with the
+// subdomains' responses, are block tridiagonal in the traces x_q = (g_q, h_q):
+// A_q x_{q-1} + B_q x_q + C_q x_{q+1} = D_q.  One lane per interface forms
+// its blocks, one lane eliminates them (block Thomas), then every node takes
+// its subdomain's state.
+__device__ double dd1_direct_step(double u, const InstDev& P, double tau, double* L) {
+  const DD1 d = dd1_layout(P, P.direct_sub, tau, L, false);
+  const int tid = threadIdx.x, N0 = d.N0;
+  dd1_prepare(d, u, false);
+  const int q = tid;
+  if (q >= 1 && q < N0) {
+    double RL[5][2], RR[5][2];
+    dd1_near(d, q, RL, RR);
+    const double up = d.ub[q * d.m], cp = d.cz ? 0.0 : up * up;
+    const double a = d.a, b = d.b;
+    // r_u = f_u - [g - a (v_L - 2 h + v_R)], r_v = f_v - [b (u_L - 2 g + u_R)
+    // - c g + h], with (u, v)_L, (u, v)_R affine in the traces; r = 0
+    double* e = d.ib + 14 * q;       // A (4), B (4), C (4), D (2)
+    e[0] = a * RL[1][1];  e[1] = a * RL[2][1];  e[2] = -b * RL[1][0];  e[3] = -b * RL[2][0];
+    e[4] = -1.0 + a * (RL[3][1] + RR[1][1]);
+    e[5] = a * (RL[4][1] + RR[2][1] - 2.0);
+    e[6] = -b * (RL[3][0] + RR[1][0] - 2.0) + cp;
+    e[7] = -b * (RL[4][0] + RR[2][0]) - 1.0;
+    e[8] = a * RR[3][1];  e[9] = a * RR[4][1];  e[10] = -b * RR[3][0];  e[11] = -b * RR[4][0];
+    e[12] = -(up + a * (RL[0][1] + RR[0][1]));
+    e[13] = -(d.fvs * up - b * (RL[0][0] + RR[0][0]));
   }
-  return 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    // forward: B'_q = B_q - A_q B'^-1_{q-1} C_{q-1}, D'_q = D_q - A_q B'^-1_{q-1} D'_{q-1}
+    // (B'^-1 kept in place of B, D' in place of D)
+    for (int k = 1; k < N0; ++k) {
+      double* e = d.ib + 14 * k;
+      if (k > 1) {
+        const double* f = d.ib + 14 * (k - 1);
+        double W[4], WC[4];
+        m2_mul(e, f + 4, W);          // A_q B'^-1_{q-1}
+        m2_mul(W, f + 8, WC);
+        for (int r = 0; r < 4; ++r) e[4 + r] -= WC[r];
+        e[12] -= W[0] * f[12] + W[1] * f[13];
+        e[13] -= W[2] * f[12] + W[3] * f[13];
+      }
+      m2_inv(e + 4, e + 4);
+    }
+    double xg = 0.0, xh = 0.0;
+    for (int k = N0 - 1; k >= 1; --k) {
+      const double* e = d.ib + 14 * k;
+      const double r0 = e[12] - (e[8] * xg + e[9] * xh), r1 = e[13] - (e[10] * xg + e[11] * xh);
+      xg = e[4] * r0 + e[5] * r1;
+      xh = e[6] * r0 + e[7] * r1;
+      d.tg[k] = xg;
+      d.th[k] = xh;
+    }
+    d.tg[0] = d.th[0] = d.tg[N0] = d.th[N0] = 0.0;
+  }
+  __syncthreads();
+  return dd1_result(d);
 }
 
 // Fine propagator of one work item with the Neumann-Neumann step: J steps;
@@ -3392,40 +3501,15 @@ k_fine_dd_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ ins
   }
 }
 
-// Scheme (2.4) steps of tau solved directly: the mixed block-tridiagonal
-// system [I, -tau L; eps^2 L - diag(c), I][u; v] = [u_n; -u_n] with
-// c = u_n^2 (f == 0: c = 0 and right-hand side [u_n; 0]) eliminated by
-// 2x2-block Thomas on one lane.  Its chain of 2n pivots is far shorter than
-// the transforms and reductions of the CG iterations the sine-basis solve
-// needs, and the result is exact up to rounding.
+// Scheme (2.4) steps of tau solved directly (dd1_direct_step); the chains
+// are the subdomains' m-node eliminations and the N0-long interface
+// elimination instead of one 2n-pivot elimination, and far shorter than the
+// transforms and reductions of CG iterations in the sine basis.
 __device__ double approx2_direct1(const Ctx1& c, double u, const InstDev& P, double tau,
                                   int steps) {
-  DD1 d;
-  d.n = c.n; d.N0 = 1; d.m = c.n + 1; d.MD = c.n; d.MN = 0;
-  d.a = tau / (P.h * P.h); d.b = P.eps * P.eps / (P.h * P.h);
-  d.ub = c.dl;                      // c_j = ub[j]^2, nodes 1..n
-  double* F = d.ub + c.n + 2;       // pivots, 4 per node
-  double* X = F + 4 * c.n;          // right-hand side, then the solution
-  for (int m = 0; m < steps; ++m) {
-    __syncthreads();
-    if (c.on) {
-      d.ub[c.i + 1] = P.f_zero ? 0.0 : u;
-      X[2 * c.i] = u;
-      X[2 * c.i + 1] = P.f_zero ? 0.0 : -u;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      dd1_factor(d, F, 1, c.n, false);
-      dd1_solve(d, F, X, c.n);
-    }
-    __syncthreads();
-    u = c.on ? X[2 * c.i] : 0.0;
-  }
+  for (int m = 0; m < steps; ++m) u = dd1_direct_step(u, P, tau, c.dl);
   return u;
 }
-
-// LDS doubles of the direct (2.4) solve after S, buf and red
-__host__ __device__ constexpr size_t direct1_lds_doubles(int n) { return 7 * (size_t)n + 2; }
 
 // Linear stabilised steps: (I + tau eps^2 L^2 - s tau L) v = u + tau L (f(u) - s u),
 // diagonal on the sine modes with 1 / sigma = rsig[i].
@@ -3515,9 +3599,11 @@ __global__ void k_fine_1d(const WorkItem* __restrict__ items, const InstDev* __r
   if (mask && !mask[P.slice_base + it.slice]) return;
   if ((kmin && it.slice < *kmin) || (active && !active[it.inst])) return;
   const int n = P.n;
-  Ctx1 c{smem, smem + n * n, smem + n * n + n, n, (int)threadIdx.x, (int)threadIdx.x < n,
-         smem + n * n + n + 64};
-  if (P.fine_kind != 2)   // the direct (2.4) solve needs no sine matrix
+  // the direct (2.4) solve needs no sine matrix: its launch holds none
+  const int so = P.fine_kind != 2 ? n * n : 0;
+  Ctx1 c{smem, smem + so, smem + so + n, n, (int)threadIdx.x, (int)threadIdx.x < n,
+         smem + so + n + 64};
+  if (so)
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) smem[idx] = S[idx];
   const int64_t in0 = (in_iter ? P.off_iter : P.off_slices) + (int64_t)it.slice * n;
   double u = c.on ? U_in[in0 + c.i] : 0.0;
@@ -3729,13 +3815,13 @@ template <int N, int NW>
 static hipError_t fine_stream(const WorkItem* items, int n_items, const InstDev* inst,
                               const double* Tg, const double* U_in, double* F_out,
                               const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
-                              hipStream_t s) {
+                              hipStream_t s, int j_steps) {
   const size_t lds = (size_t)(2 * GeoS<N, NW>::CHUNK + GeoS<N, NW>::P2) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_linear_stream<N, NW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fine_linear_stream<N, NW>), dim3(n_items), dim3(NW * 64), lds, s, items,
-                     inst, Tg, U_in, F_out, mask, active, kmin, in_iter);
+                     inst, Tg, U_in, F_out, mask, active, kmin, in_iter, j_steps);
   return hipGetLastError();
 }
 
@@ -3756,7 +3842,7 @@ hipError_t launch_fine_2d(int n, const WorkItem* items, int n_items, const InstD
   if (n_items <= 0) return hipSuccess;
   const int key = n * 100 + waves;
   switch (key) {
-    case 25608: case 25600: return fine_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s);
+    case 25608: case 25600: return fine_stream<256, 8>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
     case 3202: case 3200: return fine2d<32, 2>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
     case 3201: return fine2d<32, 1>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
     case 6404: case 6400: return fine2d<64, 4>(items, n_items, inst, Tg, U_in, F_out, mask, active, kmin, in_iter, s, j_steps);
@@ -3855,14 +3941,13 @@ hipError_t launch_fine_newton_2d(int n, const WorkItem* items, int n_items, cons
 }
 
 hipError_t launch_fine_1d(int n, const WorkItem* items, int n_items, const InstDev* inst,
-                          const double* S, const double* rsig1, const double* U_in, double* F_out,
+                          const double* S, const double* U_in, double* F_out,
                           const uint8_t* mask, const int32_t* active, const int32_t* kmin, int in_iter,
-                          hipStream_t s) {
-  (void)rsig1;
+                          hipStream_t s, int sine) {
   if (n_items <= 0) return hipSuccess;
   // lam for 1D is stored right after S (n x n) in the table block
   const double* lam = S + (size_t)n * n;
-  const size_t lds = ((size_t)n * n + n + 64 + direct1_lds_doubles(n)) * sizeof(double);
+  const size_t lds = ((sine ? (size_t)n * n : 0) + n + 64 + direct1_lds_doubles(n)) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_fine_1d,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -4177,6 +4262,15 @@ hipError_t launch_fine_newton_group(int n, int groups, const WorkItem* items, in
 // any count; at n = 128 one workgroup per slice is faster once the slices
 // alone fill the device, at n = 256 the group kernel (state on chip in the
 // members' slabs) beats the streamed one-workgroup kernel at any count.
+// Group sizes of the linear fine sweep for class size n (tuning candidates).
+int fine_group_options(int n, int* out) {
+  switch (n) {
+    case 128: out[0] = 8; out[1] = 4; return 2;
+    case 256: out[0] = 8; return 1;
+    default: return 0;
+  }
+}
+
 int fine_group_capacity(int n) {
   switch (n) {
     case 128: return 64;
