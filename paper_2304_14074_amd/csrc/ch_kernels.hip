@@ -3202,48 +3202,78 @@ __host__ __device__ constexpr size_t direct1_lds_doubles(int n) {
   return (size_t)(n + 2) + 14 * (size_t)(n + 1) + 16 * 65 + 64;
 }
 
+// 1/x by Newton's iteration r <- r (2 - x r) from the hardware estimate,
+// twice (each step squares the relative error): a shorter dependent chain
+// than a correctly rounded division, accurate to an ulp or so.
+__device__ __forceinline__ double dd1_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // Block Thomas over M nodes with pivots F (inverse 2x2 blocks, row-major) and
-// the coupling E: X holds d on entry and the solution on exit.
+// the coupling E: X holds d on entry and the solution on exit.  The next
+// node's operands are loaded before the current node's results are stored,
+// so the chain does not wait for the stores.
 __device__ void dd1_solve(const DD1& d, const double* F, double* X, int M) {
   // the running y_k stays in registers (no LDS round trip on the chain)
   double y0 = X[0], y1 = X[1];
+  double q0 = 0, q1 = 0, q2 = 0, q3 = 0, n0 = 0, n1 = 0;
+  if (M > 1) { q0 = F[0]; q1 = F[1]; q2 = F[2]; q3 = F[3]; n0 = X[2]; n1 = X[3]; }
   for (int k = 1; k < M; ++k) {
     // y_k = d_k - E Binv_{k-1} y_{k-1}
-    const double* p = F + (k - 1) * 4;
-    const double t0 = p[2] * y0 + p[3] * y1, t1 = p[0] * y0 + p[1] * y1;
-    y0 = X[2 * k] + d.a * t0;
-    y1 = X[2 * k + 1] - d.b * t1;
+    const double p0 = q0, p1 = q1, p2 = q2, p3 = q3, d0 = n0, d1 = n1;
+    if (k + 1 < M) {
+      q0 = F[4 * k]; q1 = F[4 * k + 1]; q2 = F[4 * k + 2]; q3 = F[4 * k + 3];
+      n0 = X[2 * k + 2]; n1 = X[2 * k + 3];
+    }
+    const double t0 = p2 * y0 + p3 * y1, t1 = p0 * y0 + p1 * y1;
+    y0 = d0 + d.a * t0;
+    y1 = d1 - d.b * t1;
     X[2 * k] = y0;
     X[2 * k + 1] = y1;
   }
   const double* p = F + (M - 1) * 4;
   double x0 = p[0] * y0 + p[1] * y1;
   double x1 = p[2] * y0 + p[3] * y1;
+  if (M > 1) {
+    q0 = F[4 * (M - 2)]; q1 = F[4 * (M - 2) + 1]; q2 = F[4 * (M - 2) + 2]; q3 = F[4 * (M - 2) + 3];
+    n0 = X[2 * (M - 2)]; n1 = X[2 * (M - 2) + 1];
+  }
   X[2 * M - 2] = x0; X[2 * M - 1] = x1;
   for (int k = M - 2; k >= 0; --k) {
     // x_k = Binv_k (y_k - E x_{k+1}),  E x = (-a x1, b x0)
-    const double r0 = X[2 * k] + d.a * x1, r1 = X[2 * k + 1] - d.b * x0;
-    p = F + k * 4;
-    x0 = p[0] * r0 + p[1] * r1;
-    x1 = p[2] * r0 + p[3] * r1;
+    const double p0 = q0, p1 = q1, p2 = q2, p3 = q3;
+    const double r0 = n0 + d.a * x1, r1 = n1 - d.b * x0;
+    if (k > 0) {
+      q0 = F[4 * (k - 1)]; q1 = F[4 * (k - 1) + 1]; q2 = F[4 * (k - 1) + 2]; q3 = F[4 * (k - 1) + 3];
+      n0 = X[2 * (k - 1)]; n1 = X[2 * (k - 1) + 1];
+    }
+    x0 = p0 * r0 + p1 * r1;
+    x1 = p2 * r0 + p3 * r1;
     X[2 * k] = x0; X[2 * k + 1] = x1;
   }
 }
 
-// Factor one subdomain problem: nodes lo..hi, pivots to F.
-__device__ void dd1_factor(const DD1& d, double* F, int lo, int hi, bool neumann) {
+// Factor one subdomain problem: nodes lo..hi, pivots to F; il, ir: lo, hi
+// are interface nodes of a Neumann problem.
+__device__ void dd1_factor(const DD1& d, double* F, int lo, int hi, bool il, bool ir) {
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+  double un = d.ub[lo];                       // next node's u_n, loaded ahead
   for (int j = lo; j <= hi; ++j) {
-    const bool iface = neumann && (j % d.m == 0);
+    const double uj = un;
+    if (j < hi) un = d.ub[j + 1];
+    const bool iface = (j == lo && il) || (j == hi && ir);
     const double w = iface ? 0.5 : 1.0, e = iface ? 1.0 : 2.0;
-    const double cj = d.cz ? 0.0 : d.ub[j] * d.ub[j];
+    const double cj = d.cz ? 0.0 : uj * uj;
     double B0 = w, B1 = e * d.a, B2 = -e * d.b - w * cj, B3 = w;
     if (j > lo) {
       // B -= (E Binv_prev) E;  E Binv = [[-a p2, -a p3], [b p0, b p1]]
       const double W0 = -d.a * p2, W1 = -d.a * p3, W2 = d.b * p0, W3 = d.b * p1;
       B0 -= d.b * W1; B1 += d.a * W0; B2 -= d.b * W3; B3 += d.a * W2;
     }
-    const double det = B0 * B3 - B1 * B2, id = 1.0 / det;
+    const double id = dd1_recip(B0 * B3 - B1 * B2);
     p0 = B3 * id; p1 = -B1 * id; p2 = -B2 * id; p3 = B0 * id;
     double* q = F + (j - lo) * 4;
     q[0] = p0; q[1] = p1; q[2] = p2; q[3] = p3;
@@ -3258,15 +3288,18 @@ __device__ void dd1_prepare(const DD1& d, double u, bool nn) {
   if (tid < n) d.ub[tid + 1] = u;
   if (tid == 0) { d.ub[0] = 0.0; d.ub[n + 1] = 0.0; }
   __syncthreads();
-  const int nf = nn && N0 > 1 ? 2 * N0 : N0;
-  for (int t = tid; t < nf; t += blockDim.x) {
-    const int i = t % N0;
-    if (t < N0) dd1_factor(d, d.fD + i * MD * 4, i * m + 1, (i + 1) * m - 1, false);
-    else dd1_factor(d, d.fN + i * MN * 4, max(i * m, 1), min((i + 1) * m, n), true);
-  }
+  // Dirichlet work on the first wave, Neumann work on the second: the two
+  // run side by side instead of one after the other in a divergent wave
+  const int w = tid >> 6, l = tid & 63;
+  const bool neu = nn && N0 > 1 && w == 1;
+  if (w == 0 || neu)
+    for (int i = l; i < N0; i += 64) {
+      if (!neu) dd1_factor(d, d.fD + i * MD * 4, i * m + 1, (i + 1) * m - 1, false, false);
+      else dd1_factor(d, d.fN + i * MN * 4, max(i * m, 1), min((i + 1) * m, n), i > 0, i < N0 - 1);
+    }
   __syncthreads();
   const int nd = 5 * N0;
-  for (int t = tid; t < (nn ? 9 : 5) * N0; t += blockDim.x) {
+  for (int t = w == 0 ? l : (neu ? nd + l : 9 * N0); t < (w == 0 ? nd : 9 * N0); t += 64) {
     if (t < nd) {
       // Dirichlet responses of subdomain i: 0 = to the data (traces zero),
       // 1..4 = to a unit g, h of the left interface, g, h of the right one
