@@ -135,9 +135,10 @@ def bench_nonlinear(args):
     """The 2D 256x256 implicit workload (eps = 0.015, N = 128, dt = 1e-5, scheme
     (2.3) by Newton with spectral CG): the fine sweep over all 128 slices,
     timed over the first `nl_steps` of each slice's J = 3125 steps from the
-    coarse prediction U^0.  Newton and CG iteration counts depend on the state,
-    so executed flops are not counted (roofline null); value is fine
-    grid-point-steps per second at the full shape."""
+    coarse prediction U^0.  Newton and CG iteration counts depend on the
+    state; the roofline's executed flops come from the counts the group
+    kernel records on the device.  value is fine grid-point-steps per second
+    at the full shape."""
     import dataclasses
     import torch
     import workloads
@@ -167,6 +168,14 @@ def bench_nonlinear(args):
     ms = e0.elapsed_time(e1) / args.steps
     point_steps = N * args.nl_steps * P
     ok = bool(torch.isfinite(F).all().item())
+    cq.ch_check_status()
+    # executed matrix-core work from the device's counts: n^3 flops per sine
+    # transform stage; 4 stages per Newton iteration, 4 per CG operator
+    # application, 4 per slice to enter and leave the sine basis
+    newton, applies = cq.ch_solver_counts(0)
+    stages = sum(4 * a + 4 * b + 4 for a, b in zip(newton, applies))
+    nl_flops = stages * float(n) ** 3
+    nl_tf = nl_flops / (ms / 1e3) / 1e12
     # the fully implicit backward-Euler variant of the step on the same shape
     qb = dataclasses.replace(q, nl_variant="be")
     cb = chlib.Context([qb])
@@ -194,8 +203,15 @@ def bench_nonlinear(args):
                        "n": n, "slices": N, "fine_steps_timed": args.nl_steps,
                        "fine_steps_per_slice": prob.j_fine,
                        "fine_groups": cq.ch_fine_groups(n, fine_kind="nonlinear")},
-            "roofline": None,
+            "roofline": {"bound": "mfma", "achieved": nl_tf, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": nl_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                         "kernel": "k_fine_newton_group<256,16,8> (groups of 16 workgroups per "
+                                   "slice); flops: n^3 per executed sine-transform stage, from "
+                                   "the device's Newton and CG counts"},
             "extra": {"ms_per_fine_step": ms / args.nl_steps,
+                      "newton_iterations_per_step": sum(newton) / (N * args.nl_steps),
+                      "cg_applications_per_newton_iteration": sum(applies) / max(sum(newton), 1),
+                      "executed_flops_per_sweep": nl_flops,
                       "projected_full_fine_sweep_s": ms / args.nl_steps * prob.j_fine / 1e3,
                       "status": int(st["status"][0].item()), "finite": ok,
                       "backward_euler": be}}

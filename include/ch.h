@@ -379,6 +379,22 @@ ch_status ch_judge_read(ch_ctx* ctx, int32_t inst, double* ratios, int32_t* fall
  * `stream` drains.  CH_ERR_ARG for an instance of another fine kind. */
 ch_status ch_dd_iterations(ch_ctx* ctx, int32_t inst, int32_t* iters, ch_stream stream);
 
+/* Implicit fine step (2.3) or backward Euler solved by Newton's method with
+ * spectral CG (Section 3, the Newton iteration of NPA-II), on groups of
+ * workgroups: per slice of instance inst, the Newton iterations and the
+ * applications of the CG operator (one per CG iteration, plus one to start
+ * each solve) that its J steps took in the latest fine sweep that processed
+ * it.  They give the sweep's executed matrix-core work: n^3 flops per sine
+ * transform stage, four stages per Newton iteration (the state and its cube
+ * to physical space and back) and four per operator application, plus four
+ * per slice to enter and leave the sine basis.  newton,
+ * krylov: host memory of N int32 each, written synchronously after `stream`
+ * drains.  CH_ERR_ARG for another fine kind; CH_ERR_UNSUPPORTED when the
+ * instance's class runs one workgroup per slice (those kernels do not
+ * count). */
+ch_status ch_solver_counts(ch_ctx* ctx, int32_t inst, int32_t* newton, int32_t* krylov,
+                           ch_stream stream);
+
 const char* ch_status_str(ch_status s);
 const char* ch_last_error(const ch_ctx* ctx);
 

@@ -29,7 +29,8 @@ EXPORTS = ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", 
            "ch_parareal_graph_create", "ch_graph_launch", "ch_graph_destroy", "ch_iteration_count",
            "ch_autotune", "ch_fine_variant", "ch_set_iteration", "ch_chain_variant", "ch_fine_groups",
            "ch_parareal_run", "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
-           "ch_nn_forward_static", "ch_linear_bound", "ch_judge_read", "ch_dd_iterations")
+           "ch_nn_forward_static", "ch_linear_bound", "ch_judge_read", "ch_dd_iterations",
+           "ch_solver_counts")
 
 
 class ChProblem(ctypes.Structure):
@@ -116,6 +117,7 @@ def load() -> ctypes.CDLL:
     dp = ctypes.POINTER(ctypes.c_double)
     lib.ch_judge_read.argtypes = [vp, i32, dp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
     lib.ch_dd_iterations.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
+    lib.ch_solver_counts.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
     lib.ch_linear_bound.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, i32, i32,
                                     ctypes.c_double, ctypes.c_double, dp, dp]
     for name in ("ch_nn_layer", "ch_nn_forward", "ch_nn_forward_static", "ch_nn_train_step", "ch_nn_adam", "ch_nn_to_bf16",
@@ -123,7 +125,7 @@ def load() -> ctypes.CDLL:
                  "ch_graph_destroy", "ch_iteration_count", "ch_autotune", "ch_fine_variant",
                  "ch_set_iteration", "ch_chain_variant", "ch_fine_groups", "ch_parareal_run",
                  "ch_slice_distance", "ch_check_status", "ch_set_wait_limit",
-                 "ch_linear_bound", "ch_judge_read", "ch_dd_iterations"):
+                 "ch_linear_bound", "ch_judge_read", "ch_dd_iterations", "ch_solver_counts"):
         getattr(lib, name).restype = i32
     for name in ("ch_create", "ch_destroy", "ch_workspace_size", "ch_bind_workspace", "ch_layout",
                  "ch_fine_propagate", "ch_coarse_propagate", "ch_parareal_iterate",
@@ -279,6 +281,14 @@ class Context:
         r = (ctypes.c_int32 * N)()
         self._check(self.lib.ch_dd_iterations(self.h, inst, r, _stream(stream)))
         return list(r)
+
+    def ch_solver_counts(self, inst=0, stream=None):
+        """(Newton iterations, CG operator applications) of each slice's J
+        implicit fine steps in the latest fine sweep (two lists of N ints)."""
+        N = self.problems[inst].n_slices
+        a, b = (ctypes.c_int32 * N)(), (ctypes.c_int32 * N)()
+        self._check(self.lib.ch_solver_counts(self.h, inst, a, b, _stream(stream)))
+        return list(a), list(b)
 
     def ch_set_wait_limit(self, group_seconds=0.2, pipe_seconds=10.0, stream=None):
         self._check(self.lib.ch_set_wait_limit(self.h, float(group_seconds), float(pipe_seconds),

@@ -50,7 +50,7 @@ struct ch_ctx {
   int64_t slice_total = 0, iter_total = 0;
   std::vector<ClassPlan> classes;
   Block inst_blk, active_blk, status_blk, k_blk;
-  Block dd_blk;                     // Neumann-Neumann iteration counts per slice
+  Block iters_blk;                  // solver iteration counts, two per slice
   std::vector<Block> rsig_fine_blk, rsig_stab_blk, tab_blk, work_blk;
   // learned coarse propagator
   Block nn_blk, nn_out_blk, nn_part_blk;
@@ -320,9 +320,9 @@ ch_status ch_create(const ch_problem* probs, int32_t n_inst, ch_ctx** out) {
     c->rsig_fine_blk[i] = take(sizeof(double) * P);
     c->rsig_stab_blk[i] = take(sizeof(double) * P);
   }
-  // iteration counts of the Neumann-Neumann fine step, one per slice (zeroed
-  // with the host image)
-  c->dd_blk = take(sizeof(int32_t) * (size_t)slice_base);
+  // solver iteration counts of the fine sweeps, two per slice (zeroed with
+  // the host image)
+  c->iters_blk = take(sizeof(int32_t) * 2 * (size_t)slice_base);
   c->host_init_bytes = off;
   for (auto& cp : c->classes) {
     if (cp.dim != 2) continue;
@@ -438,7 +438,7 @@ ch_status ch_bind_workspace(ch_ctx* c, void* dptr, size_t bytes, ch_stream strea
     d.tab = p.dim == 2 ? (double*)(ws + c->tab_blk[i].off) : nullptr;
     d.work = p.dim == 2 ? (double*)(ws + c->work_blk[i].off) : nullptr;
     d.status = (int32_t*)(ws + c->status_blk.off) + i;
-    d.dd_iters = (int32_t*)(ws + c->dd_blk.off) + d.slice_base;
+    d.iters = (int32_t*)(ws + c->iters_blk.off) + 2 * d.slice_base;
     // inverse symbols 1/(1 + tau eps^2 Lam^2 - s tau Lam) of the linear step
     const int n = p.n;
     std::vector<double> lam(n);
@@ -1400,6 +1400,25 @@ ch_status ch_judge_read(ch_ctx* c, int32_t inst, double* ratios, int32_t* fallba
   return CH_OK;
 }
 
+// Both counts of every slice of instance inst (host, synchronous).
+static ch_status read_iters(ch_ctx* c, int32_t inst, int32_t* outer, int32_t* inner,
+                            ch_stream stream) {
+  const int N = c->probs[inst].n_slices;
+  std::vector<int32_t> v(2 * (size_t)N);
+  hipStream_t s = (hipStream_t)stream;
+  ch_status r = hip_check(c, hipMemcpyAsync(v.data(), (int32_t*)(c->ws + c->iters_blk.off) +
+                                                          2 * c->inst[inst].slice_base,
+                                            sizeof(int32_t) * 2 * N, hipMemcpyDeviceToHost, s),
+                          "iteration count read");
+  if (r == CH_OK) r = hip_check(c, hipStreamSynchronize(s), "iteration count sync");
+  if (r != CH_OK) return r;
+  for (int k = 0; k < N; ++k) {
+    if (outer) outer[k] = v[2 * k];
+    if (inner) inner[k] = v[2 * k + 1];
+  }
+  return CH_OK;
+}
+
 ch_status ch_dd_iterations(ch_ctx* c, int32_t inst, int32_t* iters, ch_stream stream) {
   ch_status r = require_bound(c);
   if (r != CH_OK) return r;
@@ -1407,12 +1426,24 @@ ch_status ch_dd_iterations(ch_ctx* c, int32_t inst, int32_t* iters, ch_stream st
   if (!iters) return fail(c, CH_ERR_ARG, "null pointer");
   if (c->probs[inst].fine_kind != CH_FINE_APPROX2_DD)
     return fail(c, CH_ERR_ARG, "instance %d does not use the Neumann-Neumann fine step", inst);
-  hipStream_t s = (hipStream_t)stream;
-  r = hip_check(c, hipMemcpyAsync(iters, (int32_t*)(c->ws + c->dd_blk.off) + c->inst[inst].slice_base,
-                                  sizeof(int32_t) * c->probs[inst].n_slices, hipMemcpyDeviceToHost, s),
-                "iteration count read");
-  if (r == CH_OK) r = hip_check(c, hipStreamSynchronize(s), "iteration count sync");
-  return r;
+  return read_iters(c, inst, iters, nullptr, stream);
+}
+
+ch_status ch_solver_counts(ch_ctx* c, int32_t inst, int32_t* newton, int32_t* krylov,
+                           ch_stream stream) {
+  ch_status r = require_bound(c);
+  if (r != CH_OK) return r;
+  if (inst < 0 || inst >= (int32_t)c->probs.size()) return fail(c, CH_ERR_ARG, "instance index");
+  if (!newton || !krylov) return fail(c, CH_ERR_ARG, "null pointer");
+  const ch_problem& p = c->probs[inst];
+  if (p.fine_kind != CH_FINE_NONLINEAR || p.dim != 2)
+    return fail(c, CH_ERR_ARG, "instance %d does not use the 2D implicit fine step", inst);
+  for (auto& cp : c->classes)
+    if (cp.dim == 2 && cp.n == p.n && cp.fine_kind == p.fine_kind && cp.precision == p.precision &&
+        cp.fine_groups <= 1)
+      return fail(c, CH_ERR_UNSUPPORTED,
+                  "instance %d runs on one workgroup per slice, which does not count", inst);
+  return read_iters(c, inst, newton, krylov, stream);
 }
 
 ch_status ch_slice_distance(ch_ctx* c, const double* A, const double* B, double* out,

@@ -30,12 +30,14 @@ struct InstDev {
   // a group barrier (default 0.2 s) and a hand-off of the pipelined launch
   // (default 10 s); a wait that runs out flags status bit 4
   uint64_t wait_ticks, pipe_wait_ticks;
-  // Neumann-Neumann fine step: subdomains, iteration cap, relaxation, stop,
-  // per-slice iteration counts of the latest sweep
+  // Neumann-Neumann fine step: subdomains, iteration cap, relaxation, stop
   int32_t dd_sub, dd_max;
   int32_t direct_sub;        // subdomains of the direct 1D (2.4) solve
   double dd_theta, dd_tol;
-  int32_t* dd_iters;
+  // per slice of the latest fine sweep that counted: [2 s] outer iterations
+  // (Neumann-Neumann, or Newton in the group kernels), [2 s + 1] Krylov
+  // operator applications (Newton group kernels)
+  int32_t* iters;
 };
 constexpr uint64_t WAIT_TICKS_DEFAULT = 20000000ull;
 constexpr uint64_t PIPE_WAIT_TICKS_DEFAULT = 1000000000ull;

@@ -1438,7 +1438,7 @@ template <int N, int G, int NW, bool OPQ>
 __device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, const double* Dl,
                         const double* Ml, const double* Ql, double tau, double rtol, int maxit,
                         double (&rv)[GeoC<N, G, NW>::OWN], double (&xv)[GeoC<N, G, NW>::OWN],
-                        double (&y)[GeoC<N, G, NW>::OWN]) {
+                        double (&y)[GeoC<N, G, NW>::OWN], int& applies) {
   using C = GeoC<N, G, NW>;
   const int t = threadIdx.x;
   double pv[C::OWN], sv[C::OWN];
@@ -1454,6 +1454,7 @@ __device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, c
     acc[2] += rv[s] * rv[s];
   }
   coop_apply_K<N, G, NW, OPQ>(Xs, T, cc, pv, sv, Dl, Ql, tau, acc, red);
+  ++applies;
 #pragma unroll
   for (int s = 0; s < C::OWN; ++s) sv[s] = Dl[s * C::NT + t] * pv[s] + tau * sv[s];   // w_0 = K z_0
   double gam = acc[0];
@@ -1475,6 +1476,7 @@ __device__ bool coop_cg(double* Xs, const double* T, double* red, CoopCtx& cc, c
       a3[2] += rv[s] * rv[s];
     }
     coop_apply_K<N, G, NW, OPQ>(Xs, T, cc, z, y, Dl, Ql, tau, a3, red);
+    ++applies;
     if (a3[2] <= stop2) { done = true; break; }
     // a3 is the same in every member; cc.ok drops only on a barrier time-out
     if (!(a3[2] == a3[2]) || !cc.ok) break;
@@ -1538,8 +1540,9 @@ __device__ void coop_approx2(double* Xs, double (&u)[GeoC<N, G, NW>::OWN], const
       Ml[s * C::NT + t] = 1.0 / (Dl[s * C::NT + t] + tau * cshift);
       rv[s] = bs * y[s];
     }
+    int applies = 0;
     if (!coop_cg<N, G, NW, OPQ>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.krylov_rtol, P.krylov_max, rv,
-                           xv, y))
+                           xv, y, applies))
       status |= 1;
     // v = S x S: left product, exchange, right product -> row block
     __syncthreads();
@@ -1751,6 +1754,7 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) yh[s] = uh[s];
     bool ok = true;
+    int newton_its = 0, applies = 0;
     for (int m = 0; m < P.j_fine; ++m) {
       bool conv = false;
       for (int nit = 0; nit < P.newton_max && !conv; ++nit) {
@@ -1792,8 +1796,9 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
           rv[s] = -g;
           Ml[s * C::NT + t] = 1.0 / (d + tau * cshift);
         }
+        ++newton_its;
         if (!coop_cg<N, G, NW, OPQ>(Xs, T, red, cc, Dl, Ml, Ql, tau, P.nl_krylov_rtol, P.krylov_max,
-                               rv, xv, y))
+                               rv, xv, y, applies))
           ok = false;
         double a[1] = {0.0};
 #pragma unroll
@@ -1819,7 +1824,12 @@ k_fine_newton_group(const WorkItem* __restrict__ items, int n_items,
     slab_stage<N, G, NW, OPQ>(Xs, T, y);
 #pragma unroll
     for (int s = 0; s < C::OWN; ++s) F_out[off + gidx(s)] = y[s];
-    if (t == 0 && mem == 0 && (!ok || !cc.ok)) atomicOr(P.status, (ok ? 0 : 1) | (cc.ok ? 0 : 4));
+    if (t == 0 && mem == 0) {
+      // the item's Newton iterations and Krylov operator applications
+      P.iters[2 * it.slice] = newton_its;
+      P.iters[2 * it.slice + 1] = applies;
+      if (!ok || !cc.ok) atomicOr(P.status, (ok ? 0 : 1) | (cc.ok ? 0 : 4));
+    }
   }
 }
 
@@ -3511,7 +3521,7 @@ __device__ double dd1_direct_step(double u, const InstDev& P, double tau, double
 }
 
 // Fine propagator of one work item with the Neumann-Neumann step: J steps;
-// the iterations of the J steps go to dd_iters[slice].
+// the iterations of the J steps go to iters[2 slice].
 __global__ void __launch_bounds__(128)
 k_fine_dd_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ inst,
              const double* __restrict__ U_in, double* __restrict__ F_out,
@@ -3529,7 +3539,8 @@ k_fine_dd_1d(const WorkItem* __restrict__ items, const InstDev* __restrict__ ins
   for (int s = 0; s < P.j_fine; ++s) u = dd1_step(u, P, P.dt, smem, iters, status);
   if ((int)threadIdx.x < n) F_out[P.off_slices + (int64_t)it.slice * n + threadIdx.x] = u;
   if (threadIdx.x == 0) {
-    P.dd_iters[it.slice] = iters;
+    P.iters[2 * it.slice] = iters;
+    P.iters[2 * it.slice + 1] = 0;
     if (status) atomicOr(P.status, status);
   }
 }
