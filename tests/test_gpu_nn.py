@@ -248,3 +248,43 @@ def test_plain_propagator_judges_the_learned_one_like_the_oracle():
     seq = propagators.fine_sequential(p, u0)
     for j in range(N + 1):
         assert gu.rel(U[j], seq[j]) < 1e-11, j
+
+
+def test_learned_propagator_on_the_plain_one_gains_at_128_squared():
+    # The learned coarse propagator in its library form G = clip(G_plain(u) +
+    # net(u)) on the 128^2 workload (eps = 0.02, dT = 1/32, J = 1563): trained
+    # by the library's kernels on the plain propagator's defect over 24 fine
+    # trajectories (600 steps), its one-step error against F on held-out
+    # trajectories (slices k >= 1) is well below that of the plain coarse step
+    # (measured 5.6x) and of the identity.  Both propagators are applied by
+    # ch_coarse_propagate, as inside Parareal.
+    from paper_2304_14074_amd import chlib, surrogate
+    p = workloads.linear_2d_128()
+    n, N = p.n, p.n_slices
+    tr = surrogate.generate_trajectories(
+        p, np.stack([workloads.u0_uniform(n, 2, 0.05, 40000 + i) for i in range(24)]))
+    te = surrogate.generate_trajectories(
+        p, np.stack([workloads.u0_uniform(n, 2, 0.05, 41000 + i) for i in range(4)]))
+    base = surrogate.plain_coarse_of(p, tr)
+    print("training 600 steps at 128^2", flush=True)
+    _, wb, _ = surrogate.train(tr, steps=600, batch=16, lr=1e-3, base=base, k_min=1)
+    U = te[:, 1:N].reshape(-1).contiguous()
+    target = te[:, 2:N + 1].reshape(-1)
+    M = te.shape[0] * (N - 1)
+    err = {}
+    for kind in ("approx2", "neural"):
+        q = copy.copy(p)
+        q.n_slices, q.T, q.coarse_kind, q.nn_base = M, p.dT * M, kind, 1
+        ctx = chlib.Context([q])
+        if kind == "neural":
+            ctx.ch_nn_bind(wb)
+        G = torch.empty_like(U)
+        ctx.ch_coarse_propagate(U, G)
+        torch.cuda.synchronize()
+        assert ctx.ch_check_status() == [0]
+        err[kind] = float(((G - target) ** 2).mean())
+    e_id = float(((te[:, 1:N] - te[:, 2:N + 1]) ** 2).mean())
+    print(f"one-step MSE: learned {err['neural']:.3e}, plain G {err['approx2']:.3e}, "
+          f"identity {e_id:.3e}", flush=True)
+    assert err["neural"] < err["approx2"] / 2
+    assert err["neural"] < e_id / 4
