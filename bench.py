@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 FINE_LAUNCH_TRAFFIC_BYTES = (12842892.6 * 2.0 + 25674608.1) * 1024
 # the same for the pipelined launch, per iteration (counters over a 4-iteration
 # launch, divided by 4); None until taken for the kernel as it is now
-PIPE_TRAFFIC_BYTES_PER_ITERATION = (52384700.0 * 2.0 + 104752000.0) * 1024 / 4
+PIPE_TRAFFIC_BYTES_PER_ITERATION = (52387019.2 * 2.0 + 104752324.5) * 1024 / 4
 # the same for the fine sweep of the 256-instance batch (all three class launches)
 BATCHED_SWEEP_TRAFFIC_BYTES = ((6156784068.3 + 461061.6 + 105800.1) * 2.0
                                + 12305827472.0 + 839680.0 + 190464.0) * 1024

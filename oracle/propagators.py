@@ -17,13 +17,15 @@ def fine(prob, u: np.ndarray, steps: int | None = None, route: str = "lu",
          dd_iters: list | None = None) -> np.ndarray:
     """F(T_{n+1}, T_n, u): J steps of the fine scheme with tau = dT/J.
     route "lu": the sparse-LU solves; "sine": the same steps solved in the
-    sine basis (faster, equal up to rounding).  With the Neumann-Neumann fine
-    step, ``dd_iters`` receives each step's iteration count."""
+    sine basis (faster, equal up to rounding); "mixed": scheme (2.4) solved in
+    the mixed form of Section 4 (u and v = -eps^2 L u + u_n^2 u - u_n) by a
+    dense solve, a second route to the same step.  With the Neumann-Neumann
+    fine step, ``dd_iters`` receives each step's iteration count."""
     J = prob.j_fine if steps is None else steps
     tau = prob.dt
     v = np.array(u, dtype=np.float64, copy=True)
     fast = route == "sine"
-    if route not in ("lu", "sine"):
+    if route not in ("lu", "sine", "mixed") or (route == "mixed" and prob.fine_kind != "approx2"):
         raise ValueError(route)
     for _ in range(J):
         if prob.fine_kind == "linear":
@@ -35,7 +37,11 @@ def fine(prob, u: np.ndarray, steps: int | None = None, route: str = "lu",
                      f_zero=prob.f_zero)
         elif prob.fine_kind == "approx2":
             # PA-I: scheme (2.4) as the fine step
-            v = schemes.step_approx2(v, tau, prob.eps, prob.f_zero)
+            if route == "mixed":
+                from . import dd
+                v = dd.step_approx2_dd(v, tau, prob.eps, n_sub=1)[0]
+            else:
+                v = schemes.step_approx2(v, tau, prob.eps, prob.f_zero)
         elif prob.fine_kind == "approx2_dd":
             # PA-I with the Neumann-Neumann solve of (2.4) (Section 4, 1D)
             from . import dd
