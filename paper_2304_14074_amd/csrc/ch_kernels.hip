@@ -3370,6 +3370,93 @@ __device__ __forceinline__ double dd1_result(const DD1& d) {
   return v;
 }
 
+// Cross-lane moves of the interface iteration: the neighbours' values (lane
+// q - 1 and q + 1, zero past the ends) and the maximum over the lanes holding
+// interfaces, broadcast to every lane.  With N0 <= 16 the interfaces sit in
+// the first row of 16 lanes and the moves are DPP row shifts (no round trip
+// through the LDS crossbar); else cross-lane shuffles.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <bool DPP>
+__device__ __forceinline__ double dd1_left(double v, int q) {
+  if constexpr (DPP) return dpp_f64<0x111>(v);     // row_shr:1
+  else return __shfl(v, (q + 63) & 63, 64);
+}
+template <bool DPP>
+__device__ __forceinline__ double dd1_right(double v, int q) {
+  if constexpr (DPP) return dpp_f64<0x101>(v);     // row_shl:1
+  else return __shfl(v, (q + 1) & 63, 64);
+}
+// v >= 0 on every lane (zero off the interfaces)
+template <bool DPP>
+__device__ __forceinline__ double dd1_max(double v, int N0) {
+  if constexpr (DPP) {
+    // prefix maxima along row 0 by zero-filled shifts: lane 15 ends with the row's
+    v = fmax(v, dpp_f64<0x111>(v));
+    v = fmax(v, dpp_f64<0x112>(v));
+    v = fmax(v, dpp_f64<0x114>(v));
+    v = fmax(v, dpp_f64<0x118>(v));
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 15),
+                            __builtin_amdgcn_readlane(__double2loint(v), 15));
+  } else {
+    int W = 1;                            // power of two >= N0 (<= 64)
+    while (W < N0) W <<= 1;
+    for (int o = 1; o < W; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return __shfl(v, 0, 64);
+  }
+}
+
+// The Neumann-Neumann iteration on the traces (g, h) of interface q, one lane
+// each (wave 0; the other lanes carry zeros).  Returns the iterations.
+template <bool DPP>
+__device__ __forceinline__ int dd1_iterate(const DD1& d, const InstDev& P, int q, bool on,
+                                           double up, double cp, double& g, double& h,
+                                           const double (&RL)[5][2], const double (&RR)[5][2],
+                                           const double (&NL)[4][2], const double (&NRt)[4][2],
+                                           int& status) {
+  const double th = P.dd_theta;
+  int it = 0;
+  while (d.N0 > 1) {
+    // Dirichlet states next to the interface from the current traces
+    const double gl = dd1_left<DPP>(g, q), hl = dd1_left<DPP>(h, q);
+    const double gr = dd1_right<DPP>(g, q), hr = dd1_right<DPP>(h, q);
+    double Lv[2], Rv[2];
+    for (int s = 0; s < 2; ++s) {
+      Lv[s] = RL[0][s] + gl * RL[1][s] + hl * RL[2][s] + g * RL[3][s] + h * RL[4][s];
+      Rv[s] = RR[0][s] + g * RR[1][s] + h * RR[2][s] + gr * RR[3][s] + hr * RR[4][s];
+    }
+    // residual of the global equations at p_q: the jump of the Neumann traces
+    double ru = up - (g - d.a * (Lv[1] - 2.0 * h + Rv[1]));
+    double rv = d.fvs * up - (d.b * (Lv[0] - 2.0 * g + Rv[0]) - cp * g + h);
+    if (!on) ru = rv = 0.0;
+    const double rul = dd1_left<DPP>(ru, q), rvl = dd1_left<DPP>(rv, q);
+    const double rur = dd1_right<DPP>(ru, q), rvr = dd1_right<DPP>(rv, q);
+    // Neumann corrections of both neighbours at p_q, relaxed by theta
+    double dg = 0.0, dh = 0.0;
+    if (on) {
+      dg = th * (NL[0][0] * rul + NL[1][0] * rvl + NL[2][0] * ru + NL[3][0] * rv +
+                 NRt[0][0] * ru + NRt[1][0] * rv + NRt[2][0] * rur + NRt[3][0] * rvr);
+      dh = th * (NL[0][1] * rul + NL[1][1] * rvl + NL[2][1] * ru + NL[3][1] * rv +
+                 NRt[0][1] * ru + NRt[1][1] * rv + NRt[2][1] * rur + NRt[3][1] * rvr);
+    }
+    g += dg;
+    h += dh;
+    ++it;
+    // max over the interfaces of max(|dg|, |dh|) (both traces meet the
+    // tolerance iff it does; a non-finite change counts as infinite)
+    const double mx =
+        dd1_max<DPP>((dg == dg && dh == dh) ? fmax(fabs(dg), fabs(dh)) : INFINITY, d.N0);
+    if (!(mx < INFINITY)) { status |= 1; break; }
+    if (mx <= P.dd_tol) break;
+    if (it >= P.dd_max) { status |= 1; break; }
+  }
+  return it;
+}
+
 // One Neumann-Neumann step (2.4) of the thread's node value u; iters counts
 // the iterations, status bit 1 flags the cap or a non-finite update.
 __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, int& iters,
@@ -3400,46 +3487,8 @@ __device__ double dd1_step(double u, const InstDev& P, double tau, double* L, in
       for (int k = 0; k < 5; ++k) RL[k][0] = RL[k][1] = RR[k][0] = RR[k][1] = 0.0;
       for (int e = 0; e < 4; ++e) NL[e][0] = NL[e][1] = NRt[e][0] = NRt[e][1] = 0.0;
     }
-    const double th = P.dd_theta;
-    int W = 1;                            // power of two >= N0 (<= 64)
-    while (W < N0) W <<= 1;
-    int it = 0;
-    while (N0 > 1) {
-      // Dirichlet states next to the interface from the current traces
-      const double gl = __shfl(g, (q + 63) & 63, 64), hl = __shfl(h, (q + 63) & 63, 64);
-      const double gr = __shfl(g, (q + 1) & 63, 64), hr = __shfl(h, (q + 1) & 63, 64);
-      double Lv[2], Rv[2];
-      for (int s = 0; s < 2; ++s) {
-        Lv[s] = RL[0][s] + gl * RL[1][s] + hl * RL[2][s] + g * RL[3][s] + h * RL[4][s];
-        Rv[s] = RR[0][s] + g * RR[1][s] + h * RR[2][s] + gr * RR[3][s] + hr * RR[4][s];
-      }
-      // residual of the global equations at p_q: the jump of the Neumann traces
-      double ru = up - (g - d.a * (Lv[1] - 2.0 * h + Rv[1]));
-      double rv = d.fvs * up - (d.b * (Lv[0] - 2.0 * g + Rv[0]) - cp * g + h);
-      if (!on) ru = rv = 0.0;
-      const double rul = __shfl(ru, (q + 63) & 63, 64), rvl = __shfl(rv, (q + 63) & 63, 64);
-      const double rur = __shfl(ru, (q + 1) & 63, 64), rvr = __shfl(rv, (q + 1) & 63, 64);
-      // Neumann corrections of both neighbours at p_q, relaxed by theta
-      double dg = 0.0, dh = 0.0;
-      if (on) {
-        dg = th * (NL[0][0] * rul + NL[1][0] * rvl + NL[2][0] * ru + NL[3][0] * rv +
-                   NRt[0][0] * ru + NRt[1][0] * rv + NRt[2][0] * rur + NRt[3][0] * rvr);
-        dh = th * (NL[0][1] * rul + NL[1][1] * rvl + NL[2][1] * ru + NL[3][1] * rv +
-                   NRt[0][1] * ru + NRt[1][1] * rv + NRt[2][1] * rur + NRt[3][1] * rvr);
-      }
-      g += dg;
-      h += dh;
-      ++it;
-      // max over the interfaces of max(|dg|, |dh|) (both traces meet the
-      // tolerance iff it does; a non-finite change counts as infinite),
-      // reduced over the lanes 0..W-1 holding them and broadcast from lane 0
-      double mx = (dg == dg && dh == dh) ? fmax(fabs(dg), fabs(dh)) : INFINITY;
-      for (int o = 1; o < W; o <<= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-      mx = __shfl(mx, 0, 64);
-      if (!(mx < INFINITY)) { status |= 1; break; }
-      if (mx <= P.dd_tol) break;
-      if (it >= P.dd_max) { status |= 1; break; }
-    }
+    const int it = N0 <= 16 ? dd1_iterate<true>(d, P, q, on, up, cp, g, h, RL, RR, NL, NRt, status)
+                            : dd1_iterate<false>(d, P, q, on, up, cp, g, h, RL, RR, NL, NRt, status);
     iters += it;
     if (on) { d.tg[q] = g; d.th[q] = h; }
     if (tid == 0) { d.tg[0] = d.th[0] = d.tg[N0] = d.th[N0] = 0.0; }
