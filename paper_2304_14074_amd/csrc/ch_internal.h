@@ -178,7 +178,7 @@ struct NNLayer { int c_in, c_out, k, stride, act, cat; };
 constexpr int NN_LAYERS = 12;
 extern const NNLayer kNNLayers[NN_LAYERS];
 struct NNPlan {   // float offsets inside an NN workspace
-  size_t x0, act[NN_LAYERS], grad[NN_LAYERS], tmp, part, floats;
+  size_t x0, act[NN_LAYERS], grad[NN_LAYERS], tmp, part, wpart, floats;
 };
 NNPlan nn_plan(int batch, int n);
 int64_t nn_param_count();

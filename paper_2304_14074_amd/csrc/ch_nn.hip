@@ -63,7 +63,18 @@ static int in_size(int l, int n) {  // spatial size of the (concatenated) input 
   return kNNLayers[l].cat >= 0 ? 2 * s : s;
 }
 
-// Workspace layout (floats): x0 | for each layer: act | for each layer: grad | tmp | partials
+// Pixel chunks of the weight-gradient GEMM over tot output pixels: at most
+// 64, of at least 1024 pixels each (a multiple of 4).
+static int wgrad_chunks(int64_t tot) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (tot + 1023) / 1024));
+}
+static int64_t wgrad_chunk_len(int64_t tot) {
+  const int nch = wgrad_chunks(tot);
+  return ((tot + nch - 1) / nch + 3) / 4 * 4;
+}
+
+// Workspace layout (floats): x0 | for each layer: act | for each layer: grad | tmp | loss
+// partials | weight-gradient partials
 NNPlan nn_plan(int batch, int n) {
   NNPlan p;
   size_t o = 0;
@@ -82,6 +93,13 @@ NNPlan nn_plan(int batch, int n) {
   }
   p.tmp = take(maxin);
   p.part = take(4096);
+  size_t wp = 0;
+  for (int l = 0; l < NN_LAYERS; ++l) {
+    const NNLayer& L = kNNLayers[l];
+    const int64_t tot = (int64_t)batch * out_size(l, n) * out_size(l, n);
+    wp = std::max(wp, (size_t)wgrad_chunks(tot) * L.c_out * (L.c_in * L.k * L.k + 1));
+  }
+  p.wpart = take(wp);
   p.floats = o;
   return p;
 }
@@ -251,6 +269,76 @@ k_conv_bwd_weight(const float* __restrict__ G, int Co, int Ho, const float* __re
   }
   if (ci == 0 && threadIdx.x == 0)
     gw[(int64_t)Co * Ci * kk + co] = (red[9][0] + red[9][1]) + (red[9][2] + red[9][3]);
+}
+
+// Weight gradient as a GEMM on the matrix cores (FP32 MFMA 16x16x4):
+// dW[co][j] = sum over the output pixels q of G[co][q] X[j][q], with
+// j = ci k^2 + tap and X the layer's input gathered at tap (the columns of
+// an im2col matrix); column j = Ci k^2 (X = 1) gives the bias gradient.
+// Block (c, ct, jt): pixels of chunk c, output channels 16 ct.., columns
+// 64 jt.. (16 per wave); it writes its partial sums to part[c][co][j], which
+// k_wgrad_sum adds in chunk order (fixed order: reproducible bits).
+// Lane layout of the 16x16x4 product: A (16 x 4) row = lane & 15, k = lane
+// >> 4; B (4 x 16) k = lane >> 4, column = lane & 15; D row 4 (lane >> 4) +
+// r (r < 4), column lane & 15.
+typedef float nnf4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256)
+k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float* __restrict__ A,
+                       int Ca, const float* __restrict__ B, int Cb, int H, int k, int stride,
+                       int64_t tot, int64_t chunk, float* __restrict__ part) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = l & 15, g = l >> 4;
+  const int Ci = Ca + Cb, kk = k * k, J = Ci * kk, pad = k / 2;
+  const int co0 = blockIdx.y * 16, j0 = blockIdx.z * 64 + w * 16;
+  // this lane's A row (output channel) and B column (input channel, tap)
+  const int co = co0 + i, j = j0 + i;
+  const bool co_ok = co < Co, j_w = j < J, j_b = j == J;
+  const int ci = j_w ? j / kk : 0, tap = j_w ? j % kk : 0, dy = tap / k, dx = tap % k;
+  const int64_t q0 = (int64_t)blockIdx.x * chunk, q1 = min(q0 + chunk, tot);
+  // pixel q = q0 + g + 4 s of this lane, walked as (b, oy, ox)
+  int64_t q = q0 + g;
+  const int64_t HH = (int64_t)Ho * Ho;
+  int b = (int)(q / HH);
+  int rem = (int)(q % HH);
+  int oy = rem / Ho, ox = rem % Ho;
+  nnf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t p = q0; p < q1; p += 4) {
+    const bool in = q < q1;
+    const float a = (in && co_ok) ? G[((int64_t)b * Co + co) * HH + (int64_t)oy * Ho + ox] : 0.0f;
+    float x = 0.0f;
+    if (in) {
+      if (j_w) x = in_at(A, Ca, B, Cb, H, b, ci, oy * stride + dy - pad, ox * stride + dx - pad);
+      else if (j_b) x = 1.0f;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x, acc, 0, 0, 0);
+    q += 4;
+    ox += 4;
+    if (ox >= Ho) {   // Ho >= 4: at most one wrap per step
+      ox -= Ho;
+      if (++oy == Ho) { oy = 0; ++b; }
+    }
+  }
+  const int Jp = J + 1;
+  if (j < Jp)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cr = co0 + 4 * g + r;
+      if (cr < Co) part[((int64_t)blockIdx.x * Co + cr) * Jp + j] = acc[r];
+    }
+}
+
+// gw[co][j] = sum over the chunks in order of part[c][co][j] (j = J: the bias,
+// stored after all weights).
+__global__ void k_wgrad_sum(const float* __restrict__ part, int nch, int Co, int J,
+                            float* __restrict__ gw) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int Jp = J + 1;
+  if (idx >= (int64_t)Co * Jp) return;
+  const int co = (int)(idx / Jp), j = (int)(idx % Jp);
+  float s = 0.0f;
+  for (int c = 0; c < nch; ++c) s += part[((int64_t)c * Co + co) * Jp + j];
+  if (j < J) gw[(int64_t)co * J + j] = s;
+  else gw[(int64_t)Co * J + co] = s;
 }
 
 __global__ void k_to_f32(const double* __restrict__ u, float* __restrict__ x, int64_t count,
@@ -564,8 +652,15 @@ hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, 
     }
     const uint16_t* wl = w + nn_param_offset(l);
     float* gw = grad + nn_param_offset(l);
-    hipLaunchKernelGGL(k_conv_bwd_weight, dim3(L.c_in, L.c_out), dim3(256), 0, s, G, L.c_out, Ho, A,
-                       Ca, B, Cb, H, L.k, L.stride, batch, gw);
+    {
+      const int64_t tot = (int64_t)batch * Ho * Ho;
+      const int nch = wgrad_chunks(tot), J = L.c_in * L.k * L.k;
+      hipLaunchKernelGGL(k_conv_bwd_weight_mfma, dim3(nch, (L.c_out + 15) / 16, (J + 1 + 63) / 64),
+                         dim3(256), 0, s, G, L.c_out, Ho, A, Ca, B, Cb, H, L.k, L.stride, tot,
+                         wgrad_chunk_len(tot), ws + p.wpart);
+      hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks((int64_t)L.c_out * (J + 1))), dim3(256), 0, s,
+                         ws + p.wpart, nch, L.c_out, J, gw);
+    }
     if (l == 0) continue;
     const int CIB = (L.c_in % 16 == 0) ? 16 : 1;
     const size_t lds = (size_t)L.c_out * CIB * L.k * L.k * sizeof(float);
