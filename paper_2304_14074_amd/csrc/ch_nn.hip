@@ -160,6 +160,66 @@ k_conv_fwd(const float* __restrict__ A, int Ca, const float* __restrict__ B, int
   }
 }
 
+// Forward convolution on the matrix cores (FP32 MFMA 16x16x4), for c_out a
+// multiple of 16 (at most 64): Y[co][p] = bias[co] + sum_j W[co][j] X[j][p]
+// with X the im2col columns of the input (j = ci k^2 + tap).  A wave takes 16
+// output pixels (A operand: 16 pixels x 4 columns j, gathered from the
+// input) against every output channel (B operands: 4 columns x 16 channels
+// of the BF16 weights, one per group of 16 channels); a block of four waves
+// 64 consecutive pixels of one sample.  Lane layout as in the weight
+// gradient: A row = lane & 15, k = lane >> 4; B k = lane >> 4, column = lane
+// & 15; D row 4 (lane >> 4) + r, column lane & 15.
+typedef float nnf4 __attribute__((ext_vector_type(4)));
+template <int NG>
+__global__ void __launch_bounds__(256)
+k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B, int Cb, int H,
+                const uint16_t* __restrict__ w, float* __restrict__ Y, int Ho, int k, int stride,
+                int act, const int32_t* __restrict__ gate) {
+  if (gate && !*gate) return;
+  constexpr int Co = 16 * NG;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, b = blockIdx.y;
+  const int i = l & 15, g = l >> 4;
+  const int Ci = Ca + Cb, kk = k * k, J = Ci * kk, pad = k / 2;
+  const int HH = Ho * Ho;
+  const int p0 = blockIdx.x * 64 + wv * 16;
+  const int pa = p0 + i;                       // this lane's A-operand pixel
+  const bool pin = pa < HH;
+  const int oy = pin ? pa / Ho : 0, ox = pin ? pa % Ho : 0;
+  const int iy = oy * stride - pad, ix = ox * stride - pad;
+  nnf4 acc[NG];
+#pragma unroll
+  for (int c = 0; c < NG; ++c) acc[c] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
+  // column j = 4 s + g of this lane, walked as (ci, tap), tap = 3 dy + dx
+  int ci = 0, tap = g;
+  while (tap >= kk) { tap -= kk; ++ci; }
+  for (int j = g; j - g < J; j += 4) {
+    const bool jin = j < J;
+    const int dy = k == 3 ? (tap >= 6 ? 2 : (tap >= 3 ? 1 : 0)) : 0, dx = tap - k * dy;
+    const float x = (pin && jin) ? in_at(A, Ca, B, Cb, H, b, ci, iy + dy, ix + dx) : 0.0f;
+#pragma unroll
+    for (int c = 0; c < NG; ++c) {
+      const float wt = jin ? bf2f(w[(int64_t)(16 * c + i) * J + j]) : 0.0f;
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wt, acc[c], 0, 0, 0);
+    }
+    tap += 4;
+    while (tap >= kk) { tap -= kk; ++ci; }
+  }
+  const uint16_t* bias = w + (int64_t)Co * J;
+#pragma unroll
+  for (int c = 0; c < NG; ++c) {
+    const int co = 16 * c + i;
+    const float bv = bf2f(bias[co]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pr = p0 + 4 * g + r;
+      if (pr >= HH) continue;
+      float v = acc[c][r] + bv;
+      if (act) v = v > 0.0f ? v : kSlope * v;
+      Y[((int64_t)b * Co + co) * HH + pr] = v;
+    }
+  }
+}
+
 // G <- G * act'(y) in place (y the layer output; LeakyReLU is monotone, so
 // the sign of y is the sign of the pre-activation).
 __global__ void k_act_bwd(float* __restrict__ G, const float* __restrict__ Y, int64_t count) {
@@ -281,7 +341,6 @@ k_conv_bwd_weight(const float* __restrict__ G, int Co, int Ho, const float* __re
 // Lane layout of the 16x16x4 product: A (16 x 4) row = lane & 15, k = lane
 // >> 4; B (4 x 16) k = lane >> 4, column = lane & 15; D row 4 (lane >> 4) +
 // r (r < 4), column lane & 15.
-typedef float nnf4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256)
 k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float* __restrict__ A,
                        int Ca, const float* __restrict__ B, int Cb, int H, int k, int stride,
@@ -564,7 +623,19 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     }
     const int H = in_size(l, n), Ho = out_size(l, n);
     const uint16_t* wl = w + nn_param_offset(l);
-    if (L.c_out >= 16) {
+    if (L.c_out % 16 == 0 && L.c_out <= 64) {
+      const dim3 grid((unsigned)((int64_t)Ho * Ho + 63) / 64, batch);
+      switch (L.c_out / 16) {
+        case 1: hipLaunchKernelGGL(k_conv_fwd_mfma<1>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
+                                   ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
+        case 2: hipLaunchKernelGGL(k_conv_fwd_mfma<2>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
+                                   ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
+        case 3: hipLaunchKernelGGL(k_conv_fwd_mfma<3>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
+                                   ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
+        default: hipLaunchKernelGGL(k_conv_fwd_mfma<4>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
+                                    ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
+      }
+    } else if (L.c_out >= 16) {
       const size_t lds = (size_t)16 * L.c_in * L.k * L.k * sizeof(float);
       hipLaunchKernelGGL(k_conv_fwd<16>, dim3(blocks((int64_t)Ho * Ho), L.c_out / 16, batch),
                          dim3(256), lds, s, A, Ca, B, Cb, H, wl, ws + p.act[l], L.c_out, Ho, L.k,
