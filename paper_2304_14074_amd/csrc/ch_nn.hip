@@ -70,7 +70,7 @@ static int wgrad_chunks(int64_t tot) {
 }
 static int64_t wgrad_chunk_len(int64_t tot) {
   const int nch = wgrad_chunks(tot);
-  return ((tot + nch - 1) / nch + 3) / 4 * 4;
+  return ((tot + nch - 1) / nch + 15) / 16 * 16;
 }
 
 // Workspace layout (floats): x0 | for each layer: act | for each layer: grad | tmp | loss
@@ -335,41 +335,75 @@ k_conv_bwd_weight(const float* __restrict__ G, int Co, int Ho, const float* __re
 // dW[co][j] = sum over the output pixels q of G[co][q] X[j][q], with
 // j = ci k^2 + tap and X the layer's input gathered at tap (the columns of
 // an im2col matrix); column j = Ci k^2 (X = 1) gives the bias gradient.
-// Block (c, ct, jt): pixels of chunk c, output channels 16 ct.., columns
-// 64 jt.. (16 per wave); it writes its partial sums to part[c][co][j], which
-// k_wgrad_sum adds in chunk order (fixed order: reproducible bits).
-// Lane layout of the 16x16x4 product: A (16 x 4) row = lane & 15, k = lane
-// >> 4; B (4 x 16) k = lane >> 4, column = lane & 15; D row 4 (lane >> 4) +
-// r (r < 4), column lane & 15.
+// Block (c, jt): the pixels of chunk c, all output channels (16 NG), columns
+// 64 jt..; each wave takes a quarter of the chunk's pixels and holds the
+// whole 16 NG x 64 tile (NG x 4 products per step share the operands
+// loaded for them); the four waves' sums are added in wave order in LDS and
+// written to part[c][co][j], which k_wgrad_sum adds in chunk order (fixed
+// order: reproducible bits).  Lane layout of the 16x16x4 product: A (16 x 4)
+// row = lane & 15, k = lane >> 4; B (4 x 16) k = lane >> 4, column =
+// lane & 15; D row 4 (lane >> 4) + r (r < 4), column lane & 15.
+template <int NG>
 __global__ void __launch_bounds__(256)
 k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float* __restrict__ A,
                        int Ca, const float* __restrict__ B, int Cb, int H, int k, int stride,
                        int64_t tot, int64_t chunk, float* __restrict__ part) {
+  __shared__ float red[64 * NG * 16];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = l & 15, g = l >> 4;
   const int Ci = Ca + Cb, kk = k * k, J = Ci * kk, pad = k / 2;
-  const int co0 = blockIdx.y * 16, j0 = blockIdx.z * 64 + w * 16;
-  // this lane's A row (output channel) and B column (input channel, tap)
-  const int co = co0 + i, j = j0 + i;
-  const bool co_ok = co < Co, j_w = j < J, j_b = j == J;
-  const int ci = j_w ? j / kk : 0, tap = j_w ? j % kk : 0, dy = tap / k, dx = tap % k;
-  const int64_t q0 = (int64_t)blockIdx.x * chunk, q1 = min(q0 + chunk, tot);
-  // pixel q = q0 + g + 4 s of this lane, walked as (b, oy, ox)
+  const int j0 = blockIdx.y * 64;
+  // this lane's B columns j0 + 16 t + i: (input channel, tap), or the bias
+  int cit[4], dyt[4], dxt[4];
+  bool jw[4], jb[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = j0 + 16 * t + i;
+    jw[t] = j < J;
+    jb[t] = j == J;
+    const int tp = jw[t] ? j % kk : 0;
+    cit[t] = jw[t] ? j / kk : 0;
+    dyt[t] = tp / k;
+    dxt[t] = tp % k;
+  }
+  // this wave's pixels: a quarter of the chunk (chunk is a multiple of 16)
+  const int64_t sub = chunk / 4;
+  const int64_t q0 = (int64_t)blockIdx.x * chunk + w * sub;
+  const int64_t q1 = min(q0 + sub, tot);
   int64_t q = q0 + g;
   const int64_t HH = (int64_t)Ho * Ho;
   int b = (int)(q / HH);
   int rem = (int)(q % HH);
   int oy = rem / Ho, ox = rem % Ho;
-  nnf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  nnf4 acc[NG][4];
+#pragma unroll
+  for (int c = 0; c < NG; ++c)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[c][t] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int64_t p = q0; p < q1; p += 4) {
     const bool in = q < q1;
-    const float a = (in && co_ok) ? G[((int64_t)b * Co + co) * HH + (int64_t)oy * Ho + ox] : 0.0f;
-    float x = 0.0f;
-    if (in) {
-      if (j_w) x = in_at(A, Ca, B, Cb, H, b, ci, oy * stride + dy - pad, ox * stride + dx - pad);
-      else if (j_b) x = 1.0f;
+    float a[NG], x[4];
+#pragma unroll
+    for (int c = 0; c < NG; ++c) {
+      const int co = 16 * c + i;
+      a[c] = (in && co < Co) ? G[((int64_t)b * Co + co) * HH + (int64_t)oy * Ho + ox] : 0.0f;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x, acc, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      x[t] = 0.0f;
+      if (in) {
+        if (jw[t])
+          x[t] = in_at(A, Ca, B, Cb, H, b, cit[t], oy * stride + dyt[t] - pad,
+                       ox * stride + dxt[t] - pad);
+        else if (jb[t])
+          x[t] = 1.0f;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NG; ++c)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], x[t], acc[c][t], 0, 0, 0);
     q += 4;
     ox += 4;
     if (ox >= Ho) {   // Ho >= 4: at most one wrap per step
@@ -377,12 +411,33 @@ k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float*
       if (++oy == Ho) { oy = 0; ++b; }
     }
   }
-  const int Jp = J + 1;
-  if (j < Jp)
+  // the four waves' sums, added in wave order
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int cr = co0 + 4 * g + r;
-      if (cr < Co) part[((int64_t)blockIdx.x * Co + cr) * Jp + j] = acc[r];
+      for (int c = 0; c < NG; ++c)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float* d = &red[((c * 4 + t) * 4 + r) * 64 + l];
+            *d = ww == 0 ? acc[c][t][r] : *d + acc[c][t][r];
+          }
+    __syncthreads();
+  }
+  if (w != 0) return;
+  const int Jp = J + 1;
+#pragma unroll
+  for (int c = 0; c < NG; ++c)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = j0 + 16 * t + i;
+      if (j >= Jp) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int cr = 16 * c + 4 * g + r;
+        if (cr < Co) part[((int64_t)blockIdx.x * Co + cr) * Jp + j] = red[((c * 4 + t) * 4 + r) * 64 + l];
+      }
     }
 }
 
@@ -726,9 +781,18 @@ hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, 
     {
       const int64_t tot = (int64_t)batch * Ho * Ho;
       const int nch = wgrad_chunks(tot), J = L.c_in * L.k * L.k;
-      hipLaunchKernelGGL(k_conv_bwd_weight_mfma, dim3(nch, (L.c_out + 15) / 16, (J + 1 + 63) / 64),
-                         dim3(256), 0, s, G, L.c_out, Ho, A, Ca, B, Cb, H, L.k, L.stride, tot,
-                         wgrad_chunk_len(tot), ws + p.wpart);
+      const dim3 grid(nch, (J + 1 + 63) / 64);
+      const int64_t len = wgrad_chunk_len(tot);
+      switch ((L.c_out + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<1>, grid, dim3(256), 0, s, G, L.c_out, Ho,
+                                   A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
+        case 2: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<2>, grid, dim3(256), 0, s, G, L.c_out, Ho,
+                                   A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
+        case 3: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<3>, grid, dim3(256), 0, s, G, L.c_out, Ho,
+                                   A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
+        default: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<4>, grid, dim3(256), 0, s, G, L.c_out,
+                                    Ho, A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
+      }
       hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks((int64_t)L.c_out * (J + 1))), dim3(256), 0, s,
                          ws + p.wpart, nch, L.c_out, J, gw);
     }
