@@ -114,108 +114,106 @@ __device__ __forceinline__ uint16_t f2bf_rne(float f) {
   return (uint16_t)(r >> 16);
 }
 
-// Input element (b, c, y, x) of a layer whose input is either A alone or the
-// concatenation [A (Ca channels, full size), up2(B) (Cb channels, half size)].
-__device__ __forceinline__ float in_at(const float* A, int Ca, const float* B, int Cb, int H, int b,
-                                       int c, int y, int x) {
-  if (y < 0 || y >= H || x < 0 || x >= H) return 0.0f;
-  if (c < Ca) return A[(((int64_t)b * Ca + c) * H + y) * H + x];
-  const int Hh = H >> 1;
-  return B[(((int64_t)b * Cb + (c - Ca)) * Hh + (y >> 1)) * Hh + (x >> 1)];
-}
-
-// Forward convolution: one thread per output pixel, COB output channels per
-// block, the block's weights staged in LDS as FP32 (from BF16).
-template <int COB>
-__global__ void __launch_bounds__(256)
-k_conv_fwd(const float* __restrict__ A, int Ca, const float* __restrict__ B, int Cb, int H,
-           const uint16_t* __restrict__ w, float* __restrict__ Y, int Co, int Ho, int k, int stride,
-           int act, const int32_t* __restrict__ gate) {
-  extern __shared__ float wl[];
-  if (gate && !*gate) return;
-  const int Ci = Ca + Cb, kk = k * k, co0 = blockIdx.y * COB, b = blockIdx.z;
-  const int nw = COB * Ci * kk;
-  for (int i = threadIdx.x; i < nw; i += 256) wl[i] = bf2f(w[(int64_t)co0 * Ci * kk + i]);
-  const uint16_t* bias = w + (int64_t)Co * Ci * kk;
-  __syncthreads();
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= Ho * Ho) return;
-  const int oy = p / Ho, ox = p % Ho, pad = k / 2;
-  float acc[COB];
-#pragma unroll
-  for (int c = 0; c < COB; ++c) acc[c] = bf2f(bias[co0 + c]);
-  for (int ci = 0; ci < Ci; ++ci)
-    for (int dy = 0; dy < k; ++dy)
-      for (int dx = 0; dx < k; ++dx) {
-        const float xv = in_at(A, Ca, B, Cb, H, b, ci, oy * stride + dy - pad, ox * stride + dx - pad);
-        const float* wr = wl + (ci * k + dy) * k + dx;
-#pragma unroll
-        for (int c = 0; c < COB; ++c) acc[c] = fmaf(wr[c * Ci * kk], xv, acc[c]);
-      }
-#pragma unroll
-  for (int c = 0; c < COB; ++c) {
-    float v = acc[c];
-    if (act) v = v > 0.0f ? v : kSlope * v;
-    Y[(((int64_t)b * Co + co0 + c) * Ho + oy) * Ho + ox] = v;
-  }
-}
-
-// Forward convolution on the matrix cores (FP32 MFMA 16x16x4), for c_out a
-// multiple of 16 (at most 64): Y[co][p] = bias[co] + sum_j W[co][j] X[j][p]
-// with X the im2col columns of the input (j = ci k^2 + tap).  A wave takes 16
-// output pixels (A operand: 16 pixels x 4 columns j, gathered from the
-// input) against every output channel (B operands: 4 columns x 16 channels
-// of the BF16 weights, one per group of 16 channels); a block of four waves
-// 64 consecutive pixels of one sample.  Lane layout as in the weight
-// gradient: A row = lane & 15, k = lane >> 4; B k = lane >> 4, column = lane
-// & 15; D row 4 (lane >> 4) + r, column lane & 15.
+// Convolutions on the matrix cores (FP32 MFMA 16x16x4, FP32 accumulation):
+// implicit GEMMs whose contraction runs over pairs (tap, 16 channels).  A
+// block takes 16 pixels of one sample and every output column (16 NG); its
+// four waves deal the pairs among themselves in turn, each keeps its own
+// sums, and the waves' sums are added in wave order in LDS (fixed order:
+// reproducible bits).  Per pair a lane issues its four gathers and its
+// 4 NG weight loads together, then the 4 NG products.  Lane layout of the
+// 16x16x4 product: A (16 x 4) row = lane & 15, k = lane >> 4; B (4 x 16)
+// k = lane >> 4, column = lane & 15; D row 4 (lane >> 4) + r (r < 4),
+// column lane & 15.
 typedef float nnf4 __attribute__((ext_vector_type(4)));
+
+// The waves' sums of a block: waves 1-3 park theirs in red, wave 0 adds
+// them to its own in wave order.  Returns false on waves 1-3.
+template <int NG>
+__device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[NG], float* red, int wv, int l) {
+  if (wv > 0)
+#pragma unroll
+    for (int c = 0; c < NG; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(((wv - 1) * NG + c) * 4 + r) * 64 + l] = acc[c][r];
+  __syncthreads();
+  if (wv > 0) return false;
+#pragma unroll
+  for (int c = 0; c < NG; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ww = 0; ww < 3; ++ww) acc[c][r] += red[((ww * NG + c) * 4 + r) * 64 + l];
+  return true;
+}
+
+// Forward: Y[co][p] = act(bias[co] + sum over (ci, tap) of W[co][ci][tap]
+// X[ci][p + tap]), the input X either A alone or the concatenation [A (Ca
+// channels), up2(B) (Cb channels)] with Ca a multiple of 16 when Cb > 0.
+// A operand: 16 pixels x 4 channels gathered at the tap; B operands: 4
+// channels x 16 output channels of the BF16 weights; c_out <= 16 NG.
 template <int NG>
 __global__ void __launch_bounds__(256)
 k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B, int Cb, int H,
-                const uint16_t* __restrict__ w, float* __restrict__ Y, int Ho, int k, int stride,
-                int act, const int32_t* __restrict__ gate) {
+                const uint16_t* __restrict__ w, float* __restrict__ Y, int Co, int Ho, int k,
+                int stride, int act, const int32_t* __restrict__ gate) {
+  __shared__ float red[3 * NG * 4 * 64];
   if (gate && !*gate) return;
-  constexpr int Co = 16 * NG;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, b = blockIdx.y;
   const int i = l & 15, g = l >> 4;
-  const int Ci = Ca + Cb, kk = k * k, J = Ci * kk, pad = k / 2;
-  const int HH = Ho * Ho;
-  const int p0 = blockIdx.x * 64 + wv * 16;
-  const int pa = p0 + i;                       // this lane's A-operand pixel
+  const int Ci = Ca + Cb, kk = k * k, pad = k / 2, nc = (Ci + 15) >> 4, items = kk * nc;
+  const int HH = Ho * Ho, Hh = H >> 1;
+  const int pa = blockIdx.x * 16 + i;          // this lane's A-operand pixel
   const bool pin = pa < HH;
   const int oy = pin ? pa / Ho : 0, ox = pin ? pa % Ho : 0;
-  const int iy = oy * stride - pad, ix = ox * stride - pad;
   nnf4 acc[NG];
 #pragma unroll
   for (int c = 0; c < NG; ++c) acc[c] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
-  // column j = 4 s + g of this lane, walked as (ci, tap), tap = 3 dy + dx
-  int ci = 0, tap = g;
-  while (tap >= kk) { tap -= kk; ++ci; }
-  for (int j = g; j - g < J; j += 4) {
-    const bool jin = j < J;
-    const int dy = k == 3 ? (tap >= 6 ? 2 : (tap >= 3 ? 1 : 0)) : 0, dx = tap - k * dy;
-    const float x = (pin && jin) ? in_at(A, Ca, B, Cb, H, b, ci, iy + dy, ix + dx) : 0.0f;
-#pragma unroll
-    for (int c = 0; c < NG; ++c) {
-      const float wt = jin ? bf2f(w[(int64_t)(16 * c + i) * J + j]) : 0.0f;
-      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, wt, acc[c], 0, 0, 0);
+  for (int it = wv; it < items; it += 4) {
+    const int tap = it / nc, c16 = it - tap * nc;
+    const int dy = tap / k, dx = tap - dy * k;
+    const int yy = oy * stride + dy - pad, xx = ox * stride + dx - pad;
+    const bool v = pin && yy >= 0 && yy < H && xx >= 0 && xx < H;
+    const int ci0 = 16 * c16 + g;
+    const float* src;
+    int plane;
+    if (16 * c16 < Ca) {
+      src = A + ((int64_t)b * Ca + ci0) * H * H + (v ? yy * H + xx : 0);
+      plane = H * H;
+    } else {
+      src = B + ((int64_t)b * Cb + ci0 - Ca) * Hh * Hh + (v ? (yy >> 1) * Hh + (xx >> 1) : 0);
+      plane = Hh * Hh;
     }
-    tap += 4;
-    while (tap >= kk) { tap -= kk; ++ci; }
+    float x[4], wt[4][NG];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool cin = ci0 + 4 * u < Ci;
+      x[u] = (v && cin) ? src[4 * u * plane] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < NG; ++c) {
+        const int co = 16 * c + i;
+        wt[u][c] = (cin && co < Co) ? bf2f(w[((int64_t)co * Ci + ci0 + 4 * u) * kk + tap]) : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < NG; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u], wt[u][c], acc[c], 0, 0, 0);
   }
-  const uint16_t* bias = w + (int64_t)Co * J;
+  if (!ks_reduce<NG>(acc, red, wv, l)) return;
+  const uint16_t* bias = w + (int64_t)Co * Ci * kk;
 #pragma unroll
   for (int c = 0; c < NG; ++c) {
     const int co = 16 * c + i;
+    if (co >= Co) continue;
     const float bv = bf2f(bias[co]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int pr = p0 + 4 * g + r;
+      const int pr = blockIdx.x * 16 + 4 * g + r;
       if (pr >= HH) continue;
-      float v = acc[c][r] + bv;
-      if (act) v = v > 0.0f ? v : kSlope * v;
-      Y[((int64_t)b * Co + co) * HH + pr] = v;
+      float y = acc[c][r] + bv;
+      if (act) y = y > 0.0f ? y : kSlope * y;
+      Y[((int64_t)b * Co + co) * HH + pr] = y;
     }
   }
 }
@@ -227,54 +225,67 @@ __global__ void k_act_bwd(float* __restrict__ G, const float* __restrict__ Y, in
   if (i < count) G[i] = Y[i] > 0.0f ? G[i] : kSlope * G[i];
 }
 
-// Gradient w.r.t. the (concatenated) input: one thread per input pixel, CIB
-// input channels per block.  dIn[ci][y][x] = sum_co sum_taps W[co][ci][tap]
-// G[co][oy][ox] with oy*stride + dy - pad = y.  Channels < Ca go to dA
-// (added when accA), the rest to dBf at full resolution (reduced later).
-template <int CIB>
+// Gradient w.r.t. the (concatenated) input: dIn[ci][p] = sum over the pairs
+// (co, tap) of W[co][ci][tap] G[co][q], q the output pixel that the tap joins
+// to input pixel p (a zero where there is none: the border, or a tap that the
+// stride skips; stride is 1 or 2).  A operand: 16 input pixels x 4 output
+// channels gathered from G; B operands: 4 output channels x 16 input
+// channels of the BF16 weights; c_in = Ca + Cb = 16 NG.  Channels < Ca go to
+// dA (added when accA), the rest to dBf at full resolution (reduced later).
+template <int NG>
 __global__ void __launch_bounds__(256)
-k_conv_bwd_data(const float* __restrict__ G, int Co, int Ho, const uint16_t* __restrict__ w,
-                int Ca, int Cb, int H, int k, int stride, float* __restrict__ dA, int accA,
-                float* __restrict__ dBf) {
-  extern __shared__ float wl[];
-  const int Ci = Ca + Cb, kk = k * k, ci0 = blockIdx.y * CIB, b = blockIdx.z;
-  for (int i = threadIdx.x; i < Co * CIB * kk; i += 256) {
-    const int co = i / (CIB * kk), rem = i % (CIB * kk), c = rem / kk, t = rem % kk;
-    wl[i] = bf2f(w[((int64_t)co * Ci + ci0 + c) * kk + t]);
-  }
-  __syncthreads();
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= H * H) return;
-  const int y = p / H, x = p % H, pad = k / 2;
-  float acc[CIB];
+k_conv_bwd_data_mfma(const float* __restrict__ G, int Co, int Ho, const uint16_t* __restrict__ w,
+                     int Ca, int Cb, int H, int k, int stride, float* __restrict__ dA, int accA,
+                     float* __restrict__ dBf) {
+  constexpr int Ci = 16 * NG;
+  __shared__ float red[3 * NG * 4 * 64];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, b = blockIdx.y;
+  const int i = l & 15, g = l >> 4;
+  const int kk = k * k, pad = k / 2, sh = stride == 2 ? 1 : 0, nc = (Co + 15) >> 4;
+  const int items = kk * nc, HH = H * H, HoHo = Ho * Ho;
+  const int pa = blockIdx.x * 16 + i;          // this lane's A-operand pixel
+  const bool pin = pa < HH;
+  const int y = pin ? pa / H : 0, x = pin ? pa % H : 0;
+  nnf4 acc[NG];
 #pragma unroll
-  for (int c = 0; c < CIB; ++c) acc[c] = 0.0f;
-  for (int dy = 0; dy < k; ++dy) {
-    const int ty = y + pad - dy;
-    if (ty < 0 || ty % stride) continue;
-    const int oy = ty / stride;
-    if (oy >= Ho) continue;
-    for (int dx = 0; dx < k; ++dx) {
-      const int tx = x + pad - dx;
-      if (tx < 0 || tx % stride) continue;
-      const int ox = tx / stride;
-      if (ox >= Ho) continue;
-      for (int co = 0; co < Co; ++co) {
-        const float g = G[(((int64_t)b * Co + co) * Ho + oy) * Ho + ox];
-        const float* wr = wl + (co * CIB) * kk + dy * k + dx;
+  for (int c = 0; c < NG; ++c) acc[c] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int it = wv; it < items; it += 4) {
+    const int tap = it / nc, c16 = it - tap * nc;
+    const int dy = tap / k, dx = tap - dy * k;
+    const int ty = y + pad - dy, tx = x + pad - dx;
+    const int oy = ty >> sh, ox = tx >> sh;
+    const bool v = pin && ty >= 0 && tx >= 0 && !(ty & sh) && !(tx & sh) && oy < Ho && ox < Ho;
+    const int co0 = 16 * c16 + g;
+    const float* src = G + ((int64_t)b * Co + co0) * HoHo + (v ? oy * Ho + ox : 0);
+    float gv[4], wt[4][NG];
 #pragma unroll
-        for (int c = 0; c < CIB; ++c) acc[c] = fmaf(wr[c * kk], g, acc[c]);
-      }
+    for (int u = 0; u < 4; ++u) {
+      const bool cin = co0 + 4 * u < Co;
+      gv[u] = (v && cin) ? src[4 * u * HoHo] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < NG; ++c)
+        wt[u][c] = cin ? bf2f(w[((int64_t)(co0 + 4 * u) * Ci + 16 * c + i) * kk + tap]) : 0.0f;
     }
-  }
 #pragma unroll
-  for (int c = 0; c < CIB; ++c) {
-    const int ci = ci0 + c;
-    if (ci < Ca) {
-      float* d = dA + (((int64_t)b * Ca + ci) * H + y) * H + x;
-      *d = accA ? *d + acc[c] : acc[c];
-    } else {
-      dBf[(((int64_t)b * Cb + (ci - Ca)) * H + y) * H + x] = acc[c];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < NG; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[u], wt[u][c], acc[c], 0, 0, 0);
+  }
+  if (!ks_reduce<NG>(acc, red, wv, l)) return;
+#pragma unroll
+  for (int c = 0; c < NG; ++c) {
+    const int ci = 16 * c + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pr = blockIdx.x * 16 + 4 * g + r;
+      if (pr >= HH) continue;
+      if (ci < Ca) {
+        float* d = dA + ((int64_t)b * Ca + ci) * HH + pr;
+        *d = accA ? *d + acc[c][r] : acc[c][r];
+      } else {
+        dBf[((int64_t)b * Cb + (ci - Ca)) * HH + pr] = acc[c][r];
+      }
     }
   }
 }
@@ -291,58 +302,16 @@ __global__ void k_up_bwd(const float* __restrict__ dBf, float* __restrict__ dB, 
           (s[(2 * Yy + 1) * H + 2 * X] + s[(2 * Yy + 1) * H + 2 * X + 1]);
 }
 
-// Weight gradient: one block per (ci, co); each thread sums a strided set of
-// output positions for the k*k taps (and the bias when ci == 0); fixed-order
-// block reduction.
-__global__ void __launch_bounds__(256)
-k_conv_bwd_weight(const float* __restrict__ G, int Co, int Ho, const float* __restrict__ A, int Ca,
-                  const float* __restrict__ B, int Cb, int H, int k, int stride, int batch,
-                  float* __restrict__ gw) {
-  __shared__ float red[10][8];
-  const int ci = blockIdx.x, co = blockIdx.y, Ci = Ca + Cb, kk = k * k, pad = k / 2;
-  float acc[10];
-#pragma unroll
-  for (int t = 0; t < 10; ++t) acc[t] = 0.0f;
-  const int64_t tot = (int64_t)batch * Ho * Ho;
-  for (int64_t q = threadIdx.x; q < tot; q += 256) {
-    const int b = (int)(q / ((int64_t)Ho * Ho)), p = (int)(q % ((int64_t)Ho * Ho));
-    const int oy = p / Ho, ox = p % Ho;
-    const float g = G[(((int64_t)b * Co + co) * Ho + oy) * Ho + ox];
-    for (int dy = 0; dy < k; ++dy)
-      for (int dx = 0; dx < k; ++dx)
-        acc[dy * k + dx] = fmaf(g, in_at(A, Ca, B, Cb, H, b, ci, oy * stride + dy - pad,
-                                         ox * stride + dx - pad), acc[dy * k + dx]);
-    acc[9] += g;
-  }
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-  for (int t = 0; t < 10; ++t) {
-    float v = acc[t];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (l == 0) red[t][w] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < kk) {
-    const int t = threadIdx.x;
-    gw[((int64_t)co * Ci + ci) * kk + t] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
-  }
-  if (ci == 0 && threadIdx.x == 0)
-    gw[(int64_t)Co * Ci * kk + co] = (red[9][0] + red[9][1]) + (red[9][2] + red[9][3]);
-}
-
-// Weight gradient as a GEMM on the matrix cores (FP32 MFMA 16x16x4):
-// dW[co][j] = sum over the output pixels q of G[co][q] X[j][q], with
-// j = ci k^2 + tap and X the layer's input gathered at tap (the columns of
-// an im2col matrix); column j = Ci k^2 (X = 1) gives the bias gradient.
-// Block (c, jt): the pixels of chunk c, all output channels (16 NG), columns
-// 64 jt..; each wave takes a quarter of the chunk's pixels and holds the
-// whole 16 NG x 64 tile (NG x 4 products per step share the operands
-// loaded for them); the four waves' sums are added in wave order in LDS and
-// written to part[c][co][j], which k_wgrad_sum adds in chunk order (fixed
-// order: reproducible bits).  Lane layout of the 16x16x4 product: A (16 x 4)
-// row = lane & 15, k = lane >> 4; B (4 x 16) k = lane >> 4, column =
-// lane & 15; D row 4 (lane >> 4) + r (r < 4), column lane & 15.
+// Weight gradient as a GEMM on the matrix cores: dW[co][j] = sum over the
+// output pixels q of G[co][q] X[j][q], with j = ci k^2 + tap and X the
+// layer's input gathered at tap (the columns of an im2col matrix); column
+// j = Ci k^2 (X = 1) gives the bias gradient.  A operand: 16 output channels
+// x 4 pixels of G; B operand: 4 pixels x 16 columns.  Block (c, jt): the
+// pixels of chunk c, every output channel (16 NG), columns 64 jt..; each
+// wave takes a quarter of the chunk's pixels, 16 per pass (its gathers for
+// four groups of 4 pixels issued together, then NG x 16 products), and holds
+// the whole 16 NG x 64 tile; the four waves' sums are added in wave order in
+// LDS and written to part[c][co][j], which k_wgrad_sum adds in chunk order.
 template <int NG>
 __global__ void __launch_bounds__(256)
 k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float* __restrict__ A,
@@ -351,20 +320,34 @@ k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float*
   __shared__ float red[64 * NG * 16];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = l & 15, g = l >> 4;
-  const int Ci = Ca + Cb, kk = k * k, J = Ci * kk, pad = k / 2;
+  const int Ci = Ca + Cb, kk = k * k, J = Ci * kk, pad = k / 2, Hh = H >> 1;
   const int j0 = blockIdx.y * 64;
-  // this lane's B columns j0 + 16 t + i: (input channel, tap), or the bias
-  int cit[4], dyt[4], dxt[4];
+  // this lane's B columns j0 + 16 t + i: the plane of (sample 0, input
+  // channel) it reads, the per-sample stride, the resolution shift (the
+  // upsampled part of a concatenated input) and the tap; or the bias
+  const float* cp[4];
+  int64_t bs[4];
+  int hs[4], wd[4], dyp[4], dxp[4];
   bool jw[4], jb[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int j = j0 + 16 * t + i;
     jw[t] = j < J;
     jb[t] = j == J;
-    const int tp = jw[t] ? j % kk : 0;
-    cit[t] = jw[t] ? j / kk : 0;
-    dyt[t] = tp / k;
-    dxt[t] = tp % k;
+    const int ci = jw[t] ? j / kk : 0, tp = jw[t] ? j % kk : 0;
+    dyp[t] = tp / k - pad;
+    dxp[t] = tp % k - pad;
+    if (ci < Ca) {
+      cp[t] = A + (int64_t)ci * H * H;
+      bs[t] = (int64_t)Ca * H * H;
+      hs[t] = 0;
+      wd[t] = H;
+    } else {
+      cp[t] = B + (int64_t)(ci - Ca) * Hh * Hh;
+      bs[t] = (int64_t)Cb * Hh * Hh;
+      hs[t] = 1;
+      wd[t] = Hh;
+    }
   }
   // this wave's pixels: a quarter of the chunk (chunk is a multiple of 16)
   const int64_t sub = chunk / 4;
@@ -380,36 +363,45 @@ k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float*
   for (int c = 0; c < NG; ++c)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[c][t] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int64_t p = q0; p < q1; p += 4) {
-    const bool in = q < q1;
-    float a[NG], x[4];
+  for (int64_t p = q0; p < q1; p += 16) {
+    float a[4][NG], x[4][4];
+    bool ain[4], xv[4][4];
 #pragma unroll
-    for (int c = 0; c < NG; ++c) {
-      const int co = 16 * c + i;
-      a[c] = (in && co < Co) ? G[((int64_t)b * Co + co) * HH + (int64_t)oy * Ho + ox] : 0.0f;
-    }
+    for (int s = 0; s < 4; ++s) {
+      const bool in = q < q1;
+      ain[s] = in;
+      const int64_t gq = in ? (int64_t)b * Co * HH + (int64_t)oy * Ho + ox : 0;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      x[t] = 0.0f;
-      if (in) {
-        if (jw[t])
-          x[t] = in_at(A, Ca, B, Cb, H, b, cit[t], oy * stride + dyt[t] - pad,
-                       ox * stride + dxt[t] - pad);
-        else if (jb[t])
-          x[t] = 1.0f;
+      for (int c = 0; c < NG; ++c) {
+        const int co = 16 * c + i;
+        a[s][c] = G[gq + (int64_t)(co < Co ? co : 0) * HH];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int yy = oy * stride + dyp[t], xx = ox * stride + dxp[t];
+        const bool v = in && jw[t] && yy >= 0 && yy < H && xx >= 0 && xx < H;
+        xv[s][t] = v;
+        const int64_t off = v ? b * bs[t] + (int64_t)(yy >> hs[t]) * wd[t] + (xx >> hs[t]) : 0;
+        x[s][t] = cp[t][off];
+      }
+      q += 4;
+      ox += 4;
+      while (ox >= Ho) {
+        ox -= Ho;
+        if (++oy == Ho) { oy = 0; ++b; }
       }
     }
 #pragma unroll
-    for (int c = 0; c < NG; ++c)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], x[t], acc[c][t], 0, 0, 0);
-    q += 4;
-    ox += 4;
-    if (ox >= Ho) {   // Ho >= 4: at most one wrap per step
-      ox -= Ho;
-      if (++oy == Ho) { oy = 0; ++b; }
-    }
+      for (int c = 0; c < NG; ++c) {
+        const float av = (ain[s] && 16 * c + i < Co) ? a[s][c] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float xb = xv[s][t] ? x[s][t] : ((ain[s] && jb[t]) ? 1.0f : 0.0f);
+          acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xb, acc[c][t], 0, 0, 0);
+        }
+      }
   }
   // the four waves' sums, added in wave order
   for (int ww = 0; ww < 4; ++ww) {
@@ -654,13 +646,6 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
                       const NNPlan& p, double* out, hipStream_t s, const int32_t* gate,
                       const double* base) {
   const int64_t cnt = (int64_t)batch * n * n;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv_fwd<16>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   hipLaunchKernelGGL(k_to_f32, dim3(blocks(cnt)), dim3(256), 0, s, u, ws + p.x0, cnt, gate);
   for (int l = 0; l < NN_LAYERS; ++l) {
     const NNLayer& L = kNNLayers[l];
@@ -678,29 +663,19 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     }
     const int H = in_size(l, n), Ho = out_size(l, n);
     const uint16_t* wl = w + nn_param_offset(l);
-    if (L.c_out % 16 == 0 && L.c_out <= 64) {
-      const dim3 grid((unsigned)((int64_t)Ho * Ho + 63) / 64, batch);
-      switch (L.c_out / 16) {
-        case 1: hipLaunchKernelGGL(k_conv_fwd_mfma<1>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
-                                   ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
-        case 2: hipLaunchKernelGGL(k_conv_fwd_mfma<2>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
-                                   ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
-        case 3: hipLaunchKernelGGL(k_conv_fwd_mfma<3>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
-                                   ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
-        default: hipLaunchKernelGGL(k_conv_fwd_mfma<4>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,
-                                    ws + p.act[l], Ho, L.k, L.stride, L.act, gate); break;
-      }
-    } else if (L.c_out >= 16) {
-      const size_t lds = (size_t)16 * L.c_in * L.k * L.k * sizeof(float);
-      hipLaunchKernelGGL(k_conv_fwd<16>, dim3(blocks((int64_t)Ho * Ho), L.c_out / 16, batch),
-                         dim3(256), lds, s, A, Ca, B, Cb, H, wl, ws + p.act[l], L.c_out, Ho, L.k,
-                         L.stride, L.act, gate);
-    } else {
-      const size_t lds = (size_t)L.c_in * L.k * L.k * sizeof(float);
-      hipLaunchKernelGGL(k_conv_fwd<1>, dim3(blocks((int64_t)Ho * Ho), L.c_out, batch), dim3(256),
-                         lds, s, A, Ca, B, Cb, H, wl, ws + p.act[l], L.c_out, Ho, L.k, L.stride,
-                         L.act, gate);
+    // the concatenated input's first part fills whole 16-channel pairs
+    if ((Cb > 0 && Ca % 16) || L.c_out > 64) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(((int64_t)Ho * Ho + 15) / 16), batch);
+#define CH_FWD(NG)                                                                           \
+  hipLaunchKernelGGL(k_conv_fwd_mfma<NG>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,          \
+                     ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate)
+    switch ((L.c_out + 15) / 16) {
+      case 1: CH_FWD(1); break;
+      case 2: CH_FWD(2); break;
+      case 3: CH_FWD(3); break;
+      default: CH_FWD(4); break;
     }
+#undef CH_FWD
   }
   if (out)
     hipLaunchKernelGGL(k_residual_out, dim3(blocks(cnt)), dim3(256), 0, s, base ? base : u,
@@ -797,15 +772,23 @@ hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, 
                          ws + p.wpart, nch, L.c_out, J, gw);
     }
     if (l == 0) continue;
-    const int CIB = (L.c_in % 16 == 0) ? 16 : 1;
-    const size_t lds = (size_t)L.c_out * CIB * L.k * L.k * sizeof(float);
-    if (CIB == 16)
-      hipLaunchKernelGGL(k_conv_bwd_data<16>, dim3(blocks((int64_t)H * H), L.c_in / 16, batch),
-                         dim3(256), lds, s, G, L.c_out, Ho, wl, Ca, Cb, H, L.k, L.stride, dA, accA,
-                         ws + p.tmp);
-    else
-      hipLaunchKernelGGL(k_conv_bwd_data<1>, dim3(blocks((int64_t)H * H), L.c_in, batch), dim3(256),
-                         lds, s, G, L.c_out, Ho, wl, Ca, Cb, H, L.k, L.stride, dA, accA, ws + p.tmp);
+    if (L.c_in % 16 || L.c_in > 128 || (L.stride != 1 && L.stride != 2))
+      return hipErrorInvalidValue;
+    const dim3 dgrid((unsigned)(((int64_t)H * H + 15) / 16), batch);
+#define CH_BWD_DATA(NG)                                                                       \
+  hipLaunchKernelGGL(k_conv_bwd_data_mfma<NG>, dgrid, dim3(256), 0, s, G, L.c_out, Ho, wl, Ca, \
+                     Cb, H, L.k, L.stride, dA, accA, ws + p.tmp)
+    switch (L.c_in / 16) {
+      case 1: CH_BWD_DATA(1); break;
+      case 2: CH_BWD_DATA(2); break;
+      case 3: CH_BWD_DATA(3); break;
+      case 4: CH_BWD_DATA(4); break;
+      case 5: CH_BWD_DATA(5); break;
+      case 6: CH_BWD_DATA(6); break;
+      case 7: CH_BWD_DATA(7); break;
+      default: CH_BWD_DATA(8); break;
+    }
+#undef CH_BWD_DATA
     if (L.cat >= 0) {
       // the upsampled part: gradient of layer l-1's output (first writer in
       // backward order for that buffer)

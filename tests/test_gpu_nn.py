@@ -36,7 +36,7 @@ def test_layer_table_matches_reference():
         assert (cat < 0 and rcat is None) or names[cat] == rcat
 
 
-@pytest.mark.parametrize("n,batch", [(32, 3), (128, 2)])
+@pytest.mark.parametrize("n,batch", [(32, 3), (128, 2), (8, 2), (16, 1)])
 def test_forward_matches_reference(n, batch):
     from paper_2304_14074_amd import chlib
     wb, th = _weights(1)
@@ -54,9 +54,12 @@ def test_forward_matches_reference(n, batch):
     assert err < 1e-4, err
 
 
-def test_loss_and_gradients_match_reference():
+# n = 8 and 16: the deepest maps are 1 x 1 and 2 x 2 (a pixel walk of four per
+# step wraps more than once a row); batch 3 at n = 16: pixel chunks that do not
+# divide the batch's pixel count
+@pytest.mark.parametrize("n,batch", [(32, 2), (8, 2), (16, 3)])
+def test_loss_and_gradients_match_reference(n, batch):
     from paper_2304_14074_amd import chlib
-    n, batch = 32, 2
     wb, th = _weights(3)
     rng = np.random.default_rng(4)
     u = rng.uniform(-1, 1, (batch, n, n))
