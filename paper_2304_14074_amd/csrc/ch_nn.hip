@@ -64,9 +64,12 @@ static int in_size(int l, int n) {  // spatial size of the (concatenated) input 
 }
 
 // Pixel chunks of the weight-gradient GEMM over tot output pixels: at most
-// 64, of at least 1024 pixels each (a multiple of 4).
+// 256, of about 512 pixels or more each (a multiple of 16).
+// Tile count (16-pixel tiles times samples) from which the convolutions take
+// two tiles a block.
+constexpr int64_t kNNTwoTiles = 2048;
 static int wgrad_chunks(int64_t tot) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (tot + 1023) / 1024));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(256, (tot + 511) / 512));
 }
 static int64_t wgrad_chunk_len(int64_t tot) {
   const int nch = wgrad_chunks(tot);
@@ -116,33 +119,34 @@ __device__ __forceinline__ uint16_t f2bf_rne(float f) {
 
 // Convolutions on the matrix cores (FP32 MFMA 16x16x4, FP32 accumulation):
 // implicit GEMMs whose contraction runs over pairs (tap, 16 channels).  A
-// block takes 16 pixels of one sample and every output column (16 NG); its
-// four waves deal the pairs among themselves in turn, each keeps its own
-// sums, and the waves' sums are added in wave order in LDS (fixed order:
-// reproducible bits).  Per pair a lane issues its four gathers and its
-// 4 NG weight loads together, then the 4 NG products.  Lane layout of the
-// 16x16x4 product: A (16 x 4) row = lane & 15, k = lane >> 4; B (4 x 16)
-// k = lane >> 4, column = lane & 15; D row 4 (lane >> 4) + r (r < 4),
-// column lane & 15.
+// block takes T tiles of 16 pixels of one sample and every output column
+// (16 NG); its four waves deal the pairs among themselves in turn, each
+// keeps its own sums, and the waves' sums are added in wave order in LDS
+// (fixed order: reproducible bits).  Per pair a lane issues its 4 T gathers
+// and its 4 NG weight loads together, then the 4 T NG products (each weight
+// serves the T tiles).  Lane layout of the 16x16x4 product: A (16 x 4) row
+// = lane & 15, k = lane >> 4; B (4 x 16) k = lane >> 4, column = lane & 15;
+// D row 4 (lane >> 4) + r (r < 4), column lane & 15.
 typedef float nnf4 __attribute__((ext_vector_type(4)));
 
-// The waves' sums of a block: waves 1-3 park theirs in red, wave 0 adds
-// them to its own in wave order.  Returns false on waves 1-3.
-template <int NG>
-__device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[NG], float* red, int wv, int l) {
+// The waves' sums of a block (M accumulators a lane): waves 1-3 park theirs
+// in red, wave 0 adds them to its own in wave order.  Returns false on
+// waves 1-3.
+template <int M>
+__device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[M], float* red, int wv, int l) {
   if (wv > 0)
 #pragma unroll
-    for (int c = 0; c < NG; ++c)
+    for (int m = 0; m < M; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[(((wv - 1) * NG + c) * 4 + r) * 64 + l] = acc[c][r];
+      for (int r = 0; r < 4; ++r) red[(((wv - 1) * M + m) * 4 + r) * 64 + l] = acc[m][r];
   __syncthreads();
   if (wv > 0) return false;
 #pragma unroll
-  for (int c = 0; c < NG; ++c)
+  for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int ww = 0; ww < 3; ++ww) acc[c][r] += red[((ww * NG + c) * 4 + r) * 64 + l];
+      for (int ww = 0; ww < 3; ++ww) acc[m][r] += red[((ww * M + m) * 4 + r) * 64 + l];
   return true;
 }
 
@@ -151,56 +155,70 @@ __device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[NG], float* red, int wv, i
 // channels), up2(B) (Cb channels)] with Ca a multiple of 16 when Cb > 0.
 // A operand: 16 pixels x 4 channels gathered at the tap; B operands: 4
 // channels x 16 output channels of the BF16 weights; c_out <= 16 NG.
-template <int NG>
+template <int NG, int T>
 __global__ void __launch_bounds__(256)
 k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B, int Cb, int H,
                 const uint16_t* __restrict__ w, float* __restrict__ Y, int Co, int Ho, int k,
                 int stride, int act, const int32_t* __restrict__ gate) {
-  __shared__ float red[3 * NG * 4 * 64];
+  __shared__ float red[3 * T * NG * 4 * 64];
   if (gate && !*gate) return;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, b = blockIdx.y;
   const int i = l & 15, g = l >> 4;
   const int Ci = Ca + Cb, kk = k * k, pad = k / 2, nc = (Ci + 15) >> 4, items = kk * nc;
   const int HH = Ho * Ho, Hh = H >> 1;
-  const int pa = blockIdx.x * 16 + i;          // this lane's A-operand pixel
-  const bool pin = pa < HH;
-  const int oy = pin ? pa / Ho : 0, ox = pin ? pa % Ho : 0;
-  nnf4 acc[NG];
+  const int pbase = blockIdx.x * 16 * T;
+  int oy[T], ox[T];
+  bool pin[T];
 #pragma unroll
-  for (int c = 0; c < NG; ++c) acc[c] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int t = 0; t < T; ++t) {           // this lane's A-operand pixel of tile t
+    const int pa = pbase + 16 * t + i;
+    pin[t] = pa < HH;
+    oy[t] = pin[t] ? pa / Ho : 0;
+    ox[t] = pin[t] ? pa % Ho : 0;
+  }
+  nnf4 acc[T * NG];
+#pragma unroll
+  for (int m = 0; m < T * NG; ++m) acc[m] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int it = wv; it < items; it += 4) {
     const int tap = it / nc, c16 = it - tap * nc;
     const int dy = tap / k, dx = tap - dy * k;
-    const int yy = oy * stride + dy - pad, xx = ox * stride + dx - pad;
-    const bool v = pin && yy >= 0 && yy < H && xx >= 0 && xx < H;
     const int ci0 = 16 * c16 + g;
-    const float* src;
-    int plane;
-    if (16 * c16 < Ca) {
-      src = A + ((int64_t)b * Ca + ci0) * H * H + (v ? yy * H + xx : 0);
-      plane = H * H;
-    } else {
-      src = B + ((int64_t)b * Cb + ci0 - Ca) * Hh * Hh + (v ? (yy >> 1) * Hh + (xx >> 1) : 0);
-      plane = Hh * Hh;
-    }
-    float x[4], wt[4][NG];
+    const bool lowA = 16 * c16 < Ca;
+    float x[T][4], wt[4][NG];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool cin = ci0 + 4 * u < Ci;
-      x[u] = (v && cin) ? src[4 * u * plane] : 0.0f;
-#pragma unroll
-      for (int c = 0; c < NG; ++c) {
-        const int co = 16 * c + i;
-        wt[u][c] = (cin && co < Co) ? bf2f(w[((int64_t)co * Ci + ci0 + 4 * u) * kk + tap]) : 0.0f;
+    for (int t = 0; t < T; ++t) {
+      const int yy = oy[t] * stride + dy - pad, xx = ox[t] * stride + dx - pad;
+      const bool v = pin[t] && yy >= 0 && yy < H && xx >= 0 && xx < H;
+      const float* src;
+      int plane;
+      if (lowA) {
+        src = A + ((int64_t)b * Ca + ci0) * H * H + (v ? yy * H + xx : 0);
+        plane = H * H;
+      } else {
+        src = B + ((int64_t)b * Cb + ci0 - Ca) * Hh * Hh + (v ? (yy >> 1) * Hh + (xx >> 1) : 0);
+        plane = Hh * Hh;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[t][u] = (v && ci0 + 4 * u < Ci) ? src[4 * u * plane] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int c = 0; c < NG; ++c)
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u], wt[u][c], acc[c], 0, 0, 0);
+      for (int c = 0; c < NG; ++c) {
+        const int co = 16 * c + i;
+        wt[u][c] = (ci0 + 4 * u < Ci && co < Co)
+                       ? bf2f(w[((int64_t)co * Ci + ci0 + 4 * u) * kk + tap]) : 0.0f;
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < NG; ++c)
+          acc[t * NG + c] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(x[t][u], wt[u][c], acc[t * NG + c], 0, 0, 0);
   }
-  if (!ks_reduce<NG>(acc, red, wv, l)) return;
+  if (!ks_reduce<T * NG>(acc, red, wv, l)) return;
   const uint16_t* bias = w + (int64_t)Co * Ci * kk;
 #pragma unroll
   for (int c = 0; c < NG; ++c) {
@@ -208,13 +226,15 @@ k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B
     if (co >= Co) continue;
     const float bv = bf2f(bias[co]);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int pr = blockIdx.x * 16 + 4 * g + r;
-      if (pr >= HH) continue;
-      float y = acc[c][r] + bv;
-      if (act) y = y > 0.0f ? y : kSlope * y;
-      Y[((int64_t)b * Co + co) * HH + pr] = y;
-    }
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pr = pbase + 16 * t + 4 * g + r;
+        if (pr >= HH) continue;
+        float y = acc[t * NG + c][r] + bv;
+        if (act) y = y > 0.0f ? y : kSlope * y;
+        Y[((int64_t)b * Co + co) * HH + pr] = y;
+      }
   }
 }
 
@@ -232,61 +252,77 @@ __global__ void k_act_bwd(float* __restrict__ G, const float* __restrict__ Y, in
 // channels gathered from G; B operands: 4 output channels x 16 input
 // channels of the BF16 weights; c_in = Ca + Cb = 16 NG.  Channels < Ca go to
 // dA (added when accA), the rest to dBf at full resolution (reduced later).
-template <int NG>
+template <int NG, int T>
 __global__ void __launch_bounds__(256)
 k_conv_bwd_data_mfma(const float* __restrict__ G, int Co, int Ho, const uint16_t* __restrict__ w,
                      int Ca, int Cb, int H, int k, int stride, float* __restrict__ dA, int accA,
                      float* __restrict__ dBf) {
   constexpr int Ci = 16 * NG;
-  __shared__ float red[3 * NG * 4 * 64];
+  __shared__ float red[3 * T * NG * 4 * 64];
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, b = blockIdx.y;
   const int i = l & 15, g = l >> 4;
   const int kk = k * k, pad = k / 2, sh = stride == 2 ? 1 : 0, nc = (Co + 15) >> 4;
   const int items = kk * nc, HH = H * H, HoHo = Ho * Ho;
-  const int pa = blockIdx.x * 16 + i;          // this lane's A-operand pixel
-  const bool pin = pa < HH;
-  const int y = pin ? pa / H : 0, x = pin ? pa % H : 0;
-  nnf4 acc[NG];
+  const int pbase = blockIdx.x * 16 * T;
+  int y[T], x[T];
+  bool pin[T];
 #pragma unroll
-  for (int c = 0; c < NG; ++c) acc[c] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int t = 0; t < T; ++t) {           // this lane's A-operand pixel of tile t
+    const int pa = pbase + 16 * t + i;
+    pin[t] = pa < HH;
+    y[t] = pin[t] ? pa / H : 0;
+    x[t] = pin[t] ? pa % H : 0;
+  }
+  nnf4 acc[T * NG];
+#pragma unroll
+  for (int m = 0; m < T * NG; ++m) acc[m] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int it = wv; it < items; it += 4) {
     const int tap = it / nc, c16 = it - tap * nc;
     const int dy = tap / k, dx = tap - dy * k;
-    const int ty = y + pad - dy, tx = x + pad - dx;
-    const int oy = ty >> sh, ox = tx >> sh;
-    const bool v = pin && ty >= 0 && tx >= 0 && !(ty & sh) && !(tx & sh) && oy < Ho && ox < Ho;
     const int co0 = 16 * c16 + g;
-    const float* src = G + ((int64_t)b * Co + co0) * HoHo + (v ? oy * Ho + ox : 0);
-    float gv[4], wt[4][NG];
+    float gv[T][4], wt[4][NG];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool cin = co0 + 4 * u < Co;
-      gv[u] = (v && cin) ? src[4 * u * HoHo] : 0.0f;
+    for (int t = 0; t < T; ++t) {
+      const int ty = y[t] + pad - dy, tx = x[t] + pad - dx;
+      const int oy = ty >> sh, ox = tx >> sh;
+      const bool v = pin[t] && ty >= 0 && tx >= 0 && !(ty & sh) && !(tx & sh) && oy < Ho && ox < Ho;
+      const float* src = G + ((int64_t)b * Co + co0) * HoHo + (v ? oy * Ho + ox : 0);
 #pragma unroll
-      for (int c = 0; c < NG; ++c)
-        wt[u][c] = cin ? bf2f(w[((int64_t)(co0 + 4 * u) * Ci + 16 * c + i) * kk + tap]) : 0.0f;
+      for (int u = 0; u < 4; ++u) gv[t][u] = (v && co0 + 4 * u < Co) ? src[4 * u * HoHo] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int c = 0; c < NG; ++c)
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[u], wt[u][c], acc[c], 0, 0, 0);
+        wt[u][c] = co0 + 4 * u < Co ? bf2f(w[((int64_t)(co0 + 4 * u) * Ci + 16 * c + i) * kk + tap])
+                                    : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < NG; ++c)
+          acc[t * NG + c] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t][u], wt[u][c], acc[t * NG + c], 0, 0, 0);
   }
-  if (!ks_reduce<NG>(acc, red, wv, l)) return;
+  if (!ks_reduce<T * NG>(acc, red, wv, l)) return;
 #pragma unroll
   for (int c = 0; c < NG; ++c) {
     const int ci = 16 * c + i;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int pr = blockIdx.x * 16 + 4 * g + r;
-      if (pr >= HH) continue;
-      if (ci < Ca) {
-        float* d = dA + ((int64_t)b * Ca + ci) * HH + pr;
-        *d = accA ? *d + acc[c][r] : acc[c][r];
-      } else {
-        dBf[((int64_t)b * Cb + (ci - Ca)) * HH + pr] = acc[c][r];
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pr = pbase + 16 * t + 4 * g + r;
+        if (pr >= HH) continue;
+        const float v = acc[t * NG + c][r];
+        if (ci < Ca) {
+          float* d = dA + ((int64_t)b * Ca + ci) * HH + pr;
+          *d = accA ? *d + v : v;
+        } else {
+          dBf[((int64_t)b * Cb + (ci - Ca)) * HH + pr] = v;
+        }
       }
-    }
   }
 }
 
@@ -665,10 +701,18 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     const uint16_t* wl = w + nn_param_offset(l);
     // the concatenated input's first part fills whole 16-channel pairs
     if ((Cb > 0 && Ca % 16) || L.c_out > 64) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(((int64_t)Ho * Ho + 15) / 16), batch);
-#define CH_FWD(NG)                                                                           \
-  hipLaunchKernelGGL(k_conv_fwd_mfma<NG>, grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,          \
-                     ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate)
+    // two 16-pixel tiles a block (each weight load serves both) once the
+    // grid has work for every CU with them
+    const int64_t tiles = ((int64_t)Ho * Ho + 15) / 16;
+    const int T = tiles * batch >= kNNTwoTiles ? 2 : 1;
+    const dim3 grid((unsigned)((tiles + T - 1) / T), batch);
+#define CH_FWD(NG)                                                                            \
+  if (T == 2)                                                                                  \
+    hipLaunchKernelGGL((k_conv_fwd_mfma<NG, 2>), grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,   \
+                       ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate);                \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_conv_fwd_mfma<NG, 1>), grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,   \
+                       ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate)
     switch ((L.c_out + 15) / 16) {
       case 1: CH_FWD(1); break;
       case 2: CH_FWD(2); break;
@@ -774,10 +818,16 @@ hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, 
     if (l == 0) continue;
     if (L.c_in % 16 || L.c_in > 128 || (L.stride != 1 && L.stride != 2))
       return hipErrorInvalidValue;
-    const dim3 dgrid((unsigned)(((int64_t)H * H + 15) / 16), batch);
-#define CH_BWD_DATA(NG)                                                                       \
-  hipLaunchKernelGGL(k_conv_bwd_data_mfma<NG>, dgrid, dim3(256), 0, s, G, L.c_out, Ho, wl, Ca, \
-                     Cb, H, L.k, L.stride, dA, accA, ws + p.tmp)
+    const int64_t dtiles = ((int64_t)H * H + 15) / 16;
+    const int DT = dtiles * batch >= kNNTwoTiles ? 2 : 1;
+    const dim3 dgrid((unsigned)((dtiles + DT - 1) / DT), batch);
+#define CH_BWD_DATA(NG)                                                                         \
+  if (DT == 2)                                                                                   \
+    hipLaunchKernelGGL((k_conv_bwd_data_mfma<NG, 2>), dgrid, dim3(256), 0, s, G, L.c_out, Ho, wl, \
+                       Ca, Cb, H, L.k, L.stride, dA, accA, ws + p.tmp);                          \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_conv_bwd_data_mfma<NG, 1>), dgrid, dim3(256), 0, s, G, L.c_out, Ho, wl, \
+                       Ca, Cb, H, L.k, L.stride, dA, accA, ws + p.tmp)
     switch (L.c_in / 16) {
       case 1: CH_BWD_DATA(1); break;
       case 2: CH_BWD_DATA(2); break;
