@@ -469,16 +469,36 @@ k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float*
     }
 }
 
-// gw[co][j] = sum over the chunks in order of part[c][co][j] (j = J: the bias,
-// stored after all weights).
-__global__ void k_wgrad_sum(const float* __restrict__ part, int nch, int Co, int J,
-                            float* __restrict__ gw) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// gw[co][j] = sum over the chunks of part[c][co][j] (j = J: the bias, stored
+// after all weights).  A block takes 64 consecutive outputs; its four waves
+// sum a quarter of the chunks each, in chunk order (eight loads issued
+// together), and the quarters are added in order.
+__global__ void __launch_bounds__(256)
+k_wgrad_sum(const float* __restrict__ part, int nch, int Co, int J, float* __restrict__ gw) {
+  __shared__ float qs[3][64];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + l;
   const int Jp = J + 1;
-  if (idx >= (int64_t)Co * Jp) return;
-  const int co = (int)(idx / Jp), j = (int)(idx % Jp);
+  const int64_t tot = (int64_t)Co * Jp;
+  const int quarter = (nch + 3) / 4, c0 = w * quarter, c1 = min(nch, c0 + quarter);
   float s = 0.0f;
-  for (int c = 0; c < nch; ++c) s += part[((int64_t)c * Co + co) * Jp + j];
+  if (idx < tot) {
+    const float* src = part + idx;            // part[c][co][j] = part[c * Co * Jp + idx]
+    int c = c0;
+    for (; c + 8 <= c1; c += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(c + u) * tot];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < c1; ++c) s += src[(int64_t)c * tot];
+  }
+  if (w > 0) qs[w - 1][l] = s;
+  __syncthreads();
+  if (w > 0 || idx >= tot) return;
+  s = ((s + qs[0][l]) + qs[1][l]) + qs[2][l];
+  const int co = (int)(idx / Jp), j = (int)(idx % Jp);
   if (j < J) gw[(int64_t)co * J + j] = s;
   else gw[(int64_t)Co * J + co] = s;
 }
@@ -812,8 +832,8 @@ hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, 
         default: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<4>, grid, dim3(256), 0, s, G, L.c_out,
                                     Ho, A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
       }
-      hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks((int64_t)L.c_out * (J + 1))), dim3(256), 0, s,
-                         ws + p.wpart, nch, L.c_out, J, gw);
+      hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)(((int64_t)L.c_out * (J + 1) + 63) / 64)),
+                         dim3(256), 0, s, ws + p.wpart, nch, L.c_out, J, gw);
     }
     if (l == 0) continue;
     if (L.c_in % 16 || L.c_in > 128 || (L.stride != 1 && L.stride != 2))
