@@ -34,6 +34,7 @@ METRIC = "fine grid-point-steps/s; Parareal time-to-1e-8 (neural G vs plain G), 
 FP64_PEAK_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
 FP64_VECTOR_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 flop/clk)
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_TFLOPS = 157.3      # MI355X dense FP32 matrix peak
 # HBM bytes of one fine-sweep launch of the 128x128 workload, from FETCH_SIZE and
 # WRITE_SIZE counter runs calibrated by a 1 GiB copy, for the kernel as it is now;
 # set to None whenever the fine kernel changes until the counters are taken again.
@@ -44,6 +45,91 @@ PIPE_TRAFFIC_BYTES_PER_ITERATION = (52387019.2 * 2.0 + 104752324.5) * 1024 / 4
 # the same for the fine sweep of the 256-instance batch (all three class launches)
 BATCHED_SWEEP_TRAFFIC_BYTES = ((6156784068.3 + 461061.6 + 105800.1) * 2.0
                                + 12305827472.0 + 839680.0 + 190464.0) * 1024
+
+
+def nn_forward_flops(n: int) -> float:
+    """Flops (2 per multiply-add) of one forward pass of the learned coarse
+    propagator's network on an n x n grid, from the library's layer table:
+    sum over the layers of 2 c_out c_in k^2 times the output pixels (a
+    concatenating layer works at twice its predecessor's size)."""
+    from paper_2304_14074_amd import chlib
+    s, tot = n, 0.0
+    for ci, co, k, stride, _, cat in chlib.ch_nn_layers():
+        if cat >= 0:
+            s *= 2
+        s //= stride
+        tot += 2.0 * co * ci * k * k * s * s
+    return tot
+
+
+def bench_nn(args):
+    """The learned coarse propagator's network on the FP32 matrix cores
+    (diagnostic mode): one training step (forward, MSE loss, backward, Adam)
+    on a batch of 16 random 128 x 128 states, and the forward pass at batch 1
+    (one coarse step of the learned sweep) and at batch 16.  Flops counted:
+    the convolutions' multiply-adds, 2 each: forward F, input gradient F minus
+    the first layer's share, weight gradient F."""
+    import torch
+    from paper_2304_14074_amd import chlib, surrogate
+    n, batch = 128, 16
+    g = torch.Generator(device="cuda").manual_seed(0)
+    u = 0.6 * torch.rand((batch, n, n), dtype=torch.float64, device="cuda", generator=g) - 0.3
+    tgt = u + 0.01 * torch.randn((batch, n, n), dtype=torch.float64, device="cuda", generator=g)
+    wm = surrogate.init_weights(seed=0)
+    wm += 0.01 * torch.randn(wm.shape, generator=torch.Generator().manual_seed(1)).cuda()
+    wb = torch.empty(wm.numel(), dtype=torch.bfloat16, device="cuda")
+    chlib.ch_nn_to_bf16(wm, wb)
+    m, v = torch.zeros_like(wm), torch.zeros_like(wm)
+    grad = torch.empty_like(wm)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    ws = chlib.NNWorkspace(batch, n)
+    ws1 = chlib.NNWorkspace(1, n)
+    out = torch.empty_like(u)
+    s = torch.cuda.current_stream()
+    step = [0]
+
+    def train():
+        chlib.ch_nn_train_step(wb, u, tgt, grad, loss, ws)
+        step[0] += 1
+        chlib.ch_nn_adam(wm, wb, m, v, grad, 1e-4, step[0])
+
+    def timed(fn, reps):
+        for _ in range(max(args.warmup, 3)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(args.steps, 1) * 5
+    ms_train = timed(train, reps)
+    ms_f1 = timed(lambda: chlib.ch_nn_forward(wb, u[:1], out[:1], ws1), reps)
+    ms_f16 = timed(lambda: chlib.ch_nn_forward(wb, u, out, ws), reps)
+    f = nn_forward_flops(n)
+    ci0, co0, k0 = chlib.ch_nn_layers()[0][:3]
+    first = 2.0 * co0 * ci0 * k0 * k0 * n * n
+    train_flops = batch * (3 * f - first)
+    tf_train = train_flops / (ms_train / 1e3) / 1e12
+    return {"metric": "learned-propagator training TFLOP/s (diagnostic mode)", "value": tf_train,
+            "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": max(args.warmup, 3),
+            "ms_per_step": ms_train, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "surrogate network (12 convolutions, BF16 weights, FP32 "
+                                   "accumulation) on 128x128 states, training batch 16",
+                       "n": n, "batch": batch},
+            "roofline": {"bound": "mfma", "achieved": tf_train, "peak": FP32_MFMA_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf_train / FP32_MFMA_TFLOPS, "traffic": None,
+                         "kernel": "one training step: k_conv_fwd_mfma, k_conv_bwd_data_mfma, "
+                                   "k_conv_bwd_weight_mfma + k_wgrad_sum, loss and Adam"},
+            "extra": {"forward_gflop_per_sample": f / 1e9, "train_step_ms": ms_train,
+                      "forward_batch1_ms": ms_f1,
+                      "forward_batch1_tflops": f / (ms_f1 / 1e3) / 1e12,
+                      "forward_batch16_ms": ms_f16,
+                      "forward_batch16_tflops": batch * f / (ms_f16 / 1e3) / 1e12}}
 
 
 def fine_flops_per_point_step(n: int) -> float:
@@ -590,7 +676,7 @@ def main():
     ap.add_argument("--nn-traj", type=int, default=2000)
     ap.add_argument("--nn-steps", type=int, default=3000)
     ap.add_argument("--workload", default="linear_2d_128",
-                    choices=["linear_2d_128", "batched", "nonlinear", "hbm", "study", "dd"])
+                    choices=["linear_2d_128", "batched", "nonlinear", "hbm", "study", "dd", "nn"])
     ap.add_argument("--nl-steps", type=int, default=20,
                     help="implicit steps per slice timed in --workload nonlinear")
     ap.add_argument("--profile-fine", action="store_true",
@@ -620,6 +706,9 @@ def main():
         return
     if args.workload == "dd":
         print(json.dumps(dd_fine_leg()))
+        return
+    if args.workload == "nn":
+        print(json.dumps(bench_nn(args)))
         return
     if args.profile_fine:
         # one fine-sweep launch of the workload plus a plain 1 GiB device copy
