@@ -323,15 +323,16 @@ ch_status ch_nn_forward(const uint16_t* w_bf16, const double* u, int32_t batch, 
 /* For callers that cannot allocate (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc): the same forward pass as
  * ch_nn_forward, same kernels and results, with no workspace argument.  The
- * activations live in a static device array of 32 MiB (8 Mi floats) that
- * each GPU the library runs on holds until the process ends; the call
- * allocates nothing.  Limit: batch * (activation floats per sample) <= 8 Mi,
- * i.e. batch <= 5 at n = 128, 1 at n = 256, 23 at n = 64; larger requests
+ * activations and the weights copied into the forward pass's layout (0.25 Mi
+ * floats) live in a static device array of 32 MiB (8 Mi floats) that each
+ * GPU the library runs on holds until the process ends; the call allocates
+ * nothing.  Limit: batch * (activation floats per sample) + 0.25 Mi <= 8 Mi,
+ * i.e. batch <= 5 at n = 128, 1 at n = 256, 22 at n = 64; larger requests
  * return CH_ERR_ARG (with a message on stderr) before any launch.  Every
  * call on one GPU shares that array, which keeps the last call's contents
- * (nothing in it needs clearing: each activation is written before it is
- * read), so calls that overlap on one GPU (different streams, or threads)
- * race and must be serialised by the caller. */
+ * (nothing in it needs clearing: each value is written before it is read),
+ * so calls that overlap on one GPU (different streams, or threads) race and
+ * must be serialised by the caller. */
 ch_status ch_nn_forward_static(const uint16_t* w_bf16, const double* u, int32_t batch, int32_t n,
                                double* out, ch_stream stream);
 /* forward, loss = mean((u + net(u) - target)^2) (device float), gradient of

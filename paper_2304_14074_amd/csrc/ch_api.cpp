@@ -756,12 +756,14 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
       double* Ui = st->U + d.off_iter;
       const double* Fi = st->F + d.off_slices;
       double* Gi = st->G_old + d.off_slices;
+      // the weights in the forward layout once for the whole sweep
+      e = chk::nn_pack_forward(c->nn_w, nws, pl, s, act);
       if (mode == 1) {
         for (int sl = 0; sl < N && e == hipSuccess; ++sl) {
           if (gbase) e = plain(4, sl, 1, st->U, act);
           if (e == hipSuccess)
             e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, act,
-                                gbase ? gbase + sl * P : nullptr);
+                                gbase ? gbase + sl * P : nullptr, false);
           if (e == hipSuccess) e = chk::pr_correct(Ui + (sl + 1) * P, nullptr, Gi + sl * P, g, P, part, 1, act, s);
         }
       } else {
@@ -779,7 +781,7 @@ static ch_status coarse_all(ch_ctx* c, int mode, const double* U_in, double* G_o
           if (gbase) e = plain(4, sl, 1, st->U, gates + sl);
           if (e == hipSuccess)
             e = chk::nn_forward(c->nn_w, Ui + sl * P, 1, n, nws, pl, g, s, gates + sl,
-                                gbase ? gbase + sl * P : nullptr);
+                                gbase ? gbase + sl * P : nullptr, false);
           if (e == hipSuccess)
             e = chk::pr_correct(Ui + (sl + 1) * P, Fi + sl * P, Gi + sl * P, g, P,
                                 part + (int64_t)sl * nb, 0, gates + sl, s);
@@ -1301,7 +1303,7 @@ ch_status ch_nn_forward_static(const uint16_t* w, const double* u, int32_t batch
   if (!w || !u || !out || batch < 1 || n < 8 || n % 8) return CH_ERR_ARG;
   const size_t need = chk::nn_forward_floats(batch, n);
   if (need > chk::NN_STATIC_FLOATS) {
-    fprintf(stderr, "ch_nn_forward_static: batch %d at n = %d needs %zu floats of activations, "
+    fprintf(stderr, "ch_nn_forward_static: batch %d at n = %d needs %zu floats of activations and weights, "
             "more than the %zu of the static scratch\n", batch, n, need, chk::NN_STATIC_FLOATS);
     return CH_ERR_ARG;
   }

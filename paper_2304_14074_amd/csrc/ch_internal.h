@@ -178,7 +178,7 @@ struct NNLayer { int c_in, c_out, k, stride, act, cat; };
 constexpr int NN_LAYERS = 12;
 extern const NNLayer kNNLayers[NN_LAYERS];
 struct NNPlan {   // float offsets inside an NN workspace
-  size_t x0, act[NN_LAYERS], grad[NN_LAYERS], tmp, part, wpart, floats;
+  size_t x0, act[NN_LAYERS], wpf, grad[NN_LAYERS], tmp, part, wpart, wpd, floats;
 };
 NNPlan nn_plan(int batch, int n);
 int64_t nn_param_count();
@@ -186,10 +186,15 @@ int64_t nn_param_offset(int layer);
 // gate (device, nullable): every kernel of the pass returns at once when
 // *gate == 0 (a graph-captured pass that the device switches off)
 // base (nullable): out = clip(base + net(u)) instead of clip(u + net(u))
+// pack: first copy the weights into the forward pass's layout in ws (false:
+// nn_pack_forward has done so with these weights since ws last changed hands)
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
                       const NNPlan& p, double* out, hipStream_t s, const int32_t* gate = nullptr,
-                      const double* base = nullptr);
-// floats of workspace the forward pass alone uses (x0 and the activations)
+                      const double* base = nullptr, bool pack = true);
+hipError_t nn_pack_forward(const uint16_t* w, float* ws, const NNPlan& p, hipStream_t s,
+                           const int32_t* gate = nullptr);
+// floats of workspace the forward pass alone uses (x0, the activations and
+// the packed weights)
 size_t nn_forward_floats(int batch, int n);
 // the allocation-free forward pass: the file-scope device array of
 // NN_STATIC_FLOATS floats; nn_static_scratch returns its address on the

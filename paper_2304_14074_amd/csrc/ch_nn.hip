@@ -76,8 +76,26 @@ static int64_t wgrad_chunk_len(int64_t tot) {
   return ((tot + nch - 1) / nch + 15) / 16 * 16;
 }
 
-// Workspace layout (floats): x0 | for each layer: act | for each layer: grad | tmp | loss
-// partials | weight-gradient partials
+// Packed weights (FP32, from the BF16 parameters), one block per layer:
+// forward layout  Wf[tap][ci][i][c] = W[16c + i][ci][tap]   (c < ceil(c_out/16))
+// input-gradient  Wd[tap][co][i][c] = W[co][16c + i][tap]   (c < ceil(c_in/16))
+// (zero where the channel is past c_out or c_in), so the 16 lanes of one
+// MFMA operand row read one contiguous run.
+static int64_t pack_layer_floats(int l, bool fwd) {
+  const NNLayer& L = kNNLayers[l];
+  const int kk = L.k * L.k;
+  return fwd ? (int64_t)kk * L.c_in * 16 * ((L.c_out + 15) / 16)
+             : (int64_t)kk * L.c_out * 16 * ((L.c_in + 15) / 16);
+}
+static int64_t pack_offset(int layer, bool fwd) {
+  int64_t s = 0;
+  for (int l = 0; l < layer; ++l) s += (pack_layer_floats(l, fwd) + 63) / 64 * 64;
+  return s;
+}
+static int64_t pack_floats(bool fwd) { return pack_offset(NN_LAYERS, fwd); }
+
+// Workspace layout (floats): x0 | for each layer: act | forward-packed weights | for each
+// layer: grad | tmp | loss partials | weight-gradient partials | input-gradient-packed weights
 NNPlan nn_plan(int batch, int n) {
   NNPlan p;
   size_t o = 0;
@@ -90,6 +108,7 @@ NNPlan nn_plan(int batch, int n) {
     const int si = in_size(l, n);
     maxin = std::max(maxin, (size_t)batch * kNNLayers[l].c_in * si * si);
   }
+  p.wpf = take((size_t)pack_floats(true));
   for (int l = 0; l < NN_LAYERS; ++l) {
     const int s = out_size(l, n);
     p.grad[l] = take((size_t)batch * kNNLayers[l].c_out * s * s);
@@ -103,6 +122,7 @@ NNPlan nn_plan(int batch, int n) {
     wp = std::max(wp, (size_t)wgrad_chunks(tot) * L.c_out * (L.c_in * L.k * L.k + 1));
   }
   p.wpart = take(wp);
+  p.wpd = take((size_t)pack_floats(false));
   p.floats = o;
   return p;
 }
@@ -115,6 +135,54 @@ __device__ __forceinline__ uint16_t f2bf_rne(float f) {
   if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
   const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(r >> 16);
+}
+
+// NG consecutive floats at p (p aligned to 4 NG bytes, as the packed rows are).
+template <int NG>
+__device__ __forceinline__ void ld_row(const float* __restrict__ p, float (&v)[NG]) {
+  if constexpr (NG % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < NG / 4; ++q) {
+      const float4 x = reinterpret_cast<const float4*>(p)[q];
+      v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+    }
+  } else if constexpr (NG % 2 == 0) {
+#pragma unroll
+    for (int q = 0; q < NG / 2; ++q) {
+      const float2 x = reinterpret_cast<const float2*>(p)[q];
+      v[2 * q] = x.x; v[2 * q + 1] = x.y;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NG; ++c) v[c] = p[c];
+  }
+}
+
+// Every layer's weights into one packed layout (forward or input gradient),
+// one thread per packed float (the padding of each layer's block included).
+struct PackTab {
+  int64_t woff[NN_LAYERS], poff[NN_LAYERS + 1];   // BF16 and packed offsets
+  int co[NN_LAYERS], ci[NN_LAYERS], kk[NN_LAYERS];
+};
+__global__ void k_pack_weights(const uint16_t* __restrict__ w, float* __restrict__ out, PackTab t,
+                               int fwd, const int32_t* __restrict__ gate) {
+  if (gate && !*gate) return;
+  const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (d >= t.poff[NN_LAYERS]) return;
+  int l = 0;
+  while (l + 1 < NN_LAYERS && d >= t.poff[l + 1]) ++l;
+  const int64_t e = d - t.poff[l];
+  const int Co = t.co[l], Ci = t.ci[l], kk = t.kk[l];
+  const int NG = fwd ? (Co + 15) / 16 : (Ci + 15) / 16, M = fwd ? Ci : Co;
+  const int c = (int)(e % NG), i = (int)((e / NG) % 16);
+  const int64_t rest = e / (16 * NG);
+  if (rest >= (int64_t)kk * M) {   // padding
+    out[d] = 0.0f;
+    return;
+  }
+  const int tap = (int)(rest / M), r = (int)(rest % M);
+  const int co = fwd ? 16 * c + i : r, ci = fwd ? r : 16 * c + i;
+  out[d] = (co < Co && ci < Ci) ? bf2f(w[t.woff[l] + ((int64_t)co * Ci + ci) * kk + tap]) : 0.0f;
 }
 
 // Convolutions on the matrix cores (FP32 MFMA 16x16x4, FP32 accumulation):
@@ -154,12 +222,14 @@ __device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[M], float* red, int wv, in
 // X[ci][p + tap]), the input X either A alone or the concatenation [A (Ca
 // channels), up2(B) (Cb channels)] with Ca a multiple of 16 when Cb > 0.
 // A operand: 16 pixels x 4 channels gathered at the tap; B operands: 4
-// channels x 16 output channels of the BF16 weights; c_out <= 16 NG.
+// channels x 16 output channels of the weights in the forward packed layout
+// (wf, this layer's block; w for the BF16 biases); c_out <= 16 NG.
 template <int NG, int T>
 __global__ void __launch_bounds__(256)
 k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B, int Cb, int H,
-                const uint16_t* __restrict__ w, float* __restrict__ Y, int Co, int Ho, int k,
-                int stride, int act, const int32_t* __restrict__ gate) {
+                const uint16_t* __restrict__ w, const float* __restrict__ wf,
+                float* __restrict__ Y, int Co, int Ho, int k, int stride, int act,
+                const int32_t* __restrict__ gate) {
   __shared__ float red[3 * T * NG * 4 * 64];
   if (gate && !*gate) return;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, b = blockIdx.y;
@@ -202,13 +272,14 @@ k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B
       for (int u = 0; u < 4; ++u) x[t][u] = (v && ci0 + 4 * u < Ci) ? src[4 * u * plane] : 0.0f;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 4; ++u) {
+      if (ci0 + 4 * u < Ci) {
+        ld_row<NG>(wf + ((int64_t)(tap * Ci + ci0 + 4 * u) * 16 + i) * NG, wt[u]);
+      } else {
 #pragma unroll
-      for (int c = 0; c < NG; ++c) {
-        const int co = 16 * c + i;
-        wt[u][c] = (ci0 + 4 * u < Ci && co < Co)
-                       ? bf2f(w[((int64_t)co * Ci + ci0 + 4 * u) * kk + tap]) : 0.0f;
+        for (int c = 0; c < NG; ++c) wt[u][c] = 0.0f;
       }
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -250,11 +321,12 @@ __global__ void k_act_bwd(float* __restrict__ G, const float* __restrict__ Y, in
 // to input pixel p (a zero where there is none: the border, or a tap that the
 // stride skips; stride is 1 or 2).  A operand: 16 input pixels x 4 output
 // channels gathered from G; B operands: 4 output channels x 16 input
-// channels of the BF16 weights; c_in = Ca + Cb = 16 NG.  Channels < Ca go to
+// channels of the weights in the input-gradient packed layout (wd, this
+// layer's block); c_in = Ca + Cb = 16 NG.  Channels < Ca go to
 // dA (added when accA), the rest to dBf at full resolution (reduced later).
 template <int NG, int T>
 __global__ void __launch_bounds__(256)
-k_conv_bwd_data_mfma(const float* __restrict__ G, int Co, int Ho, const uint16_t* __restrict__ w,
+k_conv_bwd_data_mfma(const float* __restrict__ G, int Co, int Ho, const float* __restrict__ wd,
                      int Ca, int Cb, int H, int k, int stride, float* __restrict__ dA, int accA,
                      float* __restrict__ dBf) {
   constexpr int Ci = 16 * NG;
@@ -291,11 +363,14 @@ k_conv_bwd_data_mfma(const float* __restrict__ G, int Co, int Ho, const uint16_t
       for (int u = 0; u < 4; ++u) gv[t][u] = (v && co0 + 4 * u < Co) ? src[4 * u * HoHo] : 0.0f;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 4; ++u) {
+      if (co0 + 4 * u < Co) {
+        ld_row<NG>(wd + ((int64_t)(tap * Co + co0 + 4 * u) * 16 + i) * NG, wt[u]);
+      } else {
 #pragma unroll
-      for (int c = 0; c < NG; ++c)
-        wt[u][c] = co0 + 4 * u < Co ? bf2f(w[((int64_t)(co0 + 4 * u) * Ci + 16 * c + i) * kk + tap])
-                                    : 0.0f;
+        for (int c = 0; c < NG; ++c) wt[u][c] = 0.0f;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -698,10 +773,36 @@ hipError_t masked_copy(double* dst, const double* src, const uint8_t* mask, int6
 }
 
 // ---------------------------------------------------------------- host launchers
+static hipError_t pack_weights(const uint16_t* w, float* out, bool fwd, hipStream_t s,
+                               const int32_t* gate) {
+  PackTab t;
+  for (int l = 0; l < NN_LAYERS; ++l) {
+    const NNLayer& L = kNNLayers[l];
+    t.woff[l] = nn_param_offset(l);
+    t.poff[l] = pack_offset(l, fwd);
+    t.co[l] = L.c_out;
+    t.ci[l] = L.c_in;
+    t.kk[l] = L.k * L.k;
+  }
+  t.poff[NN_LAYERS] = pack_floats(fwd);
+  hipLaunchKernelGGL(k_pack_weights, dim3(blocks(t.poff[NN_LAYERS])), dim3(256), 0, s, w, out, t,
+                     fwd ? 1 : 0, gate);
+  return hipGetLastError();
+}
+
+hipError_t nn_pack_forward(const uint16_t* w, float* ws, const NNPlan& p, hipStream_t s,
+                           const int32_t* gate) {
+  return pack_weights(w, ws + p.wpf, true, s, gate);
+}
+
 hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, float* ws,
                       const NNPlan& p, double* out, hipStream_t s, const int32_t* gate,
-                      const double* base) {
+                      const double* base, bool pack) {
   const int64_t cnt = (int64_t)batch * n * n;
+  if (pack) {
+    const hipError_t e = nn_pack_forward(w, ws, p, s, gate);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_to_f32, dim3(blocks(cnt)), dim3(256), 0, s, u, ws + p.x0, cnt, gate);
   for (int l = 0; l < NN_LAYERS; ++l) {
     const NNLayer& L = kNNLayers[l];
@@ -719,6 +820,7 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     }
     const int H = in_size(l, n), Ho = out_size(l, n);
     const uint16_t* wl = w + nn_param_offset(l);
+    const float* wf = ws + p.wpf + pack_offset(l, true);
     // the concatenated input's first part fills whole 16-channel pairs
     if ((Cb > 0 && Ca % 16) || L.c_out > 64) return hipErrorInvalidValue;
     // two 16-pixel tiles a block (each weight load serves both) once the
@@ -729,10 +831,10 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
 #define CH_FWD(NG)                                                                            \
   if (T == 2)                                                                                  \
     hipLaunchKernelGGL((k_conv_fwd_mfma<NG, 2>), grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,   \
-                       ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate);                \
+                       wf, ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate);            \
   else                                                                                         \
     hipLaunchKernelGGL((k_conv_fwd_mfma<NG, 1>), grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,   \
-                       ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate)
+                       wf, ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate)
     switch ((L.c_out + 15) / 16) {
       case 1: CH_FWD(1); break;
       case 2: CH_FWD(2); break;
@@ -774,6 +876,7 @@ hipError_t nn_static_scratch(float** out) {
 hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, int batch, int n,
                          float* ws, const NNPlan& p, float* grad, float* loss, hipStream_t s) {
   hipError_t e = nn_forward(w, u, batch, n, ws, p, nullptr, s);
+  if (e == hipSuccess) e = pack_weights(w, ws + p.wpd, false, s, nullptr);
   if (e != hipSuccess) return e;
   const int64_t cnt = (int64_t)batch * n * n;
   const int nb = (int)blocks(cnt);
@@ -838,15 +941,16 @@ hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, 
     if (l == 0) continue;
     if (L.c_in % 16 || L.c_in > 128 || (L.stride != 1 && L.stride != 2))
       return hipErrorInvalidValue;
+    const float* wd = ws + p.wpd + pack_offset(l, false);
     const int64_t dtiles = ((int64_t)H * H + 15) / 16;
     const int DT = dtiles * batch >= kNNTwoTiles ? 2 : 1;
     const dim3 dgrid((unsigned)((dtiles + DT - 1) / DT), batch);
 #define CH_BWD_DATA(NG)                                                                         \
   if (DT == 2)                                                                                   \
-    hipLaunchKernelGGL((k_conv_bwd_data_mfma<NG, 2>), dgrid, dim3(256), 0, s, G, L.c_out, Ho, wl, \
+    hipLaunchKernelGGL((k_conv_bwd_data_mfma<NG, 2>), dgrid, dim3(256), 0, s, G, L.c_out, Ho, wd, \
                        Ca, Cb, H, L.k, L.stride, dA, accA, ws + p.tmp);                          \
   else                                                                                           \
-    hipLaunchKernelGGL((k_conv_bwd_data_mfma<NG, 1>), dgrid, dim3(256), 0, s, G, L.c_out, Ho, wl, \
+    hipLaunchKernelGGL((k_conv_bwd_data_mfma<NG, 1>), dgrid, dim3(256), 0, s, G, L.c_out, Ho, wd, \
                        Ca, Cb, H, L.k, L.stride, dA, accA, ws + p.tmp)
     switch (L.c_in / 16) {
       case 1: CH_BWD_DATA(1); break;
