@@ -63,17 +63,34 @@ static int in_size(int l, int n) {  // spatial size of the (concatenated) input 
   return kNNLayers[l].cat >= 0 ? 2 * s : s;
 }
 
-// Pixel chunks of the weight-gradient GEMM over tot output pixels: at most
-// 256, of about 512 pixels or more each (a multiple of 16).
 // Tile count (16-pixel tiles times samples) from which the convolutions take
 // two tiles a block.
 constexpr int64_t kNNTwoTiles = 2048;
-static int wgrad_chunks(int64_t tot) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(256, (tot + 511) / 512));
+
+// Chunks of the weight-gradient GEMM: a chunk is a band of R output rows of
+// one sample, R >= 512 / Ho (at least 512 pixels where the map has them) and
+// R >= batch Ho / 256 (at most about 256 chunks), fewer rows while the band's
+// staged input would pass kWgradLds bytes (two blocks a CU); a single row may
+// take up to kWgradLdsMax.  64 consecutive columns j = ci k^2 + tap span at
+// most (62 + k^2) / k^2 + 1 channels: 8 for 3 x 3 layers, 64 for 1 x 1.
+constexpr size_t kWgradLds = 96 * 1024, kWgradLdsMax = 150 * 1024;
+static int wgrad_stage_channels(const NNLayer& L) {
+  const int kk = L.k * L.k;
+  return std::min(L.c_in, (62 + kk) / kk + 1);
 }
-static int64_t wgrad_chunk_len(int64_t tot) {
-  const int nch = wgrad_chunks(tot);
-  return ((tot + nch - 1) / nch + 15) / 16 * 16;
+static size_t wgrad_lds_bytes(const NNLayer& L, int Ho, int R) {
+  const size_t rows = (size_t)(R - 1) * L.stride + L.k, cols = (size_t)(Ho - 1) * L.stride + L.k;
+  return (size_t)wgrad_stage_channels(L) * rows * cols * sizeof(float);
+}
+static int wgrad_rows(const NNLayer& L, int batch, int Ho) {
+  int R = std::max((512 + Ho - 1) / Ho, (int)(((int64_t)batch * Ho + 255) / 256));
+  R = std::min(R, Ho);
+  while (R > 1 && wgrad_lds_bytes(L, Ho, R) > kWgradLds) --R;
+  return R;
+}
+static int64_t wgrad_chunks(const NNLayer& L, int batch, int Ho) {
+  const int R = wgrad_rows(L, batch, Ho);
+  return (int64_t)batch * ((Ho + R - 1) / R);
 }
 
 // Packed weights (FP32, from the BF16 parameters), one block per layer:
@@ -118,8 +135,8 @@ NNPlan nn_plan(int batch, int n) {
   size_t wp = 0;
   for (int l = 0; l < NN_LAYERS; ++l) {
     const NNLayer& L = kNNLayers[l];
-    const int64_t tot = (int64_t)batch * out_size(l, n) * out_size(l, n);
-    wp = std::max(wp, (size_t)wgrad_chunks(tot) * L.c_out * (L.c_in * L.k * L.k + 1));
+    wp = std::max(wp, (size_t)wgrad_chunks(L, batch, out_size(l, n)) * L.c_out *
+                          (L.c_in * L.k * L.k + 1));
   }
   p.wpart = take(wp);
   p.wpd = take((size_t)pack_floats(false));
@@ -417,89 +434,86 @@ __global__ void k_up_bwd(const float* __restrict__ dBf, float* __restrict__ dB, 
 // output pixels q of G[co][q] X[j][q], with j = ci k^2 + tap and X the
 // layer's input gathered at tap (the columns of an im2col matrix); column
 // j = Ci k^2 (X = 1) gives the bias gradient.  A operand: 16 output channels
-// x 4 pixels of G; B operand: 4 pixels x 16 columns.  Block (c, jt): the
-// pixels of chunk c, every output channel (16 NG), columns 64 jt..; each
-// wave takes a quarter of the chunk's pixels, 16 per pass (its gathers for
-// four groups of 4 pixels issued together, then NG x 16 products), and holds
-// the whole 16 NG x 64 tile; the four waves' sums are added in wave order in
-// LDS and written to part[c][co][j], which k_wgrad_sum adds in chunk order.
+// x 4 pixels of G; B operand: 4 pixels x 16 columns.  Block (c, jt): chunk c
+// (R output rows of one sample), every output channel (16 NG), columns
+// 64 jt..  The block first stages the input that those columns read over the
+// band (their channels, the band's input rows and every column, zero outside
+// the map, the upsampled part of a concatenated input expanded) in LDS with
+// coalesced loads; the im2col values then come from LDS.  Each wave takes a
+// quarter of the band's pixels, 16 per pass, and holds the whole 16 NG x 64
+// tile; the four waves' sums are added in wave order in LDS and written to
+// part[c][co][j], which k_wgrad_sum adds in chunk order.
 template <int NG>
 __global__ void __launch_bounds__(256)
 k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float* __restrict__ A,
                        int Ca, const float* __restrict__ B, int Cb, int H, int k, int stride,
-                       int64_t tot, int64_t chunk, float* __restrict__ part) {
-  __shared__ float red[64 * NG * 16];
+                       int R, int nband, float* __restrict__ part) {
+  extern __shared__ float xs[];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = l & 15, g = l >> 4;
   const int Ci = Ca + Cb, kk = k * k, J = Ci * kk, pad = k / 2, Hh = H >> 1;
+  const int b = blockIdx.x / nband, r0 = (blockIdx.x % nband) * R;
+  const int nr = min(R, Ho - r0);                      // output rows of this band
   const int j0 = blockIdx.y * 64;
-  // this lane's B columns j0 + 16 t + i: the plane of (sample 0, input
-  // channel) it reads, the per-sample stride, the resolution shift (the
-  // upsampled part of a concatenated input) and the tap; or the bias
-  const float* cp[4];
-  int64_t bs[4];
-  int hs[4], wd[4], dyp[4], dxp[4];
+  const int ci_lo = j0 < J ? j0 / kk : 0;
+  const int nch = j0 < J ? min(Ci - 1, (j0 + 63) / kk) - ci_lo + 1 : 0;
+  const int rows = (nr - 1) * stride + k, cols = (Ho - 1) * stride + k;
+  const int plane = rows * cols, ybase = r0 * stride - pad;
+  // stage: xs[c][rr][cc] = input (ci_lo + c, ybase + rr, cc - pad)
+  for (int idx = threadIdx.x; idx < nch * plane; idx += 256) {
+    const int c = idx / plane, rem = idx - c * plane, rr = rem / cols, cc = rem - rr * cols;
+    const int y = ybase + rr, x = cc - pad, ci = ci_lo + c;
+    float v = 0.0f;
+    if (y >= 0 && y < H && x >= 0 && x < H)
+      v = ci < Ca ? A[(((int64_t)b * Ca + ci) * H + y) * H + x]
+                  : B[(((int64_t)b * Cb + (ci - Ca)) * Hh + (y >> 1)) * Hh + (x >> 1)];
+    xs[idx] = v;
+  }
+  // this lane's B columns j0 + 16 t + i: its offset in the staged input (the
+  // channel's plane and the tap), or the bias
+  int xo[4];
   bool jw[4], jb[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int j = j0 + 16 * t + i;
     jw[t] = j < J;
     jb[t] = j == J;
-    const int ci = jw[t] ? j / kk : 0, tp = jw[t] ? j % kk : 0;
-    dyp[t] = tp / k - pad;
-    dxp[t] = tp % k - pad;
-    if (ci < Ca) {
-      cp[t] = A + (int64_t)ci * H * H;
-      bs[t] = (int64_t)Ca * H * H;
-      hs[t] = 0;
-      wd[t] = H;
-    } else {
-      cp[t] = B + (int64_t)(ci - Ca) * Hh * Hh;
-      bs[t] = (int64_t)Cb * Hh * Hh;
-      hs[t] = 1;
-      wd[t] = Hh;
-    }
+    const int ci = jw[t] ? j / kk : ci_lo, tp = jw[t] ? j % kk : 0;
+    xo[t] = (ci - ci_lo) * plane + (tp / k) * cols + tp % k;
   }
-  // this wave's pixels: a quarter of the chunk (chunk is a multiple of 16)
-  const int64_t sub = chunk / 4;
-  const int64_t q0 = (int64_t)blockIdx.x * chunk + w * sub;
-  const int64_t q1 = min(q0 + sub, tot);
-  int64_t q = q0 + g;
+  __syncthreads();
+  // this wave's pixels: a quarter of the band's, q = oy_rel Ho + ox
+  const int P = nr * Ho, sub = (P + 63) / 64 * 16;
+  const int q0 = w * sub, q1 = min(q0 + sub, P);
+  int q = q0 + g, oy = q / Ho, ox = q % Ho;
+  const float* Gb = G + ((int64_t)b * Co * Ho + r0) * Ho;   // (b, co = 0, row r0)
   const int64_t HH = (int64_t)Ho * Ho;
-  int b = (int)(q / HH);
-  int rem = (int)(q % HH);
-  int oy = rem / Ho, ox = rem % Ho;
   nnf4 acc[NG][4];
 #pragma unroll
   for (int c = 0; c < NG; ++c)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[c][t] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int64_t p = q0; p < q1; p += 16) {
+  for (int p = q0; p < q1; p += 16) {
     float a[4][NG], x[4][4];
-    bool ain[4], xv[4][4];
+    bool ain[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const bool in = q < q1;
       ain[s] = in;
-      const int64_t gq = in ? (int64_t)b * Co * HH + (int64_t)oy * Ho + ox : 0;
+      const int gq = in ? oy * Ho + ox : 0;
 #pragma unroll
       for (int c = 0; c < NG; ++c) {
         const int co = 16 * c + i;
-        a[s][c] = G[gq + (int64_t)(co < Co ? co : 0) * HH];
+        a[s][c] = Gb[(int64_t)(co < Co ? co : 0) * HH + gq];
       }
+      const int xq = in ? oy * stride * cols + ox * stride : 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int yy = oy * stride + dyp[t], xx = ox * stride + dxp[t];
-        const bool v = in && jw[t] && yy >= 0 && yy < H && xx >= 0 && xx < H;
-        xv[s][t] = v;
-        const int64_t off = v ? b * bs[t] + (int64_t)(yy >> hs[t]) * wd[t] + (xx >> hs[t]) : 0;
-        x[s][t] = cp[t][off];
-      }
+      for (int t = 0; t < 4; ++t) x[s][t] = xs[xo[t] + xq];
       q += 4;
       ox += 4;
       while (ox >= Ho) {
         ox -= Ho;
-        if (++oy == Ho) { oy = 0; ++b; }
+        ++oy;
       }
     }
 #pragma unroll
@@ -509,12 +523,15 @@ k_conv_bwd_weight_mfma(const float* __restrict__ G, int Co, int Ho, const float*
         const float av = (ain[s] && 16 * c + i < Co) ? a[s][c] : 0.0f;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const float xb = xv[s][t] ? x[s][t] : ((ain[s] && jb[t]) ? 1.0f : 0.0f);
+          const float xb = jw[t] ? x[s][t] : (jb[t] ? 1.0f : 0.0f);
           acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xb, acc[c][t], 0, 0, 0);
         }
       }
   }
-  // the four waves' sums, added in wave order
+  // the four waves' sums, added in wave order (the staged input is no longer
+  // read: its LDS holds them)
+  __syncthreads();
+  float* red = xs;
   for (int ww = 0; ww < 4; ++ww) {
     if (w == ww)
 #pragma unroll
@@ -921,22 +938,36 @@ hipError_t nn_train_step(const uint16_t* w, const double* u, const double* tgt, 
     const uint16_t* wl = w + nn_param_offset(l);
     float* gw = grad + nn_param_offset(l);
     {
-      const int64_t tot = (int64_t)batch * Ho * Ho;
-      const int nch = wgrad_chunks(tot), J = L.c_in * L.k * L.k;
-      const dim3 grid(nch, (J + 1 + 63) / 64);
-      const int64_t len = wgrad_chunk_len(tot);
+      const int J = L.c_in * L.k * L.k, R = wgrad_rows(L, batch, Ho);
+      const int nband = (Ho + R - 1) / R;
+      const int64_t nch = (int64_t)batch * nband;
+      // the reduction reuses the staging LDS: at least 64 NG 16 floats
+      const size_t lds = std::max(wgrad_lds_bytes(L, Ho, R),
+                                  (size_t)64 * 16 * ((L.c_out + 15) / 16) * sizeof(float));
+      if (lds > kWgradLdsMax || nch > 0x7fffffff) return hipErrorInvalidValue;
+      const dim3 grid((unsigned)nch, (J + 1 + 63) / 64);
+#define CH_WGRAD(NG)                                                                              \
+  {                                                                                               \
+    static bool attr = false;                                                                     \
+    if (!attr) {                                                                                  \
+      const hipError_t ea = hipFuncSetAttribute((const void*)k_conv_bwd_weight_mfma<NG>,           \
+                                                hipFuncAttributeMaxDynamicSharedMemorySize,       \
+                                                (int)kWgradLdsMax);                               \
+      if (ea != hipSuccess) return ea;                                                            \
+      attr = true;                                                                                \
+    }                                                                                             \
+    hipLaunchKernelGGL(k_conv_bwd_weight_mfma<NG>, grid, dim3(256), lds, s, G, L.c_out, Ho, A, Ca, \
+                       B, Cb, H, L.k, L.stride, R, nband, ws + p.wpart);                          \
+  }
       switch ((L.c_out + 15) / 16) {
-        case 1: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<1>, grid, dim3(256), 0, s, G, L.c_out, Ho,
-                                   A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
-        case 2: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<2>, grid, dim3(256), 0, s, G, L.c_out, Ho,
-                                   A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
-        case 3: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<3>, grid, dim3(256), 0, s, G, L.c_out, Ho,
-                                   A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
-        default: hipLaunchKernelGGL(k_conv_bwd_weight_mfma<4>, grid, dim3(256), 0, s, G, L.c_out,
-                                    Ho, A, Ca, B, Cb, H, L.k, L.stride, tot, len, ws + p.wpart); break;
+        case 1: CH_WGRAD(1); break;
+        case 2: CH_WGRAD(2); break;
+        case 3: CH_WGRAD(3); break;
+        default: CH_WGRAD(4); break;
       }
+#undef CH_WGRAD
       hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)(((int64_t)L.c_out * (J + 1) + 63) / 64)),
-                         dim3(256), 0, s, ws + p.wpart, nch, L.c_out, J, gw);
+                         dim3(256), 0, s, ws + p.wpart, (int)nch, L.c_out, J, gw);
     }
     if (l == 0) continue;
     if (L.c_in % 16 || L.c_in > 128 || (L.stride != 1 && L.stride != 2))
