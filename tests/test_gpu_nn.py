@@ -36,7 +36,9 @@ def test_layer_table_matches_reference():
         assert (cat < 0 and rcat is None) or names[cat] == rcat
 
 
-@pytest.mark.parametrize("n,batch", [(32, 3), (128, 2), (8, 2), (16, 1)])
+# (128, 4) and (64, 16): large maps at batches where the forward takes two
+# tiles a block
+@pytest.mark.parametrize("n,batch", [(32, 3), (128, 2), (8, 2), (16, 1), (128, 4), (64, 16)])
 def test_forward_matches_reference(n, batch):
     from paper_2304_14074_amd import chlib
     wb, th = _weights(1)
@@ -56,8 +58,8 @@ def test_forward_matches_reference(n, batch):
 
 # n = 8 and 16: the deepest maps are 1 x 1 and 2 x 2 (a pixel walk of four per
 # step wraps more than once a row); batch 3 at n = 16: pixel chunks that do not
-# divide the batch's pixel count
-@pytest.mark.parametrize("n,batch", [(32, 2), (8, 2), (16, 3)])
+# divide the batch's pixel count; (64, 16): two tiles a block on the 64^2 maps
+@pytest.mark.parametrize("n,batch", [(32, 2), (8, 2), (16, 3), (64, 16)])
 def test_loss_and_gradients_match_reference(n, batch):
     from paper_2304_14074_amd import chlib
     wb, th = _weights(3)
