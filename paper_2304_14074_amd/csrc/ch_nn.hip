@@ -66,6 +66,9 @@ static int in_size(int l, int n) {  // spatial size of the (concatenated) input 
 // Tile count (16-pixel tiles times samples) from which the convolutions take
 // two tiles a block.
 constexpr int64_t kNNTwoTiles = 2048;
+// Tile count below which the forward takes 16 waves a block (small grids at
+// a small batch: the contraction split over more waves shortens each one's).
+constexpr int64_t kNNWideTiles = 256;
 
 // Chunks of the weight-gradient GEMM: a chunk is a band of R output rows of
 // one sample, R >= 512 / Ho (at least 512 pixels where the map has them) and
@@ -214,10 +217,10 @@ __global__ void k_pack_weights(const uint16_t* __restrict__ w, float* __restrict
 // D row 4 (lane >> 4) + r (r < 4), column lane & 15.
 typedef float nnf4 __attribute__((ext_vector_type(4)));
 
-// The waves' sums of a block (M accumulators a lane): waves 1-3 park theirs
-// in red, wave 0 adds them to its own in wave order.  Returns false on
-// waves 1-3.
-template <int M>
+// The waves' sums of a block of W waves (M accumulators a lane): waves
+// 1..W-1 park theirs in red, wave 0 adds them to its own in wave order.
+// Returns false on waves 1..W-1.
+template <int M, int W = 4>
 __device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[M], float* red, int wv, int l) {
   if (wv > 0)
 #pragma unroll
@@ -226,12 +229,12 @@ __device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[M], float* red, int wv, in
       for (int r = 0; r < 4; ++r) red[(((wv - 1) * M + m) * 4 + r) * 64 + l] = acc[m][r];
   __syncthreads();
   if (wv > 0) return false;
+#pragma unroll 1
+  for (int ww = 0; ww < W - 1; ++ww)
 #pragma unroll
-  for (int m = 0; m < M; ++m)
+    for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int ww = 0; ww < 3; ++ww) acc[m][r] += red[((ww * M + m) * 4 + r) * 64 + l];
+      for (int r = 0; r < 4; ++r) acc[m][r] += red[((ww * M + m) * 4 + r) * 64 + l];
   return true;
 }
 
@@ -240,14 +243,15 @@ __device__ __forceinline__ bool ks_reduce(nnf4 (&acc)[M], float* red, int wv, in
 // channels), up2(B) (Cb channels)] with Ca a multiple of 16 when Cb > 0.
 // A operand: 16 pixels x 4 channels gathered at the tap; B operands: 4
 // channels x 16 output channels of the weights in the forward packed layout
-// (wf, this layer's block; w for the BF16 biases); c_out <= 16 NG.
-template <int NG, int T>
-__global__ void __launch_bounds__(256)
+// (wf, this layer's block; w for the BF16 biases); c_out <= 16 NG.  W waves
+// a block (16 on small grids: more waves share the contraction).
+template <int NG, int T, int W = 4>
+__global__ void __launch_bounds__(64 * W)
 k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B, int Cb, int H,
                 const uint16_t* __restrict__ w, const float* __restrict__ wf,
                 float* __restrict__ Y, int Co, int Ho, int k, int stride, int act,
                 const int32_t* __restrict__ gate) {
-  __shared__ float red[3 * T * NG * 4 * 64];
+  __shared__ float red[(W - 1) * T * NG * 4 * 64];
   if (gate && !*gate) return;
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, b = blockIdx.y;
   const int i = l & 15, g = l >> 4;
@@ -266,7 +270,7 @@ k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B
   nnf4 acc[T * NG];
 #pragma unroll
   for (int m = 0; m < T * NG; ++m) acc[m] = nnf4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int it = wv; it < items; it += 4) {
+  for (int it = wv; it < items; it += W) {
     const int tap = it / nc, c16 = it - tap * nc;
     const int dy = tap / k, dx = tap - dy * k;
     const int ci0 = 16 * c16 + g;
@@ -306,7 +310,7 @@ k_conv_fwd_mfma(const float* __restrict__ A, int Ca, const float* __restrict__ B
           acc[t * NG + c] =
               __builtin_amdgcn_mfma_f32_16x16x4f32(x[t][u], wt[u][c], acc[t * NG + c], 0, 0, 0);
   }
-  if (!ks_reduce<T * NG>(acc, red, wv, l)) return;
+  if (!ks_reduce<T * NG, W>(acc, red, wv, l)) return;
   const uint16_t* bias = w + (int64_t)Co * Ci * kk;
 #pragma unroll
   for (int c = 0; c < NG; ++c) {
@@ -844,11 +848,16 @@ hipError_t nn_forward(const uint16_t* w, const double* u, int batch, int n, floa
     // grid has work for every CU with them
     const int64_t tiles = ((int64_t)Ho * Ho + 15) / 16;
     const int T = tiles * batch >= kNNTwoTiles ? 2 : 1;
+    // fewer tiles than kNNWideTiles: 16 waves a block share the contraction
+    const bool wide = tiles * batch < kNNWideTiles;
     const dim3 grid((unsigned)((tiles + T - 1) / T), batch);
 #define CH_FWD(NG)                                                                            \
   if (T == 2)                                                                                  \
     hipLaunchKernelGGL((k_conv_fwd_mfma<NG, 2>), grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,   \
                        wf, ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate);            \
+  else if (wide)                                                                               \
+    hipLaunchKernelGGL((k_conv_fwd_mfma<NG, 1, 16>), grid, dim3(1024), 0, s, A, Ca, B, Cb, H,  \
+                       wl, wf, ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate);        \
   else                                                                                         \
     hipLaunchKernelGGL((k_conv_fwd_mfma<NG, 1>), grid, dim3(256), 0, s, A, Ca, B, Cb, H, wl,   \
                        wf, ws + p.act[l], L.c_out, Ho, L.k, L.stride, L.act, gate)
