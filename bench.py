@@ -689,8 +689,8 @@ def main():
                     help="one fine sweep of the 256-instance batch and a 1 GiB copy (counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the slice-parallel multi-GPU design is described but not built.", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for {args.gpus}); "
+              "a slice-parallel multi-GPU form is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)))
