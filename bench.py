@@ -179,6 +179,14 @@ def cpu_baseline(prob, u0s, budget_s: float = 12.0) -> dict:
             else:
                 os.environ[k] = v
     pts = prob.n ** prob.dim
+    # the oracle's coarse step (2.4), timed here on one core
+    propagators.coarse(prob, u0s[0])
+    t0 = time.perf_counter()
+    for i in range(3):
+        propagators.coarse(prob, u0s[i % len(u0s)])
+    t_coarse = (time.perf_counter() - t0) / 3
+    t_step = max(secs) / steps
+    N, J = prob.n_slices, prob.j_fine
     # the rate of the timed steps: every worker's S steps over the slowest
     # worker's time (the workers' start-up and factorisation are not counted)
     return {"value": workers * steps * pts / max(secs), "unit": "grid-point-steps/s",
@@ -186,7 +194,13 @@ def cpu_baseline(prob, u0s, budget_s: float = 12.0) -> dict:
             "kind": "oracle",
             "sample": f"{workers} slices x {steps} fine steps of the {prob.n}x{prob.n} linear step, "
                       f"one slice per process (scipy sparse LU, one thread each); slowest worker "
-                      f"{max(secs):.1f} s, wall {wall:.1f} s; host os.cpu_count()={os.cpu_count()}"}
+                      f"{max(secs):.1f} s, wall {wall:.1f} s; host os.cpu_count()={os.cpu_count()}",
+            # extrapolated from the sample: the oracle's Parareal iteration on
+            # these cores (the N fine solves spread over the workers, then the
+            # N sequential coarse steps) and its serial fine solve
+            "extrapolated": {"fine_step_s": t_step, "coarse_step_s": t_coarse,
+                             "parareal_iteration_s": -(-N // workers) * J * t_step + N * t_coarse,
+                             "serial_fine_s": N * J * t_step}}
 
 
 def serial_fine_trajectory(prob, u0):
