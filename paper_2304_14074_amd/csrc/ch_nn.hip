@@ -73,8 +73,8 @@ constexpr int64_t kNNWideTiles = 256;
 // Chunks of the weight-gradient GEMM: a chunk is a band of R output rows of
 // one sample, R >= 512 / Ho (at least 512 pixels where the map has them) and
 // R >= batch Ho / 256 (at most about 256 chunks), fewer rows while the band's
-// staged input would pass kWgradLds bytes (two blocks a CU); a single row may
-// take up to kWgradLdsMax.  64 consecutive columns j = ci k^2 + tap span at
+// staged input would pass kWgradLds bytes; a single row may take up to
+// kWgradLdsMax.  64 consecutive columns j = ci k^2 + tap span at
 // most (62 + k^2) / k^2 + 1 channels: 8 for 3 x 3 layers, 64 for 1 x 1.
 constexpr size_t kWgradLds = 96 * 1024, kWgradLdsMax = 150 * 1024;
 static int wgrad_stage_channels(const NNLayer& L) {
