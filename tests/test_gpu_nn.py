@@ -153,6 +153,37 @@ def test_neural_coarse_parareal_reaches_fine_solution():
     ctx.ch_set_coarse_kind(0, "approx2")
 
 
+def test_rebound_weights_reach_the_learned_sweep():
+    # the learned sweep copies the bound weights into the network's layout once
+    # per sweep: after binding other weights, a context gives exactly what a
+    # fresh context bound to those weights gives (prediction and one iteration)
+    from paper_2304_14074_amd import chlib
+    N, J, n = 4, 10, 32
+    p = workloads.Problem(dim=2, n=n, eps=0.03, T=N * J * 4e-5, n_slices=N, j_fine=J,
+                          coarse_kind="neural")
+    wa, _ = _weights(11, scale=0.2)
+    wb, _ = _weights(12, scale=0.2)
+    u0 = torch.from_numpy(workloads.u0_uniform(n, 2, 0.3, 9).reshape(-1)).cuda()
+
+    def run(ctx):
+        st = ctx.new_state()
+        st["U"][: n * n] = u0
+        ctx.ch_parareal_iterate(st, 0.0)
+        ctx.ch_parareal_iterate(st, 0.0)
+        torch.cuda.synchronize()
+        return st["U"].clone()
+
+    ctx = chlib.Context([p])
+    ctx.ch_nn_bind(wa)
+    first = run(ctx)
+    ctx.ch_nn_bind(wb)
+    rebound = run(ctx)
+    fresh = chlib.Context([p])
+    fresh.ch_nn_bind(wb)
+    assert torch.equal(rebound, run(fresh))
+    assert not torch.equal(rebound, first)
+
+
 def test_trained_surrogate_gains_over_plain_coarse_step():
     # What the trained network gains over the method without it: trained by the
     # library's kernels on fine trajectories (64 seeds), its one-step error
